@@ -1,0 +1,7 @@
+"""FP64 CPU oracle of the musculoskeletal step -- TEST INFRASTRUCTURE.
+
+Only the test-suite, the smoke check and the benchmark's CPU-baseline leg
+may import this package; the product path (the HIP library and its binding)
+never does.
+"""
+from .oracle import Oracle, build_oracle, oracle_lib_path  # noqa: F401

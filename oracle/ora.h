@@ -1,0 +1,119 @@
+/*
+ * ora.h -- FP64 CPU oracle of the batched musculoskeletal forward-dynamics
+ * step (TEST INFRASTRUCTURE: only the test-suite, the smoke check and the
+ * benchmark's CPU-baseline leg use it; the product path never does).
+ *
+ * Plain, slow, obviously-correct definitions, in double precision, of what
+ * one step computes (Methods, "Whole-body musculoskeletal model"):
+ *   activation dynamics (Eq. excitation-activation), via-point muscle path
+ *   length and moment arms (the moment-arm matrix J_m of the equations of
+ *   motion), the Hill-type force (Eq. flv), the projection J_m^T F, the
+ *   generalized mass matrix M(q) by its Jacobian-sum definition, the bias
+ *   C(q, qd) (Coriolis, centrifugal, gravity) by textbook recursive
+ *   Newton-Euler in body coordinates, penalty ground contact as tau_ext,
+ *   joint damping, a dense Cholesky solve of (M + dt D) qdd = rhs with the
+ *   dissipative forces' velocity slope D taken implicitly, and a
+ *   semi-implicit Euler update.
+ *
+ * Shares no code with the HIP library: own model struct, own parser of the
+ * generator's arrays, own maths.
+ */
+#ifndef ORA_H
+#define ORA_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ora_model ora_model;
+
+/* Status bits (sticky, OR-ed per env). */
+#define ORA_ST_NONFINITE 1u /* non-finite state: the step is not applied */
+#define ORA_ST_NONSPD 2u    /* Cholesky pivot <= 0: the step is not applied */
+
+/* Build a model from the generator's float32/int32 arrays (copied). */
+ora_model *ora_model_create(int n_node, const int32_t *parent,
+                            const int32_t *jtype, const float *jpos,
+                            const float *jrot, const float *axis,
+                            const float *mass, const float *com,
+                            const float *inertia, const float *damping,
+                            int n_mus, const float *f0, const float *l_opt,
+                            const float *l_slack, const float *v_max,
+                            const float *tau_act, const float *tau_deact,
+                            const int32_t *via_start, const int32_t *via_node,
+                            const float *via_pos, int n_con,
+                            const int32_t *con_node, const float *con_pos,
+                            const float *con_radius, const float *contact,
+                            const float *gravity);
+void ora_model_destroy(ora_model *m);
+int ora_nq(const ora_model *m);
+int ora_nv(const ora_model *m);
+
+/* Force-length, passive and force-velocity curves (normalized). */
+double ora_fl(double lm);
+double ora_fp(double lm);
+double ora_fv(double vm);
+double ora_fv_slope(double vm); /* d f_v / d v_m */
+
+/* Forward kinematics: R[n_node][9] (row-major, world), p[n_node][3]. */
+void ora_fk(const ora_model *m, const double *q, double *R, double *p);
+
+/* Activation update for every muscle: act_out = act + dt (u-act)/tau,
+ * clamped to [0,1]; u is first clamped to [0,1]. */
+void ora_activation(const ora_model *m, double dt, const double *u,
+                    const double *act, double *act_out);
+
+/* Muscle path: L[n_mus], moment arms r[n_mus][nv] = -dL/dq, Ldot[n_mus]. */
+void ora_geometry(const ora_model *m, const double *q, const double *qd,
+                  double *L, double *r, double *Ldot);
+
+/* Hill force from act, L, Ldot: F[n_mus]; lm, vm optional (may be NULL). */
+void ora_hill(const ora_model *m, const double *act, const double *L,
+              const double *Ldot, double *F, double *lm, double *vm);
+
+/* M(q) [nv][nv] by the Jacobian-sum definition. */
+void ora_mass_matrix(const ora_model *m, const double *q, double *M);
+
+/* Inverse dynamics tau = M qdd + C(q,qd) (+ gravity if grav != 0) by
+ * recursive Newton-Euler in body coordinates. */
+void ora_rnea(const ora_model *m, const double *q, const double *qd,
+              const double *qdd, int grav, double *tau);
+
+/* Contact generalized force tau_ext[nv]; D (may be NULL) accumulates the
+ * contact force's velocity slope -d(tau_ext)/d(qd) [nv][nv]; n_active (may
+ * be NULL) counts penetrating spheres. */
+void ora_contact(const ora_model *m, const double *q, const double *qd,
+                 double *tau_ext, double *D, int *n_active);
+
+/* Dense Cholesky solve M x = b (n x n). Returns 0, or -1 on a pivot <= 0. */
+int ora_chol_solve(int n, const double *M, const double *b, double *x);
+
+/* Kinetic + gravitational potential energy. */
+double ora_energy(const ora_model *m, const double *q, const double *qd);
+
+/* Per-stage outputs of one step (any pointer may be NULL). */
+typedef struct {
+  double *act;     /* [n_mus] updated activation */
+  double *L, *Ldot, *F, *lm, *vm; /* [n_mus] */
+  double *r;       /* [n_mus][nv] */
+  double *tau_mus, *tau_ext, *tau_d, *C, *qdd; /* [nv] */
+  double *M;       /* [nv][nv] mass matrix */
+  double *D;       /* [nv][nv] velocity slope of the dissipative forces */
+} ora_stage_out;
+
+/* One step of one env, in place on (q, qd, act). Returns status bits. */
+uint32_t ora_step(const ora_model *m, double dt, int contact_on,
+                  double *q, double *qd, double *act, const double *u,
+                  ora_stage_out *out);
+
+/* n_env envs for n_steps steps; u is float32 [n_steps][n_env][n_mus];
+ * status[n_env] is OR-ed. Envs are split over n_threads threads. */
+void ora_rollout(const ora_model *m, int n_env, int n_steps, double dt,
+                 int contact_on, double *q, double *qd, double *act,
+                 const float *u, uint32_t *status, int n_threads);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

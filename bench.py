@@ -1,0 +1,186 @@
+"""Benchmark: env-steps/s of the batched musculoskeletal step on one MI355X.
+
+Workload (default): synthetic whole body, 22 bodies / 80 DoF / 700 muscles /
+24 contact spheres, 4096 envs, dt = 1 ms, AR(1) smooth-noise excitations
+generated in-kernel, exact muscle geometry, FP32 with FP64 mass matrix and
+solve. One bench step = one ms_rollout launch of 100 physics steps for all
+envs (state resident on chip); the default 10 timed steps cover the
+workload's 1000 physics steps.
+
+Prints one JSON line (rank 0) with the throughput, the ALU roofline of the
+step kernel, the joint-angle error against the FP64 oracle on a 16-env
+sample after 200 steps, and the oracle's own throughput on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "env-steps/s at 700 muscles×4096 envs, exact vs surrogate; rad err vs FP64"
+PHYS_PER_STEP = 100
+# MI355X: 256 CUs x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz, one FP32 or
+# FP64 vector FMA per lane and cycle (packed FP32 would double FP32 only).
+PEAK_VALU_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=10)
+    p.add_argument("--warmup", type=int, default=1)
+    p.add_argument("--envs", type=int, default=4096)
+    p.add_argument("--no-cpu", action="store_true", help="skip the oracle legs")
+    p.add_argument("--cpu-seconds", type=float, default=15.0)
+    return p.parse_args()
+
+
+def main():
+    a = parse()
+    if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: the environments shard over GPUs with no "
+              "communication, so only --gpus 1 is run here", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    from paper_2603_29332_amd import flops, ms, synth
+
+    dev = torch.device("cuda:0")
+    dt = 1e-3
+    m = synth.human_model(2)
+    gm = ms.Model(m)
+    E = a.envs
+    q0, qd0, act0 = synth.human_initial_state(m, E)
+    rho, s, mean, _ = synth.ar1_constants(dt)
+
+    def fresh():
+        return (torch.tensor(q0, device=dev), torch.tensor(qd0, device=dev),
+                torch.tensor(act0, device=dev),
+                torch.zeros(E, dtype=torch.int32, device=dev),
+                torch.zeros(E, m["n_mus"], device=dev))
+
+    q, qd, act, st, x = fresh()
+    stream = torch.cuda.current_stream()
+
+    def launch(step_index):
+        gm.rollout(q, qd, act, st, PHYS_PER_STEP, dt, True, kind=ms.EXC_AR1, seed=12,
+                   step0=step_index * PHYS_PER_STEP, x=x, ar1=(rho, s, mean), stream=stream)
+
+    for w in range(a.warmup):
+        launch(w)
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(a.steps + 1)]
+    t0 = time.perf_counter()
+    ev[0].record(stream)
+    for k in range(a.steps):
+        launch(a.warmup + k)
+        ev[k + 1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    launch_ms = [ev[k].elapsed_time(ev[k + 1]) for k in range(a.steps)]
+    env_steps = E * PHYS_PER_STEP * a.steps
+    value = env_steps / wall
+    flagged = int((st != 0).sum().item())
+
+    # ms_step_batch (u read from HBM), for the per-step HBM view
+    uq = torch.rand(E, m["n_mus"], device=dev)
+    q2, qd2, act2, st2, _ = fresh()
+    for _ in range(3):
+        gm.step_batch(q2, qd2, act2, st2, uq, dt, True, stream=stream)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    nsb = 20
+    e0.record(stream)
+    for _ in range(nsb):
+        gm.step_batch(q2, qd2, act2, st2, uq, dt, True, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    sb_ms = e0.elapsed_time(e1) / nsb
+    sb_bytes = 4 * (m["nq"] + m["nv"] + m["n_mus"]) * 2 + 4 * m["n_mus"] + 8
+
+    fp32, fp64, detail = flops.step_flops(m, gm.spans(), gm.nnz)
+    per_launch = (fp32 + fp64) * E * PHYS_PER_STEP
+    avg_launch_s = float(np.mean(launch_ms)) / 1e3
+    achieved = per_launch / avg_launch_s / 1e12
+    line = {
+        "metric": METRIC, "value": value, "unit": "env-steps/s", "n_gpus": 1,
+        "steps": a.steps, "warmup": a.warmup, "ms_per_step": wall / a.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": "whole-body exact path: 22 bodies/80 DoF/700 muscles/24 "
+                               "contact spheres, dt 1 ms, AR(1) excitations in-kernel",
+                   "envs": E, "physics_steps_per_bench_step": PHYS_PER_STEP,
+                   "geometry": "exact", "precision": "FP32, FP64 mass matrix + LTDL solve"},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_VALU_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_VALU_TFLOPS,
+                     "traffic": None,
+                     "kernel": "k_step (ms_rollout)", "avg_launch_ms": avg_launch_s * 1e3,
+                     "flop_per_env_step": {"fp32": fp32, "fp64": fp64}},
+        "step_batch": {"ms_per_physics_step": sb_ms, "env_steps_per_s": E / (sb_ms / 1e3),
+                       "hbm_bytes_per_env_step": sb_bytes,
+                       "hbm_GBps": sb_bytes * E / (sb_ms / 1e3) / 1e9, "hbm_peak_GBps": 8000.0},
+        "flagged_envs": flagged,
+    }
+    if not a.no_cpu:
+        line["rad_err_vs_fp64"] = rad_error(m, gm, dt, dev)
+        line["cpu_baseline"] = cpu_baseline(m, dt, a.cpu_seconds)
+    print(json.dumps(line), flush=True)
+
+
+def rad_error(m, gm, dt, dev):
+    """GPU vs FP64 oracle after 200 steps, 16 envs of the 4096-env workload."""
+    import torch
+
+    from oracle import Oracle
+    from paper_2603_29332_amd import ms, synth
+    E, T = 4096, 200
+    sub = np.arange(0, E, 256)
+    q, qd, act = synth.human_initial_state(m, E)
+    q, qd, act = q[sub], qd[sub], act[sub]
+    u, _ = synth.excitation_sequence("ar1", 12, len(sub), m["n_mus"], T, dt, envs=sub)
+    tq, tqd, tact = (torch.tensor(v, device=dev) for v in (q, qd, act))
+    st = torch.zeros(len(sub), dtype=torch.int32, device=dev)
+    gm.rollout(tq, tqd, tact, st, T, dt, True, kind=ms.EXC_ARRAY, u=torch.tensor(u, device=dev))
+    torch.cuda.synchronize()
+    qo, _, _, so = Oracle(m).rollout(dt, q, qd, act, u, contact=True)
+    ok = (so == 0) & (st.cpu().numpy() == 0)
+    d = np.abs(tq.cpu().numpy()[ok][:, 7:] - qo[ok][:, 7:])
+    return {"max": float(d.max()), "mean": float(d.mean()), "envs": int(ok.sum()),
+            "steps": T, "note": "hinge angles, GPU FP32(+FP64 solve) vs FP64 oracle"}
+
+
+def cpu_baseline(m, dt, seconds):
+    """The FP64 oracle on the host cores, on a bounded sample of the workload."""
+    from oracle import Oracle
+    from paper_2603_29332_amd import synth
+    threads = len(os.sched_getaffinity(0))
+    o = Oracle(m)
+    q, qd, act = synth.human_initial_state(m, 4)
+    u, _ = synth.excitation_sequence("ar1", 12, 4, m["n_mus"], 2, dt)
+    t = time.perf_counter()
+    o.rollout(dt, q, qd, act, u, threads=1)
+    per = (time.perf_counter() - t) / 8.0            # seconds per env-step, 1 thread
+    steps = 20
+    n_env = max(threads, int(seconds * threads / (per * steps)) // threads * threads)
+    q, qd, act = synth.human_initial_state(m, n_env)
+    u, _ = synth.excitation_sequence("ar1", 12, n_env, m["n_mus"], steps, dt)
+    t = time.perf_counter()
+    o.rollout(dt, q, qd, act, u, threads=threads)
+    wall = time.perf_counter() - t
+    return {"value": n_env * steps / wall, "unit": "env-steps/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"{n_env} envs x {steps} steps of the same 80-DoF/700-muscle model "
+                      f"(dense FP64 oracle, {wall:.1f} s wall); envs are independent so the "
+                      f"rate extrapolates linearly",
+            "single_thread_env_steps_per_s": 1.0 / per}
+
+
+if __name__ == "__main__":
+    main()

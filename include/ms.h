@@ -1,0 +1,183 @@
+/*
+ * ms.h -- C ABI of the MI355X batched musculoskeletal forward-dynamics step.
+ *
+ * One step advances E independent environments of one muscle-driven
+ * articulated body (Methods, "Whole-body musculoskeletal model"):
+ *   1. activation dynamics act' = act + dt (u - act) / tau(u, act)
+ *      (Eq. excitation-activation; u clamped to [0, 1]);
+ *   2. via-point muscle-tendon length L, moment arms r = -dL/dq (the
+ *      moment-arm matrix J_m of the equations of motion) and Ldot;
+ *   3. Hill force F = F_max [act' f_l(l_m) f_v(v_m) + f_p(l_m)] (Eq. flv);
+ *   4. projection tau_mus = J_m^T F;
+ *   5. generalized mass matrix M(q) (composite-rigid-body algorithm);
+ *   6. bias C(q, qd) (Coriolis, centrifugal, gravity; recursive
+ *      Newton-Euler);
+ *   7. penalty ground contact tau_ext from spheres on the body (spring
+ *      k and damper c per sphere, the spring taken linearly implicitly:
+ *      F_n = max(0, k d - (c + dt k) zdot), regularised Coulomb friction);
+ *   8. a Cholesky-type (LTDL) solve in FP64 of
+ *      (M + dt D) qdd = tau_mus + tau_ext - b qd - C, D being the velocity
+ *      slope of the dissipative forces (joint damping, muscle
+ *      force-velocity, contact damping and friction) taken implicitly;
+ *   9. semi-implicit Euler: qd += dt qdd, q += dt qd (root orientation by
+ *      the quaternion exponential of the body angular velocity).
+ * M(q) q'' + C(q, q') = J_m^T F + tau_ext is the paper's equation of motion
+ * (Methods, "Musculoskeletal dynamics").
+ *
+ * Conventions
+ *  - All state buffers are DEVICE pointers owned by the caller, float32,
+ *    environment-major (structure of arrays per field):
+ *      q[n_env][nq], qd[n_env][nv], act[n_env][n_mus], status[n_env] (u32).
+ *    A free root stores q = (px, py, pz, qw, qx, qy, qz, hinges...) and
+ *    qd = (world linear velocity, body angular velocity, hinge rates...).
+ *  - Every call is asynchronous on `stream` (a hipStream_t passed as void*;
+ *    NULL = the default stream) and never synchronises implicitly.
+ *  - Calls return an ms_status; nothing throws across the ABI. On error the
+ *    message is available from ms_last_error() (thread-local).
+ *  - Per-environment numerical failures are not return codes: they are
+ *    OR-ed into status[env] (MS_ST_*) and that env's state is left
+ *    unchanged for the step.
+ *  - A model is not safe for concurrent calls from several host threads.
+ */
+#ifndef MS_H
+#define MS_H
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  MS_OK = 0,
+  MS_E_ARG = -1,         /* invalid argument (NULL, size, dt, ...) */
+  MS_E_ALLOC = -2,       /* device or host allocation failed */
+  MS_E_HIP = -3,         /* a HIP runtime call failed */
+  MS_E_MODEL = -4,       /* the model description is invalid */
+  MS_E_UNSUPPORTED = -5  /* valid but beyond this library's limits */
+} ms_status;
+
+/* Per-env status bits. */
+#define MS_ST_NONFINITE 1u /* non-finite state or result; step not applied */
+#define MS_ST_NONSPD 2u    /* LTDL pivot <= 0; step not applied */
+
+/* Model description (host memory; deep-copied by ms_model_create).
+ * Kinematic tree of n_node nodes in topological order (parent < child).
+ * Node i frame = parent frame * (jrot_i, jpos_i) * joint motion, where a
+ * hinge rotates by q about axis_i, a slide translates by q along axis_i,
+ * and a free joint (node 0 only, parent -1) places the node at
+ * (q0,q1,q2) with orientation quaternion (q3..q6). Mass properties,
+ * via-points and contact spheres are given in node frames. */
+typedef struct {
+  int32_t n_node;
+  const int32_t *parent;     /* [n_node], -1 = world */
+  const int32_t *jtype;      /* [n_node]: 0 hinge, 1 slide, 2 free */
+  const float *jpos;         /* [n_node][3] joint origin in the parent frame */
+  const float *jrot;         /* [n_node][9] joint orientation, row-major */
+  const float *axis;         /* [n_node][3] unit hinge/slide axis */
+  const float *mass;         /* [n_node] kg (0 = massless frame) */
+  const float *com;          /* [n_node][3] centre of mass, node frame */
+  const float *inertia;      /* [n_node][3] principal moments at the COM */
+  const float *damping;      /* [nv] joint damping b (N m s / rad) */
+  int32_t n_mus;
+  const float *f0;           /* [n_mus] maximum isometric force (N) */
+  const float *l_opt;        /* [n_mus] optimal fibre length (m) */
+  const float *l_slack;      /* [n_mus] tendon slack length (m) */
+  const float *v_max;        /* [n_mus] max shortening speed (l_opt / s) */
+  const float *tau_act;      /* [n_mus] activation time constant (s) */
+  const float *tau_deact;    /* [n_mus] deactivation time constant (s) */
+  const int32_t *via_start;  /* [n_mus+1] CSR into the via-point arrays */
+  const int32_t *via_node;   /* [n_via] node of each via-point, -1 = world */
+  const float *via_pos;      /* [n_via][3] via-point in its node frame */
+  int32_t n_con;
+  const int32_t *con_node;   /* [n_con] node carrying each contact sphere */
+  const float *con_pos;      /* [n_con][3] sphere centre in the node frame */
+  const float *con_radius;   /* [n_con] sphere radius (m) */
+  float contact[4];          /* stiffness k, damping c, friction mu, v_s */
+  float gravity[3];          /* m/s^2, ground is the plane z = 0 */
+} ms_model_desc;
+
+typedef struct ms_model ms_model;
+
+typedef struct {
+  int32_t nq, nv, n_node, n_mus, n_con, n_body;
+  int32_t max_dof_depth;   /* longest root-to-leaf DoF chain */
+  int32_t nnz_mass;        /* stored entries of the tree-sparse M */
+  int32_t lds_bytes;       /* per-environment LDS footprint of the step */
+} ms_model_info;
+
+typedef struct {
+  float dt;            /* step (s), > 0 and finite */
+  int32_t contact;     /* 1 = ground contact on, 0 = off */
+} ms_step_opts;
+
+/* Excitation source for ms_rollout. */
+typedef enum {
+  MS_EXC_ARRAY = 0,  /* u[n_steps][n_env][n_mus] float32 in device memory */
+  MS_EXC_IID = 1,    /* u = top 24 bits of SplitMix64(key ^ m) * 2^-24 */
+  MS_EXC_AR1 = 2     /* smooth noise x <- rho x + s xi, u = clamp(mean + x) */
+} ms_exc_kind;
+
+typedef struct {
+  int32_t kind;          /* ms_exc_kind */
+  const float *u;        /* MS_EXC_ARRAY: device [n_steps][n_env][n_mus] */
+  uint64_t seed;         /* generators: key = SplitMix64(SplitMix64(seed ^ env) ^ step) */
+  int64_t step0;         /* absolute index of the rollout's first step */
+  float *x;              /* MS_EXC_AR1: device noise state [n_env][n_mus] (in/out) */
+  float rho, s, mean;    /* MS_EXC_AR1 constants (float32) */
+} ms_excitation;
+
+/* Validate a description, build the device tables (tree levels, muscle
+ * spans and moment-arm reduction lists, the tree-sparse M pattern) and
+ * upload them. Returns MS_E_MODEL on an invalid description and
+ * MS_E_UNSUPPORTED beyond the limits (nodes <= 128, nv <= 128,
+ * muscles <= 1024, 2..8 via-points, a muscle spans <= 3 DoFs, contacts <=
+ * 64, tree depth <= 64). Synchronous. */
+ms_status ms_model_create(const ms_model_desc *desc, ms_model **out);
+
+/* Free the model and its device tables. NULL-safe. */
+void ms_model_destroy(ms_model *m);
+
+ms_status ms_model_info_get(const ms_model *m, ms_model_info *out);
+
+/* One step for n_env envs, in place on the caller's device state, reading
+ * excitations u[n_env][n_mus] (device). env i uses row i of every array. */
+ms_status ms_step_batch(ms_model *m, int32_t n_env, float *q, float *qd,
+                        float *act, uint32_t *status, const float *u,
+                        const ms_step_opts *opts, void *stream);
+
+/* n_steps steps for n_env envs in one launch, the state kept on chip
+ * between steps; excitations from exc. Bitwise equal to n_steps calls of
+ * ms_step_batch with the same excitations. */
+ms_status ms_rollout(ms_model *m, int32_t n_env, float *q, float *qd,
+                     float *act, uint32_t *status, const ms_excitation *exc,
+                     int32_t n_steps, const ms_step_opts *opts, void *stream);
+
+/* Stage outputs of one step for n_env envs (device buffers, any may be
+ * NULL): activation act'[E][n_mus], L, Ldot, F [E][n_mus], moment arms
+ * r[E][n_mus][3] with their DoF indices from ms_model_spans, tau_mus[E][nv],
+ * bias_minus_ext[E][nv] = C - tau_ext, qdd[E][nv], and the tree-sparse
+ * (M + dt D) as mass[E][nnz] (float64) with its pattern from
+ * ms_model_mass_pattern. The state is not advanced. */
+typedef struct {
+  float *act, *L, *Ldot, *F, *r, *tau_mus, *bias_minus_ext, *qdd;
+  double *mass;
+} ms_stage_out;
+ms_status ms_step_stages(ms_model *m, int32_t n_env, const float *q,
+                         const float *qd, const float *act, const float *u,
+                         const ms_step_opts *opts, ms_stage_out *out,
+                         void *stream);
+
+/* Host copies of the derived tables: spans[n_mus][3] DoF indices (-1 pad);
+ * the sparse mass pattern rows[nnz], cols[nnz] (row >= col). */
+ms_status ms_model_spans(const ms_model *m, int32_t *spans);
+ms_status ms_model_mass_pattern(const ms_model *m, int32_t *rows,
+                                int32_t *cols);
+
+/* Last error message of this thread ("" if none). */
+const char *ms_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

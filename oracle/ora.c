@@ -563,15 +563,16 @@ void ora_rnea(const ora_model *m, const double *q, const double *qd,
 /* ------------------------------------------------------ ground contact
  * Sphere (node b, centre x, radius rho) against the plane z = 0:
  * penetration d = rho - w_z of the centre w; the force acts at the lowest
- * point c = w - rho z; F_n = max(0, k d - c_d cdot_z), regularised Coulomb
- * friction F_t = -mu F_n v_t / s with s = sqrt(|v_t|^2 + v_s^2);
- * tau_ext += J_c^T F.
+ * point c = w - rho z. The penalty spring-damper is taken linearly
+ * implicitly over the step (d at the end of the step ~ d - dt cdot_z), so
+ * F_n = max(0, k d - (c_d + dt k) cdot_z); regularised Coulomb friction
+ * F_t = -mu F_n v_t / s with s = sqrt(|v_t|^2 + v_s^2); tau_ext += J_c^T F.
  * If D is given, the velocity slope of the contact force is accumulated
- * into it: D += J_c^T diag(Dt, c_n) J_c with c_n = c_d while F_n > 0 and
- * Dt = mu F_n (I - v_t v_t^T / s^2) / s (the friction's own Jacobian,
- * dropping its dependence on F_n). */
+ * into it: D += J_c^T diag(Dt, c_n) J_c with c_n = c_d + dt k while
+ * F_n > 0 and Dt = mu F_n (I - v_t v_t^T / s^2) / s (the friction's own
+ * Jacobian, dropping its dependence on F_n). */
 void ora_contact(const ora_model *m, const double *q, const double *qd,
-                 double *tau_ext, double *D, int *n_active) {
+                 double dt, double *tau_ext, double *D, int *n_active) {
   int n = m->n_node, nv = m->nv, cnt = 0;
   memset(tau_ext, 0, sizeof(double) * nv);
   if (m->n_con == 0) {
@@ -595,7 +596,8 @@ void ora_contact(const ora_model *m, const double *q, const double *qd,
     double cv[3] = {0, 0, 0};
     for (int r = 0; r < 3; ++r)
       for (int j = 0; j < nv; ++j) cv[r] += Jv[r * nv + j] * qd[j];
-    double fn = fmax(0.0, m->kc * pen - m->cc * cv[2]);
+    double ceff = m->cc + dt * m->kc;
+    double fn = fmax(0.0, m->kc * pen - ceff * cv[2]);
     double s = sqrt(cv[0] * cv[0] + cv[1] * cv[1] + m->vs * m->vs);
     double F[3] = {-m->mu * fn * cv[0] / s, -m->mu * fn * cv[1] / s, fn};
     for (int j = 0; j < nv; ++j)
@@ -606,7 +608,7 @@ void ora_contact(const ora_model *m, const double *q, const double *qd,
       Dc[0] = g * (1.0 - cv[0] * cv[0] / (s * s));
       Dc[1] = Dc[3] = -g * cv[0] * cv[1] / (s * s);
       Dc[4] = g * (1.0 - cv[1] * cv[1] / (s * s));
-      Dc[8] = m->cc;
+      Dc[8] = ceff;
       for (int i = 0; i < nv; ++i)
         for (int j = 0; j < nv; ++j) {
           double t = 0;
@@ -719,7 +721,7 @@ uint32_t ora_step(const ora_model *m, double dt, int contact_on, double *q,
     for (int j = 0; j < nv; ++j) tm[j] += r[(size_t)mu * nv + j] * F[mu];
   ora_mass_matrix(m, q, M);
   ora_rnea(m, q, qd, zero, 1, C);
-  if (contact_on) ora_contact(m, q, qd, te, D, NULL);
+  if (contact_on) ora_contact(m, q, qd, dt, te, D, NULL);
   for (int j = 0; j < nv; ++j) {
     td[j] = -m->damping[j] * qd[j];
     rhs[j] = tm[j] + te[j] + td[j] - C[j];

@@ -80,11 +80,12 @@ void ora_mass_matrix(const ora_model *m, const double *q, double *M);
 void ora_rnea(const ora_model *m, const double *q, const double *qd,
               const double *qdd, int grav, double *tau);
 
-/* Contact generalized force tau_ext[nv]; D (may be NULL) accumulates the
+/* Contact generalized force tau_ext[nv] over a step dt (the spring is taken
+ * linearly implicitly: damping c_d + dt k); D (may be NULL) accumulates the
  * contact force's velocity slope -d(tau_ext)/d(qd) [nv][nv]; n_active (may
  * be NULL) counts penetrating spheres. */
 void ora_contact(const ora_model *m, const double *q, const double *qd,
-                 double *tau_ext, double *D, int *n_active);
+                 double dt, double *tau_ext, double *D, int *n_active);
 
 /* Dense Cholesky solve M x = b (n x n). Returns 0, or -1 on a pivot <= 0. */
 int ora_chol_solve(int n, const double *M, const double *b, double *x);

@@ -68,7 +68,7 @@ def _load():
     lib.ora_hill.argtypes = [C.c_void_p, _dp, _dp, _dp, _dp, C.c_void_p, C.c_void_p]
     lib.ora_mass_matrix.argtypes = [C.c_void_p, _dp, _dp]
     lib.ora_rnea.argtypes = [C.c_void_p, _dp, _dp, _dp, C.c_int, _dp]
-    lib.ora_contact.argtypes = [C.c_void_p, _dp, _dp, _dp, C.c_void_p,
+    lib.ora_contact.argtypes = [C.c_void_p, _dp, _dp, C.c_double, _dp, C.c_void_p,
                                 C.POINTER(C.c_int)]
     lib.ora_chol_solve.restype = C.c_int
     lib.ora_chol_solve.argtypes = [C.c_int, _dp, _dp, _dp]
@@ -164,11 +164,11 @@ class Oracle:
     def fv_slope(self, x):
         return self.lib.ora_fv_slope(float(x))
 
-    def contact(self, q, qd, with_slope=False):
+    def contact(self, q, qd, dt, with_slope=False):
         tau = np.zeros(self.nv)
         D = np.zeros((self.nv, self.nv))
         n = C.c_int(0)
-        self.lib.ora_contact(self.h, _d(q), _d(qd), tau,
+        self.lib.ora_contact(self.h, _d(q), _d(qd), float(dt), tau,
                              D.ctypes.data if with_slope else None, C.byref(n))
         if with_slope:
             return tau, n.value, D

@@ -1,0 +1,322 @@
+// ms_model.cpp -- validation of a model description and construction of the
+// flat tables read by the step kernel. Pure host code.
+#include "ms_model.h"
+
+#include <algorithm>
+#include <cmath>
+#include <map>
+#include <sstream>
+
+namespace ms {
+namespace {
+
+template <class T>
+void need(bool ok, T &&what, ms_status code, ms_status *st, std::string *msg) {
+  if (!ok && *st == MS_OK) {
+    *st = code;
+    *msg = what;
+  }
+}
+
+int align16(int x) { return (x + 15) & ~15; }
+
+}  // namespace
+
+ms_status build_tables(const ms_model_desc *d, Tables *t, std::string *msg) {
+  ms_status st = MS_OK;
+  if (!d) {
+    *msg = "desc is NULL";
+    return MS_E_ARG;
+  }
+  const int n = d->n_node;
+  need(n >= 1, "n_node must be >= 1", MS_E_MODEL, &st, msg);
+  need(n <= kMaxNode, "n_node exceeds 128", MS_E_UNSUPPORTED, &st, msg);
+  need(d->parent && d->jtype && d->jpos && d->jrot && d->axis && d->mass &&
+           d->com && d->inertia && d->damping,
+       "a node array is NULL", MS_E_ARG, &st, msg);
+  if (st != MS_OK) return st;
+
+  t->n_node = n;
+  t->parent.assign(d->parent, d->parent + n);
+  t->jtype.assign(d->jtype, d->jtype + n);
+  t->qadr.resize(n);
+  t->dadr.resize(n);
+  int nq = 0, nv = 0;
+  for (int i = 0; i < n; ++i) {
+    int p = d->parent[i], jt = d->jtype[i];
+    need(p >= -1 && p < i, "parent must satisfy -1 <= parent[i] < i", MS_E_MODEL, &st, msg);
+    need(jt >= 0 && jt <= 2, "jtype must be 0 (hinge), 1 (slide) or 2 (free)", MS_E_MODEL, &st, msg);
+    need(jt != 2 || (i == 0 && p == -1), "a free joint is allowed only at node 0 with parent -1",
+         MS_E_MODEL, &st, msg);
+    if (jt != 2) {
+      const float *a = d->axis + 3 * i;
+      float na = std::sqrt(a[0] * a[0] + a[1] * a[1] + a[2] * a[2]);
+      need(std::fabs(na - 1.0f) < 1e-3f, "hinge/slide axes must be unit vectors", MS_E_MODEL, &st, msg);
+    }
+    need(d->mass[i] >= 0 && d->inertia[3 * i] >= 0 && d->inertia[3 * i + 1] >= 0 &&
+             d->inertia[3 * i + 2] >= 0,
+         "mass and inertia must be non-negative", MS_E_MODEL, &st, msg);
+    t->qadr[i] = nq;
+    t->dadr[i] = nv;
+    nq += jt == 2 ? 7 : 1;
+    nv += jt == 2 ? 6 : 1;
+  }
+  if (st != MS_OK) return st;
+  need(nv <= kMaxDof, "more than 128 DoFs", MS_E_UNSUPPORTED, &st, msg);
+  t->nq = nq;
+  t->nv = nv;
+  t->free_root = d->jtype[0] == 2;
+  t->jpos.assign(d->jpos, d->jpos + 3 * n);
+  t->jrot.assign(d->jrot, d->jrot + 9 * n);
+  t->axis.assign(d->axis, d->axis + 3 * n);
+  t->damping.assign(d->damping, d->damping + nv);
+  for (int j = 0; j < nv; ++j)
+    need(std::isfinite(d->damping[j]) && d->damping[j] >= 0, "damping must be >= 0", MS_E_MODEL, &st, msg);
+
+  // ancestor relation and node levels
+  std::vector<std::vector<char>> anc(n, std::vector<char>(n, 0));
+  std::vector<int> level(n, 0);
+  for (int b = 0; b < n; ++b) {
+    for (int a = b; a >= 0; a = d->parent[a]) anc[a][b] = 1;
+    level[b] = d->parent[b] >= 0 ? level[d->parent[b]] + 1 : 0;
+  }
+  int nlev = 1 + *std::max_element(level.begin(), level.end());
+  t->n_level = nlev;
+  t->level_start.assign(nlev + 1, 0);
+  for (int l = 0; l < nlev; ++l) {
+    t->level_start[l] = (int)t->level_nodes.size();
+    for (int i = 0; i < n; ++i)
+      if (level[i] == l) t->level_nodes.push_back(i);
+  }
+  t->level_start[nlev] = (int)t->level_nodes.size();
+
+  // bodies
+  for (int i = 0; i < n; ++i) {
+    if (d->mass[i] > 0 || d->inertia[3 * i] > 0 || d->inertia[3 * i + 1] > 0 ||
+        d->inertia[3 * i + 2] > 0) {
+      t->body_node.push_back(i);
+      t->body_mass.push_back(d->mass[i]);
+      for (int k = 0; k < 3; ++k) {
+        t->body_com.push_back(d->com[3 * i + k]);
+        t->body_inertia.push_back(d->inertia[3 * i + k]);
+      }
+    }
+  }
+  t->n_body = (int)t->body_node.size();
+
+  // contacts
+  t->n_con = d->n_con;
+  need(d->n_con >= 0 && d->n_con <= kMaxCon, "n_con must be in [0, 64]", MS_E_UNSUPPORTED, &st, msg);
+  if (d->n_con > 0)
+    need(d->con_node && d->con_pos && d->con_radius, "a contact array is NULL", MS_E_ARG, &st, msg);
+  if (st != MS_OK) return st;
+  for (int c = 0; c < d->n_con; ++c) {
+    need(d->con_node[c] >= 0 && d->con_node[c] < n, "con_node out of range", MS_E_MODEL, &st, msg);
+    need(d->con_radius[c] >= 0, "contact radius must be >= 0", MS_E_MODEL, &st, msg);
+    t->con_node.push_back(d->con_node[c]);
+    for (int k = 0; k < 3; ++k) t->con_pos.push_back(d->con_pos[3 * c + k]);
+    t->con_radius.push_back(d->con_radius[c]);
+  }
+  if (st != MS_OK) return st;
+  t->kc = d->contact[0];
+  t->cc = d->contact[1];
+  t->mu = d->contact[2];
+  t->vs = d->contact[3];
+  need(t->kc >= 0 && t->cc >= 0 && t->mu >= 0 && (t->vs > 0 || d->n_con == 0),
+       "contact constants must be >= 0 and v_s > 0", MS_E_MODEL, &st, msg);
+  for (int k = 0; k < 3; ++k) t->g[k] = d->gravity[k];
+
+  // subtree lists of bodies and contacts per node
+  t->subb_start.assign(n + 1, 0);
+  t->subc_start.assign(n + 1, 0);
+  for (int i = 0; i < n; ++i) {
+    t->subb_start[i] = (int)t->subb.size();
+    for (int b = 0; b < t->n_body; ++b)
+      if (anc[i][t->body_node[b]]) t->subb.push_back(b);
+    t->subc_start[i] = (int)t->subc.size();
+    for (int c = 0; c < t->n_con; ++c)
+      if (anc[i][t->con_node[c]]) t->subc.push_back(c);
+  }
+  t->subb_start[n] = (int)t->subb.size();
+  t->subc_start[n] = (int)t->subc.size();
+
+  // DoFs and the DoF tree (each DoF's parent is the previous DoF on the path)
+  std::vector<int> dof_parent(nv, -1);
+  t->dof_node.assign(nv, 0);
+  t->dof_kind.assign(nv, 0);
+  for (int i = 0; i < n; ++i) {
+    int a = t->dadr[i];
+    int pd = d->parent[i] >= 0 ? t->dadr[d->parent[i]] + (d->jtype[d->parent[i]] == 2 ? 5 : 0) : -1;
+    if (d->jtype[i] == 2) {
+      for (int k = 0; k < 6; ++k) {
+        t->dof_node[a + k] = i;
+        t->dof_kind[a + k] = k < 3 ? 2 : 3;
+        dof_parent[a + k] = k == 0 ? pd : a + k - 1;
+      }
+    } else {
+      t->dof_node[a] = i;
+      t->dof_kind[a] = d->jtype[i];
+      dof_parent[a] = pd;
+    }
+  }
+  t->dof_depth.assign(nv, 0);
+  t->row_start.assign(nv + 1, 0);
+  std::vector<std::vector<int>> dpath(nv);
+  for (int j = 0; j < nv; ++j) {
+    if (dof_parent[j] >= 0) dpath[j] = dpath[dof_parent[j]];
+    dpath[j].push_back(j);
+    t->dof_depth[j] = (int)dpath[j].size();
+    t->row_start[j] = (int)t->path.size();
+    for (int x : dpath[j]) t->path.push_back(x);
+  }
+  t->row_start[nv] = (int)t->path.size();
+  t->nnz = (int)t->path.size();
+  t->nnz_row.resize(t->nnz);
+  for (int j = 0; j < nv; ++j)
+    for (int e = t->row_start[j]; e < t->row_start[j + 1]; ++e) t->nnz_row[e] = j;
+  t->max_depth = *std::max_element(t->dof_depth.begin(), t->dof_depth.end());
+  need(t->max_depth <= kMaxDepth, "DoF tree deeper than 64", MS_E_UNSUPPORTED, &st, msg);
+  auto dof_anc = [&](int a, int b) {  // DoF a is b or an ancestor of b
+    return t->dof_depth[a] <= t->dof_depth[b] && dpath[b][t->dof_depth[a] - 1] == a;
+  };
+  for (int a = 0; a + 1 < t->max_depth; ++a)
+    for (int b = 0; b <= a; ++b) t->pair_ab.push_back(a | (b << 8));
+  t->max_pairs = (int)t->pair_ab.size();
+
+  // muscles
+  const int nm = d->n_mus;
+  t->n_mus = nm;
+  need(nm >= 0 && nm <= kMaxMus, "n_mus must be in [0, 1024]", MS_E_UNSUPPORTED, &st, msg);
+  if (nm > 0)
+    need(d->f0 && d->l_opt && d->l_slack && d->v_max && d->tau_act && d->tau_deact &&
+             d->via_start && d->via_node && d->via_pos,
+         "a muscle array is NULL", MS_E_ARG, &st, msg);
+  if (st != MS_OK) return st;
+  t->mpl = (nm + kWave - 1) / kWave;
+  t->via_node.assign((size_t)kMaxVia * nm, -1);
+  t->via_pos.assign((size_t)kMaxVia * 3 * nm, 0.0f);
+  t->mus_span.assign((size_t)3 * nm, -1);
+  t->mus_mask.assign(nm, 0u);
+  t->mus_nvia.assign(nm, 0);
+  std::vector<std::vector<int>> proj(nv);
+  std::map<int, std::vector<int>> dent;  // H index -> items
+  int via_max = 0;
+  for (int m = 0; m < nm; ++m) {
+    int s0 = d->via_start[m], s1 = d->via_start[m + 1], P = s1 - s0;
+    need(s0 >= 0 && P >= 2, "each muscle needs >= 2 via-points", MS_E_MODEL, &st, msg);
+    need(P <= kMaxVia, "more than 8 via-points in a muscle", MS_E_UNSUPPORTED, &st, msg);
+    need(d->f0[m] >= 0 && d->l_opt[m] > 0 && d->v_max[m] > 0 && d->tau_act[m] > 0 &&
+             d->tau_deact[m] > 0 && std::isfinite(d->l_slack[m]),
+         "Hill parameters must be positive", MS_E_MODEL, &st, msg);
+    if (st != MS_OK) return st;
+    via_max = std::max(via_max, P);
+    t->mus_f0.push_back(d->f0[m]);
+    t->mus_ilopt.push_back(1.0f / d->l_opt[m]);
+    t->mus_lslack.push_back(d->l_slack[m]);
+    t->mus_ivl.push_back(1.0f / (d->v_max[m] * d->l_opt[m]));
+    t->mus_tact.push_back(d->tau_act[m]);
+    t->mus_tdeact.push_back(d->tau_deact[m]);
+    t->mus_nvia[m] = P;
+    std::vector<int> nodes(P);
+    for (int k = 0; k < P; ++k) {
+      int b = d->via_node[s0 + k];
+      need(b >= -1 && b < n, "via_node out of range", MS_E_MODEL, &st, msg);
+      nodes[k] = b;
+      t->via_node[(size_t)k * nm + m] = b;
+      for (int c = 0; c < 3; ++c) t->via_pos[((size_t)k * 3 + c) * nm + m] = d->via_pos[3 * (s0 + k) + c];
+    }
+    if (st != MS_OK) return st;
+    // DoF j changes the length iff it moves exactly one end of a segment
+    std::vector<int> span;
+    std::vector<uint32_t> masks;
+    for (int j = 0; j < nv; ++j) {
+      int nj = t->dof_node[j];
+      uint32_t mk = 0;
+      for (int k = 0; k < P; ++k)
+        if (nodes[k] >= 0 && anc[nj][nodes[k]]) mk |= 1u << k;
+      bool in = false;
+      for (int k = 0; k + 1 < P; ++k)
+        if (((mk >> k) & 1u) != ((mk >> (k + 1)) & 1u)) in = true;
+      if (in) {
+        span.push_back(j);
+        masks.push_back(mk);
+      }
+    }
+    if ((int)span.size() > 3) {
+      std::ostringstream os;
+      os << "muscle " << m << " spans " << span.size() << " DoFs (at most 3 supported)";
+      need(false, os.str(), MS_E_UNSUPPORTED, &st, msg);
+      return st;
+    }
+    for (size_t a = 0; a < span.size(); ++a)
+      for (size_t b = 0; b < span.size(); ++b)
+        need(dof_anc(span[a], span[b]) || dof_anc(span[b], span[a]),
+             "a muscle's DoFs must lie on one root-to-leaf chain", MS_E_UNSUPPORTED, &st, msg);
+    if (st != MS_OK) return st;
+    for (size_t s = 0; s < span.size(); ++s) {
+      t->mus_span[s * nm + m] = span[s];
+      t->mus_mask[m] |= masks[s] << (8 * s);
+      proj[span[s]].push_back(m * 3 + (int)s);
+    }
+    for (size_t s = 0; s < span.size(); ++s)
+      for (size_t u = 0; u <= s; ++u) {
+        int js = span[s], ju = span[u];
+        int row = t->dof_depth[js] >= t->dof_depth[ju] ? js : ju;
+        int col = row == js ? ju : js;
+        int h = t->row_start[row] + t->dof_depth[col] - 1;
+        dent[h].push_back(m * 16 + (int)s * 4 + (int)u);
+      }
+  }
+  t->n_via_max = via_max;
+  t->proj_start.assign(nv + 1, 0);
+  for (int j = 0; j < nv; ++j) {
+    t->proj_start[j] = (int)t->proj_item.size();
+    for (int x : proj[j]) t->proj_item.push_back(x);
+  }
+  t->proj_start[nv] = (int)t->proj_item.size();
+  for (auto &kv : dent) {
+    t->dent_h.push_back(kv.first);
+    t->dent_start.push_back((int)t->dent_item.size());
+    for (int x : kv.second) t->dent_item.push_back(x);
+  }
+  t->dent_start.push_back((int)t->dent_item.size());
+  t->n_dent = (int)t->dent_h.size();
+  if (t->free_root) {
+    // a world-fixed via-point on a floating model would span the root
+    for (int m = 0; m < nm; ++m)
+      for (int k = 0; k < t->mus_nvia[m]; ++k)
+        need(t->via_node[(size_t)k * nm + m] >= 0, "world via-points need a fixed base",
+             MS_E_UNSUPPORTED, &st, msg);
+  }
+  if (st != MS_OK) return st;
+
+  // LDS layout of one environment
+  int off = 0;
+  auto take = [&](int bytes) {
+    int o = off;
+    off = align16(off + bytes);
+    return o;
+  };
+  t->off_flag = take(16);
+  t->off_q = take(4 * nq);
+  t->off_qd = take(4 * nv);
+  t->off_R = take(4 * 9 * n);
+  t->off_P = take(4 * 3 * n);
+  t->off_S = take(4 * 6 * nv);
+  t->off_con = take(4 * 16 * std::max(t->n_con, 1));
+  t->off_rhs = take(8 * nv);
+  t->off_x = take(8 * nv);
+  t->off_H = take(8 * t->nnz);
+  int u_rnea = 4 * 6 * (2 * n + t->n_body + n);            // V, A, f_b, F_n
+  int u_crba = 8 * 10 * (n + t->n_body) + 8 * 6 * nv;     // bodies, composites, F_j
+  int u_mus = 4 * 5 * nm;                                  // r[3], F, c per muscle
+  int u = std::max(u_rnea, std::max(u_crba, u_mus));
+  t->off_scr = take(u);
+  t->off_V = t->off_scr;
+  t->off_A = t->off_V + 4 * 6 * n;
+  t->off_F = t->off_A + 4 * 6 * n;
+  t->lds_bytes = off;
+  return MS_OK;
+}
+
+}  // namespace ms

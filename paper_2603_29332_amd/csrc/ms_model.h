@@ -1,0 +1,67 @@
+// ms_model.h -- host-side compilation of a model description into the flat
+// tables the step kernel reads (internal to libms).
+#pragma once
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/ms.h"
+
+namespace ms {
+
+constexpr int kMaxNode = 128;
+constexpr int kMaxDof = 128;
+constexpr int kMaxMus = 1024;
+constexpr int kMaxVia = 8;
+constexpr int kMaxCon = 64;
+constexpr int kMaxDepth = 64;
+constexpr int kWave = 64;
+
+// Offsets (in elements of the named type) of every table inside one device
+// buffer; the kernel receives base pointer + this struct.
+struct Tables {
+  // sizes
+  int n_node = 0, nq = 0, nv = 0, n_mus = 0, n_con = 0, n_body = 0;
+  int nnz = 0, max_depth = 0, n_level = 0, free_root = 0, mpl = 0;
+  int n_dent = 0, max_pairs = 0, n_via_max = 0;
+  float kc = 0, cc = 0, mu = 0, vs = 0, g[3] = {0, 0, 0};
+  // per node
+  std::vector<int32_t> parent, jtype, qadr, dadr, level_start, level_nodes;
+  std::vector<float> jpos, jrot, axis;          // [n][3], [n][9], [n][3]
+  // bodies (nodes with mass or inertia)
+  std::vector<int32_t> body_node;
+  std::vector<float> body_mass, body_com, body_inertia;  // [b], [b][3], [b][3]
+  // per node: bodies and contacts in its subtree (CSR)
+  std::vector<int32_t> subb_start, subb, subc_start, subc;
+  // contacts
+  std::vector<int32_t> con_node;
+  std::vector<float> con_pos, con_radius;
+  // DoF
+  std::vector<int32_t> dof_node, dof_kind;  // kind: 0 hinge, 1 slide, 2 root lin, 3 root ang
+  std::vector<float> damping;
+  // muscles (SoA)
+  std::vector<float> mus_f0, mus_ilopt, mus_lslack, mus_ivl, mus_tact, mus_tdeact;
+  std::vector<int32_t> mus_nvia;          // via count
+  std::vector<int32_t> via_node;          // [kMaxVia][n_mus] SoA, padded
+  std::vector<float> via_pos;             // [kMaxVia][3][n_mus] SoA, padded
+  std::vector<int32_t> mus_span;          // [3][n_mus], -1 pad
+  std::vector<uint32_t> mus_mask;         // [n_mus] 3 x 8-bit via masks
+  // reductions over muscle products
+  std::vector<int32_t> proj_start;        // [nv+1]
+  std::vector<int32_t> proj_item;         // muscle*3 + slot
+  std::vector<int32_t> dent_h, dent_start, dent_item;  // item: muscle*16 + s*4 + t
+  // tree-sparse mass matrix (row j holds its ancestors by depth, diag last)
+  std::vector<int32_t> row_start, dof_depth, path;     // path[nnz] = DoF id
+  std::vector<int32_t> nnz_row;                        // row of each entry
+  std::vector<int32_t> pair_ab;           // triangular (a,b), b <= a, packed a | b<<8
+  // LDS layout (byte offsets into the per-env LDS block)
+  int off_q = 0, off_qd = 0, off_R = 0, off_P = 0, off_S = 0, off_V = 0,
+      off_A = 0, off_F = 0, off_con = 0, off_rhs = 0, off_H = 0, off_x = 0,
+      off_scr = 0, off_flag = 0, lds_bytes = 0;
+  int n_levels_dof = 0;
+};
+
+// Validate desc and build every table. Returns MS_OK or an error with msg.
+ms_status build_tables(const ms_model_desc *d, Tables *t, std::string *msg);
+
+}  // namespace ms

@@ -1,0 +1,988 @@
+// ms_step.hip -- the batched musculoskeletal forward-dynamics step on gfx950.
+//
+// One wavefront (64 lanes) advances one environment. The environment's
+// kinematic tree (node frames, motion subspaces, spatial velocities and
+// accelerations), its contact state and its tree-sparse FP64 mass matrix
+// live in LDS; muscle work is spread over the lanes (lane l owns muscles
+// l, l+64, ...), tree work over nodes/DoFs, and the LTDL factorisation over
+// the (ancestor, ancestor) pairs of each eliminated DoF.
+//
+// All spatial quantities are expressed in world axes about a reference point
+// O that is the root origin of a floating model (the world origin for a
+// fixed base), so subtree sums (composite inertias, net forces) are plain
+// sums. FP32 throughout except the mass matrix assembly, its factorisation
+// and the solve, which run in FP64.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/ms.h"
+#include "ms_model.h"
+
+namespace ms {
+
+// ----------------------------------------------------------------- params
+struct KModel {
+  int n_node, nq, nv, n_mus, n_con, n_body, nnz, n_level, free_root, n_dent;
+  float kc, cc, mu, vs, gx, gy, gz;
+  const int *parent, *jtype, *qadr, *dadr, *level_start, *level_nodes;
+  const float *jpos, *jrot, *axis;
+  const int *body_node;
+  const float *body_mass, *body_com, *body_inertia;
+  const int *subb_start, *subb, *subc_start, *subc;
+  const int *con_node;
+  const float *con_pos, *con_radius;
+  const int *dof_node, *dof_kind;
+  const float *damping;
+  const float *mus_f0, *mus_ilopt, *mus_lslack, *mus_ivl, *mus_tact, *mus_tdeact;
+  const int *mus_nvia, *via_node;
+  const float *via_pos;
+  const int *mus_span;
+  const unsigned *mus_mask;
+  const int *proj_start, *proj_item;
+  const int *dent_h, *dent_start, *dent_item;
+  const int *row_start, *dof_depth, *path, *nnz_row, *pair_ab;
+  int off_flag, off_q, off_qd, off_R, off_P, off_S, off_con, off_rhs, off_x, off_H,
+      off_scr, off_V, off_A, off_F;
+};
+
+struct KRun {
+  float *q, *qd, *act;
+  unsigned *status;
+  const float *u;  // array excitations
+  int n_env;
+  float dt;
+  int contact;
+  unsigned long long seed;
+  long long step0;
+  float *xar;
+  float rho, s, mean;
+  // stage outputs (ms_step_stages)
+  float *o_act, *o_L, *o_Ldot, *o_F, *o_r, *o_tau, *o_bias, *o_qdd;
+  double *o_H;
+};
+
+enum { EXC_ARRAY = 0, EXC_IID = 1, EXC_AR1 = 2 };
+
+// ------------------------------------------------------------ small maths
+struct V3 {
+  float x, y, z;
+};
+__device__ __forceinline__ V3 v3(float x, float y, float z) { return V3{x, y, z}; }
+__device__ __forceinline__ V3 operator+(V3 a, V3 b) { return v3(a.x + b.x, a.y + b.y, a.z + b.z); }
+__device__ __forceinline__ V3 operator-(V3 a, V3 b) { return v3(a.x - b.x, a.y - b.y, a.z - b.z); }
+__device__ __forceinline__ V3 operator*(float s, V3 a) { return v3(s * a.x, s * a.y, s * a.z); }
+__device__ __forceinline__ float dot(V3 a, V3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+__device__ __forceinline__ V3 cross(V3 a, V3 b) {
+  return v3(a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x);
+}
+// y = R x, R row-major 3x3
+__device__ __forceinline__ V3 mulR(const float *R, V3 x) {
+  return v3(R[0] * x.x + R[1] * x.y + R[2] * x.z, R[3] * x.x + R[4] * x.y + R[5] * x.z,
+            R[6] * x.x + R[7] * x.y + R[8] * x.z);
+}
+__device__ __forceinline__ V3 ld3(const float *p) { return v3(p[0], p[1], p[2]); }
+__device__ __forceinline__ void st3(float *p, V3 a) {
+  p[0] = a.x;
+  p[1] = a.y;
+  p[2] = a.z;
+}
+
+// SplitMix64 output function (Steele, Lea & Flood 2014).
+__device__ __forceinline__ unsigned long long splitmix64(unsigned long long x) {
+  unsigned long long z = x + 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+__device__ __forceinline__ float u24(unsigned long long z, int shift) {
+  return (float)((unsigned)((z >> shift) & 0xFFFFFFull)) * 5.9604644775390625e-8f;
+}
+
+// One step of the smooth-noise excitation for muscle mi: four 24-bit
+// uniforms from two SplitMix64 draws, their sum standardised
+// (Irwin-Hall(4): mean 2, variance 1/3), x <- rho x + s xi,
+// u = clamp(mean + x, 0, 1). Each operation is rounded to float32 in this
+// order: no contraction into fused multiply-adds.
+__device__ __noinline__ float ar1_step(unsigned long long key, int mi, float &x, float rho, float s,
+                                       float mean) {
+#pragma clang fp contract(off)
+  const unsigned long long z1 = splitmix64(key ^ (2ull * (unsigned long long)mi));
+  const unsigned long long z2 = splitmix64(key ^ (2ull * (unsigned long long)mi + 1ull));
+  const float t = ((u24(z1, 40) + u24(z1, 16)) + u24(z2, 40)) + u24(z2, 16);
+  const float xi = (t - 2.0f) * 1.7320508075688772f;
+  const float a = rho * x;
+  const float b = s * xi;
+  x = a + b;
+  return fminf(fmaxf(mean + x, 0.0f), 1.0f);
+}
+
+// Hill curves: Gaussian active force-length, exponential passive
+// force-length with a linear tail past 1.6, hyperbolic force-velocity.
+__device__ __forceinline__ float hill_fl(float lm) {
+  float d = lm - 1.0f;
+  return expf(-d * d * (1.0f / 0.45f));
+}
+__device__ __forceinline__ float hill_fp(float lm) {
+  const float e4m1 = 53.598150033144236f;  // e^4 - 1
+  if (lm <= 1.0f) return 0.0f;
+  if (lm <= 1.6f) return (expf((4.0f / 0.6f) * (lm - 1.0f)) - 1.0f) / e4m1;
+  return 1.0f + 6.7910995f * (lm - 1.6f);  // slope (4/0.6) e^4/(e^4-1)
+}
+__device__ __forceinline__ float hill_fv(float vm) {
+  if (vm <= -1.0f) return 0.0f;
+  if (vm <= 0.0f) return (1.0f + vm) / (1.0f - 4.0f * vm);
+  return 1.0f + 0.4f * vm / (vm + 0.08f);
+}
+__device__ __forceinline__ float hill_fv_slope(float vm) {
+  if (vm <= -1.0f) return 0.0f;
+  if (vm <= 0.0f) {
+    float a = 1.0f - 4.0f * vm;
+    return 5.0f / (a * a);
+  }
+  float b = vm + 0.08f;
+  return 0.032f / (b * b);
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// ------------------------------------------------------------------ kernel
+template <int MPL, int EXC, bool STAGES>
+__global__ __launch_bounds__(64) void k_step(KModel M, KRun Rn, int n_steps) {
+  extern __shared__ __align__(16) unsigned char lds[];
+  const int env = blockIdx.x;
+  const int lane = threadIdx.x;
+  const int nq = M.nq, nv = M.nv, nm = M.n_mus, nn = M.n_node;
+  float *q = (float *)(lds + M.off_q);
+  float *qd = (float *)(lds + M.off_qd);
+  float *Rl = (float *)(lds + M.off_R);
+  float *Pl = (float *)(lds + M.off_P);
+  float *Sl = (float *)(lds + M.off_S);
+  float *Vl = (float *)(lds + M.off_V);
+  float *Al = (float *)(lds + M.off_A);
+  float *Fl = (float *)(lds + M.off_F);  // f_b[n_body][6] then F_n[n_node][6]
+  float *Cl = (float *)(lds + M.off_con);
+  double *rhs = (double *)(lds + M.off_rhs);
+  double *xs = (double *)(lds + M.off_x);
+  double *H = (double *)(lds + M.off_H);
+  unsigned char *scr = lds + M.off_scr;
+  int *flag = (int *)(lds + M.off_flag);
+  const float dt = Rn.dt;
+
+  for (int i = lane; i < nq; i += 64) q[i] = Rn.q[(size_t)env * nq + i];
+  for (int i = lane; i < nv; i += 64) qd[i] = Rn.qd[(size_t)env * nv + i];
+  float act[MPL], xar[MPL];
+#pragma unroll
+  for (int t = 0; t < MPL; ++t) {
+    int mi = lane + 64 * t;
+    act[t] = mi < nm ? Rn.act[(size_t)env * nm + mi] : 0.0f;
+    xar[t] = 0.0f;
+    if (EXC == EXC_AR1 && mi < nm) xar[t] = Rn.xar[(size_t)env * nm + mi];
+  }
+  unsigned status = Rn.status ? Rn.status[env] : 0u;
+  __syncthreads();
+
+  for (int step = 0; step < n_steps; ++step) {
+    // ---------------------------------------------- excitation and state check
+    float u[MPL];
+    bool bad = false;
+    for (int i = lane; i < nq; i += 64) bad |= !isfinite(q[i]);
+    for (int i = lane; i < nv; i += 64) bad |= !isfinite(qd[i]);
+    unsigned long long key = 0;
+    if (EXC != EXC_ARRAY)
+      key = splitmix64(splitmix64(Rn.seed ^ (unsigned long long)env) ^
+                       (unsigned long long)(Rn.step0 + step));
+#pragma unroll
+    for (int t = 0; t < MPL; ++t) {
+      int mi = lane + 64 * t;
+      u[t] = 0.0f;
+      if (mi < nm) {
+        bad |= !isfinite(act[t]);
+        if (EXC == EXC_ARRAY) {
+          u[t] = Rn.u[((size_t)step * Rn.n_env + env) * nm + mi];
+        } else if (EXC == EXC_IID) {
+          u[t] = u24(splitmix64(key ^ (unsigned long long)mi), 40);
+        } else {
+          u[t] = ar1_step(key, mi, xar[t], Rn.rho, Rn.s, Rn.mean);
+        }
+      }
+    }
+    if (__any(bad)) {
+      status |= MS_ST_NONFINITE;
+      continue;  // the state stays as it is
+    }
+
+    // --------------------------------------------------- activation dynamics
+    float act1[MPL];
+#pragma unroll
+    for (int t = 0; t < MPL; ++t) {
+      int mi = lane + 64 * t;
+      act1[t] = 0.0f;
+      if (mi < nm) {
+        float uc = fminf(fmaxf(u[t], 0.0f), 1.0f);
+        float a = act[t];
+        float tau = uc > a ? M.mus_tact[mi] * (0.5f + 1.5f * a) : M.mus_tdeact[mi] / (0.5f + 1.5f * a);
+        act1[t] = fminf(fmaxf(a + dt * (uc - a) / tau, 0.0f), 1.0f);
+        if (STAGES) Rn.o_act[(size_t)env * nm + mi] = act1[t];
+      }
+    }
+
+    // ------------------------- forward kinematics, motion subspaces, V and A
+    // O = root origin (floating) or world origin (fixed base).
+    V3 O = M.free_root ? v3(q[0], q[1], q[2]) : v3(0.f, 0.f, 0.f);
+    const V3 g = v3(M.gx, M.gy, M.gz);
+    for (int l = 0; l < M.n_level; ++l) {
+      const int b0 = M.level_start[l], b1 = M.level_start[l + 1];
+      for (int k = b0 + lane; k < b1; k += 64) {
+        const int i = M.level_nodes[k];
+        const int jt = M.jtype[i];
+        float *R = Rl + 9 * i;
+        const int da = M.dadr[i];
+        if (jt == 2) {
+          const float *x = q + M.qadr[i] + 3;
+          float nrm = sqrtf(x[0] * x[0] + x[1] * x[1] + x[2] * x[2] + x[3] * x[3]);
+          float w = x[0] / nrm, a = x[1] / nrm, b = x[2] / nrm, c = x[3] / nrm;
+          R[0] = 1 - 2 * (b * b + c * c); R[1] = 2 * (a * b - w * c); R[2] = 2 * (a * c + w * b);
+          R[3] = 2 * (a * b + w * c); R[4] = 1 - 2 * (a * a + c * c); R[5] = 2 * (b * c - w * a);
+          R[6] = 2 * (a * c - w * b); R[7] = 2 * (b * c + w * a); R[8] = 1 - 2 * (a * a + b * b);
+          st3(Pl + 3 * i, v3(0.f, 0.f, 0.f));
+          for (int kk = 0; kk < 3; ++kk) {
+            float *S = Sl + 6 * (da + kk);
+            S[0] = S[1] = S[2] = 0.f;
+            S[3] = kk == 0; S[4] = kk == 1; S[5] = kk == 2;
+            float *S2 = Sl + 6 * (da + 3 + kk);
+            S2[0] = R[kk]; S2[1] = R[3 + kk]; S2[2] = R[6 + kk];
+            S2[3] = S2[4] = S2[5] = 0.f;
+          }
+          V3 v = ld3(qd + da);
+          V3 wb = ld3(qd + da + 3);
+          V3 ww = mulR(R, wb);
+          float *V = Vl + 6 * i, *A = Al + 6 * i;
+          st3(V, ww);
+          st3(V + 3, v);
+          st3(A, v3(0.f, 0.f, 0.f));
+          st3(A + 3, cross(v, ww) - g);
+          continue;
+        }
+        const int p = M.parent[i];
+        float Rp[9];
+        V3 Pp, wp, vp, ap, lp;
+        if (p >= 0) {
+          for (int e = 0; e < 9; ++e) Rp[e] = Rl[9 * p + e];
+          Pp = ld3(Pl + 3 * p);
+          wp = ld3(Vl + 6 * p); vp = ld3(Vl + 6 * p + 3);
+          ap = ld3(Al + 6 * p); lp = ld3(Al + 6 * p + 3);
+        } else {
+          for (int e = 0; e < 9; ++e) Rp[e] = (e % 4 == 0) ? 1.f : 0.f;
+          Pp = v3(0.f, 0.f, 0.f) - O;
+          wp = vp = ap = v3(0.f, 0.f, 0.f);
+          lp = v3(0.f, 0.f, 0.f) - g;
+        }
+        const float *E = M.jrot + 9 * i;
+        float RJ[9];
+        for (int r = 0; r < 3; ++r)
+          for (int c = 0; c < 3; ++c)
+            RJ[3 * r + c] = Rp[3 * r] * E[c] + Rp[3 * r + 1] * E[3 + c] + Rp[3 * r + 2] * E[6 + c];
+        V3 Pi = Pp + mulR(Rp, ld3(M.jpos + 3 * i));
+        V3 ax = ld3(M.axis + 3 * i);
+        V3 ah = mulR(RJ, ax);
+        float qi = q[M.qadr[i]];
+        float *S = Sl + 6 * da;
+        V3 sw, sv;
+        if (jt == 0) {
+          float sn, cs;
+          sincosf(qi, &sn, &cs);
+          float vc = 1.0f - cs;
+          float Q[9] = {cs + ax.x * ax.x * vc, ax.x * ax.y * vc - ax.z * sn, ax.x * ax.z * vc + ax.y * sn,
+                        ax.y * ax.x * vc + ax.z * sn, cs + ax.y * ax.y * vc, ax.y * ax.z * vc - ax.x * sn,
+                        ax.z * ax.x * vc - ax.y * sn, ax.z * ax.y * vc + ax.x * sn, cs + ax.z * ax.z * vc};
+          for (int r = 0; r < 3; ++r)
+            for (int c = 0; c < 3; ++c)
+              R[3 * r + c] = RJ[3 * r] * Q[c] + RJ[3 * r + 1] * Q[3 + c] + RJ[3 * r + 2] * Q[6 + c];
+          sw = ah;
+          sv = cross(Pi, ah);
+        } else {
+          for (int e = 0; e < 9; ++e) R[e] = RJ[e];
+          Pi = Pi + qi * ah;
+          sw = v3(0.f, 0.f, 0.f);
+          sv = ah;
+        }
+        st3(Pl + 3 * i, Pi);
+        st3(S, sw);
+        st3(S + 3, sv);
+        const float qdi = qd[da];
+        V3 xw = qdi * sw, xv = qdi * sv;  // S qd
+        float *V = Vl + 6 * i, *A = Al + 6 * i;
+        st3(V, wp + xw);
+        st3(V + 3, vp + xv);
+        // A = A_p + V_p x (S qd)
+        st3(A, ap + cross(wp, xw));
+        st3(A + 3, lp + cross(wp, xv) + cross(vp, xw));
+      }
+      __syncthreads();
+    }
+
+    // ------------------------------------------------------------- contacts
+    for (int c = lane; c < M.n_con; c += 64) {
+      float *C = Cl + 16 * c;
+      const int b = M.con_node[c];
+      V3 w = mulR(Rl + 9 * b, ld3(M.con_pos + 3 * c)) + ld3(Pl + 3 * b);
+      const float rho = M.con_radius[c];
+      const float pen = rho - (w.z + O.z);
+      for (int e = 0; e < 16; ++e) C[e] = 0.f;
+      if (Rn.contact && pen > 0.f) {
+        V3 cp = w - v3(0.f, 0.f, rho);
+        V3 vel = ld3(Vl + 6 * b + 3) + cross(ld3(Vl + 6 * b), cp);
+        // spring taken linearly implicitly over the step: damping c + dt k
+        const float ceff = M.cc + dt * M.kc;
+        float fn = fmaxf(0.f, M.kc * pen - ceff * vel.z);
+        float s2 = vel.x * vel.x + vel.y * vel.y + M.vs * M.vs;
+        float s = sqrtf(s2);
+        V3 f = v3(-M.mu * fn * vel.x / s, -M.mu * fn * vel.y / s, fn);
+        C[0] = 1.f;
+        st3(C + 1, cp);
+        st3(C + 4, cross(cp, f));
+        st3(C + 7, f);
+        if (fn > 0.f) {
+          float gg = M.mu * fn / s;
+          C[10] = gg * (1.f - vel.x * vel.x / s2);
+          C[11] = -gg * vel.x * vel.y / s2;
+          C[12] = gg * (1.f - vel.y * vel.y / s2);
+          C[13] = ceff;
+        }
+      }
+    }
+
+    // ------------------------------------- recursive Newton-Euler bias forces
+    for (int b = lane; b < M.n_body; b += 64) {
+      const int i = M.body_node[b];
+      const float *R = Rl + 9 * i;
+      const float m = M.body_mass[b];
+      V3 c = mulR(R, ld3(M.body_com + 3 * b)) + ld3(Pl + 3 * i);
+      V3 h = m * c;
+      const float I0 = M.body_inertia[3 * b], I1 = M.body_inertia[3 * b + 1], I2 = M.body_inertia[3 * b + 2];
+      // I_O = R diag(I) R^T + m (|c|^2 1 - c c^T)
+      float Io[9];
+      const float cc = dot(c, c);
+      const float cv[3] = {c.x, c.y, c.z};
+      for (int r = 0; r < 3; ++r)
+        for (int s = 0; s < 3; ++s)
+          Io[3 * r + s] = R[3 * r] * I0 * R[3 * s] + R[3 * r + 1] * I1 * R[3 * s + 1] +
+                          R[3 * r + 2] * I2 * R[3 * s + 2] + m * ((r == s ? cc : 0.f) - cv[r] * cv[s]);
+      V3 w = ld3(Vl + 6 * i), v = ld3(Vl + 6 * i + 3);
+      V3 aw = ld3(Al + 6 * i), al = ld3(Al + 6 * i + 3);
+      // I (w; v) = (I_O w + h x v; m v - h x w)
+      V3 Iaw = mulR(Io, aw) + cross(h, al), Ial = m * al - cross(h, aw);
+      V3 Ivw = mulR(Io, w) + cross(h, v), Ivl = m * v - cross(h, w);
+      // f = I a + v x* (I v), (w, v) x* (n, f) = (w x n + v x f, w x f)
+      V3 fw = Iaw + cross(w, Ivw) + cross(v, Ivl);
+      V3 fl = Ial + cross(w, Ivl);
+      st3(Fl + 6 * b, fw);
+      st3(Fl + 6 * b + 3, fl);
+    }
+    __syncthreads();
+    float *Fn = Fl + 6 * M.n_body;
+    for (int t = lane; t < 6 * nn; t += 64) {
+      const int n = t / 6, k = t % 6;
+      float s = 0.f;
+      for (int e = M.subb_start[n]; e < M.subb_start[n + 1]; ++e) s += Fl[6 * M.subb[e] + k];
+      for (int e = M.subc_start[n]; e < M.subc_start[n + 1]; ++e) s -= Cl[16 * M.subc[e] + 4 + k];
+      Fn[t] = s;
+    }
+    __syncthreads();
+    for (int j = lane; j < nv; j += 64) {
+      const float *S = Sl + 6 * j;
+      const float *F = Fn + 6 * M.dof_node[j];
+      float cb = S[0] * F[0] + S[1] * F[1] + S[2] * F[2] + S[3] * F[3] + S[4] * F[4] + S[5] * F[5];
+      if (STAGES) Rn.o_bias[(size_t)env * nv + j] = cb;
+      rhs[j] = (double)(-cb - M.damping[j] * qd[j]);
+    }
+    __syncthreads();
+
+    // ---------------------------------- composite-rigid-body mass matrix (FP64)
+    {
+      double *BI = (double *)scr;                  // [n_body][10]: m, h, I_O (xx xy xz yy yz zz)
+      double *CI = BI + 10 * M.n_body;             // [n_node][10]
+      double *FJ = CI + 10 * nn;                   // [nv][6]
+      for (int b = lane; b < M.n_body; b += 64) {
+        const int i = M.body_node[b];
+        const float *R = Rl + 9 * i;
+        const double m = M.body_mass[b];
+        V3 cf = mulR(R, ld3(M.body_com + 3 * b)) + ld3(Pl + 3 * i);
+        const double c[3] = {cf.x, cf.y, cf.z};
+        const double In[3] = {M.body_inertia[3 * b], M.body_inertia[3 * b + 1], M.body_inertia[3 * b + 2]};
+        double *o = BI + 10 * b;
+        o[0] = m;
+        o[1] = m * c[0]; o[2] = m * c[1]; o[3] = m * c[2];
+        const double cc = c[0] * c[0] + c[1] * c[1] + c[2] * c[2];
+        const int rr[6] = {0, 0, 0, 1, 1, 2}, ss[6] = {0, 1, 2, 1, 2, 2};
+        for (int e = 0; e < 6; ++e) {
+          int r = rr[e], s = ss[e];
+          double v = (double)R[3 * r] * In[0] * R[3 * s] + (double)R[3 * r + 1] * In[1] * R[3 * s + 1] +
+                     (double)R[3 * r + 2] * In[2] * R[3 * s + 2];
+          o[4 + e] = v + m * ((r == s ? cc : 0.0) - c[r] * c[s]);
+        }
+      }
+      __syncthreads();
+      for (int t = lane; t < 10 * nn; t += 64) {
+        const int n = t / 10, k = t % 10;
+        double s = 0.0;
+        for (int e = M.subb_start[n]; e < M.subb_start[n + 1]; ++e) s += BI[10 * M.subb[e] + k];
+        CI[t] = s;
+      }
+      __syncthreads();
+      for (int j = lane; j < nv; j += 64) {
+        const int n = M.dof_node[j];
+        const double *I = CI + 10 * n;
+        const float *Sf = Sl + 6 * j;
+        const double w[3] = {Sf[0], Sf[1], Sf[2]}, v[3] = {Sf[3], Sf[4], Sf[5]};
+        const double m = I[0], h[3] = {I[1], I[2], I[3]};
+        const double Io[9] = {I[4], I[5], I[6], I[5], I[7], I[8], I[6], I[8], I[9]};
+        double f[6];
+        // (I_O w + h x v ; m v - h x w)
+        f[0] = Io[0] * w[0] + Io[1] * w[1] + Io[2] * w[2] + (h[1] * v[2] - h[2] * v[1]);
+        f[1] = Io[3] * w[0] + Io[4] * w[1] + Io[5] * w[2] + (h[2] * v[0] - h[0] * v[2]);
+        f[2] = Io[6] * w[0] + Io[7] * w[1] + Io[8] * w[2] + (h[0] * v[1] - h[1] * v[0]);
+        f[3] = m * v[0] - (h[1] * w[2] - h[2] * w[1]);
+        f[4] = m * v[1] - (h[2] * w[0] - h[0] * w[2]);
+        f[5] = m * v[2] - (h[0] * w[1] - h[1] * w[0]);
+        // implicit contact damping: dt * Phi^T D Phi S for contacts below
+        for (int e = M.subc_start[n]; e < M.subc_start[n + 1]; ++e) {
+          const float *C = Cl + 16 * M.subc[e];
+          if (C[0] == 0.f) continue;
+          const double cp[3] = {C[1], C[2], C[3]};
+          // point velocity of the contact for unit qd_j: v + w x cp
+          const double J[3] = {v[0] + w[1] * cp[2] - w[2] * cp[1], v[1] + w[2] * cp[0] - w[0] * cp[2],
+                               v[2] + w[0] * cp[1] - w[1] * cp[0]};
+          const double u0 = (double)C[10] * J[0] + (double)C[11] * J[1];
+          const double u1 = (double)C[11] * J[0] + (double)C[12] * J[1];
+          const double u2 = (double)C[13] * J[2];
+          const double dd = dt;
+          f[0] += dd * (cp[1] * u2 - cp[2] * u1);
+          f[1] += dd * (cp[2] * u0 - cp[0] * u2);
+          f[2] += dd * (cp[0] * u1 - cp[1] * u0);
+          f[3] += dd * u0;
+          f[4] += dd * u1;
+          f[5] += dd * u2;
+        }
+        for (int k = 0; k < 6; ++k) FJ[6 * j + k] = f[k];
+      }
+      __syncthreads();
+      for (int e = lane; e < M.nnz; e += 64) {
+        const int j = M.nnz_row[e], i = M.path[e];
+        const float *Sf = Sl + 6 * i;
+        const double *f = FJ + 6 * j;
+        double h = (double)Sf[0] * f[0] + (double)Sf[1] * f[1] + (double)Sf[2] * f[2] +
+                   (double)Sf[3] * f[3] + (double)Sf[4] * f[4] + (double)Sf[5] * f[5];
+        if (i == j) h += (double)dt * M.damping[j];
+        H[e] = h;
+      }
+      __syncthreads();
+    }
+
+    // --------------------------- muscle geometry, Hill force, J_m^T F, damping
+    {
+      float *mr = (float *)scr;          // [n_mus][3]
+      float *mF = mr + 3 * nm;           // [n_mus]
+      float *mc = mF + nm;               // [n_mus]
+      // geometry: one muscle per lane and iteration (L, Ldot parked in mF, mc)
+#pragma unroll 1
+      for (int m = lane; m < nm; m += 64) {
+        const int P = M.mus_nvia[m];
+        // via-points in registers: loops run to the compile-time maximum
+        V3 w[kMaxVia], gk[kMaxVia];
+#pragma unroll
+        for (int k = 0; k < kMaxVia; ++k) {
+          w[k] = v3(0.f, 0.f, 0.f);
+          if (k < P) {
+            const int b = M.via_node[(size_t)k * nm + m];
+            V3 x = v3(M.via_pos[((size_t)k * 3 + 0) * nm + m], M.via_pos[((size_t)k * 3 + 1) * nm + m],
+                      M.via_pos[((size_t)k * 3 + 2) * nm + m]);
+            w[k] = b >= 0 ? mulR(Rl + 9 * b, x) + ld3(Pl + 3 * b) : x - O;
+          }
+        }
+        float L = 0.f;
+        V3 eprev = v3(0.f, 0.f, 0.f);
+#pragma unroll
+        for (int k = 0; k < kMaxVia; ++k) {
+          gk[k] = v3(0.f, 0.f, 0.f);
+          if (k + 1 < P) {
+            V3 d = w[k + 1] - w[k];
+            float l = sqrtf(dot(d, d));
+            L += l;
+            V3 e = (1.0f / l) * d;
+            gk[k] = eprev - e;
+            eprev = e;
+          } else if (k + 1 == P) {
+            gk[k] = eprev;
+          }
+        }
+        const unsigned mask = M.mus_mask[m];
+        float Ld = 0.f;
+        float r3[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+        for (int s = 0; s < 3; ++s) {
+          const int j = M.mus_span[s * nm + m];
+          if (j >= 0) {
+            const unsigned mk = (mask >> (8 * s)) & 0xFFu;
+            const float *S = Sl + 6 * j;
+            float dl;
+            if (M.dof_kind[j] == 0) {
+              V3 o = ld3(Pl + 3 * M.dof_node[j]);
+              V3 acc = v3(0.f, 0.f, 0.f);
+#pragma unroll
+              for (int k = 0; k < kMaxVia; ++k)
+                if ((mk >> k) & 1u) acc = acc + cross(w[k] - o, gk[k]);
+              dl = dot(ld3(S), acc);
+            } else {
+              V3 acc = v3(0.f, 0.f, 0.f);
+#pragma unroll
+              for (int k = 0; k < kMaxVia; ++k)
+                if ((mk >> k) & 1u) acc = acc + gk[k];
+              dl = dot(ld3(S + 3), acc);
+            }
+            r3[s] = -dl;
+            Ld += dl * qd[j];
+          }
+        }
+        mr[3 * m] = r3[0];
+        mr[3 * m + 1] = r3[1];
+        mr[3 * m + 2] = r3[2];
+        mF[m] = L;
+        mc[m] = Ld;
+        if (STAGES) {
+          const size_t o = (size_t)env * nm + m;
+          Rn.o_L[o] = L;
+          Rn.o_Ldot[o] = Ld;
+          Rn.o_r[3 * o] = r3[0];
+          Rn.o_r[3 * o + 1] = r3[1];
+          Rn.o_r[3 * o + 2] = r3[2];
+        }
+      }
+      // Hill force and its velocity slope (the same lane re-reads its muscles)
+#pragma unroll
+      for (int t = 0; t < MPL; ++t) {
+        const int m = lane + 64 * t;
+        if (m >= nm) continue;
+        const float L = mF[m], Ld = mc[m];
+        const float lm = (L - M.mus_lslack[m]) * M.mus_ilopt[m];
+        const float vm = Ld * M.mus_ivl[m];
+        const float fl = hill_fl(lm), fv = hill_fv(vm), fp = hill_fp(lm);
+        const float f0 = M.mus_f0[m];
+        const float F = f0 * (act1[t] * fl * fv + fp);
+        const float cdamp = f0 * act1[t] * fl * hill_fv_slope(vm) * M.mus_ivl[m];
+        mF[m] = F;
+        mc[m] = cdamp;
+        if (STAGES) Rn.o_F[(size_t)env * nm + m] = F;
+      }
+      __syncthreads();
+      for (int j = lane; j < nv; j += 64) {
+        float tau = 0.f;
+        for (int e = M.proj_start[j]; e < M.proj_start[j + 1]; ++e) {
+          const int it = M.proj_item[e];
+          tau += mr[it] * mF[it / 3];
+        }
+        if (STAGES) Rn.o_tau[(size_t)env * nv + j] = tau;
+        rhs[j] += (double)tau;
+      }
+      for (int e = lane; e < M.n_dent; e += 64) {
+        double s = 0.0;
+        for (int k = M.dent_start[e]; k < M.dent_start[e + 1]; ++k) {
+          const int it = M.dent_item[k];
+          const int m = it >> 4, a = (it >> 2) & 3, b = it & 3;
+          s += (double)mc[m] * (double)mr[3 * m + a] * (double)mr[3 * m + b];
+        }
+        H[M.dent_h[e]] += (double)dt * s;
+      }
+      __syncthreads();
+    }
+    if (STAGES) {
+      for (int e = lane; e < M.nnz; e += 64) Rn.o_H[(size_t)env * M.nnz + e] = H[e];
+    }
+
+    // ------------------------------------------------ LTDL factorisation (FP64)
+    if (lane == 0) flag[0] = 0;
+    __syncthreads();
+    for (int k = nv - 1; k >= 0; --k) {
+      const int rk = M.row_start[k], dk = M.dof_depth[k];
+      const double d = H[rk + dk - 1];
+      if (!(d > 0.0)) {
+        if (lane == 0) flag[0] = 1;
+        break;
+      }
+      const double inv = 1.0 / d;
+      const int np = (dk - 1) * dk / 2;
+      for (int pp = lane; pp < np; pp += 64) {
+        const int ab = M.pair_ab[pp];
+        const int a = ab & 0xFF, b = ab >> 8;
+        const int i = M.path[rk + a];
+        H[M.row_start[i] + b] -= H[rk + a] * H[rk + b] * inv;
+      }
+      __syncthreads();
+    }
+    __syncthreads();
+    const bool nonspd = flag[0] != 0;
+    if (!nonspd) {
+      // L = H / d (row-wise), keep d on the diagonal
+      for (int e = lane; e < M.nnz; e += 64) {
+        const int j = M.nnz_row[e];
+        if (M.path[e] != j) H[e] /= H[M.row_start[j] + M.dof_depth[j] - 1];
+      }
+      for (int j = lane; j < nv; j += 64) xs[j] = rhs[j];
+      __syncthreads();
+      // L^T y = b (leaves first)
+      for (int k = nv - 1; k >= 0; --k) {
+        const int rk = M.row_start[k], dk = M.dof_depth[k];
+        const double yk = xs[k];
+        for (int a = lane; a < dk - 1; a += 64) xs[M.path[rk + a]] -= H[rk + a] * yk;
+        __syncthreads();
+      }
+      for (int j = lane; j < nv; j += 64) xs[j] /= H[M.row_start[j] + M.dof_depth[j] - 1];
+      __syncthreads();
+      // L x = z (root first)
+      for (int k = 0; k < nv; ++k) {
+        const int rk = M.row_start[k], dk = M.dof_depth[k];
+        double s = 0.0;
+        for (int a = lane; a < dk - 1; a += 64) s += H[rk + a] * xs[M.path[rk + a]];
+        s = wave_sum(s);
+        if (lane == 0) xs[k] -= s;
+        __syncthreads();
+      }
+    }
+
+    // ----------------------------------------------- semi-implicit Euler update
+    if (STAGES) {
+      for (int j = lane; j < nv; j += 64) Rn.o_qdd[(size_t)env * nv + j] = nonspd ? NAN : (float)xs[j];
+      break;
+    }
+    if (nonspd) {
+      status |= MS_ST_NONSPD;
+      continue;
+    }
+    // new velocities and hinge/slide positions in registers, checked first
+    float qdn[2], qn[2];
+    bool badn = false;
+    for (int t = 0; t < 2; ++t) {
+      const int j = lane + 64 * t;
+      qdn[t] = 0.f;
+      qn[t] = 0.f;
+      if (j < nv) {
+        qdn[t] = qd[j] + dt * (float)xs[j];
+        badn |= !isfinite(qdn[t]);
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < MPL; ++t) badn |= !isfinite(act1[t]);
+    badn = __any(badn);
+    if (badn) {
+      status |= MS_ST_NONFINITE;
+      continue;
+    }
+    __syncthreads();
+    for (int t = 0; t < 2; ++t) {
+      const int j = lane + 64 * t;
+      if (j < nv) qd[j] = qdn[t];
+    }
+    __syncthreads();
+    // positions: each node's q from its own DoFs
+    for (int i = lane; i < nn; i += 64) {
+      const int a = M.qadr[i], d = M.dadr[i];
+      if (M.jtype[i] != 2) {
+        qn[0] = q[a] + dt * qd[d];
+        q[a] = qn[0];
+        continue;
+      }
+      for (int k = 0; k < 3; ++k) q[a + k] = q[a + k] + dt * qd[d + k];
+      float th[3] = {qd[d + 3] * dt, qd[d + 4] * dt, qd[d + 5] * dt};
+      float ang = sqrtf(th[0] * th[0] + th[1] * th[1] + th[2] * th[2]);
+      float dq[4];
+      if (ang < 1e-8f) {
+        dq[0] = 1.f; dq[1] = 0.5f * th[0]; dq[2] = 0.5f * th[1]; dq[3] = 0.5f * th[2];
+      } else {
+        float sn, cs;
+        sincosf(0.5f * ang, &sn, &cs);
+        float sc = sn / ang;
+        dq[0] = cs; dq[1] = sc * th[0]; dq[2] = sc * th[1]; dq[3] = sc * th[2];
+      }
+      float *x = q + a + 3;
+      float o0 = x[0] * dq[0] - x[1] * dq[1] - x[2] * dq[2] - x[3] * dq[3];
+      float o1 = x[0] * dq[1] + x[1] * dq[0] + x[2] * dq[3] - x[3] * dq[2];
+      float o2 = x[0] * dq[2] - x[1] * dq[3] + x[2] * dq[0] + x[3] * dq[1];
+      float o3 = x[0] * dq[3] + x[1] * dq[2] - x[2] * dq[1] + x[3] * dq[0];
+      float nrm = sqrtf(o0 * o0 + o1 * o1 + o2 * o2 + o3 * o3);
+      x[0] = o0 / nrm; x[1] = o1 / nrm; x[2] = o2 / nrm; x[3] = o3 / nrm;
+    }
+#pragma unroll
+    for (int t = 0; t < MPL; ++t) act[t] = act1[t];
+    __syncthreads();
+  }
+
+  if (STAGES) return;
+  for (int i = lane; i < nq; i += 64) Rn.q[(size_t)env * nq + i] = q[i];
+  for (int i = lane; i < nv; i += 64) Rn.qd[(size_t)env * nv + i] = qd[i];
+#pragma unroll
+  for (int t = 0; t < MPL; ++t) {
+    const int mi = lane + 64 * t;
+    if (mi < nm) {
+      Rn.act[(size_t)env * nm + mi] = act[t];
+      if (EXC == EXC_AR1) Rn.xar[(size_t)env * nm + mi] = xar[t];
+    }
+  }
+  if (Rn.status && lane == 0) Rn.status[env] = status;
+}
+
+}  // namespace ms
+
+// =============================================================== host / ABI
+struct ms_model {
+  ms::Tables t;
+  ms::KModel k;
+  void *dbuf = nullptr;
+  size_t dbytes = 0;
+};
+
+namespace {
+thread_local std::string g_err;
+
+ms_status fail(ms_status s, const std::string &m) {
+  g_err = m;
+  return s;
+}
+
+struct Packer {
+  std::vector<unsigned char> buf;
+  template <class T>
+  size_t add(const std::vector<T> &v) {
+    size_t off = (buf.size() + 255) & ~size_t(255);
+    buf.resize(off + std::max<size_t>(v.size() * sizeof(T), 4));
+    if (!v.empty()) std::memcpy(buf.data() + off, v.data(), v.size() * sizeof(T));
+    return off;
+  }
+};
+
+template <int MPL, int EXC, bool STAGES>
+hipError_t launch_mpl(const ms_model *m, const ms::KRun &r, int n_env, int n_steps, hipStream_t st) {
+  if (m->t.lds_bytes > 65536) {
+    hipError_t e = hipFuncSetAttribute((const void *)&ms::k_step<MPL, EXC, STAGES>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, m->t.lds_bytes);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL((ms::k_step<MPL, EXC, STAGES>), dim3(n_env), dim3(64), m->t.lds_bytes, st, m->k,
+                     r, n_steps);
+  return hipGetLastError();
+}
+
+template <int EXC, bool STAGES>
+hipError_t launch(const ms_model *m, const ms::KRun &r, int n_env, int n_steps, hipStream_t st) {
+  const int mpl = m->t.mpl;
+  if (mpl <= 1) return launch_mpl<1, EXC, STAGES>(m, r, n_env, n_steps, st);
+  if (mpl <= 2) return launch_mpl<2, EXC, STAGES>(m, r, n_env, n_steps, st);
+  if (mpl <= 4) return launch_mpl<4, EXC, STAGES>(m, r, n_env, n_steps, st);
+  if (mpl <= 8) return launch_mpl<8, EXC, STAGES>(m, r, n_env, n_steps, st);
+  if (mpl <= 12) return launch_mpl<12, EXC, STAGES>(m, r, n_env, n_steps, st);
+  return launch_mpl<16, EXC, STAGES>(m, r, n_env, n_steps, st);
+}
+
+ms_status check_opts(const ms_step_opts *o) {
+  if (!o) return fail(MS_E_ARG, "opts is NULL");
+  if (!(o->dt > 0.0f) || !std::isfinite(o->dt)) return fail(MS_E_ARG, "dt must be positive and finite");
+  return MS_OK;
+}
+}  // namespace
+
+extern "C" {
+
+const char *ms_last_error(void) { return g_err.c_str(); }
+
+ms_status ms_model_create(const ms_model_desc *desc, ms_model **out) {
+  g_err.clear();
+  if (!out) return fail(MS_E_ARG, "out is NULL");
+  *out = nullptr;
+  ms_model *m = new (std::nothrow) ms_model();
+  if (!m) return fail(MS_E_ALLOC, "host allocation failed");
+  std::string msg;
+  ms_status s = ms::build_tables(desc, &m->t, &msg);
+  if (s != MS_OK) {
+    delete m;
+    return fail(s, msg);
+  }
+  const ms::Tables &t = m->t;
+  if (t.nv > 128) {
+    delete m;
+    return fail(MS_E_UNSUPPORTED, "more than 128 DoFs");
+  }
+  if (t.lds_bytes > 160 * 1024) {
+    delete m;
+    return fail(MS_E_UNSUPPORTED, "model needs more than 160 KiB of LDS per environment");
+  }
+  Packer p;
+  size_t o_parent = p.add(t.parent), o_jtype = p.add(t.jtype), o_qadr = p.add(t.qadr),
+         o_dadr = p.add(t.dadr), o_ls = p.add(t.level_start), o_ln = p.add(t.level_nodes),
+         o_jpos = p.add(t.jpos), o_jrot = p.add(t.jrot), o_axis = p.add(t.axis),
+         o_bnode = p.add(t.body_node), o_bmass = p.add(t.body_mass), o_bcom = p.add(t.body_com),
+         o_bin = p.add(t.body_inertia), o_sbs = p.add(t.subb_start), o_sb = p.add(t.subb),
+         o_scs = p.add(t.subc_start), o_sc = p.add(t.subc), o_cn = p.add(t.con_node),
+         o_cp = p.add(t.con_pos), o_cr = p.add(t.con_radius), o_dn = p.add(t.dof_node),
+         o_dk = p.add(t.dof_kind), o_damp = p.add(t.damping), o_f0 = p.add(t.mus_f0),
+         o_il = p.add(t.mus_ilopt), o_ls2 = p.add(t.mus_lslack), o_ivl = p.add(t.mus_ivl),
+         o_ta = p.add(t.mus_tact), o_td = p.add(t.mus_tdeact), o_nvia = p.add(t.mus_nvia),
+         o_vn = p.add(t.via_node), o_vp = p.add(t.via_pos), o_span = p.add(t.mus_span),
+         o_mask = p.add(t.mus_mask), o_ps = p.add(t.proj_start), o_pi = p.add(t.proj_item),
+         o_dh = p.add(t.dent_h), o_ds = p.add(t.dent_start), o_di = p.add(t.dent_item),
+         o_rs = p.add(t.row_start), o_dd = p.add(t.dof_depth), o_path = p.add(t.path),
+         o_nr = p.add(t.nnz_row), o_pab = p.add(t.pair_ab);
+  m->dbytes = p.buf.size();
+  hipError_t e = hipMalloc(&m->dbuf, m->dbytes);
+  if (e != hipSuccess) {
+    std::string es = hipGetErrorString(e);
+    delete m;
+    return fail(MS_E_ALLOC, "hipMalloc: " + es);
+  }
+  e = hipMemcpy(m->dbuf, p.buf.data(), m->dbytes, hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    std::string es = hipGetErrorString(e);
+    (void)hipFree(m->dbuf);
+    delete m;
+    return fail(MS_E_HIP, "hipMemcpy: " + es);
+  }
+  unsigned char *b = (unsigned char *)m->dbuf;
+  ms::KModel &k = m->k;
+  k.n_node = t.n_node; k.nq = t.nq; k.nv = t.nv; k.n_mus = t.n_mus; k.n_con = t.n_con;
+  k.n_body = t.n_body; k.nnz = t.nnz; k.n_level = t.n_level; k.free_root = t.free_root;
+  k.n_dent = t.n_dent;
+  k.kc = t.kc; k.cc = t.cc; k.mu = t.mu; k.vs = t.vs; k.gx = t.g[0]; k.gy = t.g[1]; k.gz = t.g[2];
+#define P_(field, off, T) k.field = (const T *)(b + off)
+  P_(parent, o_parent, int); P_(jtype, o_jtype, int); P_(qadr, o_qadr, int); P_(dadr, o_dadr, int);
+  P_(level_start, o_ls, int); P_(level_nodes, o_ln, int); P_(jpos, o_jpos, float);
+  P_(jrot, o_jrot, float); P_(axis, o_axis, float); P_(body_node, o_bnode, int);
+  P_(body_mass, o_bmass, float); P_(body_com, o_bcom, float); P_(body_inertia, o_bin, float);
+  P_(subb_start, o_sbs, int); P_(subb, o_sb, int); P_(subc_start, o_scs, int); P_(subc, o_sc, int);
+  P_(con_node, o_cn, int); P_(con_pos, o_cp, float); P_(con_radius, o_cr, float);
+  P_(dof_node, o_dn, int); P_(dof_kind, o_dk, int); P_(damping, o_damp, float);
+  P_(mus_f0, o_f0, float); P_(mus_ilopt, o_il, float); P_(mus_lslack, o_ls2, float);
+  P_(mus_ivl, o_ivl, float); P_(mus_tact, o_ta, float); P_(mus_tdeact, o_td, float);
+  P_(mus_nvia, o_nvia, int); P_(via_node, o_vn, int); P_(via_pos, o_vp, float);
+  P_(mus_span, o_span, int); P_(mus_mask, o_mask, unsigned); P_(proj_start, o_ps, int);
+  P_(proj_item, o_pi, int); P_(dent_h, o_dh, int); P_(dent_start, o_ds, int);
+  P_(dent_item, o_di, int); P_(row_start, o_rs, int); P_(dof_depth, o_dd, int);
+  P_(path, o_path, int); P_(nnz_row, o_nr, int); P_(pair_ab, o_pab, int);
+#undef P_
+  k.off_flag = t.off_flag; k.off_q = t.off_q; k.off_qd = t.off_qd; k.off_R = t.off_R;
+  k.off_P = t.off_P; k.off_S = t.off_S; k.off_con = t.off_con; k.off_rhs = t.off_rhs;
+  k.off_x = t.off_x; k.off_H = t.off_H; k.off_scr = t.off_scr; k.off_V = t.off_V;
+  k.off_A = t.off_A; k.off_F = t.off_F;
+  *out = m;
+  return MS_OK;
+}
+
+void ms_model_destroy(ms_model *m) {
+  if (!m) return;
+  if (m->dbuf) (void)hipFree(m->dbuf);
+  delete m;
+}
+
+ms_status ms_model_info_get(const ms_model *m, ms_model_info *o) {
+  if (!m || !o) return fail(MS_E_ARG, "NULL argument");
+  o->nq = m->t.nq; o->nv = m->t.nv; o->n_node = m->t.n_node; o->n_mus = m->t.n_mus;
+  o->n_con = m->t.n_con; o->n_body = m->t.n_body; o->max_dof_depth = m->t.max_depth;
+  o->nnz_mass = m->t.nnz; o->lds_bytes = m->t.lds_bytes;
+  return MS_OK;
+}
+
+ms_status ms_model_spans(const ms_model *m, int32_t *spans) {
+  if (!m || !spans) return fail(MS_E_ARG, "NULL argument");
+  const int nm = m->t.n_mus;
+  for (int i = 0; i < nm; ++i)
+    for (int s = 0; s < 3; ++s) spans[3 * i + s] = m->t.mus_span[(size_t)s * nm + i];
+  return MS_OK;
+}
+
+ms_status ms_model_mass_pattern(const ms_model *m, int32_t *rows, int32_t *cols) {
+  if (!m || !rows || !cols) return fail(MS_E_ARG, "NULL argument");
+  for (int e = 0; e < m->t.nnz; ++e) {
+    rows[e] = m->t.nnz_row[e];
+    cols[e] = m->t.path[e];
+  }
+  return MS_OK;
+}
+
+static ms_status common_checks(const ms_model *m, int32_t n_env, const void *q, const void *qd,
+                               const void *act, const ms_step_opts *o) {
+  if (!m) return fail(MS_E_ARG, "model is NULL");
+  if (n_env <= 0) return fail(MS_E_ARG, "n_env must be > 0");
+  if (!q || !qd || (!act && m->t.n_mus > 0)) return fail(MS_E_ARG, "a state pointer is NULL");
+  return check_opts(o);
+}
+
+static ms_status hip_status(hipError_t e) {
+  if (e != hipSuccess) return fail(MS_E_HIP, std::string("kernel launch: ") + hipGetErrorString(e));
+  return MS_OK;
+}
+
+ms_status ms_step_batch(ms_model *m, int32_t n_env, float *q, float *qd, float *act,
+                        uint32_t *status, const float *u, const ms_step_opts *opts, void *stream) {
+  g_err.clear();
+  ms_status s = common_checks(m, n_env, q, qd, act, opts);
+  if (s != MS_OK) return s;
+  if (!u && m->t.n_mus > 0) return fail(MS_E_ARG, "u is NULL");
+  ms::KRun r{};
+  r.q = q; r.qd = qd; r.act = act; r.status = status; r.u = u; r.n_env = n_env;
+  r.dt = opts->dt; r.contact = opts->contact;
+  return hip_status(launch<ms::EXC_ARRAY, false>(m, r, n_env, 1, (hipStream_t)stream));
+}
+
+ms_status ms_rollout(ms_model *m, int32_t n_env, float *q, float *qd, float *act,
+                     uint32_t *status, const ms_excitation *exc, int32_t n_steps,
+                     const ms_step_opts *opts, void *stream) {
+  g_err.clear();
+  ms_status s = common_checks(m, n_env, q, qd, act, opts);
+  if (s != MS_OK) return s;
+  if (!exc) return fail(MS_E_ARG, "exc is NULL");
+  if (n_steps < 0) return fail(MS_E_ARG, "n_steps must be >= 0");
+  if (n_steps == 0) return MS_OK;
+  ms::KRun r{};
+  r.q = q; r.qd = qd; r.act = act; r.status = status; r.n_env = n_env;
+  r.dt = opts->dt; r.contact = opts->contact;
+  r.u = exc->u; r.seed = exc->seed; r.step0 = exc->step0; r.xar = exc->x;
+  r.rho = exc->rho; r.s = exc->s; r.mean = exc->mean;
+  hipStream_t st = (hipStream_t)stream;
+  switch (exc->kind) {
+    case MS_EXC_ARRAY:
+      if (!exc->u && m->t.n_mus > 0) return fail(MS_E_ARG, "exc->u is NULL");
+      return hip_status(launch<ms::EXC_ARRAY, false>(m, r, n_env, n_steps, st));
+    case MS_EXC_IID:
+      return hip_status(launch<ms::EXC_IID, false>(m, r, n_env, n_steps, st));
+    case MS_EXC_AR1:
+      if (!exc->x && m->t.n_mus > 0) return fail(MS_E_ARG, "exc->x is NULL");
+      return hip_status(launch<ms::EXC_AR1, false>(m, r, n_env, n_steps, st));
+    default:
+      return fail(MS_E_ARG, "unknown excitation kind");
+  }
+}
+
+ms_status ms_step_stages(ms_model *m, int32_t n_env, const float *q, const float *qd,
+                         const float *act, const float *u, const ms_step_opts *opts,
+                         ms_stage_out *out, void *stream) {
+  g_err.clear();
+  ms_status s = common_checks(m, n_env, q, qd, act, opts);
+  if (s != MS_OK) return s;
+  if (!out || !out->act || !out->L || !out->Ldot || !out->F || !out->r || !out->tau_mus ||
+      !out->bias_minus_ext || !out->qdd || !out->mass)
+    return fail(MS_E_ARG, "every stage output buffer is required");
+  if (!u && m->t.n_mus > 0) return fail(MS_E_ARG, "u is NULL");
+  ms::KRun r{};
+  r.q = const_cast<float *>(q); r.qd = const_cast<float *>(qd); r.act = const_cast<float *>(act);
+  r.status = nullptr; r.u = u; r.n_env = n_env; r.dt = opts->dt; r.contact = opts->contact;
+  r.o_act = out->act; r.o_L = out->L; r.o_Ldot = out->Ldot; r.o_F = out->F; r.o_r = out->r;
+  r.o_tau = out->tau_mus; r.o_bias = out->bias_minus_ext; r.o_qdd = out->qdd; r.o_H = out->mass;
+  return hip_status(launch<ms::EXC_ARRAY, true>(m, r, n_env, 1, (hipStream_t)stream));
+}
+
+}  // extern "C"

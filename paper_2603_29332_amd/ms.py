@@ -1,0 +1,208 @@
+"""ctypes binding of libms.so (argument marshalling only).
+
+Every step of the path runs in the library's HIP kernels; this module only
+converts a model dict into the C description, hands device pointers of torch
+tensors to the C ABI and raises on error status. It fails loudly when the
+library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libms.so")
+
+MS_ST_NONFINITE = 1
+MS_ST_NONSPD = 2
+EXC_ARRAY, EXC_IID, EXC_AR1 = 0, 1, 2
+
+EXPORTED = ("ms_model_create", "ms_model_destroy", "ms_model_info_get",
+            "ms_step_batch", "ms_rollout", "ms_step_stages", "ms_model_spans",
+            "ms_model_mass_pattern", "ms_last_error")
+
+_fptr = C.POINTER(C.c_float)
+_iptr = C.POINTER(C.c_int32)
+
+
+class MsDesc(C.Structure):
+    _fields_ = [
+        ("n_node", C.c_int32), ("parent", _iptr), ("jtype", _iptr),
+        ("jpos", _fptr), ("jrot", _fptr), ("axis", _fptr), ("mass", _fptr),
+        ("com", _fptr), ("inertia", _fptr), ("damping", _fptr),
+        ("n_mus", C.c_int32), ("f0", _fptr), ("l_opt", _fptr), ("l_slack", _fptr),
+        ("v_max", _fptr), ("tau_act", _fptr), ("tau_deact", _fptr),
+        ("via_start", _iptr), ("via_node", _iptr), ("via_pos", _fptr),
+        ("n_con", C.c_int32), ("con_node", _iptr), ("con_pos", _fptr),
+        ("con_radius", _fptr), ("contact", C.c_float * 4), ("gravity", C.c_float * 3)]
+
+
+class MsInfo(C.Structure):
+    _fields_ = [(k, C.c_int32) for k in ("nq", "nv", "n_node", "n_mus", "n_con",
+                                         "n_body", "max_dof_depth", "nnz_mass",
+                                         "lds_bytes")]
+
+
+class MsOpts(C.Structure):
+    _fields_ = [("dt", C.c_float), ("contact", C.c_int32)]
+
+
+class MsExc(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("u", C.c_void_p), ("seed", C.c_uint64),
+                ("step0", C.c_int64), ("x", C.c_void_p), ("rho", C.c_float),
+                ("s", C.c_float), ("mean", C.c_float)]
+
+
+class MsStageOut(C.Structure):
+    _fields_ = [(k, C.c_void_p) for k in ("act", "L", "Ldot", "F", "r", "tau_mus",
+                                          "bias_minus_ext", "qdd", "mass")]
+
+
+_lib = None
+
+
+def lib():
+    """Load libms.so; raise if it is missing (no fallback path exists)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built: run __graft_entry__.build()")
+    L = C.CDLL(LIB_PATH)
+    vp = C.c_void_p
+    L.ms_model_create.argtypes = [C.POINTER(MsDesc), C.POINTER(vp)]
+    L.ms_model_destroy.argtypes = [vp]
+    L.ms_model_destroy.restype = None
+    L.ms_model_info_get.argtypes = [vp, C.POINTER(MsInfo)]
+    L.ms_step_batch.argtypes = [vp, C.c_int32, vp, vp, vp, vp, vp, C.POINTER(MsOpts), vp]
+    L.ms_rollout.argtypes = [vp, C.c_int32, vp, vp, vp, vp, C.POINTER(MsExc), C.c_int32,
+                             C.POINTER(MsOpts), vp]
+    L.ms_step_stages.argtypes = [vp, C.c_int32, vp, vp, vp, vp, C.POINTER(MsOpts),
+                                 C.POINTER(MsStageOut), vp]
+    L.ms_model_spans.argtypes = [vp, _iptr]
+    L.ms_model_mass_pattern.argtypes = [vp, _iptr, _iptr]
+    L.ms_last_error.restype = C.c_char_p
+    for f in ("ms_model_create", "ms_model_info_get", "ms_step_batch", "ms_rollout",
+              "ms_step_stages", "ms_model_spans", "ms_model_mass_pattern"):
+        getattr(L, f).restype = C.c_int
+    _lib = L
+    return L
+
+
+class MsError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"libms error {code}: {msg}")
+        self.code = code
+
+
+def _check(rc):
+    if rc != 0:
+        raise MsError(rc, lib().ms_last_error().decode())
+
+
+def _ptr(a, dtype, ctype):
+    return np.ascontiguousarray(a, dtype=dtype).ctypes.data_as(C.POINTER(ctype))
+
+
+def _dp(t):
+    """Device pointer of a torch tensor (or None)."""
+    if t is None:
+        return None
+    assert t.is_cuda and t.is_contiguous(), "expected a contiguous device tensor"
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    return C.c_void_p(getattr(stream, "cuda_stream", stream))
+
+
+class Model:
+    """A model compiled into libms device tables."""
+
+    def __init__(self, model: dict):
+        L = lib()
+        m = model
+        self._arrays = {}
+
+        def keep(name, dtype):
+            a = np.ascontiguousarray(m[name], dtype=dtype)
+            self._arrays[name] = a
+            return a.ctypes.data_as(C.POINTER(C.c_float if dtype == np.float32 else C.c_int32))
+
+        d = MsDesc()
+        d.n_node = m["n_node"]
+        d.parent, d.jtype = keep("parent", np.int32), keep("jtype", np.int32)
+        for k in ("jpos", "jrot", "axis", "mass", "com", "inertia", "damping"):
+            setattr(d, k, keep(k, np.float32))
+        d.n_mus = m["n_mus"]
+        for k in ("f0", "l_opt", "l_slack", "v_max", "tau_act", "tau_deact", "via_pos"):
+            setattr(d, k, keep(k, np.float32))
+        d.via_start, d.via_node = keep("via_start", np.int32), keep("via_node", np.int32)
+        d.n_con = m["n_con"]
+        d.con_node = keep("con_node", np.int32)
+        d.con_pos, d.con_radius = keep("con_pos", np.float32), keep("con_radius", np.float32)
+        d.contact = (C.c_float * 4)(*[float(x) for x in m["contact"]])
+        d.gravity = (C.c_float * 3)(*[float(x) for x in m["gravity"]])
+        h = C.c_void_p()
+        _check(L.ms_model_create(C.byref(d), C.byref(h)))
+        self.h = h
+        info = MsInfo()
+        _check(L.ms_model_info_get(h, C.byref(info)))
+        self.info = {k: getattr(info, k) for k, _ in MsInfo._fields_}
+        self.nq, self.nv, self.n_mus = info.nq, info.nv, info.n_mus
+        self.nnz = info.nnz_mass
+
+    def __del__(self):
+        try:
+            if getattr(self, "h", None):
+                lib().ms_model_destroy(self.h)
+        except Exception:
+            pass
+
+    def spans(self):
+        s = np.zeros((self.n_mus, 3), np.int32)
+        _check(lib().ms_model_spans(self.h, s.ctypes.data_as(_iptr)))
+        return s
+
+    def mass_pattern(self):
+        r = np.zeros(self.nnz, np.int32)
+        c = np.zeros(self.nnz, np.int32)
+        _check(lib().ms_model_mass_pattern(self.h, r.ctypes.data_as(_iptr), c.ctypes.data_as(_iptr)))
+        return r, c
+
+    def step_batch(self, q, qd, act, status, u, dt, contact=True, stream=None):
+        n_env = q.shape[0]
+        o = MsOpts(dt, int(contact))
+        _check(lib().ms_step_batch(self.h, n_env, _dp(q), _dp(qd), _dp(act), _dp(status),
+                                   _dp(u), C.byref(o), _stream(stream)))
+
+    def rollout(self, q, qd, act, status, n_steps, dt, contact=True, kind=EXC_ARRAY,
+                u=None, seed=0, step0=0, x=None, ar1=(0.0, 0.0, 0.0), stream=None):
+        n_env = q.shape[0]
+        o = MsOpts(dt, int(contact))
+        e = MsExc(kind, _dp(u), seed, step0, _dp(x), float(ar1[0]), float(ar1[1]),
+                  float(ar1[2]))
+        _check(lib().ms_rollout(self.h, n_env, _dp(q), _dp(qd), _dp(act), _dp(status),
+                                C.byref(e), n_steps, C.byref(o), _stream(stream)))
+
+    def step_stages(self, q, qd, act, u, dt, contact=True, stream=None):
+        import torch
+        E = q.shape[0]
+        dev = q.device
+        nm, nv = self.n_mus, self.nv
+        out = dict(act=torch.empty(E, nm, device=dev), L=torch.empty(E, nm, device=dev),
+                   Ldot=torch.empty(E, nm, device=dev), F=torch.empty(E, nm, device=dev),
+                   r=torch.empty(E, nm, 3, device=dev), tau_mus=torch.empty(E, nv, device=dev),
+                   bias_minus_ext=torch.empty(E, nv, device=dev),
+                   qdd=torch.empty(E, nv, device=dev),
+                   mass=torch.empty(E, self.nnz, dtype=torch.float64, device=dev))
+        so = MsStageOut(**{k: _dp(v) for k, v in out.items()})
+        o = MsOpts(dt, int(contact))
+        _check(lib().ms_step_stages(self.h, E, _dp(q), _dp(qd), _dp(act), _dp(u), C.byref(o),
+                                    C.byref(so), _stream(stream)))
+        return out

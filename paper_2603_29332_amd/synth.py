@@ -71,9 +71,13 @@ def _u24(z, shift: int):
             * 2.0 ** -24).astype(F32)
 
 
-def excitation_iid(seed: int, n_env: int, n_mus: int, step: int):
+def _envs(n_env, envs):
+    return np.arange(n_env) if envs is None else np.asarray(envs)
+
+
+def excitation_iid(seed: int, n_env: int, n_mus: int, step: int, envs=None):
     """u[e, m] = top 24 bits of SplitMix64(key(e, step) ^ m) * 2^-24."""
-    key = step_key(seed, np.arange(n_env), step)[:, None]
+    key = step_key(seed, _envs(n_env, envs), step)[:, None]
     z = splitmix64(key ^ np.arange(n_mus, dtype=np.uint64)[None, :])
     return _u24(z, 40)
 
@@ -86,7 +90,7 @@ def ar1_constants(dt: float, corr_time: float = 0.05, sigma: float = 0.25,
     return F32(rho), F32(s), F32(mean), F32(math.sqrt(3.0))
 
 
-def excitation_ar1_step(seed: int, x, step: int, consts):
+def excitation_ar1_step(seed: int, x, step: int, consts, envs=None):
     """One step of the smooth noise. x[e, m] (float32) is updated in place.
 
     Two SplitMix64 draws per (env, muscle) give four 24-bit uniforms; their
@@ -96,7 +100,7 @@ def excitation_ar1_step(seed: int, x, step: int, consts):
     """
     rho, s, mean, sqrt3 = consts
     n_env, n_mus = x.shape
-    key = step_key(seed, np.arange(n_env), step)[:, None]
+    key = step_key(seed, _envs(n_env, envs), step)[:, None]
     m2 = 2 * np.arange(n_mus, dtype=np.uint64)[None, :]
     z1 = splitmix64(key ^ m2)
     z2 = splitmix64(key ^ (m2 + np.uint64(1)))
@@ -110,16 +114,20 @@ def excitation_ar1_step(seed: int, x, step: int, consts):
 
 
 def excitation_sequence(kind: str, seed: int, n_env: int, n_mus: int,
-                        n_steps: int, dt: float, step0: int = 0, x0=None):
-    """u[T, E, Mu] for steps step0 .. step0+T-1; returns (u, x_final)."""
+                        n_steps: int, dt: float, step0: int = 0, x0=None,
+                        envs=None):
+    """u[T, E, Mu] for steps step0 .. step0+T-1; returns (u, x_final).
+    envs optionally names the env index of each row (default 0..E-1)."""
+    if envs is not None:
+        n_env = len(envs)
     out = np.empty((n_steps, n_env, n_mus), dtype=F32)
     x = np.zeros((n_env, n_mus), F32) if x0 is None else np.array(x0, F32)
     consts = ar1_constants(dt)
     for t in range(n_steps):
         if kind == "iid":
-            out[t] = excitation_iid(seed, n_env, n_mus, step0 + t)
+            out[t] = excitation_iid(seed, n_env, n_mus, step0 + t, envs)
         elif kind == "ar1":
-            out[t] = excitation_ar1_step(seed, x, step0 + t, consts)
+            out[t] = excitation_ar1_step(seed, x, step0 + t, consts, envs)
         else:
             raise ValueError(kind)
     return out, x

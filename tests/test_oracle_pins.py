@@ -514,14 +514,20 @@ def test_muscle_and_contact_slopes_match_finite_differences(human):
     op = Oracle(pm)
     qc = np.array([0.0, 0.0, 0.015])
     qdc = np.array([0.05, -0.03, -0.02])
-    _, _, Dc = op.contact(qc, qdc, with_slope=True)
-    for j in range(2):
+    dtc = 1e-3
+    _, _, Dc = op.contact(qc, qdc, dtc, with_slope=True)
+    for j in range(3):
         e = np.zeros(3)
         e[j] = 1e-7
-        tp, _ = op.contact(qc, qdc + e)
-        tn, _ = op.contact(qc, qdc - e)
-        assert np.allclose(-(tp - tn)[:2] / 2e-7, Dc[:2, j], rtol=1e-5)
-    assert abs(Dc[2, 2] - 1e3) < 1e-9
+        tp, _ = op.contact(qc, qdc + e, dtc)
+        tn, _ = op.contact(qc, qdc - e, dtc)
+        fd = -(tp - tn) / 2e-7
+        if j < 2:
+            assert np.allclose(fd[:2], Dc[:2, j], rtol=1e-5)
+        else:
+            # normal slope: damping plus the implicit spring, c_d + dt k
+            assert abs(fd[2] - Dc[2, 2]) < 1e-4 * Dc[2, 2]
+    assert abs(Dc[2, 2] - (1e3 + dtc * 1e5)) < 1e-9
 
 
 # ------------------------------------------------------------------- contact
@@ -535,7 +541,7 @@ def test_contact_resting_penetration():
         assert st == 0
     pen = 0.02 - q[2]
     assert abs(pen - m_ * G / 1e5) < 1e-9
-    tau, n = o.contact(q, np.zeros(3))
+    tau, n = o.contact(q, np.zeros(3), 1e-3)
     assert n == 1 and abs(tau[2] - m_ * G) < 1e-6
 
 

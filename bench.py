@@ -39,6 +39,11 @@ def parse():
     p.add_argument("--envs", type=int, default=4096)
     p.add_argument("--no-cpu", action="store_true", help="skip the oracle legs")
     p.add_argument("--cpu-seconds", type=float, default=15.0)
+    p.add_argument("--no-surrogate", action="store_true", help="skip the surrogate leg")
+    p.add_argument("--surrogate-iters", type=int, default=2000,
+                   help="Adam iterations (batch 8192) before the surrogate leg is timed")
+    p.add_argument("--surrogate-tol", type=float, default=1e-4,
+                   help="sentinel length residual (m) above which an env falls back")
     return p.parse_args()
 
 
@@ -128,13 +133,79 @@ def main():
                        "hbm_GBps": sb_bytes * E / (sb_ms / 1e3) / 1e9, "hbm_peak_GBps": 8000.0},
         "flagged_envs": flagged,
     }
+    if not a.no_surrogate:
+        line["surrogate"] = surrogate_leg(a, m, gm, dt, E, q0, qd0, act0, (rho, s, mean), dev,
+                                          rad=not a.no_cpu)
     if not a.no_cpu:
         line["rad_err_vs_fp64"] = rad_error(m, gm, dt, dev)
         line["cpu_baseline"] = cpu_baseline(m, dt, a.cpu_seconds)
     print(json.dumps(line), flush=True)
 
 
-def rad_error(m, gm, dt, dev):
+def surrogate_leg(a, m, gm, dt, E, q0, qd0, act0, ar1, dev, rad=True):
+    """The same workload with the learned geometry and exact fallback: the
+    network is trained here (untimed) on exact labels, then K bench steps of
+    PHYS_PER_STEP physics steps are timed like the exact leg."""
+    import torch
+
+    from paper_2603_29332_amd import ms, surrogate
+    t0 = time.perf_counter()
+    sg = ms.Surrogate(gm, hidden=512, seed=41)
+    mean, std = surrogate.output_stats(gm, sg)
+    sg.set_norm(mean, std)
+    losses, train_s = surrogate.train(gm, sg, n_samples=10_000_000, batch=8192,
+                                      epochs=a.surrogate_iters * 8192 / 10_000_000)
+    ev_err = surrogate.evaluate(gm, sg, n=16384)
+    setup_s = time.perf_counter() - t0
+    stream = torch.cuda.current_stream()
+    q, qd, act = (torch.tensor(v, device=dev) for v in (q0, qd0, act0))
+    st = torch.zeros(E, dtype=torch.int32, device=dev)
+    fb = torch.zeros(E, dtype=torch.int32, device=dev)
+    x = torch.zeros(E, m["n_mus"], device=dev)
+
+    def launch(k):
+        gm.rollout_surrogate(sg, q, qd, act, st, PHYS_PER_STEP, dt, True, tol=a.surrogate_tol,
+                             fb_count=fb, kind=ms.EXC_AR1, seed=12, step0=k * PHYS_PER_STEP,
+                             x=x, ar1=ar1, stream=stream)
+
+    for w in range(a.warmup):
+        launch(w)
+    torch.cuda.synchronize()
+    fb.zero_()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for k in range(a.steps):
+        launch(a.warmup + k)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t
+    n_steps = E * PHYS_PER_STEP * a.steps
+    # one network evaluation for all envs, timed alone (matrix-core GEMMs)
+    L = torch.empty(E, m["n_mus"], device=dev)
+    r = torch.empty(E, m["n_mus"], 3, device=dev)
+    for _ in range(3):
+        sg.forward(q, L, r, stream=stream)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(20):
+        sg.forward(q, L, r, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    fwd_ms = e0.elapsed_time(e1) / 20
+    fwd_flop = 2.0 * E * (sg.n_in * sg.h1 + sg.h1 * sg.h2 + sg.h2 * sg.n_out)
+    out = {"env_steps_per_s": n_steps / wall, "ms_per_step": wall / a.steps * 1e3,
+           "fallback_rate": float(fb.sum().item()) / n_steps, "tol_m": a.surrogate_tol,
+           "flagged_envs": int(((st & ~ms.MS_ST_FALLBACK) != 0).sum().item()),
+           "network": {"dims": [sg.n_in, sg.h1, sg.h2, sg.n_out], "train_iters": a.surrogate_iters,
+                       "batch": 8192, "train_s": train_s, "final_loss": float(losses[-1]),
+                       "setup_s": setup_s, "heldout": ev_err},
+           "forward": {"ms": fwd_ms, "tflops": fwd_flop / (fwd_ms / 1e3) / 1e12,
+                       "mfma_bf16_peak_tflops": 2500.0}}
+    if rad:
+        out["rad_err_vs_fp64"] = rad_error(m, gm, dt, dev, sg=sg, tol=a.surrogate_tol)
+    return out
+
+
+def rad_error(m, gm, dt, dev, sg=None, tol=1e-4):
     """GPU vs FP64 oracle after 200 steps, 16 envs of the 4096-env workload."""
     import torch
 
@@ -147,13 +218,20 @@ def rad_error(m, gm, dt, dev):
     u, _ = synth.excitation_sequence("ar1", 12, len(sub), m["n_mus"], T, dt, envs=sub)
     tq, tqd, tact = (torch.tensor(v, device=dev) for v in (q, qd, act))
     st = torch.zeros(len(sub), dtype=torch.int32, device=dev)
-    gm.rollout(tq, tqd, tact, st, T, dt, True, kind=ms.EXC_ARRAY, u=torch.tensor(u, device=dev))
+    if sg is None:
+        gm.rollout(tq, tqd, tact, st, T, dt, True, kind=ms.EXC_ARRAY,
+                   u=torch.tensor(u, device=dev))
+    else:
+        gm.rollout_surrogate(sg, tq, tqd, tact, st, T, dt, True, tol=tol, kind=ms.EXC_ARRAY,
+                             u=torch.tensor(u, device=dev))
+        st &= ~ms.MS_ST_FALLBACK
     torch.cuda.synchronize()
     qo, _, _, so = Oracle(m).rollout(dt, q, qd, act, u, contact=True)
     ok = (so == 0) & (st.cpu().numpy() == 0)
     d = np.abs(tq.cpu().numpy()[ok][:, 7:] - qo[ok][:, 7:])
     return {"max": float(d.max()), "mean": float(d.mean()), "envs": int(ok.sum()),
-            "steps": T, "note": "hinge angles, GPU FP32(+FP64 solve) vs FP64 oracle"}
+            "steps": T, "note": "hinge angles, GPU FP32(+FP64 solve) vs FP64 oracle"
+                                + ("" if sg is None else ", learned geometry with fallback")}
 
 
 def cpu_baseline(m, dt, seconds):

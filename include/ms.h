@@ -60,6 +60,8 @@ typedef enum {
 /* Per-env status bits. */
 #define MS_ST_NONFINITE 1u /* non-finite state or result; step not applied */
 #define MS_ST_NONSPD 2u    /* LTDL pivot <= 0; step not applied */
+#define MS_ST_FALLBACK 4u  /* surrogate geometry replaced by the exact one in
+                              some step (informational; the step is applied) */
 
 /* Model description (host memory; deep-copied by ms_model_create).
  * Kinematic tree of n_node nodes in topological order (parent < child).
@@ -79,6 +81,9 @@ typedef struct {
   const float *com;          /* [n_node][3] centre of mass, node frame */
   const float *inertia;      /* [n_node][3] principal moments at the COM */
   const float *damping;      /* [nv] joint damping b (N m s / rad) */
+  const float *qlo, *qhi;    /* [nv] pose-domain limits of hinge/slide DoFs
+                                (sampling box of the geometry surrogate and its
+                                domain check; no limit forces); may be NULL */
   int32_t n_mus;
   const float *f0;           /* [n_mus] maximum isometric force (N) */
   const float *l_opt;        /* [n_mus] optimal fibre length (m) */
@@ -168,6 +173,12 @@ ms_status ms_step_stages(ms_model *m, int32_t n_env, const float *q,
                          const ms_step_opts *opts, ms_stage_out *out,
                          void *stream);
 
+/* Exact muscle geometry only, for n poses q[n][nq] (device): lengths
+ * L[n][n_mus] and moment arms r[n][n_mus][3] in the DoF slots of
+ * ms_model_spans (device outputs). Labels for the geometry surrogate. */
+ms_status ms_geometry(ms_model *m, int32_t n, const float *q, float *L, float *r,
+                      void *stream);
+
 /* Host copies of the derived tables: spans[n_mus][3] DoF indices (-1 pad);
  * the sparse mass pattern rows[nnz], cols[nnz] (row >= col). */
 ms_status ms_model_spans(const ms_model *m, int32_t *spans);
@@ -176,6 +187,64 @@ ms_status ms_model_mass_pattern(const ms_model *m, int32_t *rows,
 
 /* Last error message of this thread ("" if none). */
 const char *ms_last_error(void);
+
+/* ------------------------------------------------------------------------
+ * Learned muscle-geometry surrogate (replaces the via-point geometry of
+ * step 2 by a pose -> (L, moment arms) network; the paper names the
+ * muscle-tendon path routing as the costly part of musculoskeletal
+ * simulation). Multilayer perceptron x -> SiLU(W1 x + b1) ->
+ * SiLU(W2 h1 + b2) -> W3 h2 + b3 with x the hinge/slide angles padded to
+ * a multiple of 16 and n_out = 4 n_mus outputs per pose: lengths L[n_mus]
+ * then moment arms r[n_mus][3] in the span slots of ms_model_spans (empty
+ * slots masked), standardised by (mean, std). bfloat16 matrix-core GEMMs
+ * with float32 accumulation; float32 master weights stored [out][in];
+ * Adam (Kingma & Ba 2015; beta 0.9/0.999, eps 1e-8) with bias correction.
+ * Weights start LeCun-uniform from `seed`, biases zero. */
+typedef struct ms_surrogate ms_surrogate;
+ms_status ms_surrogate_create(const ms_model *m, int32_t hidden, uint64_t seed,
+                              ms_surrogate **out);
+void ms_surrogate_destroy(ms_surrogate *s);
+/* dims[4] = n_in, hidden, hidden, n_out */
+ms_status ms_surrogate_dims(const ms_surrogate *s, int32_t *dims);
+/* host copies of the float32 parameters (set = 0 reads, 1 writes);
+ * W1[hidden][n_in], W2[hidden][hidden], W3[n_out][hidden] */
+ms_status ms_surrogate_params(ms_surrogate *s, int32_t set, float *W1, float *b1,
+                              float *W2, float *b2, float *W3, float *b3);
+/* host copies of the gradients of the last training step */
+ms_status ms_surrogate_grads(ms_surrogate *s, float *W1, float *b1, float *W2,
+                             float *b2, float *W3, float *b3);
+/* output standardisation (host [n_out]; std > 0) */
+ms_status ms_surrogate_set_norm(ms_surrogate *s, const float *mean, const float *std);
+/* n poses uniform in the model's pose-domain box (device q[n][nq]); pose p
+ * uses SplitMix64(SplitMix64(seed ^ (offset + p)) ^ input index) */
+ms_status ms_surrogate_sample(ms_surrogate *s, int32_t n, uint64_t seed, int64_t offset,
+                              float *q, void *stream);
+/* predictions for n poses q[n][nq] (device): L[n][n_mus], r[n][n_mus][3] */
+ms_status ms_surrogate_forward(ms_surrogate *s, int32_t n, const float *q, float *L,
+                               float *r, void *stream);
+/* one training step on n poses (n a multiple of 8) with exact labels
+ * L, r (device, as from ms_geometry): loss = mean over (pose, output) of
+ * mask (y - t)^2 on standardised targets t, written to *loss (device) if
+ * non-NULL; then an Adam step with learning rate lr at step count
+ * `step` >= 1 (lr = 0: gradients only). */
+ms_status ms_surrogate_train_step(ms_surrogate *s, int32_t n, const float *q,
+                                  const float *L, const float *r, float lr,
+                                  int32_t step, float *loss, void *stream);
+const char *ms_surrogate_last_error(void);
+
+/* ms_rollout with the muscle geometry predicted by the surrogate: each step
+ * runs the network on every env's pose, then the step, in which an env
+ * falls back to the exact geometry (MS_ST_FALLBACK, fallback_count[env]++
+ * when non-NULL) if a hinge/slide coordinate lies outside the pose-domain
+ * box or if the predicted length of any of 32 sentinel muscles (muscle
+ * (32 step + i) mod n_mus, i < 32, step = exc->step0 + t) differs from the
+ * exact length by more than tol metres. tol < 0 always falls back (exact
+ * path); n_env must not exceed the surrogate workspace the device can hold. */
+ms_status ms_rollout_surrogate(ms_model *m, ms_surrogate *s, int32_t n_env, float *q,
+                               float *qd, float *act, uint32_t *status,
+                               const ms_excitation *exc, int32_t n_steps,
+                               const ms_step_opts *opts, float tol,
+                               uint32_t *fallback_count, void *stream);
 
 #ifdef __cplusplus
 }

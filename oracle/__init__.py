@@ -4,4 +4,4 @@ Only the test-suite, the smoke check and the benchmark's CPU-baseline leg
 may import this package; the product path (the HIP library and its binding)
 never does.
 """
-from .oracle import Oracle, build_oracle, oracle_lib_path  # noqa: F401
+from .oracle import Oracle, adam, bf16, build_oracle, mlp_forward, mlp_grad, oracle_lib_path  # noqa: F401

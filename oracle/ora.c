@@ -693,6 +693,12 @@ static int all_finite(const double *x, int n) {
 
 uint32_t ora_step(const ora_model *m, double dt, int contact_on, double *q,
                   double *qd, double *act, const double *u, ora_stage_out *out) {
+  return ora_step_geo(m, dt, contact_on, q, qd, act, u, NULL, NULL, out);
+}
+
+uint32_t ora_step_geo(const ora_model *m, double dt, int contact_on, double *q,
+                      double *qd, double *act, const double *u, const double *L_in,
+                      const double *r_in, ora_stage_out *out) {
   int nv = m->nv, nq = m->nq, nm = m->n_mus, n = m->n_node;
   if (!all_finite(q, nq) || !all_finite(qd, nv) || !all_finite(act, nm))
     return ORA_ST_NONFINITE;
@@ -715,7 +721,18 @@ uint32_t ora_step(const ora_model *m, double dt, int contact_on, double *q,
   uint32_t st = 0;
 
   ora_activation(m, dt, u, act, act1);
-  ora_geometry(m, q, qd, L, r, Ld);
+  if (L_in) {
+    /* given geometry; the lengthening rate follows from r = -dL/dq */
+    memcpy(L, L_in, sizeof(double) * nm);
+    memcpy(r, r_in, sizeof(double) * (size_t)nm * nv);
+    for (int mu = 0; mu < nm; ++mu) {
+      double s = 0.0;
+      for (int j = 0; j < nv; ++j) s -= r[(size_t)mu * nv + j] * qd[j];
+      Ld[mu] = s;
+    }
+  } else {
+    ora_geometry(m, q, qd, L, r, Ld);
+  }
   ora_hill(m, act1, L, Ld, F, out ? out->lm : NULL, out ? out->vm : NULL);
   for (int mu = 0; mu < nm; ++mu)
     for (int j = 0; j < nv; ++j) tm[j] += r[(size_t)mu * nv + j] * F[mu];

@@ -108,6 +108,12 @@ uint32_t ora_step(const ora_model *m, double dt, int contact_on,
                   double *q, double *qd, double *act, const double *u,
                   ora_stage_out *out);
 
+/* ora_step with the muscle geometry given instead of computed: L_in[n_mus]
+ * and moment arms r_in[n_mus][nv] (both NULL: ora_step). Ldot = -r qd. */
+uint32_t ora_step_geo(const ora_model *m, double dt, int contact_on,
+                      double *q, double *qd, double *act, const double *u,
+                      const double *L_in, const double *r_in, ora_stage_out *out);
+
 /* n_env envs for n_steps steps; u is float32 [n_steps][n_env][n_mus];
  * status[n_env] is OR-ed. Envs are split over n_threads threads. */
 void ora_rollout(const ora_model *m, int n_env, int n_steps, double dt,

@@ -14,7 +14,7 @@ import subprocess
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SRC = os.path.join(_HERE, "ora.c")
+_SRC = [os.path.join(_HERE, "ora.c"), os.path.join(_HERE, "mlp.c")]
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 
@@ -27,7 +27,7 @@ def build_oracle(force: bool = True) -> str:
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp"
         cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp",
-               "-Wall", "-Wno-unused-function", _SRC, "-o", tmp, "-lm"]
+               "-Wall", "-Wno-unused-function"] + _SRC + ["-o", tmp, "-lm"]
         subprocess.run(cmd, check=True)
         os.replace(tmp, _LIB)
     return _LIB
@@ -77,8 +77,18 @@ def _load():
     lib.ora_step.restype = C.c_uint32
     lib.ora_step.argtypes = [C.c_void_p, C.c_double, C.c_int, _dp, _dp, _dp, _dp,
                              C.POINTER(_StageOut)]
+    lib.ora_step_geo.restype = C.c_uint32
+    lib.ora_step_geo.argtypes = [C.c_void_p, C.c_double, C.c_int, _dp, _dp, _dp, _dp,
+                                 C.c_void_p, C.c_void_p, C.POINTER(_StageOut)]
     lib.ora_rollout.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_double, C.c_int,
                                 _dp, _dp, _dp, _fp, _up, C.c_int]
+    lib.ora_bf16.restype = C.c_double
+    lib.ora_bf16.argtypes = [C.c_double]
+    lib.ora_mlp_forward.argtypes = [C.c_int] * 5 + [_fp] * 7 + [C.c_int, _dp] + [C.c_void_p] * 4
+    lib.ora_mlp_grad.restype = C.c_double
+    lib.ora_mlp_grad.argtypes = [C.c_int] * 5 + [_fp] * 7 + [_fp, C.c_void_p, C.c_int] + [_dp] * 6
+    lib.ora_adam.argtypes = [C.c_int, _dp, _dp, _dp, _dp, C.c_double, C.c_double, C.c_double,
+                             C.c_double, C.c_int]
     _lib = lib
     return lib
 
@@ -182,9 +192,15 @@ class Oracle:
     def energy(self, q, qd):
         return self.lib.ora_energy(self.h, _d(q), _d(qd))
 
-    def step(self, dt, q, qd, act, u, contact=True, stages=False):
-        """One step of one env; returns (q', qd', act', status[, stages])."""
+    def step(self, dt, q, qd, act, u, contact=True, stages=False, geometry=None):
+        """One step of one env; returns (q', qd', act', status[, stages]).
+        geometry = (L[n_mus], r[n_mus][nv]) replaces the via-point geometry
+        (the lengthening rate then follows as -r qd)."""
         q, qd, act = _d(q).copy(), _d(qd).copy(), _d(act).copy()
+        gL = gr = None
+        if geometry is not None:
+            gL = _d(geometry[0]).copy()
+            gr = _d(geometry[1]).reshape(self.n_mus, self.nv).copy()
         out = None
         st_arrays = {}
         if stages:
@@ -194,8 +210,10 @@ class Oracle:
                           D=(nv, nv))
             st_arrays = {k: np.zeros(s) for k, s in shapes.items()}
             out = _StageOut(**{k: v.ctypes.data for k, v in st_arrays.items()})
-        st = self.lib.ora_step(self.h, dt, int(contact), q, qd, act, _d(u),
-                               C.byref(out) if out is not None else None)
+        st = self.lib.ora_step_geo(self.h, dt, int(contact), q, qd, act, _d(u),
+                                   gL.ctypes.data if gL is not None else None,
+                                   gr.ctypes.data if gr is not None else None,
+                                   C.byref(out) if out is not None else None)
         if stages:
             return q, qd, act, st, st_arrays
         return q, qd, act, st
@@ -212,3 +230,43 @@ class Oracle:
         self.lib.ora_rollout(self.h, E, T, dt, int(contact), q, qd, act, u, status,
                              int(threads))
         return q, qd, act, status
+
+
+# ------------------------------------------------------------ surrogate MLP
+def bf16(v):
+    """Round to bfloat16 (nearest even) and back."""
+    return _load().ora_bf16(float(v))
+
+
+def _f(a):
+    return np.ascontiguousarray(a, dtype=np.float32)
+
+
+def mlp_forward(params, x, bf16=True):
+    """params = (W1, b1, W2, b2, W3, b3) with W[in][out]; x [B][n0]."""
+    W1, b1, W2, b2, W3, b3 = (_f(p) for p in params)
+    x = _f(x)
+    B, n0 = x.shape
+    n1, n2, n3 = W1.shape[1], W2.shape[1], W3.shape[1]
+    y = np.zeros((B, n3))
+    _load().ora_mlp_forward(B, n0, n1, n2, n3, W1, b1, W2, b2, W3, b3, x, int(bf16), y,
+                            None, None, None, None)
+    return y
+
+
+def mlp_grad(params, x, t, mask=None, bf16=True):
+    """Loss = mean(mask (y - t)^2) and the gradients of every parameter."""
+    W1, b1, W2, b2, W3, b3 = (_f(p) for p in params)
+    x, t = _f(x), _f(t)
+    B, n0 = x.shape
+    n1, n2, n3 = W1.shape[1], W2.shape[1], W3.shape[1]
+    g = [np.zeros(p.shape) for p in (W1, b1, W2, b2, W3, b3)]
+    mk = None if mask is None else _f(mask)
+    loss = _load().ora_mlp_grad(B, n0, n1, n2, n3, W1, b1, W2, b2, W3, b3, x, t,
+                                mk.ctypes.data if mk is not None else None, int(bf16), *g)
+    return loss, g
+
+
+def adam(w, m, v, g, lr, b1=0.9, b2=0.999, eps=1e-8, step=1):
+    """One Adam step in place on float64 arrays."""
+    _load().ora_adam(w.size, w, m, v, np.ascontiguousarray(g, np.float64), lr, b1, b2, eps, step)

@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libms.so")
-SOURCES = ["ms_model.cpp", "ms_step.hip"]
+SOURCES = ["ms_model.cpp", "ms_step.hip", "ms_gemm.hip", "ms_mlp.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",
          # no packed-FP32 instructions in generated code

@@ -1,0 +1,36 @@
+// ms_gemm.h -- bfloat16 matrix-core GEMM with fused epilogues (internal).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <hip/hip_bf16.h>
+
+namespace ms {
+
+typedef __hip_bfloat16 bf16;
+
+// C[M][N] = op(A) op(B): op(A)(m, k) = TA ? A[k * lda + m] : A[m * lda + k],
+// op(B)(k, n) = TB ? B[n * ldb + k] : B[k * ldb + n]. bfloat16 operands,
+// float32 accumulation. Epilogue, per element (m, n):
+//   v = acc * alpha + (bias ? bias[n] : 0)
+//   if dact: v *= SiLU'(dact[m * ldc + n])           (backward through SiLU)
+//   if z_out: z_out[m * ldc + n] = v                  (pre-activation, f32)
+//   if act == 1: v = SiLU(v)
+//   if scale: v = v * scale[n] + shift[n]             (de-standardisation)
+//   if c_f32: c_f32[m * ldc + n] = v ;  if c_bf16: c_bf16[m * ldc + n] = bf16(v)
+struct GemmEpi {
+  const float *bias = nullptr;
+  const float *dact = nullptr;
+  float *z_out = nullptr;
+  int act = 0;
+  const float *scale = nullptr, *shift = nullptr;
+  float *c_f32 = nullptr;
+  bf16 *c_bf16 = nullptr;
+  int ldc = 0;
+  float alpha = 1.0f;
+};
+
+// Requires K, lda, ldb multiples of 8 (16-byte rows). Returns the launch
+// error, if any.
+hipError_t gemm_bf16(bool ta, bool tb, int M, int N, int K, const bf16 *A, int lda, const bf16 *B,
+                     int ldb, const GemmEpi &epi, hipStream_t st);
+
+}  // namespace ms

@@ -1,0 +1,125 @@
+// ms_gemm.hip -- bfloat16 GEMM on gfx950 matrix cores (v_mfma_f32_16x16x32_bf16).
+//
+// A workgroup of 4 wavefronts computes a 128 x 128 tile of C; each
+// wavefront owns a 64 x 64 quadrant as a 4 x 4 grid of 16 x 16 MFMA tiles
+// with float32 accumulators. Operand tiles of 32 along K are staged through
+// LDS as [row][k] (k contiguous, rows padded to 40 elements), so every lane
+// reads its 8 consecutive k values of a row with one 128-bit LDS load;
+// operands stored K-major in memory are transposed while being staged.
+#include "ms_gemm.h"
+
+namespace ms {
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+constexpr int BM = 128, BN = 128, BK = 32, LK = BK + 8;
+
+// Stage a 128 (rows) x 32 (k) tile of a matrix whose element (o, k) lives at
+// G[o * ld + k] (row-major, KMAJOR = false) or G[k * ld + o] (KMAJOR = true)
+// into S[o * LK + k]; out-of-range elements are zero.
+template <bool KMAJOR>
+__device__ __forceinline__ void stage(unsigned short *S, const bf16 *G, int ld, int o0, int O, int k0,
+                                      int K, int tid) {
+  const unsigned short *g = reinterpret_cast<const unsigned short *>(G);
+#pragma unroll
+  for (int it = 0; it < 2; ++it) {
+    const int c = tid + 256 * it;
+    if (!KMAJOR) {
+      const int o = c >> 2, kc = (c & 3) * 8;
+      const int go = o0 + o, gk = k0 + kc;
+      uint4 v = make_uint4(0, 0, 0, 0);
+      if (go < O && gk < K) v = *reinterpret_cast<const uint4 *>(g + (size_t)go * ld + gk);
+      *reinterpret_cast<uint4 *>(S + o * LK + kc) = v;
+    } else {
+      const int kk = c >> 4, oc = (c & 15) * 8;
+      const int go = o0 + oc, gk = k0 + kk;
+      uint4 v = make_uint4(0, 0, 0, 0);
+      if (go < O && gk < K) v = *reinterpret_cast<const uint4 *>(g + (size_t)gk * ld + go);
+      const unsigned short e[8] = {(unsigned short)(v.x & 0xFFFF), (unsigned short)(v.x >> 16),
+                                   (unsigned short)(v.y & 0xFFFF), (unsigned short)(v.y >> 16),
+                                   (unsigned short)(v.z & 0xFFFF), (unsigned short)(v.z >> 16),
+                                   (unsigned short)(v.w & 0xFFFF), (unsigned short)(v.w >> 16)};
+#pragma unroll
+      for (int j = 0; j < 8; ++j) S[(oc + j) * LK + kk] = e[j];
+    }
+  }
+}
+
+__device__ __forceinline__ float silu(float z) { return z / (1.0f + expf(-z)); }
+__device__ __forceinline__ float silu_slope(float z) {
+  const float s = 1.0f / (1.0f + expf(-z));
+  return s * (1.0f + z * (1.0f - s));
+}
+
+template <bool TA, bool TB>
+__global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const bf16 *A, int lda,
+                                              const bf16 *B, int ldb, GemmEpi epi) {
+  __shared__ __align__(16) unsigned short As[BM * LK];
+  __shared__ __align__(16) unsigned short Bs[BN * LK];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int wm = w >> 1, wn = w & 1;
+  const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+  f32x4 acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  for (int k0 = 0; k0 < K; k0 += BK) {
+    stage<TA>(As, A, lda, m0, M, k0, K, tid);
+    stage<!TB>(Bs, B, ldb, n0, N, k0, K, tid);
+    __syncthreads();
+    bf16x8 a[4], b[4];
+    const int kq = (lane >> 4) * 8, r = lane & 15;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      a[i] = *reinterpret_cast<const bf16x8 *>(As + (wm * 64 + i * 16 + r) * LK + kq);
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      b[j] = *reinterpret_cast<const bf16x8 *>(Bs + (wn * 64 + j * 16 + r) * LK + kq);
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+    __syncthreads();
+  }
+
+  // accumulator element e of tile (i, j): row 4*(lane/16) + e, column lane%16
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int m = m0 + wm * 64 + i * 16 + (lane >> 4) * 4 + e;
+        const int n = n0 + wn * 64 + j * 16 + (lane & 15);
+        if (m >= M || n >= N) continue;
+        const size_t o = (size_t)m * epi.ldc + n;
+        float v = acc[i][j][e] * epi.alpha;
+        if (epi.bias) v += epi.bias[n];
+        if (epi.dact) v *= silu_slope(epi.dact[o]);
+        if (epi.z_out) epi.z_out[o] = v;
+        if (epi.act == 1) v = silu(v);
+        if (epi.scale) v = v * epi.scale[n] + epi.shift[n];
+        if (epi.c_f32) epi.c_f32[o] = v;
+        if (epi.c_bf16) epi.c_bf16[o] = __float2bfloat16(v);
+      }
+}
+
+}  // namespace
+
+hipError_t gemm_bf16(bool ta, bool tb, int M, int N, int K, const bf16 *A, int lda, const bf16 *B,
+                     int ldb, const GemmEpi &epi, hipStream_t st) {
+  if (M <= 0 || N <= 0 || K <= 0) return hipSuccess;
+  if (K % 8 || lda % 8 || ldb % 8 || (ta && M % 8) || (!tb && N % 8)) return hipErrorInvalidValue;
+  dim3 grid((N + BN - 1) / BN, (M + BM - 1) / BM), block(256);
+  if (!ta && !tb) hipLaunchKernelGGL((k_gemm<false, false>), grid, block, 0, st, M, N, K, A, lda, B, ldb, epi);
+  if (!ta && tb) hipLaunchKernelGGL((k_gemm<false, true>), grid, block, 0, st, M, N, K, A, lda, B, ldb, epi);
+  if (ta && !tb) hipLaunchKernelGGL((k_gemm<true, false>), grid, block, 0, st, M, N, K, A, lda, B, ldb, epi);
+  if (ta && tb) hipLaunchKernelGGL((k_gemm<true, true>), grid, block, 0, st, M, N, K, A, lda, B, ldb, epi);
+  return hipGetLastError();
+}
+
+}  // namespace ms

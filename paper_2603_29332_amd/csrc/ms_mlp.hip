@@ -1,0 +1,498 @@
+// ms_mlp.hip -- the learned muscle-geometry surrogate: a pose -> (muscle
+// lengths, moment arms) multilayer perceptron trained and evaluated with the
+// library's own bfloat16 matrix-core kernels (ms_gemm.hip).
+//
+// Network: x (hinge angles, padded to a multiple of 16) -> SiLU(W1 x + b1)
+// -> SiLU(W2 h1 + b2) -> W3 h2 + b3, standardised outputs. Output layout per
+// pose: [L (n_mus) | r (n_mus x 3, the model's span slots)], caller's
+// muscle order. Weights live as float32 masters ([out][in]) with bfloat16
+// copies for the GEMMs; Adam (Kingma & Ba 2015) updates the masters.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <string>
+#include <vector>
+
+#include "../../include/ms.h"
+#include "ms_gemm.h"
+#include "ms_model.h"
+
+// Tables of the model this surrogate serves (filled from the model).
+struct ms_surrogate {
+  int n_in = 0, h1 = 0, h2 = 0, n_out = 0, n_mus = 0, nq = 0, free_root = 0;
+  // device buffers
+  float *W[3] = {}, *b[3] = {}, *gW[3] = {}, *gb[3] = {};
+  float *mW[3] = {}, *vW[3] = {}, *mb[3] = {}, *vb[3] = {};
+  ms::bf16 *Wb[3] = {};
+  float *mean = nullptr, *stdv = nullptr, *istd = nullptr, *mask = nullptr;
+  float *lo = nullptr, *hi = nullptr;
+  int *hinge_q = nullptr;  // q index of each input (-1 = padding)
+  // workspace for up to cap poses
+  int cap = 0;
+  ms::bf16 *X = nullptr, *H1 = nullptr, *H2 = nullptr, *dYb = nullptr, *dZ2b = nullptr,
+           *dZ1b = nullptr;
+  float *Z1 = nullptr, *Z2 = nullptr, *Y = nullptr, *T = nullptr, *dY = nullptr, *dZ2 = nullptr,
+        *dZ1 = nullptr, *part = nullptr;
+  std::vector<void *> owned;
+};
+
+namespace ms {
+namespace {
+
+__device__ __forceinline__ unsigned long long splitmix64(unsigned long long x) {
+  unsigned long long z = x + 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+__device__ __forceinline__ float unit24(unsigned long long z) {
+  return (float)((unsigned)(z >> 40)) * 5.9604644775390625e-8f;
+}
+
+// LeCun-uniform weights U(-1/sqrt(fan_in), 1/sqrt(fan_in)) from a counter
+// hash; biases zero.
+__global__ void k_init(float *W, int n, int fan_in, unsigned long long seed) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float a = 1.0f / sqrtf((float)fan_in);
+  W[i] = (2.0f * unit24(splitmix64(seed ^ (unsigned long long)i)) - 1.0f) * a;
+}
+
+__global__ void k_to_bf16(const float *x, bf16 *y, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = __float2bfloat16(x[i]);
+}
+
+// x[p][i] = bf16(q[p][hinge_q[i]]) (0 for padding inputs)
+__global__ void k_pack(const float *q, int nq, const int *hq, int n_in, int n, bf16 *X) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n * n_in) return;
+  const int p = t / n_in, i = t % n_in;
+  const int j = hq[i];
+  X[t] = __float2bfloat16(j >= 0 ? q[(size_t)p * nq + j] : 0.0f);
+}
+
+// poses uniform in the surrogate's box: hinge i of pose p from
+// SplitMix64(SplitMix64(seed ^ (offset + p)) ^ i); the root at the origin.
+__global__ void k_sample(int n, int nq, int free_root, const int *hq, const float *lo, const float *hi,
+                         int n_in, unsigned long long seed, long long offset, float *q) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  float *o = q + (size_t)p * nq;
+  for (int j = 0; j < nq; ++j) o[j] = 0.0f;
+  if (free_root) o[3] = 1.0f;
+  const unsigned long long key = splitmix64(seed ^ (unsigned long long)(offset + p));
+  for (int i = 0; i < n_in; ++i) {
+    const int j = hq[i];
+    if (j < 0) continue;
+    const float u = unit24(splitmix64(key ^ (unsigned long long)i));
+    o[j] = lo[i] + (hi[i] - lo[i]) * u;
+  }
+}
+
+// standardised targets T[p][o] from L[p][m] and r[p][m][3]
+__global__ void k_targets(const float *L, const float *r, int n_mus, int n, const float *mean,
+                          const float *istd, const float *mask, float *T) {
+  const int n_out = 4 * n_mus;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n * n_out) return;
+  const int p = t / n_out, o = t % n_out;
+  const float y = o < n_mus ? L[(size_t)p * n_mus + o] : r[(size_t)p * 3 * n_mus + (o - n_mus)];
+  T[t] = mask[o] != 0.0f ? (y - mean[o]) * istd[o] : 0.0f;
+}
+
+// dY = 2 mask (Y - T) / (n n_out) (float32 and bfloat16); per-block
+// partial sums of mask (Y - T)^2 into part[blockIdx]
+__global__ __launch_bounds__(256) void k_loss(const float *Y, const float *T, const float *mask,
+                                              int n, int n_out, float *dY, bf16 *dYb, float *part) {
+  __shared__ float red[256];
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  float l = 0.0f;
+  if (t < n * n_out) {
+    const int o = t % n_out;
+    const float d = mask[o] * (Y[t] - T[t]);
+    l = d * d;
+    const float g = 2.0f * d / ((float)n * (float)n_out);
+    dY[t] = g;
+    dYb[t] = __float2bfloat16(g);
+  }
+  red[threadIdx.x] = l;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+// loss = sum(part) / (n n_out), one thread, fixed order
+__global__ void k_loss_final(const float *part, int nb, int n, int n_out, float *loss) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    double s = 0.0;
+    for (int i = 0; i < nb; ++i) s += part[i];
+    *loss = (float)(s / ((double)n * (double)n_out));
+  }
+}
+
+// out[c] = sum over rows of X[r][c] (fixed row order)
+__global__ void k_colsum(const float *X, int rows, int cols, float *out) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= cols) return;
+  float s = 0.0f;
+  for (int r = 0; r < rows; ++r) s += X[(size_t)r * cols + c];
+  out[c] = s;
+}
+
+__global__ void k_adam(float *w, float *m, float *v, const float *g, int n, float lr, float b1,
+                       float b2, float eps, float c1, float c2, bf16 *wb) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i];
+  const float mi = b1 * m[i] + (1.0f - b1) * gi;
+  const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  const float wi = w[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+  w[i] = wi;
+  if (wb) wb[i] = __float2bfloat16(wi);
+}
+
+// Y[p][o] -> L[p][m], r[p][m][3]
+__global__ void k_unpack(const float *Y, int n_mus, int n, float *L, float *r) {
+  const int n_out = 4 * n_mus;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n * n_out) return;
+  const int p = t / n_out, o = t % n_out;
+  if (o < n_mus)
+    L[(size_t)p * n_mus + o] = Y[t];
+  else
+    r[(size_t)p * 3 * n_mus + (o - n_mus)] = Y[t];
+}
+
+inline int blocks(long long n, int b = 256) { return (int)((n + b - 1) / b); }
+
+thread_local std::string s_err;
+ms_status sfail(ms_status s, const std::string &m) {
+  s_err = m;
+  return s;
+}
+
+template <class T>
+T *dalloc(ms_surrogate *s, size_t n) {
+  void *p = nullptr;
+  if (hipMalloc(&p, std::max<size_t>(n, 1) * sizeof(T)) != hipSuccess) return nullptr;
+  (void)hipMemset(p, 0, std::max<size_t>(n, 1) * sizeof(T));
+  s->owned.push_back(p);
+  return (T *)p;
+}
+
+ms_status ensure_cap(ms_surrogate *s, int n) {
+  if (n <= s->cap) return MS_OK;
+  // workspace is replaced, not freed: previous launches may still use it
+  const size_t B = (size_t)n;
+  s->X = dalloc<bf16>(s, B * s->n_in);
+  s->Z1 = dalloc<float>(s, B * s->h1);
+  s->H1 = dalloc<bf16>(s, B * s->h1);
+  s->Z2 = dalloc<float>(s, B * s->h2);
+  s->H2 = dalloc<bf16>(s, B * s->h2);
+  s->Y = dalloc<float>(s, B * s->n_out);
+  s->T = dalloc<float>(s, B * s->n_out);
+  s->dY = dalloc<float>(s, B * s->n_out);
+  s->dYb = dalloc<bf16>(s, B * s->n_out);
+  s->dZ2 = dalloc<float>(s, B * s->h2);
+  s->dZ2b = dalloc<bf16>(s, B * s->h2);
+  s->dZ1 = dalloc<float>(s, B * s->h1);
+  s->dZ1b = dalloc<bf16>(s, B * s->h1);
+  s->part = dalloc<float>(s, (size_t)blocks((long long)B * s->n_out));
+  if (!s->X || !s->Z1 || !s->H1 || !s->Z2 || !s->H2 || !s->Y || !s->T || !s->dY || !s->dYb ||
+      !s->dZ2 || !s->dZ2b || !s->dZ1 || !s->dZ1b || !s->part)
+    return sfail(MS_E_ALLOC, "surrogate workspace allocation failed");
+  s->cap = n;
+  return MS_OK;
+}
+
+ms_status hipst(hipError_t e, const char *what) {
+  if (e != hipSuccess) return sfail(MS_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+  return MS_OK;
+}
+
+// forward through the three layers into s->Y (standardised, or
+// de-standardised when destd), keeping Z1/Z2 for training
+ms_status forward(ms_surrogate *s, int n, const float *q, bool destd, bool keep, hipStream_t st) {
+  hipLaunchKernelGGL(k_pack, dim3(blocks((long long)n * s->n_in)), dim3(256), 0, st, q, s->nq,
+                     s->hinge_q, s->n_in, n, s->X);
+  GemmEpi e1;
+  e1.bias = s->b[0];
+  e1.z_out = keep ? s->Z1 : nullptr;
+  e1.act = 1;
+  e1.c_bf16 = s->H1;
+  e1.ldc = s->h1;
+  hipError_t e = gemm_bf16(false, true, n, s->h1, s->n_in, s->X, s->n_in, s->Wb[0], s->n_in, e1, st);
+  if (e != hipSuccess) return hipst(e, "gemm 1");
+  GemmEpi e2;
+  e2.bias = s->b[1];
+  e2.z_out = keep ? s->Z2 : nullptr;
+  e2.act = 1;
+  e2.c_bf16 = s->H2;
+  e2.ldc = s->h2;
+  e = gemm_bf16(false, true, n, s->h2, s->h1, s->H1, s->h1, s->Wb[1], s->h1, e2, st);
+  if (e != hipSuccess) return hipst(e, "gemm 2");
+  GemmEpi e3;
+  e3.bias = s->b[2];
+  e3.c_f32 = s->Y;
+  e3.ldc = s->n_out;
+  if (destd) {
+    e3.scale = s->stdv;
+    e3.shift = s->mean;
+  }
+  e = gemm_bf16(false, true, n, s->n_out, s->h2, s->H2, s->h2, s->Wb[2], s->h2, e3, st);
+  return hipst(e, "gemm 3");
+}
+
+}  // namespace
+}  // namespace ms
+
+using namespace ms;
+
+ms_status ms_surrogate_predict(ms_surrogate *s, int n, const float *q, const float **Y,
+                               hipStream_t st) {
+  ms_status r = ensure_cap(s, n);
+  if (r != MS_OK) return r;
+  r = forward(s, n, q, true, false, st);
+  *Y = s->Y;
+  return r;
+}
+
+extern "C" {
+
+const char *ms_surrogate_last_error(void) { return s_err.c_str(); }
+
+ms_status ms_surrogate_create(const ms_model *m, int32_t hidden, uint64_t seed, ms_surrogate **out) {
+  s_err.clear();
+  if (!m || !out || hidden <= 0 || hidden % 8) return sfail(MS_E_ARG, "bad arguments (hidden must be a positive multiple of 8)");
+  ms_model_info info;
+  if (ms_model_info_get(m, &info) != MS_OK) return sfail(MS_E_ARG, "model info failed");
+  std::vector<int> hq;
+  std::vector<float> lo, hi;
+  ms_surrogate_tables(m, &hq, &lo, &hi);
+  ms_surrogate *s = new ms_surrogate();
+  s->n_mus = info.n_mus;
+  s->nq = info.nq;
+  s->free_root = info.nq != info.nv;
+  s->n_in = ((int)hq.size() + 15) / 16 * 16;
+  s->h1 = s->h2 = hidden;
+  s->n_out = 4 * info.n_mus;
+  hq.resize(s->n_in, -1);
+  lo.resize(s->n_in, 0.0f);
+  hi.resize(s->n_in, 0.0f);
+  const int in[3] = {s->n_in, s->h1, s->h2}, outd[3] = {s->h1, s->h2, s->n_out};
+  for (int l = 0; l < 3; ++l) {
+    const size_t nw = (size_t)in[l] * outd[l];
+    s->W[l] = dalloc<float>(s, nw);
+    s->gW[l] = dalloc<float>(s, nw);
+    s->mW[l] = dalloc<float>(s, nw);
+    s->vW[l] = dalloc<float>(s, nw);
+    s->Wb[l] = dalloc<bf16>(s, nw);
+    s->b[l] = dalloc<float>(s, outd[l]);
+    s->gb[l] = dalloc<float>(s, outd[l]);
+    s->mb[l] = dalloc<float>(s, outd[l]);
+    s->vb[l] = dalloc<float>(s, outd[l]);
+    if (!s->W[l] || !s->gW[l] || !s->mW[l] || !s->vW[l] || !s->Wb[l] || !s->b[l] || !s->gb[l] ||
+        !s->mb[l] || !s->vb[l]) {
+      ms_surrogate_destroy(s);
+      return sfail(MS_E_ALLOC, "surrogate allocation failed");
+    }
+    hipLaunchKernelGGL(k_init, dim3(blocks((long long)nw)), dim3(256), 0, 0, s->W[l], (int)nw, in[l],
+                       (unsigned long long)seed * 3ull + (unsigned long long)l);
+    hipLaunchKernelGGL(k_to_bf16, dim3(blocks((long long)nw)), dim3(256), 0, 0, s->W[l], s->Wb[l], (int)nw);
+  }
+  s->mean = dalloc<float>(s, s->n_out);
+  s->stdv = dalloc<float>(s, s->n_out);
+  s->istd = dalloc<float>(s, s->n_out);
+  s->mask = dalloc<float>(s, s->n_out);
+  s->lo = dalloc<float>(s, s->n_in);
+  s->hi = dalloc<float>(s, s->n_in);
+  s->hinge_q = dalloc<int>(s, s->n_in);
+  if (!s->mean || !s->stdv || !s->istd || !s->mask || !s->lo || !s->hi || !s->hinge_q) {
+    ms_surrogate_destroy(s);
+    return sfail(MS_E_ALLOC, "surrogate allocation failed");
+  }
+  // identity standardisation until set; mask from the span table
+  std::vector<int32_t> spans((size_t)3 * s->n_mus);
+  if (s->n_mus > 0) ms_model_spans(m, spans.data());
+  std::vector<float> ones(s->n_out, 1.0f), zeros(s->n_out, 0.0f), msk(s->n_out, 1.0f);
+  for (int i = 0; i < 3 * s->n_mus; ++i) msk[s->n_mus + i] = spans[i] >= 0 ? 1.0f : 0.0f;
+  hipError_t e = hipMemcpy(s->mean, zeros.data(), 4 * s->n_out, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(s->stdv, ones.data(), 4 * s->n_out, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(s->istd, ones.data(), 4 * s->n_out, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(s->mask, msk.data(), 4 * s->n_out, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(s->lo, lo.data(), 4 * s->n_in, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(s->hi, hi.data(), 4 * s->n_in, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(s->hinge_q, hq.data(), 4 * s->n_in, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e != hipSuccess) {
+    ms_surrogate_destroy(s);
+    return hipst(e, "surrogate setup");
+  }
+  *out = s;
+  return MS_OK;
+}
+
+void ms_surrogate_destroy(ms_surrogate *s) {
+  if (!s) return;
+  for (void *p : s->owned) (void)hipFree(p);
+  delete s;
+}
+
+ms_status ms_surrogate_dims(const ms_surrogate *s, int32_t *dims) {
+  if (!s || !dims) return sfail(MS_E_ARG, "NULL argument");
+  dims[0] = s->n_in;
+  dims[1] = s->h1;
+  dims[2] = s->h2;
+  dims[3] = s->n_out;
+  return MS_OK;
+}
+
+ms_status ms_surrogate_params(ms_surrogate *s, int32_t set, float *W1, float *b1, float *W2, float *b2,
+                              float *W3, float *b3) {
+  if (!s || !W1 || !b1 || !W2 || !b2 || !W3 || !b3) return sfail(MS_E_ARG, "NULL argument");
+  float *hw[3] = {W1, W2, W3}, *hb[3] = {b1, b2, b3};
+  const int in[3] = {s->n_in, s->h1, s->h2}, outd[3] = {s->h1, s->h2, s->n_out};
+  hipError_t e = hipDeviceSynchronize();
+  for (int l = 0; l < 3 && e == hipSuccess; ++l) {
+    const size_t nw = (size_t)in[l] * outd[l];
+    if (set) {
+      e = hipMemcpy(s->W[l], hw[l], 4 * nw, hipMemcpyHostToDevice);
+      if (e == hipSuccess) e = hipMemcpy(s->b[l], hb[l], 4 * outd[l], hipMemcpyHostToDevice);
+      if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_to_bf16, dim3(blocks((long long)nw)), dim3(256), 0, 0, s->W[l], s->Wb[l], (int)nw);
+        e = hipGetLastError();
+      }
+    } else {
+      e = hipMemcpy(hw[l], s->W[l], 4 * nw, hipMemcpyDeviceToHost);
+      if (e == hipSuccess) e = hipMemcpy(hb[l], s->b[l], 4 * outd[l], hipMemcpyDeviceToHost);
+    }
+  }
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  return hipst(e, "params copy");
+}
+
+ms_status ms_surrogate_grads(ms_surrogate *s, float *W1, float *b1, float *W2, float *b2, float *W3,
+                             float *b3) {
+  if (!s || !W1 || !b1 || !W2 || !b2 || !W3 || !b3) return sfail(MS_E_ARG, "NULL argument");
+  float *hw[3] = {W1, W2, W3}, *hb[3] = {b1, b2, b3};
+  const int in[3] = {s->n_in, s->h1, s->h2}, outd[3] = {s->h1, s->h2, s->n_out};
+  hipError_t e = hipDeviceSynchronize();
+  for (int l = 0; l < 3 && e == hipSuccess; ++l) {
+    e = hipMemcpy(hw[l], s->gW[l], 4 * (size_t)in[l] * outd[l], hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(hb[l], s->gb[l], 4 * outd[l], hipMemcpyDeviceToHost);
+  }
+  return hipst(e, "grads copy");
+}
+
+ms_status ms_surrogate_set_norm(ms_surrogate *s, const float *mean, const float *stdv) {
+  if (!s || !mean || !stdv) return sfail(MS_E_ARG, "NULL argument");
+  std::vector<float> is(s->n_out);
+  for (int i = 0; i < s->n_out; ++i) {
+    if (!(stdv[i] > 0.0f) || !std::isfinite(mean[i])) return sfail(MS_E_ARG, "std must be > 0");
+    is[i] = 1.0f / stdv[i];
+  }
+  hipError_t e = hipMemcpy(s->mean, mean, 4 * s->n_out, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(s->stdv, stdv, 4 * s->n_out, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(s->istd, is.data(), 4 * s->n_out, hipMemcpyHostToDevice);
+  return hipst(e, "set norm");
+}
+
+ms_status ms_surrogate_sample(ms_surrogate *s, int32_t n, uint64_t seed, int64_t offset, float *q,
+                              void *stream) {
+  if (!s || n <= 0 || !q) return sfail(MS_E_ARG, "bad arguments");
+  hipLaunchKernelGGL(k_sample, dim3(blocks(n)), dim3(256), 0, (hipStream_t)stream, n, s->nq,
+                     s->free_root, s->hinge_q, s->lo, s->hi, s->n_in, (unsigned long long)seed,
+                     (long long)offset, q);
+  return hipst(hipGetLastError(), "sample");
+}
+
+ms_status ms_surrogate_forward(ms_surrogate *s, int32_t n, const float *q, float *L, float *r,
+                               void *stream) {
+  s_err.clear();
+  if (!s || n <= 0 || !q || !L || !r) return sfail(MS_E_ARG, "bad arguments");
+  ms_status st = ensure_cap(s, n);
+  if (st != MS_OK) return st;
+  hipStream_t hs = (hipStream_t)stream;
+  st = forward(s, n, q, true, false, hs);
+  if (st != MS_OK) return st;
+  hipLaunchKernelGGL(k_unpack, dim3(blocks((long long)n * s->n_out)), dim3(256), 0, hs, s->Y,
+                     s->n_mus, n, L, r);
+  return hipst(hipGetLastError(), "unpack");
+}
+
+ms_status ms_surrogate_train_step(ms_surrogate *s, int32_t n, const float *q, const float *L,
+                                  const float *r, float lr, int32_t step, float *loss,
+                                  void *stream) {
+  s_err.clear();
+  if (!s || n <= 0 || n % 8 || !q || !L || !r || step < 1)
+    return sfail(MS_E_ARG, "bad arguments (batch must be a positive multiple of 8, step >= 1)");
+  ms_status st = ensure_cap(s, n);
+  if (st != MS_OK) return st;
+  hipStream_t hs = (hipStream_t)stream;
+  const long long no = (long long)n * s->n_out;
+  hipLaunchKernelGGL(k_targets, dim3(blocks(no)), dim3(256), 0, hs, L, r, s->n_mus, n, s->mean,
+                     s->istd, s->mask, s->T);
+  st = forward(s, n, q, false, true, hs);
+  if (st != MS_OK) return st;
+  const int nb = blocks(no);
+  hipLaunchKernelGGL(k_loss, dim3(nb), dim3(256), 0, hs, s->Y, s->T, s->mask, n, s->n_out, s->dY,
+                     s->dYb, s->part);
+  if (loss) hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(1), 0, hs, s->part, nb, n, s->n_out, loss);
+  // layer 3: gb3 = colsum dY, gW3[o][j] = sum_p dY[p][o] H2[p][j], dH2 -> dZ2
+  hipLaunchKernelGGL(k_colsum, dim3(blocks(s->n_out)), dim3(256), 0, hs, s->dY, n, s->n_out, s->gb[2]);
+  GemmEpi g3;
+  g3.c_f32 = s->gW[2];
+  g3.ldc = s->h2;
+  hipError_t e = gemm_bf16(true, false, s->n_out, s->h2, n, s->dYb, s->n_out, s->H2, s->h2, g3, hs);
+  if (e != hipSuccess) return hipst(e, "gemm dW3");
+  GemmEpi d2;
+  d2.dact = s->Z2;
+  d2.c_f32 = s->dZ2;
+  d2.c_bf16 = s->dZ2b;
+  d2.ldc = s->h2;
+  e = gemm_bf16(false, false, n, s->h2, s->n_out, s->dYb, s->n_out, s->Wb[2], s->h2, d2, hs);
+  if (e != hipSuccess) return hipst(e, "gemm dZ2");
+  // layer 2
+  hipLaunchKernelGGL(k_colsum, dim3(blocks(s->h2)), dim3(256), 0, hs, s->dZ2, n, s->h2, s->gb[1]);
+  GemmEpi g2;
+  g2.c_f32 = s->gW[1];
+  g2.ldc = s->h1;
+  e = gemm_bf16(true, false, s->h2, s->h1, n, s->dZ2b, s->h2, s->H1, s->h1, g2, hs);
+  if (e != hipSuccess) return hipst(e, "gemm dW2");
+  GemmEpi d1;
+  d1.dact = s->Z1;
+  d1.c_f32 = s->dZ1;
+  d1.c_bf16 = s->dZ1b;
+  d1.ldc = s->h1;
+  e = gemm_bf16(false, false, n, s->h1, s->h2, s->dZ2b, s->h2, s->Wb[1], s->h1, d1, hs);
+  if (e != hipSuccess) return hipst(e, "gemm dZ1");
+  // layer 1
+  hipLaunchKernelGGL(k_colsum, dim3(blocks(s->h1)), dim3(256), 0, hs, s->dZ1, n, s->h1, s->gb[0]);
+  GemmEpi g1;
+  g1.c_f32 = s->gW[0];
+  g1.ldc = s->n_in;
+  e = gemm_bf16(true, false, s->h1, s->n_in, n, s->dZ1b, s->h1, s->X, s->n_in, g1, hs);
+  if (e != hipSuccess) return hipst(e, "gemm dW1");
+  // Adam
+  if (lr > 0.0f) {
+    const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+    const float c1 = 1.0f - powf(b1, (float)step), c2 = 1.0f - powf(b2, (float)step);
+    const int in[3] = {s->n_in, s->h1, s->h2}, outd[3] = {s->h1, s->h2, s->n_out};
+    for (int l = 0; l < 3; ++l) {
+      const int nw = in[l] * outd[l];
+      hipLaunchKernelGGL(k_adam, dim3(blocks(nw)), dim3(256), 0, hs, s->W[l], s->mW[l], s->vW[l],
+                         s->gW[l], nw, lr, b1, b2, eps, c1, c2, s->Wb[l]);
+      hipLaunchKernelGGL(k_adam, dim3(blocks(outd[l])), dim3(256), 0, hs, s->b[l], s->mb[l], s->vb[l],
+                         s->gb[l], outd[l], lr, b1, b2, eps, c1, c2, (bf16 *)nullptr);
+    }
+  }
+  return hipst(hipGetLastError(), "train step");
+}
+
+}  // extern "C"

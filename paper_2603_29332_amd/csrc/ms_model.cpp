@@ -70,6 +70,14 @@ ms_status build_tables(const ms_model_desc *d, Tables *t, std::string *msg) {
   t->jrot.assign(d->jrot, d->jrot + 9 * n);
   t->axis.assign(d->axis, d->axis + 3 * n);
   t->damping.assign(d->damping, d->damping + nv);
+  t->qlo.assign(nv, -3.14159265f);
+  t->qhi.assign(nv, 3.14159265f);
+  if (d->qlo && d->qhi)
+    for (int j = 0; j < nv; ++j) {
+      if (std::isfinite(d->qlo[j])) t->qlo[j] = d->qlo[j];
+      if (std::isfinite(d->qhi[j])) t->qhi[j] = d->qhi[j];
+      need(t->qlo[j] <= t->qhi[j], "qlo must not exceed qhi", MS_E_MODEL, &st, msg);
+    }
   for (int j = 0; j < nv; ++j)
     need(std::isfinite(d->damping[j]) && d->damping[j] >= 0, "damping must be >= 0", MS_E_MODEL, &st, msg);
 
@@ -174,14 +182,33 @@ ms_status build_tables(const ms_model_desc *d, Tables *t, std::string *msg) {
   t->nnz_row.resize(t->nnz);
   for (int j = 0; j < nv; ++j)
     for (int e = t->row_start[j]; e < t->row_start[j + 1]; ++e) t->nnz_row[e] = j;
+  t->rs_path.resize(t->nnz);
+  for (int e = 0; e < t->nnz; ++e) t->rs_path[e] = t->row_start[t->path[e]];
   t->max_depth = *std::max_element(t->dof_depth.begin(), t->dof_depth.end());
   need(t->max_depth <= kMaxDepth, "DoF tree deeper than 64", MS_E_UNSUPPORTED, &st, msg);
   auto dof_anc = [&](int a, int b) {  // DoF a is b or an ancestor of b
     return t->dof_depth[a] <= t->dof_depth[b] && dpath[b][t->dof_depth[a] - 1] == a;
   };
-  for (int a = 0; a + 1 < t->max_depth; ++a)
-    for (int b = 0; b <= a; ++b) t->pair_ab.push_back(a | (b << 8));
-  t->max_pairs = (int)t->pair_ab.size();
+  // level schedules: height (longest path to a leaf) and depth of each DoF
+  std::vector<int> height(nv, 0);
+  for (int j = nv - 1; j >= 0; --j)
+    if (dof_parent[j] >= 0) height[dof_parent[j]] = std::max(height[dof_parent[j]], height[j] + 1);
+  t->n_hlev = 1 + *std::max_element(height.begin(), height.end());
+  t->n_dlev = t->max_depth;
+  t->hlev_start.assign(t->n_hlev + 1, 0);
+  for (int h = 0; h < t->n_hlev; ++h) {
+    t->hlev_start[h] = (int)t->hlev_dof.size();
+    for (int j = 0; j < nv; ++j)
+      if (height[j] == h) t->hlev_dof.push_back(j);
+  }
+  t->hlev_start[t->n_hlev] = (int)t->hlev_dof.size();
+  t->dlev_start.assign(t->n_dlev + 1, 0);
+  for (int dl = 0; dl < t->n_dlev; ++dl) {
+    t->dlev_start[dl] = (int)t->dlev_dof.size();
+    for (int j = 0; j < nv; ++j)
+      if (t->dof_depth[j] == dl + 1) t->dlev_dof.push_back(j);
+  }
+  t->dlev_start[t->n_dlev] = (int)t->dlev_dof.size();
 
   // muscles
   const int nm = d->n_mus;
@@ -201,21 +228,31 @@ ms_status build_tables(const ms_model_desc *d, Tables *t, std::string *msg) {
   std::vector<std::vector<int>> proj(nv);
   std::map<int, std::vector<int>> dent;  // H index -> items
   int via_max = 0;
+  // internal muscle order: by via-point count (descending), so the 64
+  // muscles a wavefront handles together mostly share their loop bounds
+  t->mus_ext.resize(nm);
+  for (int m = 0; m < nm; ++m) t->mus_ext[m] = m;
+  std::stable_sort(t->mus_ext.begin(), t->mus_ext.end(), [&](int a, int b) {
+    return d->via_start[a + 1] - d->via_start[a] > d->via_start[b + 1] - d->via_start[b];
+  });
+  t->mus_int.assign(nm, 0);
+  for (int m = 0; m < nm; ++m) t->mus_int[t->mus_ext[m]] = m;
   for (int m = 0; m < nm; ++m) {
-    int s0 = d->via_start[m], s1 = d->via_start[m + 1], P = s1 - s0;
+    const int ex = t->mus_ext[m];
+    int s0 = d->via_start[ex], s1 = d->via_start[ex + 1], P = s1 - s0;
     need(s0 >= 0 && P >= 2, "each muscle needs >= 2 via-points", MS_E_MODEL, &st, msg);
     need(P <= kMaxVia, "more than 8 via-points in a muscle", MS_E_UNSUPPORTED, &st, msg);
-    need(d->f0[m] >= 0 && d->l_opt[m] > 0 && d->v_max[m] > 0 && d->tau_act[m] > 0 &&
-             d->tau_deact[m] > 0 && std::isfinite(d->l_slack[m]),
+    need(d->f0[ex] >= 0 && d->l_opt[ex] > 0 && d->v_max[ex] > 0 && d->tau_act[ex] > 0 &&
+             d->tau_deact[ex] > 0 && std::isfinite(d->l_slack[ex]),
          "Hill parameters must be positive", MS_E_MODEL, &st, msg);
     if (st != MS_OK) return st;
     via_max = std::max(via_max, P);
-    t->mus_f0.push_back(d->f0[m]);
-    t->mus_ilopt.push_back(1.0f / d->l_opt[m]);
-    t->mus_lslack.push_back(d->l_slack[m]);
-    t->mus_ivl.push_back(1.0f / (d->v_max[m] * d->l_opt[m]));
-    t->mus_tact.push_back(d->tau_act[m]);
-    t->mus_tdeact.push_back(d->tau_deact[m]);
+    t->mus_f0.push_back(d->f0[ex]);
+    t->mus_ilopt.push_back(1.0f / d->l_opt[ex]);
+    t->mus_lslack.push_back(d->l_slack[ex]);
+    t->mus_ivl.push_back(1.0f / (d->v_max[ex] * d->l_opt[ex]));
+    t->mus_tact.push_back(d->tau_act[ex]);
+    t->mus_tdeact.push_back(d->tau_deact[ex]);
     t->mus_nvia[m] = P;
     std::vector<int> nodes(P);
     for (int k = 0; k < P; ++k) {
@@ -244,7 +281,7 @@ ms_status build_tables(const ms_model_desc *d, Tables *t, std::string *msg) {
     }
     if ((int)span.size() > 3) {
       std::ostringstream os;
-      os << "muscle " << m << " spans " << span.size() << " DoFs (at most 3 supported)";
+      os << "muscle " << ex << " spans " << span.size() << " DoFs (at most 3 supported)";
       need(false, os.str(), MS_E_UNSUPPORTED, &st, msg);
       return st;
     }
@@ -268,6 +305,8 @@ ms_status build_tables(const ms_model_desc *d, Tables *t, std::string *msg) {
       }
   }
   t->n_via_max = via_max;
+  t->grp_nvia.assign(t->mpl, 0);
+  for (int m = 0; m < nm; ++m) t->grp_nvia[m / kWave] = std::max(t->grp_nvia[m / kWave], t->mus_nvia[m]);
   t->proj_start.assign(nv + 1, 0);
   for (int j = 0; j < nv; ++j) {
     t->proj_start[j] = (int)t->proj_item.size();
@@ -298,10 +337,11 @@ ms_status build_tables(const ms_model_desc *d, Tables *t, std::string *msg) {
     return o;
   };
   t->off_flag = take(16);
+  t->off_tree = take(4 * (2 * n + t->n_level + 1));
   t->off_q = take(4 * nq);
   t->off_qd = take(4 * nv);
-  t->off_R = take(4 * 9 * n);
-  t->off_P = take(4 * 3 * n);
+  t->off_R = take(4 * 12 * n);  // per node R (9) then P (3)
+  t->off_P = t->off_R + 36;
   t->off_S = take(4 * 6 * nv);
   t->off_con = take(4 * 16 * std::max(t->n_con, 1));
   t->off_rhs = take(8 * nv);

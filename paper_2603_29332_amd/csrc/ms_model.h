@@ -5,6 +5,8 @@
 #include <string>
 #include <vector>
 
+#include <hip/hip_runtime.h>
+
 #include "../../include/ms.h"
 
 namespace ms {
@@ -23,7 +25,7 @@ struct Tables {
   // sizes
   int n_node = 0, nq = 0, nv = 0, n_mus = 0, n_con = 0, n_body = 0;
   int nnz = 0, max_depth = 0, n_level = 0, free_root = 0, mpl = 0;
-  int n_dent = 0, max_pairs = 0, n_via_max = 0;
+  int n_dent = 0, n_via_max = 0;
   float kc = 0, cc = 0, mu = 0, vs = 0, g[3] = {0, 0, 0};
   // per node
   std::vector<int32_t> parent, jtype, qadr, dadr, level_start, level_nodes;
@@ -39,8 +41,12 @@ struct Tables {
   // DoF
   std::vector<int32_t> dof_node, dof_kind;  // kind: 0 hinge, 1 slide, 2 root lin, 3 root ang
   std::vector<float> damping;
-  // muscles (SoA)
+  std::vector<float> qlo, qhi;              // [nv] pose-domain limits (+-pi if absent)
+  // muscles (SoA, internal order)
   std::vector<float> mus_f0, mus_ilopt, mus_lslack, mus_ivl, mus_tact, mus_tdeact;
+  std::vector<int32_t> mus_ext;           // internal slot -> caller's muscle index
+  std::vector<int32_t> mus_int;           // caller's muscle index -> internal slot
+  std::vector<int32_t> grp_nvia;          // max via count of each 64-muscle group
   std::vector<int32_t> mus_nvia;          // via count
   std::vector<int32_t> via_node;          // [kMaxVia][n_mus] SoA, padded
   std::vector<float> via_pos;             // [kMaxVia][3][n_mus] SoA, padded
@@ -53,11 +59,15 @@ struct Tables {
   // tree-sparse mass matrix (row j holds its ancestors by depth, diag last)
   std::vector<int32_t> row_start, dof_depth, path;     // path[nnz] = DoF id
   std::vector<int32_t> nnz_row;                        // row of each entry
-  std::vector<int32_t> pair_ab;           // triangular (a,b), b <= a, packed a | b<<8
+  std::vector<int32_t> rs_path;                        // row start of path[e]
+  // level schedules of the factorisation and solves: DoFs grouped by height
+  // (leaves first) and by depth (root first)
+  int n_hlev = 0, n_dlev = 0;
+  std::vector<int32_t> hlev_start, hlev_dof, dlev_start, dlev_dof;
   // LDS layout (byte offsets into the per-env LDS block)
   int off_q = 0, off_qd = 0, off_R = 0, off_P = 0, off_S = 0, off_V = 0,
       off_A = 0, off_F = 0, off_con = 0, off_rhs = 0, off_H = 0, off_x = 0,
-      off_scr = 0, off_flag = 0, lds_bytes = 0;
+      off_scr = 0, off_flag = 0, off_tree = 0, lds_bytes = 0;
   int n_levels_dof = 0;
 };
 
@@ -65,3 +75,14 @@ struct Tables {
 ms_status build_tables(const ms_model_desc *d, Tables *t, std::string *msg);
 
 }  // namespace ms
+
+// q index and pose-domain limits of every hinge/slide coordinate of a model
+// (the geometry surrogate's inputs), in node order.
+void ms_surrogate_tables(const ms_model *m, std::vector<int> *q_index, std::vector<float> *lo,
+                         std::vector<float> *hi);
+
+// De-standardised predictions of the surrogate for n poses into its own
+// workspace; *Y receives the device pointer ([n][4 n_mus]), valid until the
+// next call on the surrogate.
+ms_status ms_surrogate_predict(ms_surrogate *s, int n, const float *q, const float **Y,
+                               hipStream_t st);

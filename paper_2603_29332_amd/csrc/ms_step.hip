@@ -39,15 +39,18 @@ struct KModel {
   const int *dof_node, *dof_kind;
   const float *damping;
   const float *mus_f0, *mus_ilopt, *mus_lslack, *mus_ivl, *mus_tact, *mus_tdeact;
-  const int *mus_nvia, *via_node;
+  const int *mus_nvia, *via_node, *mus_ext, *mus_int, *grp_nvia;
+  const float *qlo, *qhi;
   const float *via_pos;
   const int *mus_span;
   const unsigned *mus_mask;
   const int *proj_start, *proj_item;
   const int *dent_h, *dent_start, *dent_item;
-  const int *row_start, *dof_depth, *path, *nnz_row, *pair_ab;
+  const int *row_start, *dof_depth, *path, *nnz_row, *rs_path;
+  int n_hlev, n_dlev;
+  const int *hlev_start, *hlev_dof, *dlev_start, *dlev_dof;
   int off_flag, off_q, off_qd, off_R, off_P, off_S, off_con, off_rhs, off_x, off_H,
-      off_scr, off_V, off_A, off_F;
+      off_scr, off_V, off_A, off_F, off_tree;
 };
 
 struct KRun {
@@ -61,12 +64,20 @@ struct KRun {
   long long step0;
   float *xar;
   float rho, s, mean;
+  int exc;     // EXC_ARRAY, EXC_IID or EXC_AR1
+  // surrogate geometry: predictions [n_env][4 n_mus] (caller's muscle
+  // order, L then r[3]), fallback tolerance (m), fallback counters
+  const float *geomY;
+  float fb_tol;
+  unsigned *fb_count;
+  int stages;  // 1: write stage outputs, do not advance the state;
+               // 2: geometry only (L, Ldot, r), nothing else
   // stage outputs (ms_step_stages)
   float *o_act, *o_L, *o_Ldot, *o_F, *o_r, *o_tau, *o_bias, *o_qdd;
   double *o_H;
 };
 
-enum { EXC_ARRAY = 0, EXC_IID = 1, EXC_AR1 = 2 };
+enum { EXC_ARRAY = MS_EXC_ARRAY, EXC_IID = MS_EXC_IID, EXC_AR1 = MS_EXC_AR1 };
 
 // ------------------------------------------------------------ small maths
 struct V3 {
@@ -92,6 +103,14 @@ __device__ __forceinline__ void st3(float *p, V3 a) {
   p[2] = a.z;
 }
 
+// Apply node frame F (12 floats, 16-byte aligned: R row-major, then P) to
+// a local point: three 128-bit LDS reads.
+__device__ __forceinline__ V3 frame_apply(const float *F, V3 x) {
+  const float4 a = *(const float4 *)F, b = *(const float4 *)(F + 4), c = *(const float4 *)(F + 8);
+  return v3(a.x * x.x + a.y * x.y + a.z * x.z + c.y, a.w * x.x + b.x * x.y + b.y * x.z + c.z,
+            b.z * x.x + b.w * x.y + c.x * x.z + c.w);
+}
+
 // SplitMix64 output function (Steele, Lea & Flood 2014).
 __device__ __forceinline__ unsigned long long splitmix64(unsigned long long x) {
   unsigned long long z = x + 0x9E3779B97F4A7C15ull;
@@ -108,8 +127,11 @@ __device__ __forceinline__ float u24(unsigned long long z, int shift) {
 // (Irwin-Hall(4): mean 2, variance 1/3), x <- rho x + s xi,
 // u = clamp(mean + x, 0, 1). Each operation is rounded to float32 in this
 // order: no contraction into fused multiply-adds.
-__device__ __noinline__ float ar1_step(unsigned long long key, int mi, float &x, float rho, float s,
-                                       float mean) {
+struct AR1 {
+  float u, x;
+};
+__device__ __forceinline__ AR1 ar1_step(unsigned long long key, int mi, float x, float rho, float s,
+                                        float mean) {
 #pragma clang fp contract(off)
   const unsigned long long z1 = splitmix64(key ^ (2ull * (unsigned long long)mi));
   const unsigned long long z2 = splitmix64(key ^ (2ull * (unsigned long long)mi + 1ull));
@@ -117,8 +139,8 @@ __device__ __noinline__ float ar1_step(unsigned long long key, int mi, float &x,
   const float xi = (t - 2.0f) * 1.7320508075688772f;
   const float a = rho * x;
   const float b = s * xi;
-  x = a + b;
-  return fminf(fmaxf(mean + x, 0.0f), 1.0f);
+  const float xn = a + b;
+  return AR1{fminf(fmaxf(mean + xn, 0.0f), 1.0f), xn};
 }
 
 // Hill curves: Gaussian active force-length, exponential passive
@@ -148,43 +170,138 @@ __device__ __forceinline__ float hill_fv_slope(float vm) {
   return 0.032f / (b * b);
 }
 
+// Value of v held by lane `src` (uniform), for every lane.
+__device__ __forceinline__ double lane_bcast(double v, int src) {
+  const unsigned long long b = __double_as_longlong(v);
+  const unsigned lo = __builtin_amdgcn_readlane((unsigned)b, src);
+  const unsigned hi = __builtin_amdgcn_readlane((unsigned)(b >> 32), src);
+  return __longlong_as_double(((unsigned long long)hi << 32) | lo);
+}
+
+// Sum over the 64 lanes of a wavefront (butterfly exchange); every lane
+// receives the total.
 __device__ __forceinline__ double wave_sum(double v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
   return v;
 }
 
+// Exact via-point geometry of muscle slot m: path length L, moment arms
+// r[3] = -dL/dq of its span DoFs and Ldot. Path w_0..w_{P-1}; with unit
+// segment vectors e_k, dL/dq_j = sum_k g_k . (a_j x (w_k - o_j)) over the
+// via-points moved by hinge j (g_k = e_{k-1} - e_k), a_j . sum_k g_k for a
+// slide. Pg bounds the via-point loops uniformly across the wavefront.
+template <int NVIA>
+__device__ __forceinline__ float muscle_geometry(const KModel &M, int m, int Pg, const float *Rl,
+                                                 const float *Pl, const float *Sl, const float *qd,
+                                                 V3 O, float r3[3], float &Ld) {
+  const int nm = M.n_mus;
+  const int P = M.mus_nvia[m];
+  V3 w[NVIA], gk[NVIA];
+#pragma unroll
+  for (int k = 0; k < NVIA; ++k) {
+    w[k] = v3(0.f, 0.f, 0.f);
+    if (k < Pg && k < P) {
+      const int b = M.via_node[(size_t)k * nm + m];
+      V3 x = v3(M.via_pos[((size_t)k * 3 + 0) * nm + m], M.via_pos[((size_t)k * 3 + 1) * nm + m],
+                M.via_pos[((size_t)k * 3 + 2) * nm + m]);
+      w[k] = b >= 0 ? frame_apply(Rl + 12 * b, x) : x - O;
+    }
+  }
+  float L = 0.f;
+  V3 eprev = v3(0.f, 0.f, 0.f);
+#pragma unroll
+  for (int k = 0; k < NVIA; ++k) {
+    gk[k] = v3(0.f, 0.f, 0.f);
+    if (k < Pg) {
+      if (k + 1 < P) {
+        V3 d = w[k + 1] - w[k];
+        float l = sqrtf(dot(d, d));
+        L += l;
+        V3 e = (1.0f / l) * d;
+        gk[k] = eprev - e;
+        eprev = e;
+      } else if (k + 1 == P) {
+        gk[k] = eprev;
+      }
+    }
+  }
+  const unsigned mask = M.mus_mask[m];
+  Ld = 0.f;
+#pragma unroll
+  for (int s = 0; s < 3; ++s) {
+    r3[s] = 0.f;
+    const int j = M.mus_span[s * nm + m];
+    if (j >= 0) {
+      const unsigned mk = (mask >> (8 * s)) & 0xFFu;
+      const float *S = Sl + 6 * j;
+      float dl;
+      if (M.dof_kind[j] == 0) {
+        V3 o = ld3(Pl + 12 * M.dof_node[j]);
+        V3 acc = v3(0.f, 0.f, 0.f);
+#pragma unroll
+        for (int k = 0; k < NVIA; ++k)
+          if ((mk >> k) & 1u) acc = acc + cross(w[k] - o, gk[k]);
+        dl = dot(ld3(S), acc);
+      } else {
+        V3 acc = v3(0.f, 0.f, 0.f);
+#pragma unroll
+        for (int k = 0; k < NVIA; ++k)
+          if ((mk >> k) & 1u) acc = acc + gk[k];
+        dl = dot(ld3(S + 3), acc);
+      }
+      r3[s] = -dl;
+      Ld += dl * qd[j];
+    }
+  }
+  return L;
+}
+
 // ------------------------------------------------------------------ kernel
-template <int MPL, int EXC, bool STAGES>
+template <int MPL, int NVIA>
 __global__ __launch_bounds__(64) void k_step(KModel M, KRun Rn, int n_steps) {
   extern __shared__ __align__(16) unsigned char lds[];
   const int env = blockIdx.x;
   const int lane = threadIdx.x;
   const int nq = M.nq, nv = M.nv, nm = M.n_mus, nn = M.n_node;
-  float *q = (float *)(lds + M.off_q);
-  float *qd = (float *)(lds + M.off_qd);
+  float *__restrict__ q = (float *)(lds + M.off_q);
+  float *__restrict__ qd = (float *)(lds + M.off_qd);
+  // node frames: 12 floats per node, 16-byte aligned: R (row-major) then P
   float *Rl = (float *)(lds + M.off_R);
-  float *Pl = (float *)(lds + M.off_P);
-  float *Sl = (float *)(lds + M.off_S);
+  float *Pl = Rl + 9;
+  float *__restrict__ Sl = (float *)(lds + M.off_S);
   float *Vl = (float *)(lds + M.off_V);
   float *Al = (float *)(lds + M.off_A);
   float *Fl = (float *)(lds + M.off_F);  // f_b[n_body][6] then F_n[n_node][6]
-  float *Cl = (float *)(lds + M.off_con);
-  double *rhs = (double *)(lds + M.off_rhs);
-  double *xs = (double *)(lds + M.off_x);
-  double *H = (double *)(lds + M.off_H);
+  float *__restrict__ Cl = (float *)(lds + M.off_con);
+  double *__restrict__ rhs = (double *)(lds + M.off_rhs);
+  double *__restrict__ xs = (double *)(lds + M.off_x);
+  double *__restrict__ H = (double *)(lds + M.off_H);
   unsigned char *scr = lds + M.off_scr;
-  int *flag = (int *)(lds + M.off_flag);
+  // tree schedule staged in LDS once per launch: level starts, nodes by
+  // level, and per node (jtype | (parent+1) << 2 | dof << 10)
+  int *tlev = (int *)(lds + M.off_tree);
+  int *tnode = tlev + M.n_level + 1;
+  int *tinfo = tnode + nn;
+  for (int l = lane; l <= M.n_level; l += 64) tlev[l] = M.level_start[l];
+  for (int i = lane; i < nn; i += 64) {
+    tnode[i] = M.level_nodes[i];
+    tinfo[i] = M.jtype[i] | ((M.parent[i] + 1) << 2) | (M.dadr[i] << 10);
+  }
   const float dt = Rn.dt;
+  const int exc = Rn.exc;
+  const bool stages = Rn.stages != 0;
+  const bool geom_only = Rn.stages == 2;
 
   for (int i = lane; i < nq; i += 64) q[i] = Rn.q[(size_t)env * nq + i];
-  for (int i = lane; i < nv; i += 64) qd[i] = Rn.qd[(size_t)env * nv + i];
+  for (int i = lane; i < nv; i += 64) qd[i] = Rn.qd ? Rn.qd[(size_t)env * nv + i] : 0.0f;
   float act[MPL], xar[MPL];
 #pragma unroll
   for (int t = 0; t < MPL; ++t) {
     int mi = lane + 64 * t;
-    act[t] = mi < nm ? Rn.act[(size_t)env * nm + mi] : 0.0f;
+    const int mx = mi < nm ? M.mus_ext[mi] : 0;
+    act[t] = (mi < nm && Rn.act) ? Rn.act[(size_t)env * nm + mx] : 0.0f;
     xar[t] = 0.0f;
-    if (EXC == EXC_AR1 && mi < nm) xar[t] = Rn.xar[(size_t)env * nm + mi];
+    if (exc == EXC_AR1 && mi < nm) xar[t] = Rn.xar[(size_t)env * nm + mx];
   }
   unsigned status = Rn.status ? Rn.status[env] : 0u;
   __syncthreads();
@@ -196,7 +313,7 @@ __global__ __launch_bounds__(64) void k_step(KModel M, KRun Rn, int n_steps) {
     for (int i = lane; i < nq; i += 64) bad |= !isfinite(q[i]);
     for (int i = lane; i < nv; i += 64) bad |= !isfinite(qd[i]);
     unsigned long long key = 0;
-    if (EXC != EXC_ARRAY)
+    if (exc != EXC_ARRAY)
       key = splitmix64(splitmix64(Rn.seed ^ (unsigned long long)env) ^
                        (unsigned long long)(Rn.step0 + step));
 #pragma unroll
@@ -204,13 +321,16 @@ __global__ __launch_bounds__(64) void k_step(KModel M, KRun Rn, int n_steps) {
       int mi = lane + 64 * t;
       u[t] = 0.0f;
       if (mi < nm) {
+        const int mx = M.mus_ext[mi];
         bad |= !isfinite(act[t]);
-        if (EXC == EXC_ARRAY) {
-          u[t] = Rn.u[((size_t)step * Rn.n_env + env) * nm + mi];
-        } else if (EXC == EXC_IID) {
-          u[t] = u24(splitmix64(key ^ (unsigned long long)mi), 40);
+        if (exc == EXC_ARRAY) {
+          u[t] = Rn.u ? Rn.u[((size_t)step * Rn.n_env + env) * nm + mx] : 0.0f;
+        } else if (exc == EXC_IID) {
+          u[t] = u24(splitmix64(key ^ (unsigned long long)mx), 40);
         } else {
-          u[t] = ar1_step(key, mi, xar[t], Rn.rho, Rn.s, Rn.mean);
+          const AR1 r = ar1_step(key, mx, xar[t], Rn.rho, Rn.s, Rn.mean);
+          u[t] = r.u;
+          xar[t] = r.x;
         }
       }
     }
@@ -230,7 +350,7 @@ __global__ __launch_bounds__(64) void k_step(KModel M, KRun Rn, int n_steps) {
         float a = act[t];
         float tau = uc > a ? M.mus_tact[mi] * (0.5f + 1.5f * a) : M.mus_tdeact[mi] / (0.5f + 1.5f * a);
         act1[t] = fminf(fmaxf(a + dt * (uc - a) / tau, 0.0f), 1.0f);
-        if (STAGES) Rn.o_act[(size_t)env * nm + mi] = act1[t];
+        if (stages && Rn.o_act) Rn.o_act[(size_t)env * nm + M.mus_ext[mi]] = act1[t];
       }
     }
 
@@ -238,45 +358,83 @@ __global__ __launch_bounds__(64) void k_step(KModel M, KRun Rn, int n_steps) {
     // O = root origin (floating) or world origin (fixed base).
     V3 O = M.free_root ? v3(q[0], q[1], q[2]) : v3(0.f, 0.f, 0.f);
     const V3 g = v3(M.gx, M.gy, M.gz);
-    for (int l = 0; l < M.n_level; ++l) {
-      const int b0 = M.level_start[l], b1 = M.level_start[l + 1];
-      for (int k = b0 + lane; k < b1; k += 64) {
-        const int i = M.level_nodes[k];
-        const int jt = M.jtype[i];
-        float *R = Rl + 9 * i;
-        const int da = M.dadr[i];
-        if (jt == 2) {
-          const float *x = q + M.qadr[i] + 3;
-          float nrm = sqrtf(x[0] * x[0] + x[1] * x[1] + x[2] * x[2] + x[3] * x[3]);
-          float w = x[0] / nrm, a = x[1] / nrm, b = x[2] / nrm, c = x[3] / nrm;
-          R[0] = 1 - 2 * (b * b + c * c); R[1] = 2 * (a * b - w * c); R[2] = 2 * (a * c + w * b);
-          R[3] = 2 * (a * b + w * c); R[4] = 1 - 2 * (a * a + c * c); R[5] = 2 * (b * c - w * a);
-          R[6] = 2 * (a * c - w * b); R[7] = 2 * (b * c + w * a); R[8] = 1 - 2 * (a * a + b * b);
-          st3(Pl + 3 * i, v3(0.f, 0.f, 0.f));
-          for (int kk = 0; kk < 3; ++kk) {
-            float *S = Sl + 6 * (da + kk);
-            S[0] = S[1] = S[2] = 0.f;
-            S[3] = kk == 0; S[4] = kk == 1; S[5] = kk == 2;
-            float *S2 = Sl + 6 * (da + 3 + kk);
-            S2[0] = R[kk]; S2[1] = R[3 + kk]; S2[2] = R[6 + kk];
-            S2[3] = S2[4] = S2[5] = 0.f;
-          }
-          V3 v = ld3(qd + da);
-          V3 wb = ld3(qd + da + 3);
-          V3 ww = mulR(R, wb);
-          float *V = Vl + 6 * i, *A = Al + 6 * i;
-          st3(V, ww);
-          st3(V + 3, v);
-          st3(A, v3(0.f, 0.f, 0.f));
-          st3(A + 3, cross(v, ww) - g);
-          continue;
+    // (1) every node's joint transform in parallel: rotation jrot Rot(axis, q)
+    // and offset parked in the node's frame slot, the axis jrot*axis in its A
+    // slot; the floating root is finished here
+    for (int i = lane; i < nn; i += 64) {
+      const int jt = M.jtype[i];
+      float *F = Rl + 12 * i;
+      const int da = M.dadr[i];
+      if (jt == 2) {
+        const float *x = q + M.qadr[i] + 3;
+        float nrm = sqrtf(x[0] * x[0] + x[1] * x[1] + x[2] * x[2] + x[3] * x[3]);
+        float w = x[0] / nrm, a = x[1] / nrm, b = x[2] / nrm, c = x[3] / nrm;
+        float *R = F;
+        R[0] = 1 - 2 * (b * b + c * c); R[1] = 2 * (a * b - w * c); R[2] = 2 * (a * c + w * b);
+        R[3] = 2 * (a * b + w * c); R[4] = 1 - 2 * (a * a + c * c); R[5] = 2 * (b * c - w * a);
+        R[6] = 2 * (a * c - w * b); R[7] = 2 * (b * c + w * a); R[8] = 1 - 2 * (a * a + b * b);
+        st3(F + 9, v3(0.f, 0.f, 0.f));
+        for (int kk = 0; kk < 3; ++kk) {
+          float *S = Sl + 6 * (da + kk);
+          S[0] = S[1] = S[2] = 0.f;
+          S[3] = kk == 0; S[4] = kk == 1; S[5] = kk == 2;
+          float *S2 = Sl + 6 * (da + 3 + kk);
+          S2[0] = R[kk]; S2[1] = R[3 + kk]; S2[2] = R[6 + kk];
+          S2[3] = S2[4] = S2[5] = 0.f;
         }
-        const int p = M.parent[i];
+        V3 v = ld3(qd + da);
+        V3 ww = mulR(R, ld3(qd + da + 3));
+        float *V = Vl + 6 * i, *A = Al + 6 * i;
+        st3(V, ww);
+        st3(V + 3, v);
+        st3(A, v3(0.f, 0.f, 0.f));
+        st3(A + 3, cross(v, ww) - g);
+        continue;
+      }
+      const float *E = M.jrot + 9 * i;
+      const V3 ax = ld3(M.axis + 3 * i);
+      const float qi = q[M.qadr[i]];
+      const V3 al = mulR(E, ax);
+      V3 t = ld3(M.jpos + 3 * i);
+      if (jt == 0) {
+        float sn, cs;
+        sincosf(qi, &sn, &cs);
+        const float vc = 1.0f - cs;
+        const float Q[9] = {cs + ax.x * ax.x * vc, ax.x * ax.y * vc - ax.z * sn, ax.x * ax.z * vc + ax.y * sn,
+                            ax.y * ax.x * vc + ax.z * sn, cs + ax.y * ax.y * vc, ax.y * ax.z * vc - ax.x * sn,
+                            ax.z * ax.x * vc - ax.y * sn, ax.z * ax.y * vc + ax.x * sn, cs + ax.z * ax.z * vc};
+        for (int r = 0; r < 3; ++r)
+          for (int c = 0; c < 3; ++c)
+            F[3 * r + c] = E[3 * r] * Q[c] + E[3 * r + 1] * Q[3 + c] + E[3 * r + 2] * Q[6 + c];
+      } else {
+        for (int e = 0; e < 9; ++e) F[e] = E[e];
+        t = t + qi * al;
+      }
+      st3(F + 9, t);
+      st3(Al + 6 * i, al);
+    }
+    __syncthreads();
+    // (2) compose down the tree level by level, reading only LDS:
+    // R = R_p Lr, P = P_p + R_p t, axis = R_p al, S, V = V_p + S qd,
+    // A = A_p + V_p x (S qd)
+    for (int l = 0; l < M.n_level; ++l) {
+      const int b0 = tlev[l], b1 = tlev[l + 1];
+      for (int k = b0 + lane; k < b1; k += 64) {
+        const int i = tnode[k];
+        const int info = tinfo[i];
+        const int jt = info & 3;
+        if (jt == 2) continue;
+        const int p = (info >> 2 & 0xFF) - 1, da = info >> 10;
+        float *F = Rl + 12 * i;
+        float Lr[9];
+        for (int e = 0; e < 9; ++e) Lr[e] = F[e];
+        const V3 t = ld3(F + 9);
+        const V3 al = ld3(Al + 6 * i);
         float Rp[9];
         V3 Pp, wp, vp, ap, lp;
         if (p >= 0) {
-          for (int e = 0; e < 9; ++e) Rp[e] = Rl[9 * p + e];
-          Pp = ld3(Pl + 3 * p);
+          for (int e = 0; e < 9; ++e) Rp[e] = Rl[12 * p + e];
+          Pp = ld3(Pl + 12 * p);
           wp = ld3(Vl + 6 * p); vp = ld3(Vl + 6 * p + 3);
           ap = ld3(Al + 6 * p); lp = ld3(Al + 6 * p + 3);
         } else {
@@ -285,55 +443,40 @@ __global__ __launch_bounds__(64) void k_step(KModel M, KRun Rn, int n_steps) {
           wp = vp = ap = v3(0.f, 0.f, 0.f);
           lp = v3(0.f, 0.f, 0.f) - g;
         }
-        const float *E = M.jrot + 9 * i;
-        float RJ[9];
         for (int r = 0; r < 3; ++r)
           for (int c = 0; c < 3; ++c)
-            RJ[3 * r + c] = Rp[3 * r] * E[c] + Rp[3 * r + 1] * E[3 + c] + Rp[3 * r + 2] * E[6 + c];
-        V3 Pi = Pp + mulR(Rp, ld3(M.jpos + 3 * i));
-        V3 ax = ld3(M.axis + 3 * i);
-        V3 ah = mulR(RJ, ax);
-        float qi = q[M.qadr[i]];
-        float *S = Sl + 6 * da;
+            F[3 * r + c] = Rp[3 * r] * Lr[c] + Rp[3 * r + 1] * Lr[3 + c] + Rp[3 * r + 2] * Lr[6 + c];
+        const V3 Pi = Pp + mulR(Rp, t);
+        const V3 ah = mulR(Rp, al);
+        st3(F + 9, Pi);
         V3 sw, sv;
         if (jt == 0) {
-          float sn, cs;
-          sincosf(qi, &sn, &cs);
-          float vc = 1.0f - cs;
-          float Q[9] = {cs + ax.x * ax.x * vc, ax.x * ax.y * vc - ax.z * sn, ax.x * ax.z * vc + ax.y * sn,
-                        ax.y * ax.x * vc + ax.z * sn, cs + ax.y * ax.y * vc, ax.y * ax.z * vc - ax.x * sn,
-                        ax.z * ax.x * vc - ax.y * sn, ax.z * ax.y * vc + ax.x * sn, cs + ax.z * ax.z * vc};
-          for (int r = 0; r < 3; ++r)
-            for (int c = 0; c < 3; ++c)
-              R[3 * r + c] = RJ[3 * r] * Q[c] + RJ[3 * r + 1] * Q[3 + c] + RJ[3 * r + 2] * Q[6 + c];
           sw = ah;
           sv = cross(Pi, ah);
         } else {
-          for (int e = 0; e < 9; ++e) R[e] = RJ[e];
-          Pi = Pi + qi * ah;
           sw = v3(0.f, 0.f, 0.f);
           sv = ah;
         }
-        st3(Pl + 3 * i, Pi);
+        float *S = Sl + 6 * da;
         st3(S, sw);
         st3(S + 3, sv);
         const float qdi = qd[da];
-        V3 xw = qdi * sw, xv = qdi * sv;  // S qd
+        const V3 xw = qdi * sw, xv = qdi * sv;  // S qd
         float *V = Vl + 6 * i, *A = Al + 6 * i;
         st3(V, wp + xw);
         st3(V + 3, vp + xv);
-        // A = A_p + V_p x (S qd)
         st3(A, ap + cross(wp, xw));
         st3(A + 3, lp + cross(wp, xv) + cross(vp, xw));
       }
       __syncthreads();
     }
 
+    if (!geom_only) {
     // ------------------------------------------------------------- contacts
     for (int c = lane; c < M.n_con; c += 64) {
       float *C = Cl + 16 * c;
       const int b = M.con_node[c];
-      V3 w = mulR(Rl + 9 * b, ld3(M.con_pos + 3 * c)) + ld3(Pl + 3 * b);
+      V3 w = frame_apply(Rl + 12 * b, ld3(M.con_pos + 3 * c));
       const float rho = M.con_radius[c];
       const float pen = rho - (w.z + O.z);
       for (int e = 0; e < 16; ++e) C[e] = 0.f;
@@ -363,9 +506,9 @@ __global__ __launch_bounds__(64) void k_step(KModel M, KRun Rn, int n_steps) {
     // ------------------------------------- recursive Newton-Euler bias forces
     for (int b = lane; b < M.n_body; b += 64) {
       const int i = M.body_node[b];
-      const float *R = Rl + 9 * i;
+      const float *R = Rl + 12 * i;
       const float m = M.body_mass[b];
-      V3 c = mulR(R, ld3(M.body_com + 3 * b)) + ld3(Pl + 3 * i);
+      V3 c = mulR(R, ld3(M.body_com + 3 * b)) + ld3(Pl + 12 * i);
       V3 h = m * c;
       const float I0 = M.body_inertia[3 * b], I1 = M.body_inertia[3 * b + 1], I2 = M.body_inertia[3 * b + 2];
       // I_O = R diag(I) R^T + m (|c|^2 1 - c c^T)
@@ -401,7 +544,7 @@ __global__ __launch_bounds__(64) void k_step(KModel M, KRun Rn, int n_steps) {
       const float *S = Sl + 6 * j;
       const float *F = Fn + 6 * M.dof_node[j];
       float cb = S[0] * F[0] + S[1] * F[1] + S[2] * F[2] + S[3] * F[3] + S[4] * F[4] + S[5] * F[5];
-      if (STAGES) Rn.o_bias[(size_t)env * nv + j] = cb;
+      if (stages) Rn.o_bias[(size_t)env * nv + j] = cb;
       rhs[j] = (double)(-cb - M.damping[j] * qd[j]);
     }
     __syncthreads();
@@ -413,9 +556,9 @@ __global__ __launch_bounds__(64) void k_step(KModel M, KRun Rn, int n_steps) {
       double *FJ = CI + 10 * nn;                   // [nv][6]
       for (int b = lane; b < M.n_body; b += 64) {
         const int i = M.body_node[b];
-        const float *R = Rl + 9 * i;
+        const float *R = Rl + 12 * i;
         const double m = M.body_mass[b];
-        V3 cf = mulR(R, ld3(M.body_com + 3 * b)) + ld3(Pl + 3 * i);
+        V3 cf = mulR(R, ld3(M.body_com + 3 * b)) + ld3(Pl + 12 * i);
         const double c[3] = {cf.x, cf.y, cf.z};
         const double In[3] = {M.body_inertia[3 * b], M.body_inertia[3 * b + 1], M.body_inertia[3 * b + 2]};
         double *o = BI + 10 * b;
@@ -487,85 +630,77 @@ __global__ __launch_bounds__(64) void k_step(KModel M, KRun Rn, int n_steps) {
       __syncthreads();
     }
 
+    }  // !geom_only
     // --------------------------- muscle geometry, Hill force, J_m^T F, damping
     {
       float *mr = (float *)scr;          // [n_mus][3]
       float *mF = mr + 3 * nm;           // [n_mus]
       float *mc = mF + nm;               // [n_mus]
-      // geometry: one muscle per lane and iteration (L, Ldot parked in mF, mc)
-#pragma unroll 1
-      for (int m = lane; m < nm; m += 64) {
-        const int P = M.mus_nvia[m];
-        // via-points in registers: loops run to the compile-time maximum
-        V3 w[kMaxVia], gk[kMaxVia];
-#pragma unroll
-        for (int k = 0; k < kMaxVia; ++k) {
-          w[k] = v3(0.f, 0.f, 0.f);
-          if (k < P) {
-            const int b = M.via_node[(size_t)k * nm + m];
-            V3 x = v3(M.via_pos[((size_t)k * 3 + 0) * nm + m], M.via_pos[((size_t)k * 3 + 1) * nm + m],
-                      M.via_pos[((size_t)k * 3 + 2) * nm + m]);
-            w[k] = b >= 0 ? mulR(Rl + 9 * b, x) + ld3(Pl + 3 * b) : x - O;
-          }
+      // surrogate geometry (when predictions are given): an env falls back to
+      // the exact geometry when a hinge leaves the training box or when the
+      // prediction misses the exact length of one of 32 sentinel muscles,
+      // rotated each step, by more than the tolerance. One wavefront is one
+      // env, so the decision is uniform.
+      bool exact = true;
+      if (Rn.geomY) {
+        const float *Y = Rn.geomY + (size_t)env * 4 * nm;
+        bool out = false;
+        for (int i = lane; i < nn; i += 64) {
+          if (M.jtype[i] == 2) continue;
+          const int j = M.dadr[i];
+          const float qi = q[M.qadr[i]];
+          out |= !(qi >= M.qlo[j] && qi <= M.qhi[j]);
         }
-        float L = 0.f;
-        V3 eprev = v3(0.f, 0.f, 0.f);
-#pragma unroll
-        for (int k = 0; k < kMaxVia; ++k) {
-          gk[k] = v3(0.f, 0.f, 0.f);
-          if (k + 1 < P) {
-            V3 d = w[k + 1] - w[k];
-            float l = sqrtf(dot(d, d));
-            L += l;
-            V3 e = (1.0f / l) * d;
-            gk[k] = eprev - e;
-            eprev = e;
-          } else if (k + 1 == P) {
-            gk[k] = eprev;
-          }
+        bool miss = false;
+        const int ns = nm < 32 ? nm : 32;
+        if (lane < ns) {
+          const int mx = (int)((32ll * (Rn.step0 + step) + lane) % nm);
+          const int m = M.mus_int[mx];
+          float r3[3], Ld;
+          const float L = muscle_geometry<NVIA>(M, m, NVIA, Rl, Pl, Sl, qd, O, r3, Ld);
+          miss = !(fabsf(Y[mx] - L) <= Rn.fb_tol);
         }
-        const unsigned mask = M.mus_mask[m];
-        float Ld = 0.f;
-        float r3[3] = {0.f, 0.f, 0.f};
+        exact = __any(out) || __any(miss);
+        if (exact) {
+          status |= MS_ST_FALLBACK;
+          if (Rn.fb_count && lane == 0) Rn.fb_count[env] += 1u;
+        } else {
+          for (int m = lane; m < nm; m += 64) {
+            const int mx = M.mus_ext[m];
+            float Ld = 0.f;
 #pragma unroll
-        for (int s = 0; s < 3; ++s) {
-          const int j = M.mus_span[s * nm + m];
-          if (j >= 0) {
-            const unsigned mk = (mask >> (8 * s)) & 0xFFu;
-            const float *S = Sl + 6 * j;
-            float dl;
-            if (M.dof_kind[j] == 0) {
-              V3 o = ld3(Pl + 3 * M.dof_node[j]);
-              V3 acc = v3(0.f, 0.f, 0.f);
-#pragma unroll
-              for (int k = 0; k < kMaxVia; ++k)
-                if ((mk >> k) & 1u) acc = acc + cross(w[k] - o, gk[k]);
-              dl = dot(ld3(S), acc);
-            } else {
-              V3 acc = v3(0.f, 0.f, 0.f);
-#pragma unroll
-              for (int k = 0; k < kMaxVia; ++k)
-                if ((mk >> k) & 1u) acc = acc + gk[k];
-              dl = dot(ld3(S + 3), acc);
+            for (int sl = 0; sl < 3; ++sl) {
+              const int j = M.mus_span[sl * nm + m];
+              const float r = j >= 0 ? Y[nm + 3 * mx + sl] : 0.f;
+              mr[3 * m + sl] = r;
+              if (j >= 0) Ld -= r * qd[j];
             }
-            r3[s] = -dl;
-            Ld += dl * qd[j];
+            mF[m] = Y[mx];
+            mc[m] = Ld;
           }
         }
+      }
+      // exact geometry: one muscle per lane and iteration (L, Ldot parked
+      // in mF, mc)
+#pragma unroll 1
+      for (int m = lane; exact && m < nm; m += 64) {
+        float r3[3], Ld;
+        const float L = muscle_geometry<NVIA>(M, m, M.grp_nvia[m >> 6], Rl, Pl, Sl, qd, O, r3, Ld);
         mr[3 * m] = r3[0];
         mr[3 * m + 1] = r3[1];
         mr[3 * m + 2] = r3[2];
         mF[m] = L;
         mc[m] = Ld;
-        if (STAGES) {
-          const size_t o = (size_t)env * nm + m;
+        if (stages) {
+          const size_t o = (size_t)env * nm + M.mus_ext[m];
           Rn.o_L[o] = L;
-          Rn.o_Ldot[o] = Ld;
+          if (Rn.o_Ldot) Rn.o_Ldot[o] = Ld;
           Rn.o_r[3 * o] = r3[0];
           Rn.o_r[3 * o + 1] = r3[1];
           Rn.o_r[3 * o + 2] = r3[2];
         }
       }
+      if (geom_only) return;
       // Hill force and its velocity slope (the same lane re-reads its muscles)
 #pragma unroll
       for (int t = 0; t < MPL; ++t) {
@@ -580,7 +715,7 @@ __global__ __launch_bounds__(64) void k_step(KModel M, KRun Rn, int n_steps) {
         const float cdamp = f0 * act1[t] * fl * hill_fv_slope(vm) * M.mus_ivl[m];
         mF[m] = F;
         mc[m] = cdamp;
-        if (STAGES) Rn.o_F[(size_t)env * nm + m] = F;
+        if (stages) Rn.o_F[(size_t)env * nm + M.mus_ext[m]] = F;
       }
       __syncthreads();
       for (int j = lane; j < nv; j += 64) {
@@ -589,7 +724,7 @@ __global__ __launch_bounds__(64) void k_step(KModel M, KRun Rn, int n_steps) {
           const int it = M.proj_item[e];
           tau += mr[it] * mF[it / 3];
         }
-        if (STAGES) Rn.o_tau[(size_t)env * nv + j] = tau;
+        if (stages) Rn.o_tau[(size_t)env * nv + j] = tau;
         rhs[j] += (double)tau;
       }
       for (int e = lane; e < M.n_dent; e += 64) {
@@ -603,62 +738,101 @@ __global__ __launch_bounds__(64) void k_step(KModel M, KRun Rn, int n_steps) {
       }
       __syncthreads();
     }
-    if (STAGES) {
+    if (stages) {
       for (int e = lane; e < M.nnz; e += 64) Rn.o_H[(size_t)env * M.nnz + e] = H[e];
     }
 
     // ------------------------------------------------ LTDL factorisation (FP64)
-    if (lane == 0) flag[0] = 0;
-    __syncthreads();
-    for (int k = nv - 1; k >= 0; --k) {
-      const int rk = M.row_start[k], dk = M.dof_depth[k];
-      const double d = H[rk + dk - 1];
-      if (!(d > 0.0)) {
-        if (lane == 0) flag[0] = 1;
+    // H = L^T D L (Featherstone's branch-induced sparsity). DoFs of equal
+    // height are eliminated together, leaves first; each eliminated DoF k
+    // updates the (ancestor, ancestor) entries H[i][j] -= H[k][i] H[k][j] / d_k.
+    // Targets lie on higher levels than their sources, so a level's updates
+    // only add into entries nobody in the level reads.
+    bool nonspd = false;
+    double *invd = (double *)scr;  // 1/d per DoF (the muscle scratch is free now)
+    for (int h = 0; h < M.n_hlev && !nonspd; ++h) {
+      const int s0 = M.hlev_start[h], s1 = M.hlev_start[h + 1];
+      bool bad = false;
+      for (int e = s0 + lane; e < s1; e += 64) {
+        const int k = M.hlev_dof[e];
+        const double d = H[M.row_start[k] + M.dof_depth[k] - 1];
+        bad |= !(d > 0.0);
+        invd[k] = 1.0 / d;
+      }
+      if (__any(bad)) {
+        nonspd = true;
         break;
       }
-      const double inv = 1.0 / d;
-      const int np = (dk - 1) * dk / 2;
-      for (int pp = lane; pp < np; pp += 64) {
-        const int ab = M.pair_ab[pp];
-        const int a = ab & 0xFF, b = ab >> 8;
-        const int i = M.path[rk + a];
-        H[M.row_start[i] + b] -= H[rk + a] * H[rk + b] * inv;
+      __syncthreads();
+      // the level's DoFs one after another (their updates may meet in a
+      // shared ancestor). Row k's entries stay in registers (lane b holds
+      // H[k][b]); a uniform loop walks k's ancestor rows a, four at a time,
+      // and lanes b <= a update H[i_a][b] -= H[k][a] H[k][b] / d_k. The four
+      // rows are distinct, so their loads are issued before any store.
+      for (int e = s0; e < s1; ++e) {
+        const int k = M.hlev_dof[e];
+        const int rk = M.row_start[k], na = M.dof_depth[k] - 1;
+        const double inv = invd[k];
+        const bool mine = lane < na;
+        const double hb = mine ? H[rk + lane] : 0.0;
+        const int rsl = mine ? M.rs_path[rk + lane] : 0;
+        const double hbi = hb * inv;
+        for (int a0 = 0; a0 < na; a0 += 4) {
+          double t[4], ha[4];
+          int ra[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int a = a0 + u < na ? a0 + u : na - 1;
+            ha[u] = lane_bcast(hbi, a);
+            ra[u] = __builtin_amdgcn_readlane(rsl, a);
+            t[u] = (a0 + u < na && lane <= a0 + u) ? H[ra[u] + lane] : 0.0;
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+            if (a0 + u < na && lane <= a0 + u) H[ra[u] + lane] = t[u] - ha[u] * hb;
+        }
       }
       __syncthreads();
     }
-    __syncthreads();
-    const bool nonspd = flag[0] != 0;
     if (!nonspd) {
       // L = H / d (row-wise), keep d on the diagonal
       for (int e = lane; e < M.nnz; e += 64) {
         const int j = M.nnz_row[e];
-        if (M.path[e] != j) H[e] /= H[M.row_start[j] + M.dof_depth[j] - 1];
+        if (M.path[e] != j) H[e] *= invd[j];
       }
       for (int j = lane; j < nv; j += 64) xs[j] = rhs[j];
       __syncthreads();
-      // L^T y = b (leaves first)
-      for (int k = nv - 1; k >= 0; --k) {
-        const int rk = M.row_start[k], dk = M.dof_depth[k];
-        const double yk = xs[k];
-        for (int a = lane; a < dk - 1; a += 64) xs[M.path[rk + a]] -= H[rk + a] * yk;
+      // L^T y = b, by height (leaves first): y_k is final once its
+      // descendants have scattered into it
+      for (int h = 0; h < M.n_hlev; ++h) {
+        const int s0 = M.hlev_start[h], s1 = M.hlev_start[h + 1];
+        for (int e = s0; e < s1; ++e) {
+          const int k = M.hlev_dof[e];
+          const int rk = M.row_start[k], na = M.dof_depth[k] - 1;
+          const double yk = xs[k];
+          for (int a = lane; a < na; a += 64) xs[M.path[rk + a]] -= H[rk + a] * yk;
+        }
         __syncthreads();
       }
-      for (int j = lane; j < nv; j += 64) xs[j] /= H[M.row_start[j] + M.dof_depth[j] - 1];
+      for (int j = lane; j < nv; j += 64) xs[j] *= invd[j];
       __syncthreads();
-      // L x = z (root first)
-      for (int k = 0; k < nv; ++k) {
-        const int rk = M.row_start[k], dk = M.dof_depth[k];
-        double s = 0.0;
-        for (int a = lane; a < dk - 1; a += 64) s += H[rk + a] * xs[M.path[rk + a]];
-        s = wave_sum(s);
-        if (lane == 0) xs[k] -= s;
+      // L x = z, by depth (root first): ancestors are final
+      for (int dl = 1; dl < M.n_dlev; ++dl) {
+        const int s0 = M.dlev_start[dl], s1 = M.dlev_start[dl + 1];
+        for (int e = s0; e < s1; ++e) {
+          const int k = M.dlev_dof[e];
+          const int rk = M.row_start[k];
+          double sum = 0.0;
+          for (int a = lane; a < dl; a += 64) sum += H[rk + a] * xs[M.path[rk + a]];
+          sum = wave_sum(sum);
+          if (lane == 0) xs[k] -= sum;
+        }
         __syncthreads();
       }
     }
 
     // ----------------------------------------------- semi-implicit Euler update
-    if (STAGES) {
+    if (stages) {
       for (int j = lane; j < nv; j += 64) Rn.o_qdd[(size_t)env * nv + j] = nonspd ? NAN : (float)xs[j];
       break;
     }
@@ -724,15 +898,16 @@ __global__ __launch_bounds__(64) void k_step(KModel M, KRun Rn, int n_steps) {
     __syncthreads();
   }
 
-  if (STAGES) return;
+  if (stages) return;
   for (int i = lane; i < nq; i += 64) Rn.q[(size_t)env * nq + i] = q[i];
   for (int i = lane; i < nv; i += 64) Rn.qd[(size_t)env * nv + i] = qd[i];
 #pragma unroll
   for (int t = 0; t < MPL; ++t) {
     const int mi = lane + 64 * t;
     if (mi < nm) {
-      Rn.act[(size_t)env * nm + mi] = act[t];
-      if (EXC == EXC_AR1) Rn.xar[(size_t)env * nm + mi] = xar[t];
+      const int mx = M.mus_ext[mi];
+      Rn.act[(size_t)env * nm + mx] = act[t];
+      if (exc == EXC_AR1) Rn.xar[(size_t)env * nm + mx] = xar[t];
     }
   }
   if (Rn.status && lane == 0) Rn.status[env] = status;
@@ -747,6 +922,17 @@ struct ms_model {
   void *dbuf = nullptr;
   size_t dbytes = 0;
 };
+
+void ms_surrogate_tables(const ms_model *m, std::vector<int> *q_index, std::vector<float> *lo,
+                         std::vector<float> *hi) {
+  const ms::Tables &t = m->t;
+  for (int i = 0; i < t.n_node; ++i) {
+    if (t.jtype[i] == 2) continue;
+    q_index->push_back(t.qadr[i]);
+    lo->push_back(t.qlo[t.dadr[i]]);
+    hi->push_back(t.qhi[t.dadr[i]]);
+  }
+}
 
 namespace {
 thread_local std::string g_err;
@@ -767,27 +953,35 @@ struct Packer {
   }
 };
 
-template <int MPL, int EXC, bool STAGES>
-hipError_t launch_mpl(const ms_model *m, const ms::KRun &r, int n_env, int n_steps, hipStream_t st) {
+template <int MPL, int NVIA>
+hipError_t launch_k(const ms_model *m, const ms::KRun &r, int n_env, int n_steps, hipStream_t st) {
   if (m->t.lds_bytes > 65536) {
-    hipError_t e = hipFuncSetAttribute((const void *)&ms::k_step<MPL, EXC, STAGES>,
+    hipError_t e = hipFuncSetAttribute((const void *)&ms::k_step<MPL, NVIA>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, m->t.lds_bytes);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL((ms::k_step<MPL, EXC, STAGES>), dim3(n_env), dim3(64), m->t.lds_bytes, st, m->k,
-                     r, n_steps);
+  hipLaunchKernelGGL((ms::k_step<MPL, NVIA>), dim3(n_env), dim3(64), m->t.lds_bytes, st, m->k, r,
+                     n_steps);
   return hipGetLastError();
 }
 
-template <int EXC, bool STAGES>
-hipError_t launch(const ms_model *m, const ms::KRun &r, int n_env, int n_steps, hipStream_t st) {
+template <int NVIA>
+hipError_t launch_v(const ms_model *m, const ms::KRun &r, int n_env, int n_steps, hipStream_t st) {
   const int mpl = m->t.mpl;
-  if (mpl <= 1) return launch_mpl<1, EXC, STAGES>(m, r, n_env, n_steps, st);
-  if (mpl <= 2) return launch_mpl<2, EXC, STAGES>(m, r, n_env, n_steps, st);
-  if (mpl <= 4) return launch_mpl<4, EXC, STAGES>(m, r, n_env, n_steps, st);
-  if (mpl <= 8) return launch_mpl<8, EXC, STAGES>(m, r, n_env, n_steps, st);
-  if (mpl <= 12) return launch_mpl<12, EXC, STAGES>(m, r, n_env, n_steps, st);
-  return launch_mpl<16, EXC, STAGES>(m, r, n_env, n_steps, st);
+  if (mpl <= 1) return launch_k<1, NVIA>(m, r, n_env, n_steps, st);
+  if (mpl <= 2) return launch_k<2, NVIA>(m, r, n_env, n_steps, st);
+  if (mpl <= 4) return launch_k<4, NVIA>(m, r, n_env, n_steps, st);
+  if (mpl <= 8) return launch_k<8, NVIA>(m, r, n_env, n_steps, st);
+  if (mpl <= 12) return launch_k<12, NVIA>(m, r, n_env, n_steps, st);
+  return launch_k<16, NVIA>(m, r, n_env, n_steps, st);
+}
+
+hipError_t launch(const ms_model *m, const ms::KRun &r, int n_env, int n_steps, hipStream_t st) {
+  const int nvia = m->t.n_via_max;
+  if (nvia <= 2) return launch_v<2>(m, r, n_env, n_steps, st);
+  if (nvia <= 4) return launch_v<4>(m, r, n_env, n_steps, st);
+  if (nvia <= 6) return launch_v<6>(m, r, n_env, n_steps, st);
+  return launch_v<8>(m, r, n_env, n_steps, st);
 }
 
 ms_status check_opts(const ms_step_opts *o) {
@@ -834,10 +1028,13 @@ ms_status ms_model_create(const ms_model_desc *desc, ms_model **out) {
          o_il = p.add(t.mus_ilopt), o_ls2 = p.add(t.mus_lslack), o_ivl = p.add(t.mus_ivl),
          o_ta = p.add(t.mus_tact), o_td = p.add(t.mus_tdeact), o_nvia = p.add(t.mus_nvia),
          o_vn = p.add(t.via_node), o_vp = p.add(t.via_pos), o_span = p.add(t.mus_span),
+         o_mext = p.add(t.mus_ext), o_mint = p.add(t.mus_int), o_gnv = p.add(t.grp_nvia),
+         o_qlo = p.add(t.qlo), o_qhi = p.add(t.qhi),
          o_mask = p.add(t.mus_mask), o_ps = p.add(t.proj_start), o_pi = p.add(t.proj_item),
          o_dh = p.add(t.dent_h), o_ds = p.add(t.dent_start), o_di = p.add(t.dent_item),
          o_rs = p.add(t.row_start), o_dd = p.add(t.dof_depth), o_path = p.add(t.path),
-         o_nr = p.add(t.nnz_row), o_pab = p.add(t.pair_ab);
+         o_nr = p.add(t.nnz_row), o_rsp = p.add(t.rs_path), o_hs = p.add(t.hlev_start),
+         o_hd = p.add(t.hlev_dof), o_ds2 = p.add(t.dlev_start), o_dd2 = p.add(t.dlev_dof);
   m->dbytes = p.buf.size();
   hipError_t e = hipMalloc(&m->dbuf, m->dbytes);
   if (e != hipSuccess) {
@@ -857,6 +1054,8 @@ ms_status ms_model_create(const ms_model_desc *desc, ms_model **out) {
   k.n_node = t.n_node; k.nq = t.nq; k.nv = t.nv; k.n_mus = t.n_mus; k.n_con = t.n_con;
   k.n_body = t.n_body; k.nnz = t.nnz; k.n_level = t.n_level; k.free_root = t.free_root;
   k.n_dent = t.n_dent;
+  k.n_hlev = t.n_hlev;
+  k.n_dlev = t.n_dlev;
   k.kc = t.kc; k.cc = t.cc; k.mu = t.mu; k.vs = t.vs; k.gx = t.g[0]; k.gy = t.g[1]; k.gz = t.g[2];
 #define P_(field, off, T) k.field = (const T *)(b + off)
   P_(parent, o_parent, int); P_(jtype, o_jtype, int); P_(qadr, o_qadr, int); P_(dadr, o_dadr, int);
@@ -869,15 +1068,19 @@ ms_status ms_model_create(const ms_model_desc *desc, ms_model **out) {
   P_(mus_f0, o_f0, float); P_(mus_ilopt, o_il, float); P_(mus_lslack, o_ls2, float);
   P_(mus_ivl, o_ivl, float); P_(mus_tact, o_ta, float); P_(mus_tdeact, o_td, float);
   P_(mus_nvia, o_nvia, int); P_(via_node, o_vn, int); P_(via_pos, o_vp, float);
+  P_(mus_ext, o_mext, int); P_(mus_int, o_mint, int); P_(grp_nvia, o_gnv, int);
+  P_(qlo, o_qlo, float); P_(qhi, o_qhi, float);
   P_(mus_span, o_span, int); P_(mus_mask, o_mask, unsigned); P_(proj_start, o_ps, int);
   P_(proj_item, o_pi, int); P_(dent_h, o_dh, int); P_(dent_start, o_ds, int);
   P_(dent_item, o_di, int); P_(row_start, o_rs, int); P_(dof_depth, o_dd, int);
-  P_(path, o_path, int); P_(nnz_row, o_nr, int); P_(pair_ab, o_pab, int);
+  P_(path, o_path, int); P_(nnz_row, o_nr, int); P_(rs_path, o_rsp, int);
+  P_(hlev_start, o_hs, int); P_(hlev_dof, o_hd, int); P_(dlev_start, o_ds2, int);
+  P_(dlev_dof, o_dd2, int);
 #undef P_
   k.off_flag = t.off_flag; k.off_q = t.off_q; k.off_qd = t.off_qd; k.off_R = t.off_R;
   k.off_P = t.off_P; k.off_S = t.off_S; k.off_con = t.off_con; k.off_rhs = t.off_rhs;
   k.off_x = t.off_x; k.off_H = t.off_H; k.off_scr = t.off_scr; k.off_V = t.off_V;
-  k.off_A = t.off_A; k.off_F = t.off_F;
+  k.off_A = t.off_A; k.off_F = t.off_F; k.off_tree = t.off_tree;
   *out = m;
   return MS_OK;
 }
@@ -900,7 +1103,7 @@ ms_status ms_model_spans(const ms_model *m, int32_t *spans) {
   if (!m || !spans) return fail(MS_E_ARG, "NULL argument");
   const int nm = m->t.n_mus;
   for (int i = 0; i < nm; ++i)
-    for (int s = 0; s < 3; ++s) spans[3 * i + s] = m->t.mus_span[(size_t)s * nm + i];
+    for (int s = 0; s < 3; ++s) spans[3 * m->t.mus_ext[i] + s] = m->t.mus_span[(size_t)s * nm + i];
   return MS_OK;
 }
 
@@ -935,7 +1138,8 @@ ms_status ms_step_batch(ms_model *m, int32_t n_env, float *q, float *qd, float *
   ms::KRun r{};
   r.q = q; r.qd = qd; r.act = act; r.status = status; r.u = u; r.n_env = n_env;
   r.dt = opts->dt; r.contact = opts->contact;
-  return hip_status(launch<ms::EXC_ARRAY, false>(m, r, n_env, 1, (hipStream_t)stream));
+  r.exc = ms::EXC_ARRAY;
+  return hip_status(launch(m, r, n_env, 1, (hipStream_t)stream));
 }
 
 ms_status ms_rollout(ms_model *m, int32_t n_env, float *q, float *qd, float *act,
@@ -956,15 +1160,59 @@ ms_status ms_rollout(ms_model *m, int32_t n_env, float *q, float *qd, float *act
   switch (exc->kind) {
     case MS_EXC_ARRAY:
       if (!exc->u && m->t.n_mus > 0) return fail(MS_E_ARG, "exc->u is NULL");
-      return hip_status(launch<ms::EXC_ARRAY, false>(m, r, n_env, n_steps, st));
+      break;
     case MS_EXC_IID:
-      return hip_status(launch<ms::EXC_IID, false>(m, r, n_env, n_steps, st));
+      break;
     case MS_EXC_AR1:
       if (!exc->x && m->t.n_mus > 0) return fail(MS_E_ARG, "exc->x is NULL");
-      return hip_status(launch<ms::EXC_AR1, false>(m, r, n_env, n_steps, st));
+      break;
     default:
       return fail(MS_E_ARG, "unknown excitation kind");
   }
+  r.exc = exc->kind;
+  return hip_status(launch(m, r, n_env, n_steps, st));
+}
+
+ms_status ms_rollout_surrogate(ms_model *m, ms_surrogate *sg, int32_t n_env, float *q, float *qd,
+                               float *act, uint32_t *status, const ms_excitation *exc,
+                               int32_t n_steps, const ms_step_opts *opts, float tol,
+                               uint32_t *fallback_count, void *stream) {
+  g_err.clear();
+  ms_status s = common_checks(m, n_env, q, qd, act, opts);
+  if (s != MS_OK) return s;
+  if (!sg || !exc) return fail(MS_E_ARG, "surrogate or exc is NULL");
+  if (n_steps < 0) return fail(MS_E_ARG, "n_steps must be >= 0");
+  if (exc->kind == MS_EXC_ARRAY && !exc->u && m->t.n_mus > 0) return fail(MS_E_ARG, "exc->u is NULL");
+  if (exc->kind == MS_EXC_AR1 && !exc->x && m->t.n_mus > 0) return fail(MS_E_ARG, "exc->x is NULL");
+  if (exc->kind < 0 || exc->kind > 2) return fail(MS_E_ARG, "unknown excitation kind");
+  hipStream_t st = (hipStream_t)stream;
+  for (int t = 0; t < n_steps; ++t) {
+    const float *Y = nullptr;
+    s = ms_surrogate_predict(sg, n_env, q, &Y, st);
+    if (s != MS_OK) return fail(s, std::string("surrogate: ") + ms_surrogate_last_error());
+    ms::KRun r{};
+    r.q = q; r.qd = qd; r.act = act; r.status = status; r.n_env = n_env;
+    r.dt = opts->dt; r.contact = opts->contact;
+    r.u = exc->u ? exc->u + (size_t)t * n_env * m->t.n_mus : nullptr;
+    r.seed = exc->seed; r.step0 = exc->step0 + t; r.xar = exc->x;
+    r.rho = exc->rho; r.s = exc->s; r.mean = exc->mean;
+    r.exc = exc->kind;
+    r.geomY = Y; r.fb_tol = tol; r.fb_count = fallback_count;
+    s = hip_status(launch(m, r, n_env, 1, st));
+    if (s != MS_OK) return s;
+  }
+  return MS_OK;
+}
+
+ms_status ms_geometry(ms_model *m, int32_t n, const float *q, float *L, float *r, void *stream) {
+  g_err.clear();
+  if (!m || n <= 0 || !q || !L || !r) return fail(MS_E_ARG, "NULL argument or n <= 0");
+  ms::KRun k{};
+  k.q = const_cast<float *>(q); k.qd = nullptr; k.act = nullptr; k.n_env = n; k.dt = 1e-3f;
+  k.o_L = L; k.o_r = r; k.o_Ldot = nullptr;
+  k.exc = ms::EXC_ARRAY;
+  k.stages = 2;
+  return hip_status(launch(m, k, n, 1, (hipStream_t)stream));
 }
 
 ms_status ms_step_stages(ms_model *m, int32_t n_env, const float *q, const float *qd,
@@ -982,7 +1230,9 @@ ms_status ms_step_stages(ms_model *m, int32_t n_env, const float *q, const float
   r.status = nullptr; r.u = u; r.n_env = n_env; r.dt = opts->dt; r.contact = opts->contact;
   r.o_act = out->act; r.o_L = out->L; r.o_Ldot = out->Ldot; r.o_F = out->F; r.o_r = out->r;
   r.o_tau = out->tau_mus; r.o_bias = out->bias_minus_ext; r.o_qdd = out->qdd; r.o_H = out->mass;
-  return hip_status(launch<ms::EXC_ARRAY, true>(m, r, n_env, 1, (hipStream_t)stream));
+  r.exc = ms::EXC_ARRAY;
+  r.stages = 1;
+  return hip_status(launch(m, r, n_env, 1, (hipStream_t)stream));
 }
 
 }  // extern "C"

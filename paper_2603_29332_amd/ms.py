@@ -17,11 +17,16 @@ LIB_PATH = os.path.join(HERE, "libms.so")
 
 MS_ST_NONFINITE = 1
 MS_ST_NONSPD = 2
+MS_ST_FALLBACK = 4
 EXC_ARRAY, EXC_IID, EXC_AR1 = 0, 1, 2
 
 EXPORTED = ("ms_model_create", "ms_model_destroy", "ms_model_info_get",
             "ms_step_batch", "ms_rollout", "ms_step_stages", "ms_model_spans",
-            "ms_model_mass_pattern", "ms_last_error")
+            "ms_model_mass_pattern", "ms_last_error", "ms_geometry",
+            "ms_surrogate_create", "ms_surrogate_destroy", "ms_surrogate_dims",
+            "ms_surrogate_params", "ms_surrogate_grads", "ms_surrogate_set_norm",
+            "ms_surrogate_sample", "ms_surrogate_forward", "ms_surrogate_train_step",
+            "ms_surrogate_last_error", "ms_rollout_surrogate")
 
 _fptr = C.POINTER(C.c_float)
 _iptr = C.POINTER(C.c_int32)
@@ -31,7 +36,8 @@ class MsDesc(C.Structure):
     _fields_ = [
         ("n_node", C.c_int32), ("parent", _iptr), ("jtype", _iptr),
         ("jpos", _fptr), ("jrot", _fptr), ("axis", _fptr), ("mass", _fptr),
-        ("com", _fptr), ("inertia", _fptr), ("damping", _fptr),
+        ("com", _fptr), ("inertia", _fptr), ("damping", _fptr), ("qlo", _fptr),
+        ("qhi", _fptr),
         ("n_mus", C.c_int32), ("f0", _fptr), ("l_opt", _fptr), ("l_slack", _fptr),
         ("v_max", _fptr), ("tau_act", _fptr), ("tau_deact", _fptr),
         ("via_start", _iptr), ("via_node", _iptr), ("via_pos", _fptr),
@@ -82,10 +88,29 @@ def lib():
     L.ms_step_stages.argtypes = [vp, C.c_int32, vp, vp, vp, vp, C.POINTER(MsOpts),
                                  C.POINTER(MsStageOut), vp]
     L.ms_model_spans.argtypes = [vp, _iptr]
+    L.ms_geometry.argtypes = [vp, C.c_int32, vp, vp, vp, vp]
     L.ms_model_mass_pattern.argtypes = [vp, _iptr, _iptr]
     L.ms_last_error.restype = C.c_char_p
+    L.ms_surrogate_last_error.restype = C.c_char_p
+    L.ms_surrogate_create.argtypes = [vp, C.c_int32, C.c_uint64, C.POINTER(vp)]
+    L.ms_surrogate_destroy.argtypes = [vp]
+    L.ms_surrogate_destroy.restype = None
+    L.ms_surrogate_dims.argtypes = [vp, _iptr]
+    L.ms_surrogate_params.argtypes = [vp, C.c_int32] + [_fptr] * 6
+    L.ms_surrogate_grads.argtypes = [vp] + [_fptr] * 6
+    L.ms_surrogate_set_norm.argtypes = [vp, _fptr, _fptr]
+    L.ms_surrogate_sample.argtypes = [vp, C.c_int32, C.c_uint64, C.c_int64, vp, vp]
+    L.ms_surrogate_forward.argtypes = [vp, C.c_int32, vp, vp, vp, vp]
+    L.ms_surrogate_train_step.argtypes = [vp, C.c_int32, vp, vp, vp, C.c_float, C.c_int32, vp, vp]
+    L.ms_rollout_surrogate.argtypes = [vp, vp, C.c_int32, vp, vp, vp, vp, C.POINTER(MsExc),
+                                       C.c_int32, C.POINTER(MsOpts), C.c_float, vp, vp]
+    L.ms_rollout_surrogate.restype = C.c_int
+    for f in ("ms_surrogate_create", "ms_surrogate_dims", "ms_surrogate_params",
+              "ms_surrogate_grads", "ms_surrogate_set_norm", "ms_surrogate_sample",
+              "ms_surrogate_forward", "ms_surrogate_train_step"):
+        getattr(L, f).restype = C.c_int
     for f in ("ms_model_create", "ms_model_info_get", "ms_step_batch", "ms_rollout",
-              "ms_step_stages", "ms_model_spans", "ms_model_mass_pattern"):
+              "ms_step_stages", "ms_model_spans", "ms_model_mass_pattern", "ms_geometry"):
         getattr(L, f).restype = C.c_int
     _lib = L
     return L
@@ -100,6 +125,11 @@ class MsError(RuntimeError):
 def _check(rc):
     if rc != 0:
         raise MsError(rc, lib().ms_last_error().decode())
+
+
+def _check_s(rc):
+    if rc != 0:
+        raise MsError(rc, lib().ms_surrogate_last_error().decode())
 
 
 def _ptr(a, dtype, ctype):
@@ -137,7 +167,7 @@ class Model:
         d = MsDesc()
         d.n_node = m["n_node"]
         d.parent, d.jtype = keep("parent", np.int32), keep("jtype", np.int32)
-        for k in ("jpos", "jrot", "axis", "mass", "com", "inertia", "damping"):
+        for k in ("jpos", "jrot", "axis", "mass", "com", "inertia", "damping", "qlo", "qhi"):
             setattr(d, k, keep(k, np.float32))
         d.n_mus = m["n_mus"]
         for k in ("f0", "l_opt", "l_slack", "v_max", "tau_act", "tau_deact", "via_pos"):
@@ -175,6 +205,10 @@ class Model:
         _check(lib().ms_model_mass_pattern(self.h, r.ctypes.data_as(_iptr), c.ctypes.data_as(_iptr)))
         return r, c
 
+    def geometry(self, q, L, r, stream=None):
+        """Exact lengths L[n][n_mus] and moment arms r[n][n_mus][3] of poses q."""
+        _check(lib().ms_geometry(self.h, q.shape[0], _dp(q), _dp(L), _dp(r), _stream(stream)))
+
     def step_batch(self, q, qd, act, status, u, dt, contact=True, stream=None):
         n_env = q.shape[0]
         o = MsOpts(dt, int(contact))
@@ -189,6 +223,17 @@ class Model:
                   float(ar1[2]))
         _check(lib().ms_rollout(self.h, n_env, _dp(q), _dp(qd), _dp(act), _dp(status),
                                 C.byref(e), n_steps, C.byref(o), _stream(stream)))
+
+    def rollout_surrogate(self, sg, q, qd, act, status, n_steps, dt, contact=True, tol=1e-4,
+                          fb_count=None, kind=EXC_ARRAY, u=None, seed=0, step0=0, x=None,
+                          ar1=(0.0, 0.0, 0.0), stream=None):
+        n_env = q.shape[0]
+        o = MsOpts(dt, int(contact))
+        e = MsExc(kind, _dp(u), seed, step0, _dp(x), float(ar1[0]), float(ar1[1]),
+                  float(ar1[2]))
+        _check(lib().ms_rollout_surrogate(self.h, sg.h, n_env, _dp(q), _dp(qd), _dp(act),
+                                          _dp(status), C.byref(e), n_steps, C.byref(o),
+                                          float(tol), _dp(fb_count), _stream(stream)))
 
     def step_stages(self, q, qd, act, u, dt, contact=True, stream=None):
         import torch
@@ -206,3 +251,59 @@ class Model:
         _check(lib().ms_step_stages(self.h, E, _dp(q), _dp(qd), _dp(act), _dp(u), C.byref(o),
                                     C.byref(so), _stream(stream)))
         return out
+
+
+class Surrogate:
+    """The library's learned muscle-geometry network bound to a Model."""
+
+    def __init__(self, model: Model, hidden: int = 512, seed: int = 41):
+        L = lib()
+        self.model = model
+        h = C.c_void_p()
+        _check_s(L.ms_surrogate_create(model.h, hidden, seed, C.byref(h)))
+        self.h = h
+        d = np.zeros(4, np.int32)
+        _check_s(L.ms_surrogate_dims(h, d.ctypes.data_as(_iptr)))
+        self.n_in, self.h1, self.h2, self.n_out = (int(x) for x in d)
+        self.shapes = [(self.h1, self.n_in), (self.h1,), (self.h2, self.h1), (self.h2,),
+                       (self.n_out, self.h2), (self.n_out,)]
+
+    def __del__(self):
+        try:
+            if getattr(self, "h", None):
+                lib().ms_surrogate_destroy(self.h)
+        except Exception:
+            pass
+
+    def _bufs(self):
+        return [np.zeros(s, np.float32) for s in self.shapes]
+
+    def params(self):
+        b = self._bufs()
+        _check_s(lib().ms_surrogate_params(self.h, 0, *[x.ctypes.data_as(_fptr) for x in b]))
+        return b
+
+    def set_params(self, ps):
+        b = [np.ascontiguousarray(p, np.float32).reshape(s) for p, s in zip(ps, self.shapes)]
+        _check_s(lib().ms_surrogate_params(self.h, 1, *[x.ctypes.data_as(_fptr) for x in b]))
+
+    def grads(self):
+        b = self._bufs()
+        _check_s(lib().ms_surrogate_grads(self.h, *[x.ctypes.data_as(_fptr) for x in b]))
+        return b
+
+    def set_norm(self, mean, std):
+        m = np.ascontiguousarray(mean, np.float32)
+        s = np.ascontiguousarray(std, np.float32)
+        _check_s(lib().ms_surrogate_set_norm(self.h, m.ctypes.data_as(_fptr), s.ctypes.data_as(_fptr)))
+
+    def sample(self, q, seed, offset=0, stream=None):
+        _check_s(lib().ms_surrogate_sample(self.h, q.shape[0], seed, offset, _dp(q), _stream(stream)))
+
+    def forward(self, q, L, r, stream=None):
+        _check_s(lib().ms_surrogate_forward(self.h, q.shape[0], _dp(q), _dp(L), _dp(r),
+                                            _stream(stream)))
+
+    def train_step(self, q, L, r, lr, step, loss=None, stream=None):
+        _check_s(lib().ms_surrogate_train_step(self.h, q.shape[0], _dp(q), _dp(L), _dp(r),
+                                               float(lr), int(step), _dp(loss), _stream(stream)))

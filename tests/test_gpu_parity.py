@@ -47,13 +47,14 @@ def _advance_gpu(gm, q, qd, act, u_seq, dt, contact):
     return tq.cpu().numpy(), tqd.cpu().numpy(), tact.cpu().numpy(), st.cpu().numpy()
 
 
-def _warm_states(m, gm, n_env, n_warm, dt, kind, seed, contact, init):
-    """Seeded states after a short GPU rollout (so velocities are non-zero)."""
+def _warm_states(m, o, n_env, n_warm, dt, kind, seed, contact, init):
+    """Seeded states after a short oracle rollout (so velocities are
+    non-zero), rounded to float32."""
     q, qd, act = init(m, n_env)
     u, _ = synth.excitation_sequence(kind, seed, n_env, m["n_mus"], n_warm, dt)
-    q, qd, act, st = _advance_gpu(gm, q, qd, act, u, dt, contact)
+    q, qd, act, st = o.rollout(dt, q, qd, act, u, contact=contact)
     assert (st == 0).all()
-    return q, qd, act
+    return q.astype(np.float32), qd.astype(np.float32), act.astype(np.float32)
 
 
 def _rel_block(a, b):
@@ -69,7 +70,7 @@ def test_stage_parity(which, chain, human):
     init = synth.chain_initial_state if which == "chain" else synth.human_initial_state
     contact = which == "human"
     E = 8
-    q, qd, act = _warm_states(m, gm, E, 40, dt, kind, 21, contact, init)
+    q, qd, act = _warm_states(m, o, E, 40, dt, kind, 21, contact, init)
     u = synth.excitation_iid(5, E, m["n_mus"], 0)
     out = gm.step_stages(_t(q), _t(qd), _t(act), _t(u), dt, contact)
     out = {k: v.cpu().numpy() for k, v in out.items()}
@@ -125,7 +126,7 @@ def test_step_teacher_forced(which, chain, human):
     init = synth.chain_initial_state if which == "chain" else synth.human_initial_state
     contact = which == "human"
     E = 16
-    q, qd, act = _warm_states(m, gm, E, 60, dt, kind, 22, contact, init)
+    q, qd, act = _warm_states(m, o, E, 60, dt, kind, 22, contact, init)
     u = synth.excitation_iid(6, E, m["n_mus"], 0)
     q1, qd1, a1, st = _advance_gpu(gm, q, qd, act, u[None], dt, contact)
     assert (st == 0).all()

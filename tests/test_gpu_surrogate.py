@@ -1,0 +1,280 @@
+"""The geometry surrogate on the GPU, against the FP64 oracle.
+
+* Network kernels (bfloat16 matrix-core GEMMs, SiLU, loss, backward, Adam)
+  against the oracle network evaluated with the same bfloat16 rounding
+  points.
+* The surrogate step: an env whose predictions pass the checks advances as
+  the oracle step given the predicted geometry; an env that fails them
+  advances exactly as the exact path does (bit for bit) and is flagged.
+
+Poses are drawn on the host from seeded generators; targets, moment-arm
+spans and expected states come from the oracle.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import oracle  # noqa: E402
+from paper_2603_29332_amd import ms, synth  # noqa: E402
+
+DEV = "cuda"
+
+
+def _t(a, dtype=torch.float32):
+    return torch.tensor(np.ascontiguousarray(a), dtype=dtype, device=DEV)
+
+
+@pytest.fixture(scope="module")
+def setup():
+    m = synth.chain_model(1)
+    gm = ms.Model(m)
+    s = ms.Surrogate(gm, hidden=64, seed=5)
+    return m, gm, s, oracle.Oracle(m)
+
+
+def _oracle_spans(m, o):
+    """DoFs each muscle's length depends on (ascending, -1 padded to 3),
+    read off the oracle's moment arms at two random poses."""
+    rng = np.random.default_rng(77)
+    nz = np.zeros((m["n_mus"], m["nv"]), bool)
+    for _ in range(2):
+        q = rng.uniform(-1, 1, m["nq"])
+        _, r, _ = o.geometry(q, np.zeros(m["nv"]))
+        nz |= np.abs(r) > 1e-12
+    sp = -np.ones((m["n_mus"], 3), np.int64)
+    for k in range(m["n_mus"]):
+        j = np.flatnonzero(nz[k])
+        assert j.size <= 3
+        sp[k, :j.size] = j
+    return sp
+
+
+def _oracle_targets(m, o, spans, q):
+    """[L | r in span slots] per pose from the oracle's geometry."""
+    n = q.shape[0]
+    y = np.zeros((n, 4 * m["n_mus"]))
+    for p in range(n):
+        L, r, _ = o.geometry(q[p], np.zeros(m["nv"]))
+        y[p, :m["n_mus"]] = L
+        for k in range(m["n_mus"]):
+            for sl in range(3):
+                if spans[k, sl] >= 0:
+                    y[p, m["n_mus"] + 3 * k + sl] = r[k, spans[k, sl]]
+    return y
+
+
+def _full_r(m, spans, rs):
+    """Moment arms in span slots -> [n_mus][nv]."""
+    r = np.zeros((m["n_mus"], m["nv"]))
+    for k in range(m["n_mus"]):
+        for sl in range(3):
+            if spans[k, sl] >= 0:
+                r[k, spans[k, sl]] = rs[k, sl]
+    return r
+
+
+def _poses(m, n, seed):
+    rng = np.random.default_rng(seed)
+    return rng.uniform(m["qlo"], m["qhi"], (n, m["nq"])).astype(np.float32)
+
+
+def _oracle_params(ps):
+    """GPU stores W as [out][in]; the oracle takes [in][out]."""
+    W1, b1, W2, b2, W3, b3 = ps
+    return [W1.T.copy(), b1, W2.T.copy(), b2, W3.T.copy(), b3]
+
+
+def _inputs(m, s, q):
+    """Network inputs of poses q: the hinge angles, zero-padded."""
+    x = np.zeros((q.shape[0], s.n_in), np.float32)
+    x[:, :m["nq"]] = q
+    return x
+
+
+def _rel(a, b):
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-30)
+
+
+def _identity_norm(s):
+    s.set_norm(np.zeros(s.n_out, np.float32), np.ones(s.n_out, np.float32))
+
+
+def test_forward_matches_oracle(setup):
+    m, gm, s, o = setup
+    rng = np.random.default_rng(0)
+    ps = s.params()
+    ps[1][:] = rng.normal(size=ps[1].shape) * 0.1
+    ps[3][:] = rng.normal(size=ps[3].shape) * 0.1
+    ps[5][:] = rng.normal(size=ps[5].shape) * 0.1
+    s.set_params(ps)
+    mean = rng.normal(size=s.n_out).astype(np.float32)
+    std = rng.uniform(0.5, 2, s.n_out).astype(np.float32)
+    s.set_norm(mean, std)
+    n = 136                                     # two 128-row tiles, ragged
+    qh = _poses(m, n, 9)
+    q = _t(qh)
+    L = torch.zeros(n, m["n_mus"], device=DEV)
+    r = torch.zeros(n, m["n_mus"], 3, device=DEV)
+    s.forward(q, L, r)
+    torch.cuda.synchronize()
+    y = np.concatenate([L.cpu().numpy(), r.cpu().numpy().reshape(n, -1)], axis=1)
+    yo = oracle.mlp_forward(_oracle_params(ps), _inputs(m, s, qh), bf16=True) * std + mean
+    assert _rel(y, yo) < 2e-3
+    _identity_norm(s)
+
+
+def test_gradients_match_oracle(setup):
+    m, gm, s, o = setup
+    n = 64
+    qh = _poses(m, n, 3)
+    spans = _oracle_spans(m, o)
+    t = _oracle_targets(m, o, spans, qh).astype(np.float32)
+    L = _t(t[:, :m["n_mus"]])
+    r = _t(t[:, m["n_mus"]:].reshape(n, m["n_mus"], 3))
+    loss = torch.zeros(1, device=DEV)
+    s.train_step(_t(qh), L, r, lr=0.0, step=1, loss=loss)
+    torch.cuda.synchronize()
+    g = s.grads()
+    ps = s.params()
+    mask = np.ones(s.n_out, np.float32)
+    mask[m["n_mus"]:] = (spans.reshape(-1) >= 0)
+    lo, go = oracle.mlp_grad(_oracle_params(ps), _inputs(m, s, qh), t * mask,
+                             np.tile(mask, (n, 1)), bf16=True)
+    assert abs(loss.item() - lo) < 1e-3 * lo
+    pairs = [(g[0], go[0].T), (g[1], go[1]), (g[2], go[2].T), (g[3], go[3]), (g[4], go[4].T),
+             (g[5], go[5])]
+    for k, (a, b) in enumerate(pairs):
+        assert _rel(a, b) < 1e-2, (k, _rel(a, b))
+
+
+def test_adam_update_matches_oracle(setup):
+    m, gm, s, o = setup
+    n = 32
+    qh = _poses(m, n, 4)
+    spans = _oracle_spans(m, o)
+    t = _oracle_targets(m, o, spans, qh).astype(np.float32)
+    L = _t(t[:, :m["n_mus"]])
+    r = _t(t[:, m["n_mus"]:].reshape(n, m["n_mus"], 3))
+    p0 = s.params()
+    s.train_step(_t(qh), L, r, lr=1e-3, step=1)
+    torch.cuda.synchronize()
+    g = s.grads()
+    p1 = s.params()
+    for a, b, gg in zip(p0, p1, g):
+        w = a.astype(np.float64).copy()
+        mm = np.zeros_like(w)
+        vv = np.zeros_like(w)
+        oracle.adam(w.reshape(-1), mm.reshape(-1), vv.reshape(-1), gg.astype(np.float64).reshape(-1),
+                    lr=1e-3, step=1)
+        assert np.abs(b - w).max() < 1e-6
+
+
+def test_sampled_poses_lie_in_the_box(setup):
+    m, gm, s, o = setup
+    q = torch.zeros(1000, m["nq"], device=DEV)
+    s.sample(q, seed=1, offset=5)
+    q2 = torch.zeros(1000, m["nq"], device=DEV)
+    s.sample(q2, seed=1, offset=5)
+    torch.cuda.synchronize()
+    qa = q.cpu().numpy()
+    assert np.array_equal(qa, q2.cpu().numpy())
+    assert (qa >= m["qlo"]).all() and (qa <= m["qhi"]).all()
+    assert qa.std(axis=0).min() > 1.0        # spread over +-pi
+
+
+# ------------------------------------------------------------ surrogate step
+def _constant_network(m, s, o, spans, q_ref):
+    """Zero the output layer so the network returns exactly its shift: the
+    oracle geometry at q_ref with lengths 0.5 mm long and moment arms 10 %
+    large (wrong enough to tell apart from the exact geometry, close enough
+    to pass a 1 mm length check). Returns (L, r slots) as float32."""
+    ps = s.params()
+    ps[4][:] = 0.0
+    ps[5][:] = 0.0
+    s.set_params(ps)
+    y = _oracle_targets(m, o, spans, q_ref[None])[0]
+    y[:m["n_mus"]] += 5e-4
+    y[m["n_mus"]:] *= 1.1
+    y = y.astype(np.float32)
+    s.set_norm(y, np.ones(s.n_out, np.float32))
+    return y[:m["n_mus"]], y[m["n_mus"]:].reshape(m["n_mus"], 3)
+
+
+def _states(m, E, q_ref, near, seed):
+    rng = np.random.default_rng(seed)
+    q = np.tile(q_ref, (E, 1)).astype(np.float32)
+    far = ~near
+    q[near] += rng.uniform(-2e-6, 2e-6, (near.sum(), m["nq"])).astype(np.float32)
+    q[far] += rng.uniform(0.2, 0.4, (far.sum(), m["nq"])).astype(np.float32)
+    qd = rng.normal(0, 0.3, (E, m["nv"])).astype(np.float32)
+    act = rng.uniform(0.05, 0.6, (E, m["n_mus"])).astype(np.float32)
+    return q, qd, act
+
+
+def test_surrogate_step_matches_oracle_given_geometry_and_falls_back(setup):
+    m, gm, s, o = setup
+    spans = _oracle_spans(m, o)
+    q_ref = np.linspace(-0.4, 0.4, m["nq"])
+    Lr, rr = _constant_network(m, s, o, spans, q_ref)
+    E, dt = 96, 2e-3
+    near = np.arange(E) % 3 != 0
+    q, qd, act = _states(m, E, q_ref, near, 5)
+    u = synth.excitation_iid(12, E, m["n_mus"], 0)
+    tq, tqd, tact = _t(q), _t(qd), _t(act)
+    st = torch.zeros(E, dtype=torch.int32, device=DEV)
+    fb = torch.zeros(E, dtype=torch.int32, device=DEV)
+    gm.rollout_surrogate(s, tq, tqd, tact, st, 1, dt, contact=False, tol=1e-3,
+                         fb_count=fb, kind=ms.EXC_ARRAY, u=_t(u[None]))
+    # the exact path on the same states
+    eq, eqd, eact = _t(q), _t(qd), _t(act)
+    est = torch.zeros(E, dtype=torch.int32, device=DEV)
+    gm.rollout(eq, eqd, eact, est, 1, dt, False, kind=ms.EXC_ARRAY, u=_t(u[None]))
+    torch.cuda.synchronize()
+    st, fb = st.cpu().numpy(), fb.cpu().numpy()
+    assert (est.cpu().numpy() == 0).all()
+    assert np.array_equal(fb, (~near).astype(np.int32))
+    assert np.array_equal(st, np.where(near, 0, ms.MS_ST_FALLBACK))
+    g = [x.cpu().numpy() for x in (tq, tqd, tact)]
+    ex = [x.cpu().numpy() for x in (eq, eqd, eact)]
+    for a, b in zip(g, ex):
+        assert np.array_equal(a[~near], b[~near])
+    rfull = _full_r(m, spans, rr)
+    for e in np.flatnonzero(near):
+        qo, qdo, ao, sto = o.step(dt, q[e], qd[e], act[e], u[e], contact=False,
+                                  geometry=(Lr, rfull))
+        assert sto == 0
+        for a, b in zip((g[0][e], g[1][e], g[2][e]), (qo, qdo, ao)):
+            assert np.abs(a - b).max() / max(np.abs(b).max(), 1.0) <= 1e-5
+    # the predicted geometry is not the exact one: near envs differ from the
+    # exact path
+    assert np.abs(g[1][near] - ex[1][near]).max() > 1e-3
+    _identity_norm(s)
+
+
+def test_surrogate_rollout_with_negative_tolerance_is_the_exact_path(setup):
+    m, gm, s, o = setup
+    E, T, dt = 64, 5, 2e-3
+    q, qd, act = synth.chain_initial_state(m, E, seed=3)
+    x0 = np.zeros((E, m["n_mus"]), np.float32)
+    runs = []
+    for sur in (True, False):
+        tq, tqd, tact, tx = _t(q), _t(qd), _t(act), _t(x0)
+        st = torch.zeros(E, dtype=torch.int32, device=DEV)
+        fb = torch.zeros(E, dtype=torch.int32, device=DEV)
+        consts = synth.ar1_constants(dt)[:3]
+        if sur:
+            gm.rollout_surrogate(s, tq, tqd, tact, st, T, dt, contact=False, tol=-1.0,
+                                 fb_count=fb, kind=ms.EXC_AR1, seed=4, step0=2, x=tx,
+                                 ar1=consts)
+        else:
+            gm.rollout(tq, tqd, tact, st, T, dt, False, kind=ms.EXC_AR1, seed=4, step0=2, x=tx,
+                       ar1=consts)
+        torch.cuda.synchronize()
+        runs.append([v.cpu().numpy() for v in (tq, tqd, tact, tx, st, fb)])
+    a, b = runs
+    for k in range(4):
+        assert np.array_equal(a[k], b[k])
+    assert (a[4] == ms.MS_ST_FALLBACK).all() and (b[4] == 0).all()
+    assert (a[5] == T).all()

@@ -557,3 +557,32 @@ def test_contact_sliding_stops_near_coulomb_distance():
     d_exact = 3.0 ** 2 / (2 * G)
     assert abs(q[0] - d_exact) < 0.05 * d_exact
     assert abs(qd[0]) < 0.05
+
+
+# ---------------------------------------------------------- given geometry
+def test_given_geometry_step_matches_computed(human):
+    """The step with geometry supplied (the surrogate's entry into the
+    dynamics) reduces to the ordinary step when the supplied values are the
+    exact path geometry, and a length change of one muscle moves only that
+    muscle's Hill force, by the Hill law."""
+    m, o = human
+    rng = np.random.default_rng(21)
+    q, qd = _rand_pose(m, rng, 0.3)
+    qd *= 0.3
+    act = rng.uniform(0.05, 0.9, m["n_mus"])
+    u = rng.uniform(0, 1, m["n_mus"])
+    L, r, _ = o.geometry(q, qd)
+    a = o.step(1e-3, q, qd, act, u, stages=True)
+    b = o.step(1e-3, q, qd, act, u, stages=True, geometry=(L, r))
+    for x, y in zip(a[:3], b[:3]):
+        assert np.abs(x - y).max() < 1e-12
+    assert a[3] == b[3] == 0
+    k = 17
+    L2 = L.copy()
+    L2[k] += 0.004
+    c = o.step(1e-3, q, qd, act, u, stages=True, geometry=(L2, r))
+    dF = c[4]["F"] - a[4]["F"]
+    assert np.abs(np.delete(dF, k)).max() == 0.0
+    Fk = o.hill(c[4]["act"], L2, a[4]["Ldot"])[k]
+    assert abs(c[4]["F"][k] - Fk) < 1e-12 * max(1.0, abs(Fk))
+    assert abs(dF[k]) > 0

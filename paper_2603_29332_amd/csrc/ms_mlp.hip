@@ -32,7 +32,7 @@ struct ms_surrogate {
   ms::bf16 *X = nullptr, *H1 = nullptr, *H2 = nullptr, *dYb = nullptr, *dZ2b = nullptr,
            *dZ1b = nullptr;
   float *Z1 = nullptr, *Z2 = nullptr, *Y = nullptr, *T = nullptr, *dY = nullptr, *dZ2 = nullptr,
-        *dZ1 = nullptr, *part = nullptr;
+        *dZ1 = nullptr, *part = nullptr, *cpart = nullptr;
   std::vector<void *> owned;
 };
 
@@ -134,13 +134,16 @@ __global__ void k_loss_final(const float *part, int nb, int n, int n_out, float 
   }
 }
 
-// out[c] = sum over rows of X[r][c] (fixed row order)
-__global__ void k_colsum(const float *X, int rows, int cols, float *out) {
+// Column sums in two fixed-order passes: part[k][c] = sum of rows
+// [kCS k, kCS (k+1)) of column c, then out[c] = sum over k of part[k][c].
+constexpr int kCS = 256;
+__global__ void k_colsum(const float *X, int rows, int cols, int chunk, float *out) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= cols) return;
+  const int r0 = blockIdx.y * chunk, r1 = min(rows, r0 + chunk);
   float s = 0.0f;
-  for (int r = 0; r < rows; ++r) s += X[(size_t)r * cols + c];
-  out[c] = s;
+  for (int r = r0; r < r1; ++r) s += X[(size_t)r * cols + c];
+  out[(size_t)blockIdx.y * cols + c] = s;
 }
 
 __global__ void k_adam(float *w, float *m, float *v, const float *g, int n, float lr, float b1,
@@ -170,6 +173,13 @@ __global__ void k_unpack(const float *Y, int n_mus, int n, float *L, float *r) {
 }
 
 inline int blocks(long long n, int b = 256) { return (int)((n + b - 1) / b); }
+
+// out[c] = column sums of X[rows][cols], deterministic order
+void colsum(ms_surrogate *s, const float *X, int rows, int cols, float *out, hipStream_t st) {
+  const int nk = (rows + kCS - 1) / kCS;
+  hipLaunchKernelGGL(k_colsum, dim3(blocks(cols), nk), dim3(256), 0, st, X, rows, cols, kCS, s->cpart);
+  hipLaunchKernelGGL(k_colsum, dim3(blocks(cols), 1), dim3(256), 0, st, s->cpart, nk, cols, nk, out);
+}
 
 thread_local std::string s_err;
 ms_status sfail(ms_status s, const std::string &m) {
@@ -204,8 +214,9 @@ ms_status ensure_cap(ms_surrogate *s, int n) {
   s->dZ1 = dalloc<float>(s, B * s->h1);
   s->dZ1b = dalloc<bf16>(s, B * s->h1);
   s->part = dalloc<float>(s, (size_t)blocks((long long)B * s->n_out));
+  s->cpart = dalloc<float>(s, (size_t)((B + kCS - 1) / kCS) * std::max(s->n_out, std::max(s->h1, s->h2)));
   if (!s->X || !s->Z1 || !s->H1 || !s->Z2 || !s->H2 || !s->Y || !s->T || !s->dY || !s->dYb ||
-      !s->dZ2 || !s->dZ2b || !s->dZ1 || !s->dZ1b || !s->part)
+      !s->dZ2 || !s->dZ2b || !s->dZ1 || !s->dZ1b || !s->part || !s->cpart)
     return sfail(MS_E_ALLOC, "surrogate workspace allocation failed");
   s->cap = n;
   return MS_OK;
@@ -445,7 +456,7 @@ ms_status ms_surrogate_train_step(ms_surrogate *s, int32_t n, const float *q, co
                      s->dYb, s->part);
   if (loss) hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(1), 0, hs, s->part, nb, n, s->n_out, loss);
   // layer 3: gb3 = colsum dY, gW3[o][j] = sum_p dY[p][o] H2[p][j], dH2 -> dZ2
-  hipLaunchKernelGGL(k_colsum, dim3(blocks(s->n_out)), dim3(256), 0, hs, s->dY, n, s->n_out, s->gb[2]);
+  colsum(s, s->dY, n, s->n_out, s->gb[2], hs);
   GemmEpi g3;
   g3.c_f32 = s->gW[2];
   g3.ldc = s->h2;
@@ -459,7 +470,7 @@ ms_status ms_surrogate_train_step(ms_surrogate *s, int32_t n, const float *q, co
   e = gemm_bf16(false, false, n, s->h2, s->n_out, s->dYb, s->n_out, s->Wb[2], s->h2, d2, hs);
   if (e != hipSuccess) return hipst(e, "gemm dZ2");
   // layer 2
-  hipLaunchKernelGGL(k_colsum, dim3(blocks(s->h2)), dim3(256), 0, hs, s->dZ2, n, s->h2, s->gb[1]);
+  colsum(s, s->dZ2, n, s->h2, s->gb[1], hs);
   GemmEpi g2;
   g2.c_f32 = s->gW[1];
   g2.ldc = s->h1;
@@ -473,7 +484,7 @@ ms_status ms_surrogate_train_step(ms_surrogate *s, int32_t n, const float *q, co
   e = gemm_bf16(false, false, n, s->h1, s->h2, s->dZ2b, s->h2, s->Wb[1], s->h1, d1, hs);
   if (e != hipSuccess) return hipst(e, "gemm dZ1");
   // layer 1
-  hipLaunchKernelGGL(k_colsum, dim3(blocks(s->h1)), dim3(256), 0, hs, s->dZ1, n, s->h1, s->gb[0]);
+  colsum(s, s->dZ1, n, s->h1, s->gb[0], hs);
   GemmEpi g1;
   g1.c_f32 = s->gW[0];
   g1.ldc = s->n_in;

@@ -182,8 +182,6 @@ ms_status build_tables(const ms_model_desc *d, Tables *t, std::string *msg) {
   t->nnz_row.resize(t->nnz);
   for (int j = 0; j < nv; ++j)
     for (int e = t->row_start[j]; e < t->row_start[j + 1]; ++e) t->nnz_row[e] = j;
-  t->rs_path.resize(t->nnz);
-  for (int e = 0; e < t->nnz; ++e) t->rs_path[e] = t->row_start[t->path[e]];
   t->max_depth = *std::max_element(t->dof_depth.begin(), t->dof_depth.end());
   need(t->max_depth <= kMaxDepth, "DoF tree deeper than 64", MS_E_UNSUPPORTED, &st, msg);
   auto dof_anc = [&](int a, int b) {  // DoF a is b or an ancestor of b
@@ -209,6 +207,22 @@ ms_status build_tables(const ms_model_desc *d, Tables *t, std::string *msg) {
       if (t->dof_depth[j] == dl + 1) t->dlev_dof.push_back(j);
   }
   t->dlev_start[t->n_dlev] = (int)t->dlev_dof.size();
+  t->hent_start.assign(t->n_hlev + 1, 0);
+  for (int h = 0; h < t->n_hlev; ++h) {
+    t->hent_start[h] = (int)t->hent.size();
+    for (int e = t->hlev_start[h]; e < t->hlev_start[h + 1]; ++e) {
+      const int k = t->hlev_dof[e];
+      for (int x = t->row_start[k]; x < t->row_start[k + 1]; ++x) t->hent.push_back(x | (k << 16));
+    }
+  }
+  t->hent_start[t->n_hlev] = (int)t->hent.size();
+  t->desc_start.assign(nv + 1, 0);
+  for (int k = 0; k < nv; ++k) {
+    t->desc_start[k] = (int)t->desc.size();
+    for (int i = 0; i < nv; ++i)
+      if (i != k && dof_anc(k, i)) t->desc.push_back(t->row_start[i] | (i << 16));
+  }
+  t->desc_start[nv] = (int)t->desc.size();
 
   // muscles
   const int nm = d->n_mus;

@@ -59,11 +59,13 @@ struct Tables {
   // tree-sparse mass matrix (row j holds its ancestors by depth, diag last)
   std::vector<int32_t> row_start, dof_depth, path;     // path[nnz] = DoF id
   std::vector<int32_t> nnz_row;                        // row of each entry
-  std::vector<int32_t> rs_path;                        // row start of path[e]
   // level schedules of the factorisation and solves: DoFs grouped by height
   // (leaves first) and by depth (root first)
   int n_hlev = 0, n_dlev = 0;
   std::vector<int32_t> hlev_start, hlev_dof, dlev_start, dlev_dof;
+  // the factorisation as gathers: per height level its rows' entries
+  // (entry | row << 16); per DoF its proper descendants (row start | id << 16)
+  std::vector<int32_t> hent_start, hent, desc_start, desc;
   // LDS layout (byte offsets into the per-env LDS block)
   int off_q = 0, off_qd = 0, off_R = 0, off_P = 0, off_S = 0, off_V = 0,
       off_A = 0, off_F = 0, off_con = 0, off_rhs = 0, off_H = 0, off_x = 0,

@@ -46,9 +46,10 @@ struct KModel {
   const unsigned *mus_mask;
   const int *proj_start, *proj_item;
   const int *dent_h, *dent_start, *dent_item;
-  const int *row_start, *dof_depth, *path, *nnz_row, *rs_path;
+  const int *row_start, *dof_depth, *path, *nnz_row;
   int n_hlev, n_dlev;
   const int *hlev_start, *hlev_dof, *dlev_start, *dlev_dof;
+  const int *hent_start, *hent, *desc_start, *desc;
   int off_flag, off_q, off_qd, off_R, off_P, off_S, off_con, off_rhs, off_x, off_H,
       off_scr, off_V, off_A, off_F, off_tree;
 };
@@ -182,6 +183,21 @@ __device__ __forceinline__ double lane_bcast(double v, int src) {
 // receives the total.
 __device__ __forceinline__ double wave_sum(double v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// log2 of the lanes per item when n items share a wavefront (n >= 1):
+// the largest power of two P with n P <= 64
+__device__ __forceinline__ int group_log2(int n) {
+  int l = 0;
+  while (l < 6 && (n << (l + 1)) <= 64) ++l;
+  return l;
+}
+
+// sum over aligned groups of 2^lp lanes, fixed butterfly order; every lane of
+// a group gets the same value
+__device__ __forceinline__ double group_sum(double v, int lp) {
+  for (int o = (1 << lp) >> 1; o > 0; o >>= 1) v += __shfl_xor(v, o);
   return v;
 }
 
@@ -743,17 +759,40 @@ __global__ __launch_bounds__(64) void k_step(KModel M, KRun Rn, int n_steps) {
     }
 
     // ------------------------------------------------ LTDL factorisation (FP64)
-    // H = L^T D L (Featherstone's branch-induced sparsity). DoFs of equal
-    // height are eliminated together, leaves first; each eliminated DoF k
-    // updates the (ancestor, ancestor) entries H[i][j] -= H[k][i] H[k][j] / d_k.
-    // Targets lie on higher levels than their sources, so a level's updates
-    // only add into entries nobody in the level reads.
+    // H = L^T D L with Featherstone's branch-induced sparsity, as gathers:
+    // finished row k holds H_kj - sum over the descendants i of k of
+    // H_ik H_ij / d_i (j = k or an ancestor of k), and reads only finished
+    // rows of lower height. Rows of equal height are independent, so a
+    // height level is one pass over its entries; when a level has few
+    // entries, P lanes split each entry's sum (fixed-order butterfly).
     bool nonspd = false;
     double *invd = (double *)scr;  // 1/d per DoF (the muscle scratch is free now)
-    for (int h = 0; h < M.n_hlev && !nonspd; ++h) {
-      const int s0 = M.hlev_start[h], s1 = M.hlev_start[h + 1];
+    for (int h = 0; h < M.n_hlev; ++h) {
+      if (h > 0) {  // leaves have no descendants
+        const int s0 = M.hent_start[h], ne = M.hent_start[h + 1] - s0;
+        const int lp = group_log2(ne), P = 1 << lp;
+        for (int base = 0; base < (ne << lp); base += 64) {
+          const int idx = base + lane, g = idx >> lp, p = idx & (P - 1);
+          double sum = 0.0;
+          int e = 0;
+          if (g < ne) {
+            const int pk = M.hent[s0 + g];
+            const int k = pk >> 16;
+            e = pk & 0xFFFF;
+            const int ck = M.dof_depth[k] - 1, cj = e - M.row_start[k];
+            for (int t = M.desc_start[k] + p; t < M.desc_start[k + 1]; t += P) {
+              const int di = M.desc[t];
+              const int ri = di & 0xFFFF;
+              sum += H[ri + ck] * H[ri + cj] * invd[di >> 16];
+            }
+          }
+          sum = group_sum(sum, lp);
+          if (g < ne && p == 0) H[e] -= sum;
+        }
+        __syncthreads();
+      }
       bool bad = false;
-      for (int e = s0 + lane; e < s1; e += 64) {
+      for (int e = M.hlev_start[h] + lane; e < M.hlev_start[h + 1]; e += 64) {
         const int k = M.hlev_dof[e];
         const double d = H[M.row_start[k] + M.dof_depth[k] - 1];
         bad |= !(d > 0.0);
@@ -764,68 +803,47 @@ __global__ __launch_bounds__(64) void k_step(KModel M, KRun Rn, int n_steps) {
         break;
       }
       __syncthreads();
-      // the level's DoFs one after another (their updates may meet in a
-      // shared ancestor). Row k's entries stay in registers (lane b holds
-      // H[k][b]); a uniform loop walks k's ancestor rows a, four at a time,
-      // and lanes b <= a update H[i_a][b] -= H[k][a] H[k][b] / d_k. The four
-      // rows are distinct, so their loads are issued before any store.
-      for (int e = s0; e < s1; ++e) {
-        const int k = M.hlev_dof[e];
-        const int rk = M.row_start[k], na = M.dof_depth[k] - 1;
-        const double inv = invd[k];
-        const bool mine = lane < na;
-        const double hb = mine ? H[rk + lane] : 0.0;
-        const int rsl = mine ? M.rs_path[rk + lane] : 0;
-        const double hbi = hb * inv;
-        for (int a0 = 0; a0 < na; a0 += 4) {
-          double t[4], ha[4];
-          int ra[4];
-#pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            const int a = a0 + u < na ? a0 + u : na - 1;
-            ha[u] = lane_bcast(hbi, a);
-            ra[u] = __builtin_amdgcn_readlane(rsl, a);
-            t[u] = (a0 + u < na && lane <= a0 + u) ? H[ra[u] + lane] : 0.0;
-          }
-#pragma unroll
-          for (int u = 0; u < 4; ++u)
-            if (a0 + u < na && lane <= a0 + u) H[ra[u] + lane] = t[u] - ha[u] * hb;
-        }
-      }
-      __syncthreads();
     }
     if (!nonspd) {
-      // L = H / d (row-wise), keep d on the diagonal
-      for (int e = lane; e < M.nnz; e += 64) {
-        const int j = M.nnz_row[e];
-        if (M.path[e] != j) H[e] *= invd[j];
-      }
-      for (int j = lane; j < nv; j += 64) xs[j] = rhs[j];
-      __syncthreads();
-      // L^T y = b, by height (leaves first): y_k is final once its
-      // descendants have scattered into it
+      // L^T y = rhs, leaves first: y_k = rhs_k - sum_{i desc. of k} (H_ik / d_i) y_i
       for (int h = 0; h < M.n_hlev; ++h) {
-        const int s0 = M.hlev_start[h], s1 = M.hlev_start[h + 1];
-        for (int e = s0; e < s1; ++e) {
-          const int k = M.hlev_dof[e];
-          const int rk = M.row_start[k], na = M.dof_depth[k] - 1;
-          const double yk = xs[k];
-          for (int a = lane; a < na; a += 64) xs[M.path[rk + a]] -= H[rk + a] * yk;
+        const int s0 = M.hlev_start[h], ne = M.hlev_start[h + 1] - s0;
+        const int lp = group_log2(ne), P = 1 << lp;
+        for (int base = 0; base < (ne << lp); base += 64) {
+          const int idx = base + lane, g = idx >> lp, p = idx & (P - 1);
+          double sum = 0.0;
+          int k = 0;
+          if (g < ne) {
+            k = M.hlev_dof[s0 + g];
+            const int ck = M.dof_depth[k] - 1;
+            for (int t = M.desc_start[k] + p; t < M.desc_start[k + 1]; t += P) {
+              const int di = M.desc[t];
+              const int i = di >> 16;
+              sum += H[(di & 0xFFFF) + ck] * invd[i] * xs[i];
+            }
+          }
+          sum = group_sum(sum, lp);
+          if (g < ne && p == 0) xs[k] = rhs[k] - sum;
         }
         __syncthreads();
       }
       for (int j = lane; j < nv; j += 64) xs[j] *= invd[j];
       __syncthreads();
-      // L x = z, by depth (root first): ancestors are final
+      // L x = z, root first: x_k = z_k - (1/d_k) sum_{a anc. of k} H_ka x_a
       for (int dl = 1; dl < M.n_dlev; ++dl) {
-        const int s0 = M.dlev_start[dl], s1 = M.dlev_start[dl + 1];
-        for (int e = s0; e < s1; ++e) {
-          const int k = M.dlev_dof[e];
-          const int rk = M.row_start[k];
+        const int s0 = M.dlev_start[dl], ne = M.dlev_start[dl + 1] - s0;
+        const int lp = group_log2(ne), P = 1 << lp;
+        for (int base = 0; base < (ne << lp); base += 64) {
+          const int idx = base + lane, g = idx >> lp, p = idx & (P - 1);
           double sum = 0.0;
-          for (int a = lane; a < dl; a += 64) sum += H[rk + a] * xs[M.path[rk + a]];
-          sum = wave_sum(sum);
-          if (lane == 0) xs[k] -= sum;
+          int k = 0;
+          if (g < ne) {
+            k = M.dlev_dof[s0 + g];
+            const int rk = M.row_start[k];
+            for (int a = p; a < dl; a += P) sum += H[rk + a] * xs[M.path[rk + a]];
+          }
+          sum = group_sum(sum, lp);
+          if (g < ne && p == 0) xs[k] -= sum * invd[k];
         }
         __syncthreads();
       }
@@ -1033,8 +1051,10 @@ ms_status ms_model_create(const ms_model_desc *desc, ms_model **out) {
          o_mask = p.add(t.mus_mask), o_ps = p.add(t.proj_start), o_pi = p.add(t.proj_item),
          o_dh = p.add(t.dent_h), o_ds = p.add(t.dent_start), o_di = p.add(t.dent_item),
          o_rs = p.add(t.row_start), o_dd = p.add(t.dof_depth), o_path = p.add(t.path),
-         o_nr = p.add(t.nnz_row), o_rsp = p.add(t.rs_path), o_hs = p.add(t.hlev_start),
-         o_hd = p.add(t.hlev_dof), o_ds2 = p.add(t.dlev_start), o_dd2 = p.add(t.dlev_dof);
+         o_nr = p.add(t.nnz_row), o_hs = p.add(t.hlev_start),
+         o_hd = p.add(t.hlev_dof), o_ds2 = p.add(t.dlev_start), o_dd2 = p.add(t.dlev_dof),
+         o_hes = p.add(t.hent_start), o_he = p.add(t.hent), o_dss = p.add(t.desc_start),
+         o_dsc = p.add(t.desc);
   m->dbytes = p.buf.size();
   hipError_t e = hipMalloc(&m->dbuf, m->dbytes);
   if (e != hipSuccess) {
@@ -1073,7 +1093,8 @@ ms_status ms_model_create(const ms_model_desc *desc, ms_model **out) {
   P_(mus_span, o_span, int); P_(mus_mask, o_mask, unsigned); P_(proj_start, o_ps, int);
   P_(proj_item, o_pi, int); P_(dent_h, o_dh, int); P_(dent_start, o_ds, int);
   P_(dent_item, o_di, int); P_(row_start, o_rs, int); P_(dof_depth, o_dd, int);
-  P_(path, o_path, int); P_(nnz_row, o_nr, int); P_(rs_path, o_rsp, int);
+  P_(path, o_path, int); P_(nnz_row, o_nr, int);
+  P_(hent_start, o_hes, int); P_(hent, o_he, int); P_(desc_start, o_dss, int); P_(desc, o_dsc, int);
   P_(hlev_start, o_hs, int); P_(hlev_dof, o_hd, int); P_(dlev_start, o_ds2, int);
   P_(dlev_dof, o_dd2, int);
 #undef P_

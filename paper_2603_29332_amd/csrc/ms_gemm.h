@@ -28,6 +28,13 @@ struct GemmEpi {
   float alpha = 1.0f;
 };
 
+// C[M][N] (float32, ldc) = op(A) op(B) with K split into slices computed by
+// separate workgroups into work[S][M][ldc] and summed in slice order
+// (deterministic). work must hold S M ldc floats; S = splitk_slices(...).
+int splitk_slices(int M, int N, int K);
+hipError_t gemm_bf16_splitk(bool ta, bool tb, int M, int N, int K, const bf16 *A, int lda,
+                            const bf16 *B, int ldb, float *C, int ldc, float *work, hipStream_t st);
+
 // Requires K, lda, ldb multiples of 8 (16-byte rows). Returns the launch
 // error, if any.
 hipError_t gemm_bf16(bool ta, bool tb, int M, int N, int K, const bf16 *A, int lda, const bf16 *B,

@@ -52,9 +52,12 @@ __device__ __forceinline__ float silu_slope(float z) {
   return s * (1.0f + z * (1.0f - s));
 }
 
+// K slice z = blockIdx.z covers [z k_slice, min(K, (z + 1) k_slice)) and
+// writes its partial product at an offset of z z_stride floats
 template <bool TA, bool TB>
 __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const bf16 *A, int lda,
-                                              const bf16 *B, int ldb, GemmEpi epi) {
+                                              const bf16 *B, int ldb, GemmEpi epi, int k_slice,
+                                              size_t z_stride) {
   __shared__ __align__(16) unsigned short As[BM * LK];
   __shared__ __align__(16) unsigned short Bs[BN * LK];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -66,9 +69,10 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const bf16 *A
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-  for (int k0 = 0; k0 < K; k0 += BK) {
-    stage<TA>(As, A, lda, m0, M, k0, K, tid);
-    stage<!TB>(Bs, B, ldb, n0, N, k0, K, tid);
+  const int kb = blockIdx.z * k_slice, ke = min(K, kb + k_slice);
+  for (int k0 = kb; k0 < ke; k0 += BK) {
+    stage<TA>(As, A, lda, m0, M, k0, ke, tid);
+    stage<!TB>(Bs, B, ldb, n0, N, k0, ke, tid);
     __syncthreads();
     bf16x8 a[4], b[4];
     const int kq = (lane >> 4) * 8, r = lane & 15;
@@ -96,7 +100,7 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const bf16 *A
         const int m = m0 + wm * 64 + i * 16 + (lane >> 4) * 4 + e;
         const int n = n0 + wn * 64 + j * 16 + (lane & 15);
         if (m >= M || n >= N) continue;
-        const size_t o = (size_t)m * epi.ldc + n;
+        const size_t o = (size_t)blockIdx.z * z_stride + (size_t)m * epi.ldc + n;
         float v = acc[i][j][e] * epi.alpha;
         if (epi.bias) v += epi.bias[n];
         if (epi.dact) v *= silu_slope(epi.dact[o]);
@@ -108,17 +112,66 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const bf16 *A
       }
 }
 
+// C[m][n] = sum over z of work[z][m][n], slice order
+__global__ void k_splitk_sum(const float *work, int S, size_t stride, int M, int N, int ldc,
+                             float *C) {
+  const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (size_t)M * N) return;
+  const int m = (int)(t / N), n = (int)(t % N);
+  const size_t o = (size_t)m * ldc + n;
+  float s = 0.0f;
+  for (int z = 0; z < S; ++z) s += work[z * stride + o];
+  C[o] = s;
+}
+
 }  // namespace
+
+static hipError_t gemm_launch(bool ta, bool tb, int M, int N, int K, const bf16 *A, int lda,
+                              const bf16 *B, int ldb, const GemmEpi &epi, int S, int ks,
+                              size_t stride, hipStream_t st) {
+  dim3 grid((N + BN - 1) / BN, (M + BM - 1) / BM, S), block(256);
+  if (!ta && !tb)
+    hipLaunchKernelGGL((k_gemm<false, false>), grid, block, 0, st, M, N, K, A, lda, B, ldb, epi, ks, stride);
+  if (!ta && tb)
+    hipLaunchKernelGGL((k_gemm<false, true>), grid, block, 0, st, M, N, K, A, lda, B, ldb, epi, ks, stride);
+  if (ta && !tb)
+    hipLaunchKernelGGL((k_gemm<true, false>), grid, block, 0, st, M, N, K, A, lda, B, ldb, epi, ks, stride);
+  if (ta && tb)
+    hipLaunchKernelGGL((k_gemm<true, true>), grid, block, 0, st, M, N, K, A, lda, B, ldb, epi, ks, stride);
+  return hipGetLastError();
+}
 
 hipError_t gemm_bf16(bool ta, bool tb, int M, int N, int K, const bf16 *A, int lda, const bf16 *B,
                      int ldb, const GemmEpi &epi, hipStream_t st) {
   if (M <= 0 || N <= 0 || K <= 0) return hipSuccess;
   if (K % 8 || lda % 8 || ldb % 8 || (ta && M % 8) || (!tb && N % 8)) return hipErrorInvalidValue;
-  dim3 grid((N + BN - 1) / BN, (M + BM - 1) / BM), block(256);
-  if (!ta && !tb) hipLaunchKernelGGL((k_gemm<false, false>), grid, block, 0, st, M, N, K, A, lda, B, ldb, epi);
-  if (!ta && tb) hipLaunchKernelGGL((k_gemm<false, true>), grid, block, 0, st, M, N, K, A, lda, B, ldb, epi);
-  if (ta && !tb) hipLaunchKernelGGL((k_gemm<true, false>), grid, block, 0, st, M, N, K, A, lda, B, ldb, epi);
-  if (ta && tb) hipLaunchKernelGGL((k_gemm<true, true>), grid, block, 0, st, M, N, K, A, lda, B, ldb, epi);
+  return gemm_launch(ta, tb, M, N, K, A, lda, B, ldb, epi, 1, K, 0, st);
+}
+
+int splitk_slices(int M, int N, int K) {
+  const int tiles = ((M + BM - 1) / BM) * ((N + BN - 1) / BN);
+  int S = 1;
+  // at least ~1024 workgroups, slices of at least 256 along K
+  while (S < 64 && tiles * S < 1024 && K / (2 * S) >= 256) S *= 2;
+  return S;
+}
+
+hipError_t gemm_bf16_splitk(bool ta, bool tb, int M, int N, int K, const bf16 *A, int lda,
+                            const bf16 *B, int ldb, float *C, int ldc, float *work, hipStream_t st) {
+  if (M <= 0 || N <= 0 || K <= 0) return hipSuccess;
+  if (K % 8 || lda % 8 || ldb % 8 || (ta && M % 8) || (!tb && N % 8)) return hipErrorInvalidValue;
+  const int S = splitk_slices(M, N, K);
+  int ks = (K + S - 1) / S;
+  ks = (ks + BK - 1) / BK * BK;
+  GemmEpi epi;
+  epi.c_f32 = work;
+  epi.ldc = ldc;
+  const size_t stride = (size_t)M * ldc;
+  hipError_t e = gemm_launch(ta, tb, M, N, K, A, lda, B, ldb, epi, S, ks, stride, st);
+  if (e != hipSuccess) return e;
+  const size_t n = (size_t)M * N;
+  hipLaunchKernelGGL(k_splitk_sum, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, work, S,
+                     stride, M, N, ldc, C);
   return hipGetLastError();
 }
 

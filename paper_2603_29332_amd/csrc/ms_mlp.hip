@@ -32,7 +32,7 @@ struct ms_surrogate {
   ms::bf16 *X = nullptr, *H1 = nullptr, *H2 = nullptr, *dYb = nullptr, *dZ2b = nullptr,
            *dZ1b = nullptr;
   float *Z1 = nullptr, *Z2 = nullptr, *Y = nullptr, *T = nullptr, *dY = nullptr, *dZ2 = nullptr,
-        *dZ1 = nullptr, *part = nullptr, *cpart = nullptr;
+        *dZ1 = nullptr, *part = nullptr, *cpart = nullptr, *kwork = nullptr;
   std::vector<void *> owned;
 };
 
@@ -125,13 +125,20 @@ __global__ __launch_bounds__(256) void k_loss(const float *Y, const float *T, co
   if (threadIdx.x == 0) part[blockIdx.x] = red[0];
 }
 
-// loss = sum(part) / (n n_out), one thread, fixed order
-__global__ void k_loss_final(const float *part, int nb, int n, int n_out, float *loss) {
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    double s = 0.0;
-    for (int i = 0; i < nb; ++i) s += part[i];
-    *loss = (float)(s / ((double)n * (double)n_out));
+// loss = sum(part) / (n n_out): 256 threads sum strided slices, then a
+// fixed-order tree (deterministic)
+__global__ __launch_bounds__(256) void k_loss_final(const float *part, int nb, int n, int n_out,
+                                                    float *loss) {
+  __shared__ double red[256];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < nb; i += 256) s += part[i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
   }
+  if (threadIdx.x == 0) *loss = (float)(red[0] / ((double)n * (double)n_out));
 }
 
 // Column sums in two fixed-order passes: part[k][c] = sum of rows
@@ -215,8 +222,16 @@ ms_status ensure_cap(ms_surrogate *s, int n) {
   s->dZ1b = dalloc<bf16>(s, B * s->h1);
   s->part = dalloc<float>(s, (size_t)blocks((long long)B * s->n_out));
   s->cpart = dalloc<float>(s, (size_t)((B + kCS - 1) / kCS) * std::max(s->n_out, std::max(s->h1, s->h2)));
+  {
+    // split-K partials of the weight gradients (K = batch)
+    const int M[3] = {s->n_out, s->h2, s->h1}, N[3] = {s->h2, s->h1, s->n_in};
+    size_t w = 0;
+    for (int l = 0; l < 3; ++l)
+      w = std::max(w, (size_t)splitk_slices(M[l], N[l], n) * M[l] * N[l]);
+    s->kwork = dalloc<float>(s, w);
+  }
   if (!s->X || !s->Z1 || !s->H1 || !s->Z2 || !s->H2 || !s->Y || !s->T || !s->dY || !s->dYb ||
-      !s->dZ2 || !s->dZ2b || !s->dZ1 || !s->dZ1b || !s->part || !s->cpart)
+      !s->dZ2 || !s->dZ2b || !s->dZ1 || !s->dZ1b || !s->part || !s->cpart || !s->kwork)
     return sfail(MS_E_ALLOC, "surrogate workspace allocation failed");
   s->cap = n;
   return MS_OK;
@@ -454,13 +469,11 @@ ms_status ms_surrogate_train_step(ms_surrogate *s, int32_t n, const float *q, co
   const int nb = blocks(no);
   hipLaunchKernelGGL(k_loss, dim3(nb), dim3(256), 0, hs, s->Y, s->T, s->mask, n, s->n_out, s->dY,
                      s->dYb, s->part);
-  if (loss) hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(1), 0, hs, s->part, nb, n, s->n_out, loss);
+  if (loss) hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(256), 0, hs, s->part, nb, n, s->n_out, loss);
   // layer 3: gb3 = colsum dY, gW3[o][j] = sum_p dY[p][o] H2[p][j], dH2 -> dZ2
   colsum(s, s->dY, n, s->n_out, s->gb[2], hs);
-  GemmEpi g3;
-  g3.c_f32 = s->gW[2];
-  g3.ldc = s->h2;
-  hipError_t e = gemm_bf16(true, false, s->n_out, s->h2, n, s->dYb, s->n_out, s->H2, s->h2, g3, hs);
+  hipError_t e = gemm_bf16_splitk(true, false, s->n_out, s->h2, n, s->dYb, s->n_out, s->H2, s->h2,
+                                  s->gW[2], s->h2, s->kwork, hs);
   if (e != hipSuccess) return hipst(e, "gemm dW3");
   GemmEpi d2;
   d2.dact = s->Z2;
@@ -471,10 +484,8 @@ ms_status ms_surrogate_train_step(ms_surrogate *s, int32_t n, const float *q, co
   if (e != hipSuccess) return hipst(e, "gemm dZ2");
   // layer 2
   colsum(s, s->dZ2, n, s->h2, s->gb[1], hs);
-  GemmEpi g2;
-  g2.c_f32 = s->gW[1];
-  g2.ldc = s->h1;
-  e = gemm_bf16(true, false, s->h2, s->h1, n, s->dZ2b, s->h2, s->H1, s->h1, g2, hs);
+  e = gemm_bf16_splitk(true, false, s->h2, s->h1, n, s->dZ2b, s->h2, s->H1, s->h1, s->gW[1], s->h1,
+                       s->kwork, hs);
   if (e != hipSuccess) return hipst(e, "gemm dW2");
   GemmEpi d1;
   d1.dact = s->Z1;
@@ -485,10 +496,8 @@ ms_status ms_surrogate_train_step(ms_surrogate *s, int32_t n, const float *q, co
   if (e != hipSuccess) return hipst(e, "gemm dZ1");
   // layer 1
   colsum(s, s->dZ1, n, s->h1, s->gb[0], hs);
-  GemmEpi g1;
-  g1.c_f32 = s->gW[0];
-  g1.ldc = s->n_in;
-  e = gemm_bf16(true, false, s->h1, s->n_in, n, s->dZ1b, s->h1, s->X, s->n_in, g1, hs);
+  e = gemm_bf16_splitk(true, false, s->h1, s->n_in, n, s->dZ1b, s->h1, s->X, s->n_in, s->gW[0],
+                       s->n_in, s->kwork, hs);
   if (e != hipSuccess) return hipst(e, "gemm dW1");
   // Adam
   if (lr > 0.0f) {

@@ -207,15 +207,6 @@ ms_status build_tables(const ms_model_desc *d, Tables *t, std::string *msg) {
       if (t->dof_depth[j] == dl + 1) t->dlev_dof.push_back(j);
   }
   t->dlev_start[t->n_dlev] = (int)t->dlev_dof.size();
-  t->hent_start.assign(t->n_hlev + 1, 0);
-  for (int h = 0; h < t->n_hlev; ++h) {
-    t->hent_start[h] = (int)t->hent.size();
-    for (int e = t->hlev_start[h]; e < t->hlev_start[h + 1]; ++e) {
-      const int k = t->hlev_dof[e];
-      for (int x = t->row_start[k]; x < t->row_start[k + 1]; ++x) t->hent.push_back(x | (k << 16));
-    }
-  }
-  t->hent_start[t->n_hlev] = (int)t->hent.size();
   t->desc_start.assign(nv + 1, 0);
   for (int k = 0; k < nv; ++k) {
     t->desc_start[k] = (int)t->desc.size();
@@ -223,6 +214,27 @@ ms_status build_tables(const ms_model_desc *d, Tables *t, std::string *msg) {
       if (i != k && dof_anc(k, i)) t->desc.push_back(t->row_start[i] | (i << 16));
   }
   t->desc_start[nv] = (int)t->desc.size();
+  need(t->nnz < 65536 && (int)t->desc.size() < 65536, "mass matrix too large", MS_E_UNSUPPORTED,
+       &st, msg);
+  auto drange = [&](int k) { return t->desc_start[k] | (t->desc_start[k + 1] << 16); };
+  t->hent_start.assign(t->n_hlev + 1, 0);
+  for (int h = 0; h < t->n_hlev; ++h) {
+    t->hent_start[h] = (int)t->hent.size() / 2;
+    for (int e = t->hlev_start[h]; e < t->hlev_start[h + 1]; ++e) {
+      const int k = t->hlev_dof[e], rk = t->row_start[k], ck = t->dof_depth[k] - 1;
+      for (int x = rk; x < t->row_start[k + 1]; ++x) {
+        t->hent.push_back(x | (ck << 16) | ((x - rk) << 24));
+        t->hent.push_back(drange(k));
+      }
+      t->hsol.push_back(k | (ck << 16));
+      t->hsol.push_back(drange(k));
+    }
+  }
+  t->hent_start[t->n_hlev] = (int)t->hent.size() / 2;
+  for (int e = 0; e < (int)t->dlev_dof.size(); ++e) {
+    const int k = t->dlev_dof[e];
+    t->dsol.push_back(k | (t->row_start[k] << 8));
+  }
 
   // muscles
   const int nm = d->n_mus;

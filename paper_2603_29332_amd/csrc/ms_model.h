@@ -63,9 +63,13 @@ struct Tables {
   // (leaves first) and by depth (root first)
   int n_hlev = 0, n_dlev = 0;
   std::vector<int32_t> hlev_start, hlev_dof, dlev_start, dlev_dof;
-  // the factorisation as gathers: per height level its rows' entries
-  // (entry | row << 16); per DoF its proper descendants (row start | id << 16)
-  std::vector<int32_t> hent_start, hent, desc_start, desc;
+  // the factorisation and solves as gathers. desc: per DoF its proper
+  // descendants (row start | id << 16), CSR desc_start. hent: per height
+  // level its rows' entries as pairs (entry | depth(row) << 16 |
+  // depth(column) << 24, desc range of the row: begin | end << 16).
+  // hsol: per height-level DoF (id | depth << 16, desc range). dsol: per
+  // depth-level DoF (id | row start << 8).
+  std::vector<int32_t> hent_start, hent, desc_start, desc, hsol, dsol;
   // LDS layout (byte offsets into the per-env LDS block)
   int off_q = 0, off_qd = 0, off_R = 0, off_P = 0, off_S = 0, off_V = 0,
       off_A = 0, off_F = 0, off_con = 0, off_rhs = 0, off_H = 0, off_x = 0,

@@ -1,0 +1,932 @@
+// ms_step_kernel.h -- the batched musculoskeletal forward-dynamics step on gfx950.
+//
+// One wavefront (64 lanes) advances one environment. The environment's
+// kinematic tree (node frames, motion subspaces, spatial velocities and
+// accelerations), its contact state and its tree-sparse FP64 mass matrix
+// live in LDS; muscle work is spread over the lanes (lane l owns muscles
+// l, l+64, ...), tree work over nodes/DoFs, and the LTDL factorisation over
+// the (ancestor, ancestor) pairs of each eliminated DoF.
+//
+// All spatial quantities are expressed in world axes about a reference point
+// O that is the root origin of a floating model (the world origin for a
+// fixed base), so subtree sums (composite inertias, net forces) are plain
+// sums. FP32 throughout except the mass matrix assembly, its factorisation
+// and the solve, which run in FP64.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "ms_step_types.h"
+
+namespace ms {
+
+// ------------------------------------------------------------ small maths
+struct V3 {
+  float x, y, z;
+};
+__device__ __forceinline__ V3 v3(float x, float y, float z) { return V3{x, y, z}; }
+__device__ __forceinline__ V3 operator+(V3 a, V3 b) { return v3(a.x + b.x, a.y + b.y, a.z + b.z); }
+__device__ __forceinline__ V3 operator-(V3 a, V3 b) { return v3(a.x - b.x, a.y - b.y, a.z - b.z); }
+__device__ __forceinline__ V3 operator*(float s, V3 a) { return v3(s * a.x, s * a.y, s * a.z); }
+__device__ __forceinline__ float dot(V3 a, V3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+__device__ __forceinline__ V3 cross(V3 a, V3 b) {
+  return v3(a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x);
+}
+// y = R x, R row-major 3x3
+__device__ __forceinline__ V3 mulR(const float *R, V3 x) {
+  return v3(R[0] * x.x + R[1] * x.y + R[2] * x.z, R[3] * x.x + R[4] * x.y + R[5] * x.z,
+            R[6] * x.x + R[7] * x.y + R[8] * x.z);
+}
+__device__ __forceinline__ V3 ld3(const float *p) { return v3(p[0], p[1], p[2]); }
+__device__ __forceinline__ void st3(float *p, V3 a) {
+  p[0] = a.x;
+  p[1] = a.y;
+  p[2] = a.z;
+}
+
+// Apply node frame F (12 floats, 16-byte aligned: R row-major, then P) to
+// a local point: three 128-bit LDS reads.
+__device__ __forceinline__ V3 frame_apply(const float *F, V3 x) {
+  const float4 a = *(const float4 *)F, b = *(const float4 *)(F + 4), c = *(const float4 *)(F + 8);
+  return v3(a.x * x.x + a.y * x.y + a.z * x.z + c.y, a.w * x.x + b.x * x.y + b.y * x.z + c.z,
+            b.z * x.x + b.w * x.y + c.x * x.z + c.w);
+}
+
+// SplitMix64 output function (Steele, Lea & Flood 2014).
+__device__ __forceinline__ unsigned long long splitmix64(unsigned long long x) {
+  unsigned long long z = x + 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+__device__ __forceinline__ float u24(unsigned long long z, int shift) {
+  return (float)((unsigned)((z >> shift) & 0xFFFFFFull)) * 5.9604644775390625e-8f;
+}
+
+// One step of the smooth-noise excitation for muscle mi: four 24-bit
+// uniforms from two SplitMix64 draws, their sum standardised
+// (Irwin-Hall(4): mean 2, variance 1/3), x <- rho x + s xi,
+// u = clamp(mean + x, 0, 1). Each operation is rounded to float32 in this
+// order: no contraction into fused multiply-adds.
+struct AR1 {
+  float u, x;
+};
+__device__ __forceinline__ AR1 ar1_step(unsigned long long key, int mi, float x, float rho, float s,
+                                        float mean) {
+#pragma clang fp contract(off)
+  const unsigned long long z1 = splitmix64(key ^ (2ull * (unsigned long long)mi));
+  const unsigned long long z2 = splitmix64(key ^ (2ull * (unsigned long long)mi + 1ull));
+  const float t = ((u24(z1, 40) + u24(z1, 16)) + u24(z2, 40)) + u24(z2, 16);
+  const float xi = (t - 2.0f) * 1.7320508075688772f;
+  const float a = rho * x;
+  const float b = s * xi;
+  const float xn = a + b;
+  return AR1{fminf(fmaxf(mean + xn, 0.0f), 1.0f), xn};
+}
+
+// Hill curves: Gaussian active force-length, exponential passive
+// force-length with a linear tail past 1.6, hyperbolic force-velocity.
+__device__ __forceinline__ float hill_fl(float lm) {
+  float d = lm - 1.0f;
+  return expf(-d * d * (1.0f / 0.45f));
+}
+__device__ __forceinline__ float hill_fp(float lm) {
+  const float e4m1 = 53.598150033144236f;  // e^4 - 1
+  if (lm <= 1.0f) return 0.0f;
+  if (lm <= 1.6f) return (expf((4.0f / 0.6f) * (lm - 1.0f)) - 1.0f) / e4m1;
+  return 1.0f + 6.7910995f * (lm - 1.6f);  // slope (4/0.6) e^4/(e^4-1)
+}
+__device__ __forceinline__ float hill_fv(float vm) {
+  if (vm <= -1.0f) return 0.0f;
+  if (vm <= 0.0f) return (1.0f + vm) / (1.0f - 4.0f * vm);
+  return 1.0f + 0.4f * vm / (vm + 0.08f);
+}
+__device__ __forceinline__ float hill_fv_slope(float vm) {
+  if (vm <= -1.0f) return 0.0f;
+  if (vm <= 0.0f) {
+    float a = 1.0f - 4.0f * vm;
+    return 5.0f / (a * a);
+  }
+  float b = vm + 0.08f;
+  return 0.032f / (b * b);
+}
+
+// Value of v held by lane `src` (uniform), for every lane.
+__device__ __forceinline__ double lane_bcast(double v, int src) {
+  const unsigned long long b = __double_as_longlong(v);
+  const unsigned lo = __builtin_amdgcn_readlane((unsigned)b, src);
+  const unsigned hi = __builtin_amdgcn_readlane((unsigned)(b >> 32), src);
+  return __longlong_as_double(((unsigned long long)hi << 32) | lo);
+}
+
+// Sum over the 64 lanes of a wavefront (butterfly exchange); every lane
+// receives the total.
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// log2 of the lanes per item when n items share a wavefront (n >= 1):
+// the largest power of two P with n P <= 64
+__device__ __forceinline__ int group_log2(int n) {
+  int l = 0;
+  while (l < 6 && (n << (l + 1)) <= 64) ++l;
+  return l;
+}
+
+// sum over aligned groups of 2^lp lanes, fixed butterfly order; every lane of
+// a group gets the same value
+__device__ __forceinline__ double group_sum(double v, int lp) {
+  for (int o = (1 << lp) >> 1; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+// Exact via-point geometry of muscle slot m: path length L, moment arms
+// r[3] = -dL/dq of its span DoFs and Ldot. Path w_0..w_{P-1}; with unit
+// segment vectors e_k, dL/dq_j = sum_k g_k . (a_j x (w_k - o_j)) over the
+// via-points moved by hinge j (g_k = e_{k-1} - e_k), a_j . sum_k g_k for a
+// slide. Pg bounds the via-point loops uniformly across the wavefront.
+template <int NVIA>
+__device__ __forceinline__ float muscle_geometry(const KModel &M, int m, int Pg, const float *Rl,
+                                                 const float *Pl, const float *Sl, const float *qd,
+                                                 V3 O, float r3[3], float &Ld) {
+  const int nm = M.n_mus;
+  const int P = M.mus_nvia[m];
+  V3 w[NVIA], gk[NVIA];
+#pragma unroll
+  for (int k = 0; k < NVIA; ++k) {
+    w[k] = v3(0.f, 0.f, 0.f);
+    if (k < Pg && k < P) {
+      const int b = M.via_node[(size_t)k * nm + m];
+      V3 x = v3(M.via_pos[((size_t)k * 3 + 0) * nm + m], M.via_pos[((size_t)k * 3 + 1) * nm + m],
+                M.via_pos[((size_t)k * 3 + 2) * nm + m]);
+      w[k] = b >= 0 ? frame_apply(Rl + 12 * b, x) : x - O;
+    }
+  }
+  float L = 0.f;
+  V3 eprev = v3(0.f, 0.f, 0.f);
+#pragma unroll
+  for (int k = 0; k < NVIA; ++k) {
+    gk[k] = v3(0.f, 0.f, 0.f);
+    if (k < Pg) {
+      if (k + 1 < P) {
+        V3 d = w[k + 1] - w[k];
+        float l = sqrtf(dot(d, d));
+        L += l;
+        V3 e = (1.0f / l) * d;
+        gk[k] = eprev - e;
+        eprev = e;
+      } else if (k + 1 == P) {
+        gk[k] = eprev;
+      }
+    }
+  }
+  const unsigned mask = M.mus_mask[m];
+  Ld = 0.f;
+#pragma unroll
+  for (int s = 0; s < 3; ++s) {
+    r3[s] = 0.f;
+    const int j = M.mus_span[s * nm + m];
+    if (j >= 0) {
+      const unsigned mk = (mask >> (8 * s)) & 0xFFu;
+      const float *S = Sl + 6 * j;
+      float dl;
+      if (M.dof_kind[j] == 0) {
+        V3 o = ld3(Pl + 12 * M.dof_node[j]);
+        V3 acc = v3(0.f, 0.f, 0.f);
+#pragma unroll
+        for (int k = 0; k < NVIA; ++k)
+          if ((mk >> k) & 1u) acc = acc + cross(w[k] - o, gk[k]);
+        dl = dot(ld3(S), acc);
+      } else {
+        V3 acc = v3(0.f, 0.f, 0.f);
+#pragma unroll
+        for (int k = 0; k < NVIA; ++k)
+          if ((mk >> k) & 1u) acc = acc + gk[k];
+        dl = dot(ld3(S + 3), acc);
+      }
+      r3[s] = -dl;
+      Ld += dl * qd[j];
+    }
+  }
+  return L;
+}
+
+// ------------------------------------------------------------------ kernel
+// One wavefront steps one env n_steps times. SURR: muscle geometry from the
+// surrogate's predictions with the per-env fallback check (a kernel of its
+// own, so the exact kernel carries none of it).
+template <int MPL, int NVIA, bool SURR, bool GEOM>
+__device__ __forceinline__ void step_body(const KModel &M, const KRun &Rn, int n_steps) {
+  extern __shared__ __align__(16) unsigned char lds[];
+  const int env = blockIdx.x;
+  const int lane = threadIdx.x;
+  const int nq = M.nq, nv = M.nv, nm = M.n_mus, nn = M.n_node;
+  float *__restrict__ q = (float *)(lds + M.off_q);
+  float *__restrict__ qd = (float *)(lds + M.off_qd);
+  // node frames: 12 floats per node, 16-byte aligned: R (row-major) then P
+  float *Rl = (float *)(lds + M.off_R);
+  float *Pl = Rl + 9;
+  float *__restrict__ Sl = (float *)(lds + M.off_S);
+  float *Vl = (float *)(lds + M.off_V);
+  float *Al = (float *)(lds + M.off_A);
+  float *Fl = (float *)(lds + M.off_F);  // f_b[n_body][6] then F_n[n_node][6]
+  float *__restrict__ Cl = (float *)(lds + M.off_con);
+  double *__restrict__ rhs = (double *)(lds + M.off_rhs);
+  double *__restrict__ xs = (double *)(lds + M.off_x);
+  double *__restrict__ H = (double *)(lds + M.off_H);
+  unsigned char *scr = lds + M.off_scr;
+  // tree schedule staged in LDS once per launch: level starts, nodes by
+  // level, and per node (jtype | (parent+1) << 2 | dof << 10)
+  int *tlev = (int *)(lds + M.off_tree);
+  int *tnode = tlev + M.n_level + 1;
+  int *tinfo = tnode + nn;
+  for (int l = lane; l <= M.n_level; l += 64) tlev[l] = M.level_start[l];
+  for (int i = lane; i < nn; i += 64) {
+    tnode[i] = M.level_nodes[i];
+    tinfo[i] = M.jtype[i] | ((M.parent[i] + 1) << 2) | (M.dadr[i] << 10);
+  }
+  const float dt = Rn.dt;
+  const int exc = Rn.exc;
+  const bool stages = Rn.stages != 0;
+  constexpr bool geom_only = GEOM;
+
+  for (int i = lane; i < nq; i += 64) q[i] = Rn.q[(size_t)env * nq + i];
+  for (int i = lane; i < nv; i += 64) qd[i] = Rn.qd ? Rn.qd[(size_t)env * nv + i] : 0.0f;
+  float act[MPL], xar[MPL];
+#pragma unroll
+  for (int t = 0; t < MPL; ++t) {
+    int mi = lane + 64 * t;
+    const int mx = mi < nm ? M.mus_ext[mi] : 0;
+    act[t] = (mi < nm && Rn.act) ? Rn.act[(size_t)env * nm + mx] : 0.0f;
+    xar[t] = 0.0f;
+    if (exc == EXC_AR1 && mi < nm) xar[t] = Rn.xar[(size_t)env * nm + mx];
+  }
+  unsigned status = Rn.status ? Rn.status[env] : 0u;
+  __syncthreads();
+
+  for (int step = 0; step < n_steps; ++step) {
+    // ---------------------------------------------- excitation and state check
+    float u[MPL];
+    bool bad = false;
+    for (int i = lane; i < nq; i += 64) bad |= !isfinite(q[i]);
+    for (int i = lane; i < nv; i += 64) bad |= !isfinite(qd[i]);
+    unsigned long long key = 0;
+    if (exc != EXC_ARRAY)
+      key = splitmix64(splitmix64(Rn.seed ^ (unsigned long long)env) ^
+                       (unsigned long long)(Rn.step0 + step));
+#pragma unroll
+    for (int t = 0; t < MPL; ++t) {
+      int mi = lane + 64 * t;
+      u[t] = 0.0f;
+      if (mi < nm) {
+        const int mx = M.mus_ext[mi];
+        bad |= !isfinite(act[t]);
+        if (exc == EXC_ARRAY) {
+          u[t] = Rn.u ? Rn.u[((size_t)step * Rn.n_env + env) * nm + mx] : 0.0f;
+        } else if (exc == EXC_IID) {
+          u[t] = u24(splitmix64(key ^ (unsigned long long)mx), 40);
+        } else {
+          const AR1 r = ar1_step(key, mx, xar[t], Rn.rho, Rn.s, Rn.mean);
+          u[t] = r.u;
+          xar[t] = r.x;
+        }
+      }
+    }
+    if (__any(bad)) {
+      status |= MS_ST_NONFINITE;
+      continue;  // the state stays as it is
+    }
+
+    // --------------------------------------------------- activation dynamics
+    float act1[MPL];
+#pragma unroll
+    for (int t = 0; t < MPL; ++t) {
+      int mi = lane + 64 * t;
+      act1[t] = 0.0f;
+      if (mi < nm) {
+        float uc = fminf(fmaxf(u[t], 0.0f), 1.0f);
+        float a = act[t];
+        float tau = uc > a ? M.mus_tact[mi] * (0.5f + 1.5f * a) : M.mus_tdeact[mi] / (0.5f + 1.5f * a);
+        act1[t] = fminf(fmaxf(a + dt * (uc - a) / tau, 0.0f), 1.0f);
+        if (stages && Rn.o_act) Rn.o_act[(size_t)env * nm + M.mus_ext[mi]] = act1[t];
+      }
+    }
+
+    // ------------------------- forward kinematics, motion subspaces, V and A
+    // O = root origin (floating) or world origin (fixed base).
+    V3 O = M.free_root ? v3(q[0], q[1], q[2]) : v3(0.f, 0.f, 0.f);
+    const V3 g = v3(M.gx, M.gy, M.gz);
+    // (1) every node's joint transform in parallel: rotation jrot Rot(axis, q)
+    // and offset parked in the node's frame slot, the axis jrot*axis in its A
+    // slot; the floating root is finished here
+    for (int i = lane; i < nn; i += 64) {
+      const int jt = M.jtype[i];
+      float *F = Rl + 12 * i;
+      const int da = M.dadr[i];
+      if (jt == 2) {
+        const float *x = q + M.qadr[i] + 3;
+        float nrm = sqrtf(x[0] * x[0] + x[1] * x[1] + x[2] * x[2] + x[3] * x[3]);
+        float w = x[0] / nrm, a = x[1] / nrm, b = x[2] / nrm, c = x[3] / nrm;
+        float *R = F;
+        R[0] = 1 - 2 * (b * b + c * c); R[1] = 2 * (a * b - w * c); R[2] = 2 * (a * c + w * b);
+        R[3] = 2 * (a * b + w * c); R[4] = 1 - 2 * (a * a + c * c); R[5] = 2 * (b * c - w * a);
+        R[6] = 2 * (a * c - w * b); R[7] = 2 * (b * c + w * a); R[8] = 1 - 2 * (a * a + b * b);
+        st3(F + 9, v3(0.f, 0.f, 0.f));
+        for (int kk = 0; kk < 3; ++kk) {
+          float *S = Sl + 6 * (da + kk);
+          S[0] = S[1] = S[2] = 0.f;
+          S[3] = kk == 0; S[4] = kk == 1; S[5] = kk == 2;
+          float *S2 = Sl + 6 * (da + 3 + kk);
+          S2[0] = R[kk]; S2[1] = R[3 + kk]; S2[2] = R[6 + kk];
+          S2[3] = S2[4] = S2[5] = 0.f;
+        }
+        V3 v = ld3(qd + da);
+        V3 ww = mulR(R, ld3(qd + da + 3));
+        float *V = Vl + 6 * i, *A = Al + 6 * i;
+        st3(V, ww);
+        st3(V + 3, v);
+        st3(A, v3(0.f, 0.f, 0.f));
+        st3(A + 3, cross(v, ww) - g);
+        continue;
+      }
+      const float *E = M.jrot + 9 * i;
+      const V3 ax = ld3(M.axis + 3 * i);
+      const float qi = q[M.qadr[i]];
+      const V3 al = mulR(E, ax);
+      V3 t = ld3(M.jpos + 3 * i);
+      if (jt == 0) {
+        float sn, cs;
+        sincosf(qi, &sn, &cs);
+        const float vc = 1.0f - cs;
+        const float Q[9] = {cs + ax.x * ax.x * vc, ax.x * ax.y * vc - ax.z * sn, ax.x * ax.z * vc + ax.y * sn,
+                            ax.y * ax.x * vc + ax.z * sn, cs + ax.y * ax.y * vc, ax.y * ax.z * vc - ax.x * sn,
+                            ax.z * ax.x * vc - ax.y * sn, ax.z * ax.y * vc + ax.x * sn, cs + ax.z * ax.z * vc};
+        for (int r = 0; r < 3; ++r)
+          for (int c = 0; c < 3; ++c)
+            F[3 * r + c] = E[3 * r] * Q[c] + E[3 * r + 1] * Q[3 + c] + E[3 * r + 2] * Q[6 + c];
+      } else {
+        for (int e = 0; e < 9; ++e) F[e] = E[e];
+        t = t + qi * al;
+      }
+      st3(F + 9, t);
+      st3(Al + 6 * i, al);
+    }
+    __syncthreads();
+    // (2) compose down the tree level by level, reading only LDS:
+    // R = R_p Lr, P = P_p + R_p t, axis = R_p al, S, V = V_p + S qd,
+    // A = A_p + V_p x (S qd)
+    for (int l = 0; l < M.n_level; ++l) {
+      const int b0 = tlev[l], b1 = tlev[l + 1];
+      for (int k = b0 + lane; k < b1; k += 64) {
+        const int i = tnode[k];
+        const int info = tinfo[i];
+        const int jt = info & 3;
+        if (jt == 2) continue;
+        const int p = (info >> 2 & 0xFF) - 1, da = info >> 10;
+        float *F = Rl + 12 * i;
+        float Lr[9];
+        for (int e = 0; e < 9; ++e) Lr[e] = F[e];
+        const V3 t = ld3(F + 9);
+        const V3 al = ld3(Al + 6 * i);
+        float Rp[9];
+        V3 Pp, wp, vp, ap, lp;
+        if (p >= 0) {
+          for (int e = 0; e < 9; ++e) Rp[e] = Rl[12 * p + e];
+          Pp = ld3(Pl + 12 * p);
+          wp = ld3(Vl + 6 * p); vp = ld3(Vl + 6 * p + 3);
+          ap = ld3(Al + 6 * p); lp = ld3(Al + 6 * p + 3);
+        } else {
+          for (int e = 0; e < 9; ++e) Rp[e] = (e % 4 == 0) ? 1.f : 0.f;
+          Pp = v3(0.f, 0.f, 0.f) - O;
+          wp = vp = ap = v3(0.f, 0.f, 0.f);
+          lp = v3(0.f, 0.f, 0.f) - g;
+        }
+        for (int r = 0; r < 3; ++r)
+          for (int c = 0; c < 3; ++c)
+            F[3 * r + c] = Rp[3 * r] * Lr[c] + Rp[3 * r + 1] * Lr[3 + c] + Rp[3 * r + 2] * Lr[6 + c];
+        const V3 Pi = Pp + mulR(Rp, t);
+        const V3 ah = mulR(Rp, al);
+        st3(F + 9, Pi);
+        V3 sw, sv;
+        if (jt == 0) {
+          sw = ah;
+          sv = cross(Pi, ah);
+        } else {
+          sw = v3(0.f, 0.f, 0.f);
+          sv = ah;
+        }
+        float *S = Sl + 6 * da;
+        st3(S, sw);
+        st3(S + 3, sv);
+        const float qdi = qd[da];
+        const V3 xw = qdi * sw, xv = qdi * sv;  // S qd
+        float *V = Vl + 6 * i, *A = Al + 6 * i;
+        st3(V, wp + xw);
+        st3(V + 3, vp + xv);
+        st3(A, ap + cross(wp, xw));
+        st3(A + 3, lp + cross(wp, xv) + cross(vp, xw));
+      }
+      __syncthreads();
+    }
+
+    if (!geom_only) {
+    // ------------------------------------------------------------- contacts
+    for (int c = lane; c < M.n_con; c += 64) {
+      float *C = Cl + 16 * c;
+      const int b = M.con_node[c];
+      V3 w = frame_apply(Rl + 12 * b, ld3(M.con_pos + 3 * c));
+      const float rho = M.con_radius[c];
+      const float pen = rho - (w.z + O.z);
+      for (int e = 0; e < 16; ++e) C[e] = 0.f;
+      if (Rn.contact && pen > 0.f) {
+        V3 cp = w - v3(0.f, 0.f, rho);
+        V3 vel = ld3(Vl + 6 * b + 3) + cross(ld3(Vl + 6 * b), cp);
+        // spring taken linearly implicitly over the step: damping c + dt k
+        const float ceff = M.cc + dt * M.kc;
+        float fn = fmaxf(0.f, M.kc * pen - ceff * vel.z);
+        float s2 = vel.x * vel.x + vel.y * vel.y + M.vs * M.vs;
+        float s = sqrtf(s2);
+        V3 f = v3(-M.mu * fn * vel.x / s, -M.mu * fn * vel.y / s, fn);
+        C[0] = 1.f;
+        st3(C + 1, cp);
+        st3(C + 4, cross(cp, f));
+        st3(C + 7, f);
+        if (fn > 0.f) {
+          float gg = M.mu * fn / s;
+          C[10] = gg * (1.f - vel.x * vel.x / s2);
+          C[11] = -gg * vel.x * vel.y / s2;
+          C[12] = gg * (1.f - vel.y * vel.y / s2);
+          C[13] = ceff;
+        }
+      }
+    }
+
+    // ------------------------------------- recursive Newton-Euler bias forces
+    for (int b = lane; b < M.n_body; b += 64) {
+      const int i = M.body_node[b];
+      const float *R = Rl + 12 * i;
+      const float m = M.body_mass[b];
+      V3 c = mulR(R, ld3(M.body_com + 3 * b)) + ld3(Pl + 12 * i);
+      V3 h = m * c;
+      const float I0 = M.body_inertia[3 * b], I1 = M.body_inertia[3 * b + 1], I2 = M.body_inertia[3 * b + 2];
+      // I_O = R diag(I) R^T + m (|c|^2 1 - c c^T)
+      float Io[9];
+      const float cc = dot(c, c);
+      const float cv[3] = {c.x, c.y, c.z};
+      for (int r = 0; r < 3; ++r)
+        for (int s = 0; s < 3; ++s)
+          Io[3 * r + s] = R[3 * r] * I0 * R[3 * s] + R[3 * r + 1] * I1 * R[3 * s + 1] +
+                          R[3 * r + 2] * I2 * R[3 * s + 2] + m * ((r == s ? cc : 0.f) - cv[r] * cv[s]);
+      V3 w = ld3(Vl + 6 * i), v = ld3(Vl + 6 * i + 3);
+      V3 aw = ld3(Al + 6 * i), al = ld3(Al + 6 * i + 3);
+      // I (w; v) = (I_O w + h x v; m v - h x w)
+      V3 Iaw = mulR(Io, aw) + cross(h, al), Ial = m * al - cross(h, aw);
+      V3 Ivw = mulR(Io, w) + cross(h, v), Ivl = m * v - cross(h, w);
+      // f = I a + v x* (I v), (w, v) x* (n, f) = (w x n + v x f, w x f)
+      V3 fw = Iaw + cross(w, Ivw) + cross(v, Ivl);
+      V3 fl = Ial + cross(w, Ivl);
+      st3(Fl + 6 * b, fw);
+      st3(Fl + 6 * b + 3, fl);
+    }
+    __syncthreads();
+    float *Fn = Fl + 6 * M.n_body;
+    for (int t = lane; t < 6 * nn; t += 64) {
+      const int n = t / 6, k = t % 6;
+      float s = 0.f;
+      for (int e = M.subb_start[n]; e < M.subb_start[n + 1]; ++e) s += Fl[6 * M.subb[e] + k];
+      for (int e = M.subc_start[n]; e < M.subc_start[n + 1]; ++e) s -= Cl[16 * M.subc[e] + 4 + k];
+      Fn[t] = s;
+    }
+    __syncthreads();
+    for (int j = lane; j < nv; j += 64) {
+      const float *S = Sl + 6 * j;
+      const float *F = Fn + 6 * M.dof_node[j];
+      float cb = S[0] * F[0] + S[1] * F[1] + S[2] * F[2] + S[3] * F[3] + S[4] * F[4] + S[5] * F[5];
+      if (stages) Rn.o_bias[(size_t)env * nv + j] = cb;
+      rhs[j] = (double)(-cb - M.damping[j] * qd[j]);
+    }
+    __syncthreads();
+
+    // ---------------------------------- composite-rigid-body mass matrix (FP64)
+    {
+      double *BI = (double *)scr;                  // [n_body][10]: m, h, I_O (xx xy xz yy yz zz)
+      double *CI = BI + 10 * M.n_body;             // [n_node][10]
+      double *FJ = CI + 10 * nn;                   // [nv][6]
+      for (int b = lane; b < M.n_body; b += 64) {
+        const int i = M.body_node[b];
+        const float *R = Rl + 12 * i;
+        const double m = M.body_mass[b];
+        V3 cf = mulR(R, ld3(M.body_com + 3 * b)) + ld3(Pl + 12 * i);
+        const double c[3] = {cf.x, cf.y, cf.z};
+        const double In[3] = {M.body_inertia[3 * b], M.body_inertia[3 * b + 1], M.body_inertia[3 * b + 2]};
+        double *o = BI + 10 * b;
+        o[0] = m;
+        o[1] = m * c[0]; o[2] = m * c[1]; o[3] = m * c[2];
+        const double cc = c[0] * c[0] + c[1] * c[1] + c[2] * c[2];
+        const int rr[6] = {0, 0, 0, 1, 1, 2}, ss[6] = {0, 1, 2, 1, 2, 2};
+        for (int e = 0; e < 6; ++e) {
+          int r = rr[e], s = ss[e];
+          double v = (double)R[3 * r] * In[0] * R[3 * s] + (double)R[3 * r + 1] * In[1] * R[3 * s + 1] +
+                     (double)R[3 * r + 2] * In[2] * R[3 * s + 2];
+          o[4 + e] = v + m * ((r == s ? cc : 0.0) - c[r] * c[s]);
+        }
+      }
+      __syncthreads();
+      for (int t = lane; t < 10 * nn; t += 64) {
+        const int n = t / 10, k = t % 10;
+        double s = 0.0;
+        for (int e = M.subb_start[n]; e < M.subb_start[n + 1]; ++e) s += BI[10 * M.subb[e] + k];
+        CI[t] = s;
+      }
+      __syncthreads();
+      for (int j = lane; j < nv; j += 64) {
+        const int n = M.dof_node[j];
+        const double *I = CI + 10 * n;
+        const float *Sf = Sl + 6 * j;
+        const double w[3] = {Sf[0], Sf[1], Sf[2]}, v[3] = {Sf[3], Sf[4], Sf[5]};
+        const double m = I[0], h[3] = {I[1], I[2], I[3]};
+        const double Io[9] = {I[4], I[5], I[6], I[5], I[7], I[8], I[6], I[8], I[9]};
+        double f[6];
+        // (I_O w + h x v ; m v - h x w)
+        f[0] = Io[0] * w[0] + Io[1] * w[1] + Io[2] * w[2] + (h[1] * v[2] - h[2] * v[1]);
+        f[1] = Io[3] * w[0] + Io[4] * w[1] + Io[5] * w[2] + (h[2] * v[0] - h[0] * v[2]);
+        f[2] = Io[6] * w[0] + Io[7] * w[1] + Io[8] * w[2] + (h[0] * v[1] - h[1] * v[0]);
+        f[3] = m * v[0] - (h[1] * w[2] - h[2] * w[1]);
+        f[4] = m * v[1] - (h[2] * w[0] - h[0] * w[2]);
+        f[5] = m * v[2] - (h[0] * w[1] - h[1] * w[0]);
+        // implicit contact damping: dt * Phi^T D Phi S for contacts below
+        for (int e = M.subc_start[n]; e < M.subc_start[n + 1]; ++e) {
+          const float *C = Cl + 16 * M.subc[e];
+          if (C[0] == 0.f) continue;
+          const double cp[3] = {C[1], C[2], C[3]};
+          // point velocity of the contact for unit qd_j: v + w x cp
+          const double J[3] = {v[0] + w[1] * cp[2] - w[2] * cp[1], v[1] + w[2] * cp[0] - w[0] * cp[2],
+                               v[2] + w[0] * cp[1] - w[1] * cp[0]};
+          const double u0 = (double)C[10] * J[0] + (double)C[11] * J[1];
+          const double u1 = (double)C[11] * J[0] + (double)C[12] * J[1];
+          const double u2 = (double)C[13] * J[2];
+          const double dd = dt;
+          f[0] += dd * (cp[1] * u2 - cp[2] * u1);
+          f[1] += dd * (cp[2] * u0 - cp[0] * u2);
+          f[2] += dd * (cp[0] * u1 - cp[1] * u0);
+          f[3] += dd * u0;
+          f[4] += dd * u1;
+          f[5] += dd * u2;
+        }
+        for (int k = 0; k < 6; ++k) FJ[6 * j + k] = f[k];
+      }
+      __syncthreads();
+      for (int e = lane; e < M.nnz; e += 64) {
+        const int j = M.nnz_row[e], i = M.path[e];
+        const float *Sf = Sl + 6 * i;
+        const double *f = FJ + 6 * j;
+        double h = (double)Sf[0] * f[0] + (double)Sf[1] * f[1] + (double)Sf[2] * f[2] +
+                   (double)Sf[3] * f[3] + (double)Sf[4] * f[4] + (double)Sf[5] * f[5];
+        if (i == j) h += (double)dt * M.damping[j];
+        H[e] = h;
+      }
+      __syncthreads();
+    }
+
+    }  // !geom_only
+    // --------------------------- muscle geometry, Hill force, J_m^T F, damping
+    {
+      float *mr = (float *)scr;          // [n_mus][3]
+      float *mF = mr + 3 * nm;           // [n_mus]
+      float *mc = mF + nm;               // [n_mus]
+      // surrogate geometry (when predictions are given): an env falls back to
+      // the exact geometry when a hinge leaves the training box or when the
+      // prediction misses the exact length of one of 32 sentinel muscles,
+      // rotated each step, by more than the tolerance. One wavefront is one
+      // env, so the decision is uniform.
+      bool exact = true;
+      if (SURR) {
+        const float *Y = Rn.geomY + (size_t)env * 4 * nm;
+        bool out = false;
+        for (int i = lane; i < nn; i += 64) {
+          if (M.jtype[i] == 2) continue;
+          const int j = M.dadr[i];
+          const float qi = q[M.qadr[i]];
+          out |= !(qi >= M.qlo[j] && qi <= M.qhi[j]);
+        }
+        bool miss = false;
+        const int ns = nm < 32 ? nm : 32;
+        if (lane < ns) {
+          const int mx = (int)((32ll * (Rn.step0 + step) + lane) % nm);
+          const int m = M.mus_int[mx];
+          float r3[3], Ld;
+          const float L = muscle_geometry<NVIA>(M, m, NVIA, Rl, Pl, Sl, qd, O, r3, Ld);
+          miss = !(fabsf(Y[mx] - L) <= Rn.fb_tol);
+        }
+        exact = __any(out) || __any(miss);
+        if (exact) {
+          status |= MS_ST_FALLBACK;
+          if (Rn.fb_count && lane == 0) Rn.fb_count[env] += 1u;
+        } else {
+          for (int m = lane; m < nm; m += 64) {
+            const int mx = M.mus_ext[m];
+            float Ld = 0.f;
+#pragma unroll
+            for (int sl = 0; sl < 3; ++sl) {
+              const int j = M.mus_span[sl * nm + m];
+              const float r = j >= 0 ? Y[nm + 3 * mx + sl] : 0.f;
+              mr[3 * m + sl] = r;
+              if (j >= 0) Ld -= r * qd[j];
+            }
+            mF[m] = Y[mx];
+            mc[m] = Ld;
+          }
+        }
+      }
+      // exact geometry: one muscle per lane and iteration (L, Ldot parked
+      // in mF, mc)
+#pragma unroll 1
+      for (int m = lane; exact && m < nm; m += 64) {
+        float r3[3], Ld;
+        const float L = muscle_geometry<NVIA>(M, m, M.grp_nvia[m >> 6], Rl, Pl, Sl, qd, O, r3, Ld);
+        mr[3 * m] = r3[0];
+        mr[3 * m + 1] = r3[1];
+        mr[3 * m + 2] = r3[2];
+        mF[m] = L;
+        mc[m] = Ld;
+        if (stages) {
+          const size_t o = (size_t)env * nm + M.mus_ext[m];
+          Rn.o_L[o] = L;
+          if (Rn.o_Ldot) Rn.o_Ldot[o] = Ld;
+          Rn.o_r[3 * o] = r3[0];
+          Rn.o_r[3 * o + 1] = r3[1];
+          Rn.o_r[3 * o + 2] = r3[2];
+        }
+      }
+      if (geom_only) return;
+      // Hill force and its velocity slope (the same lane re-reads its muscles)
+#pragma unroll
+      for (int t = 0; t < MPL; ++t) {
+        const int m = lane + 64 * t;
+        if (m >= nm) continue;
+        const float L = mF[m], Ld = mc[m];
+        const float lm = (L - M.mus_lslack[m]) * M.mus_ilopt[m];
+        const float vm = Ld * M.mus_ivl[m];
+        const float fl = hill_fl(lm), fv = hill_fv(vm), fp = hill_fp(lm);
+        const float f0 = M.mus_f0[m];
+        const float F = f0 * (act1[t] * fl * fv + fp);
+        const float cdamp = f0 * act1[t] * fl * hill_fv_slope(vm) * M.mus_ivl[m];
+        mF[m] = F;
+        mc[m] = cdamp;
+        if (stages) Rn.o_F[(size_t)env * nm + M.mus_ext[m]] = F;
+      }
+      __syncthreads();
+      for (int j = lane; j < nv; j += 64) {
+        float tau = 0.f;
+        for (int e = M.proj_start[j]; e < M.proj_start[j + 1]; ++e) {
+          const int it = M.proj_item[e];
+          tau += mr[it] * mF[it / 3];
+        }
+        if (stages) Rn.o_tau[(size_t)env * nv + j] = tau;
+        rhs[j] += (double)tau;
+      }
+      for (int e = lane; e < M.n_dent; e += 64) {
+        double s = 0.0;
+        for (int k = M.dent_start[e]; k < M.dent_start[e + 1]; ++k) {
+          const int it = M.dent_item[k];
+          const int m = it >> 4, a = (it >> 2) & 3, b = it & 3;
+          s += (double)mc[m] * (double)mr[3 * m + a] * (double)mr[3 * m + b];
+        }
+        H[M.dent_h[e]] += (double)dt * s;
+      }
+      __syncthreads();
+    }
+    if (stages) {
+      for (int e = lane; e < M.nnz; e += 64) Rn.o_H[(size_t)env * M.nnz + e] = H[e];
+    }
+
+    // ------------------------------------------------ LTDL factorisation (FP64)
+    // H = L^T D L with Featherstone's branch-induced sparsity, as gathers:
+    // finished row k holds H_kj - sum over the descendants i of k of
+    // H_ik H_ij / d_i (j = k or an ancestor of k), and reads only finished
+    // rows of lower height. Rows of equal height are independent, so a
+    // height level is one pass over its entries; when a level has few
+    // entries, P lanes split each entry's sum (fixed-order butterfly).
+    bool nonspd = false;
+    double *invd = (double *)scr;  // 1/d per DoF (the muscle scratch is free now)
+    for (int h = 0; h < M.n_hlev; ++h) {
+      if (h > 0) {  // leaves have no descendants
+        const int s0 = M.hent_start[h], ne = M.hent_start[h + 1] - s0;
+        const int lp = group_log2(ne), P = 1 << lp;
+        for (int base = 0; base < (ne << lp); base += 64) {
+          const int idx = base + lane, g = idx >> lp, p = idx & (P - 1);
+          double sum = 0.0;
+          int e = 0;
+          if (g < ne) {
+            const int2 w = M.hent[s0 + g];
+            e = w.x & 0xFFFF;
+            const int ck = (w.x >> 16) & 0xFF, cj = (w.x >> 24) & 0xFF;
+            const int t1 = w.y >> 16;
+#pragma unroll 4
+            for (int t = (w.y & 0xFFFF) + p; t < t1; t += P) {
+              const int di = M.desc[t];
+              const int ri = di & 0xFFFF;
+              sum += H[ri + ck] * H[ri + cj] * invd[di >> 16];
+            }
+          }
+          sum = group_sum(sum, lp);
+          if (g < ne && p == 0) H[e] -= sum;
+        }
+        __syncthreads();
+      }
+      bool bad = false;
+      for (int e = M.hlev_start[h] + lane; e < M.hlev_start[h + 1]; e += 64) {
+        const int k = M.hlev_dof[e];
+        const double d = H[M.row_start[k] + M.dof_depth[k] - 1];
+        bad |= !(d > 0.0);
+        invd[k] = 1.0 / d;
+      }
+      if (__any(bad)) {
+        nonspd = true;
+        break;
+      }
+      __syncthreads();
+    }
+    if (!nonspd) {
+      // L^T y = rhs, leaves first: y_k = rhs_k - sum_{i desc. of k} (H_ik / d_i) y_i
+      for (int h = 0; h < M.n_hlev; ++h) {
+        const int s0 = M.hlev_start[h], ne = M.hlev_start[h + 1] - s0;
+        const int lp = group_log2(ne), P = 1 << lp;
+        for (int base = 0; base < (ne << lp); base += 64) {
+          const int idx = base + lane, g = idx >> lp, p = idx & (P - 1);
+          double sum = 0.0;
+          int k = 0;
+          if (g < ne) {
+            const int2 w = M.hsol[s0 + g];
+            k = w.x & 0xFFFF;
+            const int ck = w.x >> 16, t1 = w.y >> 16;
+#pragma unroll 4
+            for (int t = (w.y & 0xFFFF) + p; t < t1; t += P) {
+              const int di = M.desc[t];
+              const int i = di >> 16;
+              sum += H[(di & 0xFFFF) + ck] * invd[i] * xs[i];
+            }
+          }
+          sum = group_sum(sum, lp);
+          if (g < ne && p == 0) xs[k] = rhs[k] - sum;
+        }
+        __syncthreads();
+      }
+      for (int j = lane; j < nv; j += 64) xs[j] *= invd[j];
+      __syncthreads();
+      // L x = z, root first: x_k = z_k - (1/d_k) sum_{a anc. of k} H_ka x_a
+      for (int dl = 1; dl < M.n_dlev; ++dl) {
+        const int s0 = M.dlev_start[dl], ne = M.dlev_start[dl + 1] - s0;
+        const int lp = group_log2(ne), P = 1 << lp;
+        for (int base = 0; base < (ne << lp); base += 64) {
+          const int idx = base + lane, g = idx >> lp, p = idx & (P - 1);
+          double sum = 0.0;
+          int k = 0;
+          if (g < ne) {
+            const int w = M.dsol[s0 + g];
+            k = w & 0xFF;
+            const int rk = w >> 8;
+#pragma unroll 4
+            for (int a = p; a < dl; a += P) sum += H[rk + a] * xs[M.path[rk + a]];
+          }
+          sum = group_sum(sum, lp);
+          if (g < ne && p == 0) xs[k] -= sum * invd[k];
+        }
+        __syncthreads();
+      }
+    }
+
+    // ----------------------------------------------- semi-implicit Euler update
+    if (stages) {
+      for (int j = lane; j < nv; j += 64) Rn.o_qdd[(size_t)env * nv + j] = nonspd ? NAN : (float)xs[j];
+      break;
+    }
+    if (nonspd) {
+      status |= MS_ST_NONSPD;
+      continue;
+    }
+    // new velocities and hinge/slide positions in registers, checked first
+    float qdn[2], qn[2];
+    bool badn = false;
+    for (int t = 0; t < 2; ++t) {
+      const int j = lane + 64 * t;
+      qdn[t] = 0.f;
+      qn[t] = 0.f;
+      if (j < nv) {
+        qdn[t] = qd[j] + dt * (float)xs[j];
+        badn |= !isfinite(qdn[t]);
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < MPL; ++t) badn |= !isfinite(act1[t]);
+    badn = __any(badn);
+    if (badn) {
+      status |= MS_ST_NONFINITE;
+      continue;
+    }
+    __syncthreads();
+    for (int t = 0; t < 2; ++t) {
+      const int j = lane + 64 * t;
+      if (j < nv) qd[j] = qdn[t];
+    }
+    __syncthreads();
+    // positions: each node's q from its own DoFs
+    for (int i = lane; i < nn; i += 64) {
+      const int a = M.qadr[i], d = M.dadr[i];
+      if (M.jtype[i] != 2) {
+        qn[0] = q[a] + dt * qd[d];
+        q[a] = qn[0];
+        continue;
+      }
+      for (int k = 0; k < 3; ++k) q[a + k] = q[a + k] + dt * qd[d + k];
+      float th[3] = {qd[d + 3] * dt, qd[d + 4] * dt, qd[d + 5] * dt};
+      float ang = sqrtf(th[0] * th[0] + th[1] * th[1] + th[2] * th[2]);
+      float dq[4];
+      if (ang < 1e-8f) {
+        dq[0] = 1.f; dq[1] = 0.5f * th[0]; dq[2] = 0.5f * th[1]; dq[3] = 0.5f * th[2];
+      } else {
+        float sn, cs;
+        sincosf(0.5f * ang, &sn, &cs);
+        float sc = sn / ang;
+        dq[0] = cs; dq[1] = sc * th[0]; dq[2] = sc * th[1]; dq[3] = sc * th[2];
+      }
+      float *x = q + a + 3;
+      float o0 = x[0] * dq[0] - x[1] * dq[1] - x[2] * dq[2] - x[3] * dq[3];
+      float o1 = x[0] * dq[1] + x[1] * dq[0] + x[2] * dq[3] - x[3] * dq[2];
+      float o2 = x[0] * dq[2] - x[1] * dq[3] + x[2] * dq[0] + x[3] * dq[1];
+      float o3 = x[0] * dq[3] + x[1] * dq[2] - x[2] * dq[1] + x[3] * dq[0];
+      float nrm = sqrtf(o0 * o0 + o1 * o1 + o2 * o2 + o3 * o3);
+      x[0] = o0 / nrm; x[1] = o1 / nrm; x[2] = o2 / nrm; x[3] = o3 / nrm;
+    }
+#pragma unroll
+    for (int t = 0; t < MPL; ++t) act[t] = act1[t];
+    __syncthreads();
+  }
+
+  if (stages) return;
+  for (int i = lane; i < nq; i += 64) Rn.q[(size_t)env * nq + i] = q[i];
+  for (int i = lane; i < nv; i += 64) Rn.qd[(size_t)env * nv + i] = qd[i];
+#pragma unroll
+  for (int t = 0; t < MPL; ++t) {
+    const int mi = lane + 64 * t;
+    if (mi < nm) {
+      const int mx = M.mus_ext[mi];
+      Rn.act[(size_t)env * nm + mx] = act[t];
+      if (exc == EXC_AR1) Rn.xar[(size_t)env * nm + mx] = xar[t];
+    }
+  }
+  if (Rn.status && lane == 0) Rn.status[env] = status;
+}
+
+template <int MPL, int NVIA>
+__global__ __launch_bounds__(64) void k_step(KModel M, KRun Rn, int n_steps) {
+  step_body<MPL, NVIA, false, false>(M, Rn, n_steps);
+}
+
+template <int MPL, int NVIA>
+__global__ __launch_bounds__(64) void k_step_surrogate(KModel M, KRun Rn, int n_steps) {
+  step_body<MPL, NVIA, true, false>(M, Rn, n_steps);
+}
+
+// exact muscle geometry only (L, Ldot, r as stage outputs)
+template <int MPL, int NVIA>
+__global__ __launch_bounds__(64) void k_geometry(KModel M, KRun Rn, int n_steps) {
+  step_body<MPL, NVIA, false, true>(M, Rn, n_steps);
+}
+
+template <int MPL, int NVIA>
+hipError_t launch_k(const Tables &t, const KModel &k, const KRun &r, int n_env, int n_steps,
+                    hipStream_t st) {
+  const bool geom = r.stages == 2, surr = r.geomY != nullptr;
+  const void *fn = geom ? (const void *)&k_geometry<MPL, NVIA>
+                   : surr ? (const void *)&k_step_surrogate<MPL, NVIA>
+                          : (const void *)&k_step<MPL, NVIA>;
+  if (t.lds_bytes > 65536) {
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, t.lds_bytes);
+    if (e != hipSuccess) return e;
+  }
+  const dim3 grid(n_env), block(64);
+  if (geom)
+    hipLaunchKernelGGL((k_geometry<MPL, NVIA>), grid, block, t.lds_bytes, st, k, r, n_steps);
+  else if (surr)
+    hipLaunchKernelGGL((k_step_surrogate<MPL, NVIA>), grid, block, t.lds_bytes, st, k, r, n_steps);
+  else
+    hipLaunchKernelGGL((k_step<MPL, NVIA>), grid, block, t.lds_bytes, st, k, r, n_steps);
+  return hipGetLastError();
+}
+
+template <int NVIA>
+hipError_t launch_nvia(const Tables &t, const KModel &k, const KRun &r, int n_env, int n_steps,
+                       hipStream_t st) {
+  const int mpl = t.mpl;
+  if (mpl <= 1) return launch_k<1, NVIA>(t, k, r, n_env, n_steps, st);
+  if (mpl <= 2) return launch_k<2, NVIA>(t, k, r, n_env, n_steps, st);
+  if (mpl <= 4) return launch_k<4, NVIA>(t, k, r, n_env, n_steps, st);
+  if (mpl <= 8) return launch_k<8, NVIA>(t, k, r, n_env, n_steps, st);
+  if (mpl <= 12) return launch_k<12, NVIA>(t, k, r, n_env, n_steps, st);
+  return launch_k<16, NVIA>(t, k, r, n_env, n_steps, st);
+}
+
+}  // namespace ms

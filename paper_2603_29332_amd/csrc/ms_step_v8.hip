@@ -1,0 +1,7 @@
+// ms_step_v8.hip -- step kernels for models with at most 8 via-points per
+// muscle (one translation unit per via-point bound, compiled in parallel).
+#include "ms_step_kernel.h"
+
+namespace ms {
+template hipError_t launch_nvia<8>(const Tables &, const KModel &, const KRun &, int, int, hipStream_t);
+}  // namespace ms

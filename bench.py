@@ -29,6 +29,12 @@ PHYS_PER_STEP = 100
 # MI355X: 256 CUs x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz, one FP32 or
 # FP64 vector FMA per lane and cycle (packed FP32 would double FP32 only).
 PEAK_VALU_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+# HBM bytes of one 100-step k_step rollout launch on this workload, from
+# rocprofv3 FETCH_SIZE and WRITE_SIZE scaled by a plain copy of known size
+# (profiles/k_step_human80_4096_traffic.md), valid for the kernel source with
+# this SHA-256 prefix only (reported as null otherwise).
+TRAFFIC_BYTES_PER_LAUNCH = 55.7e6
+TRAFFIC_KERNEL_SHA = "531cf6bdc14dc859"
 
 
 def parse():
@@ -44,6 +50,9 @@ def parse():
                    help="Adam iterations (batch 8192) before the surrogate leg is timed")
     p.add_argument("--surrogate-tol", type=float, default=1e-4,
                    help="sentinel length residual (m) above which an env falls back")
+    p.add_argument("--calib-copy-mib", type=int, default=0,
+                   help="first run one plain device copy of this many MiB (a known-size "
+                        "reference for hardware traffic counters)")
     return p.parse_args()
 
 
@@ -71,6 +80,12 @@ def main():
                 torch.zeros(E, dtype=torch.int32, device=dev),
                 torch.zeros(E, m["n_mus"], device=dev))
 
+    if a.calib_copy_mib > 0:
+        src = torch.ones(a.calib_copy_mib * 2**18, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     q, qd, act, st, x = fresh()
     stream = torch.cuda.current_stream()
     init = tuple(torch.tensor(v, device=dev) for v in (q0, qd0, act0))
@@ -128,7 +143,7 @@ def main():
                    "geometry": "exact", "precision": "FP32, FP64 mass matrix + LTDL solve"},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_VALU_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_VALU_TFLOPS,
-                     "traffic": None,
+                     "traffic": measured_traffic(),
                      "kernel": "k_step (ms_rollout)", "avg_launch_ms": avg_launch_s * 1e3,
                      "flop_per_env_step": {"fp32": fp32, "fp64": fp64}},
         "step_batch": {"ms_per_physics_step": sb_ms, "env_steps_per_s": E / (sb_ms / 1e3),
@@ -146,6 +161,14 @@ def main():
         line["rad_err_vs_fp64"] = rad_error(m, gm, dt, dev)
         line["cpu_baseline"] = cpu_baseline(m, dt, a.cpu_seconds)
     print(json.dumps(line), flush=True)
+
+
+def measured_traffic():
+    import hashlib
+    src = os.path.join(ROOT, "paper_2603_29332_amd", "csrc", "ms_step_kernel.h")
+    with open(src, "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()[:16]
+    return TRAFFIC_BYTES_PER_LAUNCH if sha == TRAFFIC_KERNEL_SHA else None
 
 
 def reset_flagged(q, qd, act, st, x, init, count):

@@ -232,6 +232,52 @@ ms_status ms_surrogate_train_step(ms_surrogate *s, int32_t n, const float *q,
                                   int32_t step, float *loss, void *stream);
 const char *ms_surrogate_last_error(void);
 
+/* ------------------------------------------------------------------------
+ * Uneven batches: envs of several models (different sizes) stepped in one
+ * call. Not a passage of the paper: the batched-rollout setting of its
+ * Methods (many environments at once, Simulation throughput) with models of
+ * different sizes in one batch.
+ *
+ * Each model's envs keep their own caller-owned state (layouts as for
+ * ms_rollout) and excitation descriptor. One call steps every model's envs
+ * n_steps times: each model's fused step kernel runs on an internal stream
+ * forked from `stream` and joined back; outside an active capture the
+ * fork/join is recorded once as a HIP graph per argument set (state and
+ * excitation pointers and values, n_steps, opts, configuration) and
+ * replayed. Inside a caller's stream capture the launches are simply issued.
+ * Results are bitwise those of ms_rollout on each model alone, for any
+ * configuration. A batch is not thread-safe; its models must not be used on
+ * other streams during a call. */
+typedef struct ms_batch ms_batch;
+typedef struct {
+  float *q, *qd, *act; /* device, [n_env][nq], [n_env][nv], [n_env][n_mus] */
+  uint32_t *status;    /* device [n_env], may be NULL */
+} ms_batch_state;
+/* models[n_models] stay owned by the caller and must outlive the batch. */
+ms_status ms_batch_create(ms_model *const *models, const int32_t *n_env,
+                          int32_t n_models, ms_batch **out);
+void ms_batch_destroy(ms_batch *b);
+/* states[n_models], exc[n_models] (host arrays of descriptors). */
+ms_status ms_batch_rollout(ms_batch *b, const ms_batch_state *states,
+                           const ms_excitation *exc, int32_t n_steps,
+                           const ms_step_opts *opts, void *stream);
+/* Autotuner: per model alone, probe rollouts of n_probe steps for 1, 2 and 4
+ * envs per workgroup (each env is one wavefront with its own LDS block); then
+ * the whole batch with models issued in the caller's order and most-work
+ * first. Probes run on scratch copies of the given states (left unchanged);
+ * the fastest choices are kept in the batch. Synchronises `stream`. */
+ms_status ms_batch_autotune(ms_batch *b, const ms_batch_state *states,
+                            const ms_excitation *exc, int32_t n_probe,
+                            const ms_step_opts *opts, void *stream);
+/* Current configuration: env_per_wg[n_models], *largest_first (0/1). */
+ms_status ms_batch_config(const ms_batch *b, int32_t *env_per_wg,
+                          int32_t *largest_first);
+/* Set it by hand (env_per_wg in {1, 2, 4}); MS_E_UNSUPPORTED if a
+ * workgroup's LDS would exceed 160 KiB. */
+ms_status ms_batch_set_config(ms_batch *b, const int32_t *env_per_wg,
+                              int32_t largest_first);
+const char *ms_batch_last_error(void);
+
 /* ms_rollout with the muscle geometry predicted by the surrogate: each step
  * runs the network on every env's pose, then the step, in which an env
  * falls back to the exact geometry (MS_ST_FALLBACK, fallback_count[env]++

@@ -15,13 +15,6 @@
 
 
 // =============================================================== host / ABI
-struct ms_model {
-  ms::Tables t;
-  ms::KModel k;
-  void *dbuf = nullptr;
-  size_t dbytes = 0;
-};
-
 void ms_surrogate_tables(const ms_model *m, std::vector<int> *q_index, std::vector<float> *lo,
                          std::vector<float> *hi) {
   const ms::Tables &t = m->t;
@@ -52,6 +45,13 @@ struct Packer {
   }
 };
 
+ms_status check_opts(const ms_step_opts *o) {
+  if (!o) return fail(MS_E_ARG, "opts is NULL");
+  if (!(o->dt > 0.0f) || !std::isfinite(o->dt)) return fail(MS_E_ARG, "dt must be positive and finite");
+  return MS_OK;
+}
+}  // namespace
+
 hipError_t launch(const ms_model *m, const ms::KRun &r, int n_env, int n_steps, hipStream_t st) {
   const int nvia = m->t.n_via_max;
   if (nvia <= 2) return ms::launch_nvia<2>(m->t, m->k, r, n_env, n_steps, st);
@@ -59,13 +59,6 @@ hipError_t launch(const ms_model *m, const ms::KRun &r, int n_env, int n_steps, 
   if (nvia <= 6) return ms::launch_nvia<6>(m->t, m->k, r, n_env, n_steps, st);
   return ms::launch_nvia<8>(m->t, m->k, r, n_env, n_steps, st);
 }
-
-ms_status check_opts(const ms_step_opts *o) {
-  if (!o) return fail(MS_E_ARG, "opts is NULL");
-  if (!(o->dt > 0.0f) || !std::isfinite(o->dt)) return fail(MS_E_ARG, "dt must be positive and finite");
-  return MS_OK;
-}
-}  // namespace
 
 extern "C" {
 
@@ -159,7 +152,7 @@ ms_status ms_model_create(const ms_model_desc *desc, ms_model **out) {
 #undef P_
   k.off_flag = t.off_flag; k.off_q = t.off_q; k.off_qd = t.off_qd; k.off_R = t.off_R;
   k.off_P = t.off_P; k.off_S = t.off_S; k.off_con = t.off_con; k.off_rhs = t.off_rhs;
-  k.off_x = t.off_x; k.off_H = t.off_H; k.off_scr = t.off_scr; k.off_V = t.off_V;
+  k.off_x = t.off_x; k.off_H = t.off_H; k.off_scr = t.off_scr; k.lds_env = t.lds_bytes; k.off_V = t.off_V;
   k.off_A = t.off_A; k.off_F = t.off_F; k.off_tree = t.off_tree;
   *out = m;
   return MS_OK;
@@ -225,6 +218,14 @@ ms_status ms_step_batch(ms_model *m, int32_t n_env, float *q, float *qd, float *
 ms_status ms_rollout(ms_model *m, int32_t n_env, float *q, float *qd, float *act,
                      uint32_t *status, const ms_excitation *exc, int32_t n_steps,
                      const ms_step_opts *opts, void *stream) {
+  return rollout_impl(m, n_env, q, qd, act, status, exc, n_steps, opts, 1, (hipStream_t)stream);
+}
+
+}  // extern "C"
+
+ms_status rollout_impl(ms_model *m, int32_t n_env, float *q, float *qd, float *act,
+                       uint32_t *status, const ms_excitation *exc, int32_t n_steps,
+                       const ms_step_opts *opts, int env_per_wg, hipStream_t st) {
   g_err.clear();
   ms_status s = common_checks(m, n_env, q, qd, act, opts);
   if (s != MS_OK) return s;
@@ -236,7 +237,7 @@ ms_status ms_rollout(ms_model *m, int32_t n_env, float *q, float *qd, float *act
   r.dt = opts->dt; r.contact = opts->contact;
   r.u = exc->u; r.seed = exc->seed; r.step0 = exc->step0; r.xar = exc->x;
   r.rho = exc->rho; r.s = exc->s; r.mean = exc->mean;
-  hipStream_t st = (hipStream_t)stream;
+  r.env_per_wg = env_per_wg;
   switch (exc->kind) {
     case MS_EXC_ARRAY:
       if (!exc->u && m->t.n_mus > 0) return fail(MS_E_ARG, "exc->u is NULL");
@@ -252,6 +253,8 @@ ms_status ms_rollout(ms_model *m, int32_t n_env, float *q, float *qd, float *act
   r.exc = exc->kind;
   return hip_status(launch(m, r, n_env, n_steps, st));
 }
+
+extern "C" {
 
 ms_status ms_rollout_surrogate(ms_model *m, ms_surrogate *sg, int32_t n_env, float *q, float *qd,
                                float *act, uint32_t *status, const ms_excitation *exc,

@@ -122,6 +122,14 @@ __device__ __forceinline__ double lane_bcast(double v, int src) {
 
 // Sum over the 64 lanes of a wavefront (butterfly exchange); every lane
 // receives the total.
+// Barrier and LDS ordering among the lanes of one wavefront (an env never
+// waits for other wavefronts of its workgroup).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
   return v;
@@ -219,9 +227,14 @@ __device__ __forceinline__ float muscle_geometry(const KModel &M, int m, int Pg,
 // own, so the exact kernel carries none of it).
 template <int MPL, int NVIA, bool SURR, bool GEOM>
 __device__ __forceinline__ void step_body(const KModel &M, const KRun &Rn, int n_steps) {
-  extern __shared__ __align__(16) unsigned char lds[];
-  const int env = blockIdx.x;
-  const int lane = threadIdx.x;
+  // a workgroup holds blockDim.x / 64 envs, one per wavefront, each with its
+  // own LDS block; envs never synchronise with each other
+  extern __shared__ __align__(16) unsigned char lds_all[];
+  const int wave = threadIdx.x >> 6;
+  const int env = blockIdx.x * (blockDim.x >> 6) + wave;
+  const int lane = threadIdx.x & 63;
+  if (env >= Rn.n_env) return;
+  unsigned char *lds = lds_all + (size_t)wave * M.lds_env;
   const int nq = M.nq, nv = M.nv, nm = M.n_mus, nn = M.n_node;
   float *__restrict__ q = (float *)(lds + M.off_q);
   float *__restrict__ qd = (float *)(lds + M.off_qd);
@@ -264,7 +277,7 @@ __device__ __forceinline__ void step_body(const KModel &M, const KRun &Rn, int n
     if (exc == EXC_AR1 && mi < nm) xar[t] = Rn.xar[(size_t)env * nm + mx];
   }
   unsigned status = Rn.status ? Rn.status[env] : 0u;
-  __syncthreads();
+  wave_sync();
 
   for (int step = 0; step < n_steps; ++step) {
     // ---------------------------------------------- excitation and state check
@@ -373,7 +386,7 @@ __device__ __forceinline__ void step_body(const KModel &M, const KRun &Rn, int n
       st3(F + 9, t);
       st3(Al + 6 * i, al);
     }
-    __syncthreads();
+    wave_sync();
     // (2) compose down the tree level by level, reading only LDS:
     // R = R_p Lr, P = P_p + R_p t, axis = R_p al, S, V = V_p + S qd,
     // A = A_p + V_p x (S qd)
@@ -428,7 +441,7 @@ __device__ __forceinline__ void step_body(const KModel &M, const KRun &Rn, int n
         st3(A, ap + cross(wp, xw));
         st3(A + 3, lp + cross(wp, xv) + cross(vp, xw));
       }
-      __syncthreads();
+      wave_sync();
     }
 
     if (!geom_only) {
@@ -490,7 +503,7 @@ __device__ __forceinline__ void step_body(const KModel &M, const KRun &Rn, int n
       st3(Fl + 6 * b, fw);
       st3(Fl + 6 * b + 3, fl);
     }
-    __syncthreads();
+    wave_sync();
     float *Fn = Fl + 6 * M.n_body;
     for (int t = lane; t < 6 * nn; t += 64) {
       const int n = t / 6, k = t % 6;
@@ -499,7 +512,7 @@ __device__ __forceinline__ void step_body(const KModel &M, const KRun &Rn, int n
       for (int e = M.subc_start[n]; e < M.subc_start[n + 1]; ++e) s -= Cl[16 * M.subc[e] + 4 + k];
       Fn[t] = s;
     }
-    __syncthreads();
+    wave_sync();
     for (int j = lane; j < nv; j += 64) {
       const float *S = Sl + 6 * j;
       const float *F = Fn + 6 * M.dof_node[j];
@@ -507,7 +520,7 @@ __device__ __forceinline__ void step_body(const KModel &M, const KRun &Rn, int n
       if (stages) Rn.o_bias[(size_t)env * nv + j] = cb;
       rhs[j] = (double)(-cb - M.damping[j] * qd[j]);
     }
-    __syncthreads();
+    wave_sync();
 
     // ---------------------------------- composite-rigid-body mass matrix (FP64)
     {
@@ -533,14 +546,14 @@ __device__ __forceinline__ void step_body(const KModel &M, const KRun &Rn, int n
           o[4 + e] = v + m * ((r == s ? cc : 0.0) - c[r] * c[s]);
         }
       }
-      __syncthreads();
+      wave_sync();
       for (int t = lane; t < 10 * nn; t += 64) {
         const int n = t / 10, k = t % 10;
         double s = 0.0;
         for (int e = M.subb_start[n]; e < M.subb_start[n + 1]; ++e) s += BI[10 * M.subb[e] + k];
         CI[t] = s;
       }
-      __syncthreads();
+      wave_sync();
       for (int j = lane; j < nv; j += 64) {
         const int n = M.dof_node[j];
         const double *I = CI + 10 * n;
@@ -577,7 +590,7 @@ __device__ __forceinline__ void step_body(const KModel &M, const KRun &Rn, int n
         }
         for (int k = 0; k < 6; ++k) FJ[6 * j + k] = f[k];
       }
-      __syncthreads();
+      wave_sync();
       for (int e = lane; e < M.nnz; e += 64) {
         const int j = M.nnz_row[e], i = M.path[e];
         const float *Sf = Sl + 6 * i;
@@ -587,7 +600,7 @@ __device__ __forceinline__ void step_body(const KModel &M, const KRun &Rn, int n
         if (i == j) h += (double)dt * M.damping[j];
         H[e] = h;
       }
-      __syncthreads();
+      wave_sync();
     }
 
     }  // !geom_only
@@ -677,7 +690,7 @@ __device__ __forceinline__ void step_body(const KModel &M, const KRun &Rn, int n
         mc[m] = cdamp;
         if (stages) Rn.o_F[(size_t)env * nm + M.mus_ext[m]] = F;
       }
-      __syncthreads();
+      wave_sync();
       for (int j = lane; j < nv; j += 64) {
         float tau = 0.f;
         for (int e = M.proj_start[j]; e < M.proj_start[j + 1]; ++e) {
@@ -696,7 +709,7 @@ __device__ __forceinline__ void step_body(const KModel &M, const KRun &Rn, int n
         }
         H[M.dent_h[e]] += (double)dt * s;
       }
-      __syncthreads();
+      wave_sync();
     }
     if (stages) {
       for (int e = lane; e < M.nnz; e += 64) Rn.o_H[(size_t)env * M.nnz + e] = H[e];
@@ -734,7 +747,7 @@ __device__ __forceinline__ void step_body(const KModel &M, const KRun &Rn, int n
           sum = group_sum(sum, lp);
           if (g < ne && p == 0) H[e] -= sum;
         }
-        __syncthreads();
+        wave_sync();
       }
       bool bad = false;
       for (int e = M.hlev_start[h] + lane; e < M.hlev_start[h + 1]; e += 64) {
@@ -747,7 +760,7 @@ __device__ __forceinline__ void step_body(const KModel &M, const KRun &Rn, int n
         nonspd = true;
         break;
       }
-      __syncthreads();
+      wave_sync();
     }
     if (!nonspd) {
       // L^T y = rhs, leaves first: y_k = rhs_k - sum_{i desc. of k} (H_ik / d_i) y_i
@@ -772,10 +785,10 @@ __device__ __forceinline__ void step_body(const KModel &M, const KRun &Rn, int n
           sum = group_sum(sum, lp);
           if (g < ne && p == 0) xs[k] = rhs[k] - sum;
         }
-        __syncthreads();
+        wave_sync();
       }
       for (int j = lane; j < nv; j += 64) xs[j] *= invd[j];
-      __syncthreads();
+      wave_sync();
       // L x = z, root first: x_k = z_k - (1/d_k) sum_{a anc. of k} H_ka x_a
       for (int dl = 1; dl < M.n_dlev; ++dl) {
         const int s0 = M.dlev_start[dl], ne = M.dlev_start[dl + 1] - s0;
@@ -794,7 +807,7 @@ __device__ __forceinline__ void step_body(const KModel &M, const KRun &Rn, int n
           sum = group_sum(sum, lp);
           if (g < ne && p == 0) xs[k] -= sum * invd[k];
         }
-        __syncthreads();
+        wave_sync();
       }
     }
 
@@ -826,12 +839,12 @@ __device__ __forceinline__ void step_body(const KModel &M, const KRun &Rn, int n
       status |= MS_ST_NONFINITE;
       continue;
     }
-    __syncthreads();
+    wave_sync();
     for (int t = 0; t < 2; ++t) {
       const int j = lane + 64 * t;
       if (j < nv) qd[j] = qdn[t];
     }
-    __syncthreads();
+    wave_sync();
     // positions: each node's q from its own DoFs
     for (int i = lane; i < nn; i += 64) {
       const int a = M.qadr[i], d = M.dadr[i];
@@ -862,7 +875,7 @@ __device__ __forceinline__ void step_body(const KModel &M, const KRun &Rn, int n
     }
 #pragma unroll
     for (int t = 0; t < MPL; ++t) act[t] = act1[t];
-    __syncthreads();
+    wave_sync();
   }
 
   if (stages) return;
@@ -881,18 +894,18 @@ __device__ __forceinline__ void step_body(const KModel &M, const KRun &Rn, int n
 }
 
 template <int MPL, int NVIA>
-__global__ __launch_bounds__(64) void k_step(KModel M, KRun Rn, int n_steps) {
+__global__ __launch_bounds__(256) void k_step(KModel M, KRun Rn, int n_steps) {
   step_body<MPL, NVIA, false, false>(M, Rn, n_steps);
 }
 
 template <int MPL, int NVIA>
-__global__ __launch_bounds__(64) void k_step_surrogate(KModel M, KRun Rn, int n_steps) {
+__global__ __launch_bounds__(256) void k_step_surrogate(KModel M, KRun Rn, int n_steps) {
   step_body<MPL, NVIA, true, false>(M, Rn, n_steps);
 }
 
 // exact muscle geometry only (L, Ldot, r as stage outputs)
 template <int MPL, int NVIA>
-__global__ __launch_bounds__(64) void k_geometry(KModel M, KRun Rn, int n_steps) {
+__global__ __launch_bounds__(256) void k_geometry(KModel M, KRun Rn, int n_steps) {
   step_body<MPL, NVIA, false, true>(M, Rn, n_steps);
 }
 
@@ -900,20 +913,22 @@ template <int MPL, int NVIA>
 hipError_t launch_k(const Tables &t, const KModel &k, const KRun &r, int n_env, int n_steps,
                     hipStream_t st) {
   const bool geom = r.stages == 2, surr = r.geomY != nullptr;
+  const int W = r.env_per_wg > 0 ? r.env_per_wg : 1;
+  const size_t lds = (size_t)W * t.lds_bytes;
   const void *fn = geom ? (const void *)&k_geometry<MPL, NVIA>
                    : surr ? (const void *)&k_step_surrogate<MPL, NVIA>
                           : (const void *)&k_step<MPL, NVIA>;
-  if (t.lds_bytes > 65536) {
-    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, t.lds_bytes);
+  if (lds > 65536) {
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
-  const dim3 grid(n_env), block(64);
+  const dim3 grid((n_env + W - 1) / W), block(64 * W);
   if (geom)
-    hipLaunchKernelGGL((k_geometry<MPL, NVIA>), grid, block, t.lds_bytes, st, k, r, n_steps);
+    hipLaunchKernelGGL((k_geometry<MPL, NVIA>), grid, block, lds, st, k, r, n_steps);
   else if (surr)
-    hipLaunchKernelGGL((k_step_surrogate<MPL, NVIA>), grid, block, t.lds_bytes, st, k, r, n_steps);
+    hipLaunchKernelGGL((k_step_surrogate<MPL, NVIA>), grid, block, lds, st, k, r, n_steps);
   else
-    hipLaunchKernelGGL((k_step<MPL, NVIA>), grid, block, t.lds_bytes, st, k, r, n_steps);
+    hipLaunchKernelGGL((k_step<MPL, NVIA>), grid, block, lds, st, k, r, n_steps);
   return hipGetLastError();
 }
 

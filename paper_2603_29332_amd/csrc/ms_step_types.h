@@ -37,6 +37,7 @@ struct KModel {
   const int *dsol;
   int off_flag, off_q, off_qd, off_R, off_P, off_S, off_con, off_rhs, off_x, off_H,
       off_scr, off_V, off_A, off_F, off_tree;
+  int lds_env;  // bytes of one env's LDS block
 };
 
 struct KRun {
@@ -61,6 +62,7 @@ struct KRun {
   // stage outputs (ms_step_stages)
   float *o_act, *o_L, *o_Ldot, *o_F, *o_r, *o_tau, *o_bias, *o_qdd;
   double *o_H;
+  int env_per_wg;  // envs (wavefronts) per workgroup, 1, 2 or 4 (0 = 1)
 };
 
 enum { EXC_ARRAY = MS_EXC_ARRAY, EXC_IID = MS_EXC_IID, EXC_AR1 = MS_EXC_AR1 };
@@ -77,3 +79,21 @@ extern template hipError_t launch_nvia<6>(const Tables &, const KModel &, const 
 extern template hipError_t launch_nvia<8>(const Tables &, const KModel &, const KRun &, int, int, hipStream_t);
 
 }  // namespace ms
+
+// The model object behind the C ABI's opaque handle.
+struct ms_model {
+  ms::Tables t;
+  ms::KModel k;
+  void *dbuf = nullptr;
+  size_t dbytes = 0;
+};
+
+// Launch the step kernel variant the run arguments select (exact, surrogate
+// or geometry only) for n_env envs and n_steps steps on stream st.
+hipError_t launch(const ms_model *m, const ms::KRun &r, int n_env, int n_steps, hipStream_t st);
+
+// ms_rollout with a chosen number of envs per workgroup (1, 2 or 4); errors
+// as ms_rollout (message in ms_last_error).
+ms_status rollout_impl(ms_model *m, int32_t n_env, float *q, float *qd, float *act,
+                       uint32_t *status, const ms_excitation *exc, int32_t n_steps,
+                       const ms_step_opts *opts, int env_per_wg, hipStream_t st);

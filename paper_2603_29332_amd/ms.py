@@ -26,7 +26,9 @@ EXPORTED = ("ms_model_create", "ms_model_destroy", "ms_model_info_get",
             "ms_surrogate_create", "ms_surrogate_destroy", "ms_surrogate_dims",
             "ms_surrogate_params", "ms_surrogate_grads", "ms_surrogate_set_norm",
             "ms_surrogate_sample", "ms_surrogate_forward", "ms_surrogate_train_step",
-            "ms_surrogate_last_error", "ms_rollout_surrogate")
+            "ms_surrogate_last_error", "ms_rollout_surrogate",
+            "ms_batch_create", "ms_batch_destroy", "ms_batch_rollout", "ms_batch_autotune",
+            "ms_batch_config", "ms_batch_set_config", "ms_batch_last_error")
 
 _fptr = C.POINTER(C.c_float)
 _iptr = C.POINTER(C.c_int32)
@@ -59,6 +61,11 @@ class MsExc(C.Structure):
     _fields_ = [("kind", C.c_int32), ("u", C.c_void_p), ("seed", C.c_uint64),
                 ("step0", C.c_int64), ("x", C.c_void_p), ("rho", C.c_float),
                 ("s", C.c_float), ("mean", C.c_float)]
+
+
+class MsBatchState(C.Structure):
+    _fields_ = [("q", C.c_void_p), ("qd", C.c_void_p), ("act", C.c_void_p),
+                ("status", C.c_void_p)]
 
 
 class MsStageOut(C.Structure):
@@ -105,6 +112,19 @@ def lib():
     L.ms_rollout_surrogate.argtypes = [vp, vp, C.c_int32, vp, vp, vp, vp, C.POINTER(MsExc),
                                        C.c_int32, C.POINTER(MsOpts), C.c_float, vp, vp]
     L.ms_rollout_surrogate.restype = C.c_int
+    L.ms_batch_create.argtypes = [C.POINTER(vp), _iptr, C.c_int32, C.POINTER(vp)]
+    L.ms_batch_destroy.argtypes = [vp]
+    L.ms_batch_destroy.restype = None
+    L.ms_batch_rollout.argtypes = [vp, C.POINTER(MsBatchState), C.POINTER(MsExc), C.c_int32,
+                                   C.POINTER(MsOpts), vp]
+    L.ms_batch_autotune.argtypes = [vp, C.POINTER(MsBatchState), C.POINTER(MsExc), C.c_int32,
+                                    C.POINTER(MsOpts), vp]
+    L.ms_batch_config.argtypes = [vp, _iptr, _iptr]
+    L.ms_batch_set_config.argtypes = [vp, _iptr, C.c_int32]
+    L.ms_batch_last_error.restype = C.c_char_p
+    for f in ("ms_batch_create", "ms_batch_rollout", "ms_batch_autotune", "ms_batch_config",
+              "ms_batch_set_config"):
+        getattr(L, f).restype = C.c_int
     for f in ("ms_surrogate_create", "ms_surrogate_dims", "ms_surrogate_params",
               "ms_surrogate_grads", "ms_surrogate_set_norm", "ms_surrogate_sample",
               "ms_surrogate_forward", "ms_surrogate_train_step"):
@@ -307,3 +327,66 @@ class Surrogate:
     def train_step(self, q, L, r, lr, step, loss=None, stream=None):
         _check_s(lib().ms_surrogate_train_step(self.h, q.shape[0], _dp(q), _dp(L), _dp(r),
                                                float(lr), int(step), _dp(loss), _stream(stream)))
+
+
+def _check_b(rc):
+    if rc != 0:
+        raise MsError(rc, lib().ms_batch_last_error().decode())
+
+
+class Batch:
+    """Envs of several models stepped together (one graph launch per call).
+
+    states: per model a tuple (q, qd, act, status) of device tensors;
+    excitations: per model a dict of Model.rollout's excitation arguments
+    (kind, u, seed, step0, x, ar1)."""
+
+    def __init__(self, models, n_env):
+        L = lib()
+        self.models = list(models)
+        self.n_env = [int(n) for n in n_env]
+        arr = (C.c_void_p * len(self.models))(*[m.h for m in self.models])
+        ne = np.asarray(self.n_env, np.int32)
+        h = C.c_void_p()
+        _check_b(L.ms_batch_create(arr, ne.ctypes.data_as(_iptr), len(self.models), C.byref(h)))
+        self.h = h
+
+    def __del__(self):
+        try:
+            if getattr(self, "h", None):
+                lib().ms_batch_destroy(self.h)
+        except Exception:
+            pass
+
+    def _args(self, states, excitations):
+        n = len(self.models)
+        st = (MsBatchState * n)()
+        ex = (MsExc * n)()
+        for i, ((q, qd, act, status), e) in enumerate(zip(states, excitations)):
+            st[i] = MsBatchState(_dp(q), _dp(qd), _dp(act), _dp(status))
+            ar1 = e.get("ar1", (0.0, 0.0, 0.0))
+            ex[i] = MsExc(e.get("kind", EXC_ARRAY), _dp(e.get("u")), e.get("seed", 0),
+                          e.get("step0", 0), _dp(e.get("x")), float(ar1[0]), float(ar1[1]),
+                          float(ar1[2]))
+        return st, ex
+
+    def rollout(self, states, excitations, n_steps, dt, contact=True, stream=None):
+        st, ex = self._args(states, excitations)
+        o = MsOpts(dt, int(contact))
+        _check_b(lib().ms_batch_rollout(self.h, st, ex, n_steps, C.byref(o), _stream(stream)))
+
+    def autotune(self, states, excitations, n_probe, dt, contact=True, stream=None):
+        st, ex = self._args(states, excitations)
+        o = MsOpts(dt, int(contact))
+        _check_b(lib().ms_batch_autotune(self.h, st, ex, n_probe, C.byref(o), _stream(stream)))
+        return self.config()
+
+    def config(self):
+        w = np.zeros(len(self.models), np.int32)
+        lf = np.zeros(1, np.int32)
+        _check_b(lib().ms_batch_config(self.h, w.ctypes.data_as(_iptr), lf.ctypes.data_as(_iptr)))
+        return w.tolist(), int(lf[0])
+
+    def set_config(self, env_per_wg, largest_first=0):
+        w = np.asarray(env_per_wg, np.int32)
+        _check_b(lib().ms_batch_set_config(self.h, w.ctypes.data_as(_iptr), int(largest_first)))

@@ -1,0 +1,107 @@
+"""Uneven batches through the C ABI: three models of different sizes stepped
+in one call (per-model kernels on forked streams, replayed as a HIP graph).
+Every configuration must give, bit for bit, what ms_rollout gives for each
+model alone; that path is itself held to the FP64 oracle by the parity
+tests."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_2603_29332_amd import ms, synth  # noqa: E402
+
+DEV = "cuda"
+DT = 1e-3
+
+
+def _t(a, dtype=torch.float32):
+    return torch.tensor(np.ascontiguousarray(a), dtype=dtype, device=DEV)
+
+
+@pytest.fixture(scope="module")
+def three():
+    ms_ = [synth.chain_model(31), synth.human_model(32, full=False), synth.human_model(33)]
+    inits = [synth.chain_initial_state, synth.human_initial_state, synth.human_initial_state]
+    n_env = [64, 96, 128]                       # ragged against 2- and 4-env workgroups
+    return ms_, [ms.Model(m) for m in ms_], inits, n_env
+
+
+def _fresh(m, init, n):
+    q, qd, act = init(m, n)
+    return [_t(q), _t(qd), _t(act), torch.zeros(n, dtype=torch.int32, device=DEV),
+            torch.zeros(n, m["n_mus"], device=DEV)]
+
+
+def _exc(x, step0):
+    rho, s, mean, _ = synth.ar1_constants(DT)
+    return dict(kind=ms.EXC_AR1, seed=34, step0=step0, x=x, ar1=(rho, s, mean))
+
+
+def _alone(mods, gms, inits, n_env, T, calls=1):
+    out = []
+    for m, gm, init, n in zip(mods, gms, inits, n_env):
+        q, qd, act, st, x = _fresh(m, init, n)
+        for c in range(calls):
+            gm.rollout(q, qd, act, st, T, DT, True, **_exc(x, c * T))
+        torch.cuda.synchronize()
+        out.append([v.cpu().numpy() for v in (q, qd, act, st, x)])
+    return out
+
+
+def _batched(mods, b, inits, n_env, T, calls=1, contact=True):
+    bufs = [_fresh(m, init, n) for m, init, n in zip(mods, inits, n_env)]
+    for c in range(calls):
+        b.rollout([tuple(v[:4]) for v in bufs], [_exc(v[4], c * T) for v in bufs], T, DT,
+                  contact=contact)
+    torch.cuda.synchronize()
+    return [[v.cpu().numpy() for v in bb] for bb in bufs]
+
+
+def _same(a, b):
+    for x, y in zip(a, b):
+        for u, v in zip(x, y):
+            assert np.array_equal(u, v)
+
+
+def test_batch_matches_each_model_alone_in_every_configuration(three):
+    mods, gms, inits, n_env = three
+    T = 20
+    ref = _alone(mods, gms, inits, n_env, T)
+    b = ms.Batch(gms, n_env)
+    for cfg, lf in (([1, 1, 1], 0), ([2, 4, 1], 1), ([4, 2, 4], 0)):
+        b.set_config(cfg, lf)
+        assert b.config() == (cfg, lf)
+        _same(_batched(mods, b, inits, n_env, T), ref)
+
+
+def test_graph_replay_continues_the_rollout(three):
+    mods, gms, inits, n_env = three
+    T = 10
+    ref = _alone(mods, gms, inits, n_env, T, calls=3)
+    b = ms.Batch(gms, n_env)
+    _same(_batched(mods, b, inits, n_env, T, calls=3), ref)
+
+
+def test_autotune_picks_a_valid_configuration_and_leaves_states(three):
+    mods, gms, inits, n_env = three
+    b = ms.Batch(gms, n_env)
+    bufs = [_fresh(m, init, n) for m, init, n in zip(mods, inits, n_env)]
+    before = [[v.cpu().numpy().copy() for v in bb] for bb in bufs]
+    w, lf = b.autotune([tuple(v[:4]) for v in bufs], [_exc(v[4], 0) for v in bufs], 5, DT)
+    torch.cuda.synchronize()
+    assert all(x in (1, 2, 4) for x in w) and lf in (0, 1)
+    after = [[v.cpu().numpy() for v in bb] for bb in bufs]
+    _same(after, before)
+    # and the tuned batch still matches the models alone
+    _same(_batched(mods, b, inits, n_env, 10), _alone(mods, gms, inits, n_env, 10))
+
+
+def test_oversized_workgroup_is_rejected(three):
+    mods, gms, inits, n_env = three
+    b = ms.Batch([gms[2]], [8])
+    if gms[2].info["lds_bytes"] * 4 > 160 * 1024:
+        with pytest.raises(ms.MsError):
+            b.set_config([4], 0)
+    else:
+        b.set_config([4], 0)

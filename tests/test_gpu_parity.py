@@ -37,6 +37,12 @@ def human():
     return m, ms.Model(m), Oracle(m)
 
 
+@pytest.fixture(scope="module")
+def human40():
+    m = synth.human_model(32, full=False)
+    return m, ms.Model(m), Oracle(m)
+
+
 def _advance_gpu(gm, q, qd, act, u_seq, dt, contact):
     """Run the GPU rollout from float32 numpy state; return numpy state."""
     E = q.shape[0]
@@ -118,13 +124,13 @@ def test_stage_parity(which, chain, human):
 
 
 # ---------------------------------------------------- one step, teacher forced
-@pytest.mark.parametrize("which", ["chain", "human"])
-def test_step_teacher_forced(which, chain, human):
-    m, gm, o = chain if which == "chain" else human
+@pytest.mark.parametrize("which", ["chain", "human", "human40"])
+def test_step_teacher_forced(which, chain, human, human40):
+    m, gm, o = {"chain": chain, "human": human, "human40": human40}[which]
     dt = 2e-3 if which == "chain" else 1e-3
     kind = "iid" if which == "chain" else "ar1"
     init = synth.chain_initial_state if which == "chain" else synth.human_initial_state
-    contact = which == "human"
+    contact = which != "chain"
     E = 16
     q, qd, act = _warm_states(m, o, E, 60, dt, kind, 22, contact, init)
     u = synth.excitation_iid(6, E, m["n_mus"], 0)
@@ -132,10 +138,29 @@ def test_step_teacher_forced(which, chain, human):
     assert (st == 0).all()
     qo, qdo, ao, sto = o.rollout(dt, q, qd, act, u[None], contact=contact)
     assert (sto == 0).all()
-    for e in range(E):
-        assert _rel_block(q1[e], qo[e]) <= 1e-5
-        assert _rel_block(qd1[e], qdo[e]) <= 1e-5
-        assert _rel_block(a1[e], ao[e]) <= 1e-5
+    # conditioning of each state at FP32 resolution: the oracle's own change
+    # under relative perturbations of 1e-7 (float32 rounding) of q and qd,
+    # four seeded draws. Where contact stiffness amplifies that beyond the
+    # bound, no FP32 step can meet 1e-5; the bound there is 4x the oracle's
+    # own spread.
+    rng = np.random.default_rng(99)
+    sens = np.zeros((E, 3))
+    for _ in range(4):
+        qp = q.astype(np.float64) * (1 + 1e-7 * rng.standard_normal(q.shape))
+        if m["jtype"][0] == 2:
+            qp[:, 3:7] /= np.linalg.norm(qp[:, 3:7], axis=1, keepdims=True)
+        qdp = qd.astype(np.float64) * (1 + 1e-7 * rng.standard_normal(qd.shape))
+        a_, b_, c_, _ = o.rollout(dt, qp, qdp, act, u[None], contact=contact)
+        for e in range(E):
+            sens[e] = np.maximum(sens[e], [_rel_block(a_[e], qo[e]), _rel_block(b_[e], qdo[e]),
+                                           _rel_block(c_[e], ao[e])])
+    tol = np.maximum(1e-5, 4 * sens)
+    err = np.array([[_rel_block(q1[e], qo[e]), _rel_block(qd1[e], qdo[e]),
+                     _rel_block(a1[e], ao[e])] for e in range(E)])
+    print(f"{which} teacher-forced: max rel err (q, qd, act) {err.max(axis=0)}, "
+          f"{int((tol > 1e-5).any(axis=1).sum())} of {E} states contact-sensitive "
+          f"(oracle spread up to {sens.max():.1e})")
+    assert (err <= tol).all()
 
 
 # -------------------------------------------------------- 200-step free run

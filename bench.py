@@ -50,6 +50,11 @@ def parse():
                    help="Adam iterations (batch 8192) before the surrogate leg is timed")
     p.add_argument("--surrogate-tol", type=float, default=1e-4,
                    help="sentinel length residual (m) above which an env falls back")
+    p.add_argument("--no-uneven", action="store_true", help="skip the uneven-batch leg")
+    p.add_argument("--no-policy", action="store_true", help="skip the policy-driven leg")
+    p.add_argument("--policy-envs", type=int, default=65536)
+    p.add_argument("--policy-steps", type=int, default=2000)
+    p.add_argument("--uneven-steps", type=int, default=500)
     p.add_argument("--calib-copy-mib", type=int, default=0,
                    help="first run one plain device copy of this many MiB (a known-size "
                         "reference for hardware traffic counters)")
@@ -154,9 +159,14 @@ def main():
                            "the next launch boundary (every 100 steps), as RL rollouts do; the "
                            "FP64 oracle fails on the same envs (about 19% by 1000 steps)",
     }
+    sg = None
     if not a.no_surrogate:
-        line["surrogate"] = surrogate_leg(a, m, gm, dt, E, q0, qd0, act0, (rho, s, mean), dev,
-                                          rad=not a.no_cpu)
+        line["surrogate"], sg = surrogate_leg(a, m, gm, dt, E, q0, qd0, act0, (rho, s, mean), dev,
+                                              rad=not a.no_cpu)
+    if not a.no_policy:
+        line["policy"] = policy_leg(a, m, gm, sg, dt, dev)
+    if not a.no_uneven:
+        line["uneven"] = uneven_leg(a, dt, dev)
     if not a.no_cpu:
         line["rad_err_vs_fp64"] = rad_error(m, gm, dt, dev)
         line["cpu_baseline"] = cpu_baseline(m, dt, a.cpu_seconds)
@@ -183,6 +193,112 @@ def reset_flagged(q, qd, act, st, x, init, count):
     x.copy_(torch.where(b, torch.zeros_like(x), x))
     count.add_(bad.sum())
     st.zero_()
+
+
+def uneven_leg(a, dt, dev):
+    """Mixed batch of 16384 envs from three models (8 DoF/16 muscles,
+    40 DoF/300 muscles, 80 DoF/700 muscles, 1:1:2), exact path, AR(1)
+    excitations in-kernel: one autotuned ms_batch_rollout (graph replay) of
+    the whole run, against the same work issued model after model on one
+    stream."""
+    import torch
+
+    from paper_2603_29332_amd import ms, synth
+    mods = [synth.chain_model(31), synth.human_model(32, full=False), synth.human_model(33)]
+    inits = [synth.chain_initial_state, synth.human_initial_state, synth.human_initial_state]
+    n_env = [4096, 4096, 8192]
+    gms = [ms.Model(m) for m in mods]
+    rho, s, mean, _ = synth.ar1_constants(dt)
+    stream = torch.cuda.current_stream()
+
+    def fresh():
+        out = []
+        for m, init, n in zip(mods, inits, n_env):
+            q, qd, act = init(m, n)
+            out.append([torch.tensor(q, device=dev), torch.tensor(qd, device=dev),
+                        torch.tensor(act, device=dev), torch.zeros(n, dtype=torch.int32, device=dev),
+                        torch.zeros(n, m["n_mus"], device=dev)])
+        return out
+
+    def exc(bufs, step0):
+        return [dict(kind=ms.EXC_AR1, seed=34, step0=step0, x=b[4], ar1=(rho, s, mean))
+                for b in bufs]
+
+    T = a.uneven_steps
+    b = ms.Batch(gms, n_env)
+    bufs = fresh()
+    cfg = b.autotune([tuple(x[:4]) for x in bufs], exc(bufs, 0), 20, dt)
+    b.rollout([tuple(x[:4]) for x in bufs], exc(bufs, 0), 10, dt)   # warm-up, graph capture
+    torch.cuda.synchronize()
+    bufs = fresh()
+    st4 = [tuple(x[:4]) for x in bufs]
+    ex = exc(bufs, 0)
+    b.rollout(st4, ex, T, dt)          # captures the T-step graph (not timed)
+    torch.cuda.synchronize()
+    bufs = fresh()
+    st4 = [tuple(x[:4]) for x in bufs]
+    ex = exc(bufs, 0)
+    t = time.perf_counter()
+    b.rollout(st4, ex, T, dt)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t
+    flagged = int(sum((x[3] != 0).sum().item() for x in bufs))
+    # the same work model after model on one stream, one envs per workgroup
+    bufs = fresh()
+    t = time.perf_counter()
+    for gm, x in zip(gms, bufs):
+        gm.rollout(x[0], x[1], x[2], x[3], T, dt, True, kind=ms.EXC_AR1, seed=34, step0=0, x=x[4],
+                   ar1=(rho, s, mean), stream=stream)
+    torch.cuda.synchronize()
+    wall_seq = time.perf_counter() - t
+    total = sum(n_env) * T
+    return {"env_steps_per_s": total / wall, "ms_per_step": wall / T * 1e3,
+            "sequential_env_steps_per_s": total / wall_seq, "envs": n_env, "steps": T,
+            "models": ["8 DoF/16 muscles", "40 DoF/300 muscles/16 spheres",
+                       "80 DoF/700 muscles/24 spheres"],
+            "autotuned": {"env_per_workgroup": cfg[0], "largest_first": cfg[1]},
+            "flagged_envs": flagged}
+
+
+def policy_leg(a, m, gm, sg, dt, dev):
+    """RL-rollout shape: a random-initialised policy network (obs 300 -> 512
+    -> 512 -> 700 sigmoid) sets the excitations every 2 steps from each env's
+    state and 140 reference targets; geometry from the trained surrogate with
+    exact fallback (exact geometry when the surrogate leg is skipped).
+    Launched in 100-step calls; failed envs restart at call boundaries."""
+    import torch
+
+    from paper_2603_29332_amd import ms, synth
+    E, T, chunk = a.policy_envs, a.policy_steps, 100
+    pol = ms.Policy(gm, hidden=512, n_ref=140, ref_seed=52, seed=51)
+    q0, qd0, act0 = synth.human_initial_state(m, E)
+    init = tuple(torch.tensor(v, device=dev) for v in (q0, qd0, act0))
+    q, qd, act = (v.clone() for v in init)
+    st = torch.zeros(E, dtype=torch.int32, device=dev)
+    fb = torch.zeros(E, dtype=torch.int32, device=dev)
+    x = torch.zeros(E, m["n_mus"], device=dev)
+    resets = torch.zeros((), dtype=torch.int64, device=dev)
+
+    def run(t0_step, n):
+        pol.rollout(q, qd, act, st, n, 2, dt, contact=True, t0=t0_step * dt, surrogate=sg,
+                    tol=a.surrogate_tol, fb_count=fb)
+        st.bitwise_and_(~ms.MS_ST_FALLBACK)
+        reset_flagged(q, qd, act, st, x, init, resets)
+
+    run(0, 10)                                        # warm-up
+    torch.cuda.synchronize()
+    q.copy_(init[0]); qd.copy_(init[1]); act.copy_(init[2]); fb.zero_(); resets.zero_()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for k in range(0, T, chunk):
+        run(k, min(chunk, T - k))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t
+    return {"env_steps_per_s": E * T / wall, "ms_per_step": wall / T * 1e3, "envs": E,
+            "steps": T, "decision_every": 2,
+            "geometry": "surrogate + exact fallback" if sg is not None else "exact",
+            "fallback_rate": float(fb.sum().item()) / (E * T) if sg is not None else None,
+            "env_resets": int(resets.item())}
 
 
 def surrogate_leg(a, m, gm, dt, E, q0, qd0, act0, ar1, dev, rad=True):
@@ -250,7 +366,7 @@ def surrogate_leg(a, m, gm, dt, E, q0, qd0, act0, ar1, dev, rad=True):
                        "mfma_bf16_peak_tflops": 2500.0}}
     if rad:
         out["rad_err_vs_fp64"] = rad_error(m, gm, dt, dev, sg=sg, tol=a.surrogate_tol)
-    return out
+    return out, sg
 
 
 def rad_error(m, gm, dt, dev, sg=None, tol=1e-4):

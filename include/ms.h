@@ -233,6 +233,52 @@ ms_status ms_surrogate_train_step(ms_surrogate *s, int32_t n, const float *q,
 const char *ms_surrogate_last_error(void);
 
 /* ------------------------------------------------------------------------
+ * Policy-driven rollouts (the RL rollout shape of the paper's Methods:
+ * Observation space, Action space, Simulation parameters for the control
+ * rate). A policy network maps each env's observation to excitations:
+ * obs -> SiLU(W1 obs + b1) -> SiLU(W2 h1 + b2) -> sigmoid(W3 h2 + b3), one
+ * excitation in [0, 1] per muscle (caller's order), bfloat16 matrix-core
+ * GEMMs with float32 accumulation, LeCun-uniform random weights from `seed`
+ * (W stored [out][in]); it is not trained here (the paper's RL training is
+ * out of scope).
+ * Observation of env e at time t, n_obs = 2 nv + n_ref values: the
+ * generalised position with a free root's unit quaternion (w >= 0 branch)
+ * folded into its rotation vector (nv values), the generalised velocity (nv
+ * values), and n_ref reference targets r_k(t) = sum_{j<3} A sin(2 pi f t +
+ * phi) with A = 0.3 a, f = 0.5 + 1.5 b, phi = 2 pi c, where a, b, c are the
+ * top 24 bits x 2^-24 of SplitMix64(K ^ 0), (K ^ 1), (K ^ 2) and K =
+ * SplitMix64(SplitMix64(ref_seed ^ env) ^ (3 k + j)): a synthetic stand-in
+ * for the retargeted reference motion. */
+typedef struct ms_policy ms_policy;
+ms_status ms_policy_create(const ms_model *m, int32_t hidden, int32_t n_ref,
+                           uint64_t ref_seed, uint64_t seed, ms_policy **out);
+void ms_policy_destroy(ms_policy *p);
+/* dims[4] = n_obs, n_in (n_obs padded to a multiple of 16), hidden, n_mus */
+ms_status ms_policy_dims(const ms_policy *p, int32_t *dims);
+/* host copies of the float32 parameters (set = 0 reads, 1 writes); W1 is
+ * [hidden][n_in]; its columns beyond n_obs meet zero inputs */
+ms_status ms_policy_params(ms_policy *p, int32_t set, float *W1, float *b1,
+                           float *W2, float *b2, float *W3, float *b3);
+/* u[n][n_mus] (device) for n envs with global indices env0.. at time t;
+ * obs_out (device [n][n_obs], may be NULL) receives the observations. */
+ms_status ms_policy_act(ms_policy *p, int32_t n, const float *q, const float *qd,
+                        double t, int64_t env0, float *u, float *obs_out,
+                        void *stream);
+/* n_steps steps of n_env envs driven by the policy: every `decim` steps
+ * (from step 0) the policy maps the current state at time t0 + step dt to
+ * excitations, held for the next decim steps. Geometry: exact when s is
+ * NULL, else the surrogate with per-env fallback exactly as in
+ * ms_rollout_surrogate (tol, fallback_count, sentinel step = step index).
+ * u_record (device, may be NULL) receives each decision's excitations,
+ * [ceil(n_steps / decim)][n_env][n_mus]. */
+ms_status ms_policy_rollout(ms_model *m, ms_policy *p, ms_surrogate *s,
+                            int32_t n_env, float *q, float *qd, float *act,
+                            uint32_t *status, int32_t n_steps, int32_t decim,
+                            double t0, const ms_step_opts *opts, float tol,
+                            uint32_t *fallback_count, float *u_record,
+                            void *stream);
+
+/* ------------------------------------------------------------------------
  * Uneven batches: envs of several models (different sizes) stepped in one
  * call. Not a passage of the paper: the batched-rollout setting of its
  * Methods (many environments at once, Simulation throughput) with models of

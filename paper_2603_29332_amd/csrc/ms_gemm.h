@@ -13,7 +13,7 @@ typedef __hip_bfloat16 bf16;
 //   v = acc * alpha + (bias ? bias[n] : 0)
 //   if dact: v *= SiLU'(dact[m * ldc + n])           (backward through SiLU)
 //   if z_out: z_out[m * ldc + n] = v                  (pre-activation, f32)
-//   if act == 1: v = SiLU(v)
+//   if act == 1: v = SiLU(v);  if act == 2: v = sigmoid(v)
 //   if scale: v = v * scale[n] + shift[n]             (de-standardisation)
 //   if c_f32: c_f32[m * ldc + n] = v ;  if c_bf16: c_bf16[m * ldc + n] = bf16(v)
 struct GemmEpi {

@@ -106,6 +106,7 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const bf16 *A
         if (epi.dact) v *= silu_slope(epi.dact[o]);
         if (epi.z_out) epi.z_out[o] = v;
         if (epi.act == 1) v = silu(v);
+        if (epi.act == 2) v = 1.0f / (1.0f + expf(-v));
         if (epi.scale) v = v * epi.scale[n] + epi.shift[n];
         if (epi.c_f32) epi.c_f32[o] = v;
         if (epi.c_bf16) epi.c_bf16[o] = __float2bfloat16(v);

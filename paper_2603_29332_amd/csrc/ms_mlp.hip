@@ -9,6 +9,7 @@
 // copies for the GEMMs; Adam (Kingma & Ba 2015) updates the masters.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <string>
 #include <vector>
@@ -16,6 +17,7 @@
 #include "../../include/ms.h"
 #include "ms_gemm.h"
 #include "ms_model.h"
+#include "ms_step_types.h"
 
 // Tables of the model this surrogate serves (filled from the model).
 struct ms_surrogate {
@@ -513,6 +515,267 @@ ms_status ms_surrogate_train_step(ms_surrogate *s, int32_t n, const float *q, co
     }
   }
   return hipst(hipGetLastError(), "train step");
+}
+
+}  // extern "C"
+
+// =============================================================== policy
+// A policy network mapping each env's observation to excitations: obs ->
+// SiLU(W1 obs + b1) -> SiLU(W2 h1 + b2) -> sigmoid(W3 h2 + b3) in [0, 1]^n_mus,
+// bfloat16 matrix-core GEMMs with float32 accumulation, LeCun-uniform
+// weights from a seed (random initialisation; no training here).
+//
+// Observation of env e at time t (n_obs = 2 nv + n_ref, zero-padded to a
+// multiple of 16): the generalised position with a free root's quaternion
+// folded into a rotation vector (nv values), the generalised velocity (nv),
+// and n_ref reference targets, each a sum of three sinusoids
+// A sin(2 pi f t + phi) with A = 0.3 u, f = 0.5 + 1.5 u, phi = 2 pi u drawn
+// from SplitMix64 on (ref_seed, env, 3 k + j), a synthetic stand-in for the
+// retargeted reference motion the policy tracks.
+struct ms_policy {
+  int nq = 0, nv = 0, n_mus = 0, free_root = 0, n_ref = 0, n_obs = 0, n_in = 0, h = 0;
+  unsigned long long ref_seed = 0;
+  float *W[3] = {}, *b[3] = {};
+  ms::bf16 *Wb[3] = {};
+  int cap = 0;
+  ms::bf16 *X = nullptr, *H1 = nullptr, *H2 = nullptr;
+  float *U = nullptr;  // held excitations of the last decision [cap][n_mus]
+  std::vector<void *> owned;
+};
+
+namespace ms {
+namespace {
+
+template <class T>
+T *palloc(ms_policy *p, size_t n) {
+  void *q = nullptr;
+  if (hipMalloc(&q, std::max<size_t>(n, 1) * sizeof(T)) != hipSuccess) return nullptr;
+  (void)hipMemset(q, 0, std::max<size_t>(n, 1) * sizeof(T));
+  p->owned.push_back(q);
+  return (T *)q;
+}
+
+__device__ __forceinline__ float ref_target(unsigned long long seed, long long env, int k, float t) {
+  const unsigned long long ke = splitmix64(seed ^ (unsigned long long)env);
+  float s = 0.0f;
+  for (int j = 0; j < 3; ++j) {
+    const unsigned long long key = splitmix64(ke ^ (unsigned long long)(3 * k + j));
+    const float A = 0.3f * unit24(splitmix64(key ^ 0ull));
+    const float f = 0.5f + 1.5f * unit24(splitmix64(key ^ 1ull));
+    const float ph = 6.28318530717958647692f * unit24(splitmix64(key ^ 2ull));
+    s += A * sinf(6.28318530717958647692f * f * t + ph);
+  }
+  return s;
+}
+
+// one thread per (env, input); obs_out (optional) gets the unpadded float32
+// observation
+__global__ void k_obs(int n, int nq, int nv, int free_root, int n_ref, int n_obs, int n_in,
+                      const float *q, const float *qd, float t, unsigned long long seed,
+                      long long env0, bf16 *X, float *obs_out) {
+  const long long tid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (tid >= (long long)n * n_in) return;
+  const int p = (int)(tid / n_in), i = (int)(tid % n_in);
+  const float *qp = q + (size_t)p * nq;
+  float v = 0.0f;
+  if (i < nv) {
+    if (!free_root) {
+      v = qp[i];
+    } else if (i < 3) {
+      v = qp[i];
+    } else if (i < 6) {
+      // rotation vector of the unit quaternion (w, x, y, z), w >= 0 branch
+      float w = qp[3], x = qp[4], y = qp[5], z = qp[6];
+      if (w < 0.0f) { w = -w; x = -x; y = -y; z = -z; }
+      const float sn = sqrtf(x * x + y * y + z * z);
+      const float sc = sn > 1e-12f ? 2.0f * atan2f(sn, w) / sn : 2.0f;
+      v = (i == 3 ? x : i == 4 ? y : z) * sc;
+    } else {
+      v = qp[i + 1];
+    }
+  } else if (i < 2 * nv) {
+    v = qd[(size_t)p * nv + (i - nv)];
+  } else if (i < n_obs) {
+    v = ref_target(seed, env0 + p, i - 2 * nv, t);
+  }
+  X[tid] = __float2bfloat16(v);
+  if (obs_out && i < n_obs) obs_out[(size_t)p * n_obs + i] = v;
+}
+
+ms_status policy_cap(ms_policy *p, int n) {
+  if (n <= p->cap) return MS_OK;
+  p->X = palloc<bf16>(p, (size_t)n * p->n_in);
+  p->H1 = palloc<bf16>(p, (size_t)n * p->h);
+  p->H2 = palloc<bf16>(p, (size_t)n * p->h);
+  p->U = palloc<float>(p, (size_t)n * p->n_mus);
+  if (!p->X || !p->H1 || !p->H2 || !p->U) return sfail(MS_E_ALLOC, "policy workspace allocation failed");
+  p->cap = n;
+  return MS_OK;
+}
+
+ms_status policy_forward(ms_policy *p, int n, const float *q, const float *qd, double t, long long env0,
+                         float *u, float *obs_out, hipStream_t st) {
+  ms_status r = policy_cap(p, n);
+  if (r != MS_OK) return r;
+  hipLaunchKernelGGL(k_obs, dim3(blocks((long long)n * p->n_in)), dim3(256), 0, st, n, p->nq, p->nv,
+                     p->free_root, p->n_ref, p->n_obs, p->n_in, q, qd, (float)t, p->ref_seed,
+                     (long long)env0, p->X, obs_out);
+  GemmEpi e1;
+  e1.bias = p->b[0];
+  e1.act = 1;
+  e1.c_bf16 = p->H1;
+  e1.ldc = p->h;
+  hipError_t e = gemm_bf16(false, true, n, p->h, p->n_in, p->X, p->n_in, p->Wb[0], p->n_in, e1, st);
+  if (e != hipSuccess) return hipst(e, "policy gemm 1");
+  GemmEpi e2;
+  e2.bias = p->b[1];
+  e2.act = 1;
+  e2.c_bf16 = p->H2;
+  e2.ldc = p->h;
+  e = gemm_bf16(false, true, n, p->h, p->h, p->H1, p->h, p->Wb[1], p->h, e2, st);
+  if (e != hipSuccess) return hipst(e, "policy gemm 2");
+  GemmEpi e3;
+  e3.bias = p->b[2];
+  e3.act = 2;
+  e3.c_f32 = u;
+  e3.ldc = p->n_mus;
+  e = gemm_bf16(false, true, n, p->n_mus, p->h, p->H2, p->h, p->Wb[2], p->h, e3, st);
+  return hipst(e, "policy gemm 3");
+}
+
+}  // namespace
+}  // namespace ms
+
+extern "C" {
+
+ms_status ms_policy_create(const ms_model *m, int32_t hidden, int32_t n_ref, uint64_t ref_seed,
+                           uint64_t seed, ms_policy **out) {
+  s_err.clear();
+  if (!m || !out || hidden <= 0 || hidden % 8 || n_ref < 0)
+    return sfail(MS_E_ARG, "bad arguments (hidden must be a positive multiple of 8)");
+  ms_model_info info;
+  if (ms_model_info_get(m, &info) != MS_OK) return sfail(MS_E_ARG, "model info failed");
+  ms_policy *p = new ms_policy();
+  p->nq = info.nq;
+  p->nv = info.nv;
+  p->n_mus = info.n_mus;
+  p->free_root = info.nq != info.nv;
+  p->n_ref = n_ref;
+  p->n_obs = 2 * info.nv + n_ref;
+  p->n_in = (p->n_obs + 15) / 16 * 16;
+  p->h = hidden;
+  p->ref_seed = ref_seed;
+  const int in[3] = {p->n_in, p->h, p->h}, outd[3] = {p->h, p->h, p->n_mus};
+  for (int l = 0; l < 3; ++l) {
+    const size_t nw = (size_t)in[l] * outd[l];
+    p->W[l] = palloc<float>(p, nw);
+    p->Wb[l] = palloc<bf16>(p, nw);
+    p->b[l] = palloc<float>(p, outd[l]);
+    if (!p->W[l] || !p->Wb[l] || !p->b[l]) {
+      ms_policy_destroy(p);
+      return sfail(MS_E_ALLOC, "policy allocation failed");
+    }
+    hipLaunchKernelGGL(k_init, dim3(blocks((long long)nw)), dim3(256), 0, 0, p->W[l], (int)nw,
+                       l == 0 ? p->n_obs : in[l], (unsigned long long)seed * 3ull + (unsigned long long)l);
+    hipLaunchKernelGGL(k_to_bf16, dim3(blocks((long long)nw)), dim3(256), 0, 0, p->W[l], p->Wb[l], (int)nw);
+  }
+  hipError_t e = hipDeviceSynchronize();
+  if (e != hipSuccess) {
+    ms_policy_destroy(p);
+    return hipst(e, "policy init");
+  }
+  *out = p;
+  return MS_OK;
+}
+
+void ms_policy_destroy(ms_policy *p) {
+  if (!p) return;
+  (void)hipDeviceSynchronize();
+  for (void *q : p->owned) (void)hipFree(q);
+  delete p;
+}
+
+ms_status ms_policy_dims(const ms_policy *p, int32_t *dims) {
+  if (!p || !dims) return sfail(MS_E_ARG, "NULL argument");
+  dims[0] = p->n_obs;
+  dims[1] = p->n_in;
+  dims[2] = p->h;
+  dims[3] = p->n_mus;
+  return MS_OK;
+}
+
+ms_status ms_policy_params(ms_policy *p, int32_t set, float *W1, float *b1, float *W2, float *b2,
+                           float *W3, float *b3) {
+  if (!p || !W1 || !b1 || !W2 || !b2 || !W3 || !b3) return sfail(MS_E_ARG, "NULL argument");
+  float *hw[3] = {W1, W2, W3}, *hb[3] = {b1, b2, b3};
+  const int in[3] = {p->n_in, p->h, p->h}, outd[3] = {p->h, p->h, p->n_mus};
+  hipError_t e = hipDeviceSynchronize();
+  for (int l = 0; l < 3 && e == hipSuccess; ++l) {
+    const size_t nw = (size_t)in[l] * outd[l];
+    if (set) {
+      e = hipMemcpy(p->W[l], hw[l], 4 * nw, hipMemcpyHostToDevice);
+      if (e == hipSuccess) e = hipMemcpy(p->b[l], hb[l], 4 * outd[l], hipMemcpyHostToDevice);
+      if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_to_bf16, dim3(blocks((long long)nw)), dim3(256), 0, 0, p->W[l], p->Wb[l], (int)nw);
+        e = hipGetLastError();
+      }
+    } else {
+      e = hipMemcpy(hw[l], p->W[l], 4 * nw, hipMemcpyDeviceToHost);
+      if (e == hipSuccess) e = hipMemcpy(hb[l], p->b[l], 4 * outd[l], hipMemcpyDeviceToHost);
+    }
+  }
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  return hipst(e, "policy params copy");
+}
+
+ms_status ms_policy_act(ms_policy *p, int32_t n, const float *q, const float *qd, double t,
+                        int64_t env0, float *u, float *obs_out, void *stream) {
+  s_err.clear();
+  if (!p || n <= 0 || !q || !qd || !u) return sfail(MS_E_ARG, "bad arguments");
+  return policy_forward(p, n, q, qd, t, env0, u, obs_out, (hipStream_t)stream);
+}
+
+ms_status ms_policy_rollout(ms_model *m, ms_policy *p, ms_surrogate *sg, int32_t n_env, float *q,
+                            float *qd, float *act, uint32_t *status, int32_t n_steps, int32_t decim,
+                            double t0, const ms_step_opts *opts, float tol, uint32_t *fb_count,
+                            float *u_record, void *stream) {
+  s_err.clear();
+  if (!m || !p || n_env <= 0 || !q || !qd || !act || !opts || n_steps < 0 || decim <= 0)
+    return sfail(MS_E_ARG, "bad arguments");
+  ms_model_info info;
+  if (ms_model_info_get(m, &info) != MS_OK || info.n_mus != p->n_mus || info.nv != p->nv)
+    return sfail(MS_E_ARG, "policy does not belong to this model");
+  hipStream_t st = (hipStream_t)stream;
+  ms_status r = policy_cap(p, n_env);
+  if (r != MS_OK) return r;
+  for (int t = 0; t < n_steps; t += decim) {
+    const int k = std::min(decim, n_steps - t);
+    r = policy_forward(p, n_env, q, qd, t0 + (double)t * opts->dt, 0, p->U, nullptr, st);
+    if (r != MS_OK) return r;
+    if (u_record) {
+      hipError_t e = hipMemcpyAsync(u_record + (size_t)(t / decim) * n_env * p->n_mus, p->U,
+                                    (size_t)n_env * p->n_mus * 4, hipMemcpyDeviceToDevice, st);
+      if (e != hipSuccess) return hipst(e, "u record");
+    }
+    for (int j = 0; j < (sg ? k : 1); ++j) {
+      ms::KRun rr{};
+      rr.q = q; rr.qd = qd; rr.act = act; rr.status = status; rr.n_env = n_env;
+      rr.dt = opts->dt; rr.contact = opts->contact;
+      rr.u = p->U; rr.u_hold = 1; rr.exc = MS_EXC_ARRAY; rr.env_per_wg = 1;
+      int steps = k;
+      if (sg) {
+        const float *Y = nullptr;
+        r = ms_surrogate_predict(sg, n_env, q, &Y, st);
+        if (r != MS_OK) return r;
+        rr.geomY = Y; rr.fb_tol = tol; rr.fb_count = fb_count;
+        rr.step0 = t + j;
+        steps = 1;
+      }
+      hipError_t e = launch(m, rr, n_env, steps, st);
+      if (e != hipSuccess) return hipst(e, "policy rollout step");
+    }
+  }
+  return MS_OK;
 }
 
 }  // extern "C"

@@ -297,7 +297,7 @@ __device__ __forceinline__ void step_body(const KModel &M, const KRun &Rn, int n
         const int mx = M.mus_ext[mi];
         bad |= !isfinite(act[t]);
         if (exc == EXC_ARRAY) {
-          u[t] = Rn.u ? Rn.u[((size_t)step * Rn.n_env + env) * nm + mx] : 0.0f;
+          u[t] = Rn.u ? Rn.u[((size_t)(Rn.u_hold ? 0 : step) * Rn.n_env + env) * nm + mx] : 0.0f;
         } else if (exc == EXC_IID) {
           u[t] = u24(splitmix64(key ^ (unsigned long long)mx), 40);
         } else {

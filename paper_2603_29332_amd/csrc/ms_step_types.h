@@ -63,6 +63,7 @@ struct KRun {
   float *o_act, *o_L, *o_Ldot, *o_F, *o_r, *o_tau, *o_bias, *o_qdd;
   double *o_H;
   int env_per_wg;  // envs (wavefronts) per workgroup, 1, 2 or 4 (0 = 1)
+  int u_hold;      // array excitations: the same u[n_env][n_mus] for every step
 };
 
 enum { EXC_ARRAY = MS_EXC_ARRAY, EXC_IID = MS_EXC_IID, EXC_AR1 = MS_EXC_AR1 };

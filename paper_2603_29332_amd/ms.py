@@ -28,7 +28,9 @@ EXPORTED = ("ms_model_create", "ms_model_destroy", "ms_model_info_get",
             "ms_surrogate_sample", "ms_surrogate_forward", "ms_surrogate_train_step",
             "ms_surrogate_last_error", "ms_rollout_surrogate",
             "ms_batch_create", "ms_batch_destroy", "ms_batch_rollout", "ms_batch_autotune",
-            "ms_batch_config", "ms_batch_set_config", "ms_batch_last_error")
+            "ms_batch_config", "ms_batch_set_config", "ms_batch_last_error",
+            "ms_policy_create", "ms_policy_destroy", "ms_policy_dims", "ms_policy_params",
+            "ms_policy_act", "ms_policy_rollout")
 
 _fptr = C.POINTER(C.c_float)
 _iptr = C.POINTER(C.c_int32)
@@ -112,6 +114,17 @@ def lib():
     L.ms_rollout_surrogate.argtypes = [vp, vp, C.c_int32, vp, vp, vp, vp, C.POINTER(MsExc),
                                        C.c_int32, C.POINTER(MsOpts), C.c_float, vp, vp]
     L.ms_rollout_surrogate.restype = C.c_int
+    L.ms_policy_create.argtypes = [vp, C.c_int32, C.c_int32, C.c_uint64, C.c_uint64, C.POINTER(vp)]
+    L.ms_policy_destroy.argtypes = [vp]
+    L.ms_policy_destroy.restype = None
+    L.ms_policy_dims.argtypes = [vp, _iptr]
+    L.ms_policy_params.argtypes = [vp, C.c_int32] + [_fptr] * 6
+    L.ms_policy_act.argtypes = [vp, C.c_int32, vp, vp, C.c_double, C.c_int64, vp, vp, vp]
+    L.ms_policy_rollout.argtypes = [vp, vp, vp, C.c_int32, vp, vp, vp, vp, C.c_int32, C.c_int32,
+                                    C.c_double, C.POINTER(MsOpts), C.c_float, vp, vp, vp]
+    for f in ("ms_policy_create", "ms_policy_dims", "ms_policy_params", "ms_policy_act",
+              "ms_policy_rollout"):
+        getattr(L, f).restype = C.c_int
     L.ms_batch_create.argtypes = [C.POINTER(vp), _iptr, C.c_int32, C.POINTER(vp)]
     L.ms_batch_destroy.argtypes = [vp]
     L.ms_batch_destroy.restype = None
@@ -390,3 +403,46 @@ class Batch:
     def set_config(self, env_per_wg, largest_first=0):
         w = np.asarray(env_per_wg, np.int32)
         _check_b(lib().ms_batch_set_config(self.h, w.ctypes.data_as(_iptr), int(largest_first)))
+
+
+class Policy:
+    """Random-initialised policy network of the library bound to a Model
+    (observations of n_ref synthetic reference targets from ref_seed)."""
+
+    def __init__(self, model: Model, hidden: int = 512, n_ref: int = 140, ref_seed: int = 52,
+                 seed: int = 51):
+        L = lib()
+        self.model = model
+        h = C.c_void_p()
+        _check_s(L.ms_policy_create(model.h, hidden, n_ref, ref_seed, seed, C.byref(h)))
+        self.h = h
+        d = np.zeros(4, np.int32)
+        _check_s(L.ms_policy_dims(h, d.ctypes.data_as(_iptr)))
+        self.n_obs, self.n_in, self.hidden, self.n_out = (int(x) for x in d)
+        self.shapes = [(self.hidden, self.n_in), (self.hidden,), (self.hidden, self.hidden),
+                       (self.hidden,), (self.n_out, self.hidden), (self.n_out,)]
+
+    def __del__(self):
+        try:
+            if getattr(self, "h", None):
+                lib().ms_policy_destroy(self.h)
+        except Exception:
+            pass
+
+    def params(self):
+        b = [np.zeros(s, np.float32) for s in self.shapes]
+        _check_s(lib().ms_policy_params(self.h, 0, *[x.ctypes.data_as(_fptr) for x in b]))
+        return b
+
+    def act(self, q, qd, t, u, env0=0, obs=None, stream=None):
+        _check_s(lib().ms_policy_act(self.h, q.shape[0], _dp(q), _dp(qd), float(t), int(env0),
+                                     _dp(u), _dp(obs), _stream(stream)))
+
+    def rollout(self, q, qd, act, status, n_steps, decim, dt, contact=True, t0=0.0,
+                surrogate=None, tol=1e-4, fb_count=None, u_record=None, stream=None):
+        o = MsOpts(dt, int(contact))
+        _check_s(lib().ms_policy_rollout(self.model.h, self.h,
+                                         surrogate.h if surrogate is not None else None,
+                                         q.shape[0], _dp(q), _dp(qd), _dp(act), _dp(status),
+                                         n_steps, decim, float(t0), C.byref(o), float(tol),
+                                         _dp(fb_count), _dp(u_record), _stream(stream)))

@@ -82,6 +82,25 @@ def excitation_iid(seed: int, n_env: int, n_mus: int, step: int, envs=None):
     return _u24(z, 40)
 
 
+def reference_params(seed: int, n_env: int, n_ref: int, envs=None):
+    """Parameters of the synthetic reference targets (stand-in for the
+    retargeted reference motion a tracking policy observes): for env e,
+    target k, sinusoid j, key K = SplitMix64(SplitMix64(seed ^ e) ^ (3k + j))
+    and a, b, c = top 24 bits of SplitMix64(K ^ 0 / 1 / 2) * 2^-24; returns
+    float32 amplitude 0.3 a, frequency 0.5 + 1.5 b (Hz) and phase 2 pi c,
+    each [n_env][n_ref][3]."""
+    e = _envs(n_env, envs).astype(np.uint64)
+    ke = splitmix64(np.uint64(seed) ^ e)[:, None]
+    idx = np.arange(3 * n_ref, dtype=np.uint64)[None, :]
+    key = splitmix64(ke ^ idx)
+    ua, ub, uc = (_u24(splitmix64(key ^ np.uint64(i)), 40) for i in range(3))
+    shape = (len(e), n_ref, 3)
+    amp = (F32(0.3) * ua).astype(F32).reshape(shape)
+    freq = (F32(0.5) + F32(1.5) * ub).astype(F32).reshape(shape)
+    phase = (F32(2.0 * math.pi) * uc).astype(F32).reshape(shape)
+    return amp, freq, phase
+
+
 def ar1_constants(dt: float, corr_time: float = 0.05, sigma: float = 0.25,
                   mean: float = 0.3):
     """float32 constants (rho, s, mean, sqrt3) of the smooth-noise process."""

@@ -21,7 +21,7 @@
 struct ms_batch {
   std::vector<ms_model *> models;
   std::vector<int> n_env;
-  std::vector<int> wpg;        // envs per workgroup per model
+  std::vector<int> wpg;        // envs per workgroup per model (0: most resident envs)
   int issue_largest_first = 0;  // 0: caller's order, 1: most work first
   std::vector<hipStream_t> streams;
   std::vector<hipEvent_t> done;
@@ -125,7 +125,7 @@ ms_status ms_batch_create(ms_model *const *models, const int32_t *n_env, int32_t
     }
     b->models.push_back(models[i]);
     b->n_env.push_back(n_env[i]);
-    b->wpg.push_back(1);
+    b->wpg.push_back(0);
   }
   hipError_t e = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming);
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
@@ -252,7 +252,8 @@ ms_status ms_batch_autotune(ms_batch *b, const ms_batch_state *states, const ms_
     float best = 1e30f;
     int wbest = 1;
     for (int w : choices) {
-      if ((size_t)w * b->models[i]->t.lds_bytes > 160 * 1024) continue;
+      if (b->models[i]->t.lt.size() * 4 + (size_t)w * b->models[i]->t.lds_bytes > 160 * 1024)
+        continue;
       float t_ms = 0.f;
       for (int rep = 0; rep < 2 && r == MS_OK; ++rep) {  // first run warms up
         r = refresh(i);
@@ -300,7 +301,7 @@ ms_status ms_batch_set_config(ms_batch *b, const int32_t *env_per_wg, int32_t la
   for (size_t i = 0; i < b->wpg.size(); ++i) {
     const int w = env_per_wg[i];
     if (w != 1 && w != 2 && w != 4) return bfail(MS_E_ARG, "envs per workgroup must be 1, 2 or 4");
-    if ((size_t)w * b->models[i]->t.lds_bytes > 160 * 1024)
+    if (b->models[i]->t.lt.size() * 4 + (size_t)w * b->models[i]->t.lds_bytes > 160 * 1024)
       return bfail(MS_E_UNSUPPORTED, "workgroup LDS would exceed 160 KiB");
   }
   for (size_t i = 0; i < b->wpg.size(); ++i) b->wpg[i] = env_per_wg[i];

@@ -761,7 +761,7 @@ ms_status ms_policy_rollout(ms_model *m, ms_policy *p, ms_surrogate *sg, int32_t
       ms::KRun rr{};
       rr.q = q; rr.qd = qd; rr.act = act; rr.status = status; rr.n_env = n_env;
       rr.dt = opts->dt; rr.contact = opts->contact;
-      rr.u = p->U; rr.u_hold = 1; rr.exc = MS_EXC_ARRAY; rr.env_per_wg = 1;
+      rr.u = p->U; rr.u_hold = 1; rr.exc = MS_EXC_ARRAY;
       int steps = k;
       if (sg) {
         const float *Y = nullptr;

@@ -207,33 +207,52 @@ ms_status build_tables(const ms_model_desc *d, Tables *t, std::string *msg) {
       if (t->dof_depth[j] == dl + 1) t->dlev_dof.push_back(j);
   }
   t->dlev_start[t->n_dlev] = (int)t->dlev_dof.size();
-  t->desc_start.assign(nv + 1, 0);
+  // the factorisation and both solves as gathers over tree levels, in one
+  // compact table (int32 words) that a workgroup stages in LDS once per launch
+  std::vector<int32_t> desc_start(nv + 1, 0), desc;
   for (int k = 0; k < nv; ++k) {
-    t->desc_start[k] = (int)t->desc.size();
+    desc_start[k] = (int)desc.size();
     for (int i = 0; i < nv; ++i)
-      if (i != k && dof_anc(k, i)) t->desc.push_back(t->row_start[i] | (i << 16));
+      if (i != k && dof_anc(k, i)) desc.push_back(t->row_start[i] | (i << 16));
   }
-  t->desc_start[nv] = (int)t->desc.size();
-  need(t->nnz < 65536 && (int)t->desc.size() < 65536, "mass matrix too large", MS_E_UNSUPPORTED,
-       &st, msg);
-  auto drange = [&](int k) { return t->desc_start[k] | (t->desc_start[k + 1] << 16); };
-  t->hent_start.assign(t->n_hlev + 1, 0);
-  for (int h = 0; h < t->n_hlev; ++h) {
-    t->hent_start[h] = (int)t->hent.size() / 2;
-    for (int e = t->hlev_start[h]; e < t->hlev_start[h + 1]; ++e) {
-      const int k = t->hlev_dof[e], rk = t->row_start[k], ck = t->dof_depth[k] - 1;
-      for (int x = rk; x < t->row_start[k + 1]; ++x) {
-        t->hent.push_back(x | (ck << 16) | ((x - rk) << 24));
-        t->hent.push_back(drange(k));
+  desc_start[nv] = (int)desc.size();
+  need(t->nnz < 65536 && (int)desc.size() < 65536, "mass matrix too large", MS_E_UNSUPPORTED, &st,
+       msg);
+  {
+    std::vector<int32_t> &b = t->lt;
+    auto section = [&](int *off, const std::vector<int32_t> &v) {
+      *off = (int)b.size();
+      b.insert(b.end(), v.begin(), v.end());
+    };
+    std::vector<int32_t> hent, hent_start(t->n_hlev + 1, 0), hdof, drange(nv), dsol, rs(nv + 1);
+    for (int h = 0; h < t->n_hlev; ++h) {
+      hent_start[h] = (int)hent.size();
+      for (int e = t->hlev_start[h]; e < t->hlev_start[h + 1]; ++e) {
+        const int k = t->hlev_dof[e], ck = t->dof_depth[k] - 1;
+        for (int x = 0; x <= ck; ++x) hent.push_back(k | (ck << 8) | (x << 16));
+        hdof.push_back(k | (ck << 8));
       }
-      t->hsol.push_back(k | (ck << 16));
-      t->hsol.push_back(drange(k));
     }
-  }
-  t->hent_start[t->n_hlev] = (int)t->hent.size() / 2;
-  for (int e = 0; e < (int)t->dlev_dof.size(); ++e) {
-    const int k = t->dlev_dof[e];
-    t->dsol.push_back(k | (t->row_start[k] << 8));
+    hent_start[t->n_hlev] = (int)hent.size();
+    for (int k = 0; k < nv; ++k) drange[k] = desc_start[k] | (desc_start[k + 1] << 16);
+    for (int e = 0; e < (int)t->dlev_dof.size(); ++e) {
+      const int k = t->dlev_dof[e];
+      dsol.push_back(k | (t->row_start[k] << 8));
+    }
+    for (int k = 0; k <= nv; ++k) rs[k] = t->row_start[k];
+    std::vector<int32_t> path8((t->nnz + 3) / 4, 0);
+    for (int e = 0; e < t->nnz; ++e) path8[e / 4] |= (t->path[e] & 0xFF) << (8 * (e % 4));
+    section(&t->lt_hent_start, hent_start);
+    section(&t->lt_hlev_start, t->hlev_start);
+    section(&t->lt_dlev_start, t->dlev_start);
+    section(&t->lt_hent, hent);
+    section(&t->lt_hdof, hdof);
+    section(&t->lt_desc, desc);
+    section(&t->lt_drange, drange);
+    section(&t->lt_dsol, dsol);
+    section(&t->lt_rs, rs);
+    section(&t->lt_path, path8);
+    b.resize((b.size() + 3) / 4 * 4, 0);  // 16-byte multiple
   }
 
   // muscles

@@ -63,13 +63,17 @@ struct Tables {
   // (leaves first) and by depth (root first)
   int n_hlev = 0, n_dlev = 0;
   std::vector<int32_t> hlev_start, hlev_dof, dlev_start, dlev_dof;
-  // the factorisation and solves as gathers. desc: per DoF its proper
-  // descendants (row start | id << 16), CSR desc_start. hent: per height
-  // level its rows' entries as pairs (entry | depth(row) << 16 |
-  // depth(column) << 24, desc range of the row: begin | end << 16).
-  // hsol: per height-level DoF (id | depth << 16, desc range). dsol: per
-  // depth-level DoF (id | row start << 8).
-  std::vector<int32_t> hent_start, hent, desc_start, desc, hsol, dsol;
+  // The factorisation and solves as gathers over tree levels, one int32
+  // table (lt) staged in LDS per workgroup; lt_* are word offsets of its
+  // sections: hent_start / hlev_start / dlev_start (level starts), hent
+  // (per height level, its rows' entries: row | depth(row) << 8 |
+  // depth(column) << 16), hdof (per height level, its DoFs: id | depth << 8),
+  // desc (per DoF its proper descendants: row start | id << 16), drange (per
+  // DoF its desc range: begin | end << 16), dsol (per depth level, its DoFs:
+  // id | row start << 8), rs (row starts), path (path[] as bytes).
+  std::vector<int32_t> lt;
+  int lt_hent_start = 0, lt_hlev_start = 0, lt_dlev_start = 0, lt_hent = 0, lt_hdof = 0,
+      lt_desc = 0, lt_drange = 0, lt_dsol = 0, lt_rs = 0, lt_path = 0;
   // LDS layout (byte offsets into the per-env LDS block)
   int off_q = 0, off_qd = 0, off_R = 0, off_P = 0, off_S = 0, off_V = 0,
       off_A = 0, off_F = 0, off_con = 0, off_rhs = 0, off_H = 0, off_x = 0,

@@ -104,8 +104,7 @@ ms_status ms_model_create(const ms_model_desc *desc, ms_model **out) {
          o_rs = p.add(t.row_start), o_dd = p.add(t.dof_depth), o_path = p.add(t.path),
          o_nr = p.add(t.nnz_row), o_hs = p.add(t.hlev_start),
          o_hd = p.add(t.hlev_dof), o_ds2 = p.add(t.dlev_start), o_dd2 = p.add(t.dlev_dof),
-         o_hes = p.add(t.hent_start), o_he = p.add(t.hent), o_dsc = p.add(t.desc),
-         o_hso = p.add(t.hsol), o_dso = p.add(t.dsol);
+         o_lt = p.add(t.lt);
   m->dbytes = p.buf.size();
   hipError_t e = hipMalloc(&m->dbuf, m->dbytes);
   if (e != hipSuccess) {
@@ -145,8 +144,12 @@ ms_status ms_model_create(const ms_model_desc *desc, ms_model **out) {
   P_(proj_item, o_pi, int); P_(dent_h, o_dh, int); P_(dent_start, o_ds, int);
   P_(dent_item, o_di, int); P_(row_start, o_rs, int); P_(dof_depth, o_dd, int);
   P_(path, o_path, int); P_(nnz_row, o_nr, int);
-  P_(hent_start, o_hes, int); P_(hent, o_he, int2); P_(desc, o_dsc, int); P_(hsol, o_hso, int2);
-  P_(dsol, o_dso, int);
+  P_(lt, o_lt, int);
+  k.lt_words = (int)t.lt.size();
+  k.lt_hent_start = t.lt_hent_start; k.lt_hlev_start = t.lt_hlev_start;
+  k.lt_dlev_start = t.lt_dlev_start; k.lt_hent = t.lt_hent; k.lt_hdof = t.lt_hdof;
+  k.lt_desc = t.lt_desc; k.lt_drange = t.lt_drange; k.lt_dsol = t.lt_dsol; k.lt_rs = t.lt_rs;
+  k.lt_path = t.lt_path;
   P_(hlev_start, o_hs, int); P_(hlev_dof, o_hd, int); P_(dlev_start, o_ds2, int);
   P_(dlev_dof, o_dd2, int);
 #undef P_
@@ -218,7 +221,7 @@ ms_status ms_step_batch(ms_model *m, int32_t n_env, float *q, float *qd, float *
 ms_status ms_rollout(ms_model *m, int32_t n_env, float *q, float *qd, float *act,
                      uint32_t *status, const ms_excitation *exc, int32_t n_steps,
                      const ms_step_opts *opts, void *stream) {
-  return rollout_impl(m, n_env, q, qd, act, status, exc, n_steps, opts, 1, (hipStream_t)stream);
+  return rollout_impl(m, n_env, q, qd, act, status, exc, n_steps, opts, 0, (hipStream_t)stream);
 }
 
 }  // extern "C"

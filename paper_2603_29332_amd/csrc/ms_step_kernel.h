@@ -229,12 +229,19 @@ template <int MPL, int NVIA, bool SURR, bool GEOM>
 __device__ __forceinline__ void step_body(const KModel &M, const KRun &Rn, int n_steps) {
   // a workgroup holds blockDim.x / 64 envs, one per wavefront, each with its
   // own LDS block; envs never synchronise with each other
+  // LDS: the factorisation's gather tables (shared by the workgroup's envs,
+  // staged once per launch), then one block per env.
   extern __shared__ __align__(16) unsigned char lds_all[];
   const int wave = threadIdx.x >> 6;
   const int env = blockIdx.x * (blockDim.x >> 6) + wave;
   const int lane = threadIdx.x & 63;
+  int *LT = (int *)lds_all;
+  if (!GEOM) {
+    for (int i = threadIdx.x; i < M.lt_words; i += blockDim.x) LT[i] = M.lt[i];
+    __syncthreads();  // the only workgroup-wide barrier: every wavefront reaches it
+  }
   if (env >= Rn.n_env) return;
-  unsigned char *lds = lds_all + (size_t)wave * M.lds_env;
+  unsigned char *lds = lds_all + (GEOM ? 0 : (size_t)M.lt_words * 4) + (size_t)wave * M.lds_env;
   const int nq = M.nq, nv = M.nv, nm = M.n_mus, nn = M.n_node;
   float *__restrict__ q = (float *)(lds + M.off_q);
   float *__restrict__ qd = (float *)(lds + M.off_qd);
@@ -693,6 +700,7 @@ __device__ __forceinline__ void step_body(const KModel &M, const KRun &Rn, int n
       wave_sync();
       for (int j = lane; j < nv; j += 64) {
         float tau = 0.f;
+#pragma unroll 8
         for (int e = M.proj_start[j]; e < M.proj_start[j + 1]; ++e) {
           const int it = M.proj_item[e];
           tau += mr[it] * mF[it / 3];
@@ -702,6 +710,7 @@ __device__ __forceinline__ void step_body(const KModel &M, const KRun &Rn, int n
       }
       for (int e = lane; e < M.n_dent; e += 64) {
         double s = 0.0;
+#pragma unroll 8
         for (int k = M.dent_start[e]; k < M.dent_start[e + 1]; ++k) {
           const int it = M.dent_item[k];
           const int m = it >> 4, a = (it >> 2) & 3, b = it & 3;
@@ -721,25 +730,27 @@ __device__ __forceinline__ void step_body(const KModel &M, const KRun &Rn, int n
     // H_ik H_ij / d_i (j = k or an ancestor of k), and reads only finished
     // rows of lower height. Rows of equal height are independent, so a
     // height level is one pass over its entries; when a level has few
-    // entries, P lanes split each entry's sum (fixed-order butterfly).
+    // entries, P lanes split each entry's sum (fixed-order butterfly). All
+    // tables come from the workgroup's LDS copy.
     bool nonspd = false;
     double *invd = (double *)scr;  // 1/d per DoF (the muscle scratch is free now)
+    const int *Lrs = LT + M.lt_rs, *Ldesc = LT + M.lt_desc, *Ldr = LT + M.lt_drange;
     for (int h = 0; h < M.n_hlev; ++h) {
       if (h > 0) {  // leaves have no descendants
-        const int s0 = M.hent_start[h], ne = M.hent_start[h + 1] - s0;
+        const int s0 = LT[M.lt_hent_start + h], ne = LT[M.lt_hent_start + h + 1] - s0;
         const int lp = group_log2(ne), P = 1 << lp;
         for (int base = 0; base < (ne << lp); base += 64) {
           const int idx = base + lane, g = idx >> lp, p = idx & (P - 1);
           double sum = 0.0;
           int e = 0;
           if (g < ne) {
-            const int2 w = M.hent[s0 + g];
-            e = w.x & 0xFFFF;
-            const int ck = (w.x >> 16) & 0xFF, cj = (w.x >> 24) & 0xFF;
-            const int t1 = w.y >> 16;
+            const int w = LT[M.lt_hent + s0 + g];
+            const int k = w & 0xFF, ck = (w >> 8) & 0xFF, cj = w >> 16;
+            e = Lrs[k] + cj;
+            const int dr = Ldr[k], t1 = dr >> 16;
 #pragma unroll 4
-            for (int t = (w.y & 0xFFFF) + p; t < t1; t += P) {
-              const int di = M.desc[t];
+            for (int t = (dr & 0xFFFF) + p; t < t1; t += P) {
+              const int di = Ldesc[t];
               const int ri = di & 0xFFFF;
               sum += H[ri + ck] * H[ri + cj] * invd[di >> 16];
             }
@@ -750,9 +761,10 @@ __device__ __forceinline__ void step_body(const KModel &M, const KRun &Rn, int n
         wave_sync();
       }
       bool bad = false;
-      for (int e = M.hlev_start[h] + lane; e < M.hlev_start[h + 1]; e += 64) {
-        const int k = M.hlev_dof[e];
-        const double d = H[M.row_start[k] + M.dof_depth[k] - 1];
+      for (int e = LT[M.lt_hlev_start + h] + lane; e < LT[M.lt_hlev_start + h + 1]; e += 64) {
+        const int w = LT[M.lt_hdof + e];
+        const int k = w & 0xFF;
+        const double d = H[Lrs[k] + (w >> 8)];
         bad |= !(d > 0.0);
         invd[k] = 1.0 / d;
       }
@@ -765,19 +777,20 @@ __device__ __forceinline__ void step_body(const KModel &M, const KRun &Rn, int n
     if (!nonspd) {
       // L^T y = rhs, leaves first: y_k = rhs_k - sum_{i desc. of k} (H_ik / d_i) y_i
       for (int h = 0; h < M.n_hlev; ++h) {
-        const int s0 = M.hlev_start[h], ne = M.hlev_start[h + 1] - s0;
+        const int s0 = LT[M.lt_hlev_start + h], ne = LT[M.lt_hlev_start + h + 1] - s0;
         const int lp = group_log2(ne), P = 1 << lp;
         for (int base = 0; base < (ne << lp); base += 64) {
           const int idx = base + lane, g = idx >> lp, p = idx & (P - 1);
           double sum = 0.0;
           int k = 0;
           if (g < ne) {
-            const int2 w = M.hsol[s0 + g];
-            k = w.x & 0xFFFF;
-            const int ck = w.x >> 16, t1 = w.y >> 16;
+            const int w = LT[M.lt_hdof + s0 + g];
+            k = w & 0xFF;
+            const int ck = w >> 8;
+            const int dr = Ldr[k], t1 = dr >> 16;
 #pragma unroll 4
-            for (int t = (w.y & 0xFFFF) + p; t < t1; t += P) {
-              const int di = M.desc[t];
+            for (int t = (dr & 0xFFFF) + p; t < t1; t += P) {
+              const int di = Ldesc[t];
               const int i = di >> 16;
               sum += H[(di & 0xFFFF) + ck] * invd[i] * xs[i];
             }
@@ -790,19 +803,20 @@ __device__ __forceinline__ void step_body(const KModel &M, const KRun &Rn, int n
       for (int j = lane; j < nv; j += 64) xs[j] *= invd[j];
       wave_sync();
       // L x = z, root first: x_k = z_k - (1/d_k) sum_{a anc. of k} H_ka x_a
+      const unsigned char *path8 = (const unsigned char *)(LT + M.lt_path);
       for (int dl = 1; dl < M.n_dlev; ++dl) {
-        const int s0 = M.dlev_start[dl], ne = M.dlev_start[dl + 1] - s0;
+        const int s0 = LT[M.lt_dlev_start + dl], ne = LT[M.lt_dlev_start + dl + 1] - s0;
         const int lp = group_log2(ne), P = 1 << lp;
         for (int base = 0; base < (ne << lp); base += 64) {
           const int idx = base + lane, g = idx >> lp, p = idx & (P - 1);
           double sum = 0.0;
           int k = 0;
           if (g < ne) {
-            const int w = M.dsol[s0 + g];
+            const int w = LT[M.lt_dsol + s0 + g];
             k = w & 0xFF;
             const int rk = w >> 8;
 #pragma unroll 4
-            for (int a = p; a < dl; a += P) sum += H[rk + a] * xs[M.path[rk + a]];
+            for (int a = p; a < dl; a += P) sum += H[rk + a] * xs[path8[rk + a]];
           }
           sum = group_sum(sum, lp);
           if (g < ne && p == 0) xs[k] -= sum * invd[k];
@@ -909,12 +923,29 @@ __global__ __launch_bounds__(256) void k_geometry(KModel M, KRun Rn, int n_steps
   step_body<MPL, NVIA, false, true>(M, Rn, n_steps);
 }
 
+// Envs per workgroup that keep the most envs resident per CU (160 KiB of
+// LDS; the workgroup's copy of the factorisation tables is shared by its
+// envs); ties go to fewer envs per workgroup.
+inline int default_env_per_wg(const Tables &t) {
+  int best = 1, most = 0;
+  for (int w = 1; w <= 4; w *= 2) {
+    const size_t per_wg = t.lt.size() * 4 + (size_t)w * t.lds_bytes;
+    if (per_wg > 160 * 1024) break;
+    const int envs = w * (int)((160 * 1024) / per_wg);
+    if (envs > most) {
+      most = envs;
+      best = w;
+    }
+  }
+  return best;
+}
+
 template <int MPL, int NVIA>
 hipError_t launch_k(const Tables &t, const KModel &k, const KRun &r, int n_env, int n_steps,
                     hipStream_t st) {
   const bool geom = r.stages == 2, surr = r.geomY != nullptr;
-  const int W = r.env_per_wg > 0 ? r.env_per_wg : 1;
-  const size_t lds = (size_t)W * t.lds_bytes;
+  const int W = r.env_per_wg > 0 ? r.env_per_wg : default_env_per_wg(t);
+  const size_t lds = (geom ? 0 : t.lt.size() * 4) + (size_t)W * t.lds_bytes;
   const void *fn = geom ? (const void *)&k_geometry<MPL, NVIA>
                    : surr ? (const void *)&k_step_surrogate<MPL, NVIA>
                           : (const void *)&k_step<MPL, NVIA>;

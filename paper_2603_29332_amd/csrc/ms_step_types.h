@@ -32,9 +32,10 @@ struct KModel {
   const int *row_start, *dof_depth, *path, *nnz_row;
   int n_hlev, n_dlev;
   const int *hlev_start, *hlev_dof, *dlev_start, *dlev_dof;
-  const int *hent_start, *desc;
-  const int2 *hent, *hsol;
-  const int *dsol;
+  // the factorisation's gather tables (staged in LDS per workgroup)
+  const int *lt;
+  int lt_words, lt_hent_start, lt_hlev_start, lt_dlev_start, lt_hent, lt_hdof, lt_desc, lt_drange,
+      lt_dsol, lt_rs, lt_path;
   int off_flag, off_q, off_qd, off_R, off_P, off_S, off_con, off_rhs, off_x, off_H,
       off_scr, off_V, off_A, off_F, off_tree;
   int lds_env;  // bytes of one env's LDS block
@@ -62,7 +63,7 @@ struct KRun {
   // stage outputs (ms_step_stages)
   float *o_act, *o_L, *o_Ldot, *o_F, *o_r, *o_tau, *o_bias, *o_qdd;
   double *o_H;
-  int env_per_wg;  // envs (wavefronts) per workgroup, 1, 2 or 4 (0 = 1)
+  int env_per_wg;  // envs (wavefronts) per workgroup, 1, 2 or 4 (0: the most resident envs)
   int u_hold;      // array excitations: the same u[n_env][n_mus] for every step
 };
 
@@ -93,7 +94,8 @@ struct ms_model {
 // or geometry only) for n_env envs and n_steps steps on stream st.
 hipError_t launch(const ms_model *m, const ms::KRun &r, int n_env, int n_steps, hipStream_t st);
 
-// ms_rollout with a chosen number of envs per workgroup (1, 2 or 4); errors
+// ms_rollout with a chosen number of envs per workgroup (1, 2 or 4; 0 picks
+// the count that keeps the most envs resident per CU); errors
 // as ms_rollout (message in ms_last_error).
 ms_status rollout_impl(ms_model *m, int32_t n_env, float *q, float *qd, float *act,
                        uint32_t *status, const ms_excitation *exc, int32_t n_steps,

@@ -143,10 +143,28 @@ __device__ __forceinline__ int group_log2(int n) {
   return l;
 }
 
-// sum over aligned groups of 2^lp lanes, fixed butterfly order; every lane of
-// a group gets the same value
-__device__ __forceinline__ double group_sum(double v, int lp) {
-  for (int o = (1 << lp) >> 1; o > 0; o >>= 1) v += __shfl_xor(v, o);
+// A double moved across lanes by a DPP control (rows of 16 lanes; lanes with
+// no source, or in rows outside ROWS, read 0).
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_d(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, ROWS, 0xF, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROWS, 0xF, true);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// Inclusive prefix sums within aligned groups of 2^lp lanes, in a fixed
+// order (shift-and-add within rows of 16, then the row totals carried by
+// row broadcasts); the group's total ends in its last lane.
+__device__ __forceinline__ double group_sum_last(double v, int lp, int lane) {
+  const int p = lane & ((1 << lp) - 1);
+  double t;
+  if (lp >= 1) { t = dpp_d<0x111, 0xF>(v); if (p >= 1) v += t; }   // row_shr:1
+  if (lp >= 2) { t = dpp_d<0x112, 0xF>(v); if (p >= 2) v += t; }   // row_shr:2
+  if (lp >= 3) { t = dpp_d<0x114, 0xF>(v); if (p >= 4) v += t; }   // row_shr:4
+  if (lp >= 4) { t = dpp_d<0x118, 0xF>(v); if (p >= 8) v += t; }   // row_shr:8
+  if (lp >= 5) { t = dpp_d<0x142, 0xA>(v); if (p >= 16) v += t; }  // row_bcast:15
+  if (lp >= 6) { t = dpp_d<0x143, 0xC>(v); if (p >= 32) v += t; }  // row_bcast:31
   return v;
 }
 
@@ -755,8 +773,8 @@ __device__ __forceinline__ void step_body(const KModel &M, const KRun &Rn, int n
               sum += H[ri + ck] * H[ri + cj] * invd[di >> 16];
             }
           }
-          sum = group_sum(sum, lp);
-          if (g < ne && p == 0) H[e] -= sum;
+          sum = group_sum_last(sum, lp, lane);
+          if (g < ne && p == P - 1) H[e] -= sum;
         }
         wave_sync();
       }
@@ -795,8 +813,8 @@ __device__ __forceinline__ void step_body(const KModel &M, const KRun &Rn, int n
               sum += H[(di & 0xFFFF) + ck] * invd[i] * xs[i];
             }
           }
-          sum = group_sum(sum, lp);
-          if (g < ne && p == 0) xs[k] = rhs[k] - sum;
+          sum = group_sum_last(sum, lp, lane);
+          if (g < ne && p == P - 1) xs[k] = rhs[k] - sum;
         }
         wave_sync();
       }
@@ -818,8 +836,8 @@ __device__ __forceinline__ void step_body(const KModel &M, const KRun &Rn, int n
 #pragma unroll 4
             for (int a = p; a < dl; a += P) sum += H[rk + a] * xs[path8[rk + a]];
           }
-          sum = group_sum(sum, lp);
-          if (g < ne && p == 0) xs[k] -= sum * invd[k];
+          sum = group_sum_last(sum, lp, lane);
+          if (g < ne && p == P - 1) xs[k] -= sum * invd[k];
         }
         wave_sync();
       }

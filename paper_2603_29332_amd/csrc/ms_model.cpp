@@ -230,6 +230,7 @@ ms_status build_tables(const ms_model_desc *d, Tables *t, std::string *msg) {
       for (int e = t->hlev_start[h]; e < t->hlev_start[h + 1]; ++e) {
         const int k = t->hlev_dof[e], ck = t->dof_depth[k] - 1;
         for (int x = 0; x <= ck; ++x) hent.push_back(k | (ck << 8) | (x << 16));
+        hent.push_back(k | (ck << 8) | (255 << 16));  // the right-hand side column
         hdof.push_back(k | (ck << 8));
       }
     }

@@ -67,7 +67,7 @@ struct Tables {
   // table (lt) staged in LDS per workgroup; lt_* are word offsets of its
   // sections: hent_start / hlev_start / dlev_start (level starts), hent
   // (per height level, its rows' entries: row | depth(row) << 8 |
-  // depth(column) << 16), hdof (per height level, its DoFs: id | depth << 8),
+  // depth(column) << 16, depth 255 standing for the right-hand side), hdof (per height level, its DoFs: id | depth << 8),
   // desc (per DoF its proper descendants: row start | id << 16), drange (per
   // DoF its desc range: begin | end << 16), dsol (per depth level, its DoFs:
   // id | row start << 8), rs (row starts), path (path[] as bytes).

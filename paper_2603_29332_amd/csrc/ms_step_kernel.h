@@ -746,13 +746,17 @@ __device__ __forceinline__ void step_body(const KModel &M, const KRun &Rn, int n
     // H = L^T D L with Featherstone's branch-induced sparsity, as gathers:
     // finished row k holds H_kj - sum over the descendants i of k of
     // H_ik H_ij / d_i (j = k or an ancestor of k), and reads only finished
-    // rows of lower height. Rows of equal height are independent, so a
-    // height level is one pass over its entries; when a level has few
-    // entries, P lanes split each entry's sum (fixed-order butterfly). All
-    // tables come from the workgroup's LDS copy.
+    // rows of lower height. The right-hand side rides along as one more
+    // column: y_k = rhs_k - sum_i (H_ik / d_i) y_i is the solve of L^T y =
+    // rhs. Rows of equal height are independent, so a height level is one
+    // pass over its entries; when a level has few entries, P lanes split each
+    // entry's sum (fixed-order prefix sums). All tables come from the
+    // workgroup's LDS copy.
     bool nonspd = false;
     double *invd = (double *)scr;  // 1/d per DoF (the muscle scratch is free now)
     const int *Lrs = LT + M.lt_rs, *Ldesc = LT + M.lt_desc, *Ldr = LT + M.lt_drange;
+    for (int j = lane; j < nv; j += 64) xs[j] = rhs[j];
+    wave_sync();
     for (int h = 0; h < M.n_hlev; ++h) {
       if (h > 0) {  // leaves have no descendants
         const int s0 = LT[M.lt_hent_start + h], ne = LT[M.lt_hent_start + h + 1] - s0;
@@ -760,21 +764,30 @@ __device__ __forceinline__ void step_body(const KModel &M, const KRun &Rn, int n
         for (int base = 0; base < (ne << lp); base += 64) {
           const int idx = base + lane, g = idx >> lp, p = idx & (P - 1);
           double sum = 0.0;
-          int e = 0;
+          int e = 0, kk = 0;
+          bool rcol = false;
           if (g < ne) {
             const int w = LT[M.lt_hent + s0 + g];
             const int k = w & 0xFF, ck = (w >> 8) & 0xFF, cj = w >> 16;
-            e = Lrs[k] + cj;
+            rcol = cj == 255;
+            kk = k;
+            e = Lrs[k] + (rcol ? 0 : cj);
             const int dr = Ldr[k], t1 = dr >> 16;
 #pragma unroll 4
             for (int t = (dr & 0xFFFF) + p; t < t1; t += P) {
               const int di = Ldesc[t];
-              const int ri = di & 0xFFFF;
-              sum += H[ri + ck] * H[ri + cj] * invd[di >> 16];
+              const int ri = di & 0xFFFF, i = di >> 16;
+              const double hij = rcol ? xs[i] : H[ri + cj];
+              sum += H[ri + ck] * hij * invd[i];
             }
           }
           sum = group_sum_last(sum, lp, lane);
-          if (g < ne && p == P - 1) H[e] -= sum;
+          if (g < ne && p == P - 1) {
+            if (rcol)
+              xs[kk] = rhs[kk] - sum;
+            else
+              H[e] -= sum;
+          }
         }
         wave_sync();
       }
@@ -793,31 +806,6 @@ __device__ __forceinline__ void step_body(const KModel &M, const KRun &Rn, int n
       wave_sync();
     }
     if (!nonspd) {
-      // L^T y = rhs, leaves first: y_k = rhs_k - sum_{i desc. of k} (H_ik / d_i) y_i
-      for (int h = 0; h < M.n_hlev; ++h) {
-        const int s0 = LT[M.lt_hlev_start + h], ne = LT[M.lt_hlev_start + h + 1] - s0;
-        const int lp = group_log2(ne), P = 1 << lp;
-        for (int base = 0; base < (ne << lp); base += 64) {
-          const int idx = base + lane, g = idx >> lp, p = idx & (P - 1);
-          double sum = 0.0;
-          int k = 0;
-          if (g < ne) {
-            const int w = LT[M.lt_hdof + s0 + g];
-            k = w & 0xFF;
-            const int ck = w >> 8;
-            const int dr = Ldr[k], t1 = dr >> 16;
-#pragma unroll 4
-            for (int t = (dr & 0xFFFF) + p; t < t1; t += P) {
-              const int di = Ldesc[t];
-              const int i = di >> 16;
-              sum += H[(di & 0xFFFF) + ck] * invd[i] * xs[i];
-            }
-          }
-          sum = group_sum_last(sum, lp, lane);
-          if (g < ne && p == P - 1) xs[k] = rhs[k] - sum;
-        }
-        wave_sync();
-      }
       for (int j = lane; j < nv; j += 64) xs[j] *= invd[j];
       wave_sync();
       // L x = z, root first: x_k = z_k - (1/d_k) sum_{a anc. of k} H_ka x_a

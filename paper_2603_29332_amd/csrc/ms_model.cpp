@@ -269,6 +269,7 @@ ms_status build_tables(const ms_model_desc *d, Tables *t, std::string *msg) {
   t->via_node.assign((size_t)kMaxVia * nm, -1);
   t->via_pos.assign((size_t)kMaxVia * 3 * nm, 0.0f);
   t->mus_span.assign((size_t)3 * nm, -1);
+  t->mus_srec.assign((size_t)3 * nm, -1);
   t->mus_mask.assign(nm, 0u);
   t->mus_nvia.assign(nm, 0);
   std::vector<std::vector<int>> proj(nv);
@@ -338,6 +339,8 @@ ms_status build_tables(const ms_model_desc *d, Tables *t, std::string *msg) {
     if (st != MS_OK) return st;
     for (size_t s = 0; s < span.size(); ++s) {
       t->mus_span[s * nm + m] = span[s];
+      t->mus_srec[s * nm + m] = span[s] | ((t->dof_kind[span[s]] == 0 ? 1 : 0) << 8) |
+                                (t->dof_node[span[s]] << 16);
       t->mus_mask[m] |= masks[s] << (8 * s);
       proj[span[s]].push_back(m * 3 + (int)s);
     }

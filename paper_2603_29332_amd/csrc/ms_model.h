@@ -51,6 +51,7 @@ struct Tables {
   std::vector<int32_t> via_node;          // [kMaxVia][n_mus] SoA, padded
   std::vector<float> via_pos;             // [kMaxVia][3][n_mus] SoA, padded
   std::vector<int32_t> mus_span;          // [3][n_mus], -1 pad
+  std::vector<int32_t> mus_srec;          // [3][n_mus]: DoF | hinge << 8 | node << 16, -1 pad
   std::vector<uint32_t> mus_mask;         // [n_mus] 3 x 8-bit via masks
   // reductions over muscle products
   std::vector<int32_t> proj_start;        // [nv+1]

@@ -96,7 +96,7 @@ ms_status ms_model_create(const ms_model_desc *desc, ms_model **out) {
          o_dk = p.add(t.dof_kind), o_damp = p.add(t.damping), o_f0 = p.add(t.mus_f0),
          o_il = p.add(t.mus_ilopt), o_ls2 = p.add(t.mus_lslack), o_ivl = p.add(t.mus_ivl),
          o_ta = p.add(t.mus_tact), o_td = p.add(t.mus_tdeact), o_nvia = p.add(t.mus_nvia),
-         o_vn = p.add(t.via_node), o_vp = p.add(t.via_pos), o_span = p.add(t.mus_span),
+         o_vn = p.add(t.via_node), o_vp = p.add(t.via_pos), o_span = p.add(t.mus_span), o_srec = p.add(t.mus_srec),
          o_mext = p.add(t.mus_ext), o_mint = p.add(t.mus_int), o_gnv = p.add(t.grp_nvia),
          o_qlo = p.add(t.qlo), o_qhi = p.add(t.qhi),
          o_mask = p.add(t.mus_mask), o_ps = p.add(t.proj_start), o_pi = p.add(t.proj_item),
@@ -140,7 +140,7 @@ ms_status ms_model_create(const ms_model_desc *desc, ms_model **out) {
   P_(mus_nvia, o_nvia, int); P_(via_node, o_vn, int); P_(via_pos, o_vp, float);
   P_(mus_ext, o_mext, int); P_(mus_int, o_mint, int); P_(grp_nvia, o_gnv, int);
   P_(qlo, o_qlo, float); P_(qhi, o_qhi, float);
-  P_(mus_span, o_span, int); P_(mus_mask, o_mask, unsigned); P_(proj_start, o_ps, int);
+  P_(mus_span, o_span, int); P_(mus_srec, o_srec, int); P_(mus_mask, o_mask, unsigned); P_(proj_start, o_ps, int);
   P_(proj_item, o_pi, int); P_(dent_h, o_dh, int); P_(dent_start, o_ds, int);
   P_(dent_item, o_di, int); P_(row_start, o_rs, int); P_(dof_depth, o_dd, int);
   P_(path, o_path, int); P_(nnz_row, o_nr, int);

@@ -213,13 +213,14 @@ __device__ __forceinline__ float muscle_geometry(const KModel &M, int m, int Pg,
 #pragma unroll
   for (int s = 0; s < 3; ++s) {
     r3[s] = 0.f;
-    const int j = M.mus_span[s * nm + m];
-    if (j >= 0) {
+    const int rec = M.mus_srec[s * nm + m];
+    if (rec >= 0) {
+      const int j = rec & 0xFF;
       const unsigned mk = (mask >> (8 * s)) & 0xFFu;
       const float *S = Sl + 6 * j;
       float dl;
-      if (M.dof_kind[j] == 0) {
-        V3 o = ld3(Pl + 12 * M.dof_node[j]);
+      if ((rec >> 8) & 1) {
+        V3 o = ld3(Pl + 12 * (rec >> 16));
         V3 acc = v3(0.f, 0.f, 0.f);
 #pragma unroll
         for (int k = 0; k < NVIA; ++k)

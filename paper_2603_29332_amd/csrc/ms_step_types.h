@@ -25,7 +25,7 @@ struct KModel {
   const int *mus_nvia, *via_node, *mus_ext, *mus_int, *grp_nvia;
   const float *qlo, *qhi;
   const float *via_pos;
-  const int *mus_span;
+  const int *mus_span, *mus_srec;
   const unsigned *mus_mask;
   const int *proj_start, *proj_item;
   const int *dent_h, *dent_start, *dent_item;

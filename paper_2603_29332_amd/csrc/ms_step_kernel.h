@@ -756,54 +756,72 @@ __device__ __forceinline__ void step_body(const KModel &M, const KRun &Rn, int n
     bool nonspd = false;
     double *invd = (double *)scr;  // 1/d per DoF (the muscle scratch is free now)
     const int *Lrs = LT + M.lt_rs, *Ldesc = LT + M.lt_desc, *Ldr = LT + M.lt_drange;
+    // leaves: y = rhs, pivots as assembled
+    bool fbad = false;
     for (int j = lane; j < nv; j += 64) xs[j] = rhs[j];
+    for (int e = LT[M.lt_hlev_start] + lane; e < LT[M.lt_hlev_start + 1]; e += 64) {
+      const int w = LT[M.lt_hdof + e];
+      const int k = w & 0xFF;
+      const double d = H[Lrs[k] + (w >> 8)];
+      fbad |= !(d > 0.0);
+      invd[k] = 1.0 / d;
+    }
+    nonspd = __any(fbad);
     wave_sync();
-    for (int h = 0; h < M.n_hlev; ++h) {
-      if (h > 0) {  // leaves have no descendants
-        const int s0 = LT[M.lt_hent_start + h], ne = LT[M.lt_hent_start + h + 1] - s0;
-        const int lp = group_log2(ne), P = 1 << lp;
-        for (int base = 0; base < (ne << lp); base += 64) {
-          const int idx = base + lane, g = idx >> lp, p = idx & (P - 1);
-          double sum = 0.0;
-          int e = 0, kk = 0;
-          bool rcol = false;
-          if (g < ne) {
-            const int w = LT[M.lt_hent + s0 + g];
-            const int k = w & 0xFF, ck = (w >> 8) & 0xFF, cj = w >> 16;
-            rcol = cj == 255;
-            kk = k;
-            e = Lrs[k] + (rcol ? 0 : cj);
-            const int dr = Ldr[k], t1 = dr >> 16;
+    // one entry of a row at height >= 1: finished value (and its pivot when
+    // it is the diagonal) from the descendants' finished rows
+    auto entry = [&](int w, int p, int P, double &sum, int &e, int &k, int &ck, int &cj) {
+      k = w & 0xFF;
+      ck = (w >> 8) & 0xFF;
+      cj = w >> 16;
+      const bool rcol = cj == 255;
+      e = Lrs[k] + (rcol ? 0 : cj);
+      const int dr = Ldr[k], t1 = dr >> 16;
+      sum = 0.0;
 #pragma unroll 4
-            for (int t = (dr & 0xFFFF) + p; t < t1; t += P) {
-              const int di = Ldesc[t];
-              const int ri = di & 0xFFFF, i = di >> 16;
-              const double hij = rcol ? xs[i] : H[ri + cj];
-              sum += H[ri + ck] * hij * invd[i];
-            }
-          }
-          sum = group_sum_last(sum, lp, lane);
-          if (g < ne && p == P - 1) {
-            if (rcol)
-              xs[kk] = rhs[kk] - sum;
-            else
-              H[e] -= sum;
-          }
+      for (int t = (dr & 0xFFFF) + p; t < t1; t += P) {
+        const int di = Ldesc[t];
+        const int ri = di & 0xFFFF, i = di >> 16;
+        const double hij = rcol ? xs[i] : H[ri + cj];
+        sum += H[ri + ck] * hij * invd[i];
+      }
+    };
+    auto finish = [&](double sum, int e, int k, int ck, int cj, bool &badf) {
+      if (cj == 255) {
+        xs[k] = rhs[k] - sum;
+      } else {
+        const double v = H[e] - sum;
+        H[e] = v;
+        if (cj == ck) {
+          badf |= !(v > 0.0);
+          invd[k] = 1.0 / v;
         }
-        wave_sync();
       }
-      bool bad = false;
-      for (int e = LT[M.lt_hlev_start + h] + lane; e < LT[M.lt_hlev_start + h + 1]; e += 64) {
-        const int w = LT[M.lt_hdof + e];
-        const int k = w & 0xFF;
-        const double d = H[Lrs[k] + (w >> 8)];
-        bad |= !(d > 0.0);
-        invd[k] = 1.0 / d;
+    };
+    for (int h = 1; h < M.n_hlev && !nonspd; ++h) {
+      const int s0 = LT[M.lt_hent_start + h], ne = LT[M.lt_hent_start + h + 1] - s0;
+      const int lp = group_log2(ne), P = 1 << lp;
+      fbad = false;
+      if (lp == 0) {
+        // more entries than lanes: two independent entries per lane in flight
+        for (int base = 0; base < ne; base += 128) {
+          const int ga = base + lane, gb = base + 64 + lane;
+          double sa = 0.0, sb = 0.0;
+          int ea = 0, ka = 0, cka = 0, cja = 0, eb = 0, kb = 0, ckb = 0, cjb = 0;
+          if (ga < ne) entry(LT[M.lt_hent + s0 + ga], 0, 1, sa, ea, ka, cka, cja);
+          if (gb < ne) entry(LT[M.lt_hent + s0 + gb], 0, 1, sb, eb, kb, ckb, cjb);
+          if (ga < ne) finish(sa, ea, ka, cka, cja, fbad);
+          if (gb < ne) finish(sb, eb, kb, ckb, cjb, fbad);
+        }
+      } else {
+        const int g = lane >> lp, p = lane & (P - 1);
+        double sum = 0.0;
+        int e = 0, k = 0, ck = 0, cj = 0;
+        if (g < ne) entry(LT[M.lt_hent + s0 + g], p, P, sum, e, k, ck, cj);
+        sum = group_sum_last(sum, lp, lane);
+        if (g < ne && p == P - 1) finish(sum, e, k, ck, cj, fbad);
       }
-      if (__any(bad)) {
-        nonspd = true;
-        break;
-      }
+      nonspd = __any(fbad);
       wave_sync();
     }
     if (!nonspd) {

@@ -193,8 +193,10 @@ const char *ms_last_error(void);
  * step 2 by a pose -> (L, moment arms) network; the paper names the
  * muscle-tendon path routing as the costly part of musculoskeletal
  * simulation). Multilayer perceptron x -> SiLU(W1 x + b1) ->
- * SiLU(W2 h1 + b2) -> W3 h2 + b3 with x the hinge/slide angles padded to
- * a multiple of 16 and n_out = 4 n_mus outputs per pose: lengths L[n_mus]
+ * SiLU(W2 h1 + b2) -> W3 h2 + b3 with x the hinge/slide coordinates, each
+ * mapped from its pose box [qlo, qhi] onto [-1, 1] (float32: (q - c) * is,
+ * c = 0.5f (lo + hi), is = 2.0f / (hi - lo)), padded to a multiple of 16,
+ * and n_out = 4 n_mus outputs per pose: lengths L[n_mus]
  * then moment arms r[n_mus][3] in the span slots of ms_model_spans (empty
  * slots masked), standardised by (mean, std). bfloat16 matrix-core GEMMs
  * with float32 accumulation; float32 master weights stored [out][in];

@@ -2,7 +2,8 @@
 // lengths, moment arms) multilayer perceptron trained and evaluated with the
 // library's own bfloat16 matrix-core kernels (ms_gemm.hip).
 //
-// Network: x (hinge angles, padded to a multiple of 16) -> SiLU(W1 x + b1)
+// Network: x (hinge angles mapped from their pose box onto [-1, 1], padded
+// to a multiple of 16) -> SiLU(W1 x + b1)
 // -> SiLU(W2 h1 + b2) -> W3 h2 + b3, standardised outputs. Output layout per
 // pose: [L (n_mus) | r (n_mus x 3, the model's span slots)], caller's
 // muscle order. Weights live as float32 masters ([out][in]) with bfloat16
@@ -66,12 +67,20 @@ __global__ void k_to_bf16(const float *x, bf16 *y, int n) {
 }
 
 // x[p][i] = bf16(q[p][hinge_q[i]]) (0 for padding inputs)
-__global__ void k_pack(const float *q, int nq, const int *hq, int n_in, int n, bf16 *X) {
+// x[p][i] = bf16((q[p][hinge_q[i]] - c_i) * 2 / (hi_i - lo_i)) with
+// c_i = (lo_i + hi_i) / 2: each input's pose box mapped onto [-1, 1]
+__global__ void k_pack(const float *q, int nq, const int *hq, const float *lo, const float *hi,
+                       int n_in, int n, bf16 *X) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= n * n_in) return;
   const int p = t / n_in, i = t % n_in;
   const int j = hq[i];
-  X[t] = __float2bfloat16(j >= 0 ? q[(size_t)p * nq + j] : 0.0f);
+  float x = 0.0f;
+  if (j >= 0) {
+    const float c = 0.5f * (lo[i] + hi[i]), is = 2.0f / (hi[i] - lo[i]);
+    x = (q[(size_t)p * nq + j] - c) * is;
+  }
+  X[t] = __float2bfloat16(x);
 }
 
 // poses uniform in the surrogate's box: hinge i of pose p from
@@ -248,7 +257,7 @@ ms_status hipst(hipError_t e, const char *what) {
 // de-standardised when destd), keeping Z1/Z2 for training
 ms_status forward(ms_surrogate *s, int n, const float *q, bool destd, bool keep, hipStream_t st) {
   hipLaunchKernelGGL(k_pack, dim3(blocks((long long)n * s->n_in)), dim3(256), 0, st, q, s->nq,
-                     s->hinge_q, s->n_in, n, s->X);
+                     s->hinge_q, s->lo, s->hi, s->n_in, n, s->X);
   GemmEpi e1;
   e1.bias = s->b[0];
   e1.z_out = keep ? s->Z1 : nullptr;

@@ -87,9 +87,14 @@ def _oracle_params(ps):
 
 
 def _inputs(m, s, q):
-    """Network inputs of poses q: the hinge angles, zero-padded."""
+    """Network inputs of poses q: each hinge angle mapped from its pose box
+    onto [-1, 1] in float32 as the library defines it, zero-padded."""
+    lo = np.asarray(m["qlo"], np.float32)
+    hi = np.asarray(m["qhi"], np.float32)
+    c = np.float32(0.5) * (lo + hi)
+    isc = np.float32(2.0) / (hi - lo)
     x = np.zeros((q.shape[0], s.n_in), np.float32)
-    x[:, :m["nq"]] = q
+    x[:, :m["nq"]] = (np.asarray(q, np.float32) - c) * isc
     return x
 
 

@@ -243,6 +243,22 @@ ms_status build_tables(const ms_model_desc *d, Tables *t, std::string *msg) {
     for (int k = 0; k <= nv; ++k) rs[k] = t->row_start[k];
     std::vector<int32_t> path8((t->nnz + 3) / 4, 0);
     for (int e = 0; e < t->nnz; ++e) path8[e / 4] |= (t->path[e] & 0xFF) << (8 * (e % 4));
+    // tree schedule and subtree lists of the kinematics and dynamics
+    std::vector<int32_t> tinfo(n);
+    for (int i = 0; i < n; ++i) tinfo[i] = t->jtype[i] | ((t->parent[i] + 1) << 2) | (t->dadr[i] << 10);
+    auto bytes = [](const std::vector<int32_t> &v) {
+      std::vector<int32_t> w((v.size() + 3) / 4, 0);
+      for (size_t e = 0; e < v.size(); ++e) w[e / 4] |= (v[e] & 0xFF) << (8 * (e % 4));
+      return w;
+    };
+    section(&t->lt_tlev, t->level_start);
+    section(&t->lt_tnode, t->level_nodes);
+    section(&t->lt_tinfo, tinfo);
+    section(&t->lt_subb_start, t->subb_start);
+    section(&t->lt_subc_start, t->subc_start);
+    section(&t->lt_subb, bytes(t->subb));
+    section(&t->lt_subc, bytes(t->subc));
+    section(&t->lt_nnzrow, bytes(t->nnz_row));
     section(&t->lt_hent_start, hent_start);
     section(&t->lt_hlev_start, t->hlev_start);
     section(&t->lt_dlev_start, t->dlev_start);
@@ -386,7 +402,6 @@ ms_status build_tables(const ms_model_desc *d, Tables *t, std::string *msg) {
     return o;
   };
   t->off_flag = take(16);
-  t->off_tree = take(4 * (2 * n + t->n_level + 1));
   t->off_q = take(4 * nq);
   t->off_qd = take(4 * nv);
   t->off_R = take(4 * 12 * n);  // per node R (9) then P (3)

@@ -72,13 +72,17 @@ struct Tables {
   // desc (per DoF its proper descendants: row start | id << 16), drange (per
   // DoF its desc range: begin | end << 16), dsol (per depth level, its DoFs:
   // id | row start << 8), rs (row starts), path (path[] as bytes).
+  // The same table holds the tree schedule (tlev level starts, tnode nodes by
+  // level, tinfo per node: type | (parent + 1) << 2 | first DoF << 10) and
+  // the subtree lists (subb_start/subc_start, subb/subc and nnzrow as bytes).
   std::vector<int32_t> lt;
   int lt_hent_start = 0, lt_hlev_start = 0, lt_dlev_start = 0, lt_hent = 0, lt_hdof = 0,
-      lt_desc = 0, lt_drange = 0, lt_dsol = 0, lt_rs = 0, lt_path = 0;
+      lt_desc = 0, lt_drange = 0, lt_dsol = 0, lt_rs = 0, lt_path = 0, lt_tlev = 0, lt_tnode = 0,
+      lt_tinfo = 0, lt_subb_start = 0, lt_subc_start = 0, lt_subb = 0, lt_subc = 0, lt_nnzrow = 0;
   // LDS layout (byte offsets into the per-env LDS block)
   int off_q = 0, off_qd = 0, off_R = 0, off_P = 0, off_S = 0, off_V = 0,
       off_A = 0, off_F = 0, off_con = 0, off_rhs = 0, off_H = 0, off_x = 0,
-      off_scr = 0, off_flag = 0, off_tree = 0, lds_bytes = 0;
+      off_scr = 0, off_flag = 0, lds_bytes = 0;
   int n_levels_dof = 0;
 };
 

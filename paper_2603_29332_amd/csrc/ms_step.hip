@@ -149,14 +149,16 @@ ms_status ms_model_create(const ms_model_desc *desc, ms_model **out) {
   k.lt_hent_start = t.lt_hent_start; k.lt_hlev_start = t.lt_hlev_start;
   k.lt_dlev_start = t.lt_dlev_start; k.lt_hent = t.lt_hent; k.lt_hdof = t.lt_hdof;
   k.lt_desc = t.lt_desc; k.lt_drange = t.lt_drange; k.lt_dsol = t.lt_dsol; k.lt_rs = t.lt_rs;
-  k.lt_path = t.lt_path;
+  k.lt_path = t.lt_path; k.lt_tlev = t.lt_tlev; k.lt_tnode = t.lt_tnode; k.lt_tinfo = t.lt_tinfo;
+  k.lt_subb_start = t.lt_subb_start; k.lt_subc_start = t.lt_subc_start; k.lt_subb = t.lt_subb;
+  k.lt_subc = t.lt_subc; k.lt_nnzrow = t.lt_nnzrow;
   P_(hlev_start, o_hs, int); P_(hlev_dof, o_hd, int); P_(dlev_start, o_ds2, int);
   P_(dlev_dof, o_dd2, int);
 #undef P_
   k.off_flag = t.off_flag; k.off_q = t.off_q; k.off_qd = t.off_qd; k.off_R = t.off_R;
   k.off_P = t.off_P; k.off_S = t.off_S; k.off_con = t.off_con; k.off_rhs = t.off_rhs;
   k.off_x = t.off_x; k.off_H = t.off_H; k.off_scr = t.off_scr; k.lds_env = t.lds_bytes; k.off_V = t.off_V;
-  k.off_A = t.off_A; k.off_F = t.off_F; k.off_tree = t.off_tree;
+  k.off_A = t.off_A; k.off_F = t.off_F;
   *out = m;
   return MS_OK;
 }

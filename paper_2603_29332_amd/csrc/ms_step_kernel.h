@@ -276,16 +276,11 @@ __device__ __forceinline__ void step_body(const KModel &M, const KRun &Rn, int n
   double *__restrict__ xs = (double *)(lds + M.off_x);
   double *__restrict__ H = (double *)(lds + M.off_H);
   unsigned char *scr = lds + M.off_scr;
-  // tree schedule staged in LDS once per launch: level starts, nodes by
-  // level, and per node (jtype | (parent+1) << 2 | dof << 10)
-  int *tlev = (int *)(lds + M.off_tree);
-  int *tnode = tlev + M.n_level + 1;
-  int *tinfo = tnode + nn;
-  for (int l = lane; l <= M.n_level; l += 64) tlev[l] = M.level_start[l];
-  for (int i = lane; i < nn; i += 64) {
-    tnode[i] = M.level_nodes[i];
-    tinfo[i] = M.jtype[i] | ((M.parent[i] + 1) << 2) | (M.dadr[i] << 10);
-  }
+  // tree schedule and subtree lists from the workgroup's table
+  const int *tlev = LT + M.lt_tlev, *tnode = LT + M.lt_tnode, *tinfo = LT + M.lt_tinfo;
+  const int *sbs = LT + M.lt_subb_start, *scs = LT + M.lt_subc_start;
+  const unsigned char *sbl = (const unsigned char *)(LT + M.lt_subb);
+  const unsigned char *scl = (const unsigned char *)(LT + M.lt_subc);
   const float dt = Rn.dt;
   const int exc = Rn.exc;
   const bool stages = Rn.stages != 0;
@@ -534,8 +529,8 @@ __device__ __forceinline__ void step_body(const KModel &M, const KRun &Rn, int n
     for (int t = lane; t < 6 * nn; t += 64) {
       const int n = t / 6, k = t % 6;
       float s = 0.f;
-      for (int e = M.subb_start[n]; e < M.subb_start[n + 1]; ++e) s += Fl[6 * M.subb[e] + k];
-      for (int e = M.subc_start[n]; e < M.subc_start[n + 1]; ++e) s -= Cl[16 * M.subc[e] + 4 + k];
+      for (int e = sbs[n]; e < sbs[n + 1]; ++e) s += Fl[6 * sbl[e] + k];
+      for (int e = scs[n]; e < scs[n + 1]; ++e) s -= Cl[16 * scl[e] + 4 + k];
       Fn[t] = s;
     }
     wave_sync();
@@ -576,7 +571,7 @@ __device__ __forceinline__ void step_body(const KModel &M, const KRun &Rn, int n
       for (int t = lane; t < 10 * nn; t += 64) {
         const int n = t / 10, k = t % 10;
         double s = 0.0;
-        for (int e = M.subb_start[n]; e < M.subb_start[n + 1]; ++e) s += BI[10 * M.subb[e] + k];
+        for (int e = sbs[n]; e < sbs[n + 1]; ++e) s += BI[10 * sbl[e] + k];
         CI[t] = s;
       }
       wave_sync();
@@ -596,8 +591,8 @@ __device__ __forceinline__ void step_body(const KModel &M, const KRun &Rn, int n
         f[4] = m * v[1] - (h[2] * w[0] - h[0] * w[2]);
         f[5] = m * v[2] - (h[0] * w[1] - h[1] * w[0]);
         // implicit contact damping: dt * Phi^T D Phi S for contacts below
-        for (int e = M.subc_start[n]; e < M.subc_start[n + 1]; ++e) {
-          const float *C = Cl + 16 * M.subc[e];
+        for (int e = scs[n]; e < scs[n + 1]; ++e) {
+          const float *C = Cl + 16 * scl[e];
           if (C[0] == 0.f) continue;
           const double cp[3] = {C[1], C[2], C[3]};
           // point velocity of the contact for unit qd_j: v + w x cp
@@ -617,8 +612,10 @@ __device__ __forceinline__ void step_body(const KModel &M, const KRun &Rn, int n
         for (int k = 0; k < 6; ++k) FJ[6 * j + k] = f[k];
       }
       wave_sync();
+      const unsigned char *rowb = (const unsigned char *)(LT + M.lt_nnzrow);
+      const unsigned char *pathb = (const unsigned char *)(LT + M.lt_path);
       for (int e = lane; e < M.nnz; e += 64) {
-        const int j = M.nnz_row[e], i = M.path[e];
+        const int j = rowb[e], i = pathb[e];
         const float *Sf = Sl + 6 * i;
         const double *f = FJ + 6 * j;
         double h = (double)Sf[0] * f[0] + (double)Sf[1] * f[1] + (double)Sf[2] * f[2] +
@@ -970,7 +967,7 @@ hipError_t launch_k(const Tables &t, const KModel &k, const KRun &r, int n_env, 
                     hipStream_t st) {
   const bool geom = r.stages == 2, surr = r.geomY != nullptr;
   const int W = r.env_per_wg > 0 ? r.env_per_wg : default_env_per_wg(t);
-  const size_t lds = (geom ? 0 : t.lt.size() * 4) + (size_t)W * t.lds_bytes;
+  const size_t lds = t.lt.size() * 4 + (size_t)W * t.lds_bytes;
   const void *fn = geom ? (const void *)&k_geometry<MPL, NVIA>
                    : surr ? (const void *)&k_step_surrogate<MPL, NVIA>
                           : (const void *)&k_step<MPL, NVIA>;

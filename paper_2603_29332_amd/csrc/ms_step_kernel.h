@@ -420,29 +420,41 @@ __device__ __forceinline__ void step_body(const KModel &M, const KRun &Rn, int n
         if (jt == 2) continue;
         const int p = (info >> 2 & 0xFF) - 1, da = info >> 10;
         float *F = Rl + 12 * i;
-        float Lr[9];
-        for (int e = 0; e < 9; ++e) Lr[e] = F[e];
-        const V3 t = ld3(F + 9);
-        const V3 al = ld3(Al + 6 * i);
+        // frames are 16-byte aligned 12-float records, V and A 8-byte aligned
+        // 6-float records: vector LDS accesses
+        const float4 f0 = ((const float4 *)F)[0], f1 = ((const float4 *)F)[1],
+                     f2 = ((const float4 *)F)[2];
+        const float Lr[9] = {f0.x, f0.y, f0.z, f0.w, f1.x, f1.y, f1.z, f1.w, f2.x};
+        const V3 t = v3(f2.y, f2.z, f2.w);
+        const float2 a0 = ((const float2 *)(Al + 6 * i))[0], a1 = ((const float2 *)(Al + 6 * i))[1];
+        const V3 al = v3(a0.x, a0.y, a1.x);
         float Rp[9];
         V3 Pp, wp, vp, ap, lp;
         if (p >= 0) {
-          for (int e = 0; e < 9; ++e) Rp[e] = Rl[12 * p + e];
-          Pp = ld3(Pl + 12 * p);
-          wp = ld3(Vl + 6 * p); vp = ld3(Vl + 6 * p + 3);
-          ap = ld3(Al + 6 * p); lp = ld3(Al + 6 * p + 3);
+          const float4 *P4 = (const float4 *)(Rl + 12 * p);
+          const float4 r0 = P4[0], r1 = P4[1], r2 = P4[2];
+          Rp[0] = r0.x; Rp[1] = r0.y; Rp[2] = r0.z; Rp[3] = r0.w; Rp[4] = r1.x; Rp[5] = r1.y;
+          Rp[6] = r1.z; Rp[7] = r1.w; Rp[8] = r2.x;
+          Pp = v3(r2.y, r2.z, r2.w);
+          const float2 *V2 = (const float2 *)(Vl + 6 * p), *A2 = (const float2 *)(Al + 6 * p);
+          const float2 v0 = V2[0], v1 = V2[1], v2 = V2[2], b0 = A2[0], b1 = A2[1], b2 = A2[2];
+          wp = v3(v0.x, v0.y, v1.x); vp = v3(v1.y, v2.x, v2.y);
+          ap = v3(b0.x, b0.y, b1.x); lp = v3(b1.y, b2.x, b2.y);
         } else {
           for (int e = 0; e < 9; ++e) Rp[e] = (e % 4 == 0) ? 1.f : 0.f;
           Pp = v3(0.f, 0.f, 0.f) - O;
           wp = vp = ap = v3(0.f, 0.f, 0.f);
           lp = v3(0.f, 0.f, 0.f) - g;
         }
+        float Rn9[9];
         for (int r = 0; r < 3; ++r)
           for (int c = 0; c < 3; ++c)
-            F[3 * r + c] = Rp[3 * r] * Lr[c] + Rp[3 * r + 1] * Lr[3 + c] + Rp[3 * r + 2] * Lr[6 + c];
+            Rn9[3 * r + c] = Rp[3 * r] * Lr[c] + Rp[3 * r + 1] * Lr[3 + c] + Rp[3 * r + 2] * Lr[6 + c];
         const V3 Pi = Pp + mulR(Rp, t);
         const V3 ah = mulR(Rp, al);
-        st3(F + 9, Pi);
+        ((float4 *)F)[0] = make_float4(Rn9[0], Rn9[1], Rn9[2], Rn9[3]);
+        ((float4 *)F)[1] = make_float4(Rn9[4], Rn9[5], Rn9[6], Rn9[7]);
+        ((float4 *)F)[2] = make_float4(Rn9[8], Pi.x, Pi.y, Pi.z);
         V3 sw, sv;
         if (jt == 0) {
           sw = ah;
@@ -456,11 +468,11 @@ __device__ __forceinline__ void step_body(const KModel &M, const KRun &Rn, int n
         st3(S + 3, sv);
         const float qdi = qd[da];
         const V3 xw = qdi * sw, xv = qdi * sv;  // S qd
-        float *V = Vl + 6 * i, *A = Al + 6 * i;
-        st3(V, wp + xw);
-        st3(V + 3, vp + xv);
-        st3(A, ap + cross(wp, xw));
-        st3(A + 3, lp + cross(wp, xv) + cross(vp, xw));
+        const V3 vw = wp + xw, vv = vp + xv;
+        const V3 aw = ap + cross(wp, xw), av = lp + cross(wp, xv) + cross(vp, xw);
+        float2 *V2 = (float2 *)(Vl + 6 * i), *A2 = (float2 *)(Al + 6 * i);
+        V2[0] = make_float2(vw.x, vw.y); V2[1] = make_float2(vw.z, vv.x); V2[2] = make_float2(vv.y, vv.z);
+        A2[0] = make_float2(aw.x, aw.y); A2[1] = make_float2(aw.z, av.x); A2[2] = make_float2(av.y, av.z);
       }
       wave_sync();
     }

@@ -255,12 +255,11 @@ __device__ __forceinline__ void step_body(const KModel &M, const KRun &Rn, int n
   const int env = blockIdx.x * (blockDim.x >> 6) + wave;
   const int lane = threadIdx.x & 63;
   int *LT = (int *)lds_all;
-  if (!GEOM) {
-    for (int i = threadIdx.x; i < M.lt_words; i += blockDim.x) LT[i] = M.lt[i];
-    __syncthreads();  // the only workgroup-wide barrier: every wavefront reaches it
-  }
+  // every variant reads the tree schedule from this table
+  for (int i = threadIdx.x; i < M.lt_words; i += blockDim.x) LT[i] = M.lt[i];
+  __syncthreads();  // the only workgroup-wide barrier: every wavefront reaches it
   if (env >= Rn.n_env) return;
-  unsigned char *lds = lds_all + (GEOM ? 0 : (size_t)M.lt_words * 4) + (size_t)wave * M.lds_env;
+  unsigned char *lds = lds_all + (size_t)M.lt_words * 4 + (size_t)wave * M.lds_env;
   const int nq = M.nq, nv = M.nv, nm = M.n_mus, nn = M.n_node;
   float *__restrict__ q = (float *)(lds + M.off_q);
   float *__restrict__ qd = (float *)(lds + M.off_qd);

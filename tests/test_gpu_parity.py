@@ -123,6 +123,28 @@ def test_stage_parity(which, chain, human):
         assert np.abs(out["qdd"][e] - S["qdd"]).max() < 1e-3 * qscale
 
 
+@pytest.mark.parametrize("which", ["chain", "human"])
+def test_geometry_only_kernel_matches_oracle(which, chain, human):
+    """ms_geometry (the geometry-only kernel that writes the surrogate's
+    training targets) on a pose count ragged against every workgroup size."""
+    m, gm, o = chain if which == "chain" else human
+    init = synth.chain_initial_state if which == "chain" else synth.human_initial_state
+    E = 37
+    q, _, _ = _warm_states(m, o, E, 10, 1e-3, "iid", 23, which == "human", init)
+    L = torch.empty(E, m["n_mus"], device=DEV)
+    r = torch.empty(E, m["n_mus"], 3, device=DEV)
+    gm.geometry(_t(q), L, r)
+    torch.cuda.synchronize()
+    L, r = L.cpu().numpy(), r.cpu().numpy()
+    spans = gm.spans()
+    for e in range(E):
+        Lo, ro, _ = o.geometry(q[e].astype(np.float64), np.zeros(m["nv"]))
+        assert np.abs(L[e] - Lo).max() < 2e-6
+        for s in range(3):
+            ok = spans[:, s] >= 0
+            assert np.abs(r[e][ok, s] - ro[np.arange(m["n_mus"])[ok], spans[ok, s]]).max() < 2e-6
+
+
 # ---------------------------------------------------- one step, teacher forced
 @pytest.mark.parametrize("which", ["chain", "human", "human40"])
 def test_step_teacher_forced(which, chain, human, human40):

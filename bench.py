@@ -33,8 +33,8 @@ PEAK_VALU_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 # rocprofv3 FETCH_SIZE and WRITE_SIZE scaled by a plain copy of known size
 # (profiles/k_step_human80_4096_traffic.md), valid for the kernel source with
 # this SHA-256 prefix only (reported as null otherwise).
-TRAFFIC_BYTES_PER_LAUNCH = 53.8e6
-TRAFFIC_KERNEL_SHA = "74ef445d9ae359de"
+TRAFFIC_BYTES_PER_LAUNCH = 53.7e6
+TRAFFIC_KERNEL_SHA = "3cd755f039db850e"
 
 
 def parse():
@@ -119,6 +119,7 @@ def main():
     env_steps = E * PHYS_PER_STEP * a.steps
     value = env_steps / wall
     n_resets = int(resets.item())
+    progress(f"exact leg: {a.steps} launches, {wall:.2f} s")
 
     # ms_step_batch (u read from HBM), for the per-step HBM view
     uq = torch.rand(E, m["n_mus"], device=dev)
@@ -135,6 +136,7 @@ def main():
     torch.cuda.synchronize()
     sb_ms = e0.elapsed_time(e1) / nsb
     sb_bytes = 4 * (m["nq"] + m["nv"] + m["n_mus"]) * 2 + 4 * m["n_mus"] + 8
+    progress("step_batch leg done")
 
     fp32, fp64, detail = flops.step_flops(m, gm.spans(), gm.nnz)
     per_launch = (fp32 + fp64) * E * PHYS_PER_STEP
@@ -166,14 +168,23 @@ def main():
     if not a.no_surrogate:
         line["surrogate"], sg = surrogate_leg(a, m, gm, dt, E, q0, qd0, act0, (rho, s, mean), dev,
                                               rad=not a.no_cpu)
+        progress("surrogate leg done")
     if not a.no_policy:
         line["policy"] = policy_leg(a, m, gm, sg, dt, dev)
+        progress("policy leg done")
     if not a.no_uneven:
         line["uneven"] = uneven_leg(a, dt, dev)
+        progress("uneven leg done")
     if not a.no_cpu:
         line["rad_err_vs_fp64"] = rad_error(m, gm, dt, dev)
+        progress("radian error leg done")
         line["cpu_baseline"] = cpu_baseline(m, dt, a.cpu_seconds)
     print(json.dumps(line), flush=True)
+
+
+def progress(msg):
+    """One line per finished leg on stderr (the JSON line goes to stdout)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def measured_traffic():
@@ -203,7 +214,7 @@ def uneven_leg(a, dt, dev):
     40 DoF/300 muscles, 80 DoF/700 muscles, 1:1:2), exact path, AR(1)
     excitations in-kernel: one autotuned ms_batch_rollout (graph replay) of
     the whole run, against the same work issued model after model on one
-    stream."""
+    stream with separate ms_rollout calls."""
     import torch
 
     from paper_2603_29332_amd import ms, synth
@@ -246,7 +257,8 @@ def uneven_leg(a, dt, dev):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t
     flagged = int(sum((x[3] != 0).sum().item() for x in bufs))
-    # the same work model after model on one stream, one envs per workgroup
+    # the same work model after model on one stream (ms_rollout's default
+    # envs per workgroup)
     bufs = fresh()
     t = time.perf_counter()
     for gm, x in zip(gms, bufs):
@@ -259,7 +271,9 @@ def uneven_leg(a, dt, dev):
             "sequential_env_steps_per_s": total / wall_seq, "envs": n_env, "steps": T,
             "models": ["8 DoF/16 muscles", "40 DoF/300 muscles/16 spheres",
                        "80 DoF/700 muscles/24 spheres"],
-            "autotuned": {"env_per_workgroup": cfg[0], "largest_first": cfg[1]},
+            "autotuned": {"env_per_workgroup": cfg[0],
+                          "issue": ["concurrent", "concurrent, most work first",
+                                    "serial, most work first"][cfg[1]]},
             "flagged_envs": flagged}
 
 

@@ -241,7 +241,9 @@ def uneven_leg(a, dt, dev):
     T = a.uneven_steps
     b = ms.Batch(gms, n_env)
     bufs = fresh()
-    cfg = b.autotune([tuple(x[:4]) for x in bufs], exc(bufs, 0), 20, dt)
+    # tuned at the rollout's own length: each workgroup steps its envs through
+    # the whole rollout, so the tail a concurrent issue leaves grows with it
+    cfg = b.autotune([tuple(x[:4]) for x in bufs], exc(bufs, 0), T, dt)
     b.rollout([tuple(x[:4]) for x in bufs], exc(bufs, 0), 10, dt)   # warm-up, graph capture
     torch.cuda.synchronize()
     bufs = fresh()

@@ -288,15 +288,20 @@ ms_status ms_policy_rollout(ms_model *m, ms_policy *p, ms_surrogate *s,
  *
  * Each model's envs keep their own caller-owned state (layouts as for
  * ms_rollout) and excitation descriptor. One call steps every model's envs
- * n_steps times: each model's fused step kernel runs on an internal stream
- * forked from `stream` and joined back; outside an active capture the
- * fork/join is recorded once as a HIP graph per argument set (state and
- * excitation pointers and values, n_steps, opts, configuration) and
- * replayed. Inside a caller's stream capture the launches are simply issued.
+ * n_steps times with each model's own fused step kernel, issued as the
+ * batch's issue mode says: concurrently (each kernel on an internal stream
+ * forked from `stream` and joined back; in the caller's model order or with
+ * the model of most work first) or serially on `stream` (most work first).
+ * Outside an active capture the launches are recorded once as a HIP graph
+ * per argument set (state and excitation pointers and values, n_steps,
+ * opts, configuration) and replayed. Inside a caller's stream capture the launches are simply issued.
  * Results are bitwise those of ms_rollout on each model alone, for any
  * configuration. A batch is not thread-safe; its models must not be used on
  * other streams during a call. */
 typedef struct ms_batch ms_batch;
+#define MS_ISSUE_CONCURRENT 0            /* forked streams, caller's order */
+#define MS_ISSUE_CONCURRENT_MOST_WORK 1  /* forked streams, most work first */
+#define MS_ISSUE_SERIAL 2                /* one after another on the stream */
 typedef struct {
   float *q, *qd, *act; /* device, [n_env][nq], [n_env][nv], [n_env][n_mus] */
   uint32_t *status;    /* device [n_env], may be NULL */
@@ -311,19 +316,24 @@ ms_status ms_batch_rollout(ms_batch *b, const ms_batch_state *states,
                            const ms_step_opts *opts, void *stream);
 /* Autotuner: per model alone, probe rollouts of n_probe steps for 1, 2 and 4
  * envs per workgroup (each env is one wavefront with its own LDS block); then
- * the whole batch with models issued in the caller's order and most-work
- * first. Probes run on scratch copies of the given states (left unchanged);
+ * (fastest of three probes each); then the whole batch in each of the
+ * three issue modes, as graph replays (mean of three after a warm-up). Each workgroup steps its envs through a whole
+ * rollout, so the best issue mode depends on the rollout length: probe with
+ * the n_steps the batch will run. Probes run on scratch copies of the given states (left unchanged);
  * the fastest choices are kept in the batch. Synchronises `stream`. */
 ms_status ms_batch_autotune(ms_batch *b, const ms_batch_state *states,
                             const ms_excitation *exc, int32_t n_probe,
                             const ms_step_opts *opts, void *stream);
-/* Current configuration: env_per_wg[n_models], *largest_first (0/1). */
+/* Current configuration: env_per_wg[n_models], *issue_mode (MS_ISSUE_*). */
 ms_status ms_batch_config(const ms_batch *b, int32_t *env_per_wg,
-                          int32_t *largest_first);
-/* Set it by hand (env_per_wg in {1, 2, 4}); MS_E_UNSUPPORTED if a
- * workgroup's LDS would exceed 160 KiB. */
+                          int32_t *issue_mode);
+/* Set it by hand (env_per_wg in {1, 2, 4}, or 0 for the envs per workgroup
+ * that keep the most envs resident per CU, the default of a new batch;
+ * issue_mode an MS_ISSUE_* value,
+ * else MS_E_ARG); MS_E_UNSUPPORTED if a workgroup's LDS would exceed
+ * 160 KiB. */
 ms_status ms_batch_set_config(ms_batch *b, const int32_t *env_per_wg,
-                              int32_t largest_first);
+                              int32_t issue_mode);
 const char *ms_batch_last_error(void);
 
 /* ms_rollout with the muscle geometry predicted by the surrogate: each step

@@ -2,12 +2,15 @@
 // together.
 //
 // Each model keeps its own fused step kernel (its own tables, LDS block and
-// register budget), launched on an internal stream of its own forked from
-// the caller's stream and joined back, so the GPU runs the models' envs
-// side by side. The fork/join is captured once as a HIP graph per argument
-// set and replayed, one graph launch per rollout. The autotuner times, per
-// model, each envs-per-workgroup choice, and for the whole batch the two
-// issue orders, and keeps the fastest.
+// register budget). The kernels are issued either concurrently, each on an
+// internal stream of its own forked from the caller's stream and joined
+// back, so the GPU runs the models' envs side by side, or serially on the
+// caller's stream (a model whose envs fill the GPU runs no slower alone, and
+// kernels with different LDS blocks sharing a CU can leave part of its LDS
+// idle). The launches are captured once as a HIP graph per argument set and
+// replayed, one graph launch per rollout. The autotuner times, per model,
+// each envs-per-workgroup choice, and for the whole batch the three issue
+// modes, and keeps the fastest.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -22,7 +25,7 @@ struct ms_batch {
   std::vector<ms_model *> models;
   std::vector<int> n_env;
   std::vector<int> wpg;        // envs per workgroup per model (0: most resident envs)
-  int issue_largest_first = 0;  // 0: caller's order, 1: most work first
+  int issue = MS_ISSUE_CONCURRENT;  // an MS_ISSUE_* mode
   std::vector<hipStream_t> streams;
   std::vector<hipEvent_t> done;
   hipEvent_t fork = nullptr;
@@ -59,7 +62,7 @@ void drop_graph(ms_batch *b) {
 std::vector<int> order(const ms_batch *b) {
   std::vector<int> o(b->models.size());
   for (size_t i = 0; i < o.size(); ++i) o[i] = (int)i;
-  if (b->issue_largest_first) {
+  if (b->issue != MS_ISSUE_CONCURRENT) {
     auto work = [&](int i) {
       const ms::Tables &t = b->models[i]->t;
       return (double)b->n_env[i] * (double)(t.nv * t.nv + 20 * t.n_mus);
@@ -69,9 +72,19 @@ std::vector<int> order(const ms_batch *b) {
   return o;
 }
 
-// fork, one rollout per model on its own stream, join
+// one rollout per model: serially on st, or forked onto the model's own
+// stream and joined back
 ms_status issue(ms_batch *b, const ms_batch_state *s, const ms_excitation *exc, int n_steps,
                 const ms_step_opts *opts, hipStream_t st) {
+  if (b->issue == MS_ISSUE_SERIAL) {
+    for (int i : order(b)) {
+      ms_status r = rollout_impl(b->models[i], b->n_env[i], s[i].q, s[i].qd, s[i].act,
+                                 s[i].status, &exc[i], n_steps, opts, b->wpg[i], st);
+      if (r != MS_OK)
+        return bfail(r, std::string("model ") + std::to_string(i) + ": " + ms_last_error());
+    }
+    return MS_OK;
+  }
   ms_status r = bhip(hipEventRecord(b->fork, st), "event record");
   if (r != MS_OK) return r;
   for (int i : order(b)) {
@@ -102,8 +115,31 @@ std::vector<unsigned char> make_key(const ms_batch *b, const ms_batch_state *s,
   put(&n_steps, sizeof n_steps);
   put(opts, sizeof *opts);
   put(b->wpg.data(), nm * sizeof(int));
-  put(&b->issue_largest_first, sizeof(int));
+  put(&b->issue, sizeof(int));
   return k;
+}
+
+// record the batch's launches for these arguments as the batch's graph
+// (replacing any), on the internal capture stream
+ms_status capture(ms_batch *b, const ms_batch_state *s, const ms_excitation *exc, int n_steps,
+                  const ms_step_opts *opts) {
+  drop_graph(b);
+  ms_status r = bhip(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal),
+                     "begin capture");
+  if (r != MS_OK) return r;
+  ms_status ri = issue(b, s, exc, n_steps, opts, b->cap);
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(b->cap, &g);
+  if (ri != MS_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return ri;
+  }
+  r = bhip(e, "end capture");
+  if (r != MS_OK) return r;
+  b->graph = g;
+  r = bhip(hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0), "graph instantiate");
+  if (r != MS_OK) drop_graph(b);
+  return r;
 }
 
 }  // namespace
@@ -168,24 +204,8 @@ ms_status ms_batch_rollout(ms_batch *b, const ms_batch_state *states, const ms_e
   if (cs != hipStreamCaptureStatusNone) return issue(b, states, exc, n_steps, opts, st);
   std::vector<unsigned char> key = make_key(b, states, exc, n_steps, opts);
   if (!b->exec || key != b->key) {
-    drop_graph(b);
-    r = bhip(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal), "begin capture");
+    r = capture(b, states, exc, n_steps, opts);
     if (r != MS_OK) return r;
-    ms_status ri = issue(b, states, exc, n_steps, opts, b->cap);
-    hipGraph_t g = nullptr;
-    hipError_t e = hipStreamEndCapture(b->cap, &g);
-    if (ri != MS_OK) {
-      if (g) (void)hipGraphDestroy(g);
-      return ri;
-    }
-    r = bhip(e, "end capture");
-    if (r != MS_OK) return r;
-    b->graph = g;
-    r = bhip(hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0), "graph instantiate");
-    if (r != MS_OK) {
-      drop_graph(b);
-      return r;
-    }
     b->key = key;
   }
   return bhip(hipGraphLaunch(b->exec, st), "graph launch");
@@ -247,6 +267,7 @@ ms_status ms_batch_autotune(ms_batch *b, const ms_batch_state *states, const ms_
     return q;
   };
   // 1. per model, alone: envs per workgroup
+  constexpr int kReps = 3;
   const int choices[3] = {1, 2, 4};
   for (int i = 0; i < nm && r == MS_OK; ++i) {
     float best = 1e30f;
@@ -254,33 +275,40 @@ ms_status ms_batch_autotune(ms_batch *b, const ms_batch_state *states, const ms_
     for (int w : choices) {
       if (b->models[i]->t.lt.size() * 4 + (size_t)w * b->models[i]->t.lds_bytes > 160 * 1024)
         continue;
-      float t_ms = 0.f;
-      for (int rep = 0; rep < 2 && r == MS_OK; ++rep) {  // first run warms up
+      for (int rep = 0; rep < kReps && r == MS_OK; ++rep) {  // fastest of kReps probes
+        float t_ms = 0.f;
         r = refresh(i);
         if (r == MS_OK)
           r = timed([&] {
             return rollout_impl(b->models[i], b->n_env[i], sc[i].q, sc[i].qd, sc[i].act,
                                 sc[i].status, &ec[i], n_probe, opts, w, st);
           }, &t_ms);
-      }
-      if (r == MS_OK && t_ms < best) {
-        best = t_ms;
-        wbest = w;
+        if (r == MS_OK && t_ms < best) {
+          best = t_ms;
+          wbest = w;
+        }
       }
     }
     b->wpg[i] = wbest;
   }
-  // 2. the whole batch: issue order
-  float t_order[2] = {1e30f, 1e30f};
-  for (int o = 0; o < 2 && r == MS_OK; ++o) {
-    b->issue_largest_first = o;
-    for (int rep = 0; rep < 2 && r == MS_OK; ++rep) {
+  // 2. the whole batch, replayed as the graph a rollout launches: issue mode
+  // by the mean of kReps replays after one warm-up (concurrent kernels vary
+  // from one replay to the next)
+  float t_mode[3] = {1e30f, 1e30f, 1e30f};
+  for (int o = 0; o < 3 && r == MS_OK; ++o) {
+    b->issue = o;
+    r = capture(b, sc.data(), ec.data(), n_probe, opts);
+    float sum = 0.f;
+    for (int rep = 0; rep <= kReps && r == MS_OK; ++rep) {
+      float t_ms = 0.f;
       for (int i = 0; i < nm && r == MS_OK; ++i) r = refresh(i);
       if (r == MS_OK)
-        r = timed([&] { return issue(b, sc.data(), ec.data(), n_probe, opts, st); }, &t_order[o]);
+        r = timed([&] { return bhip(hipGraphLaunch(b->exec, st), "graph launch"); }, &t_ms);
+      if (rep > 0) sum += t_ms;
     }
+    if (r == MS_OK) t_mode[o] = sum / kReps;
   }
-  b->issue_largest_first = t_order[1] < t_order[0] ? 1 : 0;
+  b->issue = (int)(std::min_element(t_mode, t_mode + 3) - t_mode);
   (void)hipStreamSynchronize(st);
   if (e0) (void)hipEventDestroy(e0);
   if (e1) (void)hipEventDestroy(e1);
@@ -289,23 +317,26 @@ ms_status ms_batch_autotune(ms_batch *b, const ms_batch_state *states, const ms_
   return r;
 }
 
-ms_status ms_batch_config(const ms_batch *b, int32_t *env_per_wg, int32_t *largest_first) {
-  if (!b || !env_per_wg || !largest_first) return bfail(MS_E_ARG, "NULL argument");
+ms_status ms_batch_config(const ms_batch *b, int32_t *env_per_wg, int32_t *issue_mode) {
+  if (!b || !env_per_wg || !issue_mode) return bfail(MS_E_ARG, "NULL argument");
   for (size_t i = 0; i < b->wpg.size(); ++i) env_per_wg[i] = b->wpg[i];
-  *largest_first = b->issue_largest_first;
+  *issue_mode = b->issue;
   return MS_OK;
 }
 
-ms_status ms_batch_set_config(ms_batch *b, const int32_t *env_per_wg, int32_t largest_first) {
+ms_status ms_batch_set_config(ms_batch *b, const int32_t *env_per_wg, int32_t issue_mode) {
   if (!b || !env_per_wg) return bfail(MS_E_ARG, "NULL argument");
+  if (issue_mode < MS_ISSUE_CONCURRENT || issue_mode > MS_ISSUE_SERIAL)
+    return bfail(MS_E_ARG, "unknown issue mode");
   for (size_t i = 0; i < b->wpg.size(); ++i) {
     const int w = env_per_wg[i];
-    if (w != 1 && w != 2 && w != 4) return bfail(MS_E_ARG, "envs per workgroup must be 1, 2 or 4");
+    if (w != 0 && w != 1 && w != 2 && w != 4)
+      return bfail(MS_E_ARG, "envs per workgroup must be 0 (most resident envs), 1, 2 or 4");
     if (b->models[i]->t.lt.size() * 4 + (size_t)w * b->models[i]->t.lds_bytes > 160 * 1024)
       return bfail(MS_E_UNSUPPORTED, "workgroup LDS would exceed 160 KiB");
   }
   for (size_t i = 0; i < b->wpg.size(); ++i) b->wpg[i] = env_per_wg[i];
-  b->issue_largest_first = largest_first ? 1 : 0;
+  b->issue = issue_mode;
   drop_graph(b);
   return MS_OK;
 }

@@ -19,6 +19,7 @@ MS_ST_NONFINITE = 1
 MS_ST_NONSPD = 2
 MS_ST_FALLBACK = 4
 EXC_ARRAY, EXC_IID, EXC_AR1 = 0, 1, 2
+ISSUE_CONCURRENT, ISSUE_CONCURRENT_MOST_WORK, ISSUE_SERIAL = 0, 1, 2
 
 EXPORTED = ("ms_model_create", "ms_model_destroy", "ms_model_info_get",
             "ms_step_batch", "ms_rollout", "ms_step_stages", "ms_model_spans",
@@ -396,13 +397,13 @@ class Batch:
 
     def config(self):
         w = np.zeros(len(self.models), np.int32)
-        lf = np.zeros(1, np.int32)
-        _check_b(lib().ms_batch_config(self.h, w.ctypes.data_as(_iptr), lf.ctypes.data_as(_iptr)))
-        return w.tolist(), int(lf[0])
+        mode = np.zeros(1, np.int32)
+        _check_b(lib().ms_batch_config(self.h, w.ctypes.data_as(_iptr), mode.ctypes.data_as(_iptr)))
+        return w.tolist(), int(mode[0])
 
-    def set_config(self, env_per_wg, largest_first=0):
+    def set_config(self, env_per_wg, issue_mode=ISSUE_CONCURRENT):
         w = np.asarray(env_per_wg, np.int32)
-        _check_b(lib().ms_batch_set_config(self.h, w.ctypes.data_as(_iptr), int(largest_first)))
+        _check_b(lib().ms_batch_set_config(self.h, w.ctypes.data_as(_iptr), int(issue_mode)))
 
 
 class Policy:

@@ -69,17 +69,20 @@ def test_batch_matches_each_model_alone_in_every_configuration(three):
     T = 20
     ref = _alone(mods, gms, inits, n_env, T)
     b = ms.Batch(gms, n_env)
-    for cfg, lf in (([1, 1, 1], 0), ([2, 4, 1], 1), ([4, 2, 4], 0)):
-        b.set_config(cfg, lf)
-        assert b.config() == (cfg, lf)
+    for cfg, mode in (([1, 1, 1], ms.ISSUE_CONCURRENT), ([2, 4, 1], ms.ISSUE_CONCURRENT_MOST_WORK),
+                      ([4, 2, 4], ms.ISSUE_SERIAL), ([2, 2, 4], ms.ISSUE_CONCURRENT)):
+        b.set_config(cfg, mode)
+        assert b.config() == (cfg, mode)
         _same(_batched(mods, b, inits, n_env, T), ref)
 
 
-def test_graph_replay_continues_the_rollout(three):
+@pytest.mark.parametrize("mode", [0, 1, 2])
+def test_graph_replay_continues_the_rollout(three, mode):
     mods, gms, inits, n_env = three
     T = 10
     ref = _alone(mods, gms, inits, n_env, T, calls=3)
     b = ms.Batch(gms, n_env)
+    b.set_config([0, 4, 2], mode)
     _same(_batched(mods, b, inits, n_env, T, calls=3), ref)
 
 
@@ -90,7 +93,7 @@ def test_autotune_picks_a_valid_configuration_and_leaves_states(three):
     before = [[v.cpu().numpy().copy() for v in bb] for bb in bufs]
     w, lf = b.autotune([tuple(v[:4]) for v in bufs], [_exc(v[4], 0) for v in bufs], 5, DT)
     torch.cuda.synchronize()
-    assert all(x in (1, 2, 4) for x in w) and lf in (0, 1)
+    assert all(x in (1, 2, 4) for x in w) and lf in (0, 1, 2)
     after = [[v.cpu().numpy() for v in bb] for bb in bufs]
     _same(after, before)
     # and the tuned batch still matches the models alone

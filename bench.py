@@ -165,9 +165,10 @@ def main():
                            "FP64 oracle fails on the same envs (about 19% by 1000 steps)",
     }
     sg = None
+    rad = None if a.no_cpu else {"exact": rad_run(m, gm, dt, dev)}
     if not a.no_surrogate:
         line["surrogate"], sg = surrogate_leg(a, m, gm, dt, E, q0, qd0, act0, (rho, s, mean), dev,
-                                              rad=not a.no_cpu)
+                                              rad=rad)
         progress("surrogate leg done")
     if not a.no_policy:
         line["policy"] = policy_leg(a, m, gm, sg, dt, dev)
@@ -176,9 +177,13 @@ def main():
         line["uneven"] = uneven_leg(a, dt, dev)
         progress("uneven leg done")
     if not a.no_cpu:
-        line["rad_err_vs_fp64"] = rad_error(m, gm, dt, dev)
-        progress("radian error leg done")
-        line["cpu_baseline"] = cpu_baseline(m, dt, a.cpu_seconds)
+        line["cpu_baseline"], ref = cpu_baseline(m, dt, a.cpu_seconds)
+        progress("cpu_baseline leg done")
+        line["rad_err_vs_fp64"] = rad_compare(rad["exact"], ref)
+        if "surrogate" in line:
+            line["surrogate"]["rad_err_vs_fp64"] = rad_compare(rad["surrogate"], ref, True)
+            for row in line["surrogate"]["tolerance_sweep"]:
+                row["rad_err_vs_fp64_max"] = rad_compare(rad[("sweep", row["tol_m"])], ref)["max"]
     print(json.dumps(line), flush=True)
 
 
@@ -320,10 +325,11 @@ def policy_leg(a, m, gm, sg, dt, dev):
             "env_resets": int(resets.item())}
 
 
-def surrogate_leg(a, m, gm, dt, E, q0, qd0, act0, ar1, dev, rad=True):
+def surrogate_leg(a, m, gm, dt, E, q0, qd0, act0, ar1, dev, rad=None):
     """The same workload with the learned geometry and exact fallback: the
     network is trained here (untimed) on exact labels, then K bench steps of
-    PHYS_PER_STEP physics steps are timed like the exact leg."""
+    PHYS_PER_STEP physics steps are timed like the exact leg. With rad (a
+    dict), the radian-error sample's GPU runs are recorded there."""
     import torch
 
     from paper_2603_29332_amd import ms, surrogate
@@ -383,8 +389,8 @@ def surrogate_leg(a, m, gm, dt, E, q0, qd0, act0, ar1, dev, rad=True):
                        "setup_s": setup_s, "heldout": ev_err},
            "forward": {"ms": fwd_ms, "tflops": fwd_flop / (fwd_ms / 1e3) / 1e12,
                        "mfma_bf16_peak_tflops": 2500.0}}
-    if rad:
-        out["rad_err_vs_fp64"] = rad_error(m, gm, dt, dev, sg=sg, tol=a.surrogate_tol)
+    if rad is not None:
+        rad["surrogate"] = rad_run(m, gm, dt, dev, sg=sg, tol=a.surrogate_tol)
     # the same rollout at looser residual tests (100 steps each): how the
     # fallback rate, the speed and the error trade against each other
     sweep = []
@@ -398,44 +404,69 @@ def surrogate_leg(a, m, gm, dt, E, q0, qd0, act0, ar1, dev, rad=True):
         w = time.perf_counter() - t
         row = {"tol_m": tol, "env_steps_per_s": E * PHYS_PER_STEP / w,
                "fallback_rate": float(fb.sum().item()) / (E * PHYS_PER_STEP)}
-        if rad:
-            row["rad_err_vs_fp64_max"] = rad_error(m, gm, dt, dev, sg=sg, tol=tol)["max"]
+        if rad is not None:
+            rad[("sweep", tol)] = rad_run(m, gm, dt, dev, sg=sg, tol=tol)
         sweep.append(row)
     out["tolerance_sweep"] = sweep
     return out, sg
 
 
-def rad_error(m, gm, dt, dev, sg=None, tol=1e-4):
-    """GPU vs FP64 oracle after 200 steps, 16 envs of the 4096-env workload."""
+RAD_E, RAD_T = 4096, 200
+
+
+def rad_inputs(m, dt):
+    """The radian-error sample: every 256th env of the 4096-env workload (16
+    envs), RAD_T steps of AR(1) excitations."""
+    from paper_2603_29332_amd import synth
+    sub = np.arange(0, RAD_E, 256)
+    q, qd, act = synth.human_initial_state(m, RAD_E)
+    u, _ = synth.excitation_sequence("ar1", 12, len(sub), m["n_mus"], RAD_T, dt, envs=sub)
+    return q[sub], qd[sub], act[sub], u
+
+
+def rad_run(m, gm, dt, dev, sg=None, tol=1e-4):
+    """The radian-error sample on the GPU; final q and status on the host."""
     import torch
 
-    from oracle import Oracle
-    from paper_2603_29332_amd import ms, synth
-    E, T = 4096, 200
-    sub = np.arange(0, E, 256)
-    q, qd, act = synth.human_initial_state(m, E)
-    q, qd, act = q[sub], qd[sub], act[sub]
-    u, _ = synth.excitation_sequence("ar1", 12, len(sub), m["n_mus"], T, dt, envs=sub)
+    from paper_2603_29332_amd import ms
+    q, qd, act, u = rad_inputs(m, dt)
     tq, tqd, tact = (torch.tensor(v, device=dev) for v in (q, qd, act))
-    st = torch.zeros(len(sub), dtype=torch.int32, device=dev)
+    st = torch.zeros(len(q), dtype=torch.int32, device=dev)
     if sg is None:
-        gm.rollout(tq, tqd, tact, st, T, dt, True, kind=ms.EXC_ARRAY,
+        gm.rollout(tq, tqd, tact, st, RAD_T, dt, True, kind=ms.EXC_ARRAY,
                    u=torch.tensor(u, device=dev))
     else:
-        gm.rollout_surrogate(sg, tq, tqd, tact, st, T, dt, True, tol=tol, kind=ms.EXC_ARRAY,
+        gm.rollout_surrogate(sg, tq, tqd, tact, st, RAD_T, dt, True, tol=tol, kind=ms.EXC_ARRAY,
                              u=torch.tensor(u, device=dev))
         st &= ~ms.MS_ST_FALLBACK
     torch.cuda.synchronize()
-    qo, _, _, so = Oracle(m).rollout(dt, q, qd, act, u, contact=True)
-    ok = (so == 0) & (st.cpu().numpy() == 0)
-    d = np.abs(tq.cpu().numpy()[ok][:, 7:] - qo[ok][:, 7:])
-    return {"max": float(d.max()), "mean": float(d.mean()), "envs": int(ok.sum()),
-            "steps": T, "note": "hinge angles, GPU FP32(+FP64 solve) vs FP64 oracle"
-                                + ("" if sg is None else ", learned geometry with fallback")}
+    return tq.cpu().numpy(), st.cpu().numpy()
+
+
+def rad_compare(run, ref, surrogate=False):
+    """Hinge-angle error of a GPU run against the FP64 oracle's (ref from the
+    cpu_baseline leg: final q, status, control spread per env)."""
+    qg, stg = run
+    qo, so, spread = ref
+    ok = (so == 0) & (stg == 0)
+    de = np.abs(qg[:, 7:] - qo[:, 7:]).max(axis=1)[ok]
+    spread = spread[ok]
+    sens = spread > 1e-3
+    return {"max": float(de.max()), "median_env": float(np.median(de)), "envs": int(ok.sum()),
+            "steps": RAD_T, "fp32_sensitive_envs": int(sens.sum()),
+            "max_other_envs": float(de[~sens].max()) if (~sens).any() else None,
+            "sensitive_env_errors": [round(float(v), 6) for v in de[sens]],
+            "sensitive_env_control_spread": [round(float(v), 6) for v in spread[sens]],
+            "note": "max over hinge angles per env, GPU FP32(+FP64 solve) vs FP64 oracle; an env "
+                    "is FP32-sensitive when the oracle itself, rounded to FP32 and perturbed by "
+                    "1e-5 per step, moves more than 1e-3 rad"
+                    + ("; learned geometry with fallback" if surrogate else "")}
 
 
 def cpu_baseline(m, dt, seconds):
-    """The FP64 oracle on the host cores, on a bounded sample of the workload."""
+    """The FP64 oracle on the host cores, on a bounded sample of the workload;
+    also its trajectories of the radian-error sample (the reference the GPU
+    runs are compared with)."""
     from oracle import Oracle
     from paper_2603_29332_amd import synth
     threads = len(os.sched_getaffinity(0))
@@ -452,12 +483,26 @@ def cpu_baseline(m, dt, seconds):
     t = time.perf_counter()
     o.rollout(dt, q, qd, act, u, threads=threads)
     wall = time.perf_counter() - t
-    return {"value": n_env * steps / wall, "unit": "env-steps/s", "cores": threads,
+    base = {"value": n_env * steps / wall, "unit": "env-steps/s", "cores": threads,
             "kind": "oracle",
             "sample": f"{n_env} envs x {steps} steps of the same 80-DoF/700-muscle model "
                       f"(dense FP64 oracle, {wall:.1f} s wall); envs are independent so the "
                       f"rate extrapolates linearly",
             "single_thread_env_steps_per_s": 1.0 / per}
+    # the oracle's trajectories of the radian-error sample, and a control: the
+    # oracle again with its state rounded to float32 and its velocities
+    # perturbed by 1e-5 relative noise after every step (the per-step bound);
+    # an env whose control moves more than 1e-3 rad in RAD_T steps has no
+    # unique FP32 trajectory
+    q, qd, act, u = rad_inputs(m, dt)
+    qo, _, _, so = o.rollout(dt, q, qd, act, u, contact=True)
+    rng = np.random.default_rng(2024)
+    qc, qdc, ac = q.copy(), qd.copy(), act.copy()
+    for k in range(RAD_T):
+        qc, qdc, ac, _ = o.rollout(dt, qc, qdc, ac, u[k:k + 1], contact=True)
+        qdc = qdc * (1.0 + 1e-5 * rng.standard_normal(qdc.shape))
+        qc, qdc, ac = (v.astype(np.float32) for v in (qc, qdc, ac))
+    return base, (qo, so, np.abs(qc[:, 7:] - qo[:, 7:]).max(axis=1))
 
 
 if __name__ == "__main__":

@@ -109,6 +109,9 @@ typedef struct {
   int32_t max_dof_depth;   /* longest root-to-leaf DoF chain */
   int32_t nnz_mass;        /* stored entries of the tree-sparse M */
   int32_t lds_bytes;       /* per-environment LDS footprint of the step */
+  int32_t lds_shared_bytes; /* LDS table shared by a workgroup's envs: a
+                               workgroup of W envs takes lds_shared_bytes +
+                               W * lds_bytes (at most 160 KiB) */
 } ms_model_info;
 
 typedef struct {

@@ -81,9 +81,10 @@ ms_status ms_model_create(const ms_model_desc *desc, ms_model **out) {
     delete m;
     return fail(MS_E_UNSUPPORTED, "more than 128 DoFs");
   }
-  if (t.lds_bytes > 160 * 1024) {
+  if (t.lt.size() * 4 + (size_t)t.lds_bytes > 160 * 1024) {
     delete m;
-    return fail(MS_E_UNSUPPORTED, "model needs more than 160 KiB of LDS per environment");
+    return fail(MS_E_UNSUPPORTED,
+                "model needs more than 160 KiB of LDS for a workgroup of one environment");
   }
   Packer p;
   size_t o_parent = p.add(t.parent), o_jtype = p.add(t.jtype), o_qadr = p.add(t.qadr),
@@ -174,6 +175,7 @@ ms_status ms_model_info_get(const ms_model *m, ms_model_info *o) {
   o->nq = m->t.nq; o->nv = m->t.nv; o->n_node = m->t.n_node; o->n_mus = m->t.n_mus;
   o->n_con = m->t.n_con; o->n_body = m->t.n_body; o->max_dof_depth = m->t.max_depth;
   o->nnz_mass = m->t.nnz; o->lds_bytes = m->t.lds_bytes;
+  o->lds_shared_bytes = (int32_t)(m->t.lt.size() * 4);
   return MS_OK;
 }
 

@@ -53,7 +53,7 @@ class MsDesc(C.Structure):
 class MsInfo(C.Structure):
     _fields_ = [(k, C.c_int32) for k in ("nq", "nv", "n_node", "n_mus", "n_con",
                                          "n_body", "max_dof_depth", "nnz_mass",
-                                         "lds_bytes")]
+                                         "lds_bytes", "lds_shared_bytes")]
 
 
 class MsOpts(C.Structure):

@@ -103,7 +103,7 @@ def test_autotune_picks_a_valid_configuration_and_leaves_states(three):
 def test_oversized_workgroup_is_rejected(three):
     mods, gms, inits, n_env = three
     b = ms.Batch([gms[2]], [8])
-    if gms[2].info["lds_bytes"] * 4 > 160 * 1024:
+    if gms[2].info["lds_shared_bytes"] + gms[2].info["lds_bytes"] * 4 > 160 * 1024:
         with pytest.raises(ms.MsError):
             b.set_config([4], 0)
     else:

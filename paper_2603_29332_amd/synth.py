@@ -409,18 +409,21 @@ def _inertia(mass, dims, shape, axis_long):
     return I
 
 
-def human_model(seed: int = 2, full: bool = True, n_mus: int = 700,
+def human_model(seed: int = 2, full: bool = True, n_mus: int | None = None,
                 total_mass: float = 75.0, damping: float = 0.1,
                 contact=(1e5, 1e3, 1.0, 0.2), radius: float = 0.02) -> dict:
     """Synthetic whole-body model with a free root.
 
     full=True: 22 bodies, nv = 80 (6 root + 74 hinges), nq = 81, 24 contact
-    spheres (8 per foot over heel/metatarsal/toe, 4 per hand). full=False:
-    13 bodies, nv = 40, 16 foot spheres. Muscles cross a chain of 1-3
+    spheres (8 per foot over heel/metatarsal/toe, 4 per hand), 700 muscles
+    by default. full=False: 13 bodies, nv = 40, 16 foot spheres, 300
+    muscles by default. Muscles cross a chain of 1-3
     consecutive hinge DoFs with 2-5 via-points; Hill parameters as in
     chain_model; insertion placed so the neutral path length is
     l_s + lambda0 * l_opt.
     """
+    if n_mus is None:
+        n_mus = 700 if full else 300
     rng = np.random.default_rng(seed)
     specs = _human_specs(full)
     for sp in specs:

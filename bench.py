@@ -33,8 +33,8 @@ PEAK_VALU_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 # rocprofv3 FETCH_SIZE and WRITE_SIZE scaled by a plain copy of known size
 # (profiles/k_step_human80_4096_traffic.md), valid for the kernel source with
 # this SHA-256 prefix only (reported as null otherwise).
-TRAFFIC_BYTES_PER_LAUNCH = 53.7e6
-TRAFFIC_KERNEL_SHA = "3cd755f039db850e"
+TRAFFIC_BYTES_PER_LAUNCH = 53.6e6
+TRAFFIC_KERNEL_SHA = "0074a7fb407c97ad"
 
 
 def parse():
@@ -451,15 +451,18 @@ def rad_compare(run, ref, surrogate=False):
     ok = (so == 0) & (stg == 0)
     de = np.abs(qg[:, 7:] - qo[:, 7:]).max(axis=1)[ok]
     spread = spread[ok]
-    sens = spread > 1e-3
+    bound = np.maximum(1e-3, 2.0 * spread)
+    sens = bound > 1e-3
     return {"max": float(de.max()), "median_env": float(np.median(de)), "envs": int(ok.sum()),
-            "steps": RAD_T, "fp32_sensitive_envs": int(sens.sum()),
+            "steps": RAD_T, "envs_within_bound": int((de <= bound).sum()),
+            "fp32_sensitive_envs": int(sens.sum()),
             "max_other_envs": float(de[~sens].max()) if (~sens).any() else None,
             "sensitive_env_errors": [round(float(v), 6) for v in de[sens]],
             "sensitive_env_control_spread": [round(float(v), 6) for v in spread[sens]],
-            "note": "max over hinge angles per env, GPU FP32(+FP64 solve) vs FP64 oracle; an env "
-                    "is FP32-sensitive when the oracle itself, rounded to FP32 and perturbed by "
-                    "1e-5 per step, moves more than 1e-3 rad"
+            "note": "max over hinge angles per env, GPU FP32(+FP64 solve) vs FP64 oracle; each "
+                    "env's bound is max(1e-3 rad, twice the spread of the oracle itself rounded "
+                    "to FP32 and perturbed by 1e-5 per step, three draws); an env whose bound "
+                    "exceeds 1e-3 rad is FP32-sensitive"
                     + ("; learned geometry with fallback" if surrogate else "")}
 
 
@@ -491,18 +494,21 @@ def cpu_baseline(m, dt, seconds):
             "single_thread_env_steps_per_s": 1.0 / per}
     # the oracle's trajectories of the radian-error sample, and a control: the
     # oracle again with its state rounded to float32 and its velocities
-    # perturbed by 1e-5 relative noise after every step (the per-step bound);
-    # an env whose control moves more than 1e-3 rad in RAD_T steps has no
-    # unique FP32 trajectory
+    # perturbed by 1e-5 relative noise after every step (the per-step bound),
+    # three seeded draws; its spread is how far errors of the permitted size
+    # carry each env in RAD_T steps
     q, qd, act, u = rad_inputs(m, dt)
     qo, _, _, so = o.rollout(dt, q, qd, act, u, contact=True)
     rng = np.random.default_rng(2024)
-    qc, qdc, ac = q.copy(), qd.copy(), act.copy()
-    for k in range(RAD_T):
-        qc, qdc, ac, _ = o.rollout(dt, qc, qdc, ac, u[k:k + 1], contact=True)
-        qdc = qdc * (1.0 + 1e-5 * rng.standard_normal(qdc.shape))
-        qc, qdc, ac = (v.astype(np.float32) for v in (qc, qdc, ac))
-    return base, (qo, so, np.abs(qc[:, 7:] - qo[:, 7:]).max(axis=1))
+    spread = np.zeros(len(q))
+    for _ in range(3):
+        qc, qdc, ac = q.copy(), qd.copy(), act.copy()
+        for k in range(RAD_T):
+            qc, qdc, ac, _ = o.rollout(dt, qc, qdc, ac, u[k:k + 1], contact=True)
+            qdc = qdc * (1.0 + 1e-5 * rng.standard_normal(qdc.shape))
+            qc, qdc, ac = (v.astype(np.float32) for v in (qc, qdc, ac))
+        spread = np.maximum(spread, np.abs(qc[:, 7:] - qo[:, 7:]).max(axis=1))
+    return base, (qo, so, spread)
 
 
 if __name__ == "__main__":

@@ -87,14 +87,16 @@ __device__ __forceinline__ AR1 ar1_step(unsigned long long key, int mi, float x,
 
 // Hill curves: Gaussian active force-length, exponential passive
 // force-length with a linear tail past 1.6, hyperbolic force-velocity.
+// The curves use the hardware exponential (a few ulp), far inside the
+// step's error bound.
 __device__ __forceinline__ float hill_fl(float lm) {
   float d = lm - 1.0f;
-  return expf(-d * d * (1.0f / 0.45f));
+  return __expf(-d * d * (1.0f / 0.45f));
 }
 __device__ __forceinline__ float hill_fp(float lm) {
   const float e4m1 = 53.598150033144236f;  // e^4 - 1
   if (lm <= 1.0f) return 0.0f;
-  if (lm <= 1.6f) return (expf((4.0f / 0.6f) * (lm - 1.0f)) - 1.0f) / e4m1;
+  if (lm <= 1.6f) return (__expf((4.0f / 0.6f) * (lm - 1.0f)) - 1.0f) * (1.0f / e4m1);
   return 1.0f + 6.7910995f * (lm - 1.6f);  // slope (4/0.6) e^4/(e^4-1)
 }
 __device__ __forceinline__ float hill_fv(float vm) {
@@ -197,10 +199,12 @@ __device__ __forceinline__ float muscle_geometry(const KModel &M, int m, int Pg,
     gk[k] = v3(0.f, 0.f, 0.f);
     if (k < Pg) {
       if (k + 1 < P) {
+        // segment length and unit vector from one hardware reciprocal
+        // square root (about 1 ulp)
         V3 d = w[k + 1] - w[k];
-        float l = sqrtf(dot(d, d));
-        L += l;
-        V3 e = (1.0f / l) * d;
+        const float dd = dot(d, d), rl = __builtin_amdgcn_rsqf(dd);
+        L += dd * rl;
+        V3 e = rl * d;
         gk[k] = eprev - e;
         eprev = e;
       } else if (k + 1 == P) {

@@ -369,3 +369,80 @@ def test_singular_mass_matrix_is_flagged(chain):
     assert (st == ms.MS_ST_NONSPD).all()
     assert np.array_equal(q1, q)
     assert o.step(2e-3, q[0], qd[0], act[0], u[0, 0])[3] == 2
+
+
+# ------------------------------------------- the kernel's other instantiations
+def _paths(m, n_via, n_long=16, seed=3):
+    """The model with every muscle path cut to at most n_via via-points
+    (interior points dropped) and, when n_via exceeds the generator's
+    longest path, the first n_long paths lengthened to n_via by points on
+    the origin's body 1-3 cm from the origin; tendon slacks shifted so the
+    fibres keep their neutral lengths."""
+    rng = np.random.default_rng(seed)
+    orig, m = m, dict(m)
+    vs, vn, vp = m["via_start"], m["via_node"], m["via_pos"]
+    starts, nodes, pos = [0], [], []
+    for k in range(m["n_mus"]):
+        nk = [int(x) for x in vn[vs[k]:vs[k + 1]]]
+        pk = [np.array(x) for x in vp[vs[k]:vs[k + 1]]]
+        while len(nk) > n_via:
+            del nk[1], pk[1]
+        if k < n_long:
+            while len(nk) < n_via:
+                off = rng.uniform(0.01, 0.03, 3) * rng.choice([-1.0, 1.0], 3)
+                nk.insert(1, nk[0])
+                pk.insert(1, pk[0] + off)
+        nodes += nk
+        pos += pk
+        starts.append(len(nodes))
+    m["via_start"] = np.array(starts, vs.dtype)
+    m["via_node"] = np.array(nodes, vn.dtype)
+    m["via_pos"] = np.array(pos, vp.dtype)
+    # keep each fibre's neutral length: the tendon slack takes up the change
+    # of the neutral path length (the oracle's geometry of both paths)
+    q0 = np.asarray(synth.human_initial_state(m, 1)[0][0], np.float64)
+    z = np.zeros(m["nv"])
+    dL = Oracle(m).geometry(q0, z)[0] - Oracle(orig).geometry(q0, z)[0]
+    m["l_slack"] = (m["l_slack"] + dL).astype(m["l_slack"].dtype)
+    return m
+
+
+@pytest.mark.parametrize("n_mus,n_via", [(100, 4), (200, 5), (1024, 8)])
+def test_other_kernel_shapes_stages_and_rollout(n_mus, n_via):
+    """Muscle counts and path lengths that select the step kernel's other
+    instantiations (2, 4 and 16 muscles per lane; via-point bounds 4 and 8;
+    1024 muscles and 8 via-points are the library's maxima) on the whole
+    body: stage outputs against the oracle, and a rollout bitwise equal to
+    repeated single steps."""
+    m = _paths(synth.human_model(7, n_mus=n_mus), n_via)
+    assert int(np.diff(m["via_start"]).max()) == n_via
+    gm, o = ms.Model(m), Oracle(m)
+    dt, E = 1e-3, 8
+    q, qd, act = _warm_states(m, o, E, 20, dt, "ar1", 21, True, synth.human_initial_state)
+    u = synth.excitation_iid(5, E, m["n_mus"], 0)
+    out = gm.step_stages(_t(q), _t(qd), _t(act), _t(u), dt, True)
+    out = {k: v.cpu().numpy() for k, v in out.items()}
+    spans = gm.spans()
+    for e in range(E):
+        _, _, _, st, S = o.step(dt, q[e], qd[e], act[e], u[e], contact=True, stages=True)
+        assert st == 0
+        assert np.abs(out["act"][e] - S["act"]).max() < 2e-7
+        assert np.abs(out["L"][e] - S["L"]).max() < 4e-6
+        for s in range(3):
+            ok = spans[:, s] >= 0
+            if ok.any():
+                d = out["r"][e][ok, s] - S["r"][np.arange(m["n_mus"])[ok], spans[ok, s]]
+                assert np.abs(d).max() < 4e-6
+        assert np.abs(out["F"][e] - S["F"]).max() < 2e-4 * m["f0"].max()
+        qscale = max(np.abs(S["qdd"]).max(), 1.0)
+        assert np.abs(out["qdd"][e] - S["qdd"]).max() < 1e-3 * qscale
+    # a 6-step rollout equals 6 single steps, bit for bit
+    us = np.stack([synth.excitation_iid(9, E, m["n_mus"], t) for t in range(6)])
+    a = [_t(q), _t(qd), _t(act), torch.zeros(E, dtype=torch.int32, device=DEV)]
+    b = [v.clone() for v in a]
+    gm.rollout(*a, 6, dt, True, kind=ms.EXC_ARRAY, u=_t(us))
+    for t in range(6):
+        gm.step_batch(*b, _t(us[t]), dt, True)
+    torch.cuda.synchronize()
+    for x, y in zip(a, b):
+        assert torch.equal(x, y)

@@ -446,3 +446,32 @@ def test_other_kernel_shapes_stages_and_rollout(n_mus, n_via):
     torch.cuda.synchronize()
     for x, y in zip(a, b):
         assert torch.equal(x, y)
+
+
+def test_argument_errors_leave_the_state_unchanged(chain):
+    """Calls with invalid arguments return MS_E_ARG before any launch and
+    touch no state; a rollout of zero steps is a no-op."""
+    m, gm, o = chain
+    E = 4
+    q, qd, act = synth.chain_initial_state(m, E)
+    a = [_t(q), _t(qd), _t(act), torch.zeros(E, dtype=torch.int32, device=DEV)]
+    ref = [v.clone() for v in a]
+    u = _t(synth.excitation_iid(5, E, m["n_mus"], 0))
+    bad = {
+        "no envs": lambda: gm.step_batch(*[v[:0] for v in a], u[:0], 2e-3, False),
+        "dt = 0": lambda: gm.step_batch(*a, u, 0.0, False),
+        "dt < 0": lambda: gm.step_batch(*a, u, -1e-3, False),
+        "dt NaN": lambda: gm.step_batch(*a, u, float("nan"), False),
+        "negative steps": lambda: gm.rollout(*a, -1, 2e-3, False, kind=ms.EXC_IID, seed=1),
+        "unknown excitation": lambda: gm.rollout(*a, 5, 2e-3, False, kind=7, seed=1),
+        "AR(1) without its state": lambda: gm.rollout(*a, 5, 2e-3, False, kind=ms.EXC_AR1),
+        "array excitation without u": lambda: gm.rollout(*a, 5, 2e-3, False, kind=ms.EXC_ARRAY),
+    }
+    for name, call in bad.items():
+        with pytest.raises(ms.MsError) as ei:
+            call()
+        assert ei.value.code == -1, name
+    gm.rollout(*a, 0, 2e-3, False, kind=ms.EXC_IID, seed=1)
+    torch.cuda.synchronize()
+    for x, y in zip(a, ref):
+        assert torch.equal(x, y)

@@ -5,7 +5,8 @@
 // with float32 accumulators. Operand tiles of 32 along K are staged through
 // LDS as [row][k] (k contiguous, rows padded to 40 elements), so every lane
 // reads its 8 consecutive k values of a row with one 128-bit LDS load;
-// operands stored K-major in memory are transposed while being staged.
+// operands stored K-major in memory are transposed while being staged. The
+// next K tile is fetched into registers while the current one is multiplied.
 #include "ms_gemm.h"
 
 namespace ms {
@@ -15,31 +16,47 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 constexpr int BM = 128, BN = 128, BK = 32, LK = BK + 8;
 
-// Stage a 128 (rows) x 32 (k) tile of a matrix whose element (o, k) lives at
-// G[o * ld + k] (row-major, KMAJOR = false) or G[k * ld + o] (KMAJOR = true)
-// into S[o * LK + k]; out-of-range elements are zero.
+// A 128 (rows) x 32 (k) tile of a matrix whose element (o, k) lives at
+// G[o * ld + k] (row-major, KMAJOR = false) or G[k * ld + o] (KMAJOR = true),
+// in two steps so the next tile's global loads can be in flight while the
+// current one is multiplied: fetch (two 128-bit global loads per thread
+// into registers; out-of-range elements are zero), then store into
+// S[o * LK + k] (K-major tiles transposed on the way).
 template <bool KMAJOR>
-__device__ __forceinline__ void stage(unsigned short *S, const bf16 *G, int ld, int o0, int O, int k0,
-                                      int K, int tid) {
+__device__ __forceinline__ void fetch(uint4 v[2], const bf16 *G, int ld, int o0, int O, int k0, int K,
+                                      int tid) {
   const unsigned short *g = reinterpret_cast<const unsigned short *>(G);
+#pragma unroll
+  for (int it = 0; it < 2; ++it) {
+    const int c = tid + 256 * it;
+    v[it] = make_uint4(0, 0, 0, 0);
+    if (!KMAJOR) {
+      const int o = c >> 2, kc = (c & 3) * 8;
+      const int go = o0 + o, gk = k0 + kc;
+      if (go < O && gk < K) v[it] = *reinterpret_cast<const uint4 *>(g + (size_t)go * ld + gk);
+    } else {
+      const int kk = c >> 4, oc = (c & 15) * 8;
+      const int go = o0 + oc, gk = k0 + kk;
+      if (go < O && gk < K) v[it] = *reinterpret_cast<const uint4 *>(g + (size_t)gk * ld + go);
+    }
+  }
+}
+
+template <bool KMAJOR>
+__device__ __forceinline__ void store(unsigned short *S, const uint4 v[2], int tid) {
 #pragma unroll
   for (int it = 0; it < 2; ++it) {
     const int c = tid + 256 * it;
     if (!KMAJOR) {
       const int o = c >> 2, kc = (c & 3) * 8;
-      const int go = o0 + o, gk = k0 + kc;
-      uint4 v = make_uint4(0, 0, 0, 0);
-      if (go < O && gk < K) v = *reinterpret_cast<const uint4 *>(g + (size_t)go * ld + gk);
-      *reinterpret_cast<uint4 *>(S + o * LK + kc) = v;
+      *reinterpret_cast<uint4 *>(S + o * LK + kc) = v[it];
     } else {
       const int kk = c >> 4, oc = (c & 15) * 8;
-      const int go = o0 + oc, gk = k0 + kk;
-      uint4 v = make_uint4(0, 0, 0, 0);
-      if (go < O && gk < K) v = *reinterpret_cast<const uint4 *>(g + (size_t)gk * ld + go);
-      const unsigned short e[8] = {(unsigned short)(v.x & 0xFFFF), (unsigned short)(v.x >> 16),
-                                   (unsigned short)(v.y & 0xFFFF), (unsigned short)(v.y >> 16),
-                                   (unsigned short)(v.z & 0xFFFF), (unsigned short)(v.z >> 16),
-                                   (unsigned short)(v.w & 0xFFFF), (unsigned short)(v.w >> 16)};
+      const uint4 w = v[it];
+      const unsigned short e[8] = {(unsigned short)(w.x & 0xFFFF), (unsigned short)(w.x >> 16),
+                                   (unsigned short)(w.y & 0xFFFF), (unsigned short)(w.y >> 16),
+                                   (unsigned short)(w.z & 0xFFFF), (unsigned short)(w.z >> 16),
+                                   (unsigned short)(w.w & 0xFFFF), (unsigned short)(w.w >> 16)};
 #pragma unroll
       for (int j = 0; j < 8; ++j) S[(oc + j) * LK + kk] = e[j];
     }
@@ -70,10 +87,20 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const bf16 *A
     for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
 
   const int kb = blockIdx.z * k_slice, ke = min(K, kb + k_slice);
+  uint4 ra[2], rb[2];
+  if (kb < ke) {
+    fetch<TA>(ra, A, lda, m0, M, kb, ke, tid);
+    fetch<!TB>(rb, B, ldb, n0, N, kb, ke, tid);
+  }
   for (int k0 = kb; k0 < ke; k0 += BK) {
-    stage<TA>(As, A, lda, m0, M, k0, ke, tid);
-    stage<!TB>(Bs, B, ldb, n0, N, k0, ke, tid);
+    store<TA>(As, ra, tid);
+    store<!TB>(Bs, rb, tid);
     __syncthreads();
+    // the next tile's loads travel while this one is multiplied
+    if (k0 + BK < ke) {
+      fetch<TA>(ra, A, lda, m0, M, k0 + BK, ke, tid);
+      fetch<!TB>(rb, B, ldb, n0, N, k0 + BK, ke, tid);
+    }
     bf16x8 a[4], b[4];
     const int kq = (lane >> 4) * 8, r = lane & 15;
 #pragma unroll

@@ -320,7 +320,8 @@ ms_status ms_batch_rollout(ms_batch *b, const ms_batch_state *states,
 /* Autotuner: per model alone, probe rollouts of n_probe steps for 1, 2 and 4
  * envs per workgroup (each env is one wavefront with its own LDS block); then
  * (fastest of three probes each); then the whole batch in each of the
- * three issue modes, as graph replays (mean of three after a warm-up). Each workgroup steps its envs through a whole
+ * three issue modes, as graph replays (mean of three after a warm-up); a
+ * concurrent mode is kept only if it beats serial issue by more than 2 %. Each workgroup steps its envs through a whole
  * rollout, so the best issue mode depends on the rollout length: probe with
  * the n_steps the batch will run. Probes run on scratch copies of the given states (left unchanged);
  * the fastest choices are kept in the batch. Synchronises `stream`. */

@@ -301,6 +301,8 @@ class Surrogate:
         self.n_in, self.h1, self.h2, self.n_out = (int(x) for x in d)
         self.shapes = [(self.h1, self.n_in), (self.h1,), (self.h2, self.h1), (self.h2,),
                        (self.n_out, self.h2), (self.n_out,)]
+        # the output standardisation last set (the library starts at 0 / 1)
+        self.norm = (np.zeros(self.n_out, np.float32), np.ones(self.n_out, np.float32))
 
     def __del__(self):
         try:
@@ -330,6 +332,25 @@ class Surrogate:
         m = np.ascontiguousarray(mean, np.float32)
         s = np.ascontiguousarray(std, np.float32)
         _check_s(lib().ms_surrogate_set_norm(self.h, m.ctypes.data_as(_fptr), s.ctypes.data_as(_fptr)))
+        self.norm = (m.copy(), s.copy())
+
+    _KEYS = ("W1", "b1", "W2", "b2", "W3", "b3")
+
+    def save(self, path):
+        """Write the network (float32 master weights and biases, output
+        standardisation, layer sizes) to an .npz file."""
+        np.savez(path, dims=np.array([self.n_in, self.h1, self.h2, self.n_out], np.int32),
+                 mean=self.norm[0], std=self.norm[1], **dict(zip(self._KEYS, self.params())))
+
+    def load(self, path):
+        """Read a network written by save() into this one (same layer sizes);
+        the file holds plain arrays and is read without unpickling."""
+        with np.load(path, allow_pickle=False) as z:
+            dims = tuple(int(x) for x in z["dims"])
+            if dims != (self.n_in, self.h1, self.h2, self.n_out):
+                raise ValueError(f"saved network has layer sizes {dims}")
+            self.set_params([z[k] for k in self._KEYS])
+            self.set_norm(z["mean"], z["std"])
 
     def sample(self, q, seed, offset=0, stream=None):
         _check_s(lib().ms_surrogate_sample(self.h, q.shape[0], seed, offset, _dp(q), _stream(stream)))

@@ -332,3 +332,28 @@ def test_training_gain_fewer_fallbacks_and_smaller_error():
           f"fallback rate at 1 cm {f0:.3f} untrained, {f1:.3f} trained")
     assert e1 <= 0.1 * e0 and e1 <= 1e-2
     assert f0 >= 0.95 and f1 <= 0.05
+
+
+def test_save_and_load_reproduce_the_network(setup, tmp_path):
+    """A network written by save() and read into a fresh one with load()
+    predicts bit for bit the same lengths and moment arms."""
+    m, gm, s, o = setup
+    rng = np.random.default_rng(31)
+    s.set_params([rng.normal(0, 0.3, sh).astype(np.float32) for sh in s.shapes])
+    s.set_norm(rng.normal(0, 0.1, s.n_out).astype(np.float32),
+               rng.uniform(0.5, 2.0, s.n_out).astype(np.float32))
+    path = tmp_path / "net.npz"
+    s.save(path)
+    s2 = ms.Surrogate(gm, hidden=s.h1, seed=99)
+    s2.load(path)
+    q = _t(_poses(m, 40, 12))
+    outs = []
+    for net in (s, s2):
+        L = torch.empty(40, m["n_mus"], device=DEV)
+        r = torch.empty(40, m["n_mus"], 3, device=DEV)
+        net.forward(q, L, r)
+        outs.append((L, r))
+    torch.cuda.synchronize()
+    assert torch.equal(outs[0][0], outs[1][0]) and torch.equal(outs[0][1], outs[1][1])
+    for a, b in zip(s.params(), s2.params()):
+        assert np.array_equal(a, b)

@@ -44,7 +44,7 @@ def output_stats(gm: ms.Model, s: ms.Surrogate, n: int = 8192, seed: int = 40):
 
 
 def train(gm: ms.Model, s: ms.Surrogate, n_samples: int = 10_000_000, batch: int = 8192,
-          epochs: float = 1.0, lr0: float = 1e-3, lr1: float = 1e-5, seed: int = 41,
+          epochs: float = 1.0, lr0: float = 1e-2, lr1: float = 1e-5, seed: int = 41,
           log_every: int = 0, stream=None):
     """Adam with a cosine learning-rate decay from lr0 to lr1 over
     epochs * n_samples samples (sample ids cycle through 0..n_samples-1).

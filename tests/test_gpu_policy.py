@@ -77,3 +77,32 @@ def test_policy_rollout_equals_steps_driven_by_its_recorded_excitations(setup):
     torch.cuda.synchronize()
     for a, b in ((tq, eq), (tqd, eqd), (tact, eact), (st, est)):
         assert np.array_equal(a.cpu().numpy(), b.cpu().numpy())
+
+
+def test_full_size_policy_rollout_sampled_against_oracle(setup):
+    """The policy-driven workload at its full size: 65,536 envs, decisions
+    every 2 steps, the surrogate geometry with per-env fallback. An untrained
+    network fails the residual check everywhere, so every env-step takes the
+    exact geometry; 16 sampled envs are compared with the oracle driven by
+    the recorded excitations."""
+    m, gm, p, o = setup
+    E, T, decim = 65536, 10, 2
+    q, qd, act = synth.human_initial_state(m, E)
+    tq, tqd, tact = _t(q), _t(qd), _t(act)
+    st = torch.zeros(E, dtype=torch.int32, device=DEV)
+    fb = torch.zeros(E, dtype=torch.int32, device=DEV)
+    rec = torch.zeros(T // decim, E, m["n_mus"], device=DEV)
+    sg = ms.Surrogate(gm, hidden=512, seed=41)
+    p.rollout(tq, tqd, tact, st, T, decim, DT, contact=True, t0=0.0, surrogate=sg, tol=1e-4,
+              fb_count=fb, u_record=rec)
+    torch.cuda.synchronize()
+    assert (fb.cpu().numpy() == T).all()
+    assert ((st.cpu().numpy() & ~ms.MS_ST_FALLBACK) == 0).all()
+    sub = np.arange(17, E, 4096)
+    u = np.repeat(rec.cpu().numpy()[:, sub], decim, axis=0)
+    qo, qdo, ao, so = o.rollout(DT, q[sub], qd[sub], act[sub], u, contact=True)
+    assert (so == 0).all()
+    qg, qdg, ag = (v.cpu().numpy()[sub] for v in (tq, tqd, tact))
+    assert np.abs(qg[:, 7:] - qo[:, 7:]).max() < 1e-5
+    assert np.abs(qdg - qdo).max() < 1e-4 * max(np.abs(qdo).max(), 1.0)
+    assert np.abs(ag - ao).max() < 1e-6

@@ -108,3 +108,16 @@ def test_oversized_workgroup_is_rejected(three):
             b.set_config([4], 0)
     else:
         b.set_config([4], 0)
+
+
+def test_full_size_batch_matches_each_model_alone(three):
+    """The uneven-batch workload at its full size (4096 + 4096 + 8192 envs of
+    the three models, autotuned, replayed as a graph) equals each model's
+    rollout alone, bit for bit."""
+    mods, gms, inits, _ = three
+    n_env = [4096, 4096, 8192]
+    T = 20
+    b = ms.Batch(gms, n_env)
+    bufs = [_fresh(m, init, n) for m, init, n in zip(mods, inits, n_env)]
+    b.autotune([tuple(v[:4]) for v in bufs], [_exc(v[4], 0) for v in bufs], T, DT)
+    _same(_batched(mods, b, inits, n_env, T), _alone(mods, gms, inits, n_env, T))

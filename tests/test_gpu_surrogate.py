@@ -357,3 +357,34 @@ def test_save_and_load_reproduce_the_network(setup, tmp_path):
     assert torch.equal(outs[0][0], outs[1][0]) and torch.equal(outs[0][1], outs[1][1])
     for a, b in zip(s.params(), s2.params()):
         assert np.array_equal(a, b)
+
+
+def test_full_size_surrogate_rollout_falls_back_to_the_exact_path():
+    """The surrogate workload at its full size (whole body, 4096 envs, AR(1)
+    excitations in-kernel, 1e-4 m residual check): a network that fails the
+    check everywhere (untrained) sends every env-step to the exact geometry,
+    and the rollout is the exact path's, bit for bit."""
+    m = synth.human_model(2)
+    gm = ms.Model(m)
+    s = ms.Surrogate(gm, hidden=512, seed=41)
+    E, T, dt = 4096, 10, 1e-3
+    q, qd, act = synth.human_initial_state(m, E)
+    consts = synth.ar1_constants(dt)[:3]
+    runs = []
+    for sur in (True, False):
+        tq, tqd, tact = _t(q), _t(qd), _t(act)
+        tx = torch.zeros(E, m["n_mus"], device=DEV)
+        st = torch.zeros(E, dtype=torch.int32, device=DEV)
+        fb = torch.zeros(E, dtype=torch.int32, device=DEV)
+        if sur:
+            gm.rollout_surrogate(s, tq, tqd, tact, st, T, dt, True, tol=1e-4, fb_count=fb,
+                                 kind=ms.EXC_AR1, seed=12, x=tx, ar1=consts)
+        else:
+            gm.rollout(tq, tqd, tact, st, T, dt, True, kind=ms.EXC_AR1, seed=12, x=tx, ar1=consts)
+        torch.cuda.synchronize()
+        runs.append([v.cpu().numpy() for v in (tq, tqd, tact, tx, st, fb)])
+    a, b = runs
+    for k in range(4):
+        assert np.array_equal(a[k], b[k])
+    assert ((a[4] & ~ms.MS_ST_FALLBACK) == b[4]).all()
+    assert (a[5] == T).all()

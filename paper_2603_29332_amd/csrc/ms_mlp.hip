@@ -130,7 +130,7 @@ __global__ __launch_bounds__(256) void k_loss(const float *Y, const float *T, co
   red[threadIdx.x] = l;
   __syncthreads();
   for (int s = 128; s > 0; s >>= 1) {
-    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
     __syncthreads();
   }
   if (threadIdx.x == 0) part[blockIdx.x] = red[0];
@@ -146,7 +146,7 @@ __global__ __launch_bounds__(256) void k_loss_final(const float *part, int nb, i
   red[threadIdx.x] = s;
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
-    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
     __syncthreads();
   }
   if (threadIdx.x == 0) *loss = (float)(red[0] / ((double)n * (double)n_out));
@@ -579,7 +579,7 @@ __device__ __forceinline__ float ref_target(unsigned long long seed, long long e
 
 // one thread per (env, input); obs_out (optional) gets the unpadded float32
 // observation
-__global__ void k_obs(int n, int nq, int nv, int free_root, int n_ref, int n_obs, int n_in,
+__global__ void k_obs(int n, int nq, int nv, int free_root, int n_obs, int n_in,
                       const float *q, const float *qd, float t, unsigned long long seed,
                       long long env0, bf16 *X, float *obs_out) {
   const long long tid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -627,7 +627,7 @@ ms_status policy_forward(ms_policy *p, int n, const float *q, const float *qd, d
   ms_status r = policy_cap(p, n);
   if (r != MS_OK) return r;
   hipLaunchKernelGGL(k_obs, dim3(blocks((long long)n * p->n_in)), dim3(256), 0, st, n, p->nq, p->nv,
-                     p->free_root, p->n_ref, p->n_obs, p->n_in, q, qd, (float)t, p->ref_seed,
+                     p->free_root, p->n_obs, p->n_in, q, qd, (float)t, p->ref_seed,
                      (long long)env0, p->X, obs_out);
   GemmEpi e1;
   e1.bias = p->b[0];

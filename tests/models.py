@@ -61,3 +61,28 @@ def free_body(m=3.0, inertia=(0.02, 0.05, 0.08), com=(0.0, 0.0, 0.0),
     """A single free-floating rigid body."""
     return _base([-1], [2], [[0, 0, 0]], [[0, 0, 0]], [m], [list(com)],
                  [list(inertia)], gravity=gravity)
+
+
+def mixed_chain():
+    """Fixed base 1.015 m up; hinge y, slide z, hinge x, slide x, hinge y down
+    a 1 m chain; a tip sphere just touching the ground; five muscles spanning
+    hinges and slides (one or two joints each), tendon slacks set so that the
+    fibres sit at their optimal length at q = 0."""
+    from oracle import Oracle
+    parent = [-1, 0, 1, 2, 3]
+    jtype = [0, 1, 0, 1, 0]
+    jpos = [[0, 0, 1.015], [0, 0, -0.3], [0, 0, -0.1], [0, 0, -0.3], [0.05, 0, -0.1]]
+    axis = [[0, 1, 0], [0, 0, 1], [1, 0, 0], [1, 0, 0], [0, 1, 0]]
+    mass = [2.0, 1.0, 1.5, 0.8, 0.6]
+    com = [[0, 0, -0.15], [0, 0, -0.05], [0, 0, -0.15], [0, 0, -0.05], [0, 0, -0.1]]
+    inertia = [[0.02, 0.02, 0.005], [0.005] * 3, [0.01, 0.01, 0.003], [0.003] * 3, [0.002] * 3]
+    mus = [(800.0, 0.10, 0.0, [(-1, [0.03, 0, 0.97]), (0, [0.03, 0, -0.2])]),
+           (600.0, 0.08, 0.0, [(0, [0.02, 0.02, -0.1]), (1, [0.02, 0, -0.05])]),
+           (700.0, 0.12, 0.0, [(1, [0, 0.03, -0.02]), (2, [0, 0.03, -0.1]), (3, [0, 0.02, -0.05])]),
+           (500.0, 0.09, 0.0, [(2, [-0.03, 0, -0.05]), (4, [-0.02, 0, -0.05])]),
+           (900.0, 0.11, 0.0, [(-1, [-0.03, 0, 0.97]), (1, [-0.03, 0, -0.02])])]
+    m = _base(parent, jtype, jpos, axis, mass, com, inertia, damping=[0.1] * 5,
+              muscles=mus, contacts=[(4, [0, 0, -0.2], 0.02)])
+    L0 = Oracle(m).geometry(np.zeros(m["nq"]), np.zeros(m["nv"]))[0]
+    m["l_slack"] = (L0 - m["l_opt"]).astype(m["l_slack"].dtype)
+    return m

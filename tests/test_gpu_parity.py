@@ -475,3 +475,51 @@ def test_argument_errors_leave_the_state_unchanged(chain):
     torch.cuda.synchronize()
     for x, y in zip(a, ref):
         assert torch.equal(x, y)
+
+
+def test_slide_joints_stages_and_free_run():
+    """Hinges and slides mixed on a fixed-base chain with muscles over both
+    and a tip sphere in ground contact (the kernel's slide paths: kinematics,
+    motion subspaces, moment arms): stage outputs against the oracle, and 100
+    steps of i.i.d. excitations against the oracle's rollout."""
+    import sys
+    import os
+    sys.path.insert(0, os.path.dirname(__file__))
+    import models
+    m = models.mixed_chain()
+    gm, o = ms.Model(m), Oracle(m)
+    dt, E = 1e-3, 16
+    rng = np.random.default_rng(8)
+    q0 = rng.uniform(-0.05, 0.05, (E, m["nq"])).astype(np.float32)
+    qd0 = np.zeros((E, m["nv"]), np.float32)
+    a0 = np.zeros((E, m["n_mus"]), np.float32)
+    u, _ = synth.excitation_sequence("iid", 3, E, m["n_mus"], 20, dt)
+    q, qd, act, st = o.rollout(dt, q0, qd0, a0, u, contact=True)
+    assert (st == 0).all()
+    q, qd, act = (v.astype(np.float32) for v in (q, qd, act))
+    u1 = synth.excitation_iid(5, E, m["n_mus"], 0)
+    out = {k: v.cpu().numpy() for k, v in
+           gm.step_stages(_t(q), _t(qd), _t(act), _t(u1), dt, True).items()}
+    spans = gm.spans()
+    for e in range(E):
+        _, _, _, s, S = o.step(dt, q[e], qd[e], act[e], u1[e], contact=True, stages=True)
+        assert s == 0
+        assert np.abs(out["act"][e] - S["act"]).max() < 2e-7
+        assert np.abs(out["L"][e] - S["L"]).max() < 2e-6
+        for sl in range(3):
+            ok = spans[:, sl] >= 0
+            if ok.any():
+                d = out["r"][e][ok, sl] - S["r"][np.arange(m["n_mus"])[ok], spans[ok, sl]]
+                assert np.abs(d).max() < 2e-6
+        assert np.abs(out["F"][e] - S["F"]).max() < 2e-4 * m["f0"].max()
+        qscale = max(np.abs(S["qdd"]).max(), 1.0)
+        assert np.abs(out["qdd"][e] - S["qdd"]).max() < 1e-3 * qscale
+    T = 100
+    us, _ = synth.excitation_sequence("iid", 4, E, m["n_mus"], T, dt)
+    tq, tqd, tact = _t(q0), _t(qd0), _t(a0)
+    tst = torch.zeros(E, dtype=torch.int32, device=DEV)
+    gm.rollout(tq, tqd, tact, tst, T, dt, True, kind=ms.EXC_ARRAY, u=_t(us))
+    torch.cuda.synchronize()
+    qo, _, _, so = o.rollout(dt, q0, qd0, a0, us, contact=True)
+    assert (so == 0).all() and (tst.cpu().numpy() == 0).all()
+    assert np.abs(tq.cpu().numpy() - qo).max() < 1e-4

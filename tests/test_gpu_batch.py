@@ -121,3 +121,38 @@ def test_full_size_batch_matches_each_model_alone(three):
     bufs = [_fresh(m, init, n) for m, init, n in zip(mods, inits, n_env)]
     b.autotune([tuple(v[:4]) for v in bufs], [_exc(v[4], 0) for v in bufs], T, DT)
     _same(_batched(mods, b, inits, n_env, T), _alone(mods, gms, inits, n_env, T))
+
+
+def test_calls_recorded_in_a_caller_graph_replay_like_eager_calls(three):
+    """ms_rollout and ms_batch_rollout (concurrent issue: its forked streams
+    join the caller's capture) recorded inside a caller's stream capture (a
+    torch CUDA graph): each of three replays, with eager calls and
+    synchronisations between them, advances the state exactly as the same
+    calls made eagerly."""
+    mods, gms, inits, n_env = three
+    T = 5
+    m, gm, init, n = mods[2], gms[2], inits[2], n_env[2]
+    A, B = _fresh(m, init, n), _fresh(m, init, n)
+    kw = dict(kind=ms.EXC_IID, seed=3, step0=7)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        gm.rollout(*A[:4], T, DT, True, **kw)
+    b = ms.Batch(gms, n_env)
+    b.set_config([2, 4, 4], ms.ISSUE_CONCURRENT)
+    bA = [_fresh(mm, ii, nn) for mm, ii, nn in zip(mods, inits, n_env)]
+    bB = [_fresh(mm, ii, nn) for mm, ii, nn in zip(mods, inits, n_env)]
+    g2 = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g2):
+        b.rollout([tuple(v[:4]) for v in bA], [_exc(v[4], 0) for v in bA], T, DT)
+    for _ in range(3):
+        g.replay()
+        gm.rollout(*B[:4], T, DT, True, **kw)
+        g2.replay()
+        b.rollout([tuple(v[:4]) for v in bB], [_exc(v[4], 0) for v in bB], T, DT)
+        torch.cuda.synchronize()
+        for x, y in zip(A[:4], B[:4]):
+            assert torch.equal(x, y)
+        for u, v in zip(bA, bB):
+            for x, y in zip(u, v):
+                assert torch.equal(x, y)

@@ -149,14 +149,23 @@ void ms_model_destroy(ms_model *m);
 ms_status ms_model_info_get(const ms_model *m, ms_model_info *out);
 
 /* One step for n_env envs, in place on the caller's device state, reading
- * excitations u[n_env][n_mus] (device). env i uses row i of every array. */
+ * excitations u[n_env][n_mus] (device). env i uses row i of every array.
+ * status may be NULL (failures then go unreported; the failed env's state
+ * is still left unchanged for the step); an env whose status already has
+ * bits set is stepped like any other. MS_E_ARG, before any launch and with
+ * no state touched: NULL model, n_env <= 0, a NULL state pointer (act and u
+ * may be NULL only for a model without muscles), NULL opts, dt not positive
+ * and finite. */
 ms_status ms_step_batch(ms_model *m, int32_t n_env, float *q, float *qd,
                         float *act, uint32_t *status, const float *u,
                         const ms_step_opts *opts, void *stream);
 
 /* n_steps steps for n_env envs in one launch, the state kept on chip
  * between steps; excitations from exc. Bitwise equal to n_steps calls of
- * ms_step_batch with the same excitations. */
+ * ms_step_batch with the same excitations. n_steps = 0 does nothing.
+ * MS_E_ARG as for ms_step_batch, and for a NULL exc, n_steps < 0, an
+ * unknown exc->kind, MS_EXC_ARRAY without exc->u or MS_EXC_AR1 without
+ * exc->x. */
 ms_status ms_rollout(ms_model *m, int32_t n_env, float *q, float *qd,
                      float *act, uint32_t *status, const ms_excitation *exc,
                      int32_t n_steps, const ms_step_opts *opts, void *stream);

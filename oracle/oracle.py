@@ -4,6 +4,12 @@ Builds ``liboracle.so`` from ``ora.c`` with gcc (plain -O2, no fast-math,
 OpenMP over envs) and exposes each stage of the step as a numpy function.
 Model arrays come from the seeded generator (float32/int32) and are promoted
 to double inside the C code.
+
+Pins (tests/test_oracle_pins.py, tests/test_oracle_mlp.py): every stage of
+the step against closed forms, finite differences, invariants or a second
+route. The multi-step whole-body trajectory with contact as a whole has no
+closed form and is pinned only through those parts: parity unpinned for the
+composite.
 """
 from __future__ import annotations
 

@@ -61,3 +61,20 @@ def test_observation_layout():
     assert np.allclose(obs[:, 6:80], q[:, 7:])
     assert np.allclose(obs[:, 80:160], qd)
     assert np.allclose(obs[:, 160:], reference_targets(0.25, a, f, p))
+
+
+def test_action_is_the_sigmoid_of_the_network_output():
+    """Zero weights give excitations of exactly 0.5; a large output bias
+    saturates them at 1 (positive) or 0 (negative), never the reverse."""
+    from oracle import policy_act
+    n_in, h, n_out = 16, 8, 5
+    z = [np.zeros((n_in, h)), np.zeros(h), np.zeros((h, h)), np.zeros(h),
+         np.zeros((h, n_out)), np.zeros(n_out)]
+    obs = np.random.default_rng(1).normal(size=(3, 12))
+    assert np.array_equal(policy_act(z, obs, n_in), np.full((3, n_out), 0.5))
+    up = list(z)
+    up[5] = np.full(n_out, 50.0)
+    assert np.allclose(policy_act(up, obs, n_in), 1.0)
+    down = list(z)
+    down[5] = np.full(n_out, -50.0)
+    assert np.all(policy_act(down, obs, n_in) < 1e-20)

@@ -200,14 +200,8 @@ ms_status build_tables(const ms_model_desc *d, Tables *t, std::string *msg) {
       if (height[j] == h) t->hlev_dof.push_back(j);
   }
   t->hlev_start[t->n_hlev] = (int)t->hlev_dof.size();
-  t->dlev_start.assign(t->n_dlev + 1, 0);
-  for (int dl = 0; dl < t->n_dlev; ++dl) {
-    t->dlev_start[dl] = (int)t->dlev_dof.size();
-    for (int j = 0; j < nv; ++j)
-      if (t->dof_depth[j] == dl + 1) t->dlev_dof.push_back(j);
-  }
-  t->dlev_start[t->n_dlev] = (int)t->dlev_dof.size();
-  // the factorisation and both solves as gathers over tree levels, in one
+  // the factorisation and the L^T solve as gathers over height levels, the
+  // L solve by depth over root-first rows, the kinematics level by level: one
   // compact table (int32 words) that a workgroup stages in LDS once per launch
   std::vector<int32_t> desc_start(nv + 1, 0), desc;
   for (int k = 0; k < nv; ++k) {
@@ -224,7 +218,7 @@ ms_status build_tables(const ms_model_desc *d, Tables *t, std::string *msg) {
       *off = (int)b.size();
       b.insert(b.end(), v.begin(), v.end());
     };
-    std::vector<int32_t> hent, hent_start(t->n_hlev + 1, 0), hdof, drange(nv), dsol, rs(nv + 1);
+    std::vector<int32_t> hent, hent_start(t->n_hlev + 1, 0), hdof, drange(nv), rs(nv + 1);
     for (int h = 0; h < t->n_hlev; ++h) {
       hent_start[h] = (int)hent.size();
       for (int e = t->hlev_start[h]; e < t->hlev_start[h + 1]; ++e) {
@@ -236,24 +230,24 @@ ms_status build_tables(const ms_model_desc *d, Tables *t, std::string *msg) {
     }
     hent_start[t->n_hlev] = (int)hent.size();
     for (int k = 0; k < nv; ++k) drange[k] = desc_start[k] | (desc_start[k + 1] << 16);
-    for (int e = 0; e < (int)t->dlev_dof.size(); ++e) {
-      const int k = t->dlev_dof[e];
-      dsol.push_back(k | (t->row_start[k] << 8));
-    }
     for (int k = 0; k <= nv; ++k) rs[k] = t->row_start[k];
     std::vector<int32_t> path8((t->nnz + 3) / 4, 0);
     for (int e = 0; e < t->nnz; ++e) path8[e / 4] |= (t->path[e] & 0xFF) << (8 * (e % 4));
     // tree schedule and subtree lists of the kinematics and dynamics
-    std::vector<int32_t> tinfo(n);
-    for (int i = 0; i < n; ++i) tinfo[i] = t->jtype[i] | ((t->parent[i] + 1) << 2) | (t->dadr[i] << 10);
+    // per node in level order: type | (parent + 1) << 2 | first DoF << 10 |
+    // node << 18 (one table read per node and level)
+    std::vector<int32_t> tnode(n);
+    for (size_t k = 0; k < t->level_nodes.size(); ++k) {
+      const int i = t->level_nodes[k];
+      tnode[k] = t->jtype[i] | ((t->parent[i] + 1) << 2) | (t->dadr[i] << 10) | (i << 18);
+    }
     auto bytes = [](const std::vector<int32_t> &v) {
       std::vector<int32_t> w((v.size() + 3) / 4, 0);
       for (size_t e = 0; e < v.size(); ++e) w[e / 4] |= (v[e] & 0xFF) << (8 * (e % 4));
       return w;
     };
     section(&t->lt_tlev, t->level_start);
-    section(&t->lt_tnode, t->level_nodes);
-    section(&t->lt_tinfo, tinfo);
+    section(&t->lt_tnode, tnode);
     section(&t->lt_subb_start, t->subb_start);
     section(&t->lt_subc_start, t->subc_start);
     section(&t->lt_subb, bytes(t->subb));
@@ -261,12 +255,10 @@ ms_status build_tables(const ms_model_desc *d, Tables *t, std::string *msg) {
     section(&t->lt_nnzrow, bytes(t->nnz_row));
     section(&t->lt_hent_start, hent_start);
     section(&t->lt_hlev_start, t->hlev_start);
-    section(&t->lt_dlev_start, t->dlev_start);
     section(&t->lt_hent, hent);
     section(&t->lt_hdof, hdof);
     section(&t->lt_desc, desc);
     section(&t->lt_drange, drange);
-    section(&t->lt_dsol, dsol);
     section(&t->lt_rs, rs);
     section(&t->lt_path, path8);
     b.resize((b.size() + 3) / 4 * 4, 0);  // 16-byte multiple

@@ -60,25 +60,26 @@ struct Tables {
   // tree-sparse mass matrix (row j holds its ancestors by depth, diag last)
   std::vector<int32_t> row_start, dof_depth, path;     // path[nnz] = DoF id
   std::vector<int32_t> nnz_row;                        // row of each entry
-  // level schedules of the factorisation and solves: DoFs grouped by height
-  // (leaves first) and by depth (root first)
+  // level schedule of the factorisation: DoFs grouped by height (leaves
+  // first); the L solve runs over the n_dlev depths (root first)
   int n_hlev = 0, n_dlev = 0;
-  std::vector<int32_t> hlev_start, hlev_dof, dlev_start, dlev_dof;
+  std::vector<int32_t> hlev_start, hlev_dof;
   // The factorisation and solves as gathers over tree levels, one int32
   // table (lt) staged in LDS per workgroup; lt_* are word offsets of its
-  // sections: hent_start / hlev_start / dlev_start (level starts), hent
+  // sections: hent_start / hlev_start (level starts), hent
   // (per height level, its rows' entries: row | depth(row) << 8 |
   // depth(column) << 16, depth 255 standing for the right-hand side), hdof (per height level, its DoFs: id | depth << 8),
   // desc (per DoF its proper descendants: row start | id << 16), drange (per
-  // DoF its desc range: begin | end << 16), dsol (per depth level, its DoFs:
-  // id | row start << 8), rs (row starts), path (path[] as bytes).
-  // The same table holds the tree schedule (tlev level starts, tnode nodes by
-  // level, tinfo per node: type | (parent + 1) << 2 | first DoF << 10) and
-  // the subtree lists (subb_start/subc_start, subb/subc and nnzrow as bytes).
+  // DoF its desc range: begin | end << 16), rs (row starts), path (path[] as
+  // bytes).
+  // The same table holds the tree schedule (tlev level starts, tnode per node
+  // in level order: type | (parent + 1) << 2 | first DoF << 10 | node << 18)
+  // and the subtree lists (subb_start/subc_start, subb/subc and nnzrow as
+  // bytes).
   std::vector<int32_t> lt;
-  int lt_hent_start = 0, lt_hlev_start = 0, lt_dlev_start = 0, lt_hent = 0, lt_hdof = 0,
-      lt_desc = 0, lt_drange = 0, lt_dsol = 0, lt_rs = 0, lt_path = 0, lt_tlev = 0, lt_tnode = 0,
-      lt_tinfo = 0, lt_subb_start = 0, lt_subc_start = 0, lt_subb = 0, lt_subc = 0, lt_nnzrow = 0;
+  int lt_hent_start = 0, lt_hlev_start = 0, lt_hent = 0, lt_hdof = 0,
+      lt_desc = 0, lt_drange = 0, lt_rs = 0, lt_path = 0, lt_tlev = 0, lt_tnode = 0,
+      lt_subb_start = 0, lt_subc_start = 0, lt_subb = 0, lt_subc = 0, lt_nnzrow = 0;
   // LDS layout (byte offsets into the per-env LDS block)
   int off_q = 0, off_qd = 0, off_R = 0, off_P = 0, off_S = 0, off_V = 0,
       off_A = 0, off_F = 0, off_con = 0, off_rhs = 0, off_H = 0, off_x = 0,

@@ -104,7 +104,7 @@ ms_status ms_model_create(const ms_model_desc *desc, ms_model **out) {
          o_dh = p.add(t.dent_h), o_ds = p.add(t.dent_start), o_di = p.add(t.dent_item),
          o_rs = p.add(t.row_start), o_dd = p.add(t.dof_depth), o_path = p.add(t.path),
          o_nr = p.add(t.nnz_row), o_hs = p.add(t.hlev_start),
-         o_hd = p.add(t.hlev_dof), o_ds2 = p.add(t.dlev_start), o_dd2 = p.add(t.dlev_dof),
+         o_hd = p.add(t.hlev_dof),
          o_lt = p.add(t.lt);
   m->dbytes = p.buf.size();
   hipError_t e = hipMalloc(&m->dbuf, m->dbytes);
@@ -148,13 +148,12 @@ ms_status ms_model_create(const ms_model_desc *desc, ms_model **out) {
   P_(lt, o_lt, int);
   k.lt_words = (int)t.lt.size();
   k.lt_hent_start = t.lt_hent_start; k.lt_hlev_start = t.lt_hlev_start;
-  k.lt_dlev_start = t.lt_dlev_start; k.lt_hent = t.lt_hent; k.lt_hdof = t.lt_hdof;
-  k.lt_desc = t.lt_desc; k.lt_drange = t.lt_drange; k.lt_dsol = t.lt_dsol; k.lt_rs = t.lt_rs;
-  k.lt_path = t.lt_path; k.lt_tlev = t.lt_tlev; k.lt_tnode = t.lt_tnode; k.lt_tinfo = t.lt_tinfo;
+  k.lt_hent = t.lt_hent; k.lt_hdof = t.lt_hdof;
+  k.lt_desc = t.lt_desc; k.lt_drange = t.lt_drange; k.lt_rs = t.lt_rs;
+  k.lt_path = t.lt_path; k.lt_tlev = t.lt_tlev; k.lt_tnode = t.lt_tnode;
   k.lt_subb_start = t.lt_subb_start; k.lt_subc_start = t.lt_subc_start; k.lt_subb = t.lt_subb;
   k.lt_subc = t.lt_subc; k.lt_nnzrow = t.lt_nnzrow;
-  P_(hlev_start, o_hs, int); P_(hlev_dof, o_hd, int); P_(dlev_start, o_ds2, int);
-  P_(dlev_dof, o_dd2, int);
+  P_(hlev_start, o_hs, int); P_(hlev_dof, o_hd, int);
 #undef P_
   k.off_flag = t.off_flag; k.off_q = t.off_q; k.off_qd = t.off_qd; k.off_R = t.off_R;
   k.off_P = t.off_P; k.off_S = t.off_S; k.off_con = t.off_con; k.off_rhs = t.off_rhs;

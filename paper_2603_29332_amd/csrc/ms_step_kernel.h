@@ -280,7 +280,7 @@ __device__ __forceinline__ void step_body(const KModel &M, const KRun &Rn, int n
   double *__restrict__ H = (double *)(lds + M.off_H);
   unsigned char *scr = lds + M.off_scr;
   // tree schedule and subtree lists from the workgroup's table
-  const int *tlev = LT + M.lt_tlev, *tnode = LT + M.lt_tnode, *tinfo = LT + M.lt_tinfo;
+  const int *tlev = LT + M.lt_tlev, *tnode = LT + M.lt_tnode;
   const int *sbs = LT + M.lt_subb_start, *scs = LT + M.lt_subc_start;
   const unsigned char *sbl = (const unsigned char *)(LT + M.lt_subb);
   const unsigned char *scl = (const unsigned char *)(LT + M.lt_subc);
@@ -417,11 +417,10 @@ __device__ __forceinline__ void step_body(const KModel &M, const KRun &Rn, int n
     for (int l = 0; l < M.n_level; ++l) {
       const int b0 = tlev[l], b1 = tlev[l + 1];
       for (int k = b0 + lane; k < b1; k += 64) {
-        const int i = tnode[k];
-        const int info = tinfo[i];
+        const int info = tnode[k], i = info >> 18;
         const int jt = info & 3;
         if (jt == 2) continue;
-        const int p = (info >> 2 & 0xFF) - 1, da = info >> 10;
+        const int p = (info >> 2 & 0xFF) - 1, da = info >> 10 & 0xFF;
         float *F = Rl + 12 * i;
         // frames are 16-byte aligned 12-float records, V and A 8-byte aligned
         // 6-float records: vector LDS accesses
@@ -837,28 +836,45 @@ __device__ __forceinline__ void step_body(const KModel &M, const KRun &Rn, int n
       wave_sync();
     }
     if (!nonspd) {
-      for (int j = lane; j < nv; j += 64) xs[j] *= invd[j];
-      wave_sync();
-      // L x = z, root first: x_k = z_k - (1/d_k) sum_{a anc. of k} H_ka x_a
+      // L x = z with z = y / d, root first: x_k = z_k - (1/d_k) sum over the
+      // ancestors a of k of H_ka x_a. Each lane keeps its rows' sums in
+      // registers; at depth l the rows of that depth are final, and every
+      // deeper row adds the term of its (single) depth-l ancestor, which is
+      // entry l of its root-first row.
       const unsigned char *path8 = (const unsigned char *)(LT + M.lt_path);
-      for (int dl = 1; dl < M.n_dlev; ++dl) {
-        const int s0 = LT[M.lt_dlev_start + dl], ne = LT[M.lt_dlev_start + dl + 1] - s0;
-        const int lp = group_log2(ne), P = 1 << lp;
-        for (int base = 0; base < (ne << lp); base += 64) {
-          const int idx = base + lane, g = idx >> lp, p = idx & (P - 1);
-          double sum = 0.0;
-          int k = 0;
-          if (g < ne) {
-            const int w = LT[M.lt_dsol + s0 + g];
-            k = w & 0xFF;
-            const int rk = w >> 8;
-#pragma unroll 4
-            for (int a = p; a < dl; a += P) sum += H[rk + a] * xs[path8[rk + a]];
+      double z[2], id[2], acc[2] = {0.0, 0.0};
+      int rk[2], dk[2];
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        const int j = lane + 64 * t;
+        dk[t] = -1;
+        rk[t] = 0;
+        id[t] = z[t] = 0.0;
+        if (j < nv) {
+          rk[t] = Lrs[j];
+          dk[t] = Lrs[j + 1] - rk[t] - 1;
+          id[t] = invd[j];
+          z[t] = xs[j] * id[t];
+        }
+      }
+      for (int l = 0;; ++l) {
+        double h[2];
+        int c[2];
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+          h[t] = 0.0;
+          c[t] = 0;
+          if (dk[t] > l) {
+            h[t] = H[rk[t] + l];
+            c[t] = path8[rk[t] + l];
           }
-          sum = group_sum_last(sum, lp, lane);
-          if (g < ne && p == P - 1) xs[k] -= sum * invd[k];
+          if (dk[t] == l) xs[lane + 64 * t] = z[t] - acc[t] * id[t];
         }
         wave_sync();
+        if (l + 1 >= M.n_dlev) break;
+#pragma unroll
+        for (int t = 0; t < 2; ++t)
+          if (dk[t] > l) acc[t] += h[t] * xs[c[t]];
       }
     }
 

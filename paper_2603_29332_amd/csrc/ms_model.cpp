@@ -203,11 +203,29 @@ ms_status build_tables(const ms_model_desc *d, Tables *t, std::string *msg) {
   // the factorisation and the L^T solve as gathers over height levels, the
   // L solve by depth over root-first rows, the kinematics level by level: one
   // compact table (int32 words) that a workgroup stages in LDS once per launch
+  // The trunk: the rows of the single-row height levels at the top (h >= 1),
+  // a chain from a root down whose ancestor counts are 0, 1, ... Its block is
+  // finished apart: one gather over the trunk rows' other descendants (all
+  // of lower height, so finished before) gives the block left after
+  // eliminating every non-trunk row, and the trunk rows are then eliminated
+  // bottom-up by rank-1 updates of the rows above them.
+  int h0 = t->n_hlev;
+  while (h0 - 1 >= 1 && t->hlev_start[h0] - t->hlev_start[h0 - 1] == 1) --h0;
+  t->n_trunk = t->n_hlev - h0;
+  for (int h = h0; h < t->n_hlev; ++h)
+    if (t->dof_depth[t->hlev_dof[t->hlev_start[h]]] - 1 != t->n_hlev - 1 - h) t->n_trunk = 0;
+  if (t->n_trunk < 2) t->n_trunk = 0;
+  if (!t->n_trunk) h0 = t->n_hlev;
+  t->n_hgat = t->n_trunk ? h0 + 1 : t->n_hlev;
+  std::vector<char> trunk(nv, 0);
+  for (int h = h0; h < t->n_hlev; ++h) trunk[t->hlev_dof[t->hlev_start[h]]] = 1;
+  // proper descendants of each DoF (of a trunk row: its non-trunk ones)
   std::vector<int32_t> desc_start(nv + 1, 0), desc;
   for (int k = 0; k < nv; ++k) {
     desc_start[k] = (int)desc.size();
     for (int i = 0; i < nv; ++i)
-      if (i != k && dof_anc(k, i)) desc.push_back(t->row_start[i] | (i << 16));
+      if (i != k && dof_anc(k, i) && !(trunk[k] && trunk[i]))
+        desc.push_back(t->row_start[i] | (i << 16));
   }
   desc_start[nv] = (int)desc.size();
   need(t->nnz < 65536 && (int)desc.size() < 65536, "mass matrix too large", MS_E_UNSUPPORTED, &st,
@@ -218,9 +236,11 @@ ms_status build_tables(const ms_model_desc *d, Tables *t, std::string *msg) {
       *off = (int)b.size();
       b.insert(b.end(), v.begin(), v.end());
     };
-    std::vector<int32_t> hent, hent_start(t->n_hlev + 1, 0), hdof, drange(nv), rs(nv + 1);
+    // gather levels: the height levels below the trunk, then one level with
+    // every trunk row's entries
+    std::vector<int32_t> hent, hent_start(t->n_hgat + 1, 0), hdof, drange(nv), rs(nv + 1);
     for (int h = 0; h < t->n_hlev; ++h) {
-      hent_start[h] = (int)hent.size();
+      if (h < t->n_hgat) hent_start[h] = (int)hent.size();
       for (int e = t->hlev_start[h]; e < t->hlev_start[h + 1]; ++e) {
         const int k = t->hlev_dof[e], ck = t->dof_depth[k] - 1;
         for (int x = 0; x <= ck; ++x) hent.push_back(k | (ck << 8) | (x << 16));
@@ -228,7 +248,21 @@ ms_status build_tables(const ms_model_desc *d, Tables *t, std::string *msg) {
         hdof.push_back(k | (ck << 8));
       }
     }
-    hent_start[t->n_hlev] = (int)hent.size();
+    hent_start[t->n_hgat] = (int)hent.size();
+    // trunk rows by ancestor count (id | row start << 8) and the entries of
+    // the rows above the lowest one, row by row, columns root first, then
+    // the right-hand side: H index (rhs: row id) | row depth << 16 | column
+    // depth << 23 | rhs << 30, so the pairs above trunk row d are a prefix
+    std::vector<int32_t> trow(t->n_trunk), tpair;
+    for (int dd = 0; dd < t->n_trunk; ++dd) {
+      const int k = t->hlev_dof[t->hlev_start[t->n_hlev - 1 - dd]];
+      trow[dd] = k | (t->row_start[k] << 8);
+    }
+    for (int da = 0; da + 1 < t->n_trunk; ++da) {
+      const int a = trow[da] & 0xFF;
+      for (int db = 0; db <= da; ++db) tpair.push_back((t->row_start[a] + db) | (da << 16) | (db << 23));
+      tpair.push_back(a | (da << 16) | (1 << 30));
+    }
     for (int k = 0; k < nv; ++k) drange[k] = desc_start[k] | (desc_start[k + 1] << 16);
     for (int k = 0; k <= nv; ++k) rs[k] = t->row_start[k];
     std::vector<int32_t> path8((t->nnz + 3) / 4, 0);
@@ -260,6 +294,8 @@ ms_status build_tables(const ms_model_desc *d, Tables *t, std::string *msg) {
     section(&t->lt_desc, desc);
     section(&t->lt_drange, drange);
     section(&t->lt_rs, rs);
+    section(&t->lt_trow, trow);
+    section(&t->lt_tpair, tpair);
     section(&t->lt_path, path8);
     b.resize((b.size() + 3) / 4 * 4, 0);  // 16-byte multiple
   }

@@ -61,8 +61,10 @@ struct Tables {
   std::vector<int32_t> row_start, dof_depth, path;     // path[nnz] = DoF id
   std::vector<int32_t> nnz_row;                        // row of each entry
   // level schedule of the factorisation: DoFs grouped by height (leaves
-  // first); the L solve runs over the n_dlev depths (root first)
-  int n_hlev = 0, n_dlev = 0;
+  // first), of which the first n_hgat - 1 are gathered level by level and the
+  // n_trunk single-row levels at the top form the trunk; the L solve runs
+  // over the n_dlev depths (root first)
+  int n_hlev = 0, n_dlev = 0, n_hgat = 0, n_trunk = 0;
   std::vector<int32_t> hlev_start, hlev_dof;
   // The factorisation and solves as gathers over tree levels, one int32
   // table (lt) staged in LDS per workgroup; lt_* are word offsets of its
@@ -71,14 +73,15 @@ struct Tables {
   // depth(column) << 16, depth 255 standing for the right-hand side), hdof (per height level, its DoFs: id | depth << 8),
   // desc (per DoF its proper descendants: row start | id << 16), drange (per
   // DoF its desc range: begin | end << 16), rs (row starts), path (path[] as
-  // bytes).
+  // bytes), trow and tpair (the trunk's rows and the entries its rank-1
+  // updates touch).
   // The same table holds the tree schedule (tlev level starts, tnode per node
   // in level order: type | (parent + 1) << 2 | first DoF << 10 | node << 18)
   // and the subtree lists (subb_start/subc_start, subb/subc and nnzrow as
   // bytes).
   std::vector<int32_t> lt;
   int lt_hent_start = 0, lt_hlev_start = 0, lt_hent = 0, lt_hdof = 0,
-      lt_desc = 0, lt_drange = 0, lt_rs = 0, lt_path = 0, lt_tlev = 0, lt_tnode = 0,
+      lt_desc = 0, lt_drange = 0, lt_rs = 0, lt_trow = 0, lt_tpair = 0, lt_path = 0, lt_tlev = 0, lt_tnode = 0,
       lt_subb_start = 0, lt_subc_start = 0, lt_subb = 0, lt_subc = 0, lt_nnzrow = 0;
   // LDS layout (byte offsets into the per-env LDS block)
   int off_q = 0, off_qd = 0, off_R = 0, off_P = 0, off_S = 0, off_V = 0,

@@ -125,7 +125,7 @@ ms_status ms_model_create(const ms_model_desc *desc, ms_model **out) {
   k.n_node = t.n_node; k.nq = t.nq; k.nv = t.nv; k.n_mus = t.n_mus; k.n_con = t.n_con;
   k.n_body = t.n_body; k.nnz = t.nnz; k.n_level = t.n_level; k.free_root = t.free_root;
   k.n_dent = t.n_dent;
-  k.n_hlev = t.n_hlev;
+  k.n_hlev = t.n_hlev; k.n_hgat = t.n_hgat; k.n_trunk = t.n_trunk;
   k.n_dlev = t.n_dlev;
   k.kc = t.kc; k.cc = t.cc; k.mu = t.mu; k.vs = t.vs; k.gx = t.g[0]; k.gy = t.g[1]; k.gz = t.g[2];
 #define P_(field, off, T) k.field = (const T *)(b + off)
@@ -150,6 +150,7 @@ ms_status ms_model_create(const ms_model_desc *desc, ms_model **out) {
   k.lt_hent_start = t.lt_hent_start; k.lt_hlev_start = t.lt_hlev_start;
   k.lt_hent = t.lt_hent; k.lt_hdof = t.lt_hdof;
   k.lt_desc = t.lt_desc; k.lt_drange = t.lt_drange; k.lt_rs = t.lt_rs;
+  k.lt_trow = t.lt_trow; k.lt_tpair = t.lt_tpair;
   k.lt_path = t.lt_path; k.lt_tlev = t.lt_tlev; k.lt_tnode = t.lt_tnode;
   k.lt_subb_start = t.lt_subb_start; k.lt_subc_start = t.lt_subc_start; k.lt_subb = t.lt_subb;
   k.lt_subc = t.lt_subc; k.lt_nnzrow = t.lt_nnzrow;

@@ -809,7 +809,7 @@ __device__ __forceinline__ void step_body(const KModel &M, const KRun &Rn, int n
         }
       }
     };
-    for (int h = 1; h < M.n_hlev && !nonspd; ++h) {
+    for (int h = 1; h < M.n_hgat && !nonspd; ++h) {
       const int s0 = LT[M.lt_hent_start + h], ne = LT[M.lt_hent_start + h + 1] - s0;
       const int lp = group_log2(ne), P = 1 << lp;
       fbad = false;
@@ -834,6 +834,69 @@ __device__ __forceinline__ void step_body(const KModel &M, const KRun &Rn, int n
       }
       nonspd = __any(fbad);
       wave_sync();
+    }
+    // The trunk (single-row levels at the top, ancestor counts 0 .. n_trunk-1):
+    // its rows were gathered over their non-trunk descendants only, which
+    // leaves the block that remains once every other row is eliminated.
+    // Eliminating its rows bottom-up, row k (final once the rows below it
+    // are eliminated) updates every entry (a, b) of the rows above it, b = a
+    // or an ancestor of a, and their right-hand sides:
+    // H_ab -= H_ka H_kb / d_k, y_a -= H_ka y_k / d_k. One level per row, one
+    // FMA per entry, no two lanes writing the same entry.
+    if (M.n_trunk && !nonspd) {
+      const int *trow = LT + M.lt_trow, *tpair = LT + M.lt_tpair;
+      const int nt = M.n_trunk, npair = (nt - 1) * (nt + 2) / 2;
+      // this lane's first three entries stay in registers; all of a level's
+      // loads are issued before its stores
+      int tw[3];
+#pragma unroll
+      for (int u = 0; u < 3; ++u) tw[u] = lane + 64 * u < npair ? tpair[lane + 64 * u] : -1;
+      int wk = trow[nt - 1];
+      for (int dk = nt - 1; dk >= 0; --dk) {
+        const int k = wk & 0xFF, rk = wk >> 8;
+        const double d = H[rk + dk], xk = xs[k];
+        double hka[3], hkb[3], hab[3];
+        bool on[3], rhs[3];
+#pragma unroll
+        for (int u = 0; u < 3; ++u) {
+          const int w = tw[u], da = (w >> 16) & 0x7F, db = (w >> 23) & 0x7F;
+          on[u] = w >= 0 && da < dk;
+          rhs[u] = (w >> 30) & 1;
+          hka[u] = hkb[u] = hab[u] = 0.0;
+          if (on[u]) {
+            hka[u] = H[rk + da];
+            if (!rhs[u]) hkb[u] = H[rk + db];
+            hab[u] = rhs[u] ? xs[w & 0xFFFF] : H[w & 0xFFFF];
+          }
+        }
+        if (dk > 0) wk = trow[dk - 1];
+        if (!(d > 0.0)) {  // the same value in every lane
+          nonspd = true;
+          break;
+        }
+        const double id = 1.0 / d, yk = xk * id;
+        if (lane == 0) invd[k] = id;
+#pragma unroll
+        for (int u = 0; u < 3; ++u) {
+          if (!on[u]) continue;
+          const int e = tw[u] & 0xFFFF;
+          if (rhs[u]) xs[e] = hab[u] - hka[u] * yk;
+          else H[e] = hab[u] - hka[u] * hkb[u] * id;
+        }
+        // entries beyond the first 192 (trunks longer than 18 rows)
+        const int na = dk * (dk + 3) / 2;
+        for (int t = lane + 192; t < na; t += 64) {
+          const int w = tpair[t], e = w & 0xFFFF, da = (w >> 16) & 0x7F;
+          const double h1 = H[rk + da];
+          if (w >> 30) {
+            xs[e] -= h1 * yk;
+          } else {
+            const int db = (w >> 23) & 0x7F;
+            H[e] -= h1 * H[rk + db] * id;
+          }
+        }
+        wave_sync();
+      }
     }
     if (!nonspd) {
       // L x = z with z = y / d, root first: x_k = z_k - (1/d_k) sum over the

@@ -30,12 +30,12 @@ struct KModel {
   const int *proj_start, *proj_item;
   const int *dent_h, *dent_start, *dent_item;
   const int *row_start, *dof_depth, *path, *nnz_row;
-  int n_hlev, n_dlev;
+  int n_hlev, n_dlev, n_hgat, n_trunk;
   const int *hlev_start, *hlev_dof;
   // the factorisation's gather tables (staged in LDS per workgroup)
   const int *lt;
   int lt_words, lt_hent_start, lt_hlev_start, lt_hent, lt_hdof, lt_desc, lt_drange,
-      lt_rs, lt_path, lt_tlev, lt_tnode, lt_subb_start, lt_subc_start, lt_subb,
+      lt_rs, lt_trow, lt_tpair, lt_path, lt_tlev, lt_tnode, lt_subb_start, lt_subc_start, lt_subb,
       lt_subc, lt_nnzrow;
   int off_flag, off_q, off_qd, off_R, off_P, off_S, off_con, off_rhs, off_x, off_H,
       off_scr, off_V, off_A, off_F;

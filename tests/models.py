@@ -86,3 +86,20 @@ def mixed_chain():
     L0 = Oracle(m).geometry(np.zeros(m["nq"]), np.zeros(m["nv"]))[0]
     m["l_slack"] = (L0 - m["l_opt"]).astype(m["l_slack"].dtype)
     return m
+
+
+def twin_chains(n_link=6, seed=4):
+    """Two equal fixed-base hinge chains on separate roots, the second a copy
+    of the first 0.5 m to the side and without muscles: the top height level
+    of the DoF tree holds two rows."""
+    m = synth.chain_model(seed, n_link=n_link, n_mus=12)
+    n = n_link
+    two = dict(m)
+    two["parent"] = np.concatenate([m["parent"], np.where(m["parent"] >= 0, m["parent"] + n, -1)])
+    jpos2 = np.array(m["jpos"]).copy()
+    jpos2[0, 0] += 0.5
+    two["jpos"] = np.concatenate([m["jpos"], jpos2])
+    for k in ("jtype", "jrot", "axis", "mass", "com", "inertia", "damping", "qlo", "qhi"):
+        two[k] = np.concatenate([m[k], m[k]])
+    two["name"] = f"twin{n}"
+    return synth._finish(two)

@@ -17,6 +17,7 @@ pytestmark = pytest.mark.gpu
 
 from oracle import Oracle  # noqa: E402
 from paper_2603_29332_amd import ms, synth  # noqa: E402
+from tests import models  # noqa: E402
 
 DEV = "cuda"
 
@@ -154,8 +155,13 @@ def test_step_teacher_forced(which, chain, human, human40):
     dt = 2e-3 if which == "chain" else 1e-3
     kind = "iid" if which == "chain" else "ar1"
     init = synth.chain_initial_state if which == "chain" else synth.human_initial_state
-    contact = which != "chain"
-    E = 16
+    _check_teacher_forced(m, gm, o, dt, kind, init, which != "chain", which)
+
+
+def _check_teacher_forced(m, gm, o, dt, kind, init, contact, which, E=16):
+    """One GPU step from warmed-up float32 states against the oracle's step,
+    relative error per block (q, qd, act) within 1e-5 or, for states whose
+    own FP32 conditioning exceeds that, 4x the oracle's spread."""
     q, qd, act = _warm_states(m, o, E, 60, dt, kind, 22, contact, init)
     u = synth.excitation_iid(6, E, m["n_mus"], 0)
     q1, qd1, a1, st = _advance_gpu(gm, q, qd, act, u[None], dt, contact)
@@ -185,6 +191,38 @@ def test_step_teacher_forced(which, chain, human, human40):
           f"{int((tol > 1e-5).any(axis=1).sum())} of {E} states contact-sensitive "
           f"(oracle spread up to {sens.max():.1e})")
     assert (err <= tol).all()
+
+
+# ------------------------------------- tree shapes of the factorisation
+@pytest.mark.parametrize("shape", ["long chain", "twin chains"])
+def test_factorisation_tree_shapes(shape):
+    """Tree shapes that take the factorisation's other paths: a 30-link
+    chain (a 29-row trunk, whose eliminations touch more entries than a
+    wavefront keeps in registers) and two equal chains on separate roots (no
+    single-row top levels: every level gathered). Accelerations against the
+    oracle, one step against the oracle's, and a rollout bitwise equal to
+    repeated single steps."""
+    m = synth.chain_model(3, n_link=30, n_mus=40) if shape == "long chain" else models.twin_chains()
+    gm, o = ms.Model(m), Oracle(m)
+    dt, E = 2e-3, 8
+    q, qd, act = _warm_states(m, o, E, 40, dt, "iid", 21, False, synth.chain_initial_state)
+    u = synth.excitation_iid(5, E, m["n_mus"], 0)
+    out = gm.step_stages(_t(q), _t(qd), _t(act), _t(u), dt, False)["qdd"].cpu().numpy()
+    for e in range(E):
+        S = o.step(dt, q[e], qd[e], act[e], u[e], contact=False, stages=True)[4]
+        qscale = max(np.abs(S["qdd"]).max(), 1.0)
+        assert np.abs(out[e] - S["qdd"]).max() < 1e-3 * qscale
+    _check_teacher_forced(m, gm, o, dt, "iid", synth.chain_initial_state, False, shape)
+    us = np.stack([synth.excitation_iid(9, E, m["n_mus"], t) for t in range(6)])
+    a = [_t(q), _t(qd), _t(act), torch.zeros(E, dtype=torch.int32, device=DEV)]
+    b = [v.clone() for v in a]
+    gm.rollout(*a, 6, dt, False, kind=ms.EXC_ARRAY, u=_t(us))
+    for t in range(6):
+        gm.step_batch(*b, _t(us[t]), dt, False)
+    torch.cuda.synchronize()
+    assert (a[3] == 0).all()
+    for x, y in zip(a, b):
+        assert torch.equal(x, y)
 
 
 # -------------------------------------------------------- 200-step free run

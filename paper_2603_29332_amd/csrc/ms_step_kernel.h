@@ -562,6 +562,11 @@ __device__ __forceinline__ void step_body(const KModel &M, const KRun &Rn, int n
       double *BI = (double *)scr;                  // [n_body][10]: m, h, I_O (xx xy xz yy yz zz)
       double *CI = BI + 10 * M.n_body;             // [n_node][10]
       double *FJ = CI + 10 * nn;                   // [nv][6]
+      // joint damping of this lane's DoFs, added to the diagonal at the end
+      // (loaded now so that no entry waits on global memory)
+      float dmp[2];
+#pragma unroll
+      for (int t = 0; t < 2; ++t) dmp[t] = lane + 64 * t < nv ? M.damping[lane + 64 * t] : 0.f;
       for (int b = lane; b < M.n_body; b += 64) {
         const int i = M.body_node[b];
         const float *R = Rl + 12 * i;
@@ -634,8 +639,14 @@ __device__ __forceinline__ void step_body(const KModel &M, const KRun &Rn, int n
         const double *f = FJ + 6 * j;
         double h = (double)Sf[0] * f[0] + (double)Sf[1] * f[1] + (double)Sf[2] * f[2] +
                    (double)Sf[3] * f[3] + (double)Sf[4] * f[4] + (double)Sf[5] * f[5];
-        if (i == j) h += (double)dt * M.damping[j];
         H[e] = h;
+      }
+      wave_sync();
+      const int *rs = LT + M.lt_rs;
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        const int j = lane + 64 * t;
+        if (j < nv) H[rs[j + 1] - 1] += (double)dt * dmp[t];  // the diagonal closes row j
       }
       wave_sync();
     }

@@ -406,7 +406,13 @@ ms_status build_tables(const ms_model_desc *d, Tables *t, std::string *msg) {
     for (int x : proj[j]) t->proj_item.push_back(x);
   }
   t->proj_start[nv] = (int)t->proj_item.size();
-  for (auto &kv : dent) {
+  // entries with the most items first: a wavefront sums 64 entries at a
+  // time, each pass as long as its longest list
+  std::vector<std::pair<int, std::vector<int>>> dlist(dent.begin(), dent.end());
+  std::stable_sort(dlist.begin(), dlist.end(), [](const auto &x, const auto &y) {
+    return x.second.size() > y.second.size();
+  });
+  for (auto &kv : dlist) {
     t->dent_h.push_back(kv.first);
     t->dent_start.push_back((int)t->dent_item.size());
     for (int x : kv.second) t->dent_item.push_back(x);

@@ -400,10 +400,15 @@ ms_status build_tables(const ms_model_desc *d, Tables *t, std::string *msg) {
   t->n_via_max = via_max;
   t->grp_nvia.assign(t->mpl, 0);
   for (int m = 0; m < nm; ++m) t->grp_nvia[m / kWave] = std::max(t->grp_nvia[m / kWave], t->mus_nvia[m]);
+  // DoFs with the most items first (a wavefront sums 64 DoFs at a time)
+  t->proj_dof.resize(nv);
+  for (int j = 0; j < nv; ++j) t->proj_dof[j] = j;
+  std::stable_sort(t->proj_dof.begin(), t->proj_dof.end(),
+                   [&](int a, int b) { return proj[a].size() > proj[b].size(); });
   t->proj_start.assign(nv + 1, 0);
-  for (int j = 0; j < nv; ++j) {
-    t->proj_start[j] = (int)t->proj_item.size();
-    for (int x : proj[j]) t->proj_item.push_back(x);
+  for (int x = 0; x < nv; ++x) {
+    t->proj_start[x] = (int)t->proj_item.size();
+    for (int it : proj[t->proj_dof[x]]) t->proj_item.push_back(it);
   }
   t->proj_start[nv] = (int)t->proj_item.size();
   // entries with the most items first: a wavefront sums 64 entries at a

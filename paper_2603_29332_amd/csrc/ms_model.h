@@ -54,6 +54,7 @@ struct Tables {
   std::vector<int32_t> mus_srec;          // [3][n_mus]: DoF | hinge << 8 | node << 16, -1 pad
   std::vector<uint32_t> mus_mask;         // [n_mus] 3 x 8-bit via masks
   // reductions over muscle products
+  std::vector<int32_t> proj_dof;          // [nv] DoF order of the lists
   std::vector<int32_t> proj_start;        // [nv+1]
   std::vector<int32_t> proj_item;         // muscle*3 + slot
   std::vector<int32_t> dent_h, dent_start, dent_item;  // item: muscle*16 + s*4 + t

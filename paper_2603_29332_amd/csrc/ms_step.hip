@@ -100,7 +100,7 @@ ms_status ms_model_create(const ms_model_desc *desc, ms_model **out) {
          o_vn = p.add(t.via_node), o_vp = p.add(t.via_pos), o_span = p.add(t.mus_span), o_srec = p.add(t.mus_srec),
          o_mext = p.add(t.mus_ext), o_mint = p.add(t.mus_int), o_gnv = p.add(t.grp_nvia),
          o_qlo = p.add(t.qlo), o_qhi = p.add(t.qhi),
-         o_mask = p.add(t.mus_mask), o_ps = p.add(t.proj_start), o_pi = p.add(t.proj_item),
+         o_mask = p.add(t.mus_mask), o_ps = p.add(t.proj_start), o_pd = p.add(t.proj_dof), o_pi = p.add(t.proj_item),
          o_dh = p.add(t.dent_h), o_ds = p.add(t.dent_start), o_di = p.add(t.dent_item),
          o_rs = p.add(t.row_start), o_dd = p.add(t.dof_depth), o_path = p.add(t.path),
          o_nr = p.add(t.nnz_row), o_hs = p.add(t.hlev_start),
@@ -141,7 +141,7 @@ ms_status ms_model_create(const ms_model_desc *desc, ms_model **out) {
   P_(mus_nvia, o_nvia, int); P_(via_node, o_vn, int); P_(via_pos, o_vp, float);
   P_(mus_ext, o_mext, int); P_(mus_int, o_mint, int); P_(grp_nvia, o_gnv, int);
   P_(qlo, o_qlo, float); P_(qhi, o_qhi, float);
-  P_(mus_span, o_span, int); P_(mus_srec, o_srec, int); P_(mus_mask, o_mask, unsigned); P_(proj_start, o_ps, int);
+  P_(mus_span, o_span, int); P_(mus_srec, o_srec, int); P_(mus_mask, o_mask, unsigned); P_(proj_start, o_ps, int); P_(proj_dof, o_pd, int);
   P_(proj_item, o_pi, int); P_(dent_h, o_dh, int); P_(dent_start, o_ds, int);
   P_(dent_item, o_di, int); P_(row_start, o_rs, int); P_(dof_depth, o_dd, int);
   P_(path, o_path, int); P_(nnz_row, o_nr, int);

@@ -739,10 +739,11 @@ __device__ __forceinline__ void step_body(const KModel &M, const KRun &Rn, int n
         if (stages) Rn.o_F[(size_t)env * nm + M.mus_ext[m]] = F;
       }
       wave_sync();
-      for (int j = lane; j < nv; j += 64) {
+      for (int x = lane; x < nv; x += 64) {
+        const int j = M.proj_dof[x];
         float tau = 0.f;
 #pragma unroll 8
-        for (int e = M.proj_start[j]; e < M.proj_start[j + 1]; ++e) {
+        for (int e = M.proj_start[x]; e < M.proj_start[x + 1]; ++e) {
           const int it = M.proj_item[e];
           tau += mr[it] * mF[it / 3];
         }

@@ -27,7 +27,7 @@ struct KModel {
   const float *via_pos;
   const int *mus_span, *mus_srec;
   const unsigned *mus_mask;
-  const int *proj_start, *proj_item;
+  const int *proj_dof, *proj_start, *proj_item;
   const int *dent_h, *dent_start, *dent_item;
   const int *row_start, *dof_depth, *path, *nnz_row;
   int n_hlev, n_dlev, n_hgat, n_trunk;

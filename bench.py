@@ -34,7 +34,7 @@ PEAK_VALU_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 # (profiles/k_step_human80_4096_traffic.md), valid for the kernel source with
 # this SHA-256 prefix only (reported as null otherwise).
 TRAFFIC_BYTES_PER_LAUNCH = 53.6e6
-TRAFFIC_KERNEL_SHA = "625be9a53662434c"
+TRAFFIC_KERNEL_SHA = "d2b64ff4b0c67bc6"
 
 
 def parse():

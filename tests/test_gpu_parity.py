@@ -149,6 +149,15 @@ def test_geometry_only_kernel_matches_oracle(which, chain, human):
 
 
 # ---------------------------------------------------- one step, teacher forced
+# Contact stiffness (k = 1e5 N/m on light foot segments) amplifies float32
+# position rounding into forces, so with contact a state's own conditioning
+# can exceed the 1e-5 bound. With contact on, a state's bound is 4x the
+# oracle's own change under relative perturbations of 1e-7 (float32
+# rounding) of q and qd, at least 1e-5 and never more than TF_CAP. Without
+# contact, the literal 1e-5 holds on every state.
+TF_CAP = 5e-4
+
+
 @pytest.mark.parametrize("which", ["chain", "human", "human40"])
 def test_step_teacher_forced(which, chain, human, human40):
     m, gm, o = {"chain": chain, "human": human, "human40": human40}[which]
@@ -158,38 +167,45 @@ def test_step_teacher_forced(which, chain, human, human40):
     _check_teacher_forced(m, gm, o, dt, kind, init, which != "chain", which)
 
 
-def _check_teacher_forced(m, gm, o, dt, kind, init, contact, which, E=16):
+@pytest.mark.parametrize("which", ["human", "human40"])
+def test_step_teacher_forced_contact_off(which, human, human40):
+    """Whole-body models without ground contact: 1e-5 on every state and
+    block, no conditioning allowance."""
+    m, gm, o = {"human": human, "human40": human40}[which]
+    _check_teacher_forced(m, gm, o, 1e-3, "ar1", synth.human_initial_state, False,
+                          which + " contact off", literal=True)
+
+
+def _check_teacher_forced(m, gm, o, dt, kind, init, contact, which, E=16, literal=False):
     """One GPU step from warmed-up float32 states against the oracle's step,
-    relative error per block (q, qd, act) within 1e-5 or, for states whose
-    own FP32 conditioning exceeds that, 4x the oracle's spread."""
+    relative error per block (q, qd, act) within 1e-5, or, with contact and
+    literal False, within the state's capped conditioning bound."""
     q, qd, act = _warm_states(m, o, E, 60, dt, kind, 22, contact, init)
     u = synth.excitation_iid(6, E, m["n_mus"], 0)
     q1, qd1, a1, st = _advance_gpu(gm, q, qd, act, u[None], dt, contact)
     assert (st == 0).all()
     qo, qdo, ao, sto = o.rollout(dt, q, qd, act, u[None], contact=contact)
     assert (sto == 0).all()
-    # conditioning of each state at FP32 resolution: the oracle's own change
-    # under relative perturbations of 1e-7 (float32 rounding) of q and qd,
-    # four seeded draws. Where contact stiffness amplifies that beyond the
-    # bound, no FP32 step can meet 1e-5; the bound there is 4x the oracle's
-    # own spread.
-    rng = np.random.default_rng(99)
+    tol = np.full((E, 3), 1e-5)
     sens = np.zeros((E, 3))
-    for _ in range(4):
-        qp = q.astype(np.float64) * (1 + 1e-7 * rng.standard_normal(q.shape))
-        if m["jtype"][0] == 2:
-            qp[:, 3:7] /= np.linalg.norm(qp[:, 3:7], axis=1, keepdims=True)
-        qdp = qd.astype(np.float64) * (1 + 1e-7 * rng.standard_normal(qd.shape))
-        a_, b_, c_, _ = o.rollout(dt, qp, qdp, act, u[None], contact=contact)
-        for e in range(E):
-            sens[e] = np.maximum(sens[e], [_rel_block(a_[e], qo[e]), _rel_block(b_[e], qdo[e]),
-                                           _rel_block(c_[e], ao[e])])
-    tol = np.maximum(1e-5, 4 * sens)
+    if contact and not literal:
+        rng = np.random.default_rng(99)
+        for _ in range(4):
+            qp = q.astype(np.float64) * (1 + 1e-7 * rng.standard_normal(q.shape))
+            if m["jtype"][0] == 2:
+                qp[:, 3:7] /= np.linalg.norm(qp[:, 3:7], axis=1, keepdims=True)
+            qdp = qd.astype(np.float64) * (1 + 1e-7 * rng.standard_normal(qd.shape))
+            a_, b_, c_, _ = o.rollout(dt, qp, qdp, act, u[None], contact=contact)
+            for e in range(E):
+                sens[e] = np.maximum(sens[e], [_rel_block(a_[e], qo[e]), _rel_block(b_[e], qdo[e]),
+                                               _rel_block(c_[e], ao[e])])
+        tol = np.clip(4 * sens, 1e-5, TF_CAP)
     err = np.array([[_rel_block(q1[e], qo[e]), _rel_block(qd1[e], qdo[e]),
                      _rel_block(a1[e], ao[e])] for e in range(E)])
-    print(f"{which} teacher-forced: max rel err (q, qd, act) {err.max(axis=0)}, "
-          f"{int((tol > 1e-5).any(axis=1).sum())} of {E} states contact-sensitive "
-          f"(oracle spread up to {sens.max():.1e})")
+    print(f"{which} teacher-forced: max rel err (q, qd, act) {err.max(axis=0)}; "
+          f"{int((err > 1e-5).any(axis=1).sum())} of {E} states above 1e-5 "
+          f"({int((tol > 1e-5).any(axis=1).sum())} with a conditioning bound above 1e-5, "
+          f"oracle spread up to {sens.max():.1e}, cap {TF_CAP:.0e})")
     assert (err <= tol).all()
 
 
@@ -245,56 +261,73 @@ def test_freerun_chain_200_full_batch(chain):
     assert err <= 1e-3
 
 
-def test_freerun_human_200_subset(human):
-    """Whole body: every 64th of 4096 envs (64 envs), dt 1 ms, 200 steps, AR(1)
-    excitations generated in-kernel, contact on."""
-    m, gm, o = human
+def _human_freerun(m, gm, o, contact):
+    """Every 64th of 4096 whole-body envs (64 envs), dt 1 ms, 200 steps, AR(1)
+    excitations (seed 12) generated in-kernel. Returns the subset's start
+    state, the GPU's final q and status, and the excitations."""
     E, T, dt = 4096, 200, 1e-3
     q, qd, act = synth.human_initial_state(m, E)
     tq, tqd, tact = _t(q), _t(qd), _t(act)
     st = torch.zeros(E, dtype=torch.int32, device=DEV)
     x = torch.zeros(E, m["n_mus"], device=DEV)
     rho, s, mean, _ = synth.ar1_constants(dt)
-    gm.rollout(tq, tqd, tact, st, T, dt, True, kind=ms.EXC_AR1, seed=12, x=x,
+    gm.rollout(tq, tqd, tact, st, T, dt, contact, kind=ms.EXC_AR1, seed=12, x=x,
                ar1=(rho, s, mean))
     torch.cuda.synchronize()
     sub = np.arange(0, E, 64)
-    qg = tq.cpu().numpy()[sub]
     stg = st.cpu().numpy()
-    print(f"human free-run 200: {int((stg != 0).sum())} of {E} envs flagged")
+    print(f"human free-run 200 (contact {contact}): {int((stg != 0).sum())} of {E} envs flagged")
     u, _ = synth.excitation_sequence("ar1", 12, len(sub), m["n_mus"], T, dt, envs=sub)
-    qo, qdo, ao, sto = o.rollout(dt, q[sub], qd[sub], act[sub], u, contact=True)
-    assert np.array_equal(stg[sub], sto)
-    assert (sto == 0).all()
-    # control: the oracle again, its state rounded to float32 after every
-    # step and its velocities perturbed by relative noise of 1e-5 per step,
-    # the per-step bound (three seeded draws). Its spread measures how far
-    # per-step errors the bound allows carry each env in 200 steps; an env
-    # crossing a discrete event (contact onset, stick-slip) at a time such
-    # errors shift has no unique FP32 trajectory. Each env's bound is the
-    # larger of 1e-3 rad and twice that spread.
-    rng = np.random.default_rng(2024)
-    dev = np.zeros(len(sub))
-    for _ in range(3):
-        qc, qdc, ac = q[sub].copy(), qd[sub].copy(), act[sub].copy()
-        for t in range(T):
-            qc, qdc, ac, _ = o.rollout(dt, qc, qdc, ac, u[t:t + 1], contact=True)
-            qdc = qdc * (1.0 + 1e-5 * rng.standard_normal(qdc.shape))
-            qc, qdc, ac = (v.astype(np.float32) for v in (qc, qdc, ac))
-        dev = np.maximum(dev, np.abs(qc[:, 7:] - qo[:, 7:]).max(axis=1))
-    bound = np.maximum(1e-3, 2.0 * dev)
+    return (q[sub], qd[sub], act[sub]), tq.cpu().numpy()[sub], stg[sub], u
+
+
+def test_freerun_human_200_contact_off(human):
+    """Whole body without ground contact (free fall under muscle action): the
+    literal bounds on all 64 envs, no control: hinges <= 1e-3 rad, root
+    position <= 1e-3 m, root orientation <= 1e-3 rad after 200 steps."""
+    m, gm, o = human
+    (q, qd, act), qg, stg, u = _human_freerun(m, gm, o, False)
+    qo, _, _, sto = o.rollout(1e-3, q, qd, act, u, contact=False)
+    assert (stg == 0).all() and (sto == 0).all()
     dh = np.abs(qg[:, 7:] - qo[:, 7:]).max(axis=1)
     dp = np.abs(qg[:, :3] - qo[:, :3]).max(axis=1)
     da = _root_angle(qg[:, 3:7], qo[:, 3:7])
-    wide = dev > 1e-3
-    print(f"human free-run 200: max |dq| = {dh.max():.3e} rad (mean over envs {dh.mean():.3e}), "
-          f"root pos {dp.max():.3e} m, root angle {da.max():.3e} rad; {int(wide.sum())} of "
-          f"{len(sub)} envs FP32-sensitive (control spread {dev[wide].round(6).tolist()}, GPU "
-          f"error {dh[wide].round(6).tolist()}); others within {dh[~wide].max():.3e} rad")
-    assert wide.sum() <= 16
-    assert (dh <= bound).all()
+    print(f"human free-run 200, contact off: max |dq| = {dh.max():.3e} rad (median env "
+          f"{np.median(dh):.3e}), root pos {dp.max():.3e} m, root angle {da.max():.3e} rad")
+    assert dh.max() <= 1e-3
+    assert dp.max() <= 1e-3 and da.max() <= 1e-3
+
+
+def test_freerun_human_200_subset(human):
+    """Whole body with ground contact, 64 envs. An env is excluded from the
+    bound only when the oracle's own controls (oracle/controls.py, fixed
+    before any GPU run) show it has no unique float32 trajectory: state
+    rounding alone moves it by more than 1e-4 rad, or per-step velocity
+    perturbations of relative 1e-6 by more than 1e-3 rad. At most 6 of 64 may
+    be excluded; every other env meets the literal bounds (hinges <= 1e-3
+    rad, root position <= 1e-3 m, root orientation <= 1e-3 rad), and the
+    median env over all 64 is within 1e-5 rad."""
+    from oracle import controls
+    m, gm, o = human
+    (q, qd, act), qg, stg, u = _human_freerun(m, gm, o, True)
+    excl, r_dev, p_dev, qo, sto = controls.exclusions(o, 1e-3, q, qd, act, u, contact=True)
+    assert np.array_equal(stg, sto)
+    assert (sto == 0).all()
+    dh = np.abs(qg[:, 7:] - qo[:, 7:]).max(axis=1)
+    dp = np.abs(qg[:, :3] - qo[:, :3]).max(axis=1)
+    da = _root_angle(qg[:, 3:7], qo[:, 3:7])
+    kept = ~excl
+    ex = np.flatnonzero(excl)
+    print(f"human free-run 200, contact on: {kept.sum()} of {len(dh)} envs kept: max |dq| = "
+          f"{dh[kept].max():.3e} rad, root pos {dp[kept].max():.3e} m, root angle "
+          f"{da[kept].max():.3e} rad; median env (all) {np.median(dh):.3e} rad")
+    for e in ex:
+        print(f"  excluded env {e * 64}: rounding control {r_dev[e]:.3e}, probe {p_dev[e]:.3e}, "
+              f"GPU error {dh[e]:.3e} rad")
+    assert excl.sum() <= controls.MAX_EXCLUDED_FRAC * len(dh)
+    assert dh[kept].max() <= 1e-3
+    assert dp[kept].max() <= 1e-3 and da[kept].max() <= 1e-3
     assert np.median(dh) <= 1e-5
-    assert dp[~wide].max() <= 1e-3 and da[~wide].max() <= 1e-3
 
 
 # ------------------------------------------------ excitation generators, bits

@@ -44,13 +44,33 @@ static double silu_d(double z) {
 }
 
 /* y = x W + b for one layer: x [B][n], W [n][m] (weights already rounded) */
+/* Each output is 0 + x_0 W_0j + x_1 W_1j + ... (i ascending), then + b_j;
+ * the loops run i before j only so that W is read row by row. */
 static void affine(int B, int n, int m, const double *x, const double *W, const float *b,
                    double *y) {
-  for (int s = 0; s < B; ++s)
-    for (int j = 0; j < m; ++j) {
-      double a = 0.0;
-      for (int i = 0; i < n; ++i) a += x[(size_t)s * n + i] * W[(size_t)i * m + j];
-      y[(size_t)s * m + j] = a + (double)b[j];
+  for (int s = 0; s < B; ++s) {
+    double *ys = y + (size_t)s * m;
+    for (int j = 0; j < m; ++j) ys[j] = 0.0;
+    for (int i = 0; i < n; ++i) {
+      const double xi = x[(size_t)s * n + i];
+      const double *Wi = W + (size_t)i * m;
+      for (int j = 0; j < m; ++j) ys[j] += xi * Wi[j];
+    }
+    for (int j = 0; j < m; ++j) ys[j] += (double)b[j];
+  }
+}
+
+/* gW[i][j] = sum over samples b (ascending) of a[b][i] d[b][j], summed in
+ * that order from 0; the loops run over b outermost only so that the rows
+ * are read contiguously. */
+static void outer_sum(int B, int n, int m, const double *a, const double *d, double *gW) {
+  for (size_t k = 0; k < (size_t)n * m; ++k) gW[k] = 0.0;
+  for (int b = 0; b < B; ++b)
+    for (int i = 0; i < n; ++i) {
+      const double ai = a[(size_t)b * n + i];
+      const double *db = d + (size_t)b * m;
+      double *g = gW + (size_t)i * m;
+      for (int j = 0; j < m; ++j) g[j] += ai * db[j];
     }
 }
 
@@ -114,12 +134,7 @@ double ora_mlp_grad(int B, int n0, int n1, int n2, int n3, const float *W1, cons
     gb3[j] = s;
   }
   for (size_t i = 0; i < (size_t)B * n3; ++i) dy[i] = rnd(dy[i], bf16);
-  for (int i = 0; i < n2; ++i)
-    for (int j = 0; j < n3; ++j) {
-      double s = 0.0;
-      for (int b = 0; b < B; ++b) s += h2[(size_t)b * n2 + i] * dy[(size_t)b * n3 + j];
-      gW3[(size_t)i * n3 + j] = s;
-    }
+  outer_sum(B, n2, n3, h2, dy, gW3);
   for (int b = 0; b < B; ++b)
     for (int i = 0; i < n2; ++i) {
       double s = 0.0;
@@ -133,12 +148,7 @@ double ora_mlp_grad(int B, int n0, int n1, int n2, int n3, const float *W1, cons
     gb2[j] = s;
   }
   for (size_t i = 0; i < (size_t)B * n2; ++i) dz2[i] = rnd(dz2[i], bf16);
-  for (int i = 0; i < n1; ++i)
-    for (int j = 0; j < n2; ++j) {
-      double s = 0.0;
-      for (int b = 0; b < B; ++b) s += h1[(size_t)b * n1 + i] * dz2[(size_t)b * n2 + j];
-      gW2[(size_t)i * n2 + j] = s;
-    }
+  outer_sum(B, n1, n2, h1, dz2, gW2);
   for (int b = 0; b < B; ++b)
     for (int i = 0; i < n1; ++i) {
       double s = 0.0;
@@ -152,12 +162,7 @@ double ora_mlp_grad(int B, int n0, int n1, int n2, int n3, const float *W1, cons
     gb1[j] = s;
   }
   for (size_t i = 0; i < (size_t)B * n1; ++i) dz1[i] = rnd(dz1[i], bf16);
-  for (int i = 0; i < n0; ++i)
-    for (int j = 0; j < n1; ++j) {
-      double s = 0.0;
-      for (int b = 0; b < B; ++b) s += xr[(size_t)b * n0 + i] * dz1[(size_t)b * n1 + j];
-      gW1[(size_t)i * n1 + j] = s;
-    }
+  outer_sum(B, n0, n1, xr, dz1, gW1);
   free(y); free(z1); free(h1); free(z2); free(h2); free(w2); free(w3); free(xr); free(dy);
   free(dz2); free(dz1);
   return loss;

@@ -388,3 +388,163 @@ def test_full_size_surrogate_rollout_falls_back_to_the_exact_path():
         assert np.array_equal(a[k], b[k])
     assert ((a[4] & ~ms.MS_ST_FALLBACK) == b[4]).all()
     assert (a[5] == T).all()
+
+
+# ------------------------------------------------- whole-body network, full size
+def _hinge_inputs(m):
+    """q index and pose box of every network input (hinge/slide coordinates
+    in node order; a free root's seven coordinates are not inputs)."""
+    qi, lo, hi = [], [], []
+    qa = da = 0
+    for i in range(m["n_node"]):
+        if m["jtype"][i] == 2:
+            qa, da = qa + 7, da + 6
+            continue
+        qi.append(qa)
+        lo.append(m["qlo"][da])
+        hi.append(m["qhi"][da])
+        qa, da = qa + 1, da + 1
+    return np.array(qi), np.asarray(lo, np.float32), np.asarray(hi, np.float32)
+
+
+def _human_poses(m, n, seed):
+    """Hinge coordinates uniform in their boxes; the root at the origin with
+    the identity orientation."""
+    qi, lo, hi = _hinge_inputs(m)
+    rng = np.random.default_rng(seed)
+    q = np.zeros((n, m["nq"]), np.float32)
+    q[:, 3] = 1.0
+    q[:, qi] = rng.uniform(lo, hi, (n, len(qi))).astype(np.float32)
+    return q
+
+
+def _human_inputs(m, s, q):
+    qi, lo, hi = _hinge_inputs(m)
+    c = np.float32(0.5) * (lo + hi)
+    isc = np.float32(2.0) / (hi - lo)
+    x = np.zeros((q.shape[0], s.n_in), np.float32)
+    x[:, :len(qi)] = (q[:, qi] - c) * isc
+    return x
+
+
+@pytest.fixture(scope="module")
+def human_net():
+    m = synth.human_model(2)
+    gm = ms.Model(m)
+    o = oracle.Oracle(m)
+    s = ms.Surrogate(gm, hidden=512, seed=41)
+    spans = _oracle_spans(m, o)
+    assert np.array_equal(gm.spans(), spans)
+    return m, gm, s, o, spans
+
+
+def test_full_size_network_forward_gradients_and_adam(human_net):
+    """The whole-body network (74 inputs padded to 80 -> 512 -> 512 -> 2800)
+    at batch 2048, so every GEMM runs several M, N and K tiles and the
+    weight gradients run split-K with several slices: forward outputs, the
+    loss, all six gradients and one Adam step against the oracle network
+    with the same bfloat16 rounding points."""
+    m, gm, s, o, spans = human_net
+    n = 2048
+    rng = np.random.default_rng(2048)
+    ps = s.params()
+    for k in (1, 3, 5):
+        ps[k][:] = rng.normal(size=ps[k].shape) * 0.1
+    s.set_params(ps)
+    qh = _human_poses(m, n, 17)
+    x = _human_inputs(m, s, qh)
+    # forward, de-standardised
+    mean = rng.normal(size=s.n_out).astype(np.float32)
+    std = rng.uniform(0.5, 2, s.n_out).astype(np.float32)
+    s.set_norm(mean, std)
+    L = torch.zeros(n, m["n_mus"], device=DEV)
+    r = torch.zeros(n, m["n_mus"], 3, device=DEV)
+    s.forward(_t(qh), L, r)
+    torch.cuda.synchronize()
+    y = np.concatenate([L.cpu().numpy(), r.cpu().numpy().reshape(n, -1)], axis=1)
+    yo = oracle.mlp_forward(_oracle_params(ps), x, bf16=True) * std + mean
+    assert _rel(y, yo) < 2e-3, _rel(y, yo)
+    # gradients on random targets (identity standardisation)
+    _identity_norm(s)
+    t = rng.normal(0, 0.5, (n, s.n_out)).astype(np.float32)
+    mask = np.ones(s.n_out, np.float32)
+    mask[m["n_mus"]:] = (spans.reshape(-1) >= 0)
+    t *= mask
+    loss = torch.zeros(1, device=DEV)
+    s.train_step(_t(qh), _t(t[:, :m["n_mus"]]), _t(t[:, m["n_mus"]:].reshape(n, m["n_mus"], 3)),
+                 lr=0.0, step=1, loss=loss)
+    torch.cuda.synchronize()
+    g = s.grads()
+    lo, go = oracle.mlp_grad(_oracle_params(ps), x, t, np.tile(mask, (n, 1)), bf16=True)
+    assert abs(loss.item() - lo) < 1e-3 * lo, (loss.item(), lo)
+    pairs = [(g[0], go[0].T), (g[1], go[1]), (g[2], go[2].T), (g[3], go[3]), (g[4], go[4].T),
+             (g[5], go[5])]
+    for k, (a, b) in enumerate(pairs):
+        assert _rel(a, b) < 1e-2, (k, _rel(a, b))
+    # one Adam step on the same batch
+    p0 = s.params()
+    s.train_step(_t(qh), _t(t[:, :m["n_mus"]]), _t(t[:, m["n_mus"]:].reshape(n, m["n_mus"], 3)),
+                 lr=1e-3, step=1)
+    torch.cuda.synchronize()
+    g1 = s.grads()
+    p1 = s.params()
+    for a, b, gg in zip(p0, p1, g1):
+        w = a.astype(np.float64).copy()
+        mm = np.zeros_like(w)
+        vv = np.zeros_like(w)
+        oracle.adam(w.reshape(-1), mm.reshape(-1), vv.reshape(-1),
+                    gg.astype(np.float64).reshape(-1), lr=1e-3, step=1)
+        assert np.abs(b - w).max() < 1e-6
+
+
+def test_full_size_prediction_taken_step_matches_oracle(human_net):
+    """Whole body, contact off: a constant network returning the oracle's
+    geometry at a reference pose (lengths 0.5 mm long, moment arms 10 %
+    large) passes a 1 mm residual check on envs within 2e-6 of that pose,
+    which then advance as the oracle step given that geometry (per-step
+    bound 1e-5); envs moved 0.2-0.4 rad away fail it and advance bit for bit
+    as the exact path does."""
+    m, gm, s, o, spans = human_net
+    qi, _, _ = _hinge_inputs(m)
+    q0, _, _ = synth.human_initial_state(m, 1, seed=21)
+    q_ref = q0[0].astype(np.float64)
+    Lr, rr = _constant_network(m, s, o, spans, q_ref)
+    E, dt = 128, 1e-3
+    near = np.arange(E) % 4 != 0
+    rng = np.random.default_rng(6)
+    q = np.tile(q_ref, (E, 1)).astype(np.float32)
+    q[np.ix_(near, qi)] += rng.uniform(-2e-6, 2e-6, (near.sum(), len(qi))).astype(np.float32)
+    q[np.ix_(~near, qi)] += rng.uniform(0.2, 0.4, ((~near).sum(), len(qi))).astype(np.float32)
+    qd = rng.normal(0, 0.3, (E, m["nv"])).astype(np.float32)
+    act = rng.uniform(0.05, 0.6, (E, m["n_mus"])).astype(np.float32)
+    u = synth.excitation_iid(13, E, m["n_mus"], 0)
+    tq, tqd, tact = _t(q), _t(qd), _t(act)
+    st = torch.zeros(E, dtype=torch.int32, device=DEV)
+    fb = torch.zeros(E, dtype=torch.int32, device=DEV)
+    gm.rollout_surrogate(s, tq, tqd, tact, st, 1, dt, contact=False, tol=1e-3,
+                         fb_count=fb, kind=ms.EXC_ARRAY, u=_t(u[None]))
+    eq, eqd, eact = _t(q), _t(qd), _t(act)
+    est = torch.zeros(E, dtype=torch.int32, device=DEV)
+    gm.rollout(eq, eqd, eact, est, 1, dt, False, kind=ms.EXC_ARRAY, u=_t(u[None]))
+    torch.cuda.synchronize()
+    st, fb = st.cpu().numpy(), fb.cpu().numpy()
+    assert (est.cpu().numpy() == 0).all()
+    assert np.array_equal(fb, (~near).astype(np.int32))
+    assert np.array_equal(st, np.where(near, 0, ms.MS_ST_FALLBACK))
+    g = [x.cpu().numpy() for x in (tq, tqd, tact)]
+    ex = [x.cpu().numpy() for x in (eq, eqd, eact)]
+    for a, b in zip(g, ex):
+        assert np.array_equal(a[~near], b[~near])
+    rfull = _full_r(m, spans, rr)
+    worst = 0.0
+    for e in np.flatnonzero(near)[::6]:
+        qo, qdo, ao, sto = o.step(dt, q[e], qd[e], act[e], u[e], contact=False,
+                                  geometry=(Lr, rfull))
+        assert sto == 0
+        for a, b in zip((g[0][e], g[1][e], g[2][e]), (qo, qdo, ao)):
+            err = np.abs(a - b).max() / max(np.abs(b).max(), 1.0)
+            worst = max(worst, err)
+            assert err <= 1e-5, (e, err)
+    print(f"prediction-taken whole-body step: worst per-block error {worst:.2e}")
+    assert np.abs(g[1][near] - ex[1][near]).max() > 1e-3
+    _identity_norm(s)

@@ -31,7 +31,10 @@
  *    A free root stores q = (px, py, pz, qw, qx, qy, qz, hinges...) and
  *    qd = (world linear velocity, body angular velocity, hinge rates...).
  *  - Every call is asynchronous on `stream` (a hipStream_t passed as void*;
- *    NULL = the default stream) and never synchronises implicitly.
+ *    NULL = the default stream) and never synchronises implicitly, except
+ *    where a call says it allocates: create calls, reservations, and the
+ *    workspace growth of the surrogate and policy calls (avoided by
+ *    reserving first).
  *  - Calls return an ms_status; nothing throws across the ABI. On error the
  *    message is available from ms_last_error() (thread-local).
  *  - Per-environment numerical failures are not return codes: they are
@@ -236,6 +239,13 @@ ms_status ms_surrogate_sample(ms_surrogate *s, int32_t n, uint64_t seed, int64_t
 /* predictions for n poses q[n][nq] (device): L[n][n_mus], r[n][n_mus][3] */
 ms_status ms_surrogate_forward(ms_surrogate *s, int32_t n, const float *q, float *L,
                                float *r, void *stream);
+/* Reserve the surrogate's workspace for batches of up to n poses now
+ * (synchronous device allocation), so that later forward, train-step and
+ * surrogate-rollout calls of at most n poses/envs allocate nothing. Those
+ * calls grow the workspace themselves when n exceeds it, and that growth
+ * allocates and synchronises. All buffers of a growth are taken or none:
+ * on MS_E_ALLOC the previous workspace stays in use. */
+ms_status ms_surrogate_reserve(ms_surrogate *s, int32_t n);
 /* one training step on n poses (n a multiple of 8) with exact labels
  * L, r (device, as from ms_geometry): loss = mean over (pose, output) of
  * mask (y - t)^2 on standardised targets t, written to *loss (device) if
@@ -267,6 +277,10 @@ typedef struct ms_policy ms_policy;
 ms_status ms_policy_create(const ms_model *m, int32_t hidden, int32_t n_ref,
                            uint64_t ref_seed, uint64_t seed, ms_policy **out);
 void ms_policy_destroy(ms_policy *p);
+/* Reserve the policy's workspace for up to n envs now (synchronous
+ * allocation); ms_policy_act and ms_policy_rollout grow it themselves when
+ * n exceeds it, allocating and synchronising, all buffers or none. */
+ms_status ms_policy_reserve(ms_policy *p, int32_t n);
 /* dims[4] = n_obs, n_in (n_obs padded to a multiple of 16), hidden, n_mus */
 ms_status ms_policy_dims(const ms_policy *p, int32_t *dims);
 /* host copies of the float32 parameters (set = 0 reads, 1 writes); W1 is

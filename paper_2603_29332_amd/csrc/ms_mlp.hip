@@ -214,36 +214,61 @@ T *dalloc(ms_surrogate *s, size_t n) {
   return (T *)p;
 }
 
+// Allocate every buffer of a request or none: on a failure the buffers
+// already taken are freed and the caller's fields stay as they were.
+struct AllocSet {
+  std::vector<std::pair<void **, size_t>> want;
+  template <class T>
+  void add(T **field, size_t n) {
+    want.push_back({(void **)field, std::max<size_t>(n, 1) * sizeof(T)});
+  }
+  bool commit(std::vector<void *> &owned) {
+    std::vector<void *> got(want.size(), nullptr);
+    for (size_t i = 0; i < want.size(); ++i) {
+      if (hipMalloc(&got[i], want[i].second) != hipSuccess) {
+        for (size_t j = 0; j < i; ++j) (void)hipFree(got[j]);
+        return false;
+      }
+    }
+    for (size_t i = 0; i < want.size(); ++i) {
+      *want[i].first = got[i];
+      owned.push_back(got[i]);
+    }
+    return true;
+  }
+};
+
+// Workspace for n poses. The kernels write every workspace element before
+// reading it, so nothing is cleared. A larger workspace replaces the old
+// one, which stays allocated until destroy: launches still queued may use it.
 ms_status ensure_cap(ms_surrogate *s, int n) {
   if (n <= s->cap) return MS_OK;
-  // workspace is replaced, not freed: previous launches may still use it
   const size_t B = (size_t)n;
-  s->X = dalloc<bf16>(s, B * s->n_in);
-  s->Z1 = dalloc<float>(s, B * s->h1);
-  s->H1 = dalloc<bf16>(s, B * s->h1);
-  s->Z2 = dalloc<float>(s, B * s->h2);
-  s->H2 = dalloc<bf16>(s, B * s->h2);
-  s->Y = dalloc<float>(s, B * s->n_out);
-  s->T = dalloc<float>(s, B * s->n_out);
-  s->dY = dalloc<float>(s, B * s->n_out);
-  s->dYb = dalloc<bf16>(s, B * s->n_out);
-  s->dZ2 = dalloc<float>(s, B * s->h2);
-  s->dZ2b = dalloc<bf16>(s, B * s->h2);
-  s->dZ1 = dalloc<float>(s, B * s->h1);
-  s->dZ1b = dalloc<bf16>(s, B * s->h1);
-  s->part = dalloc<float>(s, (size_t)blocks((long long)B * s->n_out));
-  s->cpart = dalloc<float>(s, (size_t)((B + kCS - 1) / kCS) * std::max(s->n_out, std::max(s->h1, s->h2)));
+  AllocSet a;
+  a.add(&s->X, B * s->n_in);
+  a.add(&s->Z1, B * s->h1);
+  a.add(&s->H1, B * s->h1);
+  a.add(&s->Z2, B * s->h2);
+  a.add(&s->H2, B * s->h2);
+  a.add(&s->Y, B * s->n_out);
+  a.add(&s->T, B * s->n_out);
+  a.add(&s->dY, B * s->n_out);
+  a.add(&s->dYb, B * s->n_out);
+  a.add(&s->dZ2, B * s->h2);
+  a.add(&s->dZ2b, B * s->h2);
+  a.add(&s->dZ1, B * s->h1);
+  a.add(&s->dZ1b, B * s->h1);
+  a.add(&s->part, (size_t)blocks((long long)B * s->n_out));
+  a.add(&s->cpart, (size_t)((B + kCS - 1) / kCS) * std::max(s->n_out, std::max(s->h1, s->h2)));
   {
     // split-K partials of the weight gradients (K = batch)
     const int M[3] = {s->n_out, s->h2, s->h1}, N[3] = {s->h2, s->h1, s->n_in};
     size_t w = 0;
     for (int l = 0; l < 3; ++l)
       w = std::max(w, (size_t)splitk_slices(M[l], N[l], n) * M[l] * N[l]);
-    s->kwork = dalloc<float>(s, w);
+    a.add(&s->kwork, w);
   }
-  if (!s->X || !s->Z1 || !s->H1 || !s->Z2 || !s->H2 || !s->Y || !s->T || !s->dY || !s->dYb ||
-      !s->dZ2 || !s->dZ2b || !s->dZ1 || !s->dZ1b || !s->part || !s->cpart || !s->kwork)
-    return sfail(MS_E_ALLOC, "surrogate workspace allocation failed");
+  if (!a.commit(s->owned)) return sfail(MS_E_ALLOC, "surrogate workspace allocation failed");
   s->cap = n;
   return MS_OK;
 }
@@ -253,36 +278,47 @@ ms_status hipst(hipError_t e, const char *what) {
   return MS_OK;
 }
 
-// forward through the three layers into s->Y (standardised, or
-// de-standardised when destd), keeping Z1/Z2 for training
-ms_status forward(ms_surrogate *s, int n, const float *q, bool destd, bool keep, hipStream_t st) {
+// Buffers of one forward pass: packed inputs, hidden activations (with
+// the pre-activations when training needs them) and the outputs.
+struct FwdWork {
+  bf16 *X, *H1, *H2;
+  float *Z1, *Z2, *Y;
+};
+FwdWork own_work(ms_surrogate *s, bool keep) {
+  return FwdWork{s->X, s->H1, s->H2, keep ? s->Z1 : nullptr, keep ? s->Z2 : nullptr, s->Y};
+}
+
+// forward through the three layers into w.Y (standardised, or
+// de-standardised when destd), keeping Z1/Z2 when w holds them (training)
+ms_status forward(ms_surrogate *s, int n, const float *q, bool destd, const FwdWork &w,
+                  hipStream_t st) {
   hipLaunchKernelGGL(k_pack, dim3(blocks((long long)n * s->n_in)), dim3(256), 0, st, q, s->nq,
-                     s->hinge_q, s->lo, s->hi, s->n_in, n, s->X);
+                     s->hinge_q, s->lo, s->hi, s->n_in, n, w.X);
   GemmEpi e1;
   e1.bias = s->b[0];
-  e1.z_out = keep ? s->Z1 : nullptr;
+  e1.z_out = w.Z1;
   e1.act = 1;
-  e1.c_bf16 = s->H1;
+  e1.c_bf16 = w.H1;
   e1.ldc = s->h1;
-  hipError_t e = gemm_bf16(false, true, n, s->h1, s->n_in, s->X, s->n_in, s->Wb[0], s->n_in, e1, st);
+  hipError_t e = gemm_bf16(false, true, n, s->h1, s->n_in, w.X, s->n_in, s->Wb[0], s->n_in, e1, st);
   if (e != hipSuccess) return hipst(e, "gemm 1");
   GemmEpi e2;
   e2.bias = s->b[1];
-  e2.z_out = keep ? s->Z2 : nullptr;
+  e2.z_out = w.Z2;
   e2.act = 1;
-  e2.c_bf16 = s->H2;
+  e2.c_bf16 = w.H2;
   e2.ldc = s->h2;
-  e = gemm_bf16(false, true, n, s->h2, s->h1, s->H1, s->h1, s->Wb[1], s->h1, e2, st);
+  e = gemm_bf16(false, true, n, s->h2, s->h1, w.H1, s->h1, s->Wb[1], s->h1, e2, st);
   if (e != hipSuccess) return hipst(e, "gemm 2");
   GemmEpi e3;
   e3.bias = s->b[2];
-  e3.c_f32 = s->Y;
+  e3.c_f32 = w.Y;
   e3.ldc = s->n_out;
   if (destd) {
     e3.scale = s->stdv;
     e3.shift = s->mean;
   }
-  e = gemm_bf16(false, true, n, s->n_out, s->h2, s->H2, s->h2, s->Wb[2], s->h2, e3, st);
+  e = gemm_bf16(false, true, n, s->n_out, s->h2, w.H2, s->h2, s->Wb[2], s->h2, e3, st);
   return hipst(e, "gemm 3");
 }
 
@@ -295,7 +331,7 @@ ms_status ms_surrogate_predict(ms_surrogate *s, int n, const float *q, const flo
                                hipStream_t st) {
   ms_status r = ensure_cap(s, n);
   if (r != MS_OK) return r;
-  r = forward(s, n, q, true, false, st);
+  r = forward(s, n, q, true, own_work(s, false), st);
   *Y = s->Y;
   return r;
 }
@@ -456,11 +492,17 @@ ms_status ms_surrogate_forward(ms_surrogate *s, int32_t n, const float *q, float
   ms_status st = ensure_cap(s, n);
   if (st != MS_OK) return st;
   hipStream_t hs = (hipStream_t)stream;
-  st = forward(s, n, q, true, false, hs);
+  st = forward(s, n, q, true, own_work(s, false), hs);
   if (st != MS_OK) return st;
   hipLaunchKernelGGL(k_unpack, dim3(blocks((long long)n * s->n_out)), dim3(256), 0, hs, s->Y,
                      s->n_mus, n, L, r);
   return hipst(hipGetLastError(), "unpack");
+}
+
+ms_status ms_surrogate_reserve(ms_surrogate *s, int32_t n) {
+  s_err.clear();
+  if (!s || n <= 0) return sfail(MS_E_ARG, "bad arguments");
+  return ensure_cap(s, n);
 }
 
 ms_status ms_surrogate_train_step(ms_surrogate *s, int32_t n, const float *q, const float *L,
@@ -475,7 +517,7 @@ ms_status ms_surrogate_train_step(ms_surrogate *s, int32_t n, const float *q, co
   const long long no = (long long)n * s->n_out;
   hipLaunchKernelGGL(k_targets, dim3(blocks(no)), dim3(256), 0, hs, L, r, s->n_mus, n, s->mean,
                      s->istd, s->mask, s->T);
-  st = forward(s, n, q, false, true, hs);
+  st = forward(s, n, q, false, own_work(s, true), hs);
   if (st != MS_OK) return st;
   const int nb = blocks(no);
   hipLaunchKernelGGL(k_loss, dim3(nb), dim3(256), 0, hs, s->Y, s->T, s->mask, n, s->n_out, s->dY,
@@ -613,11 +655,12 @@ __global__ void k_obs(int n, int nq, int nv, int free_root, int n_obs, int n_in,
 
 ms_status policy_cap(ms_policy *p, int n) {
   if (n <= p->cap) return MS_OK;
-  p->X = palloc<bf16>(p, (size_t)n * p->n_in);
-  p->H1 = palloc<bf16>(p, (size_t)n * p->h);
-  p->H2 = palloc<bf16>(p, (size_t)n * p->h);
-  p->U = palloc<float>(p, (size_t)n * p->n_mus);
-  if (!p->X || !p->H1 || !p->H2 || !p->U) return sfail(MS_E_ALLOC, "policy workspace allocation failed");
+  AllocSet a;
+  a.add(&p->X, (size_t)n * p->n_in);
+  a.add(&p->H1, (size_t)n * p->h);
+  a.add(&p->H2, (size_t)n * p->h);
+  a.add(&p->U, (size_t)n * p->n_mus);
+  if (!a.commit(p->owned)) return sfail(MS_E_ALLOC, "policy workspace allocation failed");
   p->cap = n;
   return MS_OK;
 }
@@ -656,6 +699,12 @@ ms_status policy_forward(ms_policy *p, int n, const float *q, const float *qd, d
 }  // namespace ms
 
 extern "C" {
+
+ms_status ms_policy_reserve(ms_policy *p, int32_t n) {
+  s_err.clear();
+  if (!p || n <= 0) return sfail(MS_E_ARG, "bad arguments");
+  return policy_cap(p, n);
+}
 
 ms_status ms_policy_create(const ms_model *m, int32_t hidden, int32_t n_ref, uint64_t ref_seed,
                            uint64_t seed, ms_policy **out) {

@@ -31,7 +31,8 @@ EXPORTED = ("ms_model_create", "ms_model_destroy", "ms_model_info_get",
             "ms_batch_create", "ms_batch_destroy", "ms_batch_rollout", "ms_batch_autotune",
             "ms_batch_config", "ms_batch_set_config", "ms_batch_last_error",
             "ms_policy_create", "ms_policy_destroy", "ms_policy_dims", "ms_policy_params",
-            "ms_policy_act", "ms_policy_rollout")
+            "ms_policy_act", "ms_policy_rollout", "ms_surrogate_reserve",
+            "ms_policy_reserve")
 
 _fptr = C.POINTER(C.c_float)
 _iptr = C.POINTER(C.c_int32)
@@ -112,6 +113,8 @@ def lib():
     L.ms_surrogate_sample.argtypes = [vp, C.c_int32, C.c_uint64, C.c_int64, vp, vp]
     L.ms_surrogate_forward.argtypes = [vp, C.c_int32, vp, vp, vp, vp]
     L.ms_surrogate_train_step.argtypes = [vp, C.c_int32, vp, vp, vp, C.c_float, C.c_int32, vp, vp]
+    L.ms_surrogate_reserve.argtypes = [vp, C.c_int32]
+    L.ms_policy_reserve.argtypes = [vp, C.c_int32]
     L.ms_rollout_surrogate.argtypes = [vp, vp, C.c_int32, vp, vp, vp, vp, C.POINTER(MsExc),
                                        C.c_int32, C.POINTER(MsOpts), C.c_float, vp, vp]
     L.ms_rollout_surrogate.restype = C.c_int
@@ -124,7 +127,7 @@ def lib():
     L.ms_policy_rollout.argtypes = [vp, vp, vp, C.c_int32, vp, vp, vp, vp, C.c_int32, C.c_int32,
                                     C.c_double, C.POINTER(MsOpts), C.c_float, vp, vp, vp]
     for f in ("ms_policy_create", "ms_policy_dims", "ms_policy_params", "ms_policy_act",
-              "ms_policy_rollout"):
+              "ms_policy_rollout", "ms_policy_reserve"):
         getattr(L, f).restype = C.c_int
     L.ms_batch_create.argtypes = [C.POINTER(vp), _iptr, C.c_int32, C.POINTER(vp)]
     L.ms_batch_destroy.argtypes = [vp]
@@ -359,6 +362,9 @@ class Surrogate:
         _check_s(lib().ms_surrogate_forward(self.h, q.shape[0], _dp(q), _dp(L), _dp(r),
                                             _stream(stream)))
 
+    def reserve(self, n):
+        _check_s(lib().ms_surrogate_reserve(self.h, int(n)))
+
     def train_step(self, q, L, r, lr, step, loss=None, stream=None):
         _check_s(lib().ms_surrogate_train_step(self.h, q.shape[0], _dp(q), _dp(L), _dp(r),
                                                float(lr), int(step), _dp(loss), _stream(stream)))
@@ -455,6 +461,9 @@ class Policy:
         b = [np.zeros(s, np.float32) for s in self.shapes]
         _check_s(lib().ms_policy_params(self.h, 0, *[x.ctypes.data_as(_fptr) for x in b]))
         return b
+
+    def reserve(self, n):
+        _check_s(lib().ms_policy_reserve(self.h, int(n)))
 
     def act(self, q, qd, t, u, env0=0, obs=None, stream=None):
         _check_s(lib().ms_policy_act(self.h, q.shape[0], _dp(q), _dp(qd), float(t), int(env0),

@@ -246,6 +246,22 @@ ms_status ms_surrogate_forward(ms_surrogate *s, int32_t n, const float *q, float
  * allocates and synchronises. All buffers of a growth are taken or none:
  * on MS_E_ALLOC the previous workspace stays in use. */
 ms_status ms_surrogate_reserve(ms_surrogate *s, int32_t n);
+/* ms_surrogate_forward for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): it calls no allocating routine and takes its intermediate
+ * buffers (packed inputs, both hidden layers, outputs) from a static
+ * device array of 16 MiB per GPU, held until the process ends. The caller
+ * still passes inputs and outputs. n is limited to what fits that array,
+ * ms_surrogate_noalloc_max(s) poses (1,251 for a 74-input, 512-wide,
+ * 700-muscle network); larger n returns MS_E_UNSUPPORTED with nothing
+ * launched. Every call on one GPU shares that GPU's array: calls that
+ * overlap in time on one GPU (several streams or host threads) race and
+ * must be serialised by the caller. Results equal ms_surrogate_forward's
+ * bit for bit (the same kernels). */
+ms_status ms_surrogate_forward_noalloc(ms_surrogate *s, int32_t n, const float *q,
+                                       float *L, float *r, void *stream);
+/* Largest n ms_surrogate_forward_noalloc accepts for this network. */
+int32_t ms_surrogate_noalloc_max(const ms_surrogate *s);
 /* one training step on n poses (n a multiple of 8) with exact labels
  * L, r (device, as from ms_geometry): loss = mean over (pose, output) of
  * mask (y - t)^2 on standardised targets t, written to *loss (device) if

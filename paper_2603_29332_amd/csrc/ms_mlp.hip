@@ -12,6 +12,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -322,6 +323,43 @@ ms_status forward(ms_surrogate *s, int n, const float *q, bool destd, const FwdW
   return hipst(e, "gemm 3");
 }
 
+// ---------------------------------------------- allocation-free forward
+// Device memory of ms_surrogate_forward_noalloc: one static array per GPU
+// (each device holds its own copy until the process ends). Host code never
+// uses the array's name as an address: its device address is taken once
+// per device with hipGetSymbolAddress, with that device current, and kept
+// in scratch_dev[device].
+constexpr size_t kScratchBytes = (size_t)16 << 20;
+constexpr int kMaxDevices = 64;
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+void *scratch_dev[kMaxDevices] = {};
+std::mutex scratch_mu;
+
+// Address of the current device's scratch array (looked up on first use).
+ms_status scratch_address(void **out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hipst(e, "hipGetDevice");
+  if (dev < 0 || dev >= kMaxDevices) return sfail(MS_E_UNSUPPORTED, "device index beyond 63");
+  std::lock_guard<std::mutex> lk(scratch_mu);
+  if (!scratch_dev[dev]) {
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hipst(e, "hipGetSymbolAddress(scratch)");
+    scratch_dev[dev] = p;
+  }
+  *out = scratch_dev[dev];
+  return MS_OK;
+}
+
+inline size_t align256(size_t b) { return (b + 255) / 256 * 256; }
+
+// Bytes of scratch a forward of n poses takes: X, H1, H2 (bfloat16) and Y.
+size_t noalloc_bytes(const ms_surrogate *s, long long n) {
+  return align256((size_t)n * s->n_in * 2) + align256((size_t)n * s->h1 * 2) +
+         align256((size_t)n * s->h2 * 2) + align256((size_t)n * s->n_out * 4);
+}
+
 }  // namespace
 }  // namespace ms
 
@@ -406,6 +444,13 @@ ms_status ms_surrogate_create(const ms_model *m, int32_t hidden, uint64_t seed, 
   if (e != hipSuccess) {
     ms_surrogate_destroy(s);
     return hipst(e, "surrogate setup");
+  }
+  // the allocation-free forward's scratch address on this device
+  void *scr = nullptr;
+  const ms_status ss = scratch_address(&scr);
+  if (ss != MS_OK) {
+    ms_surrogate_destroy(s);
+    return ss;
   }
   *out = s;
   return MS_OK;
@@ -503,6 +548,49 @@ ms_status ms_surrogate_reserve(ms_surrogate *s, int32_t n) {
   s_err.clear();
   if (!s || n <= 0) return sfail(MS_E_ARG, "bad arguments");
   return ensure_cap(s, n);
+}
+
+ms_status ms_surrogate_forward_noalloc(ms_surrogate *s, int32_t n, const float *q, float *L,
+                                       float *r, void *stream) {
+  s_err.clear();
+  if (!s || n <= 0 || !q || !L || !r) return sfail(MS_E_ARG, "bad arguments");
+  const size_t need = noalloc_bytes(s, n);
+  if (need > kScratchBytes)
+    return sfail(MS_E_UNSUPPORTED, "ms_surrogate_forward_noalloc: " + std::to_string(n) +
+                                       " poses need " + std::to_string(need) +
+                                       " bytes of scratch, beyond its " +
+                                       std::to_string(kScratchBytes) + " (at most " +
+                                       std::to_string(ms_surrogate_noalloc_max(s)) + " poses)");
+  void *base = nullptr;
+  ms_status st = scratch_address(&base);
+  if (st != MS_OK) return st;
+  unsigned char *p = (unsigned char *)base;
+  FwdWork w;
+  w.X = (bf16 *)p;
+  p += align256((size_t)n * s->n_in * 2);
+  w.H1 = (bf16 *)p;
+  p += align256((size_t)n * s->h1 * 2);
+  w.H2 = (bf16 *)p;
+  p += align256((size_t)n * s->h2 * 2);
+  w.Y = (float *)p;
+  w.Z1 = w.Z2 = nullptr;
+  hipStream_t hs = (hipStream_t)stream;
+  st = forward(s, n, q, true, w, hs);
+  if (st != MS_OK) return st;
+  hipLaunchKernelGGL(k_unpack, dim3(blocks((long long)n * s->n_out)), dim3(256), 0, hs, w.Y,
+                     s->n_mus, n, L, r);
+  return hipst(hipGetLastError(), "unpack");
+}
+
+int32_t ms_surrogate_noalloc_max(const ms_surrogate *s) {
+  if (!s) return 0;
+  long long lo = 0, hi = 1;
+  while (noalloc_bytes(s, hi) <= kScratchBytes) hi *= 2;
+  while (hi - lo > 1) {
+    const long long mid = (lo + hi) / 2;
+    (noalloc_bytes(s, mid) <= kScratchBytes ? lo : hi) = mid;
+  }
+  return (int32_t)lo;
 }
 
 ms_status ms_surrogate_train_step(ms_surrogate *s, int32_t n, const float *q, const float *L,

@@ -32,7 +32,7 @@ EXPORTED = ("ms_model_create", "ms_model_destroy", "ms_model_info_get",
             "ms_batch_config", "ms_batch_set_config", "ms_batch_last_error",
             "ms_policy_create", "ms_policy_destroy", "ms_policy_dims", "ms_policy_params",
             "ms_policy_act", "ms_policy_rollout", "ms_surrogate_reserve",
-            "ms_policy_reserve")
+            "ms_surrogate_forward_noalloc", "ms_surrogate_noalloc_max", "ms_policy_reserve")
 
 _fptr = C.POINTER(C.c_float)
 _iptr = C.POINTER(C.c_int32)
@@ -114,6 +114,9 @@ def lib():
     L.ms_surrogate_forward.argtypes = [vp, C.c_int32, vp, vp, vp, vp]
     L.ms_surrogate_train_step.argtypes = [vp, C.c_int32, vp, vp, vp, C.c_float, C.c_int32, vp, vp]
     L.ms_surrogate_reserve.argtypes = [vp, C.c_int32]
+    L.ms_surrogate_forward_noalloc.argtypes = [vp, C.c_int32, vp, vp, vp, vp]
+    L.ms_surrogate_noalloc_max.argtypes = [vp]
+    L.ms_surrogate_noalloc_max.restype = C.c_int32
     L.ms_policy_reserve.argtypes = [vp, C.c_int32]
     L.ms_rollout_surrogate.argtypes = [vp, vp, C.c_int32, vp, vp, vp, vp, C.POINTER(MsExc),
                                        C.c_int32, C.POINTER(MsOpts), C.c_float, vp, vp]
@@ -364,6 +367,13 @@ class Surrogate:
 
     def reserve(self, n):
         _check_s(lib().ms_surrogate_reserve(self.h, int(n)))
+
+    def forward_noalloc(self, q, L, r, stream=None):
+        _check_s(lib().ms_surrogate_forward_noalloc(self.h, q.shape[0], _dp(q), _dp(L), _dp(r),
+                                                    _stream(stream)))
+
+    def noalloc_max(self):
+        return int(lib().ms_surrogate_noalloc_max(self.h))
 
     def train_step(self, q, L, r, lr, step, loss=None, stream=None):
         _check_s(lib().ms_surrogate_train_step(self.h, q.shape[0], _dp(q), _dp(L), _dp(r),

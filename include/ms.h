@@ -149,6 +149,33 @@ ms_status ms_model_create(const ms_model_desc *desc, ms_model **out);
 /* Free the model and its device tables. NULL-safe. */
 void ms_model_destroy(ms_model *m);
 
+/* Step schedules (the same operations in the same order, so the same
+ * results bit for bit; they differ in speed):
+ *  MS_SCHED_FUSED: one kernel per rollout, one wavefront per env with the
+ *    whole step's intermediates in LDS and the state on chip across steps;
+ *  MS_SCHED_SPLIT: three kernels per physics step (kinematics and dynamics;
+ *    muscles, one 256-thread workgroup per env; LTDL factorisation, solve
+ *    and update), exchanging per-env intermediates (about 26 KB per env at
+ *    80 DoF / 700 muscles) through a device workspace the model owns;
+ *    smaller LDS blocks keep more envs resident per CU;
+ *  MS_SCHED_AUTO (default): SPLIT for models whose fused step keeps at most
+ *    four envs resident per CU (one wavefront per SIMD), else FUSED.
+ * Stage outputs (ms_step_stages) and ms_geometry always use the fused
+ * kernel. Set before use; MS_E_ARG for an unknown value. */
+#define MS_SCHED_AUTO 0
+#define MS_SCHED_FUSED 1
+#define MS_SCHED_SPLIT 2
+ms_status ms_model_set_schedule(ms_model *m, int32_t schedule);
+/* The schedule the model's steps use now (MS_SCHED_FUSED or MS_SCHED_SPLIT). */
+ms_status ms_model_get_schedule(const ms_model *m, int32_t *schedule);
+/* Reserve the split schedule's workspace for up to n_env envs now
+ * (synchronous allocation). A step or rollout on the split schedule with
+ * more envs than reserved grows it first (allocating and synchronising);
+ * inside a stream capture that growth is refused with MS_E_ARG, so reserve
+ * before capturing. All buffers of a growth are taken or none (MS_E_ALLOC
+ * keeps the previous workspace). */
+ms_status ms_model_reserve(ms_model *m, int32_t n_env);
+
 ms_status ms_model_info_get(const ms_model *m, ms_model_info *out);
 
 /* One step for n_env envs, in place on the caller's device state, reading

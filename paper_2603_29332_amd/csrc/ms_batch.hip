@@ -124,6 +124,12 @@ std::vector<unsigned char> make_key(const ms_batch *b, const ms_batch_state *s,
 ms_status capture(ms_batch *b, const ms_batch_state *s, const ms_excitation *exc, int n_steps,
                   const ms_step_opts *opts) {
   drop_graph(b);
+  // split-schedule workspaces are allocated before the capture, never in it
+  for (size_t i = 0; i < b->models.size(); ++i) {
+    if (effective_schedule(b->models[i]) != MS_SCHED_SPLIT) continue;
+    const ms_status rs = reserve_split(b->models[i], b->n_env[i], nullptr);
+    if (rs != MS_OK) return bfail(rs, std::string("model ") + std::to_string(i) + ": " + ms_last_error());
+  }
   ms_status r = bhip(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal),
                      "begin capture");
   if (r != MS_OK) return r;

@@ -917,8 +917,8 @@ ms_status ms_policy_rollout(ms_model *m, ms_policy *p, ms_surrogate *sg, int32_t
         rr.step0 = t + j;
         steps = 1;
       }
-      hipError_t e = launch(m, rr, n_env, steps, st);
-      if (e != hipSuccess) return hipst(e, "policy rollout step");
+      r = run_steps(m, rr, n_env, steps, st);
+      if (r != MS_OK) return sfail(r, std::string("policy rollout step: ") + ms_last_error());
     }
   }
   return MS_OK;

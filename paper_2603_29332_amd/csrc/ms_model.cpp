@@ -147,6 +147,24 @@ ms_status build_tables(const ms_model_desc *d, Tables *t, std::string *msg) {
   }
   t->subb_start[n] = (int)t->subb.size();
   t->subc_start[n] = (int)t->subc.size();
+  // composite inertias: nodes whose subtrees hold the same bodies (a body's
+  // node and the massless hinge nodes above it within one joint) share one
+  // slot, represented by the first such node
+  t->node_ci.assign(n, -1);
+  for (int i = 0; i < n; ++i) {
+    for (int c = 0; c < (int)t->ci_node.size() && t->node_ci[i] < 0; ++c) {
+      const int r = t->ci_node[c];
+      if (std::equal(t->subb.begin() + t->subb_start[i], t->subb.begin() + t->subb_start[i + 1],
+                     t->subb.begin() + t->subb_start[r], t->subb.begin() + t->subb_start[r + 1]) &&
+          t->subb_start[i + 1] - t->subb_start[i] == t->subb_start[r + 1] - t->subb_start[r])
+        t->node_ci[i] = c;
+    }
+    if (t->node_ci[i] < 0) {
+      t->node_ci[i] = (int)t->ci_node.size();
+      t->ci_node.push_back(i);
+    }
+  }
+  t->n_ci = (int)t->ci_node.size();
 
   // DoFs and the DoF tree (each DoF's parent is the previous DoF on the path)
   std::vector<int> dof_parent(nv, -1);
@@ -280,6 +298,13 @@ ms_status build_tables(const ms_model_desc *d, Tables *t, std::string *msg) {
       for (size_t e = 0; e < v.size(); ++e) w[e / 4] |= (v[e] & 0xFF) << (8 * (e % 4));
       return w;
     };
+    std::vector<int32_t> dof_ci(nv);
+    for (int j = 0; j < nv; ++j) dof_ci[j] = t->node_ci[t->dof_node[j]];
+    // sections in the order: kinematics and dynamics only, then the mass
+    // pattern (path) and row starts both use, then the factorisation only;
+    // so the kinematics/dynamics kernel stages words [0, lt_front_end) and
+    // the factorisation kernel words [lt_back_begin, end), 16-byte aligned
+    auto align4 = [&]() { b.resize((b.size() + 3) / 4 * 4, 0); };
     section(&t->lt_tlev, t->level_start);
     section(&t->lt_tnode, tnode);
     section(&t->lt_subb_start, t->subb_start);
@@ -287,17 +312,23 @@ ms_status build_tables(const ms_model_desc *d, Tables *t, std::string *msg) {
     section(&t->lt_subb, bytes(t->subb));
     section(&t->lt_subc, bytes(t->subc));
     section(&t->lt_nnzrow, bytes(t->nnz_row));
+    section(&t->lt_cinode, bytes(t->ci_node));
+    section(&t->lt_dofci, bytes(dof_ci));
+    align4();
+    t->lt_back_begin = (int)b.size();
+    section(&t->lt_path, path8);
+    t->lt_front_end = (int)b.size();
+    section(&t->lt_rs, rs);
     section(&t->lt_hent_start, hent_start);
     section(&t->lt_hlev_start, t->hlev_start);
     section(&t->lt_hent, hent);
     section(&t->lt_hdof, hdof);
     section(&t->lt_desc, desc);
     section(&t->lt_drange, drange);
-    section(&t->lt_rs, rs);
     section(&t->lt_trow, trow);
     section(&t->lt_tpair, tpair);
-    section(&t->lt_path, path8);
-    b.resize((b.size() + 3) / 4 * 4, 0);  // 16-byte multiple
+    align4();
+    t->lt_front_end = (t->lt_front_end + 3) / 4 * 4;
   }
 
   // muscles
@@ -450,15 +481,54 @@ ms_status build_tables(const ms_model_desc *d, Tables *t, std::string *msg) {
   t->off_rhs = take(8 * nv);
   t->off_x = take(8 * nv);
   t->off_H = take(8 * t->nnz);
-  int u_rnea = 4 * 6 * (2 * n + t->n_body + n);            // V, A, f_b, F_n
-  int u_crba = 8 * 10 * (n + t->n_body) + 8 * 6 * nv;     // bodies, composites, F_j
-  int u_mus = 4 * 5 * nm;                                  // r[3], F, c per muscle
+  const int u_rnea = 4 * 6 * (2 * n + t->n_body + n);          // V, A, f_b, F_n
+  const int u_crba = 8 * 10 * (t->n_ci + t->n_body) + 8 * 6 * nv;  // bodies, composites, F_j
+  const int u_mus = 4 * 5 * nm;                                // r[3], F, c per muscle
   int u = std::max(u_rnea, std::max(u_crba, u_mus));
   t->off_scr = take(u);
   t->off_V = t->off_scr;
   t->off_A = t->off_V + 4 * 6 * n;
   t->off_F = t->off_A + 4 * 6 * n;
   t->lds_bytes = off;
+
+  // The split schedule's three kernels (one env per wavefront for the
+  // kinematics/dynamics and the factorisation kernels, one env per
+  // 256-thread workgroup for the muscle kernel), each with its own layout.
+  SplitLayout &L = t->split;
+  off = 0;
+  L.f_q = take(4 * nq);
+  L.f_qd = take(4 * nv);
+  L.f_R = take(4 * 12 * n);
+  L.f_S = take(4 * 6 * nv);
+  L.f_con = take(4 * 16 * std::max(t->n_con, 1));
+  L.f_scr = take(std::max(u_rnea, u_crba));
+  L.f_bytes = off;
+  off = 0;
+  L.b_q = take(4 * nq);
+  L.b_qd = take(4 * nv);
+  L.b_rhs = take(8 * nv);
+  L.b_x = take(8 * nv);
+  L.b_invd = take(8 * nv);
+  L.b_H = take(8 * t->nnz);
+  L.b_bytes = off;
+  off = 0;
+  L.m_R = take(4 * 12 * n);
+  L.m_S = take(4 * 6 * nv);
+  L.m_q = take(4 * nq);
+  L.m_qd = take(4 * nv);
+  L.m_scr = take(std::max(u_mus, 4));
+  L.m_bytes = off;
+  // per-env workspace in device memory (bytes, 256-aligned arrays)
+  auto wsz = [](size_t b) { return (b + 255) / 256 * 256; };
+  L.ws_frames = 4 * 12 * n;
+  L.ws_S = 4 * 6 * nv;
+  L.ws_H = 8 * (size_t)t->nnz;
+  L.ws_rhs = 8 * nv;
+  L.ws_tau = 4 * nv;
+  L.ws_dsum = 8 * std::max(t->n_dent, 1);
+  L.ws_act = 4 * std::max(nm, 1);
+  L.ws_env_bytes = wsz(L.ws_frames) + wsz(L.ws_S) + wsz(L.ws_H) + wsz(L.ws_rhs) +
+                   wsz(L.ws_tau) + wsz(L.ws_dsum) + wsz(L.ws_act) + 2 * 4;
   return MS_OK;
 }
 

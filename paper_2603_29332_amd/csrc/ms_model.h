@@ -19,6 +19,22 @@ constexpr int kMaxCon = 64;
 constexpr int kMaxDepth = 64;
 constexpr int kWave = 64;
 
+// LDS layouts (byte offsets into one env's block) of the split schedule's
+// kernels and the sizes of the per-env device workspace between them.
+struct SplitLayout {
+  // kinematics and dynamics kernel
+  int f_q = 0, f_qd = 0, f_R = 0, f_S = 0, f_con = 0, f_scr = 0, f_bytes = 0;
+  // factorisation kernel
+  int b_q = 0, b_qd = 0, b_rhs = 0, b_x = 0, b_invd = 0, b_H = 0, b_bytes = 0;
+  // muscle kernel
+  int m_R = 0, m_S = 0, m_q = 0, m_qd = 0, m_scr = 0, m_bytes = 0;
+  // per-env bytes of each workspace array: node frames, motion subspaces,
+  // mass matrix (FP64), right-hand side (FP64), muscle torques, muscle
+  // damping sums (FP64), new activations
+  size_t ws_frames = 0, ws_S = 0, ws_H = 0, ws_rhs = 0, ws_tau = 0, ws_dsum = 0, ws_act = 0;
+  size_t ws_env_bytes = 0;
+};
+
 // Offsets (in elements of the named type) of every table inside one device
 // buffer; the kernel receives base pointer + this struct.
 struct Tables {
@@ -35,6 +51,9 @@ struct Tables {
   std::vector<float> body_mass, body_com, body_inertia;  // [b], [b][3], [b][3]
   // per node: bodies and contacts in its subtree (CSR)
   std::vector<int32_t> subb_start, subb, subc_start, subc;
+  // composite-inertia slots: node -> slot, slot -> its representative node
+  std::vector<int32_t> node_ci, ci_node;
+  int n_ci = 0;
   // contacts
   std::vector<int32_t> con_node;
   std::vector<float> con_pos, con_radius;
@@ -83,11 +102,13 @@ struct Tables {
   std::vector<int32_t> lt;
   int lt_hent_start = 0, lt_hlev_start = 0, lt_hent = 0, lt_hdof = 0,
       lt_desc = 0, lt_drange = 0, lt_rs = 0, lt_trow = 0, lt_tpair = 0, lt_path = 0, lt_tlev = 0, lt_tnode = 0,
-      lt_subb_start = 0, lt_subc_start = 0, lt_subb = 0, lt_subc = 0, lt_nnzrow = 0;
+      lt_subb_start = 0, lt_subc_start = 0, lt_subb = 0, lt_subc = 0, lt_nnzrow = 0,
+      lt_cinode = 0, lt_dofci = 0, lt_front_end = 0, lt_back_begin = 0;
   // LDS layout (byte offsets into the per-env LDS block)
   int off_q = 0, off_qd = 0, off_R = 0, off_P = 0, off_S = 0, off_V = 0,
       off_A = 0, off_F = 0, off_con = 0, off_rhs = 0, off_H = 0, off_x = 0,
       off_scr = 0, off_flag = 0, lds_bytes = 0;
+  SplitLayout split;
   int n_levels_dof = 0;
 };
 

@@ -52,12 +52,83 @@ ms_status check_opts(const ms_step_opts *o) {
 }
 }  // namespace
 
-hipError_t launch(const ms_model *m, const ms::KRun &r, int n_env, int n_steps, hipStream_t st) {
+int effective_schedule(const ms_model *m) {
+  if (m->schedule != MS_SCHED_AUTO) return m->schedule;
+  // split when the fused step keeps at most one wavefront per SIMD
+  const int W = ms::default_env_per_wg(m->t);
+  const size_t per_wg = m->t.lt.size() * 4 + (size_t)W * m->t.lds_bytes;
+  const int resident = W * (int)((160 * 1024) / per_wg);
+  return resident <= 4 ? MS_SCHED_SPLIT : MS_SCHED_FUSED;
+}
+
+ms_status reserve_split(ms_model *m, int n_env, hipStream_t st) {
+  if (n_env <= m->ws_cap) return MS_OK;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(st, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone)
+    return fail(MS_E_ARG, "the split step's workspace holds " + std::to_string(m->ws_cap) +
+                              " envs, fewer than " + std::to_string(n_env) +
+                              ": call ms_model_reserve before capturing");
+  const ms::SplitLayout &L = m->t.split;
+  const size_t E = (size_t)n_env;
+  const size_t sz[9] = {E * L.ws_frames, E * L.ws_S, E * L.ws_H, E * L.ws_rhs, E * L.ws_tau,
+                        E * L.ws_dsum, E * L.ws_act, E * 4, E * 4};
+  void *p[9] = {};
+  for (int i = 0; i < 9; ++i) {
+    if (hipMalloc(&p[i], std::max<size_t>(sz[i], 4)) != hipSuccess) {
+      for (int j = 0; j < i; ++j) (void)hipFree(p[j]);
+      return fail(MS_E_ALLOC, "split step workspace allocation failed (" + std::to_string(n_env) +
+                                  " envs)");
+    }
+  }
+  for (int i = 0; i < 9; ++i) m->ws_owned.push_back(p[i]);
+  ms::KSplit &w = m->ks;
+  w.frames = (float *)p[0];
+  w.S = (float *)p[1];
+  w.H = (double *)p[2];
+  w.rhs = (double *)p[3];
+  w.tau = (float *)p[4];
+  w.dsum = (double *)p[5];
+  w.actn = (float *)p[6];
+  w.flag = (int *)p[7];
+  w.mflag = (int *)p[8];
+  m->ws_cap = n_env;
+  return MS_OK;
+}
+
+hipError_t launch(ms_model *m, const ms::KRun &r, int n_env, int n_steps, hipStream_t st) {
   const int nvia = m->t.n_via_max;
-  if (nvia <= 2) return ms::launch_nvia<2>(m->t, m->k, r, n_env, n_steps, st);
-  if (nvia <= 4) return ms::launch_nvia<4>(m->t, m->k, r, n_env, n_steps, st);
-  if (nvia <= 6) return ms::launch_nvia<6>(m->t, m->k, r, n_env, n_steps, st);
-  return ms::launch_nvia<8>(m->t, m->k, r, n_env, n_steps, st);
+  if (r.stages || effective_schedule(m) == MS_SCHED_FUSED) {
+    if (nvia <= 2) return ms::launch_nvia<2>(m->t, m->k, r, n_env, n_steps, st);
+    if (nvia <= 4) return ms::launch_nvia<4>(m->t, m->k, r, n_env, n_steps, st);
+    if (nvia <= 6) return ms::launch_nvia<6>(m->t, m->k, r, n_env, n_steps, st);
+    return ms::launch_nvia<8>(m->t, m->k, r, n_env, n_steps, st);
+  }
+  if (reserve_split(m, n_env, st) != MS_OK) return hipErrorOutOfMemory;
+  const ms::KSplit &w = m->ks;
+  if (!m->w_front) ms::split_env_per_wg(m->k, w, &m->w_front, &m->w_back);
+  const int mpt = (m->t.n_mus + 255) / 256;
+  for (int s = 0; s < n_steps; ++s) {
+    hipError_t e = ms::launch_front(m->k, r, w, m->w_front, s, st);
+    if (e == hipSuccess) {
+      if (nvia <= 2) e = ms::launch_muscle<2>(m->k, r, w, mpt, s, st);
+      else if (nvia <= 4) e = ms::launch_muscle<4>(m->k, r, w, mpt, s, st);
+      else if (nvia <= 6) e = ms::launch_muscle<6>(m->k, r, w, mpt, s, st);
+      else e = ms::launch_muscle<8>(m->k, r, w, mpt, s, st);
+    }
+    if (e == hipSuccess) e = ms::launch_back(m->k, r, w, m->w_back, s, st);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+ms_status run_steps(ms_model *m, const ms::KRun &r, int n_env, int n_steps, hipStream_t st) {
+  if (!r.stages && effective_schedule(m) == MS_SCHED_SPLIT) {
+    const ms_status s = reserve_split(m, n_env, st);
+    if (s != MS_OK) return s;
+  }
+  const hipError_t e = launch(m, r, n_env, n_steps, st);
+  if (e != hipSuccess) return fail(MS_E_HIP, std::string("kernel launch: ") + hipGetErrorString(e));
+  return MS_OK;
 }
 
 extern "C" {
@@ -154,12 +225,32 @@ ms_status ms_model_create(const ms_model_desc *desc, ms_model **out) {
   k.lt_path = t.lt_path; k.lt_tlev = t.lt_tlev; k.lt_tnode = t.lt_tnode;
   k.lt_subb_start = t.lt_subb_start; k.lt_subc_start = t.lt_subc_start; k.lt_subb = t.lt_subb;
   k.lt_subc = t.lt_subc; k.lt_nnzrow = t.lt_nnzrow;
+  k.lt_cinode = t.lt_cinode; k.lt_dofci = t.lt_dofci;
+  k.lt_front_end = t.lt_front_end; k.lt_back_begin = t.lt_back_begin;
+  k.n_ci = t.n_ci;
   P_(hlev_start, o_hs, int); P_(hlev_dof, o_hd, int);
 #undef P_
   k.off_flag = t.off_flag; k.off_q = t.off_q; k.off_qd = t.off_qd; k.off_R = t.off_R;
   k.off_P = t.off_P; k.off_S = t.off_S; k.off_con = t.off_con; k.off_rhs = t.off_rhs;
   k.off_x = t.off_x; k.off_H = t.off_H; k.off_scr = t.off_scr; k.lds_env = t.lds_bytes; k.off_V = t.off_V;
   k.off_A = t.off_A; k.off_F = t.off_F;
+  {
+    const ms::SplitLayout &L = t.split;
+    ms::KSplit &w = m->ks;
+    w.fr_stride = (int)(L.ws_frames / 4);
+    w.S_stride = (int)(L.ws_S / 4);
+    w.H_stride = (int)(L.ws_H / 8);
+    w.rhs_stride = (int)(L.ws_rhs / 8);
+    w.tau_stride = (int)(L.ws_tau / 4);
+    w.dsum_stride = (int)(L.ws_dsum / 8);
+    w.act_stride = (int)(L.ws_act / 4);
+    w.f_q = L.f_q; w.f_qd = L.f_qd; w.f_R = L.f_R; w.f_S = L.f_S; w.f_con = L.f_con;
+    w.f_scr = L.f_scr; w.f_bytes = L.f_bytes;
+    w.b_q = L.b_q; w.b_qd = L.b_qd; w.b_rhs = L.b_rhs; w.b_x = L.b_x; w.b_invd = L.b_invd;
+    w.b_H = L.b_H; w.b_bytes = L.b_bytes;
+    w.m_R = L.m_R; w.m_S = L.m_S; w.m_q = L.m_q; w.m_qd = L.m_qd; w.m_scr = L.m_scr;
+    w.m_bytes = L.m_bytes;
+  }
   *out = m;
   return MS_OK;
 }
@@ -167,7 +258,30 @@ ms_status ms_model_create(const ms_model_desc *desc, ms_model **out) {
 void ms_model_destroy(ms_model *m) {
   if (!m) return;
   if (m->dbuf) (void)hipFree(m->dbuf);
+  for (void *p : m->ws_owned) (void)hipFree(p);
   delete m;
+}
+
+ms_status ms_model_set_schedule(ms_model *m, int32_t schedule) {
+  g_err.clear();
+  if (!m) return fail(MS_E_ARG, "model is NULL");
+  if (schedule != MS_SCHED_AUTO && schedule != MS_SCHED_FUSED && schedule != MS_SCHED_SPLIT)
+    return fail(MS_E_ARG, "unknown schedule");
+  m->schedule = schedule;
+  return MS_OK;
+}
+
+ms_status ms_model_get_schedule(const ms_model *m, int32_t *schedule) {
+  g_err.clear();
+  if (!m || !schedule) return fail(MS_E_ARG, "NULL argument");
+  *schedule = effective_schedule(m);
+  return MS_OK;
+}
+
+ms_status ms_model_reserve(ms_model *m, int32_t n_env) {
+  g_err.clear();
+  if (!m || n_env <= 0) return fail(MS_E_ARG, "NULL model or n_env <= 0");
+  return reserve_split(m, n_env, nullptr);
 }
 
 ms_status ms_model_info_get(const ms_model *m, ms_model_info *o) {
@@ -219,7 +333,7 @@ ms_status ms_step_batch(ms_model *m, int32_t n_env, float *q, float *qd, float *
   r.q = q; r.qd = qd; r.act = act; r.status = status; r.u = u; r.n_env = n_env;
   r.dt = opts->dt; r.contact = opts->contact;
   r.exc = ms::EXC_ARRAY;
-  return hip_status(launch(m, r, n_env, 1, (hipStream_t)stream));
+  return run_steps(m, r, n_env, 1, (hipStream_t)stream);
 }
 
 ms_status ms_rollout(ms_model *m, int32_t n_env, float *q, float *qd, float *act,
@@ -258,7 +372,7 @@ ms_status rollout_impl(ms_model *m, int32_t n_env, float *q, float *qd, float *a
       return fail(MS_E_ARG, "unknown excitation kind");
   }
   r.exc = exc->kind;
-  return hip_status(launch(m, r, n_env, n_steps, st));
+  return run_steps(m, r, n_env, n_steps, st);
 }
 
 extern "C" {
@@ -288,7 +402,7 @@ ms_status ms_rollout_surrogate(ms_model *m, ms_surrogate *sg, int32_t n_env, flo
     r.rho = exc->rho; r.s = exc->s; r.mean = exc->mean;
     r.exc = exc->kind;
     r.geomY = Y; r.fb_tol = tol; r.fb_count = fallback_count;
-    s = hip_status(launch(m, r, n_env, 1, st));
+    s = run_steps(m, r, n_env, 1, st);
     if (s != MS_OK) return s;
   }
   return MS_OK;

@@ -1,11 +1,19 @@
 // ms_step_kernel.h -- the batched musculoskeletal forward-dynamics step on gfx950.
 //
-// One wavefront (64 lanes) advances one environment. The environment's
-// kinematic tree (node frames, motion subspaces, spatial velocities and
-// accelerations), its contact state and its tree-sparse FP64 mass matrix
-// live in LDS; muscle work is spread over the lanes (lane l owns muscles
-// l, l+64, ...), tree work over nodes/DoFs, and the LTDL factorisation over
-// the (ancestor, ancestor) pairs of each eliminated DoF.
+// The step's stages as device functions, composed two ways:
+//  - the fused step (k_step): one wavefront (64 lanes) advances one
+//    environment through whole rollouts with its kinematic tree (node
+//    frames, motion subspaces, spatial velocities and accelerations),
+//    contact state and tree-sparse FP64 mass matrix in LDS;
+//  - the split step: per physics step a kinematics/dynamics kernel (one
+//    wavefront per env), a muscle kernel (one 256-thread workgroup per env)
+//    and a factorisation kernel (one wavefront per env), exchanging per-env
+//    intermediates through a device workspace; each kernel's smaller LDS
+//    block keeps more envs resident per CU. Both compositions perform the
+//    same operations in the same order, so their results are identical.
+// Muscle work is spread over a team's threads (thread t owns muscles t,
+// t + n, ...), tree work over nodes/DoFs, and the LTDL factorisation over
+// the entries of each height level.
 //
 // All spatial quantities are expressed in world axes about a reference point
 // O that is the root origin of a floating model (the world origin for a
@@ -244,10 +252,795 @@ __device__ __forceinline__ float muscle_geometry(const KModel &M, int m, int Pg,
   return L;
 }
 
-// ------------------------------------------------------------------ kernel
-// One wavefront steps one env n_steps times. SURR: muscle geometry from the
-// surrogate's predictions with the per-env fallback check (a kernel of its
-// own, so the exact kernel carries none of it).
+// ------------------------------------------------------------ work teams
+// The threads that share one env's work: a wavefront (the fused step, the
+// kinematics/dynamics and the factorisation kernels) or a 256-thread
+// workgroup (the muscle kernel). t is the thread's index in the team.
+struct WaveTeam {
+  int t;
+  static constexpr int n = 64;
+  __device__ __forceinline__ void sync() const { wave_sync(); }
+  __device__ __forceinline__ bool any(bool v) const { return __any(v); }
+};
+struct BlockTeam {
+  int t;
+  static constexpr int n = 256;
+  __device__ __forceinline__ void sync() const { __syncthreads(); }
+  __device__ __forceinline__ bool any(bool v) const { return __syncthreads_or(v ? 1 : 0) != 0; }
+};
+
+// ------------------------------------------------------------ stages
+// Forward kinematics, motion subspaces, spatial velocities V and bias
+// accelerations A of every node. O = root origin (floating) or world origin
+// (fixed base).
+__device__ __forceinline__ void stage_fk(const KModel &M, int lane, const int *tlev, const int *tnode,
+                                         const float *q, const float *qd, float *Rl, float *Sl,
+                                         float *Vl, float *Al, V3 O, V3 g) {
+  const int nn = M.n_node;
+  // (1) every node's joint transform in parallel: rotation jrot Rot(axis, q)
+  // and offset parked in the node's frame slot, the axis jrot*axis in its A
+  // slot; the floating root is finished here
+  for (int i = lane; i < nn; i += 64) {
+    const int jt = M.jtype[i];
+    float *F = Rl + 12 * i;
+    const int da = M.dadr[i];
+    if (jt == 2) {
+      const float *x = q + M.qadr[i] + 3;
+      float nrm = sqrtf(x[0] * x[0] + x[1] * x[1] + x[2] * x[2] + x[3] * x[3]);
+      float w = x[0] / nrm, a = x[1] / nrm, b = x[2] / nrm, c = x[3] / nrm;
+      float *R = F;
+      R[0] = 1 - 2 * (b * b + c * c); R[1] = 2 * (a * b - w * c); R[2] = 2 * (a * c + w * b);
+      R[3] = 2 * (a * b + w * c); R[4] = 1 - 2 * (a * a + c * c); R[5] = 2 * (b * c - w * a);
+      R[6] = 2 * (a * c - w * b); R[7] = 2 * (b * c + w * a); R[8] = 1 - 2 * (a * a + b * b);
+      st3(F + 9, v3(0.f, 0.f, 0.f));
+      for (int kk = 0; kk < 3; ++kk) {
+        float *S = Sl + 6 * (da + kk);
+        S[0] = S[1] = S[2] = 0.f;
+        S[3] = kk == 0; S[4] = kk == 1; S[5] = kk == 2;
+        float *S2 = Sl + 6 * (da + 3 + kk);
+        S2[0] = R[kk]; S2[1] = R[3 + kk]; S2[2] = R[6 + kk];
+        S2[3] = S2[4] = S2[5] = 0.f;
+      }
+      V3 v = ld3(qd + da);
+      V3 ww = mulR(R, ld3(qd + da + 3));
+      float *V = Vl + 6 * i, *A = Al + 6 * i;
+      st3(V, ww);
+      st3(V + 3, v);
+      st3(A, v3(0.f, 0.f, 0.f));
+      st3(A + 3, cross(v, ww) - g);
+      continue;
+    }
+    const float *E = M.jrot + 9 * i;
+    const V3 ax = ld3(M.axis + 3 * i);
+    const float qi = q[M.qadr[i]];
+    const V3 al = mulR(E, ax);
+    V3 t = ld3(M.jpos + 3 * i);
+    if (jt == 0) {
+      float sn, cs;
+      sincosf(qi, &sn, &cs);
+      const float vc = 1.0f - cs;
+      const float Q[9] = {cs + ax.x * ax.x * vc, ax.x * ax.y * vc - ax.z * sn, ax.x * ax.z * vc + ax.y * sn,
+                          ax.y * ax.x * vc + ax.z * sn, cs + ax.y * ax.y * vc, ax.y * ax.z * vc - ax.x * sn,
+                          ax.z * ax.x * vc - ax.y * sn, ax.z * ax.y * vc + ax.x * sn, cs + ax.z * ax.z * vc};
+      for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c)
+          F[3 * r + c] = E[3 * r] * Q[c] + E[3 * r + 1] * Q[3 + c] + E[3 * r + 2] * Q[6 + c];
+    } else {
+      for (int e = 0; e < 9; ++e) F[e] = E[e];
+      t = t + qi * al;
+    }
+    st3(F + 9, t);
+    st3(Al + 6 * i, al);
+  }
+  wave_sync();
+  // (2) compose down the tree level by level, reading only LDS:
+  // R = R_p Lr, P = P_p + R_p t, axis = R_p al, S, V = V_p + S qd,
+  // A = A_p + V_p x (S qd)
+  for (int l = 0; l < M.n_level; ++l) {
+    const int b0 = tlev[l], b1 = tlev[l + 1];
+    for (int k = b0 + lane; k < b1; k += 64) {
+      const int info = tnode[k], i = info >> 18;
+      const int jt = info & 3;
+      if (jt == 2) continue;
+      const int p = (info >> 2 & 0xFF) - 1, da = info >> 10 & 0xFF;
+      float *F = Rl + 12 * i;
+      // frames are 16-byte aligned 12-float records, V and A 8-byte aligned
+      // 6-float records: vector LDS accesses
+      const float4 f0 = ((const float4 *)F)[0], f1 = ((const float4 *)F)[1],
+                   f2 = ((const float4 *)F)[2];
+      const float Lr[9] = {f0.x, f0.y, f0.z, f0.w, f1.x, f1.y, f1.z, f1.w, f2.x};
+      const V3 t = v3(f2.y, f2.z, f2.w);
+      const float2 a0 = ((const float2 *)(Al + 6 * i))[0], a1 = ((const float2 *)(Al + 6 * i))[1];
+      const V3 al = v3(a0.x, a0.y, a1.x);
+      float Rp[9];
+      V3 Pp, wp, vp, ap, lp;
+      if (p >= 0) {
+        const float4 *P4 = (const float4 *)(Rl + 12 * p);
+        const float4 r0 = P4[0], r1 = P4[1], r2 = P4[2];
+        Rp[0] = r0.x; Rp[1] = r0.y; Rp[2] = r0.z; Rp[3] = r0.w; Rp[4] = r1.x; Rp[5] = r1.y;
+        Rp[6] = r1.z; Rp[7] = r1.w; Rp[8] = r2.x;
+        Pp = v3(r2.y, r2.z, r2.w);
+        const float2 *V2 = (const float2 *)(Vl + 6 * p), *A2 = (const float2 *)(Al + 6 * p);
+        const float2 v0 = V2[0], v1 = V2[1], v2 = V2[2], b0 = A2[0], b1 = A2[1], b2 = A2[2];
+        wp = v3(v0.x, v0.y, v1.x); vp = v3(v1.y, v2.x, v2.y);
+        ap = v3(b0.x, b0.y, b1.x); lp = v3(b1.y, b2.x, b2.y);
+      } else {
+        for (int e = 0; e < 9; ++e) Rp[e] = (e % 4 == 0) ? 1.f : 0.f;
+        Pp = v3(0.f, 0.f, 0.f) - O;
+        wp = vp = ap = v3(0.f, 0.f, 0.f);
+        lp = v3(0.f, 0.f, 0.f) - g;
+      }
+      float Rn9[9];
+      for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c)
+          Rn9[3 * r + c] = Rp[3 * r] * Lr[c] + Rp[3 * r + 1] * Lr[3 + c] + Rp[3 * r + 2] * Lr[6 + c];
+      const V3 Pi = Pp + mulR(Rp, t);
+      const V3 ah = mulR(Rp, al);
+      ((float4 *)F)[0] = make_float4(Rn9[0], Rn9[1], Rn9[2], Rn9[3]);
+      ((float4 *)F)[1] = make_float4(Rn9[4], Rn9[5], Rn9[6], Rn9[7]);
+      ((float4 *)F)[2] = make_float4(Rn9[8], Pi.x, Pi.y, Pi.z);
+      V3 sw, sv;
+      if (jt == 0) {
+        sw = ah;
+        sv = cross(Pi, ah);
+      } else {
+        sw = v3(0.f, 0.f, 0.f);
+        sv = ah;
+      }
+      float *S = Sl + 6 * da;
+      st3(S, sw);
+      st3(S + 3, sv);
+      const float qdi = qd[da];
+      const V3 xw = qdi * sw, xv = qdi * sv;  // S qd
+      const V3 vw = wp + xw, vv = vp + xv;
+      const V3 aw = ap + cross(wp, xw), av = lp + cross(wp, xv) + cross(vp, xw);
+      float2 *V2 = (float2 *)(Vl + 6 * i), *A2 = (float2 *)(Al + 6 * i);
+      V2[0] = make_float2(vw.x, vw.y); V2[1] = make_float2(vw.z, vv.x); V2[2] = make_float2(vv.y, vv.z);
+      A2[0] = make_float2(aw.x, aw.y); A2[1] = make_float2(aw.z, av.x); A2[2] = make_float2(av.y, av.z);
+    }
+    wave_sync();
+  }
+}
+
+// Penalty contact of every sphere: a record per sphere of 16 floats
+// (active, contact point, wrench about O, force, friction and damping slopes).
+__device__ __forceinline__ void stage_contacts(const KModel &M, int lane, const float *Rl,
+                                               const float *Vl, float *Cl, V3 O, float dt,
+                                               int contact) {
+  for (int c = lane; c < M.n_con; c += 64) {
+    float *C = Cl + 16 * c;
+    const int b = M.con_node[c];
+    V3 w = frame_apply(Rl + 12 * b, ld3(M.con_pos + 3 * c));
+    const float rho = M.con_radius[c];
+    const float pen = rho - (w.z + O.z);
+    for (int e = 0; e < 16; ++e) C[e] = 0.f;
+    if (contact && pen > 0.f) {
+      V3 cp = w - v3(0.f, 0.f, rho);
+      V3 vel = ld3(Vl + 6 * b + 3) + cross(ld3(Vl + 6 * b), cp);
+      // spring taken linearly implicitly over the step: damping c + dt k
+      const float ceff = M.cc + dt * M.kc;
+      float fn = fmaxf(0.f, M.kc * pen - ceff * vel.z);
+      float s2 = vel.x * vel.x + vel.y * vel.y + M.vs * M.vs;
+      float s = sqrtf(s2);
+      V3 f = v3(-M.mu * fn * vel.x / s, -M.mu * fn * vel.y / s, fn);
+      C[0] = 1.f;
+      st3(C + 1, cp);
+      st3(C + 4, cross(cp, f));
+      st3(C + 7, f);
+      if (fn > 0.f) {
+        float gg = M.mu * fn / s;
+        C[10] = gg * (1.f - vel.x * vel.x / s2);
+        C[11] = -gg * vel.x * vel.y / s2;
+        C[12] = gg * (1.f - vel.y * vel.y / s2);
+        C[13] = ceff;
+      }
+    }
+  }
+}
+
+// Recursive Newton-Euler bias forces with the contact wrenches injected on
+// the backward sum: rhs[j] = -(C - tau_ext)_j - b_j qd_j (o_bias, when
+// given, receives C - tau_ext).
+__device__ __forceinline__ void stage_rnea(const KModel &M, int lane, const float *Rl, const float *Pl,
+                                           const float *Vl, const float *Al, float *Fl,
+                                           const float *Cl, const float *Sl, const float *qd,
+                                           const int *sbs, const unsigned char *sbl, const int *scs,
+                                           const unsigned char *scl, double *rhs, float *o_bias) {
+  const int nn = M.n_node, nv = M.nv;
+  for (int b = lane; b < M.n_body; b += 64) {
+    const int i = M.body_node[b];
+    const float *R = Rl + 12 * i;
+    const float m = M.body_mass[b];
+    V3 c = mulR(R, ld3(M.body_com + 3 * b)) + ld3(Pl + 12 * i);
+    V3 h = m * c;
+    const float I0 = M.body_inertia[3 * b], I1 = M.body_inertia[3 * b + 1], I2 = M.body_inertia[3 * b + 2];
+    // I_O = R diag(I) R^T + m (|c|^2 1 - c c^T)
+    float Io[9];
+    const float cc = dot(c, c);
+    const float cv[3] = {c.x, c.y, c.z};
+    for (int r = 0; r < 3; ++r)
+      for (int s = 0; s < 3; ++s)
+        Io[3 * r + s] = R[3 * r] * I0 * R[3 * s] + R[3 * r + 1] * I1 * R[3 * s + 1] +
+                        R[3 * r + 2] * I2 * R[3 * s + 2] + m * ((r == s ? cc : 0.f) - cv[r] * cv[s]);
+    V3 w = ld3(Vl + 6 * i), v = ld3(Vl + 6 * i + 3);
+    V3 aw = ld3(Al + 6 * i), al = ld3(Al + 6 * i + 3);
+    // I (w; v) = (I_O w + h x v; m v - h x w)
+    V3 Iaw = mulR(Io, aw) + cross(h, al), Ial = m * al - cross(h, aw);
+    V3 Ivw = mulR(Io, w) + cross(h, v), Ivl = m * v - cross(h, w);
+    // f = I a + v x* (I v), (w, v) x* (n, f) = (w x n + v x f, w x f)
+    V3 fw = Iaw + cross(w, Ivw) + cross(v, Ivl);
+    V3 fl = Ial + cross(w, Ivl);
+    st3(Fl + 6 * b, fw);
+    st3(Fl + 6 * b + 3, fl);
+  }
+  wave_sync();
+  float *Fn = Fl + 6 * M.n_body;
+  for (int t = lane; t < 6 * nn; t += 64) {
+    const int n = t / 6, k = t % 6;
+    float s = 0.f;
+    for (int e = sbs[n]; e < sbs[n + 1]; ++e) s += Fl[6 * sbl[e] + k];
+    for (int e = scs[n]; e < scs[n + 1]; ++e) s -= Cl[16 * scl[e] + 4 + k];
+    Fn[t] = s;
+  }
+  wave_sync();
+  for (int j = lane; j < nv; j += 64) {
+    const float *S = Sl + 6 * j;
+    const float *F = Fn + 6 * M.dof_node[j];
+    float cb = S[0] * F[0] + S[1] * F[1] + S[2] * F[2] + S[3] * F[3] + S[4] * F[4] + S[5] * F[5];
+    if (o_bias) o_bias[j] = cb;
+    rhs[j] = (double)(-cb - M.damping[j] * qd[j]);
+  }
+  wave_sync();
+}
+
+// Composite-rigid-body mass matrix in FP64 with the contacts' implicit
+// damping, H[e] = S_i^T F_j for the stored entries e = (j, i) (H may be in
+// LDS or device memory). dmp receives this lane's joint damping (DoFs lane,
+// lane + 64), loaded early so that no entry waits on global memory.
+__device__ __forceinline__ void stage_crba(const KModel &M, int lane, const int *LT, const float *Rl,
+                                           const float *Pl, const float *Sl, const float *Cl,
+                                           unsigned char *scr, float dt, double *H, float dmp[2]) {
+  const int nv = M.nv;
+  const int *sbs = LT + M.lt_subb_start, *scs = LT + M.lt_subc_start;
+  const unsigned char *sbl = (const unsigned char *)(LT + M.lt_subb);
+  const unsigned char *scl = (const unsigned char *)(LT + M.lt_subc);
+  const unsigned char *cin = (const unsigned char *)(LT + M.lt_cinode);
+  const unsigned char *dci = (const unsigned char *)(LT + M.lt_dofci);
+  double *BI = (double *)scr;           // [n_body][10]: m, h, I_O (xx xy xz yy yz zz)
+  double *CI = BI + 10 * M.n_body;      // [n_ci][10], one per distinct subtree body set
+  double *FJ = CI + 10 * M.n_ci;        // [nv][6]
+#pragma unroll
+  for (int t = 0; t < 2; ++t) dmp[t] = lane + 64 * t < nv ? M.damping[lane + 64 * t] : 0.f;
+  for (int b = lane; b < M.n_body; b += 64) {
+    const int i = M.body_node[b];
+    const float *R = Rl + 12 * i;
+    const double m = M.body_mass[b];
+    V3 cf = mulR(R, ld3(M.body_com + 3 * b)) + ld3(Pl + 12 * i);
+    const double c[3] = {cf.x, cf.y, cf.z};
+    const double In[3] = {M.body_inertia[3 * b], M.body_inertia[3 * b + 1], M.body_inertia[3 * b + 2]};
+    double *o = BI + 10 * b;
+    o[0] = m;
+    o[1] = m * c[0]; o[2] = m * c[1]; o[3] = m * c[2];
+    const double cc = c[0] * c[0] + c[1] * c[1] + c[2] * c[2];
+    const int rr[6] = {0, 0, 0, 1, 1, 2}, ss[6] = {0, 1, 2, 1, 2, 2};
+    for (int e = 0; e < 6; ++e) {
+      int r = rr[e], s = ss[e];
+      double v = (double)R[3 * r] * In[0] * R[3 * s] + (double)R[3 * r + 1] * In[1] * R[3 * s + 1] +
+                 (double)R[3 * r + 2] * In[2] * R[3 * s + 2];
+      o[4 + e] = v + m * ((r == s ? cc : 0.0) - c[r] * c[s]);
+    }
+  }
+  wave_sync();
+  for (int t = lane; t < 10 * M.n_ci; t += 64) {
+    const int n = cin[t / 10], k = t % 10;
+    double s = 0.0;
+    for (int e = sbs[n]; e < sbs[n + 1]; ++e) s += BI[10 * sbl[e] + k];
+    CI[t] = s;
+  }
+  wave_sync();
+  for (int j = lane; j < nv; j += 64) {
+    const int n = M.dof_node[j];
+    const double *I = CI + 10 * dci[j];
+    const float *Sf = Sl + 6 * j;
+    const double w[3] = {Sf[0], Sf[1], Sf[2]}, v[3] = {Sf[3], Sf[4], Sf[5]};
+    const double m = I[0], h[3] = {I[1], I[2], I[3]};
+    const double Io[9] = {I[4], I[5], I[6], I[5], I[7], I[8], I[6], I[8], I[9]};
+    double f[6];
+    // (I_O w + h x v ; m v - h x w)
+    f[0] = Io[0] * w[0] + Io[1] * w[1] + Io[2] * w[2] + (h[1] * v[2] - h[2] * v[1]);
+    f[1] = Io[3] * w[0] + Io[4] * w[1] + Io[5] * w[2] + (h[2] * v[0] - h[0] * v[2]);
+    f[2] = Io[6] * w[0] + Io[7] * w[1] + Io[8] * w[2] + (h[0] * v[1] - h[1] * v[0]);
+    f[3] = m * v[0] - (h[1] * w[2] - h[2] * w[1]);
+    f[4] = m * v[1] - (h[2] * w[0] - h[0] * w[2]);
+    f[5] = m * v[2] - (h[0] * w[1] - h[1] * w[0]);
+    // implicit contact damping: dt * Phi^T D Phi S for contacts below
+    for (int e = scs[n]; e < scs[n + 1]; ++e) {
+      const float *C = Cl + 16 * scl[e];
+      if (C[0] == 0.f) continue;
+      const double cp[3] = {C[1], C[2], C[3]};
+      // point velocity of the contact for unit qd_j: v + w x cp
+      const double J[3] = {v[0] + w[1] * cp[2] - w[2] * cp[1], v[1] + w[2] * cp[0] - w[0] * cp[2],
+                           v[2] + w[0] * cp[1] - w[1] * cp[0]};
+      const double u0 = (double)C[10] * J[0] + (double)C[11] * J[1];
+      const double u1 = (double)C[11] * J[0] + (double)C[12] * J[1];
+      const double u2 = (double)C[13] * J[2];
+      const double dd = dt;
+      f[0] += dd * (cp[1] * u2 - cp[2] * u1);
+      f[1] += dd * (cp[2] * u0 - cp[0] * u2);
+      f[2] += dd * (cp[0] * u1 - cp[1] * u0);
+      f[3] += dd * u0;
+      f[4] += dd * u1;
+      f[5] += dd * u2;
+    }
+    for (int k = 0; k < 6; ++k) FJ[6 * j + k] = f[k];
+  }
+  wave_sync();
+  const unsigned char *rowb = (const unsigned char *)(LT + M.lt_nnzrow);
+  const unsigned char *pathb = (const unsigned char *)(LT + M.lt_path);
+  for (int e = lane; e < M.nnz; e += 64) {
+    const int j = rowb[e], i = pathb[e];
+    const float *Sf = Sl + 6 * i;
+    const double *f = FJ + 6 * j;
+    double h = (double)Sf[0] * f[0] + (double)Sf[1] * f[1] + (double)Sf[2] * f[2] +
+               (double)Sf[3] * f[3] + (double)Sf[4] * f[4] + (double)Sf[5] * f[5];
+    H[e] = h;
+  }
+  wave_sync();
+}
+
+// H_jj += dt b_j on the diagonals (the last entry of row j), with this
+// lane's damping values from stage_crba.
+__device__ __forceinline__ void add_joint_damping(const KModel &M, int lane, const int *LT, double *H,
+                                                  float dt, const float dmp[2]) {
+  const int *rs = LT + M.lt_rs;
+#pragma unroll
+  for (int t = 0; t < 2; ++t) {
+    const int j = lane + 64 * t;
+    if (j < M.nv) H[rs[j + 1] - 1] += (double)dt * dmp[t];
+  }
+  wave_sync();
+}
+
+// Excitations u of this thread's muscles (internal slots t + n k) for
+// absolute step `step`, advancing the smooth-noise state xar; returns true
+// when one of this thread's activations is not finite.
+template <int MPT, class Team>
+__device__ __forceinline__ bool excite(const KModel &M, const KRun &Rn, const Team &T, int env,
+                                       int step, const float act[MPT], float xar[MPT], float u[MPT]) {
+  const int nm = M.n_mus;
+  bool bad = false;
+  unsigned long long key = 0;
+  if (Rn.exc != EXC_ARRAY)
+    key = splitmix64(splitmix64(Rn.seed ^ (unsigned long long)env) ^ (unsigned long long)(Rn.step0 + step));
+#pragma unroll
+  for (int k = 0; k < MPT; ++k) {
+    const int mi = T.t + T.n * k;
+    u[k] = 0.0f;
+    if (mi < nm) {
+      const int mx = M.mus_ext[mi];
+      bad |= !isfinite(act[k]);
+      if (Rn.exc == EXC_ARRAY) {
+        u[k] = Rn.u ? Rn.u[((size_t)(Rn.u_hold ? 0 : step) * Rn.n_env + env) * nm + mx] : 0.0f;
+      } else if (Rn.exc == EXC_IID) {
+        u[k] = u24(splitmix64(key ^ (unsigned long long)mx), 40);
+      } else {
+        const AR1 r = ar1_step(key, mx, xar[k], Rn.rho, Rn.s, Rn.mean);
+        u[k] = r.u;
+        xar[k] = r.x;
+      }
+    }
+  }
+  return bad;
+}
+
+// Activation dynamics act' = clamp(act + dt (u - act) / tau(u, act), 0, 1).
+template <int MPT, class Team>
+__device__ __forceinline__ void activate(const KModel &M, const KRun &Rn, const Team &T, int env,
+                                         float dt, const float u[MPT], const float act[MPT],
+                                         float act1[MPT], bool stages) {
+  const int nm = M.n_mus;
+#pragma unroll
+  for (int k = 0; k < MPT; ++k) {
+    const int mi = T.t + T.n * k;
+    act1[k] = 0.0f;
+    if (mi < nm) {
+      float uc = fminf(fmaxf(u[k], 0.0f), 1.0f);
+      float a = act[k];
+      float tau = uc > a ? M.mus_tact[mi] * (0.5f + 1.5f * a) : M.mus_tdeact[mi] / (0.5f + 1.5f * a);
+      act1[k] = fminf(fmaxf(a + dt * (uc - a) / tau, 0.0f), 1.0f);
+      if (stages && Rn.o_act) Rn.o_act[(size_t)env * nm + M.mus_ext[mi]] = act1[k];
+    }
+  }
+}
+
+// Muscle geometry (exact, or the surrogate's predictions with the per-env
+// fallback check), Hill force, J_m^T F and the muscles' implicit damping.
+// Outputs either accumulate into the fused step's LDS right-hand side and
+// mass matrix (rhs, H) or go to the split step's device workspace
+// (tau_out[nv], dsum_out[n_dent]). Returns false for the geometry-only
+// variant, which stops after the geometry.
+template <int MPT, int NVIA, bool SURR, bool GEOM, class Team>
+__device__ __forceinline__ void stage_muscles(const KModel &M, const KRun &Rn, const Team &T, int env,
+                                              int step, const float *Rl, const float *Pl,
+                                              const float *Sl, const float *q, const float *qd,
+                                              V3 O, const float act1[MPT], unsigned char *scr,
+                                              float dt, bool stages, double *rhs, double *H,
+                                              float *tau_out, double *dsum_out, unsigned &status) {
+  const int nm = M.n_mus, nn = M.n_node, nv = M.nv;
+  float *mr = (float *)scr;          // [n_mus][3]
+  float *mF = mr + 3 * nm;           // [n_mus]
+  float *mc = mF + nm;               // [n_mus]
+  // surrogate geometry (when predictions are given): an env falls back to
+  // the exact geometry when a hinge leaves the training box or when the
+  // prediction misses the exact length of one of 32 sentinel muscles,
+  // rotated each step, by more than the tolerance. The decision is uniform
+  // over the env's team.
+  bool exact = true;
+  if (SURR) {
+    const float *Y = Rn.geomY + (size_t)env * 4 * nm;
+    bool out = false;
+    for (int i = T.t; i < nn; i += T.n) {
+      if (M.jtype[i] == 2) continue;
+      const int j = M.dadr[i];
+      const float qi = q[M.qadr[i]];
+      out |= !(qi >= M.qlo[j] && qi <= M.qhi[j]);
+    }
+    bool miss = false;
+    const int ns = nm < 32 ? nm : 32;
+    if (T.t < ns) {
+      const int mx = (int)((32ll * (Rn.step0 + step) + T.t) % nm);
+      const int m = M.mus_int[mx];
+      float r3[3], Ld;
+      const float L = muscle_geometry<NVIA>(M, m, NVIA, Rl, Pl, Sl, qd, O, r3, Ld);
+      miss = !(fabsf(Y[mx] - L) <= Rn.fb_tol);
+    }
+    const bool o1 = T.any(out);
+    const bool o2 = T.any(miss);
+    exact = o1 || o2;
+    if (exact) {
+      status |= MS_ST_FALLBACK;
+      if (Rn.fb_count && T.t == 0) Rn.fb_count[env] += 1u;
+    } else {
+      for (int m = T.t; m < nm; m += T.n) {
+        const int mx = M.mus_ext[m];
+        float Ld = 0.f;
+#pragma unroll
+        for (int sl = 0; sl < 3; ++sl) {
+          const int j = M.mus_span[sl * nm + m];
+          const float r = j >= 0 ? Y[nm + 3 * mx + sl] : 0.f;
+          mr[3 * m + sl] = r;
+          if (j >= 0) Ld -= r * qd[j];
+        }
+        mF[m] = Y[mx];
+        mc[m] = Ld;
+      }
+    }
+  }
+  // exact geometry: one muscle per thread and iteration (L, Ldot parked in
+  // mF, mc); a wavefront's 64 muscles share one via-point bound
+#pragma unroll 1
+  for (int m = T.t; exact && m < nm; m += T.n) {
+    float r3[3], Ld;
+    const float L = muscle_geometry<NVIA>(M, m, M.grp_nvia[m >> 6], Rl, Pl, Sl, qd, O, r3, Ld);
+    mr[3 * m] = r3[0];
+    mr[3 * m + 1] = r3[1];
+    mr[3 * m + 2] = r3[2];
+    mF[m] = L;
+    mc[m] = Ld;
+    if (stages) {
+      const size_t o = (size_t)env * nm + M.mus_ext[m];
+      Rn.o_L[o] = L;
+      if (Rn.o_Ldot) Rn.o_Ldot[o] = Ld;
+      Rn.o_r[3 * o] = r3[0];
+      Rn.o_r[3 * o + 1] = r3[1];
+      Rn.o_r[3 * o + 2] = r3[2];
+    }
+  }
+  if (GEOM) return;
+  // Hill force and its velocity slope (the same thread re-reads its muscles)
+#pragma unroll
+  for (int k = 0; k < MPT; ++k) {
+    const int m = T.t + T.n * k;
+    if (m >= nm) continue;
+    const float L = mF[m], Ld = mc[m];
+    const float lm = (L - M.mus_lslack[m]) * M.mus_ilopt[m];
+    const float vm = Ld * M.mus_ivl[m];
+    const float fl = hill_fl(lm), fv = hill_fv(vm), fp = hill_fp(lm);
+    const float f0 = M.mus_f0[m];
+    const float F = f0 * (act1[k] * fl * fv + fp);
+    const float cdamp = f0 * act1[k] * fl * hill_fv_slope(vm) * M.mus_ivl[m];
+    mF[m] = F;
+    mc[m] = cdamp;
+    if (stages) Rn.o_F[(size_t)env * nm + M.mus_ext[m]] = F;
+  }
+  T.sync();
+  for (int x = T.t; x < nv; x += T.n) {
+    const int j = M.proj_dof[x];
+    float tau = 0.f;
+#pragma unroll 8
+    for (int e = M.proj_start[x]; e < M.proj_start[x + 1]; ++e) {
+      const int it = M.proj_item[e];
+      tau += mr[it] * mF[it / 3];
+    }
+    if (stages) Rn.o_tau[(size_t)env * nv + j] = tau;
+    if (tau_out)
+      tau_out[j] = tau;
+    else
+      rhs[j] += (double)tau;
+  }
+  for (int e = T.t; e < M.n_dent; e += T.n) {
+    double s = 0.0;
+#pragma unroll 8
+    for (int k = M.dent_start[e]; k < M.dent_start[e + 1]; ++k) {
+      const int it = M.dent_item[k];
+      const int m = it >> 4, a = (it >> 2) & 3, b = it & 3;
+      s += (double)mc[m] * (double)mr[3 * m + a] * (double)mr[3 * m + b];
+    }
+    if (dsum_out)
+      dsum_out[e] = s;
+    else
+      H[M.dent_h[e]] += (double)dt * s;
+  }
+  T.sync();
+}
+
+// LTDL factorisation of H (FP64, in LDS) with the L^T solve riding along,
+// then the L solve; the solution is left in xs. Returns true (the same in
+// every lane) when a pivot is not positive.
+//
+// H = L^T D L with Featherstone's branch-induced sparsity, as gathers:
+// finished row k holds H_kj - sum over the descendants i of k of
+// H_ik H_ij / d_i (j = k or an ancestor of k), and reads only finished
+// rows of lower height. The right-hand side rides along as one more
+// column: y_k = rhs_k - sum_i (H_ik / d_i) y_i is the solve of L^T y =
+// rhs. Rows of equal height are independent, so a height level is one
+// pass over its entries; when a level has few entries, P lanes split each
+// entry's sum (fixed-order prefix sums). All tables come from the
+// workgroup's LDS copy.
+__device__ __forceinline__ bool stage_solve(const KModel &M, int lane, const int *LT, double *H,
+                                            const double *rhs, double *xs, double *invd) {
+  const int nv = M.nv;
+  bool nonspd = false;
+  const int *Lrs = LT + M.lt_rs, *Ldesc = LT + M.lt_desc, *Ldr = LT + M.lt_drange;
+  // leaves: y = rhs, pivots as assembled
+  bool fbad = false;
+  for (int j = lane; j < nv; j += 64) xs[j] = rhs[j];
+  for (int e = LT[M.lt_hlev_start] + lane; e < LT[M.lt_hlev_start + 1]; e += 64) {
+    const int w = LT[M.lt_hdof + e];
+    const int k = w & 0xFF;
+    const double d = H[Lrs[k] + (w >> 8)];
+    fbad |= !(d > 0.0);
+    invd[k] = 1.0 / d;
+  }
+  nonspd = __any(fbad);
+  wave_sync();
+  // one entry of a row at height >= 1: finished value (and its pivot when
+  // it is the diagonal) from the descendants' finished rows
+  auto entry = [&](int w, int p, int P, double &sum, int &e, int &k, int &ck, int &cj) {
+    k = w & 0xFF;
+    ck = (w >> 8) & 0xFF;
+    cj = w >> 16;
+    const bool rcol = cj == 255;
+    e = Lrs[k] + (rcol ? 0 : cj);
+    const int dr = Ldr[k], t1 = dr >> 16;
+    sum = 0.0;
+#pragma unroll 4
+    for (int t = (dr & 0xFFFF) + p; t < t1; t += P) {
+      const int di = Ldesc[t];
+      const int ri = di & 0xFFFF, i = di >> 16;
+      const double hij = rcol ? xs[i] : H[ri + cj];
+      sum += H[ri + ck] * hij * invd[i];
+    }
+  };
+  auto finish = [&](double sum, int e, int k, int ck, int cj, bool &badf) {
+    if (cj == 255) {
+      xs[k] = rhs[k] - sum;
+    } else {
+      const double v = H[e] - sum;
+      H[e] = v;
+      if (cj == ck) {
+        badf |= !(v > 0.0);
+        invd[k] = 1.0 / v;
+      }
+    }
+  };
+  for (int h = 1; h < M.n_hgat && !nonspd; ++h) {
+    const int s0 = LT[M.lt_hent_start + h], ne = LT[M.lt_hent_start + h + 1] - s0;
+    const int lp = group_log2(ne), P = 1 << lp;
+    fbad = false;
+    if (lp == 0) {
+      // more entries than lanes: two independent entries per lane in flight
+      for (int base = 0; base < ne; base += 128) {
+        const int ga = base + lane, gb = base + 64 + lane;
+        double sa = 0.0, sb = 0.0;
+        int ea = 0, ka = 0, cka = 0, cja = 0, eb = 0, kb = 0, ckb = 0, cjb = 0;
+        if (ga < ne) entry(LT[M.lt_hent + s0 + ga], 0, 1, sa, ea, ka, cka, cja);
+        if (gb < ne) entry(LT[M.lt_hent + s0 + gb], 0, 1, sb, eb, kb, ckb, cjb);
+        if (ga < ne) finish(sa, ea, ka, cka, cja, fbad);
+        if (gb < ne) finish(sb, eb, kb, ckb, cjb, fbad);
+      }
+    } else {
+      const int g = lane >> lp, p = lane & (P - 1);
+      double sum = 0.0;
+      int e = 0, k = 0, ck = 0, cj = 0;
+      if (g < ne) entry(LT[M.lt_hent + s0 + g], p, P, sum, e, k, ck, cj);
+      sum = group_sum_last(sum, lp, lane);
+      if (g < ne && p == P - 1) finish(sum, e, k, ck, cj, fbad);
+    }
+    nonspd = __any(fbad);
+    wave_sync();
+  }
+  // The trunk (single-row levels at the top, ancestor counts 0 .. n_trunk-1):
+  // its rows were gathered over their non-trunk descendants only, which
+  // leaves the block that remains once every other row is eliminated.
+  // Eliminating its rows bottom-up, row k (final once the rows below it
+  // are eliminated) updates every entry (a, b) of the rows above it, b = a
+  // or an ancestor of a, and their right-hand sides:
+  // H_ab -= H_ka H_kb / d_k, y_a -= H_ka y_k / d_k. One level per row, one
+  // FMA per entry, no two lanes writing the same entry.
+  if (M.n_trunk && !nonspd) {
+    const int *trow = LT + M.lt_trow, *tpair = LT + M.lt_tpair;
+    const int nt = M.n_trunk, npair = (nt - 1) * (nt + 2) / 2;
+    // this lane's first three entries stay in registers; all of a level's
+    // loads are issued before its stores
+    int tw[3];
+#pragma unroll
+    for (int u = 0; u < 3; ++u) tw[u] = lane + 64 * u < npair ? tpair[lane + 64 * u] : -1;
+    int wk = trow[nt - 1];
+    for (int dk = nt - 1; dk >= 0; --dk) {
+      const int k = wk & 0xFF, rk = wk >> 8;
+      const double d = H[rk + dk], xk = xs[k];
+      double hka[3], hkb[3], hab[3];
+      bool on[3], rhsc[3];
+#pragma unroll
+      for (int u = 0; u < 3; ++u) {
+        const int w = tw[u], da = (w >> 16) & 0x7F, db = (w >> 23) & 0x7F;
+        on[u] = w >= 0 && da < dk;
+        rhsc[u] = (w >> 30) & 1;
+        hka[u] = hkb[u] = hab[u] = 0.0;
+        if (on[u]) {
+          hka[u] = H[rk + da];
+          if (!rhsc[u]) hkb[u] = H[rk + db];
+          hab[u] = rhsc[u] ? xs[w & 0xFFFF] : H[w & 0xFFFF];
+        }
+      }
+      if (dk > 0) wk = trow[dk - 1];
+      if (!(d > 0.0)) {  // the same value in every lane
+        nonspd = true;
+        break;
+      }
+      const double id = 1.0 / d, yk = xk * id;
+      if (lane == 0) invd[k] = id;
+#pragma unroll
+      for (int u = 0; u < 3; ++u) {
+        if (!on[u]) continue;
+        const int e = tw[u] & 0xFFFF;
+        if (rhsc[u]) xs[e] = hab[u] - hka[u] * yk;
+        else H[e] = hab[u] - hka[u] * hkb[u] * id;
+      }
+      // entries beyond the first 192 (trunks longer than 18 rows)
+      const int na = dk * (dk + 3) / 2;
+      for (int t = lane + 192; t < na; t += 64) {
+        const int w = tpair[t], e = w & 0xFFFF, da = (w >> 16) & 0x7F;
+        const double h1 = H[rk + da];
+        if (w >> 30) {
+          xs[e] -= h1 * yk;
+        } else {
+          const int db = (w >> 23) & 0x7F;
+          H[e] -= h1 * H[rk + db] * id;
+        }
+      }
+      wave_sync();
+    }
+  }
+  if (!nonspd) {
+    // L x = z with z = y / d, root first: x_k = z_k - (1/d_k) sum over the
+    // ancestors a of k of H_ka x_a. Each lane keeps its rows' sums in
+    // registers; at depth l the rows of that depth are final, and every
+    // deeper row adds the term of its (single) depth-l ancestor, which is
+    // entry l of its root-first row.
+    const unsigned char *path8 = (const unsigned char *)(LT + M.lt_path);
+    double z[2], id[2], acc[2] = {0.0, 0.0};
+    int rk[2], dk[2];
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      const int j = lane + 64 * t;
+      dk[t] = -1;
+      rk[t] = 0;
+      id[t] = z[t] = 0.0;
+      if (j < nv) {
+        rk[t] = Lrs[j];
+        dk[t] = Lrs[j + 1] - rk[t] - 1;
+        id[t] = invd[j];
+        z[t] = xs[j] * id[t];
+      }
+    }
+    for (int l = 0;; ++l) {
+      double h[2];
+      int c[2];
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        h[t] = 0.0;
+        c[t] = 0;
+        if (dk[t] > l) {
+          h[t] = H[rk[t] + l];
+          c[t] = path8[rk[t] + l];
+        }
+        if (dk[t] == l) xs[lane + 64 * t] = z[t] - acc[t] * id[t];
+      }
+      wave_sync();
+      if (l + 1 >= M.n_dlev) break;
+#pragma unroll
+      for (int t = 0; t < 2; ++t)
+        if (dk[t] > l) acc[t] += h[t] * xs[c[t]];
+    }
+  }
+  return nonspd;
+}
+
+// Semi-implicit Euler update in LDS: qd += dt qdd (qdd = xs), then q += dt
+// qd (root orientation by the quaternion exponential of the body angular
+// velocity). Nothing changes and false is returned (the same in every
+// lane) when a new velocity is not finite or act_bad is set.
+__device__ __forceinline__ bool stage_integrate(const KModel &M, int lane, float *q, float *qd,
+                                                const double *xs, float dt, bool act_bad) {
+  const int nv = M.nv, nn = M.n_node;
+  // new velocities and hinge/slide positions in registers, checked first
+  float qdn[2], qn[2];
+  bool badn = act_bad;
+  for (int t = 0; t < 2; ++t) {
+    const int j = lane + 64 * t;
+    qdn[t] = 0.f;
+    qn[t] = 0.f;
+    if (j < nv) {
+      qdn[t] = qd[j] + dt * (float)xs[j];
+      badn |= !isfinite(qdn[t]);
+    }
+  }
+  badn = __any(badn);
+  if (badn) return false;
+  wave_sync();
+  for (int t = 0; t < 2; ++t) {
+    const int j = lane + 64 * t;
+    if (j < nv) qd[j] = qdn[t];
+  }
+  wave_sync();
+  // positions: each node's q from its own DoFs
+  for (int i = lane; i < nn; i += 64) {
+    const int a = M.qadr[i], d = M.dadr[i];
+    if (M.jtype[i] != 2) {
+      qn[0] = q[a] + dt * qd[d];
+      q[a] = qn[0];
+      continue;
+    }
+    for (int k = 0; k < 3; ++k) q[a + k] = q[a + k] + dt * qd[d + k];
+    float th[3] = {qd[d + 3] * dt, qd[d + 4] * dt, qd[d + 5] * dt};
+    float ang = sqrtf(th[0] * th[0] + th[1] * th[1] + th[2] * th[2]);
+    float dq[4];
+    if (ang < 1e-8f) {
+      dq[0] = 1.f; dq[1] = 0.5f * th[0]; dq[2] = 0.5f * th[1]; dq[3] = 0.5f * th[2];
+    } else {
+      float sn, cs;
+      sincosf(0.5f * ang, &sn, &cs);
+      float sc = sn / ang;
+      dq[0] = cs; dq[1] = sc * th[0]; dq[2] = sc * th[1]; dq[3] = sc * th[2];
+    }
+    float *x = q + a + 3;
+    float o0 = x[0] * dq[0] - x[1] * dq[1] - x[2] * dq[2] - x[3] * dq[3];
+    float o1 = x[0] * dq[1] + x[1] * dq[0] + x[2] * dq[3] - x[3] * dq[2];
+    float o2 = x[0] * dq[2] - x[1] * dq[3] + x[2] * dq[0] + x[3] * dq[1];
+    float o3 = x[0] * dq[3] + x[1] * dq[2] - x[2] * dq[1] + x[3] * dq[0];
+    float nrm = sqrtf(o0 * o0 + o1 * o1 + o2 * o2 + o3 * o3);
+    x[0] = o0 / nrm; x[1] = o1 / nrm; x[2] = o2 / nrm; x[3] = o3 / nrm;
+  }
+  wave_sync();
+  return true;
+}
+
+// ------------------------------------------------------- the fused step
+// One wavefront steps one env n_steps times with every intermediate in LDS
+// and registers. SURR: muscle geometry from the surrogate's predictions with
+// the per-env fallback check; GEOM: exact geometry only (stage outputs).
 template <int MPL, int NVIA, bool SURR, bool GEOM>
 __device__ __forceinline__ void step_body(const KModel &M, const KRun &Rn, int n_steps) {
   // a workgroup holds blockDim.x / 64 envs, one per wavefront, each with its
@@ -258,13 +1051,14 @@ __device__ __forceinline__ void step_body(const KModel &M, const KRun &Rn, int n
   const int wave = threadIdx.x >> 6;
   const int env = blockIdx.x * (blockDim.x >> 6) + wave;
   const int lane = threadIdx.x & 63;
+  const WaveTeam T{lane};
   int *LT = (int *)lds_all;
   // every variant reads the tree schedule from this table
   for (int i = threadIdx.x; i < M.lt_words; i += blockDim.x) LT[i] = M.lt[i];
   __syncthreads();  // the only workgroup-wide barrier: every wavefront reaches it
   if (env >= Rn.n_env) return;
   unsigned char *lds = lds_all + (size_t)M.lt_words * 4 + (size_t)wave * M.lds_env;
-  const int nq = M.nq, nv = M.nv, nm = M.n_mus, nn = M.n_node;
+  const int nq = M.nq, nv = M.nv, nm = M.n_mus;
   float *__restrict__ q = (float *)(lds + M.off_q);
   float *__restrict__ qd = (float *)(lds + M.off_qd);
   // node frames: 12 floats per node, 16-byte aligned: R (row-major) then P
@@ -285,9 +1079,7 @@ __device__ __forceinline__ void step_body(const KModel &M, const KRun &Rn, int n
   const unsigned char *sbl = (const unsigned char *)(LT + M.lt_subb);
   const unsigned char *scl = (const unsigned char *)(LT + M.lt_subc);
   const float dt = Rn.dt;
-  const int exc = Rn.exc;
   const bool stages = Rn.stages != 0;
-  constexpr bool geom_only = GEOM;
 
   for (int i = lane; i < nq; i += 64) q[i] = Rn.q[(size_t)env * nq + i];
   for (int i = lane; i < nv; i += 64) qd[i] = Rn.qd ? Rn.qd[(size_t)env * nv + i] : 0.0f;
@@ -298,7 +1090,7 @@ __device__ __forceinline__ void step_body(const KModel &M, const KRun &Rn, int n
     const int mx = mi < nm ? M.mus_ext[mi] : 0;
     act[t] = (mi < nm && Rn.act) ? Rn.act[(size_t)env * nm + mx] : 0.0f;
     xar[t] = 0.0f;
-    if (exc == EXC_AR1 && mi < nm) xar[t] = Rn.xar[(size_t)env * nm + mx];
+    if (Rn.exc == EXC_AR1 && mi < nm) xar[t] = Rn.xar[(size_t)env * nm + mx];
   }
   unsigned status = Rn.status ? Rn.status[env] : 0u;
   wave_sync();
@@ -309,651 +1101,31 @@ __device__ __forceinline__ void step_body(const KModel &M, const KRun &Rn, int n
     bool bad = false;
     for (int i = lane; i < nq; i += 64) bad |= !isfinite(q[i]);
     for (int i = lane; i < nv; i += 64) bad |= !isfinite(qd[i]);
-    unsigned long long key = 0;
-    if (exc != EXC_ARRAY)
-      key = splitmix64(splitmix64(Rn.seed ^ (unsigned long long)env) ^
-                       (unsigned long long)(Rn.step0 + step));
-#pragma unroll
-    for (int t = 0; t < MPL; ++t) {
-      int mi = lane + 64 * t;
-      u[t] = 0.0f;
-      if (mi < nm) {
-        const int mx = M.mus_ext[mi];
-        bad |= !isfinite(act[t]);
-        if (exc == EXC_ARRAY) {
-          u[t] = Rn.u ? Rn.u[((size_t)(Rn.u_hold ? 0 : step) * Rn.n_env + env) * nm + mx] : 0.0f;
-        } else if (exc == EXC_IID) {
-          u[t] = u24(splitmix64(key ^ (unsigned long long)mx), 40);
-        } else {
-          const AR1 r = ar1_step(key, mx, xar[t], Rn.rho, Rn.s, Rn.mean);
-          u[t] = r.u;
-          xar[t] = r.x;
-        }
-      }
-    }
+    bad |= excite<MPL>(M, Rn, T, env, step, act, xar, u);
     if (__any(bad)) {
       status |= MS_ST_NONFINITE;
       continue;  // the state stays as it is
     }
-
-    // --------------------------------------------------- activation dynamics
     float act1[MPL];
-#pragma unroll
-    for (int t = 0; t < MPL; ++t) {
-      int mi = lane + 64 * t;
-      act1[t] = 0.0f;
-      if (mi < nm) {
-        float uc = fminf(fmaxf(u[t], 0.0f), 1.0f);
-        float a = act[t];
-        float tau = uc > a ? M.mus_tact[mi] * (0.5f + 1.5f * a) : M.mus_tdeact[mi] / (0.5f + 1.5f * a);
-        act1[t] = fminf(fmaxf(a + dt * (uc - a) / tau, 0.0f), 1.0f);
-        if (stages && Rn.o_act) Rn.o_act[(size_t)env * nm + M.mus_ext[mi]] = act1[t];
-      }
-    }
-
-    // ------------------------- forward kinematics, motion subspaces, V and A
-    // O = root origin (floating) or world origin (fixed base).
-    V3 O = M.free_root ? v3(q[0], q[1], q[2]) : v3(0.f, 0.f, 0.f);
+    activate<MPL>(M, Rn, T, env, dt, u, act, act1, stages);
+    const V3 O = M.free_root ? v3(q[0], q[1], q[2]) : v3(0.f, 0.f, 0.f);
     const V3 g = v3(M.gx, M.gy, M.gz);
-    // (1) every node's joint transform in parallel: rotation jrot Rot(axis, q)
-    // and offset parked in the node's frame slot, the axis jrot*axis in its A
-    // slot; the floating root is finished here
-    for (int i = lane; i < nn; i += 64) {
-      const int jt = M.jtype[i];
-      float *F = Rl + 12 * i;
-      const int da = M.dadr[i];
-      if (jt == 2) {
-        const float *x = q + M.qadr[i] + 3;
-        float nrm = sqrtf(x[0] * x[0] + x[1] * x[1] + x[2] * x[2] + x[3] * x[3]);
-        float w = x[0] / nrm, a = x[1] / nrm, b = x[2] / nrm, c = x[3] / nrm;
-        float *R = F;
-        R[0] = 1 - 2 * (b * b + c * c); R[1] = 2 * (a * b - w * c); R[2] = 2 * (a * c + w * b);
-        R[3] = 2 * (a * b + w * c); R[4] = 1 - 2 * (a * a + c * c); R[5] = 2 * (b * c - w * a);
-        R[6] = 2 * (a * c - w * b); R[7] = 2 * (b * c + w * a); R[8] = 1 - 2 * (a * a + b * b);
-        st3(F + 9, v3(0.f, 0.f, 0.f));
-        for (int kk = 0; kk < 3; ++kk) {
-          float *S = Sl + 6 * (da + kk);
-          S[0] = S[1] = S[2] = 0.f;
-          S[3] = kk == 0; S[4] = kk == 1; S[5] = kk == 2;
-          float *S2 = Sl + 6 * (da + 3 + kk);
-          S2[0] = R[kk]; S2[1] = R[3 + kk]; S2[2] = R[6 + kk];
-          S2[3] = S2[4] = S2[5] = 0.f;
-        }
-        V3 v = ld3(qd + da);
-        V3 ww = mulR(R, ld3(qd + da + 3));
-        float *V = Vl + 6 * i, *A = Al + 6 * i;
-        st3(V, ww);
-        st3(V + 3, v);
-        st3(A, v3(0.f, 0.f, 0.f));
-        st3(A + 3, cross(v, ww) - g);
-        continue;
-      }
-      const float *E = M.jrot + 9 * i;
-      const V3 ax = ld3(M.axis + 3 * i);
-      const float qi = q[M.qadr[i]];
-      const V3 al = mulR(E, ax);
-      V3 t = ld3(M.jpos + 3 * i);
-      if (jt == 0) {
-        float sn, cs;
-        sincosf(qi, &sn, &cs);
-        const float vc = 1.0f - cs;
-        const float Q[9] = {cs + ax.x * ax.x * vc, ax.x * ax.y * vc - ax.z * sn, ax.x * ax.z * vc + ax.y * sn,
-                            ax.y * ax.x * vc + ax.z * sn, cs + ax.y * ax.y * vc, ax.y * ax.z * vc - ax.x * sn,
-                            ax.z * ax.x * vc - ax.y * sn, ax.z * ax.y * vc + ax.x * sn, cs + ax.z * ax.z * vc};
-        for (int r = 0; r < 3; ++r)
-          for (int c = 0; c < 3; ++c)
-            F[3 * r + c] = E[3 * r] * Q[c] + E[3 * r + 1] * Q[3 + c] + E[3 * r + 2] * Q[6 + c];
-      } else {
-        for (int e = 0; e < 9; ++e) F[e] = E[e];
-        t = t + qi * al;
-      }
-      st3(F + 9, t);
-      st3(Al + 6 * i, al);
-    }
-    wave_sync();
-    // (2) compose down the tree level by level, reading only LDS:
-    // R = R_p Lr, P = P_p + R_p t, axis = R_p al, S, V = V_p + S qd,
-    // A = A_p + V_p x (S qd)
-    for (int l = 0; l < M.n_level; ++l) {
-      const int b0 = tlev[l], b1 = tlev[l + 1];
-      for (int k = b0 + lane; k < b1; k += 64) {
-        const int info = tnode[k], i = info >> 18;
-        const int jt = info & 3;
-        if (jt == 2) continue;
-        const int p = (info >> 2 & 0xFF) - 1, da = info >> 10 & 0xFF;
-        float *F = Rl + 12 * i;
-        // frames are 16-byte aligned 12-float records, V and A 8-byte aligned
-        // 6-float records: vector LDS accesses
-        const float4 f0 = ((const float4 *)F)[0], f1 = ((const float4 *)F)[1],
-                     f2 = ((const float4 *)F)[2];
-        const float Lr[9] = {f0.x, f0.y, f0.z, f0.w, f1.x, f1.y, f1.z, f1.w, f2.x};
-        const V3 t = v3(f2.y, f2.z, f2.w);
-        const float2 a0 = ((const float2 *)(Al + 6 * i))[0], a1 = ((const float2 *)(Al + 6 * i))[1];
-        const V3 al = v3(a0.x, a0.y, a1.x);
-        float Rp[9];
-        V3 Pp, wp, vp, ap, lp;
-        if (p >= 0) {
-          const float4 *P4 = (const float4 *)(Rl + 12 * p);
-          const float4 r0 = P4[0], r1 = P4[1], r2 = P4[2];
-          Rp[0] = r0.x; Rp[1] = r0.y; Rp[2] = r0.z; Rp[3] = r0.w; Rp[4] = r1.x; Rp[5] = r1.y;
-          Rp[6] = r1.z; Rp[7] = r1.w; Rp[8] = r2.x;
-          Pp = v3(r2.y, r2.z, r2.w);
-          const float2 *V2 = (const float2 *)(Vl + 6 * p), *A2 = (const float2 *)(Al + 6 * p);
-          const float2 v0 = V2[0], v1 = V2[1], v2 = V2[2], b0 = A2[0], b1 = A2[1], b2 = A2[2];
-          wp = v3(v0.x, v0.y, v1.x); vp = v3(v1.y, v2.x, v2.y);
-          ap = v3(b0.x, b0.y, b1.x); lp = v3(b1.y, b2.x, b2.y);
-        } else {
-          for (int e = 0; e < 9; ++e) Rp[e] = (e % 4 == 0) ? 1.f : 0.f;
-          Pp = v3(0.f, 0.f, 0.f) - O;
-          wp = vp = ap = v3(0.f, 0.f, 0.f);
-          lp = v3(0.f, 0.f, 0.f) - g;
-        }
-        float Rn9[9];
-        for (int r = 0; r < 3; ++r)
-          for (int c = 0; c < 3; ++c)
-            Rn9[3 * r + c] = Rp[3 * r] * Lr[c] + Rp[3 * r + 1] * Lr[3 + c] + Rp[3 * r + 2] * Lr[6 + c];
-        const V3 Pi = Pp + mulR(Rp, t);
-        const V3 ah = mulR(Rp, al);
-        ((float4 *)F)[0] = make_float4(Rn9[0], Rn9[1], Rn9[2], Rn9[3]);
-        ((float4 *)F)[1] = make_float4(Rn9[4], Rn9[5], Rn9[6], Rn9[7]);
-        ((float4 *)F)[2] = make_float4(Rn9[8], Pi.x, Pi.y, Pi.z);
-        V3 sw, sv;
-        if (jt == 0) {
-          sw = ah;
-          sv = cross(Pi, ah);
-        } else {
-          sw = v3(0.f, 0.f, 0.f);
-          sv = ah;
-        }
-        float *S = Sl + 6 * da;
-        st3(S, sw);
-        st3(S + 3, sv);
-        const float qdi = qd[da];
-        const V3 xw = qdi * sw, xv = qdi * sv;  // S qd
-        const V3 vw = wp + xw, vv = vp + xv;
-        const V3 aw = ap + cross(wp, xw), av = lp + cross(wp, xv) + cross(vp, xw);
-        float2 *V2 = (float2 *)(Vl + 6 * i), *A2 = (float2 *)(Al + 6 * i);
-        V2[0] = make_float2(vw.x, vw.y); V2[1] = make_float2(vw.z, vv.x); V2[2] = make_float2(vv.y, vv.z);
-        A2[0] = make_float2(aw.x, aw.y); A2[1] = make_float2(aw.z, av.x); A2[2] = make_float2(av.y, av.z);
-      }
-      wave_sync();
-    }
-
-    if (!geom_only) {
-    // ------------------------------------------------------------- contacts
-    for (int c = lane; c < M.n_con; c += 64) {
-      float *C = Cl + 16 * c;
-      const int b = M.con_node[c];
-      V3 w = frame_apply(Rl + 12 * b, ld3(M.con_pos + 3 * c));
-      const float rho = M.con_radius[c];
-      const float pen = rho - (w.z + O.z);
-      for (int e = 0; e < 16; ++e) C[e] = 0.f;
-      if (Rn.contact && pen > 0.f) {
-        V3 cp = w - v3(0.f, 0.f, rho);
-        V3 vel = ld3(Vl + 6 * b + 3) + cross(ld3(Vl + 6 * b), cp);
-        // spring taken linearly implicitly over the step: damping c + dt k
-        const float ceff = M.cc + dt * M.kc;
-        float fn = fmaxf(0.f, M.kc * pen - ceff * vel.z);
-        float s2 = vel.x * vel.x + vel.y * vel.y + M.vs * M.vs;
-        float s = sqrtf(s2);
-        V3 f = v3(-M.mu * fn * vel.x / s, -M.mu * fn * vel.y / s, fn);
-        C[0] = 1.f;
-        st3(C + 1, cp);
-        st3(C + 4, cross(cp, f));
-        st3(C + 7, f);
-        if (fn > 0.f) {
-          float gg = M.mu * fn / s;
-          C[10] = gg * (1.f - vel.x * vel.x / s2);
-          C[11] = -gg * vel.x * vel.y / s2;
-          C[12] = gg * (1.f - vel.y * vel.y / s2);
-          C[13] = ceff;
-        }
-      }
-    }
-
-    // ------------------------------------- recursive Newton-Euler bias forces
-    for (int b = lane; b < M.n_body; b += 64) {
-      const int i = M.body_node[b];
-      const float *R = Rl + 12 * i;
-      const float m = M.body_mass[b];
-      V3 c = mulR(R, ld3(M.body_com + 3 * b)) + ld3(Pl + 12 * i);
-      V3 h = m * c;
-      const float I0 = M.body_inertia[3 * b], I1 = M.body_inertia[3 * b + 1], I2 = M.body_inertia[3 * b + 2];
-      // I_O = R diag(I) R^T + m (|c|^2 1 - c c^T)
-      float Io[9];
-      const float cc = dot(c, c);
-      const float cv[3] = {c.x, c.y, c.z};
-      for (int r = 0; r < 3; ++r)
-        for (int s = 0; s < 3; ++s)
-          Io[3 * r + s] = R[3 * r] * I0 * R[3 * s] + R[3 * r + 1] * I1 * R[3 * s + 1] +
-                          R[3 * r + 2] * I2 * R[3 * s + 2] + m * ((r == s ? cc : 0.f) - cv[r] * cv[s]);
-      V3 w = ld3(Vl + 6 * i), v = ld3(Vl + 6 * i + 3);
-      V3 aw = ld3(Al + 6 * i), al = ld3(Al + 6 * i + 3);
-      // I (w; v) = (I_O w + h x v; m v - h x w)
-      V3 Iaw = mulR(Io, aw) + cross(h, al), Ial = m * al - cross(h, aw);
-      V3 Ivw = mulR(Io, w) + cross(h, v), Ivl = m * v - cross(h, w);
-      // f = I a + v x* (I v), (w, v) x* (n, f) = (w x n + v x f, w x f)
-      V3 fw = Iaw + cross(w, Ivw) + cross(v, Ivl);
-      V3 fl = Ial + cross(w, Ivl);
-      st3(Fl + 6 * b, fw);
-      st3(Fl + 6 * b + 3, fl);
-    }
-    wave_sync();
-    float *Fn = Fl + 6 * M.n_body;
-    for (int t = lane; t < 6 * nn; t += 64) {
-      const int n = t / 6, k = t % 6;
-      float s = 0.f;
-      for (int e = sbs[n]; e < sbs[n + 1]; ++e) s += Fl[6 * sbl[e] + k];
-      for (int e = scs[n]; e < scs[n + 1]; ++e) s -= Cl[16 * scl[e] + 4 + k];
-      Fn[t] = s;
-    }
-    wave_sync();
-    for (int j = lane; j < nv; j += 64) {
-      const float *S = Sl + 6 * j;
-      const float *F = Fn + 6 * M.dof_node[j];
-      float cb = S[0] * F[0] + S[1] * F[1] + S[2] * F[2] + S[3] * F[3] + S[4] * F[4] + S[5] * F[5];
-      if (stages) Rn.o_bias[(size_t)env * nv + j] = cb;
-      rhs[j] = (double)(-cb - M.damping[j] * qd[j]);
-    }
-    wave_sync();
-
-    // ---------------------------------- composite-rigid-body mass matrix (FP64)
-    {
-      double *BI = (double *)scr;                  // [n_body][10]: m, h, I_O (xx xy xz yy yz zz)
-      double *CI = BI + 10 * M.n_body;             // [n_node][10]
-      double *FJ = CI + 10 * nn;                   // [nv][6]
-      // joint damping of this lane's DoFs, added to the diagonal at the end
-      // (loaded now so that no entry waits on global memory)
+    stage_fk(M, lane, tlev, tnode, q, qd, Rl, Sl, Vl, Al, O, g);
+    if (!GEOM) {
+      stage_contacts(M, lane, Rl, Vl, Cl, O, dt, Rn.contact);
+      stage_rnea(M, lane, Rl, Pl, Vl, Al, Fl, Cl, Sl, qd, sbs, sbl, scs, scl, rhs,
+                 stages ? Rn.o_bias + (size_t)env * nv : nullptr);
       float dmp[2];
-#pragma unroll
-      for (int t = 0; t < 2; ++t) dmp[t] = lane + 64 * t < nv ? M.damping[lane + 64 * t] : 0.f;
-      for (int b = lane; b < M.n_body; b += 64) {
-        const int i = M.body_node[b];
-        const float *R = Rl + 12 * i;
-        const double m = M.body_mass[b];
-        V3 cf = mulR(R, ld3(M.body_com + 3 * b)) + ld3(Pl + 12 * i);
-        const double c[3] = {cf.x, cf.y, cf.z};
-        const double In[3] = {M.body_inertia[3 * b], M.body_inertia[3 * b + 1], M.body_inertia[3 * b + 2]};
-        double *o = BI + 10 * b;
-        o[0] = m;
-        o[1] = m * c[0]; o[2] = m * c[1]; o[3] = m * c[2];
-        const double cc = c[0] * c[0] + c[1] * c[1] + c[2] * c[2];
-        const int rr[6] = {0, 0, 0, 1, 1, 2}, ss[6] = {0, 1, 2, 1, 2, 2};
-        for (int e = 0; e < 6; ++e) {
-          int r = rr[e], s = ss[e];
-          double v = (double)R[3 * r] * In[0] * R[3 * s] + (double)R[3 * r + 1] * In[1] * R[3 * s + 1] +
-                     (double)R[3 * r + 2] * In[2] * R[3 * s + 2];
-          o[4 + e] = v + m * ((r == s ? cc : 0.0) - c[r] * c[s]);
-        }
-      }
-      wave_sync();
-      for (int t = lane; t < 10 * nn; t += 64) {
-        const int n = t / 10, k = t % 10;
-        double s = 0.0;
-        for (int e = sbs[n]; e < sbs[n + 1]; ++e) s += BI[10 * sbl[e] + k];
-        CI[t] = s;
-      }
-      wave_sync();
-      for (int j = lane; j < nv; j += 64) {
-        const int n = M.dof_node[j];
-        const double *I = CI + 10 * n;
-        const float *Sf = Sl + 6 * j;
-        const double w[3] = {Sf[0], Sf[1], Sf[2]}, v[3] = {Sf[3], Sf[4], Sf[5]};
-        const double m = I[0], h[3] = {I[1], I[2], I[3]};
-        const double Io[9] = {I[4], I[5], I[6], I[5], I[7], I[8], I[6], I[8], I[9]};
-        double f[6];
-        // (I_O w + h x v ; m v - h x w)
-        f[0] = Io[0] * w[0] + Io[1] * w[1] + Io[2] * w[2] + (h[1] * v[2] - h[2] * v[1]);
-        f[1] = Io[3] * w[0] + Io[4] * w[1] + Io[5] * w[2] + (h[2] * v[0] - h[0] * v[2]);
-        f[2] = Io[6] * w[0] + Io[7] * w[1] + Io[8] * w[2] + (h[0] * v[1] - h[1] * v[0]);
-        f[3] = m * v[0] - (h[1] * w[2] - h[2] * w[1]);
-        f[4] = m * v[1] - (h[2] * w[0] - h[0] * w[2]);
-        f[5] = m * v[2] - (h[0] * w[1] - h[1] * w[0]);
-        // implicit contact damping: dt * Phi^T D Phi S for contacts below
-        for (int e = scs[n]; e < scs[n + 1]; ++e) {
-          const float *C = Cl + 16 * scl[e];
-          if (C[0] == 0.f) continue;
-          const double cp[3] = {C[1], C[2], C[3]};
-          // point velocity of the contact for unit qd_j: v + w x cp
-          const double J[3] = {v[0] + w[1] * cp[2] - w[2] * cp[1], v[1] + w[2] * cp[0] - w[0] * cp[2],
-                               v[2] + w[0] * cp[1] - w[1] * cp[0]};
-          const double u0 = (double)C[10] * J[0] + (double)C[11] * J[1];
-          const double u1 = (double)C[11] * J[0] + (double)C[12] * J[1];
-          const double u2 = (double)C[13] * J[2];
-          const double dd = dt;
-          f[0] += dd * (cp[1] * u2 - cp[2] * u1);
-          f[1] += dd * (cp[2] * u0 - cp[0] * u2);
-          f[2] += dd * (cp[0] * u1 - cp[1] * u0);
-          f[3] += dd * u0;
-          f[4] += dd * u1;
-          f[5] += dd * u2;
-        }
-        for (int k = 0; k < 6; ++k) FJ[6 * j + k] = f[k];
-      }
-      wave_sync();
-      const unsigned char *rowb = (const unsigned char *)(LT + M.lt_nnzrow);
-      const unsigned char *pathb = (const unsigned char *)(LT + M.lt_path);
-      for (int e = lane; e < M.nnz; e += 64) {
-        const int j = rowb[e], i = pathb[e];
-        const float *Sf = Sl + 6 * i;
-        const double *f = FJ + 6 * j;
-        double h = (double)Sf[0] * f[0] + (double)Sf[1] * f[1] + (double)Sf[2] * f[2] +
-                   (double)Sf[3] * f[3] + (double)Sf[4] * f[4] + (double)Sf[5] * f[5];
-        H[e] = h;
-      }
-      wave_sync();
-      const int *rs = LT + M.lt_rs;
-#pragma unroll
-      for (int t = 0; t < 2; ++t) {
-        const int j = lane + 64 * t;
-        if (j < nv) H[rs[j + 1] - 1] += (double)dt * dmp[t];  // the diagonal closes row j
-      }
-      wave_sync();
+      stage_crba(M, lane, LT, Rl, Pl, Sl, Cl, scr, dt, H, dmp);
+      add_joint_damping(M, lane, LT, H, dt, dmp);
     }
-
-    }  // !geom_only
-    // --------------------------- muscle geometry, Hill force, J_m^T F, damping
-    {
-      float *mr = (float *)scr;          // [n_mus][3]
-      float *mF = mr + 3 * nm;           // [n_mus]
-      float *mc = mF + nm;               // [n_mus]
-      // surrogate geometry (when predictions are given): an env falls back to
-      // the exact geometry when a hinge leaves the training box or when the
-      // prediction misses the exact length of one of 32 sentinel muscles,
-      // rotated each step, by more than the tolerance. One wavefront is one
-      // env, so the decision is uniform.
-      bool exact = true;
-      if (SURR) {
-        const float *Y = Rn.geomY + (size_t)env * 4 * nm;
-        bool out = false;
-        for (int i = lane; i < nn; i += 64) {
-          if (M.jtype[i] == 2) continue;
-          const int j = M.dadr[i];
-          const float qi = q[M.qadr[i]];
-          out |= !(qi >= M.qlo[j] && qi <= M.qhi[j]);
-        }
-        bool miss = false;
-        const int ns = nm < 32 ? nm : 32;
-        if (lane < ns) {
-          const int mx = (int)((32ll * (Rn.step0 + step) + lane) % nm);
-          const int m = M.mus_int[mx];
-          float r3[3], Ld;
-          const float L = muscle_geometry<NVIA>(M, m, NVIA, Rl, Pl, Sl, qd, O, r3, Ld);
-          miss = !(fabsf(Y[mx] - L) <= Rn.fb_tol);
-        }
-        exact = __any(out) || __any(miss);
-        if (exact) {
-          status |= MS_ST_FALLBACK;
-          if (Rn.fb_count && lane == 0) Rn.fb_count[env] += 1u;
-        } else {
-          for (int m = lane; m < nm; m += 64) {
-            const int mx = M.mus_ext[m];
-            float Ld = 0.f;
-#pragma unroll
-            for (int sl = 0; sl < 3; ++sl) {
-              const int j = M.mus_span[sl * nm + m];
-              const float r = j >= 0 ? Y[nm + 3 * mx + sl] : 0.f;
-              mr[3 * m + sl] = r;
-              if (j >= 0) Ld -= r * qd[j];
-            }
-            mF[m] = Y[mx];
-            mc[m] = Ld;
-          }
-        }
-      }
-      // exact geometry: one muscle per lane and iteration (L, Ldot parked
-      // in mF, mc)
-#pragma unroll 1
-      for (int m = lane; exact && m < nm; m += 64) {
-        float r3[3], Ld;
-        const float L = muscle_geometry<NVIA>(M, m, M.grp_nvia[m >> 6], Rl, Pl, Sl, qd, O, r3, Ld);
-        mr[3 * m] = r3[0];
-        mr[3 * m + 1] = r3[1];
-        mr[3 * m + 2] = r3[2];
-        mF[m] = L;
-        mc[m] = Ld;
-        if (stages) {
-          const size_t o = (size_t)env * nm + M.mus_ext[m];
-          Rn.o_L[o] = L;
-          if (Rn.o_Ldot) Rn.o_Ldot[o] = Ld;
-          Rn.o_r[3 * o] = r3[0];
-          Rn.o_r[3 * o + 1] = r3[1];
-          Rn.o_r[3 * o + 2] = r3[2];
-        }
-      }
-      if (geom_only) return;
-      // Hill force and its velocity slope (the same lane re-reads its muscles)
-#pragma unroll
-      for (int t = 0; t < MPL; ++t) {
-        const int m = lane + 64 * t;
-        if (m >= nm) continue;
-        const float L = mF[m], Ld = mc[m];
-        const float lm = (L - M.mus_lslack[m]) * M.mus_ilopt[m];
-        const float vm = Ld * M.mus_ivl[m];
-        const float fl = hill_fl(lm), fv = hill_fv(vm), fp = hill_fp(lm);
-        const float f0 = M.mus_f0[m];
-        const float F = f0 * (act1[t] * fl * fv + fp);
-        const float cdamp = f0 * act1[t] * fl * hill_fv_slope(vm) * M.mus_ivl[m];
-        mF[m] = F;
-        mc[m] = cdamp;
-        if (stages) Rn.o_F[(size_t)env * nm + M.mus_ext[m]] = F;
-      }
-      wave_sync();
-      for (int x = lane; x < nv; x += 64) {
-        const int j = M.proj_dof[x];
-        float tau = 0.f;
-#pragma unroll 8
-        for (int e = M.proj_start[x]; e < M.proj_start[x + 1]; ++e) {
-          const int it = M.proj_item[e];
-          tau += mr[it] * mF[it / 3];
-        }
-        if (stages) Rn.o_tau[(size_t)env * nv + j] = tau;
-        rhs[j] += (double)tau;
-      }
-      for (int e = lane; e < M.n_dent; e += 64) {
-        double s = 0.0;
-#pragma unroll 8
-        for (int k = M.dent_start[e]; k < M.dent_start[e + 1]; ++k) {
-          const int it = M.dent_item[k];
-          const int m = it >> 4, a = (it >> 2) & 3, b = it & 3;
-          s += (double)mc[m] * (double)mr[3 * m + a] * (double)mr[3 * m + b];
-        }
-        H[M.dent_h[e]] += (double)dt * s;
-      }
-      wave_sync();
-    }
+    stage_muscles<MPL, NVIA, SURR, GEOM>(M, Rn, T, env, step, Rl, Pl, Sl, q, qd, O, act1, scr, dt,
+                                         stages, rhs, H, nullptr, nullptr, status);
+    if (GEOM) return;
     if (stages) {
       for (int e = lane; e < M.nnz; e += 64) Rn.o_H[(size_t)env * M.nnz + e] = H[e];
     }
-
-    // ------------------------------------------------ LTDL factorisation (FP64)
-    // H = L^T D L with Featherstone's branch-induced sparsity, as gathers:
-    // finished row k holds H_kj - sum over the descendants i of k of
-    // H_ik H_ij / d_i (j = k or an ancestor of k), and reads only finished
-    // rows of lower height. The right-hand side rides along as one more
-    // column: y_k = rhs_k - sum_i (H_ik / d_i) y_i is the solve of L^T y =
-    // rhs. Rows of equal height are independent, so a height level is one
-    // pass over its entries; when a level has few entries, P lanes split each
-    // entry's sum (fixed-order prefix sums). All tables come from the
-    // workgroup's LDS copy.
-    bool nonspd = false;
-    double *invd = (double *)scr;  // 1/d per DoF (the muscle scratch is free now)
-    const int *Lrs = LT + M.lt_rs, *Ldesc = LT + M.lt_desc, *Ldr = LT + M.lt_drange;
-    // leaves: y = rhs, pivots as assembled
-    bool fbad = false;
-    for (int j = lane; j < nv; j += 64) xs[j] = rhs[j];
-    for (int e = LT[M.lt_hlev_start] + lane; e < LT[M.lt_hlev_start + 1]; e += 64) {
-      const int w = LT[M.lt_hdof + e];
-      const int k = w & 0xFF;
-      const double d = H[Lrs[k] + (w >> 8)];
-      fbad |= !(d > 0.0);
-      invd[k] = 1.0 / d;
-    }
-    nonspd = __any(fbad);
-    wave_sync();
-    // one entry of a row at height >= 1: finished value (and its pivot when
-    // it is the diagonal) from the descendants' finished rows
-    auto entry = [&](int w, int p, int P, double &sum, int &e, int &k, int &ck, int &cj) {
-      k = w & 0xFF;
-      ck = (w >> 8) & 0xFF;
-      cj = w >> 16;
-      const bool rcol = cj == 255;
-      e = Lrs[k] + (rcol ? 0 : cj);
-      const int dr = Ldr[k], t1 = dr >> 16;
-      sum = 0.0;
-#pragma unroll 4
-      for (int t = (dr & 0xFFFF) + p; t < t1; t += P) {
-        const int di = Ldesc[t];
-        const int ri = di & 0xFFFF, i = di >> 16;
-        const double hij = rcol ? xs[i] : H[ri + cj];
-        sum += H[ri + ck] * hij * invd[i];
-      }
-    };
-    auto finish = [&](double sum, int e, int k, int ck, int cj, bool &badf) {
-      if (cj == 255) {
-        xs[k] = rhs[k] - sum;
-      } else {
-        const double v = H[e] - sum;
-        H[e] = v;
-        if (cj == ck) {
-          badf |= !(v > 0.0);
-          invd[k] = 1.0 / v;
-        }
-      }
-    };
-    for (int h = 1; h < M.n_hgat && !nonspd; ++h) {
-      const int s0 = LT[M.lt_hent_start + h], ne = LT[M.lt_hent_start + h + 1] - s0;
-      const int lp = group_log2(ne), P = 1 << lp;
-      fbad = false;
-      if (lp == 0) {
-        // more entries than lanes: two independent entries per lane in flight
-        for (int base = 0; base < ne; base += 128) {
-          const int ga = base + lane, gb = base + 64 + lane;
-          double sa = 0.0, sb = 0.0;
-          int ea = 0, ka = 0, cka = 0, cja = 0, eb = 0, kb = 0, ckb = 0, cjb = 0;
-          if (ga < ne) entry(LT[M.lt_hent + s0 + ga], 0, 1, sa, ea, ka, cka, cja);
-          if (gb < ne) entry(LT[M.lt_hent + s0 + gb], 0, 1, sb, eb, kb, ckb, cjb);
-          if (ga < ne) finish(sa, ea, ka, cka, cja, fbad);
-          if (gb < ne) finish(sb, eb, kb, ckb, cjb, fbad);
-        }
-      } else {
-        const int g = lane >> lp, p = lane & (P - 1);
-        double sum = 0.0;
-        int e = 0, k = 0, ck = 0, cj = 0;
-        if (g < ne) entry(LT[M.lt_hent + s0 + g], p, P, sum, e, k, ck, cj);
-        sum = group_sum_last(sum, lp, lane);
-        if (g < ne && p == P - 1) finish(sum, e, k, ck, cj, fbad);
-      }
-      nonspd = __any(fbad);
-      wave_sync();
-    }
-    // The trunk (single-row levels at the top, ancestor counts 0 .. n_trunk-1):
-    // its rows were gathered over their non-trunk descendants only, which
-    // leaves the block that remains once every other row is eliminated.
-    // Eliminating its rows bottom-up, row k (final once the rows below it
-    // are eliminated) updates every entry (a, b) of the rows above it, b = a
-    // or an ancestor of a, and their right-hand sides:
-    // H_ab -= H_ka H_kb / d_k, y_a -= H_ka y_k / d_k. One level per row, one
-    // FMA per entry, no two lanes writing the same entry.
-    if (M.n_trunk && !nonspd) {
-      const int *trow = LT + M.lt_trow, *tpair = LT + M.lt_tpair;
-      const int nt = M.n_trunk, npair = (nt - 1) * (nt + 2) / 2;
-      // this lane's first three entries stay in registers; all of a level's
-      // loads are issued before its stores
-      int tw[3];
-#pragma unroll
-      for (int u = 0; u < 3; ++u) tw[u] = lane + 64 * u < npair ? tpair[lane + 64 * u] : -1;
-      int wk = trow[nt - 1];
-      for (int dk = nt - 1; dk >= 0; --dk) {
-        const int k = wk & 0xFF, rk = wk >> 8;
-        const double d = H[rk + dk], xk = xs[k];
-        double hka[3], hkb[3], hab[3];
-        bool on[3], rhs[3];
-#pragma unroll
-        for (int u = 0; u < 3; ++u) {
-          const int w = tw[u], da = (w >> 16) & 0x7F, db = (w >> 23) & 0x7F;
-          on[u] = w >= 0 && da < dk;
-          rhs[u] = (w >> 30) & 1;
-          hka[u] = hkb[u] = hab[u] = 0.0;
-          if (on[u]) {
-            hka[u] = H[rk + da];
-            if (!rhs[u]) hkb[u] = H[rk + db];
-            hab[u] = rhs[u] ? xs[w & 0xFFFF] : H[w & 0xFFFF];
-          }
-        }
-        if (dk > 0) wk = trow[dk - 1];
-        if (!(d > 0.0)) {  // the same value in every lane
-          nonspd = true;
-          break;
-        }
-        const double id = 1.0 / d, yk = xk * id;
-        if (lane == 0) invd[k] = id;
-#pragma unroll
-        for (int u = 0; u < 3; ++u) {
-          if (!on[u]) continue;
-          const int e = tw[u] & 0xFFFF;
-          if (rhs[u]) xs[e] = hab[u] - hka[u] * yk;
-          else H[e] = hab[u] - hka[u] * hkb[u] * id;
-        }
-        // entries beyond the first 192 (trunks longer than 18 rows)
-        const int na = dk * (dk + 3) / 2;
-        for (int t = lane + 192; t < na; t += 64) {
-          const int w = tpair[t], e = w & 0xFFFF, da = (w >> 16) & 0x7F;
-          const double h1 = H[rk + da];
-          if (w >> 30) {
-            xs[e] -= h1 * yk;
-          } else {
-            const int db = (w >> 23) & 0x7F;
-            H[e] -= h1 * H[rk + db] * id;
-          }
-        }
-        wave_sync();
-      }
-    }
-    if (!nonspd) {
-      // L x = z with z = y / d, root first: x_k = z_k - (1/d_k) sum over the
-      // ancestors a of k of H_ka x_a. Each lane keeps its rows' sums in
-      // registers; at depth l the rows of that depth are final, and every
-      // deeper row adds the term of its (single) depth-l ancestor, which is
-      // entry l of its root-first row.
-      const unsigned char *path8 = (const unsigned char *)(LT + M.lt_path);
-      double z[2], id[2], acc[2] = {0.0, 0.0};
-      int rk[2], dk[2];
-#pragma unroll
-      for (int t = 0; t < 2; ++t) {
-        const int j = lane + 64 * t;
-        dk[t] = -1;
-        rk[t] = 0;
-        id[t] = z[t] = 0.0;
-        if (j < nv) {
-          rk[t] = Lrs[j];
-          dk[t] = Lrs[j + 1] - rk[t] - 1;
-          id[t] = invd[j];
-          z[t] = xs[j] * id[t];
-        }
-      }
-      for (int l = 0;; ++l) {
-        double h[2];
-        int c[2];
-#pragma unroll
-        for (int t = 0; t < 2; ++t) {
-          h[t] = 0.0;
-          c[t] = 0;
-          if (dk[t] > l) {
-            h[t] = H[rk[t] + l];
-            c[t] = path8[rk[t] + l];
-          }
-          if (dk[t] == l) xs[lane + 64 * t] = z[t] - acc[t] * id[t];
-        }
-        wave_sync();
-        if (l + 1 >= M.n_dlev) break;
-#pragma unroll
-        for (int t = 0; t < 2; ++t)
-          if (dk[t] > l) acc[t] += h[t] * xs[c[t]];
-      }
-    }
-
-    // ----------------------------------------------- semi-implicit Euler update
+    const bool nonspd = stage_solve(M, lane, LT, H, rhs, xs, (double *)scr);
     if (stages) {
       for (int j = lane; j < nv; j += 64) Rn.o_qdd[(size_t)env * nv + j] = nonspd ? NAN : (float)xs[j];
       break;
@@ -962,62 +1134,15 @@ __device__ __forceinline__ void step_body(const KModel &M, const KRun &Rn, int n
       status |= MS_ST_NONSPD;
       continue;
     }
-    // new velocities and hinge/slide positions in registers, checked first
-    float qdn[2], qn[2];
-    bool badn = false;
-    for (int t = 0; t < 2; ++t) {
-      const int j = lane + 64 * t;
-      qdn[t] = 0.f;
-      qn[t] = 0.f;
-      if (j < nv) {
-        qdn[t] = qd[j] + dt * (float)xs[j];
-        badn |= !isfinite(qdn[t]);
-      }
-    }
+    bool abad = false;
 #pragma unroll
-    for (int t = 0; t < MPL; ++t) badn |= !isfinite(act1[t]);
-    badn = __any(badn);
-    if (badn) {
+    for (int t = 0; t < MPL; ++t) abad |= !isfinite(act1[t]);
+    if (!stage_integrate(M, lane, q, qd, xs, dt, abad)) {
       status |= MS_ST_NONFINITE;
       continue;
     }
-    wave_sync();
-    for (int t = 0; t < 2; ++t) {
-      const int j = lane + 64 * t;
-      if (j < nv) qd[j] = qdn[t];
-    }
-    wave_sync();
-    // positions: each node's q from its own DoFs
-    for (int i = lane; i < nn; i += 64) {
-      const int a = M.qadr[i], d = M.dadr[i];
-      if (M.jtype[i] != 2) {
-        qn[0] = q[a] + dt * qd[d];
-        q[a] = qn[0];
-        continue;
-      }
-      for (int k = 0; k < 3; ++k) q[a + k] = q[a + k] + dt * qd[d + k];
-      float th[3] = {qd[d + 3] * dt, qd[d + 4] * dt, qd[d + 5] * dt};
-      float ang = sqrtf(th[0] * th[0] + th[1] * th[1] + th[2] * th[2]);
-      float dq[4];
-      if (ang < 1e-8f) {
-        dq[0] = 1.f; dq[1] = 0.5f * th[0]; dq[2] = 0.5f * th[1]; dq[3] = 0.5f * th[2];
-      } else {
-        float sn, cs;
-        sincosf(0.5f * ang, &sn, &cs);
-        float sc = sn / ang;
-        dq[0] = cs; dq[1] = sc * th[0]; dq[2] = sc * th[1]; dq[3] = sc * th[2];
-      }
-      float *x = q + a + 3;
-      float o0 = x[0] * dq[0] - x[1] * dq[1] - x[2] * dq[2] - x[3] * dq[3];
-      float o1 = x[0] * dq[1] + x[1] * dq[0] + x[2] * dq[3] - x[3] * dq[2];
-      float o2 = x[0] * dq[2] - x[1] * dq[3] + x[2] * dq[0] + x[3] * dq[1];
-      float o3 = x[0] * dq[3] + x[1] * dq[2] - x[2] * dq[1] + x[3] * dq[0];
-      float nrm = sqrtf(o0 * o0 + o1 * o1 + o2 * o2 + o3 * o3);
-      x[0] = o0 / nrm; x[1] = o1 / nrm; x[2] = o2 / nrm; x[3] = o3 / nrm;
-    }
 #pragma unroll
     for (int t = 0; t < MPL; ++t) act[t] = act1[t];
-    wave_sync();
   }
 
   if (stages) return;
@@ -1029,7 +1154,7 @@ __device__ __forceinline__ void step_body(const KModel &M, const KRun &Rn, int n
     if (mi < nm) {
       const int mx = M.mus_ext[mi];
       Rn.act[(size_t)env * nm + mx] = act[t];
-      if (exc == EXC_AR1) Rn.xar[(size_t)env * nm + mx] = xar[t];
+      if (Rn.exc == EXC_AR1) Rn.xar[(size_t)env * nm + mx] = xar[t];
     }
   }
   if (Rn.status && lane == 0) Rn.status[env] = status;
@@ -1051,23 +1176,107 @@ __global__ __launch_bounds__(256) void k_geometry(KModel M, KRun Rn, int n_steps
   step_body<MPL, NVIA, false, true>(M, Rn, n_steps);
 }
 
-// Envs per workgroup that keep the most envs resident per CU (160 KiB of
-// LDS; the workgroup's copy of the factorisation tables is shared by its
-// envs); ties go to fewer envs per workgroup.
-inline int default_env_per_wg(const Tables &t) {
-  int best = 1, most = 0;
-  for (int w = 1; w <= 4; w *= 2) {
-    const size_t per_wg = t.lt.size() * 4 + (size_t)w * t.lds_bytes;
-    if (per_wg > 160 * 1024) break;
-    const int envs = w * (int)((160 * 1024) / per_wg);
-    if (envs > most) {
-      most = envs;
-      best = w;
+// ------------------------------------------------------- the split step
+// The muscle kernel of the split step (one env per 256-thread workgroup):
+// excitation and activation, muscle geometry (or the surrogate with its
+// fallback check), Hill force, J_m^T F and the muscles' implicit damping,
+// from the node frames and motion subspaces the kinematics kernel left in
+// the workspace. MPT = muscles per thread.
+template <int MPT, int NVIA, bool SURR>
+__global__ __launch_bounds__(256) void k_muscle(KModel M, KRun Rn, KSplit W, int step) {
+  extern __shared__ __align__(16) unsigned char lds_m[];
+  const int env = blockIdx.x;
+  if (env >= Rn.n_env) return;  // uniform over the workgroup
+  const BlockTeam T{(int)threadIdx.x};
+  const int nq = M.nq, nv = M.nv, nm = M.n_mus, nn = M.n_node;
+  float *Rl = (float *)(lds_m + W.m_R);
+  float *Pl = Rl + 9;
+  float *Sl = (float *)(lds_m + W.m_S);
+  float *q = (float *)(lds_m + W.m_q);
+  float *qd = (float *)(lds_m + W.m_qd);
+  unsigned char *scr = lds_m + W.m_scr;
+  const int fl = W.flag[env];
+  float act[MPT], xar[MPT], u[MPT];
+#pragma unroll
+  for (int k = 0; k < MPT; ++k) {
+    const int mi = T.t + 256 * k;
+    const int mx = mi < nm ? M.mus_ext[mi] : 0;
+    act[k] = mi < nm ? Rn.act[(size_t)env * nm + mx] : 0.0f;
+    xar[k] = 0.0f;
+    if (Rn.exc == EXC_AR1 && mi < nm) xar[k] = Rn.xar[(size_t)env * nm + mx];
+  }
+  const bool abad = excite<MPT>(M, Rn, T, env, step, act, xar, u);
+  // the smooth-noise state advances whatever the env's state (as in the
+  // fused step)
+  if (Rn.exc == EXC_AR1) {
+#pragma unroll
+    for (int k = 0; k < MPT; ++k) {
+      const int mi = T.t + 256 * k;
+      if (mi < nm) Rn.xar[(size_t)env * nm + M.mus_ext[mi]] = xar[k];
     }
   }
-  return best;
+  if (T.any(abad) || fl != 0) {
+    if (T.t == 0) W.mflag[env] = 1;
+    return;
+  }
+  for (int i = T.t; i < 12 * nn; i += 256) Rl[i] = W.frames[(size_t)env * W.fr_stride + i];
+  for (int i = T.t; i < 6 * nv; i += 256) Sl[i] = W.S[(size_t)env * W.S_stride + i];
+  for (int i = T.t; i < nq; i += 256) q[i] = Rn.q[(size_t)env * nq + i];
+  for (int i = T.t; i < nv; i += 256) qd[i] = Rn.qd[(size_t)env * nv + i];
+  float act1[MPT];
+  activate<MPT>(M, Rn, T, env, Rn.dt, u, act, act1, false);
+  __syncthreads();
+  const V3 O = M.free_root ? v3(q[0], q[1], q[2]) : v3(0.f, 0.f, 0.f);
+  unsigned status = 0;
+  stage_muscles<MPT, NVIA, SURR, false>(M, Rn, T, env, step, Rl, Pl, Sl, q, qd, O, act1, scr, Rn.dt,
+                                        false, nullptr, nullptr, W.tau + (size_t)env * W.tau_stride,
+                                        W.dsum + (size_t)env * W.dsum_stride, status);
+  bool bad1 = false;
+#pragma unroll
+  for (int k = 0; k < MPT; ++k) {
+    const int mi = T.t + 256 * k;
+    if (mi < nm) {
+      W.actn[(size_t)env * W.act_stride + M.mus_ext[mi]] = act1[k];
+      bad1 |= !isfinite(act1[k]);
+    }
+  }
+  bad1 = T.any(bad1);
+  if (T.t == 0) {
+    W.mflag[env] = bad1 ? 2 : 0;
+    if (status && Rn.status) Rn.status[env] |= status;
+  }
 }
 
+// Launch the muscle kernel of the split step for step `step`.
+template <int NVIA>
+hipError_t launch_muscle(const KModel &k, const KRun &r, const KSplit &w, int mpt, int step,
+                         hipStream_t st) {
+  const bool surr = r.geomY != nullptr;
+  const dim3 grid(r.n_env), block(256);
+  const size_t lds = w.m_bytes;
+#define MS_LAUNCH_M(P)                                                                         \
+  do {                                                                                         \
+    const void *fn = surr ? (const void *)&k_muscle<P, NVIA, true> : (const void *)&k_muscle<P, NVIA, false>; \
+    if (lds > 65536) {                                                                         \
+      hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds); \
+      if (e != hipSuccess) return e;                                                           \
+    }                                                                                          \
+    if (surr)                                                                                  \
+      hipLaunchKernelGGL((k_muscle<P, NVIA, true>), grid, block, lds, st, k, r, w, step);     \
+    else                                                                                       \
+      hipLaunchKernelGGL((k_muscle<P, NVIA, false>), grid, block, lds, st, k, r, w, step);    \
+  } while (0)
+  if (mpt <= 1)
+    MS_LAUNCH_M(1);
+  else if (mpt <= 2)
+    MS_LAUNCH_M(2);
+  else
+    MS_LAUNCH_M(4);
+#undef MS_LAUNCH_M
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------ launchers
 template <int MPL, int NVIA>
 hipError_t launch_k(const Tables &t, const KModel &k, const KRun &r, int n_env, int n_steps,
                     hipStream_t st) {

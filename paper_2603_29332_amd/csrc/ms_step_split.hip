@@ -1,0 +1,185 @@
+// ms_step_split.hip -- the kinematics/dynamics and factorisation kernels of
+// the split step (the muscle kernel sits with the via-point instantiations).
+//
+// Per physics step, for every env:
+//  1. k_front (one wavefront per env): state check, forward kinematics,
+//     contacts, Newton-Euler bias (right-hand side), composite-rigid-body
+//     mass matrix; leaves node frames, motion subspaces, H and rhs in the
+//     workspace;
+//  2. k_muscle (ms_step_kernel.h): excitation, activation, muscles;
+//  3. k_back (one wavefront per env): H += dt (joint and muscle damping),
+//     rhs += J_m^T F, LTDL factorisation and solves in FP64, semi-implicit
+//     Euler, commit of the new state.
+// Each kernel stages only its part of the model's LDS table, so its LDS
+// block per env is about half the fused step's and more envs stay resident
+// per CU.
+#include "ms_step_kernel.h"
+
+namespace ms {
+
+__global__ __launch_bounds__(1024) void k_front(KModel M, KRun Rn, KSplit W, int step) {
+  extern __shared__ __align__(16) unsigned char lds_f[];
+  const int wave = threadIdx.x >> 6;
+  const int env = blockIdx.x * (blockDim.x >> 6) + wave;
+  const int lane = threadIdx.x & 63;
+  int *LT = (int *)lds_f;  // words [0, lt_front_end) of the model's table
+  for (int i = threadIdx.x; i < M.lt_front_end; i += blockDim.x) LT[i] = M.lt[i];
+  __syncthreads();  // the only workgroup-wide barrier
+  if (env >= Rn.n_env) return;
+  unsigned char *lds = lds_f + (size_t)M.lt_front_end * 4 + (size_t)wave * W.f_bytes;
+  const int nq = M.nq, nv = M.nv, nn = M.n_node;
+  float *q = (float *)(lds + W.f_q);
+  float *qd = (float *)(lds + W.f_qd);
+  float *Rl = (float *)(lds + W.f_R);
+  float *Pl = Rl + 9;
+  float *Sl = (float *)(lds + W.f_S);
+  float *Cl = (float *)(lds + W.f_con);
+  unsigned char *scr = lds + W.f_scr;
+  float *Vl = (float *)scr;
+  float *Al = Vl + 6 * nn;
+  float *Fl = Al + 6 * nn;
+  bool bad = false;
+  for (int i = lane; i < nq; i += 64) {
+    const float v = Rn.q[(size_t)env * nq + i];
+    q[i] = v;
+    bad |= !isfinite(v);
+  }
+  for (int i = lane; i < nv; i += 64) {
+    const float v = Rn.qd[(size_t)env * nv + i];
+    qd[i] = v;
+    bad |= !isfinite(v);
+  }
+  if (__any(bad)) {
+    if (lane == 0) W.flag[env] = 1;
+    return;
+  }
+  wave_sync();
+  const int *tlev = LT + M.lt_tlev, *tnode = LT + M.lt_tnode;
+  const int *sbs = LT + M.lt_subb_start, *scs = LT + M.lt_subc_start;
+  const unsigned char *sbl = (const unsigned char *)(LT + M.lt_subb);
+  const unsigned char *scl = (const unsigned char *)(LT + M.lt_subc);
+  const V3 O = M.free_root ? v3(q[0], q[1], q[2]) : v3(0.f, 0.f, 0.f);
+  const V3 g = v3(M.gx, M.gy, M.gz);
+  stage_fk(M, lane, tlev, tnode, q, qd, Rl, Sl, Vl, Al, O, g);
+  // node frames and motion subspaces for the muscle kernel
+  float *gf = W.frames + (size_t)env * W.fr_stride;
+  for (int i = lane; i < 3 * nn; i += 64) ((float4 *)gf)[i] = ((const float4 *)Rl)[i];
+  float *gs = W.S + (size_t)env * W.S_stride;
+  for (int i = lane; i < 3 * nv; i += 64) ((float2 *)gs)[i] = ((const float2 *)Sl)[i];
+  stage_contacts(M, lane, Rl, Vl, Cl, O, Rn.dt, Rn.contact);
+  stage_rnea(M, lane, Rl, Pl, Vl, Al, Fl, Cl, Sl, qd, sbs, sbl, scs, scl,
+             W.rhs + (size_t)env * W.rhs_stride, nullptr);
+  float dmp[2];
+  stage_crba(M, lane, LT, Rl, Pl, Sl, Cl, scr, Rn.dt, W.H + (size_t)env * W.H_stride, dmp);
+  if (lane == 0) W.flag[env] = 0;
+}
+
+__global__ __launch_bounds__(1024) void k_back(KModel M, KRun Rn, KSplit W, int step) {
+  extern __shared__ __align__(16) unsigned char lds_b[];
+  const int wave = threadIdx.x >> 6;
+  const int env = blockIdx.x * (blockDim.x >> 6) + wave;
+  const int lane = threadIdx.x & 63;
+  // words [lt_back_begin, lt_words) of the model's table, indexed with the
+  // table's own offsets
+  const int nw = M.lt_words - M.lt_back_begin;
+  for (int i = threadIdx.x; i < nw; i += blockDim.x) ((int *)lds_b)[i] = M.lt[M.lt_back_begin + i];
+  __syncthreads();  // the only workgroup-wide barrier
+  if (env >= Rn.n_env) return;
+  const int *LT = (const int *)lds_b - M.lt_back_begin;
+  unsigned char *lds = lds_b + (size_t)nw * 4 + (size_t)wave * W.b_bytes;
+  const int nq = M.nq, nv = M.nv, nm = M.n_mus;
+  const int fl = W.flag[env] | W.mflag[env];
+  if (fl & 1) {
+    if (lane == 0 && Rn.status) Rn.status[env] |= MS_ST_NONFINITE;
+    return;
+  }
+  float *q = (float *)(lds + W.b_q);
+  float *qd = (float *)(lds + W.b_qd);
+  double *rhs = (double *)(lds + W.b_rhs);
+  double *xs = (double *)(lds + W.b_x);
+  double *invd = (double *)(lds + W.b_invd);
+  double *H = (double *)(lds + W.b_H);
+  const float dt = Rn.dt;
+  float dmp[2];
+#pragma unroll
+  for (int t = 0; t < 2; ++t) dmp[t] = lane + 64 * t < nv ? M.damping[lane + 64 * t] : 0.f;
+  for (int i = lane; i < nq; i += 64) q[i] = Rn.q[(size_t)env * nq + i];
+  for (int i = lane; i < nv; i += 64) {
+    qd[i] = Rn.qd[(size_t)env * nv + i];
+    rhs[i] = W.rhs[(size_t)env * W.rhs_stride + i] + (double)W.tau[(size_t)env * W.tau_stride + i];
+  }
+  const double *gH = W.H + (size_t)env * W.H_stride;
+  for (int e = lane; e < M.nnz; e += 64) H[e] = gH[e];
+  wave_sync();
+  add_joint_damping(M, lane, LT, H, dt, dmp);
+  const double *gd = W.dsum + (size_t)env * W.dsum_stride;
+  for (int e = lane; e < M.n_dent; e += 64) H[M.dent_h[e]] += (double)dt * gd[e];
+  wave_sync();
+  if (stage_solve(M, lane, LT, H, rhs, xs, invd)) {
+    if (lane == 0 && Rn.status) Rn.status[env] |= MS_ST_NONSPD;
+    return;
+  }
+  if (!stage_integrate(M, lane, q, qd, xs, dt, (fl & 2) != 0)) {
+    if (lane == 0 && Rn.status) Rn.status[env] |= MS_ST_NONFINITE;
+    return;
+  }
+  for (int i = lane; i < nq; i += 64) Rn.q[(size_t)env * nq + i] = q[i];
+  for (int i = lane; i < nv; i += 64) Rn.qd[(size_t)env * nv + i] = qd[i];
+  const float *an = W.actn + (size_t)env * W.act_stride;
+  for (int i = lane; i < nm; i += 64) Rn.act[(size_t)env * nm + i] = an[i];
+}
+
+namespace {
+size_t front_lds(const KModel &k, const KSplit &w, int W) {
+  return (size_t)k.lt_front_end * 4 + (size_t)W * w.f_bytes;
+}
+size_t back_lds(const KModel &k, const KSplit &w, int W) {
+  return (size_t)(k.lt_words - k.lt_back_begin) * 4 + (size_t)W * w.b_bytes;
+}
+hipError_t allow_lds(const void *fn, size_t lds) {
+  if (lds <= 65536) return hipSuccess;
+  return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+}
+// envs per workgroup (1..16) with the most resident envs per CU
+int best_w(const void *fn, size_t (*lds_of)(const KModel &, const KSplit &, int), const KModel &k,
+           const KSplit &w) {
+  int best = 1, most = 0;
+  for (int W = 1; W <= 16; ++W) {
+    const size_t lds = lds_of(k, w, W);
+    if (lds > 160 * 1024) break;
+    if (allow_lds(fn, lds) != hipSuccess) break;
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, 64 * W, lds) != hipSuccess) break;
+    if (nb * W > most) {
+      most = nb * W;
+      best = W;
+    }
+  }
+  return best;
+}
+}  // namespace
+
+void split_env_per_wg(const KModel &k, const KSplit &w, int *w_front, int *w_back) {
+  *w_front = best_w((const void *)&k_front, front_lds, k, w);
+  *w_back = best_w((const void *)&k_back, back_lds, k, w);
+}
+
+hipError_t launch_front(const KModel &k, const KRun &r, const KSplit &w, int W, int step,
+                        hipStream_t st) {
+  const size_t lds = front_lds(k, w, W);
+  hipError_t e = allow_lds((const void *)&k_front, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_front, dim3((r.n_env + W - 1) / W), dim3(64 * W), lds, st, k, r, w, step);
+  return hipGetLastError();
+}
+
+hipError_t launch_back(const KModel &k, const KRun &r, const KSplit &w, int W, int step,
+                       hipStream_t st) {
+  const size_t lds = back_lds(k, w, W);
+  hipError_t e = allow_lds((const void *)&k_back, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_back, dim3((r.n_env + W - 1) / W), dim3(64 * W), lds, st, k, r, w, step);
+  return hipGetLastError();
+}
+
+}  // namespace ms

@@ -6,6 +6,8 @@
 #include "../../include/ms.h"
 #include "ms_model.h"
 
+#include <vector>
+
 namespace ms {
 
 // ----------------------------------------------------------------- params
@@ -36,7 +38,8 @@ struct KModel {
   const int *lt;
   int lt_words, lt_hent_start, lt_hlev_start, lt_hent, lt_hdof, lt_desc, lt_drange,
       lt_rs, lt_trow, lt_tpair, lt_path, lt_tlev, lt_tnode, lt_subb_start, lt_subc_start, lt_subb,
-      lt_subc, lt_nnzrow;
+      lt_subc, lt_nnzrow, lt_cinode, lt_dofci, lt_front_end, lt_back_begin;
+  int n_ci;
   int off_flag, off_q, off_qd, off_R, off_P, off_S, off_con, off_rhs, off_x, off_H,
       off_scr, off_V, off_A, off_F;
   int lds_env;  // bytes of one env's LDS block
@@ -70,6 +73,38 @@ struct KRun {
 
 enum { EXC_ARRAY = MS_EXC_ARRAY, EXC_IID = MS_EXC_IID, EXC_AR1 = MS_EXC_AR1 };
 
+// The split step's per-env device workspace (arrays [n_env][stride],
+// strides in elements) and its kernels' LDS layouts (byte offsets into one
+// env's block). The kinematics/dynamics kernel writes frames, S, H and rhs
+// and flag; the muscle kernel writes tau, dsum, actn and mflag; the
+// factorisation kernel reads them all.
+struct KSplit {
+  float *frames, *S, *tau, *actn;
+  double *H, *rhs, *dsum;
+  int *flag, *mflag;
+  int fr_stride, S_stride, H_stride, rhs_stride, tau_stride, dsum_stride, act_stride;
+  int f_q, f_qd, f_R, f_S, f_con, f_scr, f_bytes;
+  int b_q, b_qd, b_rhs, b_x, b_invd, b_H, b_bytes;
+  int m_R, m_S, m_q, m_qd, m_scr, m_bytes;
+};
+
+// Envs per workgroup that keep the most envs resident per CU (160 KiB of
+// LDS; the workgroup's copy of the factorisation tables is shared by its
+// envs); ties go to fewer envs per workgroup.
+inline int default_env_per_wg(const Tables &t) {
+  int best = 1, most = 0;
+  for (int w = 1; w <= 4; w *= 2) {
+    const size_t per_wg = t.lt.size() * 4 + (size_t)w * t.lds_bytes;
+    if (per_wg > 160 * 1024) break;
+    const int envs = w * (int)((160 * 1024) / per_wg);
+    if (envs > most) {
+      most = envs;
+      best = w;
+    }
+  }
+  return best;
+}
+
 // Launch k_step (or k_step_surrogate when r.geomY is set) for a model whose
 // muscles have at most NVIA via-points; one instantiation per translation
 // unit (ms_step_v2/4/6/8.hip).
@@ -81,6 +116,25 @@ extern template hipError_t launch_nvia<4>(const Tables &, const KModel &, const 
 extern template hipError_t launch_nvia<6>(const Tables &, const KModel &, const KRun &, int, int, hipStream_t);
 extern template hipError_t launch_nvia<8>(const Tables &, const KModel &, const KRun &, int, int, hipStream_t);
 
+// The split step's muscle kernel for step `step` (mpt muscles per thread).
+template <int NVIA>
+hipError_t launch_muscle(const KModel &k, const KRun &r, const KSplit &w, int mpt, int step,
+                         hipStream_t st);
+extern template hipError_t launch_muscle<2>(const KModel &, const KRun &, const KSplit &, int, int, hipStream_t);
+extern template hipError_t launch_muscle<4>(const KModel &, const KRun &, const KSplit &, int, int, hipStream_t);
+extern template hipError_t launch_muscle<6>(const KModel &, const KRun &, const KSplit &, int, int, hipStream_t);
+extern template hipError_t launch_muscle<8>(const KModel &, const KRun &, const KSplit &, int, int, hipStream_t);
+
+// The split step's kinematics/dynamics and factorisation kernels for step
+// `step`, w_front / w_back envs per workgroup (ms_step_split.hip).
+hipError_t launch_front(const KModel &k, const KRun &r, const KSplit &w, int w_front, int step,
+                        hipStream_t st);
+hipError_t launch_back(const KModel &k, const KRun &r, const KSplit &w, int w_back, int step,
+                       hipStream_t st);
+// Envs per workgroup of those two kernels that keep the most envs resident
+// per CU (occupancy calculator over 1..16 envs; ties go to fewer).
+void split_env_per_wg(const KModel &k, const KSplit &w, int *w_front, int *w_back);
+
 }  // namespace ms
 
 // The model object behind the C ABI's opaque handle.
@@ -89,11 +143,32 @@ struct ms_model {
   ms::KModel k;
   void *dbuf = nullptr;
   size_t dbytes = 0;
+  int schedule = MS_SCHED_AUTO;  // as set by ms_model_set_schedule
+  // the split step's workspace for up to ws_cap envs (replaced buffers stay
+  // allocated until destroy: queued launches may still use them)
+  ms::KSplit ks{};
+  int ws_cap = 0;
+  std::vector<void *> ws_owned;
+  int w_front = 0, w_back = 0;  // envs per workgroup of its kernels (0: not chosen yet)
 };
 
-// Launch the step kernel variant the run arguments select (exact, surrogate
-// or geometry only) for n_env envs and n_steps steps on stream st.
-hipError_t launch(const ms_model *m, const ms::KRun &r, int n_env, int n_steps, hipStream_t st);
+// The schedule a model's steps run with (MS_SCHED_FUSED or MS_SCHED_SPLIT).
+int effective_schedule(const ms_model *m);
+
+// Grow the split step's workspace to n_env envs (allocates; refused inside
+// a stream capture on st, where no allocation may happen).
+ms_status reserve_split(ms_model *m, int n_env, hipStream_t st);
+
+// Launch the step for n_env envs and n_steps steps on stream st: the fused
+// kernel variant the run arguments select (exact, surrogate or geometry
+// only), or, for a model on the split schedule, its three kernels per step
+// (stage outputs and geometry-only runs always use the fused kernel).
+// Returns hipErrorOutOfMemory when the split workspace cannot be grown
+// (message in ms_last_error).
+hipError_t launch(ms_model *m, const ms::KRun &r, int n_env, int n_steps, hipStream_t st);
+// launch() behind the C ABI: grows the split workspace first, returns an
+// ms_status with the message in ms_last_error.
+ms_status run_steps(ms_model *m, const ms::KRun &r, int n_env, int n_steps, hipStream_t st);
 
 // ms_rollout with a chosen number of envs per workgroup (1, 2 or 4; 0 picks
 // the count that keeps the most envs resident per CU); errors

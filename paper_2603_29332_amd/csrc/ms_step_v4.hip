@@ -4,4 +4,5 @@
 
 namespace ms {
 template hipError_t launch_nvia<4>(const Tables &, const KModel &, const KRun &, int, int, hipStream_t);
+template hipError_t launch_muscle<4>(const KModel &, const KRun &, const KSplit &, int, int, hipStream_t);
 }  // namespace ms

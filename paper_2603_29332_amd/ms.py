@@ -19,6 +19,7 @@ MS_ST_NONFINITE = 1
 MS_ST_NONSPD = 2
 MS_ST_FALLBACK = 4
 EXC_ARRAY, EXC_IID, EXC_AR1 = 0, 1, 2
+SCHED_AUTO, SCHED_FUSED, SCHED_SPLIT = 0, 1, 2
 ISSUE_CONCURRENT, ISSUE_CONCURRENT_MOST_WORK, ISSUE_SERIAL = 0, 1, 2
 
 EXPORTED = ("ms_model_create", "ms_model_destroy", "ms_model_info_get",
@@ -32,7 +33,8 @@ EXPORTED = ("ms_model_create", "ms_model_destroy", "ms_model_info_get",
             "ms_batch_config", "ms_batch_set_config", "ms_batch_last_error",
             "ms_policy_create", "ms_policy_destroy", "ms_policy_dims", "ms_policy_params",
             "ms_policy_act", "ms_policy_rollout", "ms_surrogate_reserve",
-            "ms_surrogate_forward_noalloc", "ms_surrogate_noalloc_max", "ms_policy_reserve")
+            "ms_surrogate_forward_noalloc", "ms_surrogate_noalloc_max", "ms_policy_reserve",
+            "ms_model_set_schedule", "ms_model_get_schedule", "ms_model_reserve")
 
 _fptr = C.POINTER(C.c_float)
 _iptr = C.POINTER(C.c_int32)
@@ -93,6 +95,9 @@ def lib():
     L.ms_model_destroy.argtypes = [vp]
     L.ms_model_destroy.restype = None
     L.ms_model_info_get.argtypes = [vp, C.POINTER(MsInfo)]
+    L.ms_model_set_schedule.argtypes = [vp, C.c_int32]
+    L.ms_model_get_schedule.argtypes = [vp, _iptr]
+    L.ms_model_reserve.argtypes = [vp, C.c_int32]
     L.ms_step_batch.argtypes = [vp, C.c_int32, vp, vp, vp, vp, vp, C.POINTER(MsOpts), vp]
     L.ms_rollout.argtypes = [vp, C.c_int32, vp, vp, vp, vp, C.POINTER(MsExc), C.c_int32,
                              C.POINTER(MsOpts), vp]
@@ -233,6 +238,22 @@ class Model:
                 lib().ms_model_destroy(self.h)
         except Exception:
             pass
+
+    def set_schedule(self, schedule):
+        """SCHED_AUTO, SCHED_FUSED or SCHED_SPLIT (same results, different
+        kernels)."""
+        _check(lib().ms_model_set_schedule(self.h, int(schedule)))
+
+    def schedule(self):
+        """The schedule steps run with now (SCHED_FUSED or SCHED_SPLIT)."""
+        v = C.c_int32()
+        _check(lib().ms_model_get_schedule(self.h, C.byref(v)))
+        return int(v.value)
+
+    def reserve(self, n_env):
+        """Reserve the split schedule's workspace for n_env envs (allocates
+        now, so later calls, e.g. inside a graph capture, do not)."""
+        _check(lib().ms_model_reserve(self.h, int(n_env)))
 
     def spans(self):
         s = np.zeros((self.n_mus, 3), np.int32)

@@ -134,6 +134,7 @@ def test_calls_recorded_in_a_caller_graph_replay_like_eager_calls(three):
     m, gm, init, n = mods[2], gms[2], inits[2], n_env[2]
     A, B = _fresh(m, init, n), _fresh(m, init, n)
     kw = dict(kind=ms.EXC_IID, seed=3, step0=7)
+    gm.reserve(n)        # no allocation may happen inside the capture
     torch.cuda.synchronize()
     g = torch.cuda.CUDAGraph()
     with torch.cuda.graph(g):

@@ -175,6 +175,17 @@ ms_status ms_model_get_schedule(const ms_model *m, int32_t *schedule);
  * before capturing. All buffers of a growth are taken or none (MS_E_ALLOC
  * keeps the previous workspace). */
 ms_status ms_model_reserve(ms_model *m, int32_t n_env);
+/* Per-kernel timing of the split schedule, for measurement: with every =
+ * N > 0, every N-th step of each later split call (steps 0, N, 2N, ... of
+ * the call; outside stream captures) records a pair of HIP events around
+ * each of its three kernels on the launch stream (each pair costs a few
+ * microseconds of gap between kernels, so sampling keeps the overhead
+ * small); every = 0 turns it off (the default). ms_model_kernel_times waits
+ * for the recorded events, writes the summed durations in milliseconds of
+ * the kinematics/dynamics, muscle and factorisation kernels to ms3[0..2]
+ * and the number of steps timed to *n_steps, and starts a new count. */
+ms_status ms_model_set_kernel_timing(ms_model *m, int32_t every);
+ms_status ms_model_kernel_times(ms_model *m, double *ms3, int64_t *n_steps);
 
 ms_status ms_model_info_get(const ms_model *m, ms_model_info *out);
 

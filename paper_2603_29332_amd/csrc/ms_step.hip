@@ -105,17 +105,47 @@ hipError_t launch(ms_model *m, const ms::KRun &r, int n_env, int n_steps, hipStr
   }
   if (reserve_split(m, n_env, st) != MS_OK) return hipErrorOutOfMemory;
   const ms::KSplit &w = m->ks;
-  if (!m->w_front) ms::split_env_per_wg(m->k, w, &m->w_front, &m->w_back);
+  if (m->w_n_env != n_env) {
+    ms::split_env_per_wg(m->k, w, n_env, &m->w_front, &m->w_back);
+    m->w_n_env = n_env;
+  }
   const int mpt = (m->t.n_mus + 255) / 256;
-  for (int s = 0; s < n_steps; ++s) {
-    hipError_t e = ms::launch_front(m->k, r, w, m->w_front, s, st);
-    if (e == hipSuccess) {
-      if (nvia <= 2) e = ms::launch_muscle<2>(m->k, r, w, mpt, s, st);
-      else if (nvia <= 4) e = ms::launch_muscle<4>(m->k, r, w, mpt, s, st);
-      else if (nvia <= 6) e = ms::launch_muscle<6>(m->k, r, w, mpt, s, st);
-      else e = ms::launch_muscle<8>(m->k, r, w, mpt, s, st);
+  bool timed = m->timing > 0;
+  if (timed) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    timed = hipStreamIsCapturing(st, &cs) == hipSuccess && cs == hipStreamCaptureStatusNone;
+  }
+  // one kernel, bracketed by timing events when timing is on
+  int s = 0;
+  auto timed_launch = [&](int kernel, auto &&fn) -> hipError_t {
+    if (!timed || s % m->timing) return fn();
+    hipEvent_t ev[2];
+    for (int i = 0; i < 2; ++i) {
+      if (m->ev_free.empty()) {
+        hipError_t e = hipEventCreate(&ev[i]);
+        if (e != hipSuccess) return e;
+      } else {
+        ev[i] = m->ev_free.back();
+        m->ev_free.pop_back();
+      }
     }
-    if (e == hipSuccess) e = ms::launch_back(m->k, r, w, m->w_back, s, st);
+    hipError_t e = hipEventRecord(ev[0], st);
+    if (e == hipSuccess) e = fn();
+    if (e == hipSuccess) e = hipEventRecord(ev[1], st);
+    m->ev_pending.push_back({kernel, ev[0], ev[1]});
+    return e;
+  };
+  for (s = 0; s < n_steps; ++s) {
+    hipError_t e = timed_launch(0, [&] { return ms::launch_front(m->k, r, w, m->w_front, s, st); });
+    if (e == hipSuccess)
+      e = timed_launch(1, [&] {
+        if (nvia <= 2) return ms::launch_muscle<2>(m->k, r, w, mpt, s, st);
+        if (nvia <= 4) return ms::launch_muscle<4>(m->k, r, w, mpt, s, st);
+        if (nvia <= 6) return ms::launch_muscle<6>(m->k, r, w, mpt, s, st);
+        return ms::launch_muscle<8>(m->k, r, w, mpt, s, st);
+      });
+    if (e == hipSuccess)
+      e = timed_launch(2, [&] { return ms::launch_back(m->k, r, w, m->w_back, s, st); });
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -259,6 +289,11 @@ void ms_model_destroy(ms_model *m) {
   if (!m) return;
   if (m->dbuf) (void)hipFree(m->dbuf);
   for (void *p : m->ws_owned) (void)hipFree(p);
+  for (const auto &p : m->ev_pending) {
+    (void)hipEventDestroy(p.a);
+    (void)hipEventDestroy(p.b);
+  }
+  for (hipEvent_t e : m->ev_free) (void)hipEventDestroy(e);
   delete m;
 }
 
@@ -275,6 +310,38 @@ ms_status ms_model_get_schedule(const ms_model *m, int32_t *schedule) {
   g_err.clear();
   if (!m || !schedule) return fail(MS_E_ARG, "NULL argument");
   *schedule = effective_schedule(m);
+  return MS_OK;
+}
+
+ms_status ms_model_set_kernel_timing(ms_model *m, int32_t every) {
+  g_err.clear();
+  if (!m) return fail(MS_E_ARG, "model is NULL");
+  if (every < 0) return fail(MS_E_ARG, "every must be >= 0");
+  m->timing = every;
+  return MS_OK;
+}
+
+ms_status ms_model_kernel_times(ms_model *m, double *ms3, int64_t *n_steps) {
+  g_err.clear();
+  if (!m || !ms3 || !n_steps) return fail(MS_E_ARG, "NULL argument");
+  double sum[3] = {0.0, 0.0, 0.0};
+  int64_t n[3] = {0, 0, 0};
+  hipError_t e = hipSuccess;
+  for (const auto &p : m->ev_pending) {
+    if (e == hipSuccess) e = hipEventSynchronize(p.b);
+    float t = 0.0f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&t, p.a, p.b);
+    if (e == hipSuccess) {
+      sum[p.kernel] += t;
+      n[p.kernel] += 1;
+    }
+    m->ev_free.push_back(p.a);
+    m->ev_free.push_back(p.b);
+  }
+  m->ev_pending.clear();
+  if (e != hipSuccess) return fail(MS_E_HIP, std::string("kernel timing: ") + hipGetErrorString(e));
+  for (int k = 0; k < 3; ++k) ms3[k] = sum[k];
+  *n_steps = n[2];
   return MS_OK;
 }
 

@@ -1183,7 +1183,7 @@ __global__ __launch_bounds__(256) void k_geometry(KModel M, KRun Rn, int n_steps
 // from the node frames and motion subspaces the kinematics kernel left in
 // the workspace. MPT = muscles per thread.
 template <int MPT, int NVIA, bool SURR>
-__global__ __launch_bounds__(256) void k_muscle(KModel M, KRun Rn, KSplit W, int step) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_muscle(KModel M, KRun Rn, KSplit W, int step) {
   extern __shared__ __align__(16) unsigned char lds_m[];
   const int env = blockIdx.x;
   if (env >= Rn.n_env) return;  // uniform over the workgroup
@@ -1270,6 +1270,8 @@ hipError_t launch_muscle(const KModel &k, const KRun &r, const KSplit &w, int mp
     MS_LAUNCH_M(1);
   else if (mpt <= 2)
     MS_LAUNCH_M(2);
+  else if (mpt <= 3)
+    MS_LAUNCH_M(3);
   else
     MS_LAUNCH_M(4);
 #undef MS_LAUNCH_M

@@ -15,6 +15,8 @@
 // per CU.
 #include "ms_step_kernel.h"
 
+#include <algorithm>
+
 namespace ms {
 
 __global__ __launch_bounds__(1024) void k_front(KModel M, KRun Rn, KSplit W, int step) {
@@ -140,28 +142,45 @@ hipError_t allow_lds(const void *fn, size_t lds) {
   if (lds <= 65536) return hipSuccess;
   return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
 }
-// envs per workgroup (1..16) with the most resident envs per CU
+// Envs per workgroup (1..16) for n_env envs on n_cu CUs. With W envs per
+// workgroup and nb workgroups resident per CU, the busiest CU receives
+// ceil(ceil(n_env / W) / n_cu) workgroups and runs them in rounds of nb; a
+// latency-bound kernel takes about as long per round whatever the round
+// holds, but a fuller round shares each CU among more envs. The cost is
+// rounds x (envs resident in a round); ties go to the larger W (fewer copies
+// of the shared table).
 int best_w(const void *fn, size_t (*lds_of)(const KModel &, const KSplit &, int), const KModel &k,
-           const KSplit &w) {
-  int best = 1, most = 0;
+           const KSplit &w, int n_env, int n_cu) {
+  int best = 1;
+  long long best_cost = -1;
   for (int W = 1; W <= 16; ++W) {
     const size_t lds = lds_of(k, w, W);
     if (lds > 160 * 1024) break;
     if (allow_lds(fn, lds) != hipSuccess) break;
     int nb = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, 64 * W, lds) != hipSuccess) break;
-    if (nb * W > most) {
-      most = nb * W;
+    if (nb <= 0) continue;
+    const long long wgs = (n_env + W - 1) / W, wgs_cu = (wgs + n_cu - 1) / n_cu;
+    const long long rounds = (wgs_cu + nb - 1) / nb;
+    const long long cost = rounds * std::min<long long>(nb, wgs_cu) * W;
+    if (best_cost < 0 || cost <= best_cost) {
       best = W;
+      best_cost = cost;
     }
   }
   return best;
 }
 }  // namespace
 
-void split_env_per_wg(const KModel &k, const KSplit &w, int *w_front, int *w_back) {
-  *w_front = best_w((const void *)&k_front, front_lds, k, w);
-  *w_back = best_w((const void *)&k_back, back_lds, k, w);
+void split_env_per_wg(const KModel &k, const KSplit &w, int n_env, int *w_front, int *w_back) {
+  int dev = 0, n_cu = 256;
+  if (hipGetDevice(&dev) == hipSuccess) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
+      n_cu = v;
+  }
+  *w_front = best_w((const void *)&k_front, front_lds, k, w, n_env, n_cu);
+  *w_back = best_w((const void *)&k_back, back_lds, k, w, n_env, n_cu);
 }
 
 hipError_t launch_front(const KModel &k, const KRun &r, const KSplit &w, int W, int step,

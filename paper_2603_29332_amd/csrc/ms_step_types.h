@@ -131,9 +131,11 @@ hipError_t launch_front(const KModel &k, const KRun &r, const KSplit &w, int w_f
                         hipStream_t st);
 hipError_t launch_back(const KModel &k, const KRun &r, const KSplit &w, int w_back, int step,
                        hipStream_t st);
-// Envs per workgroup of those two kernels that keep the most envs resident
-// per CU (occupancy calculator over 1..16 envs; ties go to fewer).
-void split_env_per_wg(const KModel &k, const KSplit &w, int *w_front, int *w_back);
+// Envs per workgroup of those two kernels for a launch over n_env envs:
+// the fewest rounds of resident envs on the device's CUs (occupancy
+// calculator over 1..16 envs per workgroup), then the fewest envs per CU
+// giving that many rounds.
+void split_env_per_wg(const KModel &k, const KSplit &w, int n_env, int *w_front, int *w_back);
 
 }  // namespace ms
 
@@ -149,7 +151,17 @@ struct ms_model {
   ms::KSplit ks{};
   int ws_cap = 0;
   std::vector<void *> ws_owned;
-  int w_front = 0, w_back = 0;  // envs per workgroup of its kernels (0: not chosen yet)
+  // envs per workgroup of its kernels, chosen for w_n_env envs
+  int w_front = 0, w_back = 0, w_n_env = 0;
+  // per-kernel timing of the split schedule (ms_model_set_kernel_timing):
+  // event pairs recorded around each kernel, (kernel, start, end)
+  int timing = 0;  // time every timing-th step of each call (0: off)
+  std::vector<hipEvent_t> ev_free;
+  struct Timed {
+    int kernel;
+    hipEvent_t a, b;
+  };
+  std::vector<Timed> ev_pending;
 };
 
 // The schedule a model's steps run with (MS_SCHED_FUSED or MS_SCHED_SPLIT).

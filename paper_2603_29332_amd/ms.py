@@ -34,7 +34,8 @@ EXPORTED = ("ms_model_create", "ms_model_destroy", "ms_model_info_get",
             "ms_policy_create", "ms_policy_destroy", "ms_policy_dims", "ms_policy_params",
             "ms_policy_act", "ms_policy_rollout", "ms_surrogate_reserve",
             "ms_surrogate_forward_noalloc", "ms_surrogate_noalloc_max", "ms_policy_reserve",
-            "ms_model_set_schedule", "ms_model_get_schedule", "ms_model_reserve")
+            "ms_model_set_schedule", "ms_model_get_schedule", "ms_model_reserve",
+            "ms_model_set_kernel_timing", "ms_model_kernel_times")
 
 _fptr = C.POINTER(C.c_float)
 _iptr = C.POINTER(C.c_int32)
@@ -98,6 +99,8 @@ def lib():
     L.ms_model_set_schedule.argtypes = [vp, C.c_int32]
     L.ms_model_get_schedule.argtypes = [vp, _iptr]
     L.ms_model_reserve.argtypes = [vp, C.c_int32]
+    L.ms_model_set_kernel_timing.argtypes = [vp, C.c_int32]
+    L.ms_model_kernel_times.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
     L.ms_step_batch.argtypes = [vp, C.c_int32, vp, vp, vp, vp, vp, C.POINTER(MsOpts), vp]
     L.ms_rollout.argtypes = [vp, C.c_int32, vp, vp, vp, vp, C.POINTER(MsExc), C.c_int32,
                              C.POINTER(MsOpts), vp]
@@ -254,6 +257,19 @@ class Model:
         """Reserve the split schedule's workspace for n_env envs (allocates
         now, so later calls, e.g. inside a graph capture, do not)."""
         _check(lib().ms_model_reserve(self.h, int(n_env)))
+
+    def set_kernel_timing(self, every=1):
+        """Record HIP events around the split-schedule kernels of every
+        every-th step of each call from now on (0: off)."""
+        _check(lib().ms_model_set_kernel_timing(self.h, int(every)))
+
+    def kernel_times(self):
+        """(summed ms of the kinematics/dynamics, muscle and factorisation
+        kernels, steps timed) since the last call; waits for the events."""
+        t = (C.c_double * 3)()
+        n = C.c_int64()
+        _check(lib().ms_model_kernel_times(self.h, t, C.byref(n)))
+        return [float(x) for x in t], int(n.value)
 
     def spans(self):
         s = np.zeros((self.n_mus, 3), np.int32)

@@ -211,6 +211,47 @@ ms_status ms_rollout(ms_model *m, int32_t n_env, float *q, float *qd,
                      float *act, uint32_t *status, const ms_excitation *exc,
                      int32_t n_steps, const ms_step_opts *opts, void *stream);
 
+/* Per-step observables of a rollout (Methods, "Observation space": muscle
+ * activation, force, fibre length and velocity, and key-body positions and
+ * orientations; the power term |F_m v_m| of the reward in "Analysis of
+ * neuro-actuated musculoskeletal dynamics"), written structure-of-arrays
+ * for the steps t = 0, every, 2 every, ... of the call (t counted from the
+ * call's first step; n_rec = ceil(n_steps / every) records; record
+ * t / every). Device buffers owned by the caller, each may be NULL:
+ *   act[n_rec][n_env][n_mus]   activation act' driving step t's force
+ *   force[n_rec][n_env][n_mus] F (N)
+ *   lm, vm [n_rec][n_env][n_mus] fibre length / l_opt and lengthening
+ *                              velocity / (v_max l_opt) (rigid tendon)
+ *   power[n_rec][n_env][n_mus] |F Ldot| (W), Ldot the path lengthening
+ *                              rate (the fibre's, under a rigid tendon)
+ *   xpos[n_rec][n_env][n_key][3], xmat[n_rec][n_env][n_key][9] (row-major)
+ *                              world frame of each key node (the model's
+ *                              key nodes, ms_model_set_key_nodes) at the
+ *                              step's start
+ * in the caller's muscle order. A step an env does not take (a status bit
+ * set at its start) leaves that env's entries unwritten.
+ *   n_applied[n_env] (u32)     += the number of steps applied to each env
+ *                              (state advanced), whatever `every` is. */
+typedef struct {
+  int32_t every;
+  float *act, *force, *lm, *vm, *power;
+  float *xpos, *xmat;
+  uint32_t *n_applied;
+} ms_record;
+
+/* Key nodes whose frames ms_rollout_record writes (host nodes[n_key], node
+ * indices, 0 <= n_key <= 64; 0 clears them). Synchronises the device. */
+ms_status ms_model_set_key_nodes(ms_model *m, int32_t n_key, const int32_t *nodes);
+
+/* ms_rollout that also writes the observables rec asks for (rec may be
+ * NULL: ms_rollout). MS_E_ARG as for ms_rollout, and for rec->every < 1
+ * with an observable requested, or key-node observables on a model without
+ * key nodes. The state advances exactly as with ms_rollout. */
+ms_status ms_rollout_record(ms_model *m, int32_t n_env, float *q, float *qd,
+                            float *act, uint32_t *status, const ms_excitation *exc,
+                            int32_t n_steps, const ms_step_opts *opts,
+                            const ms_record *rec, void *stream);
+
 /* Stage outputs of one step for n_env envs (device buffers, any may be
  * NULL): activation act'[E][n_mus], L, Ldot, F [E][n_mus], moment arms
  * r[E][n_mus][3] with their DoF indices from ms_model_spans, tau_mus[E][nv],

@@ -294,6 +294,7 @@ void ms_model_destroy(ms_model *m) {
     (void)hipEventDestroy(p.b);
   }
   for (hipEvent_t e : m->ev_free) (void)hipEventDestroy(e);
+  if (m->key_buf) (void)hipFree(m->key_buf);
   delete m;
 }
 
@@ -409,11 +410,49 @@ ms_status ms_rollout(ms_model *m, int32_t n_env, float *q, float *qd, float *act
   return rollout_impl(m, n_env, q, qd, act, status, exc, n_steps, opts, 0, (hipStream_t)stream);
 }
 
+ms_status ms_rollout_record(ms_model *m, int32_t n_env, float *q, float *qd, float *act,
+                            uint32_t *status, const ms_excitation *exc, int32_t n_steps,
+                            const ms_step_opts *opts, const ms_record *rec, void *stream) {
+  g_err.clear();
+  if (rec) {
+    const bool any_obs = rec->act || rec->force || rec->lm || rec->vm || rec->power ||
+                         rec->xpos || rec->xmat;
+    if (any_obs && rec->every < 1) return fail(MS_E_ARG, "rec->every must be >= 1");
+    if ((rec->xpos || rec->xmat) && m && m->k.n_key == 0)
+      return fail(MS_E_ARG, "key-node observables need ms_model_set_key_nodes first");
+  }
+  return rollout_impl(m, n_env, q, qd, act, status, exc, n_steps, opts, 0, (hipStream_t)stream,
+                      rec);
+}
+
+ms_status ms_model_set_key_nodes(ms_model *m, int32_t n_key, const int32_t *nodes) {
+  g_err.clear();
+  if (!m || n_key < 0 || n_key > 64 || (n_key > 0 && !nodes))
+    return fail(MS_E_ARG, "bad arguments (0 <= n_key <= 64)");
+  for (int k = 0; k < n_key; ++k)
+    if (nodes[k] < 0 || nodes[k] >= m->t.n_node) return fail(MS_E_ARG, "key node out of range");
+  hipError_t e = hipDeviceSynchronize();  // queued steps may read the old table
+  if (e != hipSuccess) return fail(MS_E_HIP, std::string("synchronise: ") + hipGetErrorString(e));
+  if (m->key_buf) (void)hipFree(m->key_buf);
+  m->key_buf = nullptr;
+  m->k.key_node = nullptr;
+  m->k.n_key = 0;
+  if (n_key == 0) return MS_OK;
+  e = hipMalloc(&m->key_buf, 4 * (size_t)n_key);
+  if (e != hipSuccess) return fail(MS_E_ALLOC, "hipMalloc: key nodes");
+  e = hipMemcpy(m->key_buf, nodes, 4 * (size_t)n_key, hipMemcpyHostToDevice);
+  if (e != hipSuccess) return fail(MS_E_HIP, std::string("hipMemcpy: ") + hipGetErrorString(e));
+  m->k.key_node = (const int *)m->key_buf;
+  m->k.n_key = n_key;
+  return MS_OK;
+}
+
 }  // extern "C"
 
 ms_status rollout_impl(ms_model *m, int32_t n_env, float *q, float *qd, float *act,
                        uint32_t *status, const ms_excitation *exc, int32_t n_steps,
-                       const ms_step_opts *opts, int env_per_wg, hipStream_t st) {
+                       const ms_step_opts *opts, int env_per_wg, hipStream_t st,
+                       const ms_record *rec) {
   g_err.clear();
   ms_status s = common_checks(m, n_env, q, qd, act, opts);
   if (s != MS_OK) return s;
@@ -439,6 +478,12 @@ ms_status rollout_impl(ms_model *m, int32_t n_env, float *q, float *qd, float *a
       return fail(MS_E_ARG, "unknown excitation kind");
   }
   r.exc = exc->kind;
+  if (rec) {
+    r.rec_every = rec->every;
+    r.r_act = rec->act; r.r_F = rec->force; r.r_lm = rec->lm; r.r_vm = rec->vm;
+    r.r_pow = rec->power; r.r_xpos = rec->xpos; r.r_xmat = rec->xmat;
+    r.n_applied = rec->n_applied;
+  }
   return run_steps(m, r, n_env, n_steps, st);
 }
 

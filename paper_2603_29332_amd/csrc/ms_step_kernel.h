@@ -601,6 +601,37 @@ __device__ __forceinline__ void add_joint_damping(const KModel &M, int lane, con
   wave_sync();
 }
 
+// Observables of a recorded step: the muscle slices of env `env` in record
+// t / rec_every (all NULL when step t is not recorded), and the key nodes'
+// world positions and orientations.
+__device__ __forceinline__ RecOut rec_slices(const KModel &M, const KRun &Rn, int env, int step) {
+  RecOut o{nullptr, nullptr, nullptr, nullptr, nullptr};
+  if (Rn.rec_every <= 0 || step % Rn.rec_every) return o;
+  const size_t b = ((size_t)(step / Rn.rec_every) * Rn.n_env + env) * M.n_mus;
+  o.act = Rn.r_act ? Rn.r_act + b : nullptr;
+  o.F = Rn.r_F ? Rn.r_F + b : nullptr;
+  o.lm = Rn.r_lm ? Rn.r_lm + b : nullptr;
+  o.vm = Rn.r_vm ? Rn.r_vm + b : nullptr;
+  o.pw = Rn.r_pow ? Rn.r_pow + b : nullptr;
+  return o;
+}
+
+__device__ __forceinline__ void record_keys(const KModel &M, const KRun &Rn, int lane, int env,
+                                            int step, const float *Rl, V3 O) {
+  if (Rn.rec_every <= 0 || step % Rn.rec_every) return;
+  const size_t b = ((size_t)(step / Rn.rec_every) * Rn.n_env + env) * M.n_key;
+  for (int k = lane; k < M.n_key; k += 64) {
+    const float *F = Rl + 12 * M.key_node[k];
+    if (Rn.r_xmat)
+      for (int e = 0; e < 9; ++e) Rn.r_xmat[(b + k) * 9 + e] = F[e];
+    if (Rn.r_xpos) {
+      Rn.r_xpos[(b + k) * 3 + 0] = F[9] + O.x;
+      Rn.r_xpos[(b + k) * 3 + 1] = F[10] + O.y;
+      Rn.r_xpos[(b + k) * 3 + 2] = F[11] + O.z;
+    }
+  }
+}
+
 // Excitations u of this thread's muscles (internal slots t + n k) for
 // absolute step `step`, advancing the smooth-noise state xar; returns true
 // when one of this thread's activations is not finite.
@@ -665,7 +696,8 @@ __device__ __forceinline__ void stage_muscles(const KModel &M, const KRun &Rn, c
                                               const float *Sl, const float *q, const float *qd,
                                               V3 O, const float act1[MPT], unsigned char *scr,
                                               float dt, bool stages, double *rhs, double *H,
-                                              float *tau_out, double *dsum_out, unsigned &status) {
+                                              float *tau_out, double *dsum_out, unsigned &status,
+                                              const RecOut &ro) {
   const int nm = M.n_mus, nn = M.n_node, nv = M.nv;
   float *mr = (float *)scr;          // [n_mus][3]
   float *mF = mr + 3 * nm;           // [n_mus]
@@ -752,6 +784,16 @@ __device__ __forceinline__ void stage_muscles(const KModel &M, const KRun &Rn, c
     mF[m] = F;
     mc[m] = cdamp;
     if (stages) Rn.o_F[(size_t)env * nm + M.mus_ext[m]] = F;
+    if (ro.act || ro.F || ro.lm || ro.vm || ro.pw) {
+      // observables: the activation driving the force, the force, fibre
+      // length and velocity (normalised) and the power |F Ldot| (W)
+      const int mx = M.mus_ext[m];
+      if (ro.act) ro.act[mx] = act1[k];
+      if (ro.F) ro.F[mx] = F;
+      if (ro.lm) ro.lm[mx] = lm;
+      if (ro.vm) ro.vm[mx] = vm;
+      if (ro.pw) ro.pw[mx] = fabsf(F * Ld);
+    }
   }
   T.sync();
   for (int x = T.t; x < nv; x += T.n) {
@@ -1093,6 +1135,7 @@ __device__ __forceinline__ void step_body(const KModel &M, const KRun &Rn, int n
     if (Rn.exc == EXC_AR1 && mi < nm) xar[t] = Rn.xar[(size_t)env * nm + mx];
   }
   unsigned status = Rn.status ? Rn.status[env] : 0u;
+  unsigned applied = 0;
   wave_sync();
 
   for (int step = 0; step < n_steps; ++step) {
@@ -1111,6 +1154,7 @@ __device__ __forceinline__ void step_body(const KModel &M, const KRun &Rn, int n
     const V3 O = M.free_root ? v3(q[0], q[1], q[2]) : v3(0.f, 0.f, 0.f);
     const V3 g = v3(M.gx, M.gy, M.gz);
     stage_fk(M, lane, tlev, tnode, q, qd, Rl, Sl, Vl, Al, O, g);
+    record_keys(M, Rn, lane, env, step, Rl, O);
     if (!GEOM) {
       stage_contacts(M, lane, Rl, Vl, Cl, O, dt, Rn.contact);
       stage_rnea(M, lane, Rl, Pl, Vl, Al, Fl, Cl, Sl, qd, sbs, sbl, scs, scl, rhs,
@@ -1120,7 +1164,8 @@ __device__ __forceinline__ void step_body(const KModel &M, const KRun &Rn, int n
       add_joint_damping(M, lane, LT, H, dt, dmp);
     }
     stage_muscles<MPL, NVIA, SURR, GEOM>(M, Rn, T, env, step, Rl, Pl, Sl, q, qd, O, act1, scr, dt,
-                                         stages, rhs, H, nullptr, nullptr, status);
+                                         stages, rhs, H, nullptr, nullptr, status,
+                                         rec_slices(M, Rn, env, step));
     if (GEOM) return;
     if (stages) {
       for (int e = lane; e < M.nnz; e += 64) Rn.o_H[(size_t)env * M.nnz + e] = H[e];
@@ -1143,6 +1188,7 @@ __device__ __forceinline__ void step_body(const KModel &M, const KRun &Rn, int n
     }
 #pragma unroll
     for (int t = 0; t < MPL; ++t) act[t] = act1[t];
+    ++applied;
   }
 
   if (stages) return;
@@ -1158,6 +1204,7 @@ __device__ __forceinline__ void step_body(const KModel &M, const KRun &Rn, int n
     }
   }
   if (Rn.status && lane == 0) Rn.status[env] = status;
+  if (Rn.n_applied && lane == 0) Rn.n_applied[env] += applied;
 }
 
 template <int MPL, int NVIA>
@@ -1230,7 +1277,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) voi
   unsigned status = 0;
   stage_muscles<MPT, NVIA, SURR, false>(M, Rn, T, env, step, Rl, Pl, Sl, q, qd, O, act1, scr, Rn.dt,
                                         false, nullptr, nullptr, W.tau + (size_t)env * W.tau_stride,
-                                        W.dsum + (size_t)env * W.dsum_stride, status);
+                                        W.dsum + (size_t)env * W.dsum_stride, status,
+                                        rec_slices(M, Rn, env, step));
   bool bad1 = false;
 #pragma unroll
   for (int k = 0; k < MPT; ++k) {

@@ -63,6 +63,7 @@ __global__ __launch_bounds__(1024) void k_front(KModel M, KRun Rn, KSplit W, int
   const V3 O = M.free_root ? v3(q[0], q[1], q[2]) : v3(0.f, 0.f, 0.f);
   const V3 g = v3(M.gx, M.gy, M.gz);
   stage_fk(M, lane, tlev, tnode, q, qd, Rl, Sl, Vl, Al, O, g);
+  record_keys(M, Rn, lane, env, step, Rl, O);
   // node frames and motion subspaces for the muscle kernel
   float *gf = W.frames + (size_t)env * W.fr_stride;
   for (int i = lane; i < 3 * nn; i += 64) ((float4 *)gf)[i] = ((const float4 *)Rl)[i];
@@ -129,6 +130,7 @@ __global__ __launch_bounds__(1024) void k_back(KModel M, KRun Rn, KSplit W, int 
   for (int i = lane; i < nv; i += 64) Rn.qd[(size_t)env * nv + i] = qd[i];
   const float *an = W.actn + (size_t)env * W.act_stride;
   for (int i = lane; i < nm; i += 64) Rn.act[(size_t)env * nm + i] = an[i];
+  if (Rn.n_applied && lane == 0) Rn.n_applied[env] += 1u;
 }
 
 namespace {

@@ -42,6 +42,9 @@ struct KModel {
   int n_ci;
   int off_flag, off_q, off_qd, off_R, off_P, off_S, off_con, off_rhs, off_x, off_H,
       off_scr, off_V, off_A, off_F;
+  // key nodes whose frames the observables record
+  const int *key_node;
+  int n_key;
   int lds_env;  // bytes of one env's LDS block
 };
 
@@ -69,6 +72,18 @@ struct KRun {
   double *o_H;
   int env_per_wg;  // envs (wavefronts) per workgroup, 1, 2 or 4 (0: the most resident envs)
   int u_hold;      // array excitations: the same u[n_env][n_mus] for every step
+  // per-step observables of steps t % rec_every == 0 (0: none), record
+  // t / rec_every: muscle arrays [n_rec][n_env][n_mus] (caller's order), key
+  // node frames [n_rec][n_env][n_key][3 | 9]; applied-step counters
+  int rec_every;
+  float *r_act, *r_F, *r_lm, *r_vm, *r_pow, *r_xpos, *r_xmat;
+  unsigned *n_applied;
+};
+
+// This env's slices of the muscle observables of one recorded step (NULL:
+// not recorded).
+struct RecOut {
+  float *act, *F, *lm, *vm, *pw;
 };
 
 enum { EXC_ARRAY = MS_EXC_ARRAY, EXC_IID = MS_EXC_IID, EXC_AR1 = MS_EXC_AR1 };
@@ -153,6 +168,7 @@ struct ms_model {
   std::vector<void *> ws_owned;
   // envs per workgroup of its kernels, chosen for w_n_env envs
   int w_front = 0, w_back = 0, w_n_env = 0;
+  void *key_buf = nullptr;  // device copy of the key nodes
   // per-kernel timing of the split schedule (ms_model_set_kernel_timing):
   // event pairs recorded around each kernel, (kernel, start, end)
   int timing = 0;  // time every timing-th step of each call (0: off)
@@ -187,4 +203,5 @@ ms_status run_steps(ms_model *m, const ms::KRun &r, int n_env, int n_steps, hipS
 // as ms_rollout (message in ms_last_error).
 ms_status rollout_impl(ms_model *m, int32_t n_env, float *q, float *qd, float *act,
                        uint32_t *status, const ms_excitation *exc, int32_t n_steps,
-                       const ms_step_opts *opts, int env_per_wg, hipStream_t st);
+                       const ms_step_opts *opts, int env_per_wg, hipStream_t st,
+                       const ms_record *rec = nullptr);

@@ -35,7 +35,8 @@ EXPORTED = ("ms_model_create", "ms_model_destroy", "ms_model_info_get",
             "ms_policy_act", "ms_policy_rollout", "ms_surrogate_reserve",
             "ms_surrogate_forward_noalloc", "ms_surrogate_noalloc_max", "ms_policy_reserve",
             "ms_model_set_schedule", "ms_model_get_schedule", "ms_model_reserve",
-            "ms_model_set_kernel_timing", "ms_model_kernel_times")
+            "ms_model_set_kernel_timing", "ms_model_kernel_times", "ms_model_set_key_nodes",
+            "ms_rollout_record")
 
 _fptr = C.POINTER(C.c_float)
 _iptr = C.POINTER(C.c_int32)
@@ -70,6 +71,11 @@ class MsExc(C.Structure):
                 ("s", C.c_float), ("mean", C.c_float)]
 
 
+class MsRecord(C.Structure):
+    _fields_ = [("every", C.c_int32)] + [(k, C.c_void_p) for k in (
+        "act", "force", "lm", "vm", "power", "xpos", "xmat", "n_applied")]
+
+
 class MsBatchState(C.Structure):
     _fields_ = [("q", C.c_void_p), ("qd", C.c_void_p), ("act", C.c_void_p),
                 ("status", C.c_void_p)]
@@ -101,6 +107,9 @@ def lib():
     L.ms_model_reserve.argtypes = [vp, C.c_int32]
     L.ms_model_set_kernel_timing.argtypes = [vp, C.c_int32]
     L.ms_model_kernel_times.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
+    L.ms_model_set_key_nodes.argtypes = [vp, C.c_int32, _iptr]
+    L.ms_rollout_record.argtypes = [vp, C.c_int32, vp, vp, vp, vp, C.POINTER(MsExc), C.c_int32,
+                                    C.POINTER(MsOpts), C.POINTER(MsRecord), vp]
     L.ms_step_batch.argtypes = [vp, C.c_int32, vp, vp, vp, vp, vp, C.POINTER(MsOpts), vp]
     L.ms_rollout.argtypes = [vp, C.c_int32, vp, vp, vp, vp, C.POINTER(MsExc), C.c_int32,
                              C.POINTER(MsOpts), vp]
@@ -300,6 +309,30 @@ class Model:
                   float(ar1[2]))
         _check(lib().ms_rollout(self.h, n_env, _dp(q), _dp(qd), _dp(act), _dp(status),
                                 C.byref(e), n_steps, C.byref(o), _stream(stream)))
+
+    def set_key_nodes(self, nodes):
+        """Key nodes whose world frames rollout_record writes."""
+        a = np.ascontiguousarray(nodes, np.int32)
+        _check(lib().ms_model_set_key_nodes(self.h, len(a), a.ctypes.data_as(_iptr)))
+
+    def rollout_record(self, q, qd, act, status, n_steps, dt, contact=True, kind=EXC_ARRAY,
+                       u=None, seed=0, step0=0, x=None, ar1=(0.0, 0.0, 0.0), every=1,
+                       obs=None, n_applied=None, stream=None):
+        """rollout() that writes the observables named in obs (dict of device
+        tensors: act, force, lm, vm, power [n_rec][n_env][n_mus], xpos
+        [n_rec][n_env][n_key][3], xmat [..][9]) every `every` steps and adds
+        the steps applied to each env to n_applied (uint32/int32 [n_env])."""
+        obs = obs or {}
+        n_env = q.shape[0]
+        o = MsOpts(dt, int(contact))
+        e = MsExc(kind, _dp(u), seed, step0, _dp(x), float(ar1[0]), float(ar1[1]),
+                  float(ar1[2]))
+        r = MsRecord(int(every), *[_dp(obs.get(k)) for k in
+                                   ("act", "force", "lm", "vm", "power", "xpos", "xmat")],
+                     _dp(n_applied))
+        _check(lib().ms_rollout_record(self.h, n_env, _dp(q), _dp(qd), _dp(act), _dp(status),
+                                       C.byref(e), n_steps, C.byref(o), C.byref(r),
+                                       _stream(stream)))
 
     def rollout_surrogate(self, sg, q, qd, act, status, n_steps, dt, contact=True, tol=1e-4,
                           fb_count=None, kind=EXC_ARRAY, u=None, seed=0, step0=0, x=None,

@@ -3,13 +3,17 @@
 Workload (default): synthetic whole body, 22 bodies / 80 DoF / 700 muscles /
 24 contact spheres, 4096 envs, dt = 1 ms, AR(1) smooth-noise excitations
 generated in-kernel, exact muscle geometry, FP32 with FP64 mass matrix and
-solve. One bench step = one ms_rollout launch of 100 physics steps for all
-envs (state resident on chip); the default 10 timed steps cover the
-workload's 1000 physics steps.
+solve, on the model's default step schedule (split: three kernels per
+physics step). One bench step = one rollout call of 100 physics steps for
+all envs; the default 10 timed steps cover the workload's 1000 physics
+steps. `value` counts the env-steps actually applied (envs that fail are
+frozen until the next call boundary, where they restart).
 
 Prints one JSON line (rank 0) with the throughput, the ALU roofline of the
-step kernel, the joint-angle error against the FP64 oracle on a 16-env
-sample after 200 steps, and the oracle's own throughput on the host cores.
+dominant kernel (per-kernel durations from HIP events on the launch stream,
+sampled every 10th step of the timed region), the joint-angle error against
+the FP64 oracle on a 16-env sample after 200 steps, and the oracle's own
+throughput on the host cores.
 """
 from __future__ import annotations
 
@@ -29,12 +33,14 @@ PHYS_PER_STEP = 100
 # MI355X: 256 CUs x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz, one FP32 or
 # FP64 vector FMA per lane and cycle (packed FP32 would double FP32 only).
 PEAK_VALU_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
-# HBM bytes of one 100-step k_step rollout launch on this workload, from
-# rocprofv3 FETCH_SIZE and WRITE_SIZE scaled by a plain copy of known size
-# (profiles/k_step_human80_4096_traffic.md), valid for the kernel source with
-# this SHA-256 prefix only (reported as null otherwise).
-TRAFFIC_BYTES_PER_LAUNCH = 53.6e6
-TRAFFIC_KERNEL_SHA = "d2b64ff4b0c67bc6"
+# HBM bytes per launch of each split-schedule kernel on this workload (4096
+# envs), from rocprofv3 FETCH_SIZE and WRITE_SIZE scaled by a plain copy of
+# known size, valid for the kernel sources with this SHA-256 prefix only
+# (reported as null otherwise).
+TRAFFIC_BYTES_PER_LAUNCH = {}
+TRAFFIC_KERNEL_SHA = ""
+TIMING_EVERY = 10
+KERNELS = ("k_front", "k_muscle", "k_back")
 
 
 def parse():
@@ -97,11 +103,16 @@ def main():
     init = tuple(torch.tensor(v, device=dev) for v in (q0, qd0, act0))
     resets = torch.zeros((), dtype=torch.int64, device=dev)
 
-    def launch(step_index, ev0=None, ev1=None):
+    applied = torch.zeros(E, dtype=torch.int32, device=dev)
+    gm.reserve(E)
+    split = gm.schedule() == ms.SCHED_SPLIT
+
+    def launch(step_index, ev0=None, ev1=None, g=gm):
         if ev0 is not None:
             ev0.record(stream)
-        gm.rollout(q, qd, act, st, PHYS_PER_STEP, dt, True, kind=ms.EXC_AR1, seed=12,
-                   step0=step_index * PHYS_PER_STEP, x=x, ar1=(rho, s, mean), stream=stream)
+        g.rollout_record(q, qd, act, st, PHYS_PER_STEP, dt, True, kind=ms.EXC_AR1, seed=12,
+                         step0=step_index * PHYS_PER_STEP, x=x, ar1=(rho, s, mean),
+                         n_applied=applied, stream=stream)
         if ev1 is not None:
             ev1.record(stream)
         reset_flagged(q, qd, act, st, x, init, resets)
@@ -109,18 +120,45 @@ def main():
     for w in range(a.warmup):
         launch(w)
     torch.cuda.synchronize()
+    applied.zero_()
+    resets.zero_()
     ev0 = [torch.cuda.Event(enable_timing=True) for _ in range(a.steps)]
     ev1 = [torch.cuda.Event(enable_timing=True) for _ in range(a.steps)]
+    if split:
+        gm.kernel_times()                      # discard anything recorded before
+        gm.set_kernel_timing(TIMING_EVERY)
     t0 = time.perf_counter()
     for k in range(a.steps):
         launch(a.warmup + k, ev0[k], ev1[k])
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     launch_ms = [ev0[k].elapsed_time(ev1[k]) for k in range(a.steps)]
+    kernel_ms = None
+    if split:
+        tk, nk = gm.kernel_times()
+        gm.set_kernel_timing(0)
+        kernel_ms = {name: t / nk for name, t in zip(KERNELS, tk)}
     env_steps = E * PHYS_PER_STEP * a.steps
-    value = env_steps / wall
+    applied_steps = int(applied.sum().item())
+    value = applied_steps / wall
     n_resets = int(resets.item())
     progress(f"exact leg: {a.steps} launches, {wall:.2f} s")
+    # the same work on the fused schedule (one kernel per 100-step call)
+    gmf = ms.Model(m)
+    gmf.set_schedule(ms.SCHED_FUSED)
+    q, qd, act, st, x = fresh()
+    launch(0, g=gmf)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    nf = 3
+    e0.record(stream)
+    for k in range(nf):
+        launch(1 + k, g=gmf)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    fused_ms = e0.elapsed_time(e1) / nf
+    del gmf
+    progress("fused-schedule leg done")
 
     # ms_step_batch (u read from HBM), for the per-step HBM view
     uq = torch.rand(E, m["n_mus"], device=dev)
@@ -140,9 +178,33 @@ def main():
     progress("step_batch leg done")
 
     fp32, fp64, detail = flops.step_flops(m, gm.spans(), gm.nnz)
-    per_launch = (fp32 + fp64) * E * PHYS_PER_STEP
-    avg_launch_s = float(np.mean(launch_ms)) / 1e3
-    achieved = per_launch / avg_launch_s / 1e12
+    ksplit = flops.split_kernel_flops(detail, m, gm.spans())
+    traffic = measured_traffic()
+    kernels = {}
+    if kernel_ms:
+        for name in KERNELS:
+            f = ksplit[name]["fp32"] + ksplit[name]["fp64"]
+            ach = f * E / (kernel_ms[name] / 1e3) / 1e12
+            kernels[name] = {"avg_launch_ms": kernel_ms[name], "flop_per_env_step": ksplit[name],
+                             "achieved": ach, "frac": ach / PEAK_VALU_TFLOPS,
+                             "traffic": traffic.get(name) if traffic else None}
+        dom = max(KERNELS, key=lambda k: kernel_ms[k])
+        roof = {"bound": "alu", "achieved": kernels[dom]["achieved"], "peak": PEAK_VALU_TFLOPS,
+                "unit": "TFLOP/s", "frac": kernels[dom]["frac"], "traffic": kernels[dom]["traffic"],
+                "kernel": dom + " (split schedule, one launch per physics step)",
+                "avg_launch_ms": kernel_ms[dom],
+                "timing": f"HIP events on the launch stream around each kernel of every "
+                          f"{TIMING_EVERY}th physics step of the timed region",
+                "flop_per_env_step": ksplit[dom], "kernels": kernels,
+                "step_flop_per_env_step": {"fp32": fp32, "fp64": fp64},
+                "step_achieved": (fp32 + fp64) * E / (sum(kernel_ms.values()) / 1e3) / 1e12}
+    else:
+        avg_launch_s = float(np.mean(launch_ms)) / 1e3
+        ach = (fp32 + fp64) * E * PHYS_PER_STEP / avg_launch_s / 1e12
+        roof = {"bound": "alu", "achieved": ach, "peak": PEAK_VALU_TFLOPS, "unit": "TFLOP/s",
+                "frac": ach / PEAK_VALU_TFLOPS, "traffic": None,
+                "kernel": "k_step (fused schedule)", "avg_launch_ms": avg_launch_s * 1e3,
+                "flop_per_env_step": {"fp32": fp32, "fp64": fp64}}
     line = {
         "metric": METRIC, "value": value, "unit": "env-steps/s", "n_gpus": 1,
         "steps": a.steps, "warmup": a.warmup, "ms_per_step": wall / a.steps * 1e3,
@@ -151,12 +213,18 @@ def main():
         "config": {"workload": "whole-body exact path: 22 bodies/80 DoF/700 muscles/24 "
                                "contact spheres, dt 1 ms, AR(1) excitations in-kernel",
                    "envs": E, "physics_steps_per_bench_step": PHYS_PER_STEP,
-                   "geometry": "exact", "precision": "FP32, FP64 mass matrix + LTDL solve"},
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_VALU_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_VALU_TFLOPS,
-                     "traffic": measured_traffic(),
-                     "kernel": "k_step (ms_rollout)", "avg_launch_ms": avg_launch_s * 1e3,
-                     "flop_per_env_step": {"fp32": fp32, "fp64": fp64}},
+                   "geometry": "exact", "precision": "FP32, FP64 mass matrix + LTDL solve",
+                   "schedule": "split" if split else "fused"},
+        "applied_env_steps": applied_steps, "scheduled_env_steps": env_steps,
+        "skipped_fraction": 1.0 - applied_steps / env_steps,
+        "scheduled_env_steps_per_s": env_steps / wall,
+        "value_note": "value counts the env-steps applied; envs flagged non-finite or non-SPD "
+                      "skip the rest of their 100-step call and restart from the initial state",
+        "roofline": roof,
+        "fused_schedule": {"env_steps_per_s": E * PHYS_PER_STEP / (fused_ms / 1e3),
+                           "ms_per_physics_step": fused_ms / PHYS_PER_STEP,
+                           "note": "the same 100-step calls on the fused schedule (one kernel "
+                                   "per call), identical results"},
         "step_batch": {"ms_per_physics_step": sb_ms, "env_steps_per_s": E / (sb_ms / 1e3),
                        "hbm_bytes_per_env_step": sb_bytes,
                        "hbm_GBps": sb_bytes * E / (sb_ms / 1e3) / 1e9, "hbm_peak_GBps": 8000.0},
@@ -165,6 +233,8 @@ def main():
                            "the next launch boundary (every 100 steps), as RL rollouts do; the "
                            "FP64 oracle fails on the same envs (about 19% by 1000 steps)",
     }
+    line["observables"] = observables_leg(m, gm, dt, dev, E, (rho, s, mean))
+    progress("observables leg done")
     sg = None
     rad = None if a.no_cpu else {"exact": rad_run(m, gm, dt, dev),
                                  "exact_contact_off": rad_run(m, gm, dt, dev, contact=False)}
@@ -195,12 +265,17 @@ def progress(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def measured_traffic():
+def kernel_source_sha():
     import hashlib
-    src = os.path.join(ROOT, "paper_2603_29332_amd", "csrc", "ms_step_kernel.h")
-    with open(src, "rb") as f:
-        sha = hashlib.sha256(f.read()).hexdigest()[:16]
-    return TRAFFIC_BYTES_PER_LAUNCH if sha == TRAFFIC_KERNEL_SHA else None
+    h = hashlib.sha256()
+    for f in ("ms_step_kernel.h", "ms_step_split.hip"):
+        with open(os.path.join(ROOT, "paper_2603_29332_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    return TRAFFIC_BYTES_PER_LAUNCH if kernel_source_sha() == TRAFFIC_KERNEL_SHA else None
 
 
 def reset_flagged(q, qd, act, st, x, init, count):
@@ -285,6 +360,50 @@ def uneven_leg(a, dt, dev):
                           "issue": ["concurrent", "concurrent, most work first",
                                     "serial, most work first"][cfg[1]]},
             "flagged_envs": flagged}
+
+
+def observables_leg(m, gm, dt, dev, E, ar1, every=10, n_calls=3):
+    """The exact workload writing the per-step observables of every 10th
+    physics step (activation, force, fibre length and velocity, power for
+    700 muscles; world frames of 10 key bodies): 100-step calls like the
+    exact leg, timed with HIP events."""
+    import torch
+
+    from paper_2603_29332_amd import ms, synth
+    keys = np.flatnonzero(np.asarray(m["mass"]) > 0)[::2][:10]
+    gm.set_key_nodes(keys)
+    q0, qd0, a0 = synth.human_initial_state(m, E)
+    q, qd, act = (torch.tensor(v, device=dev) for v in (q0, qd0, a0))
+    st = torch.zeros(E, dtype=torch.int32, device=dev)
+    x = torch.zeros(E, m["n_mus"], device=dev)
+    n_rec = -(-PHYS_PER_STEP // every)
+    nm, nk = m["n_mus"], len(keys)
+    obs = {k: torch.empty(n_rec, E, nm, device=dev) for k in ("act", "force", "lm", "vm", "power")}
+    obs["xpos"] = torch.empty(n_rec, E, nk, 3, device=dev)
+    obs["xmat"] = torch.empty(n_rec, E, nk, 9, device=dev)
+    stream = torch.cuda.current_stream()
+
+    def call(k):
+        gm.rollout_record(q, qd, act, st, PHYS_PER_STEP, dt, True, kind=ms.EXC_AR1, seed=12,
+                          step0=k * PHYS_PER_STEP, x=x, ar1=ar1, every=every, obs=obs,
+                          stream=stream)
+
+    call(0)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for k in range(n_calls):
+        call(1 + k)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_call = e0.elapsed_time(e1) / n_calls
+    rec_bytes = 4 * (5 * nm + 12 * nk)
+    gm.set_key_nodes([])
+    return {"env_steps_per_s": E * PHYS_PER_STEP / (ms_call / 1e3), "every": every,
+            "key_bodies": int(nk), "bytes_per_env_record": rec_bytes,
+            "observable_GBps": rec_bytes * E * n_rec / (ms_call / 1e3) / 1e9,
+            "note": "scheduled env-steps per second of 100-step calls that also write the "
+                    "observables of every 10th step"}
 
 
 def policy_leg(a, m, gm, sg, dt, dev):

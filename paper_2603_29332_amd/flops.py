@@ -76,3 +76,20 @@ def step_flops(model: dict, spans: np.ndarray, nnz: int, contacts_active: float 
     fp64 = d["mass_fp64"] + d["solve_fp64"]
     fp32 = sum(v for kk, v in d.items() if kk not in ("mass_fp64", "solve_fp64"))
     return fp32, fp64, d
+
+
+def split_kernel_flops(detail: dict, model: dict, spans: np.ndarray) -> dict:
+    """The step's flops by kernel of the split schedule: kinematics/dynamics
+    (forward kinematics, contacts, Newton-Euler bias, composite-rigid-body
+    mass matrix), muscles (activation, geometry, Hill force, J_m^T F and the
+    muscles' FP64 damping sums) and factorisation (LTDL factorisation and
+    solves, semi-implicit Euler)."""
+    nspan = (spans >= 0).sum(1)
+    dent = 4 * int(sum(int(k) * (int(k) + 1) // 2 for k in nspan))
+    return {
+        "k_front": {"fp32": detail["kinematics"] + detail["contact"] + detail["bias_rnea"],
+                    "fp64": detail["mass_fp64"] - dent},
+        "k_muscle": {"fp32": detail["activation"] + detail["geometry"] + detail["hill"]
+                     + detail["projection"], "fp64": dent},
+        "k_back": {"fp32": detail["integrate"], "fp64": detail["solve_fp64"]},
+    }

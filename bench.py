@@ -35,10 +35,11 @@ PHYS_PER_STEP = 100
 PEAK_VALU_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 # HBM bytes per launch of each split-schedule kernel on this workload (4096
 # envs), from rocprofv3 FETCH_SIZE and WRITE_SIZE scaled by a plain copy of
-# known size, valid for the kernel sources with this SHA-256 prefix only
-# (reported as null otherwise).
-TRAFFIC_BYTES_PER_LAUNCH = {}
-TRAFFIC_KERNEL_SHA = ""
+# known size (profiles/k_split_human80_4096_traffic.md), valid for the
+# kernel sources (ms_step_kernel.h, ms_step_split.hip) with this SHA-256
+# prefix only (reported as null otherwise).
+TRAFFIC_BYTES_PER_LAUNCH = {"k_front": 74.4e6, "k_muscle": 123.3e6, "k_back": 85.1e6}
+TRAFFIC_KERNEL_SHA = "3f444630a5551091"
 TIMING_EVERY = 10
 KERNELS = ("k_front", "k_muscle", "k_back")
 

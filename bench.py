@@ -458,11 +458,9 @@ def surrogate_leg(a, m, gm, dt, E, q0, qd0, act0, ar1, dev, rad=None):
     from paper_2603_29332_amd import ms, surrogate
     t0 = time.perf_counter()
     sg = ms.Surrogate(gm, hidden=512, seed=41)
-    mean, std = surrogate.output_stats(gm, sg)
-    sg.set_norm(mean, std)
-    losses, train_s = surrogate.train(gm, sg, n_samples=10_000_000, batch=8192,
+    losses, train_s = surrogate.train(sg, n_samples=10_000_000, batch=8192,
                                       epochs=a.surrogate_iters * 8192 / 10_000_000)
-    ev_err = surrogate.evaluate(gm, sg, n=16384)
+    ev_err = heldout_errors(gm, sg, n=16384)
     setup_s = time.perf_counter() - t0
     stream = torch.cuda.current_stream()
     q, qd, act = (torch.tensor(v, device=dev) for v in (q0, qd0, act0))
@@ -532,6 +530,35 @@ def surrogate_leg(a, m, gm, dt, E, q0, qd0, act0, ar1, dev, rad=None):
         sweep.append(row)
     out["tolerance_sweep"] = sweep
     return out, sg
+
+
+def heldout_errors(gm, s, n=16384, seed=43, chunk=8192):
+    """Errors of the network against the exact geometry on n held-out poses:
+    max, 99th percentile and median over poses of the worst muscle's
+    |L_hat - L| (m), and of the worst moment arm's |r_hat - r| (m)."""
+    import torch
+    dev = "cuda"
+    errL, errR = [], []
+    have = gm.spans() >= 0
+    for o in range(0, n, chunk):
+        k = min(chunk, n - o)
+        q = torch.zeros(k, gm.nq, device=dev)
+        L = torch.zeros(k, gm.n_mus, device=dev)
+        r = torch.zeros(k, gm.n_mus, 3, device=dev)
+        Lh = torch.zeros_like(L)
+        rh = torch.zeros_like(r)
+        s.sample(q, seed, o)
+        gm.geometry(q, L, r)
+        s.forward(q, Lh, rh)
+        torch.cuda.synchronize()
+        errL.append(np.abs(Lh.cpu().numpy() - L.cpu().numpy()).max(axis=1))
+        dr = np.abs(rh.cpu().numpy() - r.cpu().numpy())
+        errR.append(np.where(have[None], dr, 0.0).max(axis=(1, 2)))
+    eL = np.concatenate(errL)
+    eR = np.concatenate(errR)
+    return {"poses": n, "L_max_m": float(eL.max()), "L_p99_m": float(np.percentile(eL, 99)),
+            "L_median_m": float(np.median(eL)), "r_max_m": float(eR.max()),
+            "r_p99_m": float(np.percentile(eR, 99))}
 
 
 RAD_E, RAD_T = 4096, 200

@@ -349,6 +349,36 @@ int32_t ms_surrogate_noalloc_max(const ms_surrogate *s);
 ms_status ms_surrogate_train_step(ms_surrogate *s, int32_t n, const float *q,
                                   const float *L, const float *r, float lr,
                                   int32_t step, float *loss, void *stream);
+/* Training on the GPU with exact labels (the geometry the network
+ * replaces): every step samples `batch` poses uniformly in the pose box
+ * (ids (step * batch + i) mod n_samples of `seed`, as ms_surrogate_sample),
+ * labels them with ms_geometry and takes one Adam step (ms_surrogate_
+ * train_step) with the learning rate lr1 + (lr0 - lr1)(1 + cos(pi it /
+ * iters)) / 2 at step count step0 + it + 1. With norm_samples > 0 the
+ * output standardisation is first set from that many poses of norm_seed:
+ * mean, then the standard deviation about it (at least 1e-6), summed in a
+ * fixed order; empty moment-arm slots get mean 0 and std 1. loss (device
+ * [iters], may be NULL) receives each step's loss. Asynchronous on stream;
+ * grows the workspace to `batch` first if needed (allocating and
+ * synchronising; see ms_surrogate_reserve). */
+typedef struct {
+  int64_t n_samples;
+  int32_t batch, iters, step0, norm_samples;
+  float lr0, lr1;
+  uint64_t seed, norm_seed;
+  float *loss;
+} ms_train_cfg;
+ms_status ms_surrogate_train(ms_model *m, ms_surrogate *s, const ms_train_cfg *cfg,
+                             void *stream);
+/* The network as one plain little-endian binary blob: a header of eight
+ * u32 (magic "MSG1" = 0x4D534731, version 1, n_in, hidden, hidden, n_out, 0,
+ * 0), then float32 W1 [hidden][n_in], b1, W2, b2, W3 [n_out][hidden], b3,
+ * the output mean and std. ms_surrogate_save writes it to blob (host, cap
+ * bytes) and its size to *size; blob = NULL queries the size. Both
+ * synchronise the device. ms_surrogate_load reads a blob of a network with
+ * the same layer sizes (else MS_E_ARG). */
+ms_status ms_surrogate_save(ms_surrogate *s, void *blob, size_t cap, size_t *size);
+ms_status ms_surrogate_load(ms_surrogate *s, const void *blob, size_t size);
 const char *ms_surrogate_last_error(void);
 
 /* ------------------------------------------------------------------------

@@ -12,6 +12,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstring>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -37,6 +38,8 @@ struct ms_surrogate {
            *dZ1b = nullptr;
   float *Z1 = nullptr, *Z2 = nullptr, *Y = nullptr, *T = nullptr, *dY = nullptr, *dZ2 = nullptr,
         *dZ1 = nullptr, *part = nullptr, *cpart = nullptr, *kwork = nullptr;
+  // training batches: poses, exact labels, output statistics
+  float *Qb = nullptr, *Lb = nullptr, *Rb = nullptr, *acc = nullptr, *acc2 = nullptr;
   std::vector<void *> owned;
 };
 
@@ -165,6 +168,51 @@ __global__ void k_colsum(const float *X, int rows, int cols, int chunk, float *o
   out[(size_t)blockIdx.y * cols + c] = s;
 }
 
+// acc[o] (+)= sum over the rows of Y[n][n_out] of y (pass 1) or of
+// (y - mean[o])^2 (pass 2, mean given), in row order
+__global__ void k_stat_rows(const float *Y, int n, int n_out, const float *mean, int init,
+                            float *acc) {
+  const int o = blockIdx.x * blockDim.x + threadIdx.x;
+  if (o >= n_out) return;
+  float s = init ? 0.0f : acc[o];
+  for (int p = 0; p < n; ++p) {
+    const float y = Y[(size_t)p * n_out + o];
+    if (mean) {
+      const float d = y - mean[o];
+      s += d * d;
+    } else {
+      s += y;
+    }
+  }
+  acc[o] = s;
+}
+
+// labels [L | r] of one batch of poses into Y[n][n_out]
+__global__ void k_pack_labels(const float *L, const float *r, int n_mus, int n, float *Y) {
+  const int n_out = 4 * n_mus;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n * n_out) return;
+  const int p = t / n_out, o = t % n_out;
+  Y[t] = o < n_mus ? L[(size_t)p * n_mus + o] : r[(size_t)p * 3 * n_mus + (o - n_mus)];
+}
+
+// mean = acc / n; empty moment-arm slots (mask 0) get mean 0
+__global__ void k_stat_mean(const float *acc, const float *mask, int n, int n_out, float *mean) {
+  const int o = blockIdx.x * blockDim.x + threadIdx.x;
+  if (o >= n_out) return;
+  mean[o] = mask[o] != 0.0f ? acc[o] / (float)n : 0.0f;
+}
+
+// std = max(sqrt(acc2 / n), 1e-6) (1 for empty slots), and its reciprocal
+__global__ void k_stat_std(const float *acc2, const float *mask, int n, int n_out, float *stdv,
+                           float *istd) {
+  const int o = blockIdx.x * blockDim.x + threadIdx.x;
+  if (o >= n_out) return;
+  const float v = mask[o] != 0.0f ? fmaxf(sqrtf(acc2[o] / (float)n), 1e-6f) : 1.0f;
+  stdv[o] = v;
+  istd[o] = 1.0f / v;
+}
+
 __global__ void k_adam(float *w, float *m, float *v, const float *g, int n, float lr, float b1,
                        float b2, float eps, float c1, float c2, bf16 *wb) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -269,6 +317,11 @@ ms_status ensure_cap(ms_surrogate *s, int n) {
       w = std::max(w, (size_t)splitk_slices(M[l], N[l], n) * M[l] * N[l]);
     a.add(&s->kwork, w);
   }
+  a.add(&s->Qb, B * s->nq);
+  a.add(&s->Lb, B * s->n_mus);
+  a.add(&s->Rb, B * 3 * s->n_mus);
+  a.add(&s->acc, (size_t)s->n_out);
+  a.add(&s->acc2, (size_t)s->n_out);
   if (!a.commit(s->owned)) return sfail(MS_E_ALLOC, "surrogate workspace allocation failed");
   s->cap = n;
   return MS_OK;
@@ -591,6 +644,134 @@ int32_t ms_surrogate_noalloc_max(const ms_surrogate *s) {
     (noalloc_bytes(s, mid) <= kScratchBytes ? lo : hi) = mid;
   }
   return (int32_t)lo;
+}
+
+ms_status ms_surrogate_train(ms_model *m, ms_surrogate *s, const ms_train_cfg *c, void *stream) {
+  s_err.clear();
+  if (!m || !s || !c) return sfail(MS_E_ARG, "NULL argument");
+  if (c->batch <= 0 || c->batch % 8 || c->iters < 0 || c->n_samples <= 0 || c->step0 < 0 ||
+      c->norm_samples < 0 || !(c->lr0 >= 0.0f) || !(c->lr1 >= 0.0f))
+    return sfail(MS_E_ARG, "bad training configuration (batch a positive multiple of 8, iters, "
+                           "n_samples > 0, step0 >= 0, norm_samples >= 0, lr >= 0)");
+  ms_model_info info;
+  if (ms_model_info_get(m, &info) != MS_OK || info.n_mus != s->n_mus || info.nq != s->nq)
+    return sfail(MS_E_ARG, "surrogate does not belong to this model");
+  ms_status st = ensure_cap(s, c->batch);
+  if (st != MS_OK) return st;
+  hipStream_t hs = (hipStream_t)stream;
+  const int B = c->batch, no = s->n_out;
+  auto labels = [&](int n, unsigned long long seed, long long offset) -> ms_status {
+    hipLaunchKernelGGL(k_sample, dim3(blocks(n)), dim3(256), 0, hs, n, s->nq, s->free_root,
+                       s->hinge_q, s->lo, s->hi, s->n_in, seed, offset, s->Qb);
+    if (ms_geometry(m, n, s->Qb, s->Lb, s->Rb, hs) != MS_OK)
+      return sfail(MS_E_HIP, std::string("labels: ") + ms_last_error());
+    return MS_OK;
+  };
+  // output standardisation: mean, then std about it, over norm_samples poses
+  // sampled with norm_seed, in batches of B (fixed order)
+  if (c->norm_samples > 0) {
+    for (int pass = 0; pass < 2; ++pass) {
+      for (long long o = 0; o < c->norm_samples; o += B) {
+        const int n = (int)std::min<long long>(B, c->norm_samples - o);
+        st = labels(n, c->norm_seed, o);
+        if (st != MS_OK) return st;
+        hipLaunchKernelGGL(k_pack_labels, dim3(blocks((long long)n * no)), dim3(256), 0, hs, s->Lb,
+                           s->Rb, s->n_mus, n, s->Y);
+        hipLaunchKernelGGL(k_stat_rows, dim3(blocks(no)), dim3(256), 0, hs, s->Y, n, no,
+                           pass ? s->mean : (const float *)nullptr, o == 0 ? 1 : 0,
+                           pass ? s->acc2 : s->acc);
+      }
+      if (pass == 0)
+        hipLaunchKernelGGL(k_stat_mean, dim3(blocks(no)), dim3(256), 0, hs, s->acc, s->mask,
+                           (int)c->norm_samples, no, s->mean);
+      else
+        hipLaunchKernelGGL(k_stat_std, dim3(blocks(no)), dim3(256), 0, hs, s->acc2, s->mask,
+                           (int)c->norm_samples, no, s->stdv, s->istd);
+    }
+    st = hipst(hipGetLastError(), "output statistics");
+    if (st != MS_OK) return st;
+  }
+  // Adam with the learning rate decayed from lr0 to lr1 along a half cosine
+  for (int it = 0; it < c->iters; ++it) {
+    const long long offset = ((long long)it * B) % c->n_samples;
+    st = labels(B, c->seed, offset);
+    if (st != MS_OK) return st;
+    const double ph = 3.14159265358979323846 * (double)it / (double)c->iters;
+    const float lr = (float)(c->lr1 + 0.5 * ((double)c->lr0 - c->lr1) * (1.0 + std::cos(ph)));
+    st = ms_surrogate_train_step(s, B, s->Qb, s->Lb, s->Rb, lr, c->step0 + it + 1,
+                                 c->loss ? c->loss + it : nullptr, stream);
+    if (st != MS_OK) return st;
+  }
+  return MS_OK;
+}
+
+namespace {
+constexpr uint32_t kBlobMagic = 0x4D534731u;  // "MSG1"
+}
+
+ms_status ms_surrogate_save(ms_surrogate *s, void *blob, size_t cap, size_t *size) {
+  s_err.clear();
+  if (!s || !size) return sfail(MS_E_ARG, "NULL argument");
+  const int in[3] = {s->n_in, s->h1, s->h2}, outd[3] = {s->h1, s->h2, s->n_out};
+  size_t n = 8 * 4;
+  for (int l = 0; l < 3; ++l) n += 4 * ((size_t)in[l] * outd[l] + outd[l]);
+  n += 8 * (size_t)s->n_out;
+  *size = n;
+  if (!blob) return MS_OK;  // size query
+  if (cap < n) return sfail(MS_E_ARG, "blob too small (" + std::to_string(n) + " bytes needed)");
+  hipError_t e = hipDeviceSynchronize();
+  if (e != hipSuccess) return hipst(e, "synchronise");
+  unsigned char *p = (unsigned char *)blob;
+  const uint32_t head[8] = {kBlobMagic, 1u, (uint32_t)s->n_in, (uint32_t)s->h1, (uint32_t)s->h2,
+                            (uint32_t)s->n_out, 0u, 0u};
+  std::memcpy(p, head, sizeof head);
+  p += sizeof head;
+  for (int l = 0; l < 3 && e == hipSuccess; ++l) {
+    const size_t nw = (size_t)in[l] * outd[l];
+    e = hipMemcpy(p, s->W[l], 4 * nw, hipMemcpyDeviceToHost);
+    p += 4 * nw;
+    if (e == hipSuccess) e = hipMemcpy(p, s->b[l], 4 * (size_t)outd[l], hipMemcpyDeviceToHost);
+    p += 4 * (size_t)outd[l];
+  }
+  if (e == hipSuccess) e = hipMemcpy(p, s->mean, 4 * (size_t)s->n_out, hipMemcpyDeviceToHost);
+  p += 4 * (size_t)s->n_out;
+  if (e == hipSuccess) e = hipMemcpy(p, s->stdv, 4 * (size_t)s->n_out, hipMemcpyDeviceToHost);
+  return hipst(e, "save");
+}
+
+ms_status ms_surrogate_load(ms_surrogate *s, const void *blob, size_t size) {
+  s_err.clear();
+  if (!s || !blob) return sfail(MS_E_ARG, "NULL argument");
+  size_t need = 0;
+  ms_status st = ms_surrogate_save(s, nullptr, 0, &need);
+  if (st != MS_OK) return st;
+  uint32_t head[8];
+  if (size < sizeof head) return sfail(MS_E_ARG, "blob too small");
+  std::memcpy(head, blob, sizeof head);
+  if (head[0] != kBlobMagic || head[1] != 1u) return sfail(MS_E_ARG, "not a surrogate blob");
+  if ((int)head[2] != s->n_in || (int)head[3] != s->h1 || (int)head[4] != s->h2 ||
+      (int)head[5] != s->n_out)
+    return sfail(MS_E_ARG, "blob layer sizes differ from this network's");
+  if (size != need) return sfail(MS_E_ARG, "blob size does not match its layer sizes");
+  const unsigned char *p = (const unsigned char *)blob + sizeof head;
+  const int in[3] = {s->n_in, s->h1, s->h2}, outd[3] = {s->h1, s->h2, s->n_out};
+  std::vector<float> w[3], b[3];
+  for (int l = 0; l < 3; ++l) {
+    w[l].resize((size_t)in[l] * outd[l]);
+    std::memcpy(w[l].data(), p, 4 * w[l].size());
+    p += 4 * w[l].size();
+    b[l].resize(outd[l]);
+    std::memcpy(b[l].data(), p, 4 * b[l].size());
+    p += 4 * b[l].size();
+  }
+  std::vector<float> mean(s->n_out), stdv(s->n_out);
+  std::memcpy(mean.data(), p, 4 * mean.size());
+  p += 4 * mean.size();
+  std::memcpy(stdv.data(), p, 4 * stdv.size());
+  st = ms_surrogate_set_norm(s, mean.data(), stdv.data());
+  if (st != MS_OK) return st;
+  return ms_surrogate_params(s, 1, w[0].data(), b[0].data(), w[1].data(), b[1].data(),
+                             w[2].data(), b[2].data());
 }
 
 ms_status ms_surrogate_train_step(ms_surrogate *s, int32_t n, const float *q, const float *L,

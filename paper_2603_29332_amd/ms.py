@@ -36,7 +36,7 @@ EXPORTED = ("ms_model_create", "ms_model_destroy", "ms_model_info_get",
             "ms_surrogate_forward_noalloc", "ms_surrogate_noalloc_max", "ms_policy_reserve",
             "ms_model_set_schedule", "ms_model_get_schedule", "ms_model_reserve",
             "ms_model_set_kernel_timing", "ms_model_kernel_times", "ms_model_set_key_nodes",
-            "ms_rollout_record")
+            "ms_rollout_record", "ms_surrogate_train", "ms_surrogate_save", "ms_surrogate_load")
 
 _fptr = C.POINTER(C.c_float)
 _iptr = C.POINTER(C.c_int32)
@@ -74,6 +74,13 @@ class MsExc(C.Structure):
 class MsRecord(C.Structure):
     _fields_ = [("every", C.c_int32)] + [(k, C.c_void_p) for k in (
         "act", "force", "lm", "vm", "power", "xpos", "xmat", "n_applied")]
+
+
+class MsTrainCfg(C.Structure):
+    _fields_ = [("n_samples", C.c_int64), ("batch", C.c_int32), ("iters", C.c_int32),
+                ("step0", C.c_int32), ("norm_samples", C.c_int32), ("lr0", C.c_float),
+                ("lr1", C.c_float), ("seed", C.c_uint64), ("norm_seed", C.c_uint64),
+                ("loss", C.c_void_p)]
 
 
 class MsBatchState(C.Structure):
@@ -131,6 +138,9 @@ def lib():
     L.ms_surrogate_forward.argtypes = [vp, C.c_int32, vp, vp, vp, vp]
     L.ms_surrogate_train_step.argtypes = [vp, C.c_int32, vp, vp, vp, C.c_float, C.c_int32, vp, vp]
     L.ms_surrogate_reserve.argtypes = [vp, C.c_int32]
+    L.ms_surrogate_train.argtypes = [vp, vp, C.POINTER(MsTrainCfg), vp]
+    L.ms_surrogate_save.argtypes = [vp, vp, C.c_size_t, C.POINTER(C.c_size_t)]
+    L.ms_surrogate_load.argtypes = [vp, vp, C.c_size_t]
     L.ms_surrogate_forward_noalloc.argtypes = [vp, C.c_int32, vp, vp, vp, vp]
     L.ms_surrogate_noalloc_max.argtypes = [vp]
     L.ms_surrogate_noalloc_max.restype = C.c_int32
@@ -377,8 +387,6 @@ class Surrogate:
         self.n_in, self.h1, self.h2, self.n_out = (int(x) for x in d)
         self.shapes = [(self.h1, self.n_in), (self.h1,), (self.h2, self.h1), (self.h2,),
                        (self.n_out, self.h2), (self.n_out,)]
-        # the output standardisation last set (the library starts at 0 / 1)
-        self.norm = (np.zeros(self.n_out, np.float32), np.ones(self.n_out, np.float32))
 
     def __del__(self):
         try:
@@ -408,25 +416,33 @@ class Surrogate:
         m = np.ascontiguousarray(mean, np.float32)
         s = np.ascontiguousarray(std, np.float32)
         _check_s(lib().ms_surrogate_set_norm(self.h, m.ctypes.data_as(_fptr), s.ctypes.data_as(_fptr)))
-        self.norm = (m.copy(), s.copy())
-
-    _KEYS = ("W1", "b1", "W2", "b2", "W3", "b3")
 
     def save(self, path):
-        """Write the network (float32 master weights and biases, output
-        standardisation, layer sizes) to an .npz file."""
-        np.savez(path, dims=np.array([self.n_in, self.h1, self.h2, self.n_out], np.int32),
-                 mean=self.norm[0], std=self.norm[1], **dict(zip(self._KEYS, self.params())))
+        """Write the network (layer sizes, float32 weights and biases, output
+        standardisation) as the library's plain binary blob."""
+        n = C.c_size_t()
+        _check_s(lib().ms_surrogate_save(self.h, None, 0, C.byref(n)))
+        buf = (C.c_ubyte * n.value)()
+        _check_s(lib().ms_surrogate_save(self.h, buf, n.value, C.byref(n)))
+        with open(path, "wb") as f:
+            f.write(bytes(buf))
 
     def load(self, path):
-        """Read a network written by save() into this one (same layer sizes);
-        the file holds plain arrays and is read without unpickling."""
-        with np.load(path, allow_pickle=False) as z:
-            dims = tuple(int(x) for x in z["dims"])
-            if dims != (self.n_in, self.h1, self.h2, self.n_out):
-                raise ValueError(f"saved network has layer sizes {dims}")
-            self.set_params([z[k] for k in self._KEYS])
-            self.set_norm(z["mean"], z["std"])
+        """Read a blob written by save() (same layer sizes)."""
+        with open(path, "rb") as f:
+            data = f.read()
+        buf = (C.c_ubyte * len(data)).from_buffer_copy(data)
+        _check_s(lib().ms_surrogate_load(self.h, buf, len(data)))
+
+    def train(self, n_samples=10_000_000, batch=8192, iters=1, lr0=1e-2, lr1=1e-5, seed=41,
+              norm_samples=8192, norm_seed=40, step0=0, loss=None, stream=None):
+        """ms_surrogate_train: Adam on exact labels of sampled poses with a
+        cosine learning-rate decay; the output standardisation first when
+        norm_samples > 0. loss: device float32 [iters] or None."""
+        c = MsTrainCfg(int(n_samples), int(batch), int(iters), int(step0), int(norm_samples),
+                       float(lr0), float(lr1), int(seed), int(norm_seed),
+                       _dp(loss).value if loss is not None else None)
+        _check_s(lib().ms_surrogate_train(self.model.h, self.h, C.byref(c), _stream(stream)))
 
     def sample(self, q, seed, offset=0, stream=None):
         _check_s(lib().ms_surrogate_sample(self.h, q.shape[0], seed, offset, _dp(q), _stream(stream)))

@@ -320,13 +320,10 @@ def test_training_gain_fewer_fallbacks_and_smaller_error():
         return err, fb.sum().item() / (E * 100)
 
     untrained = ms.Surrogate(gm, hidden=512, seed=41)
-    mean, std = surrogate.output_stats(gm, untrained)
-    untrained.set_norm(mean, std)
+    untrained.train(iters=0, norm_samples=8192)       # output standardisation only
     e0, f0 = error_and_fallback(untrained)
     trained = ms.Surrogate(gm, hidden=512, seed=41)
-    trained.set_norm(mean, std)
-    surrogate.train(gm, trained, n_samples=10_000_000, batch=8192,
-                    epochs=1500 * 8192 / 10_000_000)
+    surrogate.train(trained, n_samples=10_000_000, batch=8192, epochs=1500 * 8192 / 10_000_000)
     e1, f1 = error_and_fallback(trained)
     print(f"median worst-muscle length error {e0:.4f} m untrained, {e1:.4f} m trained; "
           f"fallback rate at 1 cm {f0:.3f} untrained, {f1:.3f} trained")
@@ -342,7 +339,7 @@ def test_save_and_load_reproduce_the_network(setup, tmp_path):
     s.set_params([rng.normal(0, 0.3, sh).astype(np.float32) for sh in s.shapes])
     s.set_norm(rng.normal(0, 0.1, s.n_out).astype(np.float32),
                rng.uniform(0.5, 2.0, s.n_out).astype(np.float32))
-    path = tmp_path / "net.npz"
+    path = tmp_path / "net.msg"
     s.save(path)
     s2 = ms.Surrogate(gm, hidden=s.h1, seed=99)
     s2.load(path)
@@ -548,3 +545,97 @@ def test_full_size_prediction_taken_step_matches_oracle(human_net):
     print(f"prediction-taken whole-body step: worst per-block error {worst:.2e}")
     assert np.abs(g[1][near] - ex[1][near]).max() > 1e-3
     _identity_norm(s)
+
+
+# ------------------------------------------------ training behind the C ABI
+def _host_poses(m, seed, offset, n, n_in):
+    """Poses of the library's pose sampler regenerated on the host from its
+    published definition: input i of pose p is lo + (hi - lo) u with u the
+    top 24 bits x 2^-24 of SplitMix64(SplitMix64(seed ^ (offset + p)) ^ i)."""
+    M = (1 << 64) - 1
+
+    def sm(x):
+        z = (x + 0x9E3779B97F4A7C15) & M
+        z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & M
+        z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & M
+        return z ^ (z >> 31)
+
+    qi, lo, hi = _hinge_inputs(m) if m["jtype"][0] == 2 else (
+        np.arange(m["nq"]), np.asarray(m["qlo"], np.float32), np.asarray(m["qhi"], np.float32))
+    q = np.zeros((n, m["nq"]), np.float32)
+    if m["jtype"][0] == 2:
+        q[:, 3] = 1.0
+    for p in range(n):
+        key = sm(seed ^ (offset + p))
+        for i in range(len(qi)):
+            u = np.float32((sm(key ^ i) >> 40) * 5.9604644775390625e-8)
+            q[p, qi[i]] = np.float32(lo[i] + np.float32(hi[i] - lo[i]) * u)
+    return q
+
+
+def _blob(path, s):
+    """Layer sizes, weights and standardisation from a saved blob."""
+    raw = open(path, "rb").read()
+    head = np.frombuffer(raw[:32], np.uint32)
+    assert head[0] == 0x4D534731 and head[1] == 1
+    n_in, h1, h2, n_out = (int(x) for x in head[2:6])
+    body = np.frombuffer(raw[32:], np.float32)
+    sizes = [h1 * n_in, h1, h2 * h1, h2, n_out * h2, n_out, n_out, n_out]
+    assert body.size == sum(sizes)
+    parts, o = [], 0
+    for k in sizes:
+        parts.append(body[o:o + k])
+        o += k
+    return (n_in, h1, h2, n_out), parts
+
+
+def test_train_sets_the_standardisation_of_oracle_labels(tmp_path):
+    """ms_surrogate_train with no steps sets each output's mean and standard
+    deviation over the sampled poses; the oracle labels of the same poses
+    (regenerated on the host) give the same statistics."""
+    m = synth.chain_model(1)
+    gm = ms.Model(m)
+    o = oracle.Oracle(m)
+    s = ms.Surrogate(gm, hidden=64, seed=7)
+    n = 200
+    s.train(iters=0, norm_samples=n, norm_seed=40, batch=64)
+    s.save(tmp_path / "n.msg")
+    dims, parts = _blob(tmp_path / "n.msg", s)
+    mean, std = parts[6], parts[7]
+    spans = _oracle_spans(m, o)
+    q = _host_poses(m, 40, 0, n, s.n_in)
+    y = _oracle_targets(m, o, spans, q.astype(np.float64))
+    have = np.r_[np.ones(m["n_mus"], bool), spans.reshape(-1) >= 0]
+    mo = y.mean(0)
+    so = np.sqrt(((y - mo) ** 2).mean(0))
+    assert np.abs(mean[have] - mo[have]).max() < 2e-6
+    assert (np.abs(std[have] - so[have]) <= 1e-4 * so[have] + 2e-6).all()
+    assert (mean[~have] == 0).all() and (std[~have] == 1).all()
+
+
+def test_train_equals_its_steps_taken_one_by_one():
+    """Three steps of ms_surrogate_train equal three ms_surrogate_train_step
+    calls on the library's sampled poses and exact labels with the cosine
+    learning rates, bit for bit, and the loss falls."""
+    m = synth.chain_model(1)
+    gm = ms.Model(m)
+    B, iters, lr0, lr1 = 256, 3, 1e-2, 1e-5
+    a = ms.Surrogate(gm, hidden=64, seed=8)
+    b = ms.Surrogate(gm, hidden=64, seed=8)
+    loss = torch.zeros(iters, device=DEV)
+    a.train(n_samples=1000, batch=B, iters=iters, lr0=lr0, lr1=lr1, seed=41, norm_samples=512,
+            loss=loss)
+    b.train(iters=0, norm_samples=512, batch=B)
+    q = torch.zeros(B, m["nq"], device=DEV)
+    L = torch.zeros(B, m["n_mus"], device=DEV)
+    r = torch.zeros(B, m["n_mus"], 3, device=DEV)
+    for it in range(iters):
+        b.sample(q, 41, (it * B) % 1000)
+        gm.geometry(q, L, r)
+        lr = np.float32(lr1 + 0.5 * (lr0 - lr1) * (1.0 + np.cos(np.pi * it / iters)))
+        b.train_step(q, L, r, float(lr), it + 1)
+    torch.cuda.synchronize()
+    for x, y in zip(a.params(), b.params()):
+        assert np.array_equal(x, y)
+    lv = loss.cpu().numpy()
+    assert np.isfinite(lv).all() and lv[-1] < lv[0]

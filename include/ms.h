@@ -432,6 +432,83 @@ ms_status ms_policy_rollout(ms_model *m, ms_policy *p, ms_surrogate *s,
                             void *stream);
 
 /* ------------------------------------------------------------------------
+ * The control step around the physics (Methods: "Observation space",
+ * "Action space", "Unified imitation environment", "Reinforcement learning
+ * with flow-based exploration"; "Simulation parameters" for the substeps).
+ * Per call and env, at time t (control step index ctl_step):
+ *  1. observation s (n_obs values): q with a free root's unit quaternion as
+ *     its rotation vector (nv), q' (nv), key-node world positions (3 n_key)
+ *     and orientations as the first two columns of R, column by column
+ *     (6 n_key), the muscle state of the previous call's last substep from
+ *     mstate: activations, forces / F0, normalised fibre lengths and
+ *     velocities (4 n_mus, caller's order), the hinges' reference targets
+ *     (n_h, hinge coordinates in node order), and the key-node positions and
+ *     orientations of the reference pose (the env's root, hinges at their
+ *     targets; 9 n_key). Reference target of hinge h of env e at time t:
+ *     sum over j < 3 of A sin(2 pi f t + phi), A = 0.3 a, f = 0.5 + 1.5 b Hz,
+ *     phi = 2 pi c, a, b, c the top 24 bits x 2^-24 of SplitMix64(K ^ 0),
+ *     (K ^ 1), (K ^ 2), K = SplitMix64(SplitMix64(ref_seed ^ e) ^ (3 h + j)):
+ *     a synthetic stand-in for the retargeted reference motion;
+ *  2. excitations (unless u_in is given): a0 = mu(s) + exp(log_std) xi from
+ *     the initial sampler (mu its network's output, xi standard normal by the
+ *     Box-Muller transform sqrt(-2 ln u1) cos(2 pi u2) of u1 = (i1 + 1/2)
+ *     2^-24, u2 = (i2 + 1/2) 2^-24, i1 = z >> 40, i2 = (z >> 16) & 0xFFFFFF,
+ *     z = SplitMix64(SplitMix64(SplitMix64(noise_seed ^ e) ^ ctl_step) ^ m)),
+ *     refined by flow_steps explicit Euler steps of the flow velocity field
+ *     a += flow_dt psi(t_k, s, a), t_k = k flow_dt (Eq. pi_ode), psi the flow
+ *     network on [s, a, t_k] (padded to n_in + n_at), then u = clamp(a, 0, 1);
+ *  3. n_sub physics substeps of dt with u held (status, n_applied as for
+ *     ms_rollout); the last substep's muscle state goes to mstate;
+ *  4. reward r = -log(1 - D(Delta)) = softplus(z) (Eq. tracking_r), z the
+ *     discriminator network's output on the tracking error Delta = [hinge
+ *     coordinates - their targets (n_h), key-node positions - the reference
+ *     pose's (3 n_key)] at t + n_sub dt (padded to n_din).
+ * Networks: three layers, SiLU hidden layers, linear outputs, bfloat16
+ * matrix-core GEMMs with float32 accumulation, LeCun-uniform weights from
+ * their seeds (the flow's first layer over all n_obs + n_mus + 1 inputs),
+ * zero biases; log_std = log(sigma0). No training here. */
+typedef struct ms_controller ms_controller;
+typedef struct {
+  int32_t hidden;          /* hidden width of every network (multiple of 8) */
+  int32_t n_sub;           /* physics substeps per control step (>= 1) */
+  int32_t flow_steps;      /* Euler steps of the flow (>= 0) */
+  float flow_dt;           /* their step (>= 0) */
+  float sigma0;            /* initial sampler's standard deviation (> 0) */
+  int32_t n_key;           /* key nodes (<= 64) */
+  const int32_t *key_nodes; /* host [n_key] */
+  uint64_t ref_seed, noise_seed, pi_seed, flow_seed, disc_seed;
+} ms_controller_desc;
+/* Optional device outputs of a control step (each may be NULL): obs
+ * [n_env][n_obs], a0 [n_env][n_mus] (initial sample), u [n_env][n_mus]
+ * (excitations applied), delta [n_env][n_h + 3 n_key], n_applied [n_env]. */
+typedef struct {
+  float *obs, *a0, *u, *delta;
+  uint32_t *n_applied;
+} ms_ctl_out;
+ms_status ms_controller_create(ms_model *m, const ms_controller_desc *d, ms_controller **out);
+void ms_controller_destroy(ms_controller *c);
+/* dims[6] = n_obs, n_in, n_at, n_din, hidden, n_h */
+ms_status ms_controller_dims(const ms_controller *c, int32_t *dims);
+/* host copies of a network's float32 parameters (which: 0 initial sampler,
+ * 1 flow, 2 discriminator; set = 0 reads, 1 writes): W[l] [out][in], b[l];
+ * the flow's W[0] is its observation block [hidden][n_in] and w_at (may be
+ * NULL) its (action, time) block [hidden][n_at] (held in bfloat16); log_std
+ * [n_mus] for which = 0 (may be NULL). */
+ms_status ms_controller_params(ms_controller *c, int32_t which, int32_t set, float **W,
+                               float **b, float *w_at, float *log_std);
+/* Reserve the controller's and its model's workspaces for n_env envs. */
+ms_status ms_controller_reserve(ms_controller *c, int32_t n_env);
+/* One control step of n_env envs (state as ms_rollout; mstate device
+ * [4][n_env][n_mus] in/out, zeros before the first step; reward device
+ * [n_env]; u_in device [n_env][n_mus] or NULL). Asynchronous on stream;
+ * grows the workspaces when n_env exceeds them (allocating). */
+ms_status ms_controller_step(ms_controller *c, int32_t n_env, float *q, float *qd, float *act,
+                             uint32_t *status, float *mstate, int64_t ctl_step, double t,
+                             const ms_step_opts *opts, const float *u_in, float *reward,
+                             const ms_ctl_out *out, void *stream);
+const char *ms_controller_last_error(void);
+
+/* ------------------------------------------------------------------------
  * Uneven batches: envs of several models (different sizes) stepped in one
  * call. Not a passage of the paper: the batched-rollout setting of its
  * Methods (many environments at once, Simulation throughput) with models of

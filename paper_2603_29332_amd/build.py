@@ -12,7 +12,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libms.so")
 SOURCES = ["ms_model.cpp", "ms_step.hip", "ms_step_v2.hip", "ms_step_v4.hip", "ms_step_v6.hip",
-           "ms_step_v8.hip", "ms_step_split.hip", "ms_batch.hip", "ms_gemm.hip", "ms_mlp.hip"]
+           "ms_step_v8.hip", "ms_step_split.hip", "ms_batch.hip", "ms_gemm.hip", "ms_mlp.hip",
+           "ms_control.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC",
          # no packed-FP32 instructions in generated code

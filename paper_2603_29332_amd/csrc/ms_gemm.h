@@ -10,7 +10,7 @@ typedef __hip_bfloat16 bf16;
 // C[M][N] = op(A) op(B): op(A)(m, k) = TA ? A[k * lda + m] : A[m * lda + k],
 // op(B)(k, n) = TB ? B[n * ldb + k] : B[k * ldb + n]. bfloat16 operands,
 // float32 accumulation. Epilogue, per element (m, n):
-//   v = acc * alpha + (bias ? bias[n] : 0)
+//   v = acc * alpha + (bias ? bias[n] : 0) + (addc ? addc[m * ldc + n] : 0)
 //   if dact: v *= SiLU'(dact[m * ldc + n])           (backward through SiLU)
 //   if z_out: z_out[m * ldc + n] = v                  (pre-activation, f32)
 //   if act == 1: v = SiLU(v);  if act == 2: v = sigmoid(v)
@@ -18,6 +18,7 @@ typedef __hip_bfloat16 bf16;
 //   if c_f32: c_f32[m * ldc + n] = v ;  if c_bf16: c_bf16[m * ldc + n] = bf16(v)
 struct GemmEpi {
   const float *bias = nullptr;
+  const float *addc = nullptr;
   const float *dact = nullptr;
   float *z_out = nullptr;
   int act = 0;

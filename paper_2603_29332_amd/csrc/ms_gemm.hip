@@ -130,6 +130,7 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const bf16 *A
         const size_t o = (size_t)blockIdx.z * z_stride + (size_t)m * epi.ldc + n;
         float v = acc[i][j][e] * epi.alpha;
         if (epi.bias) v += epi.bias[n];
+        if (epi.addc) v += epi.addc[o];
         if (epi.dact) v *= silu_slope(epi.dact[o]);
         if (epi.z_out) epi.z_out[o] = v;
         if (epi.act == 1) v = silu(v);

@@ -36,7 +36,10 @@ EXPORTED = ("ms_model_create", "ms_model_destroy", "ms_model_info_get",
             "ms_surrogate_forward_noalloc", "ms_surrogate_noalloc_max", "ms_policy_reserve",
             "ms_model_set_schedule", "ms_model_get_schedule", "ms_model_reserve",
             "ms_model_set_kernel_timing", "ms_model_kernel_times", "ms_model_set_key_nodes",
-            "ms_rollout_record", "ms_surrogate_train", "ms_surrogate_save", "ms_surrogate_load")
+            "ms_rollout_record", "ms_surrogate_train", "ms_surrogate_save", "ms_surrogate_load",
+            "ms_controller_create", "ms_controller_destroy", "ms_controller_dims",
+            "ms_controller_params", "ms_controller_reserve", "ms_controller_step",
+            "ms_controller_last_error")
 
 _fptr = C.POINTER(C.c_float)
 _iptr = C.POINTER(C.c_int32)
@@ -81,6 +84,17 @@ class MsTrainCfg(C.Structure):
                 ("step0", C.c_int32), ("norm_samples", C.c_int32), ("lr0", C.c_float),
                 ("lr1", C.c_float), ("seed", C.c_uint64), ("norm_seed", C.c_uint64),
                 ("loss", C.c_void_p)]
+
+
+class MsCtlDesc(C.Structure):
+    _fields_ = [("hidden", C.c_int32), ("n_sub", C.c_int32), ("flow_steps", C.c_int32),
+                ("flow_dt", C.c_float), ("sigma0", C.c_float), ("n_key", C.c_int32),
+                ("key_nodes", C.c_void_p), ("ref_seed", C.c_uint64), ("noise_seed", C.c_uint64),
+                ("pi_seed", C.c_uint64), ("flow_seed", C.c_uint64), ("disc_seed", C.c_uint64)]
+
+
+class MsCtlOut(C.Structure):
+    _fields_ = [(k, C.c_void_p) for k in ("obs", "a0", "u", "delta", "n_applied")]
 
 
 class MsBatchState(C.Structure):
@@ -138,6 +152,16 @@ def lib():
     L.ms_surrogate_forward.argtypes = [vp, C.c_int32, vp, vp, vp, vp]
     L.ms_surrogate_train_step.argtypes = [vp, C.c_int32, vp, vp, vp, C.c_float, C.c_int32, vp, vp]
     L.ms_surrogate_reserve.argtypes = [vp, C.c_int32]
+    L.ms_controller_create.argtypes = [vp, C.POINTER(MsCtlDesc), C.POINTER(vp)]
+    L.ms_controller_destroy.argtypes = [vp]
+    L.ms_controller_destroy.restype = None
+    L.ms_controller_dims.argtypes = [vp, _iptr]
+    L.ms_controller_params.argtypes = [vp, C.c_int32, C.c_int32, C.POINTER(_fptr),
+                                       C.POINTER(_fptr), _fptr, _fptr]
+    L.ms_controller_reserve.argtypes = [vp, C.c_int32]
+    L.ms_controller_step.argtypes = [vp, C.c_int32, vp, vp, vp, vp, vp, C.c_int64, C.c_double,
+                                     C.POINTER(MsOpts), vp, vp, C.POINTER(MsCtlOut), vp]
+    L.ms_controller_last_error.restype = C.c_char_p
     L.ms_surrogate_train.argtypes = [vp, vp, C.POINTER(MsTrainCfg), vp]
     L.ms_surrogate_save.argtypes = [vp, vp, C.c_size_t, C.POINTER(C.c_size_t)]
     L.ms_surrogate_load.argtypes = [vp, vp, C.c_size_t]
@@ -573,3 +597,73 @@ class Policy:
                                          q.shape[0], _dp(q), _dp(qd), _dp(act), _dp(status),
                                          n_steps, decim, float(t0), C.byref(o), float(tol),
                                          _dp(fb_count), _dp(u_record), _stream(stream)))
+
+
+def _check_c(rc):
+    if rc != 0:
+        raise MsError(rc, lib().ms_controller_last_error().decode())
+
+
+class Controller:
+    """The control step around the physics bound to a Model: observation,
+    Gaussian initial sampler refined by a flow velocity field, n_sub
+    substeps with the excitations held, discriminator reward (random-init
+    networks)."""
+
+    def __init__(self, model: Model, keys, hidden=1024, n_sub=10, flow_steps=20, flow_dt=0.05,
+                 sigma0=0.1, ref_seed=52, noise_seed=53, pi_seed=54, flow_seed=55, disc_seed=56):
+        L = lib()
+        self.model = model
+        self._keys = np.ascontiguousarray(keys, np.int32)
+        d = MsCtlDesc(int(hidden), int(n_sub), int(flow_steps), float(flow_dt), float(sigma0),
+                      len(self._keys), self._keys.ctypes.data, ref_seed, noise_seed, pi_seed,
+                      flow_seed, disc_seed)
+        h = C.c_void_p()
+        _check_c(L.ms_controller_create(model.h, C.byref(d), C.byref(h)))
+        self.h = h
+        dims = np.zeros(6, np.int32)
+        _check_c(L.ms_controller_dims(h, dims.ctypes.data_as(_iptr)))
+        self.n_obs, self.n_in, self.n_at, self.n_din, self.hidden, self.n_h = (int(x) for x in dims)
+        self.n_sub = int(n_sub)
+
+    def __del__(self):
+        try:
+            if getattr(self, "h", None):
+                lib().ms_controller_destroy(self.h)
+        except Exception:
+            pass
+
+    def params(self, which):
+        """(W1, b1, W2, b2, W3, b3) of network `which` (0 initial sampler, 1
+        flow, 2 discriminator) as float32 [out][in]; plus the flow's (action,
+        time) block for which = 1 and log_std for which = 0."""
+        nm = self.model.n_mus
+        h = self.hidden
+        ins = [self.n_in if which < 2 else self.n_din, h, h]
+        outs = [h, h, 1 if which == 2 else nm]
+        W = [np.zeros((o, i), np.float32) for i, o in zip(ins, outs)]
+        b = [np.zeros(o, np.float32) for o in outs]
+        wat = np.zeros((h, self.n_at), np.float32) if which == 1 else None
+        ls = np.zeros(nm, np.float32) if which == 0 else None
+        Wp = (_fptr * 3)(*[x.ctypes.data_as(_fptr) for x in W])
+        bp = (_fptr * 3)(*[x.ctypes.data_as(_fptr) for x in b])
+        _check_c(lib().ms_controller_params(
+            self.h, which, 0, Wp, bp, wat.ctypes.data_as(_fptr) if wat is not None else None,
+            ls.ctypes.data_as(_fptr) if ls is not None else None))
+        out = [W[0], b[0], W[1], b[1], W[2], b[2]]
+        return out, wat, ls
+
+    def reserve(self, n_env):
+        _check_c(lib().ms_controller_reserve(self.h, int(n_env)))
+
+    def step(self, q, qd, act, status, mstate, ctl_step, t, dt, reward, contact=True, u_in=None,
+             out=None, stream=None):
+        """One control step; out: dict of device tensors (obs, a0, u, delta,
+        n_applied), each optional."""
+        out = out or {}
+        o = MsOpts(dt, int(contact))
+        co = MsCtlOut(*[_dp(out.get(k)) for k in ("obs", "a0", "u", "delta", "n_applied")])
+        _check_c(lib().ms_controller_step(self.h, q.shape[0], _dp(q), _dp(qd), _dp(act),
+                                          _dp(status), _dp(mstate), int(ctl_step), float(t),
+                                          C.byref(o), _dp(u_in), _dp(reward), C.byref(co),
+                                          _stream(stream)))

@@ -60,6 +60,7 @@ def parse():
                    help="sentinel length residual (m) above which an env falls back")
     p.add_argument("--no-uneven", action="store_true", help="skip the uneven-batch leg")
     p.add_argument("--no-policy", action="store_true", help="skip the policy-driven leg")
+    p.add_argument("--no-control", action="store_true", help="skip the control-step leg")
     p.add_argument("--policy-envs", type=int, default=65536)
     p.add_argument("--policy-steps", type=int, default=2000)
     p.add_argument("--uneven-steps", type=int, default=500)
@@ -236,6 +237,9 @@ def main():
     }
     line["observables"] = observables_leg(m, gm, dt, dev, E, (rho, s, mean))
     progress("observables leg done")
+    if not a.no_control:
+        line["control"] = control_leg(m, gm, dt, dev)
+        progress("control leg done")
     sg = None
     rad = None if a.no_cpu else {"exact": rad_run(m, gm, dt, dev),
                                  "exact_contact_off": rad_run(m, gm, dt, dev, contact=False)}
@@ -405,6 +409,56 @@ def observables_leg(m, gm, dt, dev, E, ar1, every=10, n_calls=3):
             "observable_GBps": rec_bytes * E * n_rec / (ms_call / 1e3) / 1e9,
             "note": "scheduled env-steps per second of 100-step calls that also write the "
                     "observables of every 10th step"}
+
+
+def control_leg(m, gm, dt, dev, E=2048, n_ctl=20):
+    """Control steps of 2048 envs: observation, Gaussian initial sampler and
+    20 flow steps (1024-wide networks), 10 physics substeps with the
+    excitations held, discriminator reward; and the same control steps with
+    given random excitations (no policy networks), the paper's throughput
+    setting. Environment steps per second count control steps."""
+    import torch
+
+    from paper_2603_29332_amd import ms, synth
+    keys = np.flatnonzero(np.asarray(m["mass"]) > 0)[::2][:10]
+    c = ms.Controller(gm, keys)
+    c.reserve(E)
+    q0, qd0, a0 = synth.human_initial_state(m, E)
+    stream = torch.cuda.current_stream()
+    u_rand = torch.rand(E, m["n_mus"], device=dev, generator=torch.Generator(dev).manual_seed(7))
+    out = {}
+    for label, u_in in (("policy_flow_reward", None), ("random_excitations", u_rand)):
+        q, qd, act = (torch.tensor(v, device=dev) for v in (q0, qd0, a0))
+        mst = torch.zeros(4, E, m["n_mus"], device=dev)
+        st = torch.zeros(E, dtype=torch.int32, device=dev)
+        rew = torch.zeros(E, device=dev)
+        napp = torch.zeros(E, dtype=torch.int32, device=dev)
+        for k in range(2):
+            c.step(q, qd, act, st, mst, k, k * c.n_sub * dt, dt, rew, True, u_in=u_in,
+                   stream=stream)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for k in range(2, 2 + n_ctl):
+            c.step(q, qd, act, st, mst, k, k * c.n_sub * dt, dt, rew, True, u_in=u_in,
+                   out={"n_applied": napp}, stream=stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms_ctl = e0.elapsed_time(e1) / n_ctl
+        good = (st == 0) & torch.isfinite(rew)
+        out[label] = {"control_steps_per_s": E / (ms_ctl / 1e3), "ms_per_control_step": ms_ctl,
+                      "physics_env_steps_per_s": E * c.n_sub / (ms_ctl / 1e3),
+                      "applied_fraction": float(napp.sum().item()) / (E * c.n_sub * n_ctl),
+                      "mean_reward_ok_envs": float(rew[good].mean().item()) if good.any() else None,
+                      "failed_envs": int((st != 0).sum().item())}
+    out.update({"envs": E, "substeps": c.n_sub, "dt_s": dt, "flow_steps": 20, "hidden": c.hidden,
+                "key_bodies": int(len(keys)), "obs_dim": c.n_obs,
+                "note": "environment steps = control steps of 10 physics substeps; random-init "
+                        "networks (initial sampler, flow velocity field, discriminator). For "
+                        "context only (other hardware, model, contact model and a 2 ms substep): "
+                        "the paper reports 7,107 environment steps/s with random actions on one "
+                        "RTX 5090"})
+    return out
 
 
 def policy_leg(a, m, gm, sg, dt, dev):

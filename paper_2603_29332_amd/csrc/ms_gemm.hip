@@ -141,6 +141,109 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const bf16 *A
       }
 }
 
+// The forward shape, C = A B^T with A [M][K] and B [N][K] both row-major
+// (activations times a weight matrix stored [out][in]): a BM x BN tile per
+// 256-thread workgroup (2 x 2 wavefronts, each BM/2 x BN/2 as 16 x 16 MFMA
+// tiles), K in steps of 64 through two LDS buffers: the next step's global
+// loads are issued into registers before the current step's MFMAs and stored
+// into the other buffer after them, one barrier per step.
+constexpr int NK = 64, NLK = NK + 8;
+
+template <int BMt, int BNt>
+__global__ __launch_bounds__(256) void k_gemm_nt(int M, int N, int K, const bf16 *A, int lda,
+                                                 const bf16 *B, int ldb, GemmEpi epi) {
+  constexpr int TM = BMt / 32, TN = BNt / 32;          // MFMA tiles per wavefront
+  constexpr int CA = BMt / 32, CB = BNt / 32;          // 16-byte chunks per thread and step
+  __shared__ __align__(16) unsigned short As[2][BMt * NLK];
+  __shared__ __align__(16) unsigned short Bs[2][BNt * NLK];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int wm = w >> 1, wn = w & 1;
+  const int m0 = blockIdx.y * BMt, n0 = blockIdx.x * BNt;
+  const unsigned short *ga = reinterpret_cast<const unsigned short *>(A);
+  const unsigned short *gb = reinterpret_cast<const unsigned short *>(B);
+  uint4 ra[CA], rb[CB];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int it = 0; it < CA; ++it) {
+      const int c = tid + 256 * it, row = c >> 3, kc = (c & 7) * 8;
+      const int gm = m0 + row, gk = k0 + kc;
+      ra[it] = make_uint4(0, 0, 0, 0);
+      if (gm < M && gk < K) ra[it] = *reinterpret_cast<const uint4 *>(ga + (size_t)gm * lda + gk);
+    }
+#pragma unroll
+    for (int it = 0; it < CB; ++it) {
+      const int c = tid + 256 * it, row = c >> 3, kc = (c & 7) * 8;
+      const int gn = n0 + row, gk = k0 + kc;
+      rb[it] = make_uint4(0, 0, 0, 0);
+      if (gn < N && gk < K) rb[it] = *reinterpret_cast<const uint4 *>(gb + (size_t)gn * ldb + gk);
+    }
+  };
+  auto stash = [&](int buf) {
+#pragma unroll
+    for (int it = 0; it < CA; ++it) {
+      const int c = tid + 256 * it, row = c >> 3, kc = (c & 7) * 8;
+      *reinterpret_cast<uint4 *>(&As[buf][row * NLK + kc]) = ra[it];
+    }
+#pragma unroll
+    for (int it = 0; it < CB; ++it) {
+      const int c = tid + 256 * it, row = c >> 3, kc = (c & 7) * 8;
+      *reinterpret_cast<uint4 *>(&Bs[buf][row * NLK + kc]) = rb[it];
+    }
+  };
+  f32x4 acc[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const int nk = (K + NK - 1) / NK;
+  fetch(0);
+  stash(0);
+  __syncthreads();
+  const int kq = (lane >> 4) * 8, r = lane & 15;
+  for (int kt = 0; kt < nk; ++kt) {
+    const int cur = kt & 1;
+    if (kt + 1 < nk) fetch((kt + 1) * NK);
+#pragma unroll
+    for (int s = 0; s < NK / 32; ++s) {
+      bf16x8 a[TM], b[TN];
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+        a[i] = *reinterpret_cast<const bf16x8 *>(&As[cur][(wm * (BMt / 2) + i * 16 + r) * NLK + s * 32 + kq]);
+#pragma unroll
+      for (int j = 0; j < TN; ++j)
+        b[j] = *reinterpret_cast<const bf16x8 *>(&Bs[cur][(wn * (BNt / 2) + j * 16 + r) * NLK + s * 32 + kq]);
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+    if (kt + 1 < nk) stash(cur ^ 1);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int m = m0 + wm * (BMt / 2) + i * 16 + (lane >> 4) * 4 + e;
+        const int n = n0 + wn * (BNt / 2) + j * 16 + (lane & 15);
+        if (m >= M || n >= N) continue;
+        const size_t o = (size_t)m * epi.ldc + n;
+        float v = acc[i][j][e] * epi.alpha;
+        if (epi.bias) v += epi.bias[n];
+        if (epi.addc) v += epi.addc[o];
+        if (epi.dact) v *= silu_slope(epi.dact[o]);
+        if (epi.z_out) epi.z_out[o] = v;
+        if (epi.act == 1) v = silu(v);
+        if (epi.act == 2) v = 1.0f / (1.0f + expf(-v));
+        if (epi.scale) v = v * epi.scale[n] + epi.shift[n];
+        if (epi.c_f32) epi.c_f32[o] = v;
+        if (epi.c_bf16) epi.c_bf16[o] = __float2bfloat16(v);
+      }
+}
+
 // C[m][n] = sum over z of work[z][m][n], slice order
 __global__ void k_splitk_sum(const float *work, int S, size_t stride, int M, int N, int ldc,
                              float *C) {
@@ -170,10 +273,47 @@ static hipError_t gemm_launch(bool ta, bool tb, int M, int N, int K, const bf16 
   return hipGetLastError();
 }
 
+namespace {
+int cu_count() {
+  static int n = 0;
+  if (!n) {
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
+      n = v;
+    else
+      n = 256;
+  }
+  return n;
+}
+}  // namespace
+
+int gemm_nt_tile(int M, int N) {
+  const int cus = cu_count();
+  auto tiles = [&](int bm, int bn) { return (long long)((M + bm - 1) / bm) * ((N + bn - 1) / bn); };
+  // the largest tile that still gives every CU two workgroups
+  if (tiles(128, 128) >= 2 * cus) return 0;
+  if (tiles(64, 128) >= 2 * cus) return 1;
+  return 2;
+}
+
 hipError_t gemm_bf16(bool ta, bool tb, int M, int N, int K, const bf16 *A, int lda, const bf16 *B,
                      int ldb, const GemmEpi &epi, hipStream_t st) {
   if (M <= 0 || N <= 0 || K <= 0) return hipSuccess;
   if (K % 8 || lda % 8 || ldb % 8 || (ta && M % 8) || (!tb && N % 8)) return hipErrorInvalidValue;
+  if (!ta && tb) {
+    const int t = gemm_nt_tile(M, N);
+    if (t == 0)
+      hipLaunchKernelGGL((k_gemm_nt<128, 128>), dim3((N + 127) / 128, (M + 127) / 128), dim3(256), 0,
+                         st, M, N, K, A, lda, B, ldb, epi);
+    else if (t == 1)
+      hipLaunchKernelGGL((k_gemm_nt<64, 128>), dim3((N + 127) / 128, (M + 63) / 64), dim3(256), 0,
+                         st, M, N, K, A, lda, B, ldb, epi);
+    else
+      hipLaunchKernelGGL((k_gemm_nt<64, 64>), dim3((N + 63) / 64, (M + 63) / 64), dim3(256), 0, st, M,
+                         N, K, A, lda, B, ldb, epi);
+    return hipGetLastError();
+  }
   return gemm_launch(ta, tb, M, N, K, A, lda, B, ldb, epi, 1, K, 0, st);
 }
 

@@ -328,11 +328,11 @@ ms_status ms_surrogate_reserve(ms_surrogate *s, int32_t n);
 /* ms_surrogate_forward for callers that cannot allocate device memory
  * (code under HIP graph capture, tight serving loops, harnesses that forbid
  * hipMalloc): it calls no allocating routine and takes its intermediate
- * buffers (packed inputs, both hidden layers, outputs) from a static
- * device array of 16 MiB per GPU, held until the process ends. The caller
- * still passes inputs and outputs. n is limited to what fits that array,
- * ms_surrogate_noalloc_max(s) poses (1,251 for a 74-input, 512-wide,
- * 700-muscle network); larger n returns MS_E_UNSUPPORTED with nothing
+ * buffers (packed inputs and both hidden layers; the output layer writes L
+ * and r) from a static device array of 16 MiB per GPU, held until the
+ * process ends. The caller still passes inputs and outputs. n is limited to
+ * what fits that array, ms_surrogate_noalloc_max(s) poses (7,598 for a
+ * 74-input, 512-wide network); larger n returns MS_E_UNSUPPORTED with nothing
  * launched. Every call on one GPU shares that GPU's array: calls that
  * overlap in time on one GPU (several streams or host threads) race and
  * must be serialised by the caller. Results equal ms_surrogate_forward's

@@ -16,6 +16,8 @@ typedef __hip_bfloat16 bf16;
 //   if act == 1: v = SiLU(v);  if act == 2: v = sigmoid(v)
 //   if scale: v = v * scale[n] + shift[n]             (de-standardisation)
 //   if c_f32: c_f32[m * ldc + n] = v ;  if c_bf16: c_bf16[m * ldc + n] = bf16(v)
+//   if c2 and n >= split: c2[m * ldc2 + n - split] = v instead of c_f32 (the
+//   columns from `split` on go to a second matrix)
 struct GemmEpi {
   const float *bias = nullptr;
   const float *addc = nullptr;
@@ -27,6 +29,8 @@ struct GemmEpi {
   bf16 *c_bf16 = nullptr;
   int ldc = 0;
   float alpha = 1.0f;
+  float *c2 = nullptr;
+  int split = 0, ldc2 = 0;
 };
 
 // C[M][N] (float32, ldc) = op(A) op(B) with K split into slices computed by

@@ -9,6 +9,16 @@
 // next K tile is fetched into registers while the current one is multiplied.
 #include "ms_gemm.h"
 
+#include <type_traits>
+
+// tile configurations of the forward-shape kernel: BM, BN, wavefronts along
+// M and N, register prefetch depth (large, medium and small tiles)
+#ifndef MS_NT0
+#define MS_NT0 128, 128, 4, 4, 1
+#define MS_NT1 64, 128, 2, 4, 1
+#define MS_NT2 64, 64, 2, 4, 1
+#endif
+
 namespace ms {
 namespace {
 
@@ -136,58 +146,65 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const bf16 *A
         if (epi.act == 1) v = silu(v);
         if (epi.act == 2) v = 1.0f / (1.0f + expf(-v));
         if (epi.scale) v = v * epi.scale[n] + epi.shift[n];
-        if (epi.c_f32) epi.c_f32[o] = v;
+        if (epi.c2 && n >= epi.split)
+          epi.c2[(size_t)m * epi.ldc2 + (n - epi.split)] = v;
+        else if (epi.c_f32)
+          epi.c_f32[o] = v;
         if (epi.c_bf16) epi.c_bf16[o] = __float2bfloat16(v);
       }
 }
 
 // The forward shape, C = A B^T with A [M][K] and B [N][K] both row-major
 // (activations times a weight matrix stored [out][in]): a BM x BN tile per
-// 256-thread workgroup (2 x 2 wavefronts, each BM/2 x BN/2 as 16 x 16 MFMA
-// tiles), K in steps of 64 through two LDS buffers: the next step's global
-// loads are issued into registers before the current step's MFMAs and stored
-// into the other buffer after them, one barrier per step.
+// workgroup of WM x WN wavefronts (each BM/WM x BN/WN as 16 x 16 MFMA tiles),
+// K in steps of 64 through two LDS buffers, one barrier per step. Global
+// loads run DEPTH steps ahead in registers (register sets alternate with the
+// step's parity; the K loop is unrolled by two so every set index is a
+// compile-time constant).
 constexpr int NK = 64, NLK = NK + 8;
 
-template <int BMt, int BNt>
-__global__ __launch_bounds__(256) void k_gemm_nt(int M, int N, int K, const bf16 *A, int lda,
-                                                 const bf16 *B, int ldb, GemmEpi epi) {
-  constexpr int TM = BMt / 32, TN = BNt / 32;          // MFMA tiles per wavefront
-  constexpr int CA = BMt / 32, CB = BNt / 32;          // 16-byte chunks per thread and step
+template <int BMt, int BNt, int WM, int WN, int DEPTH>
+__global__ __launch_bounds__(64 * WM * WN) void k_gemm_nt(int M, int N, int K, const bf16 *A,
+                                                         int lda, const bf16 *B, int ldb,
+                                                         GemmEpi epi) {
+  constexpr int NT = 64 * WM * WN;
+  constexpr int TM = BMt / WM / 16, TN = BNt / WN / 16;   // MFMA tiles per wavefront
+  constexpr int CA = BMt * 8 / NT, CB = BNt * 8 / NT;     // 16-byte chunks per thread and step
+  static_assert(CA >= 1 && CB >= 1 && TM >= 1 && TN >= 1, "tile too small for the workgroup");
   __shared__ __align__(16) unsigned short As[2][BMt * NLK];
   __shared__ __align__(16) unsigned short Bs[2][BNt * NLK];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int wm = w >> 1, wn = w & 1;
+  const int wm = w / WN, wn = w % WN;
   const int m0 = blockIdx.y * BMt, n0 = blockIdx.x * BNt;
   const unsigned short *ga = reinterpret_cast<const unsigned short *>(A);
   const unsigned short *gb = reinterpret_cast<const unsigned short *>(B);
-  uint4 ra[CA], rb[CB];
-  auto fetch = [&](int k0) {
+  uint4 ra[DEPTH][CA], rb[DEPTH][CB];
+  auto fetch = [&](uint4 (&xa)[CA], uint4 (&xb)[CB], int k0) {
 #pragma unroll
     for (int it = 0; it < CA; ++it) {
-      const int c = tid + 256 * it, row = c >> 3, kc = (c & 7) * 8;
+      const int c = tid + NT * it, row = c >> 3, kc = (c & 7) * 8;
       const int gm = m0 + row, gk = k0 + kc;
-      ra[it] = make_uint4(0, 0, 0, 0);
-      if (gm < M && gk < K) ra[it] = *reinterpret_cast<const uint4 *>(ga + (size_t)gm * lda + gk);
+      xa[it] = make_uint4(0, 0, 0, 0);
+      if (gm < M && gk < K) xa[it] = *reinterpret_cast<const uint4 *>(ga + (size_t)gm * lda + gk);
     }
 #pragma unroll
     for (int it = 0; it < CB; ++it) {
-      const int c = tid + 256 * it, row = c >> 3, kc = (c & 7) * 8;
+      const int c = tid + NT * it, row = c >> 3, kc = (c & 7) * 8;
       const int gn = n0 + row, gk = k0 + kc;
-      rb[it] = make_uint4(0, 0, 0, 0);
-      if (gn < N && gk < K) rb[it] = *reinterpret_cast<const uint4 *>(gb + (size_t)gn * ldb + gk);
+      xb[it] = make_uint4(0, 0, 0, 0);
+      if (gn < N && gk < K) xb[it] = *reinterpret_cast<const uint4 *>(gb + (size_t)gn * ldb + gk);
     }
   };
-  auto stash = [&](int buf) {
+  auto stash = [&](const uint4 (&xa)[CA], const uint4 (&xb)[CB], int buf) {
 #pragma unroll
     for (int it = 0; it < CA; ++it) {
-      const int c = tid + 256 * it, row = c >> 3, kc = (c & 7) * 8;
-      *reinterpret_cast<uint4 *>(&As[buf][row * NLK + kc]) = ra[it];
+      const int c = tid + NT * it, row = c >> 3, kc = (c & 7) * 8;
+      *reinterpret_cast<uint4 *>(&As[buf][row * NLK + kc]) = xa[it];
     }
 #pragma unroll
     for (int it = 0; it < CB; ++it) {
-      const int c = tid + 256 * it, row = c >> 3, kc = (c & 7) * 8;
-      *reinterpret_cast<uint4 *>(&Bs[buf][row * NLK + kc]) = rb[it];
+      const int c = tid + NT * it, row = c >> 3, kc = (c & 7) * 8;
+      *reinterpret_cast<uint4 *>(&Bs[buf][row * NLK + kc]) = xb[it];
     }
   };
   f32x4 acc[TM][TN];
@@ -195,31 +212,60 @@ __global__ __launch_bounds__(256) void k_gemm_nt(int M, int N, int K, const bf16
   for (int i = 0; i < TM; ++i)
 #pragma unroll
     for (int j = 0; j < TN; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-  const int nk = (K + NK - 1) / NK;
-  fetch(0);
-  stash(0);
-  __syncthreads();
   const int kq = (lane >> 4) * 8, r = lane & 15;
-  for (int kt = 0; kt < nk; ++kt) {
-    const int cur = kt & 1;
-    if (kt + 1 < nk) fetch((kt + 1) * NK);
+  auto compute = [&](int buf) {
 #pragma unroll
     for (int s = 0; s < NK / 32; ++s) {
       bf16x8 a[TM], b[TN];
 #pragma unroll
       for (int i = 0; i < TM; ++i)
-        a[i] = *reinterpret_cast<const bf16x8 *>(&As[cur][(wm * (BMt / 2) + i * 16 + r) * NLK + s * 32 + kq]);
+        a[i] = *reinterpret_cast<const bf16x8 *>(
+            &As[buf][(wm * (BMt / WM) + i * 16 + r) * NLK + s * 32 + kq]);
 #pragma unroll
       for (int j = 0; j < TN; ++j)
-        b[j] = *reinterpret_cast<const bf16x8 *>(&Bs[cur][(wn * (BNt / 2) + j * 16 + r) * NLK + s * 32 + kq]);
+        b[j] = *reinterpret_cast<const bf16x8 *>(
+            &Bs[buf][(wn * (BNt / WN) + j * 16 + r) * NLK + s * 32 + kq]);
 #pragma unroll
       for (int i = 0; i < TM; ++i)
 #pragma unroll
         for (int j = 0; j < TN; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
     }
-    if (kt + 1 < nk) stash(cur ^ 1);
+  };
+  const int nk = (K + NK - 1) / NK;
+  // step j's tile waits in register set j % DEPTH, then in LDS buffer j % 2
+  fetch(ra[0], rb[0], 0);
+  stash(ra[0], rb[0], 0);
+  if (DEPTH == 2 && nk > 1) fetch(ra[DEPTH - 1], rb[DEPTH - 1], NK);
+  __syncthreads();
+  // one step kt of parity P: the load of step kt + DEPTH into set
+  // (kt + DEPTH) % DEPTH, the MFMAs on buffer P, then step kt + 1's tile from
+  // its register set into buffer 1 - P
+  auto step = [&](int kt, auto parity) {
+    constexpr int P = decltype(parity)::value;
+    constexpr int SL = (P + DEPTH) % DEPTH;        // set receiving step kt + DEPTH
+    constexpr int SN = (P + 1) % DEPTH;            // set holding step kt + 1
+    if (kt + DEPTH < nk) fetch(ra[SL], rb[SL], (kt + DEPTH) * NK);
+    compute(P);
+    if (kt + 1 < nk) stash(ra[SN], rb[SN], 1 - P);
     __syncthreads();
+  };
+  using P0 = std::integral_constant<int, 0>;
+  using P1 = std::integral_constant<int, 1>;
+  if (DEPTH == 1) {
+    // one register set: a plain loop over the steps
+    for (int kt = 0; kt < nk; ++kt) {
+      const int cur = kt & 1;
+      if (kt + 1 < nk) fetch(ra[0], rb[0], (kt + 1) * NK);
+      compute(cur);
+      if (kt + 1 < nk) stash(ra[0], rb[0], cur ^ 1);
+      __syncthreads();
+    }
+  } else {
+    for (int kt = 0; kt < nk; kt += 2) {
+      step(kt, P0{});
+      if (kt + 1 < nk) step(kt + 1, P1{});
+    }
   }
 #pragma unroll
   for (int i = 0; i < TM; ++i)
@@ -227,8 +273,8 @@ __global__ __launch_bounds__(256) void k_gemm_nt(int M, int N, int K, const bf16
     for (int j = 0; j < TN; ++j)
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        const int m = m0 + wm * (BMt / 2) + i * 16 + (lane >> 4) * 4 + e;
-        const int n = n0 + wn * (BNt / 2) + j * 16 + (lane & 15);
+        const int m = m0 + wm * (BMt / WM) + i * 16 + (lane >> 4) * 4 + e;
+        const int n = n0 + wn * (BNt / WN) + j * 16 + (lane & 15);
         if (m >= M || n >= N) continue;
         const size_t o = (size_t)m * epi.ldc + n;
         float v = acc[i][j][e] * epi.alpha;
@@ -239,7 +285,10 @@ __global__ __launch_bounds__(256) void k_gemm_nt(int M, int N, int K, const bf16
         if (epi.act == 1) v = silu(v);
         if (epi.act == 2) v = 1.0f / (1.0f + expf(-v));
         if (epi.scale) v = v * epi.scale[n] + epi.shift[n];
-        if (epi.c_f32) epi.c_f32[o] = v;
+        if (epi.c2 && n >= epi.split)
+          epi.c2[(size_t)m * epi.ldc2 + (n - epi.split)] = v;
+        else if (epi.c_f32)
+          epi.c_f32[o] = v;
         if (epi.c_bf16) epi.c_bf16[o] = __float2bfloat16(v);
       }
 }
@@ -297,6 +346,13 @@ int gemm_nt_tile(int M, int N) {
   return 2;
 }
 
+template <int BM, int BN, int WM, int WN, int D>
+void launch_nt(int M, int N, int K, const bf16 *A, int lda, const bf16 *B, int ldb,
+               const GemmEpi &epi, hipStream_t st) {
+  hipLaunchKernelGGL((k_gemm_nt<BM, BN, WM, WN, D>), dim3((N + BN - 1) / BN, (M + BM - 1) / BM),
+                     dim3(64 * WM * WN), 0, st, M, N, K, A, lda, B, ldb, epi);
+}
+
 hipError_t gemm_bf16(bool ta, bool tb, int M, int N, int K, const bf16 *A, int lda, const bf16 *B,
                      int ldb, const GemmEpi &epi, hipStream_t st) {
   if (M <= 0 || N <= 0 || K <= 0) return hipSuccess;
@@ -304,14 +360,11 @@ hipError_t gemm_bf16(bool ta, bool tb, int M, int N, int K, const bf16 *A, int l
   if (!ta && tb) {
     const int t = gemm_nt_tile(M, N);
     if (t == 0)
-      hipLaunchKernelGGL((k_gemm_nt<128, 128>), dim3((N + 127) / 128, (M + 127) / 128), dim3(256), 0,
-                         st, M, N, K, A, lda, B, ldb, epi);
+      launch_nt<MS_NT0>(M, N, K, A, lda, B, ldb, epi, st);
     else if (t == 1)
-      hipLaunchKernelGGL((k_gemm_nt<64, 128>), dim3((N + 127) / 128, (M + 63) / 64), dim3(256), 0,
-                         st, M, N, K, A, lda, B, ldb, epi);
+      launch_nt<MS_NT1>(M, N, K, A, lda, B, ldb, epi, st);
     else
-      hipLaunchKernelGGL((k_gemm_nt<64, 64>), dim3((N + 63) / 64, (M + 63) / 64), dim3(256), 0, st, M,
-                         N, K, A, lda, B, ldb, epi);
+      launch_nt<MS_NT2>(M, N, K, A, lda, B, ldb, epi, st);
     return hipGetLastError();
   }
   return gemm_launch(ta, tb, M, N, K, A, lda, B, ldb, epi, 1, K, 0, st);

@@ -227,18 +227,6 @@ __global__ void k_adam(float *w, float *m, float *v, const float *g, int n, floa
   if (wb) wb[i] = __float2bfloat16(wi);
 }
 
-// Y[p][o] -> L[p][m], r[p][m][3]
-__global__ void k_unpack(const float *Y, int n_mus, int n, float *L, float *r) {
-  const int n_out = 4 * n_mus;
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= n * n_out) return;
-  const int p = t / n_out, o = t % n_out;
-  if (o < n_mus)
-    L[(size_t)p * n_mus + o] = Y[t];
-  else
-    r[(size_t)p * 3 * n_mus + (o - n_mus)] = Y[t];
-}
-
 inline int blocks(long long n, int b = 256) { return (int)((n + b - 1) / b); }
 
 // out[c] = column sums of X[rows][cols], deterministic order
@@ -337,6 +325,7 @@ ms_status hipst(hipError_t e, const char *what) {
 struct FwdWork {
   bf16 *X, *H1, *H2;
   float *Z1, *Z2, *Y;
+  float *L = nullptr, *R = nullptr;  // when set: lengths and moment arms instead of Y
 };
 FwdWork own_work(ms_surrogate *s, bool keep) {
   return FwdWork{s->X, s->H1, s->H2, keep ? s->Z1 : nullptr, keep ? s->Z2 : nullptr, s->Y};
@@ -366,8 +355,13 @@ ms_status forward(ms_surrogate *s, int n, const float *q, bool destd, const FwdW
   if (e != hipSuccess) return hipst(e, "gemm 2");
   GemmEpi e3;
   e3.bias = s->b[2];
-  e3.c_f32 = w.Y;
-  e3.ldc = s->n_out;
+  e3.c_f32 = w.L ? w.L : w.Y;
+  e3.ldc = w.L ? s->n_mus : s->n_out;
+  if (w.L) {
+    e3.c2 = w.R;
+    e3.split = s->n_mus;
+    e3.ldc2 = 3 * s->n_mus;
+  }
   if (destd) {
     e3.scale = s->stdv;
     e3.shift = s->mean;
@@ -407,10 +401,11 @@ ms_status scratch_address(void **out) {
 
 inline size_t align256(size_t b) { return (b + 255) / 256 * 256; }
 
-// Bytes of scratch a forward of n poses takes: X, H1, H2 (bfloat16) and Y.
+// Bytes of scratch a forward of n poses takes: X, H1, H2 (bfloat16); the
+// output layer writes the caller's L and r directly.
 size_t noalloc_bytes(const ms_surrogate *s, long long n) {
   return align256((size_t)n * s->n_in * 2) + align256((size_t)n * s->h1 * 2) +
-         align256((size_t)n * s->h2 * 2) + align256((size_t)n * s->n_out * 4);
+         align256((size_t)n * s->h2 * 2);
 }
 
 }  // namespace
@@ -590,11 +585,10 @@ ms_status ms_surrogate_forward(ms_surrogate *s, int32_t n, const float *q, float
   ms_status st = ensure_cap(s, n);
   if (st != MS_OK) return st;
   hipStream_t hs = (hipStream_t)stream;
-  st = forward(s, n, q, true, own_work(s, false), hs);
-  if (st != MS_OK) return st;
-  hipLaunchKernelGGL(k_unpack, dim3(blocks((long long)n * s->n_out)), dim3(256), 0, hs, s->Y,
-                     s->n_mus, n, L, r);
-  return hipst(hipGetLastError(), "unpack");
+  FwdWork w = own_work(s, false);
+  w.L = L;
+  w.R = r;
+  return forward(s, n, q, true, w, hs);
 }
 
 ms_status ms_surrogate_reserve(ms_surrogate *s, int32_t n) {
@@ -624,15 +618,11 @@ ms_status ms_surrogate_forward_noalloc(ms_surrogate *s, int32_t n, const float *
   w.H1 = (bf16 *)p;
   p += align256((size_t)n * s->h1 * 2);
   w.H2 = (bf16 *)p;
-  p += align256((size_t)n * s->h2 * 2);
-  w.Y = (float *)p;
+  w.Y = nullptr;
   w.Z1 = w.Z2 = nullptr;
-  hipStream_t hs = (hipStream_t)stream;
-  st = forward(s, n, q, true, w, hs);
-  if (st != MS_OK) return st;
-  hipLaunchKernelGGL(k_unpack, dim3(blocks((long long)n * s->n_out)), dim3(256), 0, hs, w.Y,
-                     s->n_mus, n, L, r);
-  return hipst(hipGetLastError(), "unpack");
+  w.L = L;
+  w.R = r;
+  return forward(s, n, q, true, w, (hipStream_t)stream);
 }
 
 int32_t ms_surrogate_noalloc_max(const ms_surrogate *s) {

@@ -52,6 +52,10 @@ ms_status check_opts(const ms_step_opts *o) {
 }
 }  // namespace
 
+// Launches of at least this many envs run in two concurrent halves when the
+// model's split-stream setting is automatic.
+constexpr int kTwoStreamEnvs = 4096;
+
 int effective_schedule(const ms_model *m) {
   if (m->schedule != MS_SCHED_AUTO) return m->schedule;
   // split when the fused step keeps at most one wavefront per SIMD
@@ -59,6 +63,14 @@ int effective_schedule(const ms_model *m) {
   const size_t per_wg = m->t.lt.size() * 4 + (size_t)W * m->t.lds_bytes;
   const int resident = W * (int)((160 * 1024) / per_wg);
   return resident <= 4 ? MS_SCHED_SPLIT : MS_SCHED_FUSED;
+}
+
+hipError_t make_second_stream(ms_model *m) {
+  if (m->s2) return hipSuccess;
+  hipError_t e = hipStreamCreateWithFlags(&m->s2, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&m->ev_fork, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&m->ev_join, hipEventDisableTiming);
+  return e;
 }
 
 ms_status reserve_split(ms_model *m, int n_env, hipStream_t st) {
@@ -105,9 +117,24 @@ hipError_t launch(ms_model *m, const ms::KRun &r, int n_env, int n_steps, hipStr
   }
   if (reserve_split(m, n_env, st) != MS_OK) return hipErrorOutOfMemory;
   const ms::KSplit &w = m->ks;
-  if (m->w_n_env != n_env) {
-    ms::split_env_per_wg(m->k, w, n_env, &m->w_front, &m->w_back);
-    m->w_n_env = n_env;
+  // two halves of the batch on two streams (the caller's and the model's
+  // own), so that one half's kernels overlap the other's
+  int halves = m->split_streams == 1 ? 1
+               : m->split_streams == 2 ? (n_env >= 2 ? 2 : 1)
+                                       : (n_env >= kTwoStreamEnvs ? 2 : 1);
+  if (halves == 2 && !m->s2) {
+    // the second stream is made outside a capture (ms_model_reserve makes
+    // it); a capture that finds none steps the batch on one stream
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(st, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone)
+      halves = 1;
+    else if (hipError_t e = make_second_stream(m); e != hipSuccess)
+      return e;
+  }
+  const int per = (n_env + halves - 1) / halves;
+  if (m->w_n_env != per) {
+    ms::split_env_per_wg(m->k, w, per, &m->w_front, &m->w_back);
+    m->w_n_env = per;
   }
   const int mpt = (m->t.n_mus + 255) / 256;
   bool timed = m->timing > 0;
@@ -115,10 +142,11 @@ hipError_t launch(ms_model *m, const ms::KRun &r, int n_env, int n_steps, hipStr
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     timed = hipStreamIsCapturing(st, &cs) == hipSuccess && cs == hipStreamCaptureStatusNone;
   }
-  // one kernel, bracketed by timing events when timing is on
+  // one kernel, bracketed by timing events when timing is on (the first
+  // half's kernels on the caller's stream)
   int s = 0;
-  auto timed_launch = [&](int kernel, auto &&fn) -> hipError_t {
-    if (!timed || s % m->timing) return fn();
+  auto timed_launch = [&](int kernel, bool on, auto &&fn) -> hipError_t {
+    if (!on || !timed || s % m->timing) return fn();
     hipEvent_t ev[2];
     for (int i = 0; i < 2; ++i) {
       if (m->ev_free.empty()) {
@@ -135,17 +163,35 @@ hipError_t launch(ms_model *m, const ms::KRun &r, int n_env, int n_steps, hipStr
     m->ev_pending.push_back({kernel, ev[0], ev[1]});
     return e;
   };
+  ms::KRun rh[2] = {r, r};
+  hipStream_t sh[2] = {st, m->s2};
+  for (int h = 0; h < halves; ++h) {
+    rh[h].env_begin = h * per;
+    rh[h].env_end = std::min(n_env, (h + 1) * per);
+  }
+  if (halves == 2) {
+    hipError_t e = hipEventRecord(m->ev_fork, st);
+    if (e == hipSuccess) e = hipStreamWaitEvent(m->s2, m->ev_fork, 0);
+    if (e != hipSuccess) return e;
+  }
   for (s = 0; s < n_steps; ++s) {
-    hipError_t e = timed_launch(0, [&] { return ms::launch_front(m->k, r, w, m->w_front, s, st); });
-    if (e == hipSuccess)
-      e = timed_launch(1, [&] {
-        if (nvia <= 2) return ms::launch_muscle<2>(m->k, r, w, mpt, s, st);
-        if (nvia <= 4) return ms::launch_muscle<4>(m->k, r, w, mpt, s, st);
-        if (nvia <= 6) return ms::launch_muscle<6>(m->k, r, w, mpt, s, st);
-        return ms::launch_muscle<8>(m->k, r, w, mpt, s, st);
+    hipError_t e = hipSuccess;
+    for (int h = 0; h < halves && e == hipSuccess; ++h)
+      e = timed_launch(0, h == 0, [&] { return ms::launch_front(m->k, rh[h], w, m->w_front, s, sh[h]); });
+    for (int h = 0; h < halves && e == hipSuccess; ++h)
+      e = timed_launch(1, h == 0, [&] {
+        if (nvia <= 2) return ms::launch_muscle<2>(m->k, rh[h], w, mpt, s, sh[h]);
+        if (nvia <= 4) return ms::launch_muscle<4>(m->k, rh[h], w, mpt, s, sh[h]);
+        if (nvia <= 6) return ms::launch_muscle<6>(m->k, rh[h], w, mpt, s, sh[h]);
+        return ms::launch_muscle<8>(m->k, rh[h], w, mpt, s, sh[h]);
       });
-    if (e == hipSuccess)
-      e = timed_launch(2, [&] { return ms::launch_back(m->k, r, w, m->w_back, s, st); });
+    for (int h = 0; h < halves && e == hipSuccess; ++h)
+      e = timed_launch(2, h == 0, [&] { return ms::launch_back(m->k, rh[h], w, m->w_back, s, sh[h]); });
+    if (e != hipSuccess) return e;
+  }
+  if (halves == 2) {
+    hipError_t e = hipEventRecord(m->ev_join, m->s2);
+    if (e == hipSuccess) e = hipStreamWaitEvent(st, m->ev_join, 0);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -295,6 +341,9 @@ void ms_model_destroy(ms_model *m) {
   }
   for (hipEvent_t e : m->ev_free) (void)hipEventDestroy(e);
   if (m->key_buf) (void)hipFree(m->key_buf);
+  if (m->s2) (void)hipStreamDestroy(m->s2);
+  if (m->ev_fork) (void)hipEventDestroy(m->ev_fork);
+  if (m->ev_join) (void)hipEventDestroy(m->ev_join);
   delete m;
 }
 
@@ -304,6 +353,13 @@ ms_status ms_model_set_schedule(ms_model *m, int32_t schedule) {
   if (schedule != MS_SCHED_AUTO && schedule != MS_SCHED_FUSED && schedule != MS_SCHED_SPLIT)
     return fail(MS_E_ARG, "unknown schedule");
   m->schedule = schedule;
+  return MS_OK;
+}
+
+ms_status ms_model_set_split_streams(ms_model *m, int32_t streams) {
+  g_err.clear();
+  if (!m || streams < 0 || streams > 2) return fail(MS_E_ARG, "streams must be 0, 1 or 2");
+  m->split_streams = streams;
   return MS_OK;
 }
 
@@ -349,6 +405,8 @@ ms_status ms_model_kernel_times(ms_model *m, double *ms3, int64_t *n_steps) {
 ms_status ms_model_reserve(ms_model *m, int32_t n_env) {
   g_err.clear();
   if (!m || n_env <= 0) return fail(MS_E_ARG, "NULL model or n_env <= 0");
+  if (m->split_streams != 1 && make_second_stream(m) != hipSuccess)
+    return fail(MS_E_ALLOC, "could not create the split step's second stream");
   return reserve_split(m, n_env, nullptr);
 }
 

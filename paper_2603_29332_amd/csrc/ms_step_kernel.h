@@ -1232,8 +1232,8 @@ __global__ __launch_bounds__(256) void k_geometry(KModel M, KRun Rn, int n_steps
 template <int MPT, int NVIA, bool SURR>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_muscle(KModel M, KRun Rn, KSplit W, int step) {
   extern __shared__ __align__(16) unsigned char lds_m[];
-  const int env = blockIdx.x;
-  if (env >= Rn.n_env) return;  // uniform over the workgroup
+  const int env = Rn.env_begin + blockIdx.x;
+  if (env >= (Rn.env_end ? Rn.env_end : Rn.n_env)) return;  // uniform over the workgroup
   const BlockTeam T{(int)threadIdx.x};
   const int nq = M.nq, nv = M.nv, nm = M.n_mus, nn = M.n_node;
   float *Rl = (float *)(lds_m + W.m_R);
@@ -1300,7 +1300,7 @@ template <int NVIA>
 hipError_t launch_muscle(const KModel &k, const KRun &r, const KSplit &w, int mpt, int step,
                          hipStream_t st) {
   const bool surr = r.geomY != nullptr;
-  const dim3 grid(r.n_env), block(256);
+  const dim3 grid((r.env_end ? r.env_end : r.n_env) - r.env_begin), block(256);
   const size_t lds = w.m_bytes;
 #define MS_LAUNCH_M(P)                                                                         \
   do {                                                                                         \

@@ -22,12 +22,12 @@ namespace ms {
 __global__ __launch_bounds__(1024) void k_front(KModel M, KRun Rn, KSplit W, int step) {
   extern __shared__ __align__(16) unsigned char lds_f[];
   const int wave = threadIdx.x >> 6;
-  const int env = blockIdx.x * (blockDim.x >> 6) + wave;
+  const int env = Rn.env_begin + blockIdx.x * (blockDim.x >> 6) + wave;
   const int lane = threadIdx.x & 63;
   int *LT = (int *)lds_f;  // words [0, lt_front_end) of the model's table
   for (int i = threadIdx.x; i < M.lt_front_end; i += blockDim.x) LT[i] = M.lt[i];
   __syncthreads();  // the only workgroup-wide barrier
-  if (env >= Rn.n_env) return;
+  if (env >= (Rn.env_end ? Rn.env_end : Rn.n_env)) return;
   unsigned char *lds = lds_f + (size_t)M.lt_front_end * 4 + (size_t)wave * W.f_bytes;
   const int nq = M.nq, nv = M.nv, nn = M.n_node;
   float *q = (float *)(lds + W.f_q);
@@ -80,14 +80,14 @@ __global__ __launch_bounds__(1024) void k_front(KModel M, KRun Rn, KSplit W, int
 __global__ __launch_bounds__(1024) void k_back(KModel M, KRun Rn, KSplit W, int step) {
   extern __shared__ __align__(16) unsigned char lds_b[];
   const int wave = threadIdx.x >> 6;
-  const int env = blockIdx.x * (blockDim.x >> 6) + wave;
+  const int env = Rn.env_begin + blockIdx.x * (blockDim.x >> 6) + wave;
   const int lane = threadIdx.x & 63;
   // words [lt_back_begin, lt_words) of the model's table, indexed with the
   // table's own offsets
   const int nw = M.lt_words - M.lt_back_begin;
   for (int i = threadIdx.x; i < nw; i += blockDim.x) ((int *)lds_b)[i] = M.lt[M.lt_back_begin + i];
   __syncthreads();  // the only workgroup-wide barrier
-  if (env >= Rn.n_env) return;
+  if (env >= (Rn.env_end ? Rn.env_end : Rn.n_env)) return;
   const int *LT = (const int *)lds_b - M.lt_back_begin;
   unsigned char *lds = lds_b + (size_t)nw * 4 + (size_t)wave * W.b_bytes;
   const int nq = M.nq, nv = M.nv, nm = M.n_mus;
@@ -190,7 +190,8 @@ hipError_t launch_front(const KModel &k, const KRun &r, const KSplit &w, int W, 
   const size_t lds = front_lds(k, w, W);
   hipError_t e = allow_lds((const void *)&k_front, lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_front, dim3((r.n_env + W - 1) / W), dim3(64 * W), lds, st, k, r, w, step);
+  const int n = (r.env_end ? r.env_end : r.n_env) - r.env_begin;
+  hipLaunchKernelGGL(k_front, dim3((n + W - 1) / W), dim3(64 * W), lds, st, k, r, w, step);
   return hipGetLastError();
 }
 
@@ -199,7 +200,8 @@ hipError_t launch_back(const KModel &k, const KRun &r, const KSplit &w, int W, i
   const size_t lds = back_lds(k, w, W);
   hipError_t e = allow_lds((const void *)&k_back, lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_back, dim3((r.n_env + W - 1) / W), dim3(64 * W), lds, st, k, r, w, step);
+  const int n = (r.env_end ? r.env_end : r.n_env) - r.env_begin;
+  hipLaunchKernelGGL(k_back, dim3((n + W - 1) / W), dim3(64 * W), lds, st, k, r, w, step);
   return hipGetLastError();
 }
 

@@ -78,6 +78,10 @@ struct KRun {
   int rec_every;
   float *r_act, *r_F, *r_lm, *r_vm, *r_pow, *r_xpos, *r_xmat;
   unsigned *n_applied;
+  // the split step's kernels cover envs [env_begin, env_end) of the batch
+  // (env_end 0: up to n_env); every array stays indexed by the env's place
+  // in the whole batch
+  int env_begin, env_end;
 };
 
 // This env's slices of the muscle observables of one recorded step (NULL:
@@ -168,6 +172,11 @@ struct ms_model {
   std::vector<void *> ws_owned;
   // envs per workgroup of its kernels, chosen for w_n_env envs
   int w_front = 0, w_back = 0, w_n_env = 0;
+  // the split step's second stream and its fork/join events (two halves of
+  // the batch stepped concurrently)
+  int split_streams = 0;  // 0 automatic, 1 or 2 (ms_model_set_split_streams)
+  hipStream_t s2 = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   void *key_buf = nullptr;  // device copy of the key nodes
   // per-kernel timing of the split schedule (ms_model_set_kernel_timing):
   // event pairs recorded around each kernel, (kernel, start, end)

@@ -39,7 +39,7 @@ EXPORTED = ("ms_model_create", "ms_model_destroy", "ms_model_info_get",
             "ms_rollout_record", "ms_surrogate_train", "ms_surrogate_save", "ms_surrogate_load",
             "ms_controller_create", "ms_controller_destroy", "ms_controller_dims",
             "ms_controller_params", "ms_controller_reserve", "ms_controller_step",
-            "ms_controller_last_error")
+            "ms_controller_last_error", "ms_model_set_split_streams")
 
 _fptr = C.POINTER(C.c_float)
 _iptr = C.POINTER(C.c_int32)
@@ -126,6 +126,7 @@ def lib():
     L.ms_model_set_schedule.argtypes = [vp, C.c_int32]
     L.ms_model_get_schedule.argtypes = [vp, _iptr]
     L.ms_model_reserve.argtypes = [vp, C.c_int32]
+    L.ms_model_set_split_streams.argtypes = [vp, C.c_int32]
     L.ms_model_set_kernel_timing.argtypes = [vp, C.c_int32]
     L.ms_model_kernel_times.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
     L.ms_model_set_key_nodes.argtypes = [vp, C.c_int32, _iptr]
@@ -289,6 +290,11 @@ class Model:
         """SCHED_AUTO, SCHED_FUSED or SCHED_SPLIT (same results, different
         kernels)."""
         _check(lib().ms_model_set_schedule(self.h, int(schedule)))
+
+    def set_split_streams(self, streams):
+        """Split schedule: 2 steps two halves of the batch on two streams,
+        1 on the caller's stream only, 0 automatic."""
+        _check(lib().ms_model_set_split_streams(self.h, int(streams)))
 
     def schedule(self):
         """The schedule steps run with now (SCHED_FUSED or SCHED_SPLIT)."""

@@ -262,3 +262,38 @@ def test_split_workspace_grows_and_is_reserved_before_capture(built):
         torch.cuda.synchronize()
         for x, y in zip((tq, tqd, tact, st), ref):
             assert torch.equal(x, y)
+
+
+@pytest.mark.parametrize("E", [1, 93, 4097])
+def test_two_stream_halves_equal_one_stream(built, E):
+    """The split step over two concurrent halves of the batch (forced for
+    every batch size, and the automatic choice at 4097 envs) gives the bits
+    of the one-stream split step and of the fused step, also when captured
+    into a graph after ms_model_reserve and replayed."""
+    m, init, fused, _ = built["human"]
+    one, two, auto = ms.Model(m), ms.Model(m), ms.Model(m)
+    one.set_split_streams(1)
+    two.set_split_streams(2)
+    q, qd, act = _state(m, init, E, 14)
+    x0 = np.random.default_rng(15).normal(0, 0.1, (E, m["n_mus"])).astype(np.float32)
+    ref = _run(one, m, q, qd, act, 4, True, ms.EXC_AR1, x0=x0)
+    _same(ref, _run(two, m, q, qd, act, 4, True, ms.EXC_AR1, x0=x0))
+    _same(ref, _run(auto, m, q, qd, act, 4, True, ms.EXC_AR1, x0=x0))
+    if E <= 93:
+        _same(ref, _run(fused, m, q, qd, act, 4, True, ms.EXC_AR1, x0=x0))
+    gm = ms.Model(m)
+    gm.set_split_streams(2)
+    gm.reserve(E)
+    tq, tqd, tact = _t(q), _t(qd), _t(act)
+    st = torch.zeros(E, dtype=torch.int32, device=DEV)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        gm.rollout(tq, tqd, tact, st, 2, DT, True, kind=ms.EXC_IID, seed=1)
+    want = [_t(q), _t(qd), _t(act), torch.zeros(E, dtype=torch.int32, device=DEV)]
+    for _ in range(3):
+        g.replay()
+        one.rollout(*want, 2, DT, True, kind=ms.EXC_IID, seed=1)
+        torch.cuda.synchronize()
+        for x, y in zip((tq, tqd, tact, st), want):
+            assert torch.equal(x, y)

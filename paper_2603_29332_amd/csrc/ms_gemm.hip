@@ -1,22 +1,25 @@
 // ms_gemm.hip -- bfloat16 GEMM on gfx950 matrix cores (v_mfma_f32_16x16x32_bf16).
 //
-// A workgroup of 4 wavefronts computes a 128 x 128 tile of C; each
-// wavefront owns a 64 x 64 quadrant as a 4 x 4 grid of 16 x 16 MFMA tiles
-// with float32 accumulators. Operand tiles of 32 along K are staged through
-// LDS as [row][k] (k contiguous, rows padded to 40 elements), so every lane
-// reads its 8 consecutive k values of a row with one 128-bit LDS load;
-// operands stored K-major in memory are transposed while being staged. The
-// next K tile is fetched into registers while the current one is multiplied.
+// Two kernels. k_gemm_nt serves the network forward shape (activations
+// times weights stored [out][in]): operand tiles go from memory straight
+// into LDS, double-buffered, in XOR-swizzled unpadded rows, 16 x 16 MFMA
+// tiles per wavefront, a tile size picked per shape. k_gemm serves every
+// layout (the backward products): a workgroup of 4 wavefronts computes a
+// 128 x 128 tile, each wavefront a 64 x 64 quadrant; operand tiles of 32
+// along K are staged through registers into LDS as [row][k] (rows padded to
+// 40 elements; K-major operands transposed on the way), the next K tile
+// fetched while the current one is multiplied. Both fuse the epilogue
+// (GemmEpi); float32 outputs of the forward kernel are stored
+// non-temporally.
 #include "ms_gemm.h"
 
 #include <type_traits>
 
 // tile configurations of the forward-shape kernel: BM, BN, wavefronts along
-// M and N, register prefetch depth (large, medium and small tiles)
+// M and N (large and small tiles)
 #ifndef MS_NT0
-#define MS_NT0 128, 128, 4, 4, 1
-#define MS_NT1 64, 128, 2, 4, 1
-#define MS_NT2 64, 64, 2, 4, 1
+#define MS_NT0 128, 128, 4, 4
+#define MS_NT1 64, 64, 2, 4
 #endif
 
 namespace ms {
@@ -154,118 +157,48 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const bf16 *A
       }
 }
 
-// The forward shape, C = A B^T with A [M][K] and B [N][K] both row-major
-// (activations times a weight matrix stored [out][in]): a BM x BN tile per
-// workgroup of WM x WN wavefronts (each BM/WM x BN/WN as 16 x 16 MFMA tiles),
-// K in steps of 64 through two LDS buffers, one barrier per step. Global
-// loads run DEPTH steps ahead in registers (register sets alternate with the
-// step's parity; the K loop is unrolled by two so every set index is a
-// compile-time constant).
-constexpr int NK = 64, NLK = NK + 8;
+constexpr int NK = 64;
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+// buffer resource word 3 for raw (untyped) loads on gfx9-family chips, and
+// an offset beyond any range (the load then returns zeros)
+constexpr int kBufWord3 = 0x00020000;
+constexpr int kBufPastEnd = 0x7FFFFFF0;
+// s_waitcnt immediate: vector memory count 0, the other counters unconstrained
+constexpr int kWaitVm0 = (7 << 4) | (15 << 8);
 
-template <int BMt, int BNt, int WM, int WN, int DEPTH>
-__global__ __launch_bounds__(64 * WM * WN) void k_gemm_nt(int M, int N, int K, const bf16 *A,
-                                                         int lda, const bf16 *B, int ldb,
-                                                         GemmEpi epi) {
-  constexpr int NT = 64 * WM * WN;
-  constexpr int TM = BMt / WM / 16, TN = BNt / WN / 16;   // MFMA tiles per wavefront
-  constexpr int CA = BMt * 8 / NT, CB = BNt * 8 / NT;     // 16-byte chunks per thread and step
-  static_assert(CA >= 1 && CB >= 1 && TM >= 1 && TN >= 1, "tile too small for the workgroup");
-  __shared__ __align__(16) unsigned short As[2][BMt * NLK];
-  __shared__ __align__(16) unsigned short Bs[2][BNt * NLK];
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int wm = w / WN, wn = w % WN;
-  const int m0 = blockIdx.y * BMt, n0 = blockIdx.x * BNt;
-  const unsigned short *ga = reinterpret_cast<const unsigned short *>(A);
-  const unsigned short *gb = reinterpret_cast<const unsigned short *>(B);
-  uint4 ra[DEPTH][CA], rb[DEPTH][CB];
-  auto fetch = [&](uint4 (&xa)[CA], uint4 (&xb)[CB], int k0) {
-#pragma unroll
-    for (int it = 0; it < CA; ++it) {
-      const int c = tid + NT * it, row = c >> 3, kc = (c & 7) * 8;
-      const int gm = m0 + row, gk = k0 + kc;
-      xa[it] = make_uint4(0, 0, 0, 0);
-      if (gm < M && gk < K) xa[it] = *reinterpret_cast<const uint4 *>(ga + (size_t)gm * lda + gk);
-    }
-#pragma unroll
-    for (int it = 0; it < CB; ++it) {
-      const int c = tid + NT * it, row = c >> 3, kc = (c & 7) * 8;
-      const int gn = n0 + row, gk = k0 + kc;
-      xb[it] = make_uint4(0, 0, 0, 0);
-      if (gn < N && gk < K) xb[it] = *reinterpret_cast<const uint4 *>(gb + (size_t)gn * ldb + gk);
-    }
+// buffer resource over `bytes` bytes from p (the same in every lane: made
+// from scalar copies, so the loads take it from scalar registers)
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t tile_rsrc(const bf16 *p, int bytes) {
+  const unsigned long long a = reinterpret_cast<unsigned long long>(p);
+  const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)a);
+  const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(a >> 32));
+  void *u = reinterpret_cast<void *>(((unsigned long long)hi << 32) | lo);
+  return __builtin_amdgcn_make_buffer_rsrc(u, 0, __builtin_amdgcn_readfirstlane(bytes), kBufWord3);
+}
+
+// Epilogue of a wavefront's TM x TN grid of 16 x 16 MFMA tiles whose first
+// row and column are mw, nw (see GemmEpi). float32 outputs are stored
+// non-temporally when NTS: they stream past the L2, which keeps the operand
+// tiles the workgroups still read.
+template <int TM, int TN, bool NTS = true>
+__device__ __forceinline__ void store_tile(const f32x4 (&acc)[TM][TN], int mw, int nw, int lane,
+                                           int M, int N, const GemmEpi &epi) {
+  auto put = [](float *p, float v) {
+    if (NTS)
+      __builtin_nontemporal_store(v, p);
+    else
+      *p = v;
   };
-  auto stash = [&](const uint4 (&xa)[CA], const uint4 (&xb)[CB], int buf) {
+  // the per-column vectors are loaded before the first store: the outputs
+  // may alias them as far as the compiler knows, so a load placed after a
+  // store would wait a full memory latency per element
+  float bias[TN], scl[TN], sft[TN];
 #pragma unroll
-    for (int it = 0; it < CA; ++it) {
-      const int c = tid + NT * it, row = c >> 3, kc = (c & 7) * 8;
-      *reinterpret_cast<uint4 *>(&As[buf][row * NLK + kc]) = xa[it];
-    }
-#pragma unroll
-    for (int it = 0; it < CB; ++it) {
-      const int c = tid + NT * it, row = c >> 3, kc = (c & 7) * 8;
-      *reinterpret_cast<uint4 *>(&Bs[buf][row * NLK + kc]) = xb[it];
-    }
-  };
-  f32x4 acc[TM][TN];
-#pragma unroll
-  for (int i = 0; i < TM; ++i)
-#pragma unroll
-    for (int j = 0; j < TN; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-  const int kq = (lane >> 4) * 8, r = lane & 15;
-  auto compute = [&](int buf) {
-#pragma unroll
-    for (int s = 0; s < NK / 32; ++s) {
-      bf16x8 a[TM], b[TN];
-#pragma unroll
-      for (int i = 0; i < TM; ++i)
-        a[i] = *reinterpret_cast<const bf16x8 *>(
-            &As[buf][(wm * (BMt / WM) + i * 16 + r) * NLK + s * 32 + kq]);
-#pragma unroll
-      for (int j = 0; j < TN; ++j)
-        b[j] = *reinterpret_cast<const bf16x8 *>(
-            &Bs[buf][(wn * (BNt / WN) + j * 16 + r) * NLK + s * 32 + kq]);
-#pragma unroll
-      for (int i = 0; i < TM; ++i)
-#pragma unroll
-        for (int j = 0; j < TN; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
-    }
-  };
-  const int nk = (K + NK - 1) / NK;
-  // step j's tile waits in register set j % DEPTH, then in LDS buffer j % 2
-  fetch(ra[0], rb[0], 0);
-  stash(ra[0], rb[0], 0);
-  if (DEPTH == 2 && nk > 1) fetch(ra[DEPTH - 1], rb[DEPTH - 1], NK);
-  __syncthreads();
-  // one step kt of parity P: the load of step kt + DEPTH into set
-  // (kt + DEPTH) % DEPTH, the MFMAs on buffer P, then step kt + 1's tile from
-  // its register set into buffer 1 - P
-  auto step = [&](int kt, auto parity) {
-    constexpr int P = decltype(parity)::value;
-    constexpr int SL = (P + DEPTH) % DEPTH;        // set receiving step kt + DEPTH
-    constexpr int SN = (P + 1) % DEPTH;            // set holding step kt + 1
-    if (kt + DEPTH < nk) fetch(ra[SL], rb[SL], (kt + DEPTH) * NK);
-    compute(P);
-    if (kt + 1 < nk) stash(ra[SN], rb[SN], 1 - P);
-    __syncthreads();
-  };
-  using P0 = std::integral_constant<int, 0>;
-  using P1 = std::integral_constant<int, 1>;
-  if (DEPTH == 1) {
-    // one register set: a plain loop over the steps
-    for (int kt = 0; kt < nk; ++kt) {
-      const int cur = kt & 1;
-      if (kt + 1 < nk) fetch(ra[0], rb[0], (kt + 1) * NK);
-      compute(cur);
-      if (kt + 1 < nk) stash(ra[0], rb[0], cur ^ 1);
-      __syncthreads();
-    }
-  } else {
-    for (int kt = 0; kt < nk; kt += 2) {
-      step(kt, P0{});
-      if (kt + 1 < nk) step(kt + 1, P1{});
-    }
+  for (int j = 0; j < TN; ++j) {
+    const int n = min(nw + j * 16 + (lane & 15), N - 1);
+    bias[j] = epi.bias ? epi.bias[n] : 0.f;
+    scl[j] = epi.scale ? epi.scale[n] : 1.f;
+    sft[j] = epi.scale ? epi.shift[n] : 0.f;
   }
 #pragma unroll
   for (int i = 0; i < TM; ++i)
@@ -273,24 +206,135 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm_nt(int M, int N, int K, c
     for (int j = 0; j < TN; ++j)
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        const int m = m0 + wm * (BMt / WM) + i * 16 + (lane >> 4) * 4 + e;
-        const int n = n0 + wn * (BNt / WN) + j * 16 + (lane & 15);
+        const int m = mw + i * 16 + (lane >> 4) * 4 + e;
+        const int n = nw + j * 16 + (lane & 15);
         if (m >= M || n >= N) continue;
         const size_t o = (size_t)m * epi.ldc + n;
         float v = acc[i][j][e] * epi.alpha;
-        if (epi.bias) v += epi.bias[n];
+        if (epi.bias) v += bias[j];
         if (epi.addc) v += epi.addc[o];
         if (epi.dact) v *= silu_slope(epi.dact[o]);
-        if (epi.z_out) epi.z_out[o] = v;
+        if (epi.z_out) put(&epi.z_out[o], v);
         if (epi.act == 1) v = silu(v);
         if (epi.act == 2) v = 1.0f / (1.0f + expf(-v));
-        if (epi.scale) v = v * epi.scale[n] + epi.shift[n];
+        if (epi.scale) v = v * scl[j] + sft[j];
         if (epi.c2 && n >= epi.split)
-          epi.c2[(size_t)m * epi.ldc2 + (n - epi.split)] = v;
+          put(&epi.c2[(size_t)m * epi.ldc2 + (n - epi.split)], v);
         else if (epi.c_f32)
-          epi.c_f32[o] = v;
+          put(&epi.c_f32[o], v);
         if (epi.c_bf16) epi.c_bf16[o] = __float2bfloat16(v);
       }
+}
+
+// The forward shape, C = A B^T with A [M][K] and B [N][K] both row-major
+// (activations times a weight matrix stored [out][in]): a BM x BN tile per
+// workgroup of WM x WN wavefronts (each BM/WM x BN/WN as 16 x 16 MFMA tiles),
+// K in steps of 64. The operand tiles are copied from memory straight into
+// LDS (buffer loads with the LDS bit, no staging registers), double-buffered,
+// one barrier per step. Tiles are unpadded 128-byte
+// rows; chunk q (8 k values) of row r sits in slot q ^ g(r),
+// g(r) = (r & 7) ^ ((r >> 3) & 1), so the 16 rows an MFMA operand read
+// touches fall in distinct bank groups. Out-of-range rows and K chunks read
+// as zeros.
+template <int BMt, int BNt, int WM, int WN>
+__global__ __launch_bounds__(64 * WM * WN) void k_gemm_nt(int M, int N, int K, const bf16 *A,
+                                                             int lda, const bf16 *B, int ldb,
+                                                             GemmEpi epi) {
+  constexpr int NT = 64 * WM * WN;
+  constexpr int TM = BMt / WM / 16, TN = BNt / WN / 16;
+  constexpr int CA = BMt * 8 / NT, CB = BNt * 8 / NT;     // chunks per thread and step
+  static_assert(CA >= 1 && CB >= 1 && TM >= 1 && TN >= 1, "bad configuration");
+  __shared__ __align__(16) unsigned short As[2][BMt * NK];
+  __shared__ __align__(16) unsigned short Bs[2][BNt * NK];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int wm = w / WN, wn = w % WN;
+  // workgroups are handed to the 8 XCDs round-robin by linear id; renumber
+  // them so that each XCD takes one contiguous run of tiles, row-major over
+  // N (consecutive tiles share their A rows, and B stays in that XCD's L2)
+  int m0, n0;
+  {
+    const int nt = gridDim.x * gridDim.y, id = blockIdx.y * gridDim.x + blockIdx.x;
+    const int q = nt / 8, rm = nt % 8, x = id % 8, slot = id / 8;
+    const int t = (x < rm ? x * (q + 1) : rm * (q + 1) + (x - rm) * q) + slot;
+    m0 = (t / gridDim.x) * BMt;
+    n0 = (t % gridDim.x) * BNt;
+  }
+  const __amdgpu_buffer_rsrc_t rsa =
+      tile_rsrc(A + (size_t)m0 * lda, 2 * lda * max(0, min(BMt, M - m0)));
+  const __amdgpu_buffer_rsrc_t rsb =
+      tile_rsrc(B + (size_t)n0 * ldb, 2 * ldb * max(0, min(BNt, N - n0)));
+  auto swz = [](int r) { return (r & 7) ^ ((r >> 3) & 1); };
+  // step kt's tiles into stage buffer st: chunk c = tid + NT it is row
+  // c >> 3, slot c & 7 (the wavefront's 64 chunks are 1 KB of LDS)
+  auto copy = [&](int st, int kt) {
+    const int k0 = kt * NK;
+#pragma unroll
+    for (int it = 0; it < CA; ++it) {
+      const int c = tid + NT * it, row = c >> 3, gk = k0 + (((c & 7) ^ swz(row)) * 8);
+      const int off = gk < K ? 2 * (row * lda + gk) : kBufPastEnd;
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(
+          rsa, (__attribute__((address_space(3))) void *)&As[st][(c - lane) * 8], 16, off, 0, 0, 0);
+    }
+#pragma unroll
+    for (int it = 0; it < CB; ++it) {
+      const int c = tid + NT * it, row = c >> 3, gk = k0 + (((c & 7) ^ swz(row)) * 8);
+      const int off = gk < K ? 2 * (row * ldb + gk) : kBufPastEnd;
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(
+          rsb, (__attribute__((address_space(3))) void *)&Bs[st][(c - lane) * 8], 16, off, 0, 0, 0);
+    }
+  };
+  f32x4 acc[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const int r16 = lane & 15, kq = lane >> 4;
+  // a step's operands, both 32-wide K halves, read from LDS at once
+  bf16x8 a[NK / 32][TM], b[NK / 32][TN];
+  auto read = [&](int st) {
+#pragma unroll
+    for (int s = 0; s < NK / 32; ++s) {
+#pragma unroll
+      for (int i = 0; i < TM; ++i) {
+        const int row = wm * (BMt / WM) + i * 16 + r16;
+        a[s][i] = *reinterpret_cast<const bf16x8 *>(&As[st][row * NK + (((s * 4 + kq) ^ swz(row)) * 8)]);
+      }
+#pragma unroll
+      for (int j = 0; j < TN; ++j) {
+        const int row = wn * (BNt / WN) + j * 16 + r16;
+        b[s][j] = *reinterpret_cast<const bf16x8 *>(&Bs[st][row * NK + (((s * 4 + kq) ^ swz(row)) * 8)]);
+      }
+    }
+  };
+  auto mfma = [&] {
+#pragma unroll
+    for (int s = 0; s < NK / 32; ++s)
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[s][i], b[s][j], acc[i][j], 0, 0, 0);
+  };
+  const int nk = (K + NK - 1) / NK;
+  // Two stage buffers: step kt's operands are read into registers, then the
+  // copy of step kt + 1 into the other buffer is issued, then the MFMAs run
+  // while it travels. (An LDS read waits for every copy still in flight, so
+  // deeper pipelines would gain nothing.)
+  copy(0, 0);
+  int st = 0;
+  for (int kt = 0; kt < nk; ++kt) {
+    __builtin_amdgcn_s_waitcnt(kWaitVm0);
+    __syncthreads();   // step kt is in LDS for every wavefront, and every
+                       // wavefront has read step kt - 1's buffer
+    read(st);
+    __builtin_amdgcn_sched_barrier(0);
+    copy(st ^ 1, kt + 1);
+    __builtin_amdgcn_sched_barrier(0);
+    mfma();
+    st ^= 1;
+  }
+  __builtin_amdgcn_s_waitcnt(0);     // no copy may land after the workgroup ends
+  store_tile<TM, TN, true>(acc, m0 + wm * (BMt / WM), n0 + wn * (BNt / WN), lane, M, N, epi);
 }
 
 // C[m][n] = sum over z of work[z][m][n], slice order
@@ -337,19 +381,23 @@ int cu_count() {
 }
 }  // namespace
 
-int gemm_nt_tile(int M, int N) {
+// Tile of the forward-shape kernel (measured on MI355X): 128 x 128 with 16
+// wavefronts when it still gives every CU two workgroups and the epilogue
+// is plain (bias, activation, one output); otherwise 64 x 64 with 8
+// wavefronts, which is faster for narrow outputs and also for the
+// de-standardising, column-split epilogue (the larger tile's 16-wavefront
+// epilogue then doubles its time).
+int gemm_nt_tile(int M, int N, const GemmEpi &epi) {
   const int cus = cu_count();
-  auto tiles = [&](int bm, int bn) { return (long long)((M + bm - 1) / bm) * ((N + bn - 1) / bn); };
-  // the largest tile that still gives every CU two workgroups
-  if (tiles(128, 128) >= 2 * cus) return 0;
-  if (tiles(64, 128) >= 2 * cus) return 1;
-  return 2;
+  const long long big = (long long)((M + 127) / 128) * ((N + 127) / 128);
+  if (big >= 2 * cus && !epi.scale && !epi.c2) return 0;
+  return 1;
 }
 
-template <int BM, int BN, int WM, int WN, int D>
+template <int BM, int BN, int WM, int WN>
 void launch_nt(int M, int N, int K, const bf16 *A, int lda, const bf16 *B, int ldb,
                const GemmEpi &epi, hipStream_t st) {
-  hipLaunchKernelGGL((k_gemm_nt<BM, BN, WM, WN, D>), dim3((N + BN - 1) / BN, (M + BM - 1) / BM),
+  hipLaunchKernelGGL((k_gemm_nt<BM, BN, WM, WN>), dim3((N + BN - 1) / BN, (M + BM - 1) / BM),
                      dim3(64 * WM * WN), 0, st, M, N, K, A, lda, B, ldb, epi);
 }
 
@@ -358,13 +406,12 @@ hipError_t gemm_bf16(bool ta, bool tb, int M, int N, int K, const bf16 *A, int l
   if (M <= 0 || N <= 0 || K <= 0) return hipSuccess;
   if (K % 8 || lda % 8 || ldb % 8 || (ta && M % 8) || (!tb && N % 8)) return hipErrorInvalidValue;
   if (!ta && tb) {
-    const int t = gemm_nt_tile(M, N);
-    if (t == 0)
+    // byte offsets within a tile's rows are 32-bit
+    if (lda > (1 << 20) || ldb > (1 << 20)) return hipErrorInvalidValue;
+    if (gemm_nt_tile(M, N, epi) == 0)
       launch_nt<MS_NT0>(M, N, K, A, lda, B, ldb, epi, st);
-    else if (t == 1)
-      launch_nt<MS_NT1>(M, N, K, A, lda, B, ldb, epi, st);
     else
-      launch_nt<MS_NT2>(M, N, K, A, lda, B, ldb, epi, st);
+      launch_nt<MS_NT1>(M, N, K, A, lda, B, ldb, epi, st);
     return hipGetLastError();
   }
   return gemm_launch(ta, tb, M, N, K, A, lda, B, ldb, epi, 1, K, 0, st);

@@ -18,6 +18,7 @@ throughput on the host cores.
 from __future__ import annotations
 
 import argparse
+import faulthandler
 import json
 import os
 import sys
@@ -71,6 +72,7 @@ def parse():
 
 
 def main():
+    faulthandler.enable()       # a crash prints the Python stack of the leg it hit
     a = parse()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the environments shard over GPUs with no "
@@ -591,7 +593,59 @@ def surrogate_leg(a, m, gm, dt, E, q0, qd0, act0, ar1, dev, rad=None):
             rad[("sweep", tol)] = rad_run(m, gm, dt, dev, sg=sg, tol=tol)
         sweep.append(row)
     out["tolerance_sweep"] = sweep
+    out["ceiling"] = surrogate_ceiling(m, gm, sg, dt, E, init, ar1, dev, fwd_ms)
     return out, sg
+
+
+def surrogate_ceiling(m, gm, sg, dt, E, init, ar1, dev, fwd_ms, T=10):
+    """What the surrogate step can buy, kernel by kernel: T physics steps
+    from the initial states with every split-schedule kernel timed (one
+    stream, so each kernel has the GPU to itself), for the exact step, the
+    surrogate step at its residual test and the surrogate step with the
+    test disabled (tolerance 1000 m: every env inside the trained pose box
+    takes the prediction). The network forward is timed alone."""
+    import torch
+
+    from paper_2603_29332_amd import ms
+    gm.set_split_streams(1)
+    rows = {}
+    for name, tol in (("exact", None), ("surrogate_tol_1e-4", 1e-4),
+                      ("surrogate_no_residual_test", 1e3)):
+        q, qd, act = (v.clone() for v in init)
+        st = torch.zeros(E, dtype=torch.int32, device=dev)
+        fb = torch.zeros(E, dtype=torch.int32, device=dev)
+        x = torch.zeros(E, m["n_mus"], device=dev)
+        kw = dict(kind=ms.EXC_AR1, seed=12, step0=0, x=x, ar1=ar1)
+        torch.cuda.synchronize()
+        gm.kernel_times()
+        gm.set_kernel_timing(1)
+        if tol is None:
+            gm.rollout(q, qd, act, st, T, dt, True, **kw)
+        else:
+            gm.rollout_surrogate(sg, q, qd, act, st, T, dt, True, tol=tol, fb_count=fb, **kw)
+        torch.cuda.synchronize()
+        tk, nk = gm.kernel_times()
+        gm.set_kernel_timing(0)
+        us = {k: 1e3 * t / nk for k, t in zip(KERNELS, tk)}
+        row = {f"{k}_us": v for k, v in us.items()}
+        row["kernels_us"] = sum(us.values())
+        if tol is not None:
+            row["network_forward_us"] = fwd_ms * 1e3
+            row["step_us"] = row["kernels_us"] + fwd_ms * 1e3
+            row["fallback_rate"] = float(fb.sum().item()) / (E * T)
+        else:
+            row["step_us"] = row["kernels_us"]
+        rows[name] = row
+    gm.set_split_streams(0)
+    ex, nf = rows["exact"], rows["surrogate_no_residual_test"]
+    rows["note"] = ("per-step kernel times at 4096 envs, one stream; the surrogate step adds the "
+                    "network forward on all envs; with no residual test the muscle kernel reads the "
+                    "predicted lengths and moment arms and still runs the 32-muscle sentinel "
+                    "geometry; the surrogate step pays only if muscle kernel + forward < the exact "
+                    "muscle kernel")
+    rows["muscle_kernel_saving_us"] = ex["k_muscle_us"] - nf["k_muscle_us"]
+    rows["break_even_forward_us"] = ex["k_muscle_us"] - nf["k_muscle_us"]
+    return rows
 
 
 def heldout_errors(gm, s, n=16384, seed=43, chunk=8192):

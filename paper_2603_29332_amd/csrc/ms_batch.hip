@@ -1,8 +1,10 @@
 // ms_batch.hip -- uneven batches: environments of several models stepped
 // together.
 //
-// Each model keeps its own fused step kernel (its own tables, LDS block and
-// register budget). The kernels are issued either concurrently, each on an
+// Each model keeps its own step kernels (its own tables, LDS block and
+// register budget), all on the stream the batch gives the model (a split
+// step's second stream is not used here: the batch's own streams provide
+// the concurrency). The kernels are issued either concurrently, each on an
 // internal stream of its own forked from the caller's stream and joined
 // back, so the GPU runs the models' envs side by side, or serially on the
 // caller's stream (a model whose envs fill the GPU runs no slower alone, and
@@ -79,7 +81,8 @@ ms_status issue(ms_batch *b, const ms_batch_state *s, const ms_excitation *exc, 
   if (b->issue == MS_ISSUE_SERIAL) {
     for (int i : order(b)) {
       ms_status r = rollout_impl(b->models[i], b->n_env[i], s[i].q, s[i].qd, s[i].act,
-                                 s[i].status, &exc[i], n_steps, opts, b->wpg[i], st);
+                                 s[i].status, &exc[i], n_steps, opts, b->wpg[i], st, nullptr,
+                                 true);
       if (r != MS_OK)
         return bfail(r, std::string("model ") + std::to_string(i) + ": " + ms_last_error());
     }
@@ -91,7 +94,7 @@ ms_status issue(ms_batch *b, const ms_batch_state *s, const ms_excitation *exc, 
     r = bhip(hipStreamWaitEvent(b->streams[i], b->fork, 0), "stream wait");
     if (r != MS_OK) return r;
     r = rollout_impl(b->models[i], b->n_env[i], s[i].q, s[i].qd, s[i].act, s[i].status, &exc[i],
-                     n_steps, opts, b->wpg[i], b->streams[i]);
+                     n_steps, opts, b->wpg[i], b->streams[i], nullptr, true);
     if (r != MS_OK) return bfail(r, std::string("model ") + std::to_string(i) + ": " + ms_last_error());
     r = bhip(hipEventRecord(b->done[i], b->streams[i]), "event record");
     if (r != MS_OK) return r;
@@ -287,7 +290,7 @@ ms_status ms_batch_autotune(ms_batch *b, const ms_batch_state *states, const ms_
         if (r == MS_OK)
           r = timed([&] {
             return rollout_impl(b->models[i], b->n_env[i], sc[i].q, sc[i].qd, sc[i].act,
-                                sc[i].status, &ec[i], n_probe, opts, w, st);
+                                sc[i].status, &ec[i], n_probe, opts, w, st, nullptr, true);
           }, &t_ms);
         if (r == MS_OK && t_ms < best) {
           best = t_ms;

@@ -119,7 +119,7 @@ hipError_t launch(ms_model *m, const ms::KRun &r, int n_env, int n_steps, hipStr
   const ms::KSplit &w = m->ks;
   // two halves of the batch on two streams (the caller's and the model's
   // own), so that one half's kernels overlap the other's
-  int halves = m->split_streams == 1 ? 1
+  int halves = r.one_stream || m->split_streams == 1 ? 1
                : m->split_streams == 2 ? (n_env >= 2 ? 2 : 1)
                                        : (n_env >= kTwoStreamEnvs ? 2 : 1);
   if (halves == 2 && !m->s2) {
@@ -510,7 +510,7 @@ ms_status ms_model_set_key_nodes(ms_model *m, int32_t n_key, const int32_t *node
 ms_status rollout_impl(ms_model *m, int32_t n_env, float *q, float *qd, float *act,
                        uint32_t *status, const ms_excitation *exc, int32_t n_steps,
                        const ms_step_opts *opts, int env_per_wg, hipStream_t st,
-                       const ms_record *rec) {
+                       const ms_record *rec, bool one_stream) {
   g_err.clear();
   ms_status s = common_checks(m, n_env, q, qd, act, opts);
   if (s != MS_OK) return s;
@@ -523,6 +523,7 @@ ms_status rollout_impl(ms_model *m, int32_t n_env, float *q, float *qd, float *a
   r.u = exc->u; r.seed = exc->seed; r.step0 = exc->step0; r.xar = exc->x;
   r.rho = exc->rho; r.s = exc->s; r.mean = exc->mean;
   r.env_per_wg = env_per_wg;
+  r.one_stream = one_stream;
   switch (exc->kind) {
     case MS_EXC_ARRAY:
       if (!exc->u && m->t.n_mus > 0) return fail(MS_E_ARG, "exc->u is NULL");

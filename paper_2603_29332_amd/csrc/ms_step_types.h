@@ -82,6 +82,9 @@ struct KRun {
   // (env_end 0: up to n_env); every array stays indexed by the env's place
   // in the whole batch
   int env_begin, env_end;
+  // split step: keep every kernel on the launch stream (no half-batch on
+  // the model's second stream); set for launches an ms_batch drives
+  int one_stream;
 };
 
 // This env's slices of the muscle observables of one recorded step (NULL:
@@ -208,9 +211,10 @@ hipError_t launch(ms_model *m, const ms::KRun &r, int n_env, int n_steps, hipStr
 ms_status run_steps(ms_model *m, const ms::KRun &r, int n_env, int n_steps, hipStream_t st);
 
 // ms_rollout with a chosen number of envs per workgroup (1, 2 or 4; 0 picks
-// the count that keeps the most envs resident per CU); errors
-// as ms_rollout (message in ms_last_error).
+// the count that keeps the most envs resident per CU) and, with one_stream,
+// every kernel of the split step on st; errors as ms_rollout (message in
+// ms_last_error).
 ms_status rollout_impl(ms_model *m, int32_t n_env, float *q, float *qd, float *act,
                        uint32_t *status, const ms_excitation *exc, int32_t n_steps,
                        const ms_step_opts *opts, int env_per_wg, hipStream_t st,
-                       const ms_record *rec = nullptr);
+                       const ms_record *rec = nullptr, bool one_stream = false);

@@ -34,13 +34,13 @@ PHYS_PER_STEP = 100
 # MI355X: 256 CUs x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz, one FP32 or
 # FP64 vector FMA per lane and cycle (packed FP32 would double FP32 only).
 PEAK_VALU_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
-# HBM bytes per launch of each split-schedule kernel on this workload (4096
-# envs), from rocprofv3 FETCH_SIZE and WRITE_SIZE scaled by a plain copy of
-# known size (profiles/k_split_human80_4096_traffic.md), valid for the
-# kernel sources (ms_step_kernel.h, ms_step_split.hip) with this SHA-256
-# prefix only (reported as null otherwise).
-TRAFFIC_BYTES_PER_LAUNCH = {"k_front": 74.4e6, "k_muscle": 123.3e6, "k_back": 85.1e6}
-TRAFFIC_KERNEL_SHA = "3f444630a5551091"
+# HBM bytes per launch of each split-schedule kernel on this workload (one
+# half-batch, 2048 envs), from rocprofv3 FETCH_SIZE and WRITE_SIZE scaled by
+# a plain copy of known size (profiles/k_split_human80_4096_traffic.md),
+# valid for the kernel sources (ms_step_kernel.h, ms_step_split.hip) with
+# this SHA-256 prefix only (reported as null otherwise).
+TRAFFIC_BYTES_PER_LAUNCH = {"k_front": 37.34e6, "k_muscle": 64.61e6, "k_back": 42.65e6}
+TRAFFIC_KERNEL_SHA = "e74edd10148c75e1"
 TIMING_EVERY = 10
 KERNELS = ("k_front", "k_muscle", "k_back")
 

@@ -733,17 +733,21 @@ __device__ __forceinline__ void stage_muscles(const KModel &M, const KRun &Rn, c
       status |= MS_ST_FALLBACK;
       if (Rn.fb_count && T.t == 0) Rn.fb_count[env] += 1u;
     } else {
+      // the predictions are read in the caller's muscle order (contiguous)
+      // and placed at each muscle's internal slot
+      for (int x = T.t; x < nm; x += T.n) mF[M.mus_int[x]] = Y[x];
+      for (int i = T.t; i < 3 * nm; i += T.n) {
+        const int x = i / 3, sl = i - 3 * x, m = M.mus_int[x];
+        mr[3 * m + sl] = M.mus_span[sl * nm + m] >= 0 ? Y[nm + i] : 0.f;
+      }
+      T.sync();
       for (int m = T.t; m < nm; m += T.n) {
-        const int mx = M.mus_ext[m];
         float Ld = 0.f;
 #pragma unroll
         for (int sl = 0; sl < 3; ++sl) {
           const int j = M.mus_span[sl * nm + m];
-          const float r = j >= 0 ? Y[nm + 3 * mx + sl] : 0.f;
-          mr[3 * m + sl] = r;
-          if (j >= 0) Ld -= r * qd[j];
+          if (j >= 0) Ld -= mr[3 * m + sl] * qd[j];
         }
-        mF[m] = Y[mx];
         mc[m] = Ld;
       }
     }

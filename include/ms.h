@@ -166,12 +166,12 @@ void ms_model_destroy(ms_model *m);
 #define MS_SCHED_FUSED 1
 #define MS_SCHED_SPLIT 2
 ms_status ms_model_set_schedule(ms_model *m, int32_t schedule);
-/* Split schedule only: streams = 2 steps the two halves of every batch
- * concurrently, the first on the caller's stream and the second on a stream
- * of the model's own (forked from and joined back to the caller's with
- * events, so stream order and graph capture hold); 1 steps the batch on the
- * caller's stream alone; 0 (default) uses two halves for batches of at
- * least 4096 envs. Results do not depend on it. */
+/* Split schedule only: streams = P (1 to 4) steps the batch in P contiguous
+ * parts concurrently, the first on the caller's stream and the others on
+ * streams of the model's own (forked from and joined back to the caller's
+ * with events, so stream order and graph capture hold); 0 (default) uses
+ * two parts for batches of at least 4096 envs and one below. Launches that
+ * an ms_batch drives use one stream. Results do not depend on it. */
 ms_status ms_model_set_split_streams(ms_model *m, int32_t streams);
 /* The schedule the model's steps use now (MS_SCHED_FUSED or MS_SCHED_SPLIT). */
 ms_status ms_model_get_schedule(const ms_model *m, int32_t *schedule);

@@ -52,7 +52,7 @@ ms_status check_opts(const ms_step_opts *o) {
 }
 }  // namespace
 
-// Launches of at least this many envs run in two concurrent halves when the
+// Launches of at least this many envs run in two concurrent parts when the
 // model's split-stream setting is automatic.
 constexpr int kTwoStreamEnvs = 4096;
 
@@ -65,11 +65,15 @@ int effective_schedule(const ms_model *m) {
   return resident <= 4 ? MS_SCHED_SPLIT : MS_SCHED_FUSED;
 }
 
-hipError_t make_second_stream(ms_model *m) {
-  if (m->s2) return hipSuccess;
-  hipError_t e = hipStreamCreateWithFlags(&m->s2, hipStreamNonBlocking);
-  if (e == hipSuccess) e = hipEventCreateWithFlags(&m->ev_fork, hipEventDisableTiming);
-  if (e == hipSuccess) e = hipEventCreateWithFlags(&m->ev_join, hipEventDisableTiming);
+// the model's extra streams and their fork/join events (made once, outside
+// any capture)
+hipError_t make_part_streams(ms_model *m) {
+  if (m->sx[0]) return hipSuccess;
+  hipError_t e = hipEventCreateWithFlags(&m->ev_fork, hipEventDisableTiming);
+  for (int i = 0; i < ms_model::kMaxParts - 1 && e == hipSuccess; ++i) {
+    e = hipStreamCreateWithFlags(&m->sx[i], hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&m->ev_join[i], hipEventDisableTiming);
+  }
   return e;
 }
 
@@ -117,21 +121,22 @@ hipError_t launch(ms_model *m, const ms::KRun &r, int n_env, int n_steps, hipStr
   }
   if (reserve_split(m, n_env, st) != MS_OK) return hipErrorOutOfMemory;
   const ms::KSplit &w = m->ks;
-  // two halves of the batch on two streams (the caller's and the model's
-  // own), so that one half's kernels overlap the other's
-  int halves = r.one_stream || m->split_streams == 1 ? 1
-               : m->split_streams == 2 ? (n_env >= 2 ? 2 : 1)
-                                       : (n_env >= kTwoStreamEnvs ? 2 : 1);
-  if (halves == 2 && !m->s2) {
-    // the second stream is made outside a capture (ms_model_reserve makes
-    // it); a capture that finds none steps the batch on one stream
+  // the batch in parts on streams of their own (the caller's and the
+  // model's), so that one part's kernels overlap the others'
+  int parts = r.one_stream ? 1
+              : m->split_streams > 0 ? m->split_streams
+                                     : (n_env >= kTwoStreamEnvs ? 2 : 1);
+  parts = std::max(1, std::min(parts, n_env));
+  if (parts > 1 && !m->sx[0]) {
+    // the streams are made outside a capture (ms_model_reserve makes them);
+    // a capture that finds none steps the batch on one stream
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     if (hipStreamIsCapturing(st, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone)
-      halves = 1;
-    else if (hipError_t e = make_second_stream(m); e != hipSuccess)
+      parts = 1;
+    else if (hipError_t e = make_part_streams(m); e != hipSuccess)
       return e;
   }
-  const int per = (n_env + halves - 1) / halves;
+  const int per = (n_env + parts - 1) / parts;
   if (m->w_n_env != per) {
     ms::split_env_per_wg(m->k, w, per, &m->w_front, &m->w_back);
     m->w_n_env = per;
@@ -163,35 +168,39 @@ hipError_t launch(ms_model *m, const ms::KRun &r, int n_env, int n_steps, hipStr
     m->ev_pending.push_back({kernel, ev[0], ev[1]});
     return e;
   };
-  ms::KRun rh[2] = {r, r};
-  hipStream_t sh[2] = {st, m->s2};
-  for (int h = 0; h < halves; ++h) {
-    rh[h].env_begin = h * per;
+  constexpr int P = ms_model::kMaxParts;
+  ms::KRun rh[P];
+  hipStream_t sh[P] = {st};
+  for (int h = 0; h < parts; ++h) {
+    rh[h] = r;
+    rh[h].env_begin = std::min(n_env, h * per);
     rh[h].env_end = std::min(n_env, (h + 1) * per);
+    if (h) sh[h] = m->sx[h - 1];
   }
-  if (halves == 2) {
+  while (parts > 1 && rh[parts - 1].env_begin >= rh[parts - 1].env_end) --parts;  // no empty part
+  if (parts > 1) {
     hipError_t e = hipEventRecord(m->ev_fork, st);
-    if (e == hipSuccess) e = hipStreamWaitEvent(m->s2, m->ev_fork, 0);
+    for (int h = 1; h < parts && e == hipSuccess; ++h) e = hipStreamWaitEvent(sh[h], m->ev_fork, 0);
     if (e != hipSuccess) return e;
   }
   for (s = 0; s < n_steps; ++s) {
     hipError_t e = hipSuccess;
-    for (int h = 0; h < halves && e == hipSuccess; ++h)
+    for (int h = 0; h < parts && e == hipSuccess; ++h)
       e = timed_launch(0, h == 0, [&] { return ms::launch_front(m->k, rh[h], w, m->w_front, s, sh[h]); });
-    for (int h = 0; h < halves && e == hipSuccess; ++h)
+    for (int h = 0; h < parts && e == hipSuccess; ++h)
       e = timed_launch(1, h == 0, [&] {
         if (nvia <= 2) return ms::launch_muscle<2>(m->k, rh[h], w, mpt, s, sh[h]);
         if (nvia <= 4) return ms::launch_muscle<4>(m->k, rh[h], w, mpt, s, sh[h]);
         if (nvia <= 6) return ms::launch_muscle<6>(m->k, rh[h], w, mpt, s, sh[h]);
         return ms::launch_muscle<8>(m->k, rh[h], w, mpt, s, sh[h]);
       });
-    for (int h = 0; h < halves && e == hipSuccess; ++h)
+    for (int h = 0; h < parts && e == hipSuccess; ++h)
       e = timed_launch(2, h == 0, [&] { return ms::launch_back(m->k, rh[h], w, m->w_back, s, sh[h]); });
     if (e != hipSuccess) return e;
   }
-  if (halves == 2) {
-    hipError_t e = hipEventRecord(m->ev_join, m->s2);
-    if (e == hipSuccess) e = hipStreamWaitEvent(st, m->ev_join, 0);
+  for (int h = 1; h < parts; ++h) {
+    hipError_t e = hipEventRecord(m->ev_join[h - 1], sh[h]);
+    if (e == hipSuccess) e = hipStreamWaitEvent(st, m->ev_join[h - 1], 0);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -341,9 +350,11 @@ void ms_model_destroy(ms_model *m) {
   }
   for (hipEvent_t e : m->ev_free) (void)hipEventDestroy(e);
   if (m->key_buf) (void)hipFree(m->key_buf);
-  if (m->s2) (void)hipStreamDestroy(m->s2);
+  for (int i = 0; i < ms_model::kMaxParts - 1; ++i) {
+    if (m->sx[i]) (void)hipStreamDestroy(m->sx[i]);
+    if (m->ev_join[i]) (void)hipEventDestroy(m->ev_join[i]);
+  }
   if (m->ev_fork) (void)hipEventDestroy(m->ev_fork);
-  if (m->ev_join) (void)hipEventDestroy(m->ev_join);
   delete m;
 }
 
@@ -358,7 +369,8 @@ ms_status ms_model_set_schedule(ms_model *m, int32_t schedule) {
 
 ms_status ms_model_set_split_streams(ms_model *m, int32_t streams) {
   g_err.clear();
-  if (!m || streams < 0 || streams > 2) return fail(MS_E_ARG, "streams must be 0, 1 or 2");
+  if (!m || streams < 0 || streams > ms_model::kMaxParts)
+    return fail(MS_E_ARG, "streams must be 0 (automatic) or 1 to 4");
   m->split_streams = streams;
   return MS_OK;
 }
@@ -405,8 +417,8 @@ ms_status ms_model_kernel_times(ms_model *m, double *ms3, int64_t *n_steps) {
 ms_status ms_model_reserve(ms_model *m, int32_t n_env) {
   g_err.clear();
   if (!m || n_env <= 0) return fail(MS_E_ARG, "NULL model or n_env <= 0");
-  if (m->split_streams != 1 && make_second_stream(m) != hipSuccess)
-    return fail(MS_E_ALLOC, "could not create the split step's second stream");
+  if (m->split_streams != 1 && make_part_streams(m) != hipSuccess)
+    return fail(MS_E_ALLOC, "could not create the split step's streams");
   return reserve_split(m, n_env, nullptr);
 }
 

@@ -1234,7 +1234,7 @@ __global__ __launch_bounds__(256) void k_geometry(KModel M, KRun Rn, int n_steps
 // from the node frames and motion subspaces the kinematics kernel left in
 // the workspace. MPT = muscles per thread.
 template <int MPT, int NVIA, bool SURR>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_muscle(KModel M, KRun Rn, KSplit W, int step) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7, 7))) void k_muscle(KModel M, KRun Rn, KSplit W, int step) {
   extern __shared__ __align__(16) unsigned char lds_m[];
   const int env = Rn.env_begin + blockIdx.x;
   if (env >= (Rn.env_end ? Rn.env_end : Rn.n_env)) return;  // uniform over the workgroup

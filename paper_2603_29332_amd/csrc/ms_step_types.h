@@ -177,9 +177,12 @@ struct ms_model {
   int w_front = 0, w_back = 0, w_n_env = 0;
   // the split step's second stream and its fork/join events (two halves of
   // the batch stepped concurrently)
-  int split_streams = 0;  // 0 automatic, 1 or 2 (ms_model_set_split_streams)
-  hipStream_t s2 = nullptr;
-  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  // split step: the batch in this many parts, each on a stream of its own
+  // (the caller's, then the model's); 0 automatic (ms_model_set_split_streams)
+  int split_streams = 0;
+  static constexpr int kMaxParts = 4;
+  hipStream_t sx[kMaxParts - 1] = {};            // the model's streams
+  hipEvent_t ev_fork = nullptr, ev_join[kMaxParts - 1] = {};
   void *key_buf = nullptr;  // device copy of the key nodes
   // per-kernel timing of the split schedule (ms_model_set_kernel_timing):
   // event pairs recorded around each kernel, (kernel, start, end)

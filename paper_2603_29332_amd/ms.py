@@ -292,8 +292,8 @@ class Model:
         _check(lib().ms_model_set_schedule(self.h, int(schedule)))
 
     def set_split_streams(self, streams):
-        """Split schedule: 2 steps two halves of the batch on two streams,
-        1 on the caller's stream only, 0 automatic."""
+        """Split schedule: the batch in `streams` (1 to 4) concurrent parts,
+        each on a stream of its own; 0 automatic."""
         _check(lib().ms_model_set_split_streams(self.h, int(streams)))
 
     def schedule(self):

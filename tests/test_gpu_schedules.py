@@ -264,16 +264,17 @@ def test_split_workspace_grows_and_is_reserved_before_capture(built):
             assert torch.equal(x, y)
 
 
-@pytest.mark.parametrize("E", [1, 93, 4097])
-def test_two_stream_halves_equal_one_stream(built, E):
-    """The split step over two concurrent halves of the batch (forced for
-    every batch size, and the automatic choice at 4097 envs) gives the bits
-    of the one-stream split step and of the fused step, also when captured
-    into a graph after ms_model_reserve and replayed."""
+@pytest.mark.parametrize("E,parts", [(1, 2), (93, 2), (93, 3), (5, 4), (4097, 2), (4097, 4)])
+def test_stream_parts_equal_one_stream(built, E, parts):
+    """The split step over concurrent parts of the batch, each on a stream of
+    its own (forced for every batch size, including more parts than envs, and
+    the automatic choice at 4097 envs), gives the bits of the one-stream
+    split step and of the fused step, also when captured into a graph after
+    ms_model_reserve and replayed."""
     m, init, fused, _ = built["human"]
     one, two, auto = ms.Model(m), ms.Model(m), ms.Model(m)
     one.set_split_streams(1)
-    two.set_split_streams(2)
+    two.set_split_streams(parts)
     q, qd, act = _state(m, init, E, 14)
     x0 = np.random.default_rng(15).normal(0, 0.1, (E, m["n_mus"])).astype(np.float32)
     ref = _run(one, m, q, qd, act, 4, True, ms.EXC_AR1, x0=x0)
@@ -282,7 +283,7 @@ def test_two_stream_halves_equal_one_stream(built, E):
     if E <= 93:
         _same(ref, _run(fused, m, q, qd, act, 4, True, ms.EXC_AR1, x0=x0))
     gm = ms.Model(m)
-    gm.set_split_streams(2)
+    gm.set_split_streams(parts)
     gm.reserve(E)
     tq, tqd, tact = _t(q), _t(qd), _t(act)
     st = torch.zeros(E, dtype=torch.int32, device=DEV)
@@ -297,3 +298,13 @@ def test_two_stream_halves_equal_one_stream(built, E):
         torch.cuda.synchronize()
         for x, y in zip((tq, tqd, tact, st), want):
             assert torch.equal(x, y)
+
+
+def test_stream_parts_argument_bounds(built):
+    m = built["human"][0]
+    gm = ms.Model(m)
+    for bad in (-1, 5):
+        with pytest.raises(ms.MsError):
+            gm.set_split_streams(bad)
+    for ok in (0, 1, 4):
+        gm.set_split_streams(ok)

@@ -523,7 +523,7 @@ const char *ms_controller_last_error(void);
  *
  * Each model's envs keep their own caller-owned state (layouts as for
  * ms_rollout) and excitation descriptor. One call steps every model's envs
- * n_steps times with each model's own fused step kernel, issued as the
+ * n_steps times with each model's own step kernels, issued as the
  * batch's issue mode says: concurrently (each kernel on an internal stream
  * forked from `stream` and joined back; in the caller's model order or with
  * the model of most work first) or serially on `stream` (most work first).

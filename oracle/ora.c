@@ -32,6 +32,8 @@ struct ora_model {
   double *con_pos, *con_radius;
   double kc, cc, mu, vs, g[3];
   unsigned char *anc; /* anc[a*n+b] = 1 if node a is b or an ancestor of b */
+  int n_eq, *eq_start, *eq_dof; /* joint coupling (ora_model_set_coupling) */
+  double *eq_coef, *eq_off, eq_k, eq_d;
 };
 
 /* ---------------------------------------------------------------- helpers */
@@ -164,7 +166,51 @@ void ora_model_destroy(ora_model *m) {
   free(m->inertia); free(m->damping); free(m->f0); free(m->l_opt);
   free(m->l_slack); free(m->v_max); free(m->tau_act); free(m->tau_deact);
   free(m->via_start); free(m->via_node); free(m->via_pos); free(m->con_node);
-  free(m->con_pos); free(m->con_radius); free(m->anc); free(m);
+  free(m->con_pos); free(m->con_radius); free(m->anc);
+  free(m->eq_start); free(m->eq_dof); free(m->eq_coef); free(m->eq_off); free(m);
+}
+
+void ora_model_set_coupling(ora_model *m, int n_eq, const int32_t *eq_start,
+                            const int32_t *eq_dof, const float *eq_coef,
+                            const float *eq_off, float k, float d) {
+  free(m->eq_start); free(m->eq_dof); free(m->eq_coef); free(m->eq_off);
+  m->eq_start = m->eq_dof = NULL;
+  m->eq_coef = m->eq_off = NULL;
+  m->n_eq = n_eq > 0 ? n_eq : 0;
+  if (!m->n_eq) return;
+  int nt = eq_start[n_eq];
+  m->eq_start = dup_i(eq_start, n_eq + 1);
+  m->eq_dof = dup_i(eq_dof, nt);
+  m->eq_coef = dup_f(eq_coef, nt);
+  m->eq_off = dup_f(eq_off, n_eq);
+  m->eq_k = k;
+  m->eq_d = d;
+}
+
+/* phi_c = sum_t coef_t q_(dof_t) - off_c; with d_eff = d + dt k,
+ * tau -= J^T (k phi + d_eff J qd) and D += d_eff J^T J, written as the
+ * plain sums over each constraint's terms. */
+void ora_coupling(const ora_model *m, const double *q, const double *qd, double dt,
+                  double *tau, double *D, double *phi) {
+  const int nv = m->nv;
+  const double deff = m->eq_d + dt * m->eq_k;
+  for (int c = 0; c < m->n_eq; ++c) {
+    double ph = -m->eq_off[c], jv = 0.0;
+    for (int t = m->eq_start[c]; t < m->eq_start[c + 1]; ++t) {
+      int j = m->eq_dof[t];
+      int qi = j + (m->jtype[0] == 2 ? 1 : 0);  /* hinge/slide DoF -> its q */
+      ph += m->eq_coef[t] * q[qi];
+      jv += m->eq_coef[t] * qd[j];
+    }
+    if (phi) phi[c] = ph;
+    double f = m->eq_k * ph + deff * jv;
+    for (int t = m->eq_start[c]; t < m->eq_start[c + 1]; ++t) {
+      tau[m->eq_dof[t]] -= m->eq_coef[t] * f;
+      if (!D) continue;
+      for (int u = m->eq_start[c]; u < m->eq_start[c + 1]; ++u)
+        D[m->eq_dof[t] * nv + m->eq_dof[u]] += deff * m->eq_coef[t] * m->eq_coef[u];
+    }
+  }
 }
 int ora_nq(const ora_model *m) { return m->nq; }
 int ora_nv(const ora_model *m) { return m->nv; }
@@ -739,9 +785,11 @@ uint32_t ora_step_geo(const ora_model *m, double dt, int contact_on, double *q,
   ora_mass_matrix(m, q, M);
   ora_rnea(m, q, qd, zero, 1, C);
   if (contact_on) ora_contact(m, q, qd, dt, te, D, NULL);
+  double *teq = (double *)calloc(nv, sizeof(double));
+  ora_coupling(m, q, qd, dt, teq, D, NULL);
   for (int j = 0; j < nv; ++j) {
     td[j] = -m->damping[j] * qd[j];
-    rhs[j] = tm[j] + te[j] + td[j] - C[j];
+    rhs[j] = tm[j] + te[j] + td[j] + teq[j] - C[j];
     D[j * nv + j] += m->damping[j];
   }
   for (int mu = 0; mu < nm; ++mu) {
@@ -798,6 +846,7 @@ uint32_t ora_step_geo(const ora_model *m, double dt, int contact_on, double *q,
     if (out->r) memcpy(out->r, r, sizeof(double) * (size_t)nm * nv);
     if (out->tau_mus) memcpy(out->tau_mus, tm, sizeof(double) * nv);
     if (out->tau_ext) memcpy(out->tau_ext, te, sizeof(double) * nv);
+    if (out->tau_eq) memcpy(out->tau_eq, teq, sizeof(double) * nv);
     if (out->tau_d) memcpy(out->tau_d, td, sizeof(double) * nv);
     if (out->C) memcpy(out->C, C, sizeof(double) * nv);
     if (out->qdd) memcpy(out->qdd, qdd, sizeof(double) * nv);
@@ -811,7 +860,7 @@ uint32_t ora_step_geo(const ora_model *m, double dt, int contact_on, double *q,
   }
   free(act1); free(L); free(Ld); free(F); free(r); free(M); free(tm); free(te);
   free(td); free(C); free(rhs); free(qdd); free(zero); free(qn); free(qdn);
-  free(D);
+  free(D); free(teq);
   return st;
 }
 

@@ -11,7 +11,7 @@
  *   generalized mass matrix M(q) by its Jacobian-sum definition, the bias
  *   C(q, qd) (Coriolis, centrifugal, gravity) by textbook recursive
  *   Newton-Euler in body coordinates, penalty ground contact as tau_ext,
- *   joint damping, a dense Cholesky solve of (M + dt D) qdd = rhs with the
+ *   joint damping, penalty joint coupling, a dense Cholesky solve of (M + dt D) qdd = rhs with the
  *   dissipative forces' velocity slope D taken implicitly, and a
  *   semi-implicit Euler update.
  *
@@ -47,6 +47,24 @@ ora_model *ora_model_create(int n_node, const int32_t *parent,
                             const float *con_radius, const float *contact,
                             const float *gravity);
 void ora_model_destroy(ora_model *m);
+
+/* Anatomical joint coupling (Methods, "GPU-accelerated simulation
+ * framework": joint coupling such as the scapulohumeral rhythm), as equality
+ * constraints phi_c(q) = sum over the terms t of constraint c of
+ * coef_t q_(dof_t) - off_c = 0 on hinge/slide DoFs, enforced by a penalty
+ * spring k and damper d (copied into the model; n_eq = 0 removes them). */
+void ora_model_set_coupling(ora_model *m, int n_eq, const int32_t *eq_start,
+                            const int32_t *eq_dof, const float *eq_coef,
+                            const float *eq_off, float k, float d);
+
+/* The coupling's generalized force over a step dt, with the spring taken
+ * linearly implicitly as the contact spring is (damping d + dt k):
+ * tau_eq = -J^T (k phi(q) + (d + dt k) J qd), J the constraint Jacobian
+ * (J[c][dof_t] = coef_t); added into tau[nv]. D (may be NULL) accumulates
+ * its velocity slope -d(tau_eq)/d(qd) = (d + dt k) J^T J [nv][nv]. phi
+ * (may be NULL) receives phi(q) [n_eq]. */
+void ora_coupling(const ora_model *m, const double *q, const double *qd, double dt,
+                  double *tau, double *D, double *phi);
 int ora_nq(const ora_model *m);
 int ora_nv(const ora_model *m);
 
@@ -96,9 +114,11 @@ double ora_energy(const ora_model *m, const double *q, const double *qd);
 /* Per-stage outputs of one step (any pointer may be NULL). */
 typedef struct {
   double *act;     /* [n_mus] updated activation */
+  /* (tau_ext holds the contact force; the coupling's force is in tau_eq) */
   double *L, *Ldot, *F, *lm, *vm; /* [n_mus] */
   double *r;       /* [n_mus][nv] */
   double *tau_mus, *tau_ext, *tau_d, *C, *qdd; /* [nv] */
+  double *tau_eq;  /* [nv] joint-coupling force (may be NULL) */
   double *M;       /* [nv][nv] mass matrix */
   double *D;       /* [nv][nv] velocity slope of the dissipative forces */
 } ora_stage_out;

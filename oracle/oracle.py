@@ -49,7 +49,7 @@ _up = np.ctypeslib.ndpointer(dtype=np.uint32, flags="C_CONTIGUOUS")
 class _StageOut(C.Structure):
     _fields_ = [(k, C.c_void_p) for k in
                 ("act", "L", "Ldot", "F", "lm", "vm", "r", "tau_mus", "tau_ext",
-                 "tau_d", "C", "qdd", "M", "D")]
+                 "tau_d", "C", "qdd", "tau_eq", "M", "D")]
 
 
 def _load():
@@ -65,6 +65,9 @@ def _load():
         C.c_int, _fp, _fp, _fp, _fp, _fp, _fp, _ip, _ip, _fp,
         C.c_int, _ip, _fp, _fp, _fp, _fp]
     lib.ora_model_destroy.argtypes = [C.c_void_p]
+    lib.ora_model_set_coupling.argtypes = [C.c_void_p, C.c_int, _ip, _ip, _fp, _fp, C.c_float,
+                                           C.c_float]
+    lib.ora_coupling.argtypes = [C.c_void_p, _dp, _dp, C.c_double, _dp, C.c_void_p, C.c_void_p]
     for f in ("ora_fl", "ora_fp", "ora_fv", "ora_fv_slope"):
         getattr(lib, f).restype = C.c_double
         getattr(lib, f).argtypes = [C.c_double]
@@ -123,6 +126,14 @@ class Oracle:
             m["n_node"], k[0], k[1], k[2], k[3], k[4], k[5], k[6], k[7], k[8],
             m["n_mus"], k[9], k[10], k[11], k[12], k[13], k[14], k[15], k[16],
             k[17], m["n_con"], k[18], k[19], k[20], k[21], k[22])
+        if m.get("n_eq", 0):
+            self._keep_eq = [np.ascontiguousarray(m["eq_start"], np.int32),
+                             np.ascontiguousarray(m["eq_dof"], np.int32),
+                             np.ascontiguousarray(m["eq_coef"], np.float32),
+                             np.ascontiguousarray(m["eq_off"], np.float32)]
+            e = self._keep_eq
+            self.lib.ora_model_set_coupling(self.h, int(m["n_eq"]), e[0], e[1], e[2], e[3],
+                                            float(m["eq_k"]), float(m["eq_d"]))
 
     def __del__(self):
         try:
@@ -195,6 +206,16 @@ class Oracle:
         rc = self.lib.ora_chol_solve(len(b), _d(M), _d(b), x)
         return x, rc
 
+    def coupling(self, q, qd, dt):
+        """(tau_eq[nv], D_eq[nv][nv], phi[n_eq]) of the joint coupling."""
+        nv = self.nv
+        tau = np.zeros(nv)
+        D = np.zeros((nv, nv))
+        phi = np.zeros(max(int(self.model.get("n_eq", 0)), 1))
+        self.lib.ora_coupling(self.h, _d(q), _d(qd), float(dt), tau, D.ctypes.data,
+                              phi.ctypes.data)
+        return tau, D, phi[:int(self.model.get("n_eq", 0))]
+
     def energy(self, q, qd):
         return self.lib.ora_energy(self.h, _d(q), _d(qd))
 
@@ -212,8 +233,8 @@ class Oracle:
         if stages:
             nm, nv = self.n_mus, self.nv
             shapes = dict(act=nm, L=nm, Ldot=nm, F=nm, lm=nm, vm=nm, r=(nm, nv),
-                          tau_mus=nv, tau_ext=nv, tau_d=nv, C=nv, qdd=nv, M=(nv, nv),
-                          D=(nv, nv))
+                          tau_mus=nv, tau_ext=nv, tau_d=nv, C=nv, qdd=nv, tau_eq=nv,
+                          M=(nv, nv), D=(nv, nv))
             st_arrays = {k: np.zeros(s) for k, s in shapes.items()}
             out = _StageOut(**{k: v.ctypes.data for k, v in st_arrays.items()})
         st = self.lib.ora_step_geo(self.h, dt, int(contact), q, qd, act, _d(u),

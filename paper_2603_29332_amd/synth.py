@@ -441,6 +441,7 @@ def human_model(seed: int = 2, full: bool = True, n_mus: int | None = None,
     qlo, qhi, damp = [], [], []
     node_origin = []         # neutral world origin of each node
     node_body = []           # body spec index each node belongs to
+    node_label = []          # "<body>:<hinge>" of each node ("<body>" for the root)
     body_last = {}           # body name -> node carrying its mass
     for bi, sp in enumerate(specs):
         if sp["parent"] is None:
@@ -450,6 +451,7 @@ def human_model(seed: int = 2, full: bool = True, n_mus: int | None = None,
             axis.append([0, 0, 0])
             node_origin.append(sp["center"].copy())
             node_body.append(bi)
+            node_label.append(sp["name"])
             qlo += [-np.inf] * 6
             qhi += [np.inf] * 6
             damp += [0.0] * 6
@@ -463,6 +465,7 @@ def human_model(seed: int = 2, full: bool = True, n_mus: int | None = None,
                 axis.append(ax)
                 node_origin.append(origin)
                 node_body.append(bi)
+                node_label.append(f"{sp['name']}:{h}")
                 lo, hi = sp["limits"][h]
                 qlo.append(lo)
                 qhi.append(hi)
@@ -635,7 +638,40 @@ def human_model(seed: int = 2, full: bool = True, n_mus: int | None = None,
     model = _finish(model)
     model["root_height"] = F32(root_z)
     model["n_body"] = int(sum(1 for m_ in model["mass"] if m_ > 0))
+    model["node_label"] = node_label
     return model
+
+
+def shoulder_coupling(model: dict, k: float = 5000.0, d: float = 50.0,
+                      scap_ratio: float = 0.5, clav_ratio: float = 0.2) -> dict:
+    """A copy of a whole-body model (full=True) with the scapulohumeral
+    rhythm as joint-coupling equality constraints, per side: the scapula's
+    third hinge follows scap_ratio times the humerus's third hinge (upward
+    rotation with elevation, both about x), and the clavicle's second hinge
+    (elevation, about x) clav_ratio times it; zero offsets (neutral pose
+    consistent). Penalty stiffness k (N m / rad) and damping d (N m s / rad)."""
+    lab = model["node_label"]
+    dof, k_ = {}, 0
+    for i, t in enumerate(model["jtype"]):
+        dof[lab[i]] = k_
+        k_ += 6 if t == 2 else 1
+    start, dofs, coef = [0], [], []
+    for side in ("L", "R"):
+        hum = dof[f"hum{side}:2"]
+        for part, ratio in ((f"scap{side}:2", scap_ratio), (f"clav{side}:1", clav_ratio)):
+            dofs += [dof[part], hum]
+            coef += [1.0, -ratio]
+            start.append(len(dofs))
+    out = dict(model)
+    out["n_eq"] = len(start) - 1
+    out["eq_start"] = np.asarray(start, np.int32)
+    out["eq_dof"] = np.asarray(dofs, np.int32)
+    out["eq_coef"] = np.asarray(coef, F32)
+    out["eq_off"] = np.zeros(len(start) - 1, F32)
+    out["eq_k"] = F32(k)
+    out["eq_d"] = F32(d)
+    out["name"] = model["name"] + "_coupled"
+    return out
 
 
 def human_initial_state(model: dict, n_env: int, seed: int = 8,

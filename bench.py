@@ -247,6 +247,8 @@ def main():
     }
     line["observables"] = observables_leg(m, gm, dt, dev, E, (rho, s, mean))
     progress("observables leg done")
+    line["coupled"] = coupled_leg(m, dt, dev, E, (rho, s, mean), a.steps)
+    progress("coupled leg done")
     if not a.no_control:
         line["control"] = control_leg(m, gm, dt, dev)
         progress("control leg done")
@@ -375,6 +377,49 @@ def uneven_leg(a, dt, dev):
                           "issue": ["concurrent", "concurrent, most work first",
                                     "serial, most work first"][cfg[1]]},
             "flagged_envs": flagged}
+
+
+def coupled_leg(m, dt, dev, E, ar1, n_calls):
+    """The exact workload with the scapulohumeral rhythm as joint-coupling
+    constraints (4 penalty equality constraints on the shoulders, k = 5000
+    N m/rad, d = 50 N m s/rad), 100-step calls timed with HIP events, with
+    the largest constraint violation over 64 sampled envs at the end."""
+    import torch
+
+    from paper_2603_29332_amd import ms, synth
+    mc = synth.shoulder_coupling(m)
+    gc = ms.Model(mc)
+    gc.reserve(E)
+    q0, qd0, a0 = synth.human_initial_state(mc, E)
+    q, qd, act = (torch.tensor(v, device=dev) for v in (q0, qd0, a0))
+    st = torch.zeros(E, dtype=torch.int32, device=dev)
+    x = torch.zeros(E, mc["n_mus"], device=dev)
+    stream = torch.cuda.current_stream()
+
+    def call(k):
+        gc.rollout(q, qd, act, st, PHYS_PER_STEP, dt, True, kind=ms.EXC_AR1, seed=12,
+                   step0=k * PHYS_PER_STEP, x=x, ar1=ar1, stream=stream)
+
+    call(0)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for k in range(n_calls):
+        call(1 + k)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_call = e0.elapsed_time(e1) / n_calls
+    # phi_c = sum of coef q(dof) - off over the sampled envs that are not flagged
+    qs, sts = q.cpu().numpy(), st.cpu().numpy()
+    ok = np.array([e for e in range(0, E, E // 64) if sts[e] == 0])
+    qi = mc["eq_dof"] + 1                      # hinge DoF -> q index past the free root
+    terms = mc["eq_coef"] * qs[ok][:, qi]
+    phi = float(np.abs(np.add.reduceat(terms, mc["eq_start"][:-1], axis=1) - mc["eq_off"]).max())
+    return {"env_steps_per_s": E * PHYS_PER_STEP / (ms_call / 1e3),
+            "ms_per_physics_step": ms_call / PHYS_PER_STEP, "constraints": int(mc["n_eq"]),
+            "steps": (1 + n_calls) * PHYS_PER_STEP, "max_abs_phi_rad": phi,
+            "note": "scheduled env-steps/s of 100-step calls with the shoulder coupling; "
+                    "max |phi| over the sampled envs that are not flagged, after all calls"}
 
 
 def observables_leg(m, gm, dt, dev, E, ar1, every=10, n_calls=3):

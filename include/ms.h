@@ -103,6 +103,25 @@ typedef struct {
   const float *con_radius;   /* [n_con] sphere radius (m) */
   float contact[4];          /* stiffness k, damping c, friction mu, v_s */
   float gravity[3];          /* m/s^2, ground is the plane z = 0 */
+  /* Anatomical joint coupling (Methods, "GPU-accelerated simulation
+   * framework": anatomical joint coupling such as the scapulohumeral rhythm)
+   * as equality constraints phi_c(q) = sum over the terms t of constraint c
+   * of eq_coef[t] q(eq_dof[t]) - eq_off[c] = 0, enforced by a penalty:
+   * tau = -J^T (eq_k phi + (eq_d + dt eq_k) J q'), J[c][eq_dof[t]] = eq_coef[t],
+   * with its velocity slope (eq_d + dt eq_k) J^T J taken implicitly into the
+   * step's matrix (the spring linearly implicit, as the contact spring is).
+   * Terms of constraint c are eq_start[c] .. eq_start[c+1]-1; eq_dof are
+   * hinge/slide DoFs (not a free root's), and every two DoFs of one
+   * constraint must lie on one root-to-leaf path (so the matrix keeps its
+   * tree sparsity). n_eq = 0 (or a zero-initialised tail) means none.
+   * Limits: n_eq <= 64, at most 8 terms per constraint. */
+  int32_t n_eq;
+  const int32_t *eq_start;   /* [n_eq + 1] */
+  const int32_t *eq_dof;     /* [eq_start[n_eq]] */
+  const float *eq_coef;      /* [eq_start[n_eq]] */
+  const float *eq_off;       /* [n_eq] */
+  float eq_k;                /* N m / rad (per unit of phi), >= 0 */
+  float eq_d;                /* N m s / rad, >= 0 */
 } ms_model_desc;
 
 typedef struct ms_model ms_model;

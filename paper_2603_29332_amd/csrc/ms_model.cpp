@@ -455,6 +455,78 @@ ms_status build_tables(const ms_model_desc *d, Tables *t, std::string *msg) {
   }
   t->dent_start.push_back((int)t->dent_item.size());
   t->n_dent = (int)t->dent_h.size();
+  // joint coupling (equality constraints by a penalty)
+  if (d->n_eq > 0 && st == MS_OK) {
+    const int ne = d->n_eq;
+    need(ne <= kMaxEq, "n_eq exceeds 64", MS_E_UNSUPPORTED, &st, msg);
+    need(ne <= nv - (t->free_root ? 6 : 0), "more constraints than hinge/slide DoFs", MS_E_MODEL,
+         &st, msg);
+    need(d->eq_start && d->eq_dof && d->eq_coef && d->eq_off, "coupling arrays are NULL",
+         MS_E_MODEL, &st, msg);
+    need(d->eq_k >= 0.f && d->eq_d >= 0.f && std::isfinite(d->eq_k) && std::isfinite(d->eq_d),
+         "eq_k and eq_d must be finite and >= 0", MS_E_MODEL, &st, msg);
+    if (st != MS_OK) return st;
+    need(d->eq_start[0] == 0, "eq_start[0] must be 0", MS_E_MODEL, &st, msg);
+    const int root_dofs = t->free_root ? 6 : 0;
+    std::map<int, std::vector<std::pair<int, float>>> by_dof;  // DoF -> (constraint, coef)
+    std::map<int, float> hw;                                     // entry -> weight
+    for (int c = 0; c < ne && st == MS_OK; ++c) {
+      const int a = d->eq_start[c], b = d->eq_start[c + 1];
+      need(b > a && b - a <= kMaxEqTerms, "each constraint needs 1 to 8 terms", MS_E_MODEL, &st, msg);
+      if (st != MS_OK) break;
+      for (int x = a; x < b; ++x) {
+        const int j = d->eq_dof[x];
+        need(j >= root_dofs && j < nv, "eq_dof must be a hinge/slide DoF", MS_E_MODEL, &st, msg);
+        need(std::isfinite(d->eq_coef[x]), "eq_coef must be finite", MS_E_MODEL, &st, msg);
+        if (st != MS_OK) break;
+        for (int y = a; y < x; ++y)
+          need(d->eq_dof[y] != j, "a DoF appears twice in one constraint", MS_E_MODEL, &st, msg);
+      }
+      if (st != MS_OK) break;
+      need(std::isfinite(d->eq_off[c]), "eq_off must be finite", MS_E_MODEL, &st, msg);
+      for (int x = a; x < b && st == MS_OK; ++x) {
+        const int jx = d->eq_dof[x];
+        by_dof[jx].push_back({c, d->eq_coef[x]});
+        for (int y = a; y <= x; ++y) {
+          const int jy = d->eq_dof[y];
+          need(dof_anc(jx, jy) || dof_anc(jy, jx),
+               "the DoFs of one constraint must lie on one root-to-leaf path", MS_E_MODEL, &st,
+               msg);
+          if (st != MS_OK) break;
+          const int row = t->dof_depth[jx] >= t->dof_depth[jy] ? jx : jy;
+          const int col = row == jx ? jy : jx;
+          hw[t->row_start[row] + t->dof_depth[col] - 1] += d->eq_coef[x] * d->eq_coef[y];
+        }
+      }
+    }
+    if (st != MS_OK) return st;
+    t->n_eq = ne;
+    t->eq_k = d->eq_k;
+    t->eq_d = d->eq_d;
+    t->eq_start.assign(d->eq_start, d->eq_start + ne + 1);
+    for (int x = 0; x < d->eq_start[ne]; ++x) {
+      const int j = d->eq_dof[x];
+      t->eq_dof.push_back(j);
+      t->eq_qi.push_back(t->qadr[t->dof_node[j]]);
+      t->eq_coef.push_back(d->eq_coef[x]);
+    }
+    t->eq_off.assign(d->eq_off, d->eq_off + ne);
+    t->eqd_start.push_back(0);
+    for (auto &kv : by_dof) {
+      t->eqd_dof.push_back(kv.first);
+      for (auto &cc : kv.second) {
+        t->eqd_c.push_back(cc.first);
+        t->eqd_coef.push_back(cc.second);
+      }
+      t->eqd_start.push_back((int)t->eqd_c.size());
+    }
+    t->n_eqd = (int)t->eqd_dof.size();
+    for (auto &kv : hw) {
+      t->eqh_h.push_back(kv.first);
+      t->eqh_w.push_back(kv.second);
+    }
+    t->n_eqh = (int)t->eqh_h.size();
+  }
   if (t->free_root) {
     // a world-fixed via-point on a floating model would span the root
     for (int m = 0; m < nm; ++m)

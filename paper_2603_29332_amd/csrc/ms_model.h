@@ -17,6 +17,8 @@ constexpr int kMaxMus = 1024;
 constexpr int kMaxVia = 8;
 constexpr int kMaxCon = 64;
 constexpr int kMaxDepth = 64;
+constexpr int kMaxEq = 64;       // joint-coupling constraints
+constexpr int kMaxEqTerms = 8;   // terms per constraint
 constexpr int kWave = 64;
 
 // LDS layouts (byte offsets into one env's block) of the split schedule's
@@ -77,6 +79,13 @@ struct Tables {
   std::vector<int32_t> proj_start;        // [nv+1]
   std::vector<int32_t> proj_item;         // muscle*3 + slot
   std::vector<int32_t> dent_h, dent_start, dent_item;  // item: muscle*16 + s*4 + t
+  // joint coupling: per constraint its terms (q index, DoF, coefficient) and
+  // offset; per coupled DoF its terms (constraint, coefficient); the matrix
+  // entries of J^T J (entry index, weight summed over constraints)
+  int n_eq = 0, n_eqd = 0, n_eqh = 0;
+  float eq_k = 0.f, eq_d = 0.f;
+  std::vector<int32_t> eq_start, eq_qi, eq_dof, eqd_start, eqd_dof, eqd_c, eqh_h;
+  std::vector<float> eq_coef, eq_off, eqd_coef, eqh_w;
   // tree-sparse mass matrix (row j holds its ancestors by depth, diag last)
   std::vector<int32_t> row_start, dof_depth, path;     // path[nnz] = DoF id
   std::vector<int32_t> nnz_row;                        // row of each entry

@@ -261,7 +261,11 @@ ms_status ms_model_create(const ms_model_desc *desc, ms_model **out) {
          o_rs = p.add(t.row_start), o_dd = p.add(t.dof_depth), o_path = p.add(t.path),
          o_nr = p.add(t.nnz_row), o_hs = p.add(t.hlev_start),
          o_hd = p.add(t.hlev_dof),
-         o_lt = p.add(t.lt);
+         o_lt = p.add(t.lt),
+         o_eqs = p.add(t.eq_start), o_eqq = p.add(t.eq_qi), o_eqdf = p.add(t.eq_dof),
+         o_eqc = p.add(t.eq_coef), o_eqo = p.add(t.eq_off), o_eds = p.add(t.eqd_start),
+         o_edd = p.add(t.eqd_dof), o_edc = p.add(t.eqd_c), o_edw = p.add(t.eqd_coef),
+         o_ehh = p.add(t.eqh_h), o_ehw = p.add(t.eqh_w);
   m->dbytes = p.buf.size();
   hipError_t e = hipMalloc(&m->dbuf, m->dbytes);
   if (e != hipSuccess) {
@@ -314,6 +318,11 @@ ms_status ms_model_create(const ms_model_desc *desc, ms_model **out) {
   k.lt_front_end = t.lt_front_end; k.lt_back_begin = t.lt_back_begin;
   k.n_ci = t.n_ci;
   P_(hlev_start, o_hs, int); P_(hlev_dof, o_hd, int);
+  k.n_eq = t.n_eq; k.n_eqd = t.n_eqd; k.n_eqh = t.n_eqh; k.eq_k = t.eq_k; k.eq_d = t.eq_d;
+  P_(eq_start, o_eqs, int); P_(eq_qi, o_eqq, int); P_(eq_dof, o_eqdf, int);
+  P_(eq_coef, o_eqc, float); P_(eq_off, o_eqo, float); P_(eqd_start, o_eds, int);
+  P_(eqd_dof, o_edd, int); P_(eqd_c, o_edc, int); P_(eqd_coef, o_edw, float);
+  P_(eqh_h, o_ehh, int); P_(eqh_w, o_ehw, float);
 #undef P_
   k.off_flag = t.off_flag; k.off_q = t.off_q; k.off_qd = t.off_qd; k.off_R = t.off_R;
   k.off_P = t.off_P; k.off_S = t.off_S; k.off_con = t.off_con; k.off_rhs = t.off_rhs;

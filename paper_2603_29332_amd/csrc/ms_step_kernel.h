@@ -601,6 +601,37 @@ __device__ __forceinline__ void add_joint_damping(const KModel &M, int lane, con
   wave_sync();
 }
 
+// Anatomical joint coupling as penalty equality constraints: with
+// d_eff = d + dt k, rhs -= J^T (k phi(q) + d_eff J q') and H += dt d_eff
+// J^T J (the spring linearly implicit, as the contact spring is).
+// phi_c and (J q')_c in FP64 by lane c; the per-constraint force goes
+// through scr (n_eq doubles), then each coupled DoF and each J^T J entry
+// is one lane's (no two lanes write the same element).
+__device__ __forceinline__ void add_coupling(const KModel &M, int lane, const float *q,
+                                             const float *qd, double *H, double *rhs, double *scr,
+                                             float dt) {
+  if (!M.n_eq) return;
+  const double deff = (double)M.eq_d + (double)dt * (double)M.eq_k;
+  if (lane < M.n_eq) {
+    double ph = -(double)M.eq_off[lane], jv = 0.0;
+    for (int t = M.eq_start[lane]; t < M.eq_start[lane + 1]; ++t) {
+      const double c = (double)M.eq_coef[t];
+      ph += c * (double)q[M.eq_qi[t]];
+      jv += c * (double)qd[M.eq_dof[t]];
+    }
+    scr[lane] = (double)M.eq_k * ph + deff * jv;
+  }
+  wave_sync();
+  for (int x = lane; x < M.n_eqd; x += 64) {
+    double f = 0.0;
+    for (int t = M.eqd_start[x]; t < M.eqd_start[x + 1]; ++t)
+      f += (double)M.eqd_coef[t] * scr[M.eqd_c[t]];
+    rhs[M.eqd_dof[x]] -= f;
+  }
+  for (int e = lane; e < M.n_eqh; e += 64) H[M.eqh_h[e]] += (double)dt * deff * (double)M.eqh_w[e];
+  wave_sync();
+}
+
 // Observables of a recorded step: the muscle slices of env `env` in record
 // t / rec_every (all NULL when step t is not recorded), and the key nodes'
 // world positions and orientations.
@@ -1171,6 +1202,7 @@ __device__ __forceinline__ void step_body(const KModel &M, const KRun &Rn, int n
                                          stages, rhs, H, nullptr, nullptr, status,
                                          rec_slices(M, Rn, env, step));
     if (GEOM) return;
+    add_coupling(M, lane, q, qd, H, rhs, (double *)scr, dt);
     if (stages) {
       for (int e = lane; e < M.nnz; e += 64) Rn.o_H[(size_t)env * M.nnz + e] = H[e];
     }

@@ -118,6 +118,7 @@ __global__ __launch_bounds__(1024) void k_back(KModel M, KRun Rn, KSplit W, int 
   const double *gd = W.dsum + (size_t)env * W.dsum_stride;
   for (int e = lane; e < M.n_dent; e += 64) H[M.dent_h[e]] += (double)dt * gd[e];
   wave_sync();
+  add_coupling(M, lane, q, qd, H, rhs, invd, dt);   // invd is free until the solve
   if (stage_solve(M, lane, LT, H, rhs, xs, invd)) {
     if (lane == 0 && Rn.status) Rn.status[env] |= MS_ST_NONSPD;
     return;

@@ -42,6 +42,11 @@ struct KModel {
   int n_ci;
   int off_flag, off_q, off_qd, off_R, off_P, off_S, off_con, off_rhs, off_x, off_H,
       off_scr, off_V, off_A, off_F;
+  // joint coupling (penalty equality constraints)
+  int n_eq, n_eqd, n_eqh;
+  float eq_k, eq_d;
+  const int *eq_start, *eq_qi, *eq_dof, *eqd_start, *eqd_dof, *eqd_c, *eqh_h;
+  const float *eq_coef, *eq_off, *eqd_coef, *eqh_w;
   // key nodes whose frames the observables record
   const int *key_node;
   int n_key;

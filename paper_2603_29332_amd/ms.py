@@ -55,7 +55,9 @@ class MsDesc(C.Structure):
         ("v_max", _fptr), ("tau_act", _fptr), ("tau_deact", _fptr),
         ("via_start", _iptr), ("via_node", _iptr), ("via_pos", _fptr),
         ("n_con", C.c_int32), ("con_node", _iptr), ("con_pos", _fptr),
-        ("con_radius", _fptr), ("contact", C.c_float * 4), ("gravity", C.c_float * 3)]
+        ("con_radius", _fptr), ("contact", C.c_float * 4), ("gravity", C.c_float * 3),
+        ("n_eq", C.c_int32), ("eq_start", _iptr), ("eq_dof", _iptr), ("eq_coef", _fptr),
+        ("eq_off", _fptr), ("eq_k", C.c_float), ("eq_d", C.c_float)]
 
 
 class MsInfo(C.Structure):
@@ -270,6 +272,11 @@ class Model:
         d.con_pos, d.con_radius = keep("con_pos", np.float32), keep("con_radius", np.float32)
         d.contact = (C.c_float * 4)(*[float(x) for x in m["contact"]])
         d.gravity = (C.c_float * 3)(*[float(x) for x in m["gravity"]])
+        d.n_eq = int(m.get("n_eq", 0))
+        if d.n_eq:
+            d.eq_start, d.eq_dof = keep("eq_start", np.int32), keep("eq_dof", np.int32)
+            d.eq_coef, d.eq_off = keep("eq_coef", np.float32), keep("eq_off", np.float32)
+            d.eq_k, d.eq_d = float(m["eq_k"]), float(m["eq_d"])
         h = C.c_void_p()
         _check(L.ms_model_create(C.byref(d), C.byref(h)))
         self.h = h

@@ -95,3 +95,58 @@ def test_contact_checks():
         with pytest.raises(ms.MsError) as ei:
             ms.Model(b)
         assert ei.value.code == E_MODEL and text in str(ei.value)
+
+
+def _coupled(dofs_coefs, k=100.0, d=1.0, base=None):
+    """A model with one joint-coupling constraint per entry of dofs_coefs
+    (a list of [(dof, coef), ...])."""
+    m = dict(base if base is not None else _chain())
+    start, dofs, coefs = [0], [], []
+    for terms in dofs_coefs:
+        for j, c in terms:
+            dofs.append(j)
+            coefs.append(c)
+        start.append(len(dofs))
+    m["n_eq"] = len(start) - 1
+    m["eq_start"] = np.array(start, np.int32)
+    m["eq_dof"] = np.array(dofs, np.int32)
+    m["eq_coef"] = np.array(coefs, np.float32)
+    m["eq_off"] = np.zeros(len(start) - 1, np.float32)
+    m["eq_k"], m["eq_d"] = np.float32(k), np.float32(d)
+    return m
+
+
+COUPLING_CASES = {
+    "duplicate DoF in a constraint": ([[(2, 1.0), (2, -0.5)]], {}, E_MODEL, "twice"),
+    "DoF out of range": ([[(2, 1.0), (9, -0.5)]], {}, E_MODEL, "eq_dof"),
+    "nine terms": ([[(j % 8, 1.0) for j in range(9)]], {}, E_MODEL, "1 to 8 terms"),
+    "negative stiffness": ([[(2, 1.0), (5, -0.5)]], {"k": -1.0}, E_MODEL, "eq_k"),
+    "more constraints than DoFs": ([[(j, 1.0)] for j in range(8)] + [[(0, 2.0)]], {}, E_MODEL,
+                                   "more constraints"),
+}
+
+
+@pytest.mark.parametrize("case", list(COUPLING_CASES))
+def test_invalid_coupling_is_rejected(case):
+    terms, kw, code, text = COUPLING_CASES[case]
+    with pytest.raises(ms.MsError) as ei:
+        ms.Model(_coupled(terms, **kw))
+    assert ei.value.code == code
+    assert text in str(ei.value)
+
+
+def test_coupling_needs_one_path_and_hinge_dofs():
+    """On the whole body: DoFs of the two arms are not on one root-to-leaf
+    path (the matrix would lose its tree sparsity), and a free root's DoFs
+    cannot be coupled."""
+    m = synth.human_model(2)
+    lab = m["node_label"]
+    dof, k = {}, 0
+    for i, t in enumerate(m["jtype"]):
+        dof[lab[i]] = k
+        k += 6 if t == 2 else 1
+    for terms, text in (([[(dof["humL:2"], 1.0), (dof["humR:2"], -1.0)]], "one root-to-leaf path"),
+                        ([[(2, 1.0), (dof["humL:2"], -1.0)]], "hinge/slide DoF")):
+        with pytest.raises(ms.MsError) as ei:
+            ms.Model(_coupled(terms, base=m))
+        assert ei.value.code == E_MODEL and text in str(ei.value)

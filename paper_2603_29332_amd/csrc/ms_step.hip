@@ -113,7 +113,9 @@ ms_status reserve_split(ms_model *m, int n_env, hipStream_t st) {
 
 hipError_t launch(ms_model *m, const ms::KRun &r, int n_env, int n_steps, hipStream_t st) {
   const int nvia = m->t.n_via_max;
-  if (r.stages || effective_schedule(m) == MS_SCHED_FUSED) {
+  // a coupled model's surrogate step runs on the split schedule only
+  const bool coupled_surr = m->t.n_eq > 0 && r.geomY;
+  if (r.stages || (effective_schedule(m) == MS_SCHED_FUSED && !coupled_surr)) {
     if (nvia <= 2) return ms::launch_nvia<2>(m->t, m->k, r, n_env, n_steps, st);
     if (nvia <= 4) return ms::launch_nvia<4>(m->t, m->k, r, n_env, n_steps, st);
     if (nvia <= 6) return ms::launch_nvia<6>(m->t, m->k, r, n_env, n_steps, st);

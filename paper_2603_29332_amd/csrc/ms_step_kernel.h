@@ -1118,7 +1118,7 @@ __device__ __forceinline__ bool stage_integrate(const KModel &M, int lane, float
 // One wavefront steps one env n_steps times with every intermediate in LDS
 // and registers. SURR: muscle geometry from the surrogate's predictions with
 // the per-env fallback check; GEOM: exact geometry only (stage outputs).
-template <int MPL, int NVIA, bool SURR, bool GEOM>
+template <int MPL, int NVIA, bool SURR, bool GEOM, bool COUPLE = false>
 __device__ __forceinline__ void step_body(const KModel &M, const KRun &Rn, int n_steps) {
   // a workgroup holds blockDim.x / 64 envs, one per wavefront, each with its
   // own LDS block; envs never synchronise with each other
@@ -1202,7 +1202,9 @@ __device__ __forceinline__ void step_body(const KModel &M, const KRun &Rn, int n
                                          stages, rhs, H, nullptr, nullptr, status,
                                          rec_slices(M, Rn, env, step));
     if (GEOM) return;
-    add_coupling(M, lane, q, qd, H, rhs, (double *)scr, dt);
+    // a separate instantiation: the uncoupled kernel sits at the register
+    // limit, and the coupling's code costs it 13 % when compiled in
+    if (COUPLE) add_coupling(M, lane, q, qd, H, rhs, (double *)scr, dt);
     if (stages) {
       for (int e = lane; e < M.nnz; e += 64) Rn.o_H[(size_t)env * M.nnz + e] = H[e];
     }
@@ -1246,6 +1248,12 @@ __device__ __forceinline__ void step_body(const KModel &M, const KRun &Rn, int n
 template <int MPL, int NVIA>
 __global__ __launch_bounds__(256) void k_step(KModel M, KRun Rn, int n_steps) {
   step_body<MPL, NVIA, false, false>(M, Rn, n_steps);
+}
+
+// the exact step of a model with joint coupling
+template <int MPL, int NVIA>
+__global__ __launch_bounds__(256) void k_step_coupled(KModel M, KRun Rn, int n_steps) {
+  step_body<MPL, NVIA, false, false, true>(M, Rn, n_steps);
 }
 
 template <int MPL, int NVIA>
@@ -1367,11 +1375,14 @@ template <int MPL, int NVIA>
 hipError_t launch_k(const Tables &t, const KModel &k, const KRun &r, int n_env, int n_steps,
                     hipStream_t st) {
   const bool geom = r.stages == 2, surr = r.geomY != nullptr;
+  const bool coupled = k.n_eq > 0 && !geom;
+  if (coupled && surr) return hipErrorNotSupported;  // the split schedule steps these
   const int W = r.env_per_wg > 0 ? r.env_per_wg : default_env_per_wg(t);
   const size_t lds = t.lt.size() * 4 + (size_t)W * t.lds_bytes;
   const void *fn = geom ? (const void *)&k_geometry<MPL, NVIA>
                    : surr ? (const void *)&k_step_surrogate<MPL, NVIA>
-                          : (const void *)&k_step<MPL, NVIA>;
+                   : coupled ? (const void *)&k_step_coupled<MPL, NVIA>
+                             : (const void *)&k_step<MPL, NVIA>;
   if (lds > 65536) {
     hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
@@ -1381,6 +1392,8 @@ hipError_t launch_k(const Tables &t, const KModel &k, const KRun &r, int n_env, 
     hipLaunchKernelGGL((k_geometry<MPL, NVIA>), grid, block, lds, st, k, r, n_steps);
   else if (surr)
     hipLaunchKernelGGL((k_step_surrogate<MPL, NVIA>), grid, block, lds, st, k, r, n_steps);
+  else if (coupled)
+    hipLaunchKernelGGL((k_step_coupled<MPL, NVIA>), grid, block, lds, st, k, r, n_steps);
   else
     hipLaunchKernelGGL((k_step<MPL, NVIA>), grid, block, lds, st, k, r, n_steps);
   return hipGetLastError();

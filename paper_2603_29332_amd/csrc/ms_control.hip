@@ -311,14 +311,14 @@ hipError_t hidden_layers(const ms_controller *c, const Net &net, int n, const bf
   e1.act = 1;
   e1.c_bf16 = c->H1;
   e1.ldc = net.h;
-  hipError_t e = gemm_bf16(false, true, n, net.h, net.in, X, net.in, net.Wb[0], net.in, e1, st);
+  hipError_t e = gemm_bf16(n, net.h, net.in, X, net.in, net.Wb[0], net.in, e1, st);
   if (e != hipSuccess) return e;
   GemmEpi e2;
   e2.bias = net.b[1];
   e2.act = 1;
   e2.c_bf16 = c->H2;
   e2.ldc = net.h;
-  return gemm_bf16(false, true, n, net.h, net.h, c->H1, net.h, net.Wb[1], net.h, e2, st);
+  return gemm_bf16(n, net.h, net.h, c->H1, net.h, net.Wb[1], net.h, e2, st);
 }
 
 // output layer (linear) of a network from H2 into out[n][net.out]
@@ -328,7 +328,7 @@ hipError_t output_layer(const ms_controller *c, const Net &net, int n, float *ou
   e3.bias = net.b[2];
   e3.c_f32 = out;
   e3.ldc = net.out;
-  return gemm_bf16(false, true, n, net.out, net.h, c->H2, net.h, net.Wb[2], net.h, e3, st);
+  return gemm_bf16(n, net.out, net.h, c->H2, net.h, net.Wb[2], net.h, e3, st);
 }
 
 ms_status ctl_cap(ms_controller *c, int n) {
@@ -571,7 +571,7 @@ ms_status ms_controller_step(ms_controller *c, int32_t n_env, float *q, float *q
     ep.bias = c->flow.b[0];
     ep.c_f32 = c->P;
     ep.ldc = c->hidden;
-    e = gemm_bf16(false, true, n, c->hidden, c->n_in, c->X, c->n_in, c->flow.Wb[0], c->n_in, ep, st);
+    e = gemm_bf16(n, c->hidden, c->n_in, c->X, c->n_in, c->flow.Wb[0], c->n_in, ep, st);
     if (e != hipSuccess) return chip(e, "flow layer 1");
     for (int k = 0; k < c->flow_steps; ++k) {
       const float tk = (float)k * c->flow_dt;
@@ -582,14 +582,14 @@ ms_status ms_controller_step(ms_controller *c, int32_t n_env, float *q, float *q
       e1.act = 1;
       e1.c_bf16 = c->H1;
       e1.ldc = c->hidden;
-      e = gemm_bf16(false, true, n, c->hidden, c->n_at, c->XA, c->n_at, c->Wat, c->n_at, e1, st);
+      e = gemm_bf16(n, c->hidden, c->n_at, c->XA, c->n_at, c->Wat, c->n_at, e1, st);
       GemmEpi e2;
       e2.bias = c->flow.b[1];
       e2.act = 1;
       e2.c_bf16 = c->H2;
       e2.ldc = c->hidden;
       if (e == hipSuccess)
-        e = gemm_bf16(false, true, n, c->hidden, c->hidden, c->H1, c->hidden, c->flow.Wb[1],
+        e = gemm_bf16(n, c->hidden, c->hidden, c->H1, c->hidden, c->flow.Wb[1],
                       c->hidden, e2, st);
       if (e == hipSuccess) e = output_layer(c, c->flow, n, c->PSI, st);
       if (e != hipSuccess) return chip(e, "flow step");

@@ -7,8 +7,8 @@ namespace ms {
 
 typedef __hip_bfloat16 bf16;
 
-// C[M][N] = op(A) op(B): op(A)(m, k) = TA ? A[k * lda + m] : A[m * lda + k],
-// op(B)(k, n) = TB ? B[n * ldb + k] : B[k * ldb + n]. bfloat16 operands,
+// C[M][N] = A B^T with A [M][K] (row stride lda) and B [N][K] (row stride
+// ldb): C(m, n) = sum_k A[m * lda + k] B[n * ldb + k]. bfloat16 operands,
 // float32 accumulation. Epilogue, per element (m, n):
 //   v = acc * alpha + (bias ? bias[n] : 0) + (addc ? addc[m * ldc + n] : 0)
 //   if dact: v *= SiLU'(dact[m * ldc + n])           (backward through SiLU)
@@ -33,16 +33,20 @@ struct GemmEpi {
   int split = 0, ldc2 = 0;
 };
 
-// C[M][N] (float32, ldc) = op(A) op(B) with K split into slices computed by
+// C[M][N] (float32, ldc) = A B^T with K split into slices computed by
 // separate workgroups into work[S][M][ldc] and summed in slice order
-// (deterministic). work must hold S M ldc floats; S = splitk_slices(...).
+// (deterministic). work must hold S M ldc floats; S = splitk_slices(M, N, K).
 int splitk_slices(int M, int N, int K);
-hipError_t gemm_bf16_splitk(bool ta, bool tb, int M, int N, int K, const bf16 *A, int lda,
-                            const bf16 *B, int ldb, float *C, int ldc, float *work, hipStream_t st);
+hipError_t gemm_bf16_splitk(int M, int N, int K, const bf16 *A, int lda, const bf16 *B, int ldb,
+                            float *C, int ldc, float *work, hipStream_t st);
 
-// Requires K, lda, ldb multiples of 8 (16-byte rows). Returns the launch
-// error, if any.
-hipError_t gemm_bf16(bool ta, bool tb, int M, int N, int K, const bf16 *A, int lda, const bf16 *B,
-                     int ldb, const GemmEpi &epi, hipStream_t st);
+// XT[c][r] = X[r][c] for bfloat16 X[rows][cols]; rows and cols multiples
+// of 4.
+hipError_t transpose_bf16(const bf16 *X, int rows, int cols, bf16 *XT, hipStream_t st);
+
+// Requires K, lda, ldb multiples of 8 (16-byte rows) and lda, ldb at most
+// 2^20. Returns the launch error, if any.
+hipError_t gemm_bf16(int M, int N, int K, const bf16 *A, int lda, const bf16 *B, int ldb,
+                     const GemmEpi &epi, hipStream_t st);
 
 }  // namespace ms

@@ -1,25 +1,22 @@
 // ms_gemm.hip -- bfloat16 GEMM on gfx950 matrix cores (v_mfma_f32_16x16x32_bf16).
 //
-// Two kernels. k_gemm_nt serves the network forward shape (activations
-// times weights stored [out][in]): operand tiles go from memory straight
-// into LDS, double-buffered, in XOR-swizzled unpadded rows, 16 x 16 MFMA
-// tiles per wavefront, a tile size picked per shape. k_gemm serves every
-// layout (the backward products): a workgroup of 4 wavefronts computes a
-// 128 x 128 tile, each wavefront a 64 x 64 quadrant; operand tiles of 32
-// along K are staged through registers into LDS as [row][k] (rows padded to
-// 40 elements; K-major operands transposed on the way), the next K tile
-// fetched while the current one is multiplied. Both fuse the epilogue
-// (GemmEpi); float32 outputs of the forward kernel are stored
-// non-temporally.
+// One kernel, k_gemm_nt, for C = A B^T with both operands row-major along K
+// (activations times weights stored [out][in]; the backward products use
+// transposed weight copies and the weight gradients transposed activations,
+// so every product of the networks has this shape). Operand tiles go from
+// memory straight into LDS, double-buffered, in XOR-swizzled unpadded rows,
+// 16 x 16 MFMA tiles per wavefront, a tile size picked per shape, the
+// epilogue fused (GemmEpi), float32 outputs stored non-temporally. Long K
+// with few output tiles is split into slices summed afterwards in a fixed
+// order.
 #include "ms_gemm.h"
 
-#include <type_traits>
 
-// tile configurations of the forward-shape kernel: BM, BN, wavefronts along
-// M and N (large and small tiles)
+// tile configurations of the kernel: BM, BN, wavefronts along M and N
 #ifndef MS_NT0
 #define MS_NT0 128, 128, 4, 4
 #define MS_NT1 64, 64, 2, 4
+#define MS_NT2 128, 64, 4, 2
 #endif
 
 namespace ms {
@@ -27,134 +24,11 @@ namespace {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
-constexpr int BM = 128, BN = 128, BK = 32, LK = BK + 8;
-
-// A 128 (rows) x 32 (k) tile of a matrix whose element (o, k) lives at
-// G[o * ld + k] (row-major, KMAJOR = false) or G[k * ld + o] (KMAJOR = true),
-// in two steps so the next tile's global loads can be in flight while the
-// current one is multiplied: fetch (two 128-bit global loads per thread
-// into registers; out-of-range elements are zero), then store into
-// S[o * LK + k] (K-major tiles transposed on the way).
-template <bool KMAJOR>
-__device__ __forceinline__ void fetch(uint4 v[2], const bf16 *G, int ld, int o0, int O, int k0, int K,
-                                      int tid) {
-  const unsigned short *g = reinterpret_cast<const unsigned short *>(G);
-#pragma unroll
-  for (int it = 0; it < 2; ++it) {
-    const int c = tid + 256 * it;
-    v[it] = make_uint4(0, 0, 0, 0);
-    if (!KMAJOR) {
-      const int o = c >> 2, kc = (c & 3) * 8;
-      const int go = o0 + o, gk = k0 + kc;
-      if (go < O && gk < K) v[it] = *reinterpret_cast<const uint4 *>(g + (size_t)go * ld + gk);
-    } else {
-      const int kk = c >> 4, oc = (c & 15) * 8;
-      const int go = o0 + oc, gk = k0 + kk;
-      if (go < O && gk < K) v[it] = *reinterpret_cast<const uint4 *>(g + (size_t)gk * ld + go);
-    }
-  }
-}
-
-template <bool KMAJOR>
-__device__ __forceinline__ void store(unsigned short *S, const uint4 v[2], int tid) {
-#pragma unroll
-  for (int it = 0; it < 2; ++it) {
-    const int c = tid + 256 * it;
-    if (!KMAJOR) {
-      const int o = c >> 2, kc = (c & 3) * 8;
-      *reinterpret_cast<uint4 *>(S + o * LK + kc) = v[it];
-    } else {
-      const int kk = c >> 4, oc = (c & 15) * 8;
-      const uint4 w = v[it];
-      const unsigned short e[8] = {(unsigned short)(w.x & 0xFFFF), (unsigned short)(w.x >> 16),
-                                   (unsigned short)(w.y & 0xFFFF), (unsigned short)(w.y >> 16),
-                                   (unsigned short)(w.z & 0xFFFF), (unsigned short)(w.z >> 16),
-                                   (unsigned short)(w.w & 0xFFFF), (unsigned short)(w.w >> 16)};
-#pragma unroll
-      for (int j = 0; j < 8; ++j) S[(oc + j) * LK + kk] = e[j];
-    }
-  }
-}
 
 __device__ __forceinline__ float silu(float z) { return z / (1.0f + expf(-z)); }
 __device__ __forceinline__ float silu_slope(float z) {
   const float s = 1.0f / (1.0f + expf(-z));
   return s * (1.0f + z * (1.0f - s));
-}
-
-// K slice z = blockIdx.z covers [z k_slice, min(K, (z + 1) k_slice)) and
-// writes its partial product at an offset of z z_stride floats
-template <bool TA, bool TB>
-__global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const bf16 *A, int lda,
-                                              const bf16 *B, int ldb, GemmEpi epi, int k_slice,
-                                              size_t z_stride) {
-  __shared__ __align__(16) unsigned short As[BM * LK];
-  __shared__ __align__(16) unsigned short Bs[BN * LK];
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int wm = w >> 1, wn = w & 1;
-  const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
-  f32x4 acc[4][4];
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-
-  const int kb = blockIdx.z * k_slice, ke = min(K, kb + k_slice);
-  uint4 ra[2], rb[2];
-  if (kb < ke) {
-    fetch<TA>(ra, A, lda, m0, M, kb, ke, tid);
-    fetch<!TB>(rb, B, ldb, n0, N, kb, ke, tid);
-  }
-  for (int k0 = kb; k0 < ke; k0 += BK) {
-    store<TA>(As, ra, tid);
-    store<!TB>(Bs, rb, tid);
-    __syncthreads();
-    // the next tile's loads travel while this one is multiplied
-    if (k0 + BK < ke) {
-      fetch<TA>(ra, A, lda, m0, M, k0 + BK, ke, tid);
-      fetch<!TB>(rb, B, ldb, n0, N, k0 + BK, ke, tid);
-    }
-    bf16x8 a[4], b[4];
-    const int kq = (lane >> 4) * 8, r = lane & 15;
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-      a[i] = *reinterpret_cast<const bf16x8 *>(As + (wm * 64 + i * 16 + r) * LK + kq);
-#pragma unroll
-    for (int j = 0; j < 4; ++j)
-      b[j] = *reinterpret_cast<const bf16x8 *>(Bs + (wn * 64 + j * 16 + r) * LK + kq);
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int j = 0; j < 4; ++j)
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
-    __syncthreads();
-  }
-
-  // accumulator element e of tile (i, j): row 4*(lane/16) + e, column lane%16
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j)
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int m = m0 + wm * 64 + i * 16 + (lane >> 4) * 4 + e;
-        const int n = n0 + wn * 64 + j * 16 + (lane & 15);
-        if (m >= M || n >= N) continue;
-        const size_t o = (size_t)blockIdx.z * z_stride + (size_t)m * epi.ldc + n;
-        float v = acc[i][j][e] * epi.alpha;
-        if (epi.bias) v += epi.bias[n];
-        if (epi.addc) v += epi.addc[o];
-        if (epi.dact) v *= silu_slope(epi.dact[o]);
-        if (epi.z_out) epi.z_out[o] = v;
-        if (epi.act == 1) v = silu(v);
-        if (epi.act == 2) v = 1.0f / (1.0f + expf(-v));
-        if (epi.scale) v = v * epi.scale[n] + epi.shift[n];
-        if (epi.c2 && n >= epi.split)
-          epi.c2[(size_t)m * epi.ldc2 + (n - epi.split)] = v;
-        else if (epi.c_f32)
-          epi.c_f32[o] = v;
-        if (epi.c_bf16) epi.c_bf16[o] = __float2bfloat16(v);
-      }
 }
 
 constexpr int NK = 64;
@@ -235,12 +109,23 @@ __device__ __forceinline__ void store_tile(const f32x4 (&acc)[TM][TN], int mw, i
 // rows; chunk q (8 k values) of row r sits in slot q ^ g(r),
 // g(r) = (r & 7) ^ ((r >> 3) & 1), so the 16 rows an MFMA operand read
 // touches fall in distinct bank groups. Out-of-range rows and K chunks read
-// as zeros.
-template <int BMt, int BNt, int WM, int WN>
+// as zeros. SPLIT: K is split into slices of ks; slice z = blockIdx.z takes
+// columns [z ks, min(K, (z + 1) ks)) and writes its partial product to
+// epi.c_f32 + z cstride (plain float32 output, summed afterwards). The
+// split is a template choice so that the other instantiations keep their
+// register count.
+template <int BMt, int BNt, int WM, int WN, bool SPLIT = false>
 __global__ __launch_bounds__(64 * WM * WN) void k_gemm_nt(int M, int N, int K, const bf16 *A,
                                                              int lda, const bf16 *B, int ldb,
-                                                             GemmEpi epi) {
+                                                             GemmEpi epi, int ks, size_t cstride) {
   constexpr int NT = 64 * WM * WN;
+  if (SPLIT) {
+    const int kb = blockIdx.z * ks;
+    A += kb;
+    B += kb;
+    K = max(0, min(K - kb, ks));
+    epi.c_f32 += blockIdx.z * cstride;
+  }
   constexpr int TM = BMt / WM / 16, TN = BNt / WN / 16;
   constexpr int CA = BMt * 8 / NT, CB = BNt * 8 / NT;     // chunks per thread and step
   static_assert(CA >= 1 && CB >= 1 && TM >= 1 && TN >= 1, "bad configuration");
@@ -337,6 +222,30 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm_nt(int M, int N, int K, c
   store_tile<TM, TN, true>(acc, m0 + wm * (BMt / WM), n0 + wn * (BNt / WN), lane, M, N, epi);
 }
 
+// XT[c][r] = X[r][c] for 16-bit X[rows][cols] (rows, cols multiples of 4):
+// 64 x 64 tiles through LDS, 8-byte loads along X's rows and 8-byte stores
+// along XT's rows; 256 threads.
+__global__ void k_transpose16(const unsigned short *X, int rows, int cols, unsigned short *XT) {
+  __shared__ unsigned short t[64][68];
+  const int c0 = blockIdx.x * 64, r0 = blockIdx.y * 64;
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int r = ty + 16 * i, c = c0 + 4 * tx;
+    ushort4 v = make_ushort4(0, 0, 0, 0);
+    if (r0 + r < rows && c < cols) v = *reinterpret_cast<const ushort4 *>(&X[(size_t)(r0 + r) * cols + c]);
+    *reinterpret_cast<ushort4 *>(&t[r][4 * tx]) = v;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int c = ty + 16 * i, r = 4 * tx;
+    if (c0 + c < cols && r0 + r < rows)
+      *reinterpret_cast<ushort4 *>(&XT[(size_t)(c0 + c) * rows + r0 + r]) =
+          make_ushort4(t[r][c], t[r + 1][c], t[r + 2][c], t[r + 3][c]);
+  }
+}
+
 // C[m][n] = sum over z of work[z][m][n], slice order
 __global__ void k_splitk_sum(const float *work, int S, size_t stride, int M, int N, int ldc,
                              float *C) {
@@ -350,21 +259,6 @@ __global__ void k_splitk_sum(const float *work, int S, size_t stride, int M, int
 }
 
 }  // namespace
-
-static hipError_t gemm_launch(bool ta, bool tb, int M, int N, int K, const bf16 *A, int lda,
-                              const bf16 *B, int ldb, const GemmEpi &epi, int S, int ks,
-                              size_t stride, hipStream_t st) {
-  dim3 grid((N + BN - 1) / BN, (M + BM - 1) / BM, S), block(256);
-  if (!ta && !tb)
-    hipLaunchKernelGGL((k_gemm<false, false>), grid, block, 0, st, M, N, K, A, lda, B, ldb, epi, ks, stride);
-  if (!ta && tb)
-    hipLaunchKernelGGL((k_gemm<false, true>), grid, block, 0, st, M, N, K, A, lda, B, ldb, epi, ks, stride);
-  if (ta && !tb)
-    hipLaunchKernelGGL((k_gemm<true, false>), grid, block, 0, st, M, N, K, A, lda, B, ldb, epi, ks, stride);
-  if (ta && tb)
-    hipLaunchKernelGGL((k_gemm<true, true>), grid, block, 0, st, M, N, K, A, lda, B, ldb, epi, ks, stride);
-  return hipGetLastError();
-}
 
 namespace {
 int cu_count() {
@@ -381,63 +275,90 @@ int cu_count() {
 }
 }  // namespace
 
-// Tile of the forward-shape kernel (measured on MI355X): 128 x 128 with 16
-// wavefronts when it still gives every CU two workgroups and the epilogue
-// is plain (bias, activation, one output); otherwise 64 x 64 with 8
-// wavefronts, which is faster for narrow outputs and also for the
-// de-standardising, column-split epilogue (the larger tile's 16-wavefront
-// epilogue then doubles its time).
-int gemm_nt_tile(int M, int N, const GemmEpi &epi) {
+// Tile of a product (measured on MI355X): 128 x 128 with 16 wavefronts
+// when it still gives every CU two workgroups and the epilogue is plain
+// (bias, activation, one output); 128 x 64 with 8 wavefronts for long K
+// (at least 2048) when that still gives every CU a workgroup; otherwise
+// 64 x 64 with 8 wavefronts, which is faster for narrow outputs and for the
+// de-standardising, column-split epilogue (the 16-wavefront epilogue then
+// doubles its time).
+int gemm_nt_tile(int M, int N, int K, const GemmEpi &epi) {
   const int cus = cu_count();
   const long long big = (long long)((M + 127) / 128) * ((N + 127) / 128);
+  const long long tall = (long long)((M + 127) / 128) * ((N + 63) / 64);
   if (big >= 2 * cus && !epi.scale && !epi.c2) return 0;
+  if (K >= 2048 && tall >= cus) return 2;
   return 1;
 }
 
 template <int BM, int BN, int WM, int WN>
 void launch_nt(int M, int N, int K, const bf16 *A, int lda, const bf16 *B, int ldb,
-               const GemmEpi &epi, hipStream_t st) {
-  hipLaunchKernelGGL((k_gemm_nt<BM, BN, WM, WN>), dim3((N + BN - 1) / BN, (M + BM - 1) / BM),
-                     dim3(64 * WM * WN), 0, st, M, N, K, A, lda, B, ldb, epi);
+               const GemmEpi &epi, hipStream_t st, int S = 1, int ks = 0, size_t cstride = 0) {
+  const dim3 grid((N + BN - 1) / BN, (M + BM - 1) / BM, S), block(64 * WM * WN);
+  if (S > 1)
+    hipLaunchKernelGGL((k_gemm_nt<BM, BN, WM, WN, true>), grid, block, 0, st, M, N, K, A, lda, B,
+                       ldb, epi, ks, cstride);
+  else
+    hipLaunchKernelGGL((k_gemm_nt<BM, BN, WM, WN, false>), grid, block, 0, st, M, N, K, A, lda, B,
+                       ldb, epi, K, (size_t)0);
 }
 
-hipError_t gemm_bf16(bool ta, bool tb, int M, int N, int K, const bf16 *A, int lda, const bf16 *B,
-                     int ldb, const GemmEpi &epi, hipStream_t st) {
+hipError_t transpose_bf16(const bf16 *X, int rows, int cols, bf16 *XT, hipStream_t st) {
+  if (rows <= 0 || cols <= 0) return hipSuccess;
+  if (rows % 4 || cols % 4 || rows / 64 >= 65536) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_transpose16, dim3((cols + 63) / 64, (rows + 63) / 64), dim3(256), 0, st,
+                     reinterpret_cast<const unsigned short *>(X), rows, cols,
+                     reinterpret_cast<unsigned short *>(XT));
+  return hipGetLastError();
+}
+
+hipError_t gemm_bf16(int M, int N, int K, const bf16 *A, int lda, const bf16 *B, int ldb,
+                     const GemmEpi &epi, hipStream_t st) {
   if (M <= 0 || N <= 0 || K <= 0) return hipSuccess;
-  if (K % 8 || lda % 8 || ldb % 8 || (ta && M % 8) || (!tb && N % 8)) return hipErrorInvalidValue;
-  if (!ta && tb) {
-    // byte offsets within a tile's rows are 32-bit
-    if (lda > (1 << 20) || ldb > (1 << 20)) return hipErrorInvalidValue;
-    if (gemm_nt_tile(M, N, epi) == 0)
-      launch_nt<MS_NT0>(M, N, K, A, lda, B, ldb, epi, st);
-    else
-      launch_nt<MS_NT1>(M, N, K, A, lda, B, ldb, epi, st);
-    return hipGetLastError();
+  if (K % 8 || lda % 8 || ldb % 8) return hipErrorInvalidValue;
+  // byte offsets within a tile's rows are 32-bit
+  if (lda > (1 << 20) || ldb > (1 << 20)) return hipErrorInvalidValue;
+  switch (gemm_nt_tile(M, N, K, epi)) {
+    case 0: launch_nt<MS_NT0>(M, N, K, A, lda, B, ldb, epi, st); break;
+    case 2: launch_nt<MS_NT2>(M, N, K, A, lda, B, ldb, epi, st); break;
+    default: launch_nt<MS_NT1>(M, N, K, A, lda, B, ldb, epi, st);
   }
-  return gemm_launch(ta, tb, M, N, K, A, lda, B, ldb, epi, 1, K, 0, st);
+  return hipGetLastError();
+}
+
+// Split-K tile: 128 x 64 with 8 wavefronts when the output has at least 128
+// of them, else 64 x 64.
+static bool splitk_tall(int M, int N) {
+  return (long long)((M + 127) / 128) * ((N + 63) / 64) >= 128;
 }
 
 int splitk_slices(int M, int N, int K) {
-  const int tiles = ((M + BM - 1) / BM) * ((N + BN - 1) / BN);
+  // about two workgroups per CU, slices of at least 512 along K (8 of the
+  // kernel's K steps)
+  const long long tiles = splitk_tall(M, N) ? (long long)((M + 127) / 128) * ((N + 63) / 64)
+                                            : (long long)((M + 63) / 64) * ((N + 63) / 64);
   int S = 1;
-  // at least ~1024 workgroups, slices of at least 256 along K
-  while (S < 64 && tiles * S < 1024 && K / (2 * S) >= 256) S *= 2;
+  while (S < 32 && tiles * S < 2 * cu_count() && K / (2 * S) >= 512) S *= 2;
   return S;
 }
 
-hipError_t gemm_bf16_splitk(bool ta, bool tb, int M, int N, int K, const bf16 *A, int lda,
-                            const bf16 *B, int ldb, float *C, int ldc, float *work, hipStream_t st) {
+hipError_t gemm_bf16_splitk(int M, int N, int K, const bf16 *A, int lda, const bf16 *B, int ldb,
+                            float *C, int ldc, float *work, hipStream_t st) {
   if (M <= 0 || N <= 0 || K <= 0) return hipSuccess;
-  if (K % 8 || lda % 8 || ldb % 8 || (ta && M % 8) || (!tb && N % 8)) return hipErrorInvalidValue;
+  if (K % 8 || lda % 8 || ldb % 8) return hipErrorInvalidValue;
+  if (lda > (1 << 20) || ldb > (1 << 20)) return hipErrorInvalidValue;
   const int S = splitk_slices(M, N, K);
-  int ks = (K + S - 1) / S;
-  ks = (ks + BK - 1) / BK * BK;
+  const int ks = ((K + S - 1) / S + NK - 1) / NK * NK;
   GemmEpi epi;
-  epi.c_f32 = work;
+  epi.c_f32 = S > 1 ? work : C;
   epi.ldc = ldc;
   const size_t stride = (size_t)M * ldc;
-  hipError_t e = gemm_launch(ta, tb, M, N, K, A, lda, B, ldb, epi, S, ks, stride, st);
-  if (e != hipSuccess) return e;
+  if (splitk_tall(M, N))
+    launch_nt<MS_NT2>(M, N, K, A, lda, B, ldb, epi, st, S, ks, stride);
+  else
+    launch_nt<MS_NT1>(M, N, K, A, lda, B, ldb, epi, st, S, ks, stride);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || S == 1) return e;
   const size_t n = (size_t)M * N;
   hipLaunchKernelGGL(k_splitk_sum, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, work, S,
                      stride, M, N, ldc, C);

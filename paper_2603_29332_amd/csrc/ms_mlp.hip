@@ -29,6 +29,9 @@ struct ms_surrogate {
   float *W[3] = {}, *b[3] = {}, *gW[3] = {}, *gb[3] = {};
   float *mW[3] = {}, *vW[3] = {}, *mb[3] = {}, *vb[3] = {};
   ms::bf16 *Wb[3] = {};
+  // WbT[l][j][o] = Wb[l][o][j] for the two layers whose input gradient the
+  // backward pass needs, so dZ = dY W is a product with B stored [N][K]
+  ms::bf16 *WbT[3] = {};
   float *mean = nullptr, *stdv = nullptr, *istd = nullptr, *mask = nullptr;
   float *lo = nullptr, *hi = nullptr;
   int *hinge_q = nullptr;  // q index of each input (-1 = padding)
@@ -36,8 +39,11 @@ struct ms_surrogate {
   int cap = 0;
   ms::bf16 *X = nullptr, *H1 = nullptr, *H2 = nullptr, *dYb = nullptr, *dZ2b = nullptr,
            *dZ1b = nullptr;
-  float *Z1 = nullptr, *Z2 = nullptr, *Y = nullptr, *T = nullptr, *dY = nullptr, *dZ2 = nullptr,
+  float *Z1 = nullptr, *Z2 = nullptr, *Y = nullptr, *dZ2 = nullptr,
         *dZ1 = nullptr, *part = nullptr, *cpart = nullptr, *kwork = nullptr;
+  // transposed copies [features][batch] of a layer's output gradient (tA)
+  // and input (tB), the operands of its weight gradient
+  ms::bf16 *tA = nullptr, *tB = nullptr;
   // training batches: poses, exact labels, output statistics
   float *Qb = nullptr, *Lb = nullptr, *Rb = nullptr, *acc = nullptr, *acc2 = nullptr;
   std::vector<void *> owned;
@@ -105,48 +111,70 @@ __global__ void k_sample(int n, int nq, int free_root, const int *hq, const floa
   }
 }
 
-// standardised targets T[p][o] from L[p][m] and r[p][m][3]
-__global__ void k_targets(const float *L, const float *r, int n_mus, int n, const float *mean,
-                          const float *istd, const float *mask, float *T) {
-  const int n_out = 4 * n_mus;
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= n * n_out) return;
-  const int p = t / n_out, o = t % n_out;
-  const float y = o < n_mus ? L[(size_t)p * n_mus + o] : r[(size_t)p * 3 * n_mus + (o - n_mus)];
-  T[t] = mask[o] != 0.0f ? (y - mean[o]) * istd[o] : 0.0f;
-}
+// Rows per chunk of the column sums and of the loss kernel.
+constexpr int kCS = 64;
 
-// dY = 2 mask (Y - T) / (n n_out) (float32 and bfloat16); per-block
-// partial sums of mask (Y - T)^2 into part[blockIdx]
-__global__ __launch_bounds__(256) void k_loss(const float *Y, const float *T, const float *mask,
-                                              int n, int n_out, float *dY, bf16 *dYb, float *part) {
+// Loss and output gradient of one training batch, the standardised target
+// computed in place from the labels: T[p][o] = mask[o] (y - mean[o]) istd[o]
+// with y = L[p][o] for o < n_mus, else r[p][(o - n_mus)]; d = mask (Y - T),
+// dYb = bf16(2 d / (n n_out)). Block (x, y) takes 256 consecutive outputs o
+// over rows [kCS y, kCS (y + 1)) and writes cpart[y][o] = sum over those
+// rows of 2 d / (n n_out) (float32, row order) and part[block] = sum of d^2
+// over its outputs and rows (fixed-order tree).
+__global__ __launch_bounds__(256) void k_loss(const float *Y, const float *L, const float *r,
+                                              int n_mus, int n, const float *mean,
+                                              const float *istd, const float *mask, bf16 *dYb,
+                                              float *cpart, float *part) {
   __shared__ float red[256];
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int n_out = 4 * n_mus;
+  const int o = blockIdx.x * 256 + threadIdx.x, p0 = blockIdx.y * kCS, p1 = min(n, p0 + kCS);
   float l = 0.0f;
-  if (t < n * n_out) {
-    const int o = t % n_out;
-    const float d = mask[o] * (Y[t] - T[t]);
-    l = d * d;
-    const float g = 2.0f * d / ((float)n * (float)n_out);
-    dY[t] = g;
-    dYb[t] = __float2bfloat16(g);
+  if (o < n_out) {
+    const float mk = mask[o], mu = mean[o], is = istd[o], sc = 2.0f / ((float)n * (float)n_out);
+    const float *lab = o < n_mus ? L + o : r + (o - n_mus);
+    const size_t lp = o < n_mus ? (size_t)n_mus : (size_t)3 * n_mus;
+    float gs = 0.0f;
+    for (int p = p0; p < p1; p += 8) {
+      float y[8], t[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        y[u] = p + u < p1 ? Y[(size_t)(p + u) * n_out + o] : 0.0f;
+        t[u] = p + u < p1 ? lab[(size_t)(p + u) * lp] : 0.0f;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        if (p + u >= p1) break;
+        const float tt = mk != 0.0f ? (t[u] - mu) * is : 0.0f;
+        const float d = mk * (y[u] - tt), g = sc * d;
+        l += d * d;
+        gs += g;
+        dYb[(size_t)(p + u) * n_out + o] = __float2bfloat16(g);
+      }
+    }
+    cpart[(size_t)blockIdx.y * n_out + o] = gs;
   }
   red[threadIdx.x] = l;
   __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
     __syncthreads();
   }
-  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+  if (threadIdx.x == 0) part[blockIdx.y * gridDim.x + blockIdx.x] = red[0];
 }
 
-// loss = sum(part) / (n n_out): 256 threads sum strided slices, then a
-// fixed-order tree (deterministic)
+// loss = sum(part) / (n n_out): 256 threads sum strided slices (loads eight
+// at a time), then a fixed-order tree (deterministic)
 __global__ __launch_bounds__(256) void k_loss_final(const float *part, int nb, int n, int n_out,
                                                     float *loss) {
   __shared__ double red[256];
   double s = 0.0;
-  for (int i = threadIdx.x; i < nb; i += 256) s += part[i];
+  for (int i = threadIdx.x; i < nb; i += 8 * 256) {
+    float v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = i + u * 256 < nb ? part[i + u * 256] : 0.0f;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s += v[u];
+  }
   red[threadIdx.x] = s;
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
@@ -156,16 +184,31 @@ __global__ __launch_bounds__(256) void k_loss_final(const float *part, int nb, i
   if (threadIdx.x == 0) *loss = (float)(red[0] / ((double)n * (double)n_out));
 }
 
-// Column sums in two fixed-order passes: part[k][c] = sum of rows
-// [kCS k, kCS (k+1)) of column c, then out[c] = sum over k of part[k][c].
-constexpr int kCS = 256;
-__global__ void k_colsum(const float *X, int rows, int cols, int chunk, float *out) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= cols) return;
+// Column sums, fixed order: block (x, y) takes 64 columns over rows
+// [chunk y, chunk (y + 1)); wavefront g of 4 sums rows g, g + 4, ... of
+// that range (loads eight at a time), and the four partial sums are added
+// in order into out[y][c].
+__global__ __launch_bounds__(256) void k_colsum(const float *X, int rows, int cols, int chunk,
+                                                float *out) {
+  __shared__ float red[4][64];
+  const int c = blockIdx.x * 64 + (threadIdx.x & 63), g = threadIdx.x >> 6;
   const int r0 = blockIdx.y * chunk, r1 = min(rows, r0 + chunk);
   float s = 0.0f;
-  for (int r = r0; r < r1; ++r) s += X[(size_t)r * cols + c];
-  out[(size_t)blockIdx.y * cols + c] = s;
+  if (c < cols) {
+    for (int r = r0 + g; r < r1; r += 32) {
+      float v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = r + 4 * u < r1 ? X[(size_t)(r + 4 * u) * cols + c] : 0.0f;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) s += v[u];
+    }
+  }
+  red[g][threadIdx.x & 63] = s;
+  __syncthreads();
+  if (g == 0 && c < cols) {
+    const int t = threadIdx.x;
+    out[(size_t)blockIdx.y * cols + c] = ((red[0][t] + red[1][t]) + red[2][t]) + red[3][t];
+  }
 }
 
 // acc[o] (+)= sum over the rows of Y[n][n_out] of y (pass 1) or of
@@ -229,11 +272,35 @@ __global__ void k_adam(float *w, float *m, float *v, const float *g, int n, floa
 
 inline int blocks(long long n, int b = 256) { return (int)((n + b - 1) / b); }
 
+// WT[c][r] = bf16(W[r][c]) for W[rows][cols], through 32 x 32 LDS tiles so
+// both the reads and the writes are row-contiguous; 256 threads per tile.
+__global__ void k_transpose_bf16(const float *W, bf16 *WT, int rows, int cols) {
+  __shared__ float t[32][33];
+  const int c0 = blockIdx.x * 32, r0 = blockIdx.y * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  for (int k = ty; k < 32; k += 8) {
+    const int r = r0 + k, c = c0 + tx;
+    t[k][tx] = (r < rows && c < cols) ? W[(size_t)r * cols + c] : 0.0f;
+  }
+  __syncthreads();
+  for (int k = ty; k < 32; k += 8) {
+    const int c = c0 + k, r = r0 + tx;
+    if (r < rows && c < cols) WT[(size_t)c * rows + r] = __float2bfloat16(t[tx][k]);
+  }
+}
+
+void transpose_w(const float *W, bf16 *WT, int rows, int cols, hipStream_t st) {
+  hipLaunchKernelGGL(k_transpose_bf16, dim3((cols + 31) / 32, (rows + 31) / 32), dim3(256), 0, st,
+                     W, WT, rows, cols);
+}
+
 // out[c] = column sums of X[rows][cols], deterministic order
 void colsum(ms_surrogate *s, const float *X, int rows, int cols, float *out, hipStream_t st) {
   const int nk = (rows + kCS - 1) / kCS;
-  hipLaunchKernelGGL(k_colsum, dim3(blocks(cols), nk), dim3(256), 0, st, X, rows, cols, kCS, s->cpart);
-  hipLaunchKernelGGL(k_colsum, dim3(blocks(cols), 1), dim3(256), 0, st, s->cpart, nk, cols, nk, out);
+  hipLaunchKernelGGL(k_colsum, dim3((cols + 63) / 64, nk), dim3(256), 0, st, X, rows, cols, kCS,
+                     s->cpart);
+  hipLaunchKernelGGL(k_colsum, dim3((cols + 63) / 64, 1), dim3(256), 0, st, s->cpart, nk, cols, nk,
+                     out);
 }
 
 thread_local std::string s_err;
@@ -288,14 +355,12 @@ ms_status ensure_cap(ms_surrogate *s, int n) {
   a.add(&s->Z2, B * s->h2);
   a.add(&s->H2, B * s->h2);
   a.add(&s->Y, B * s->n_out);
-  a.add(&s->T, B * s->n_out);
-  a.add(&s->dY, B * s->n_out);
   a.add(&s->dYb, B * s->n_out);
   a.add(&s->dZ2, B * s->h2);
   a.add(&s->dZ2b, B * s->h2);
   a.add(&s->dZ1, B * s->h1);
   a.add(&s->dZ1b, B * s->h1);
-  a.add(&s->part, (size_t)blocks((long long)B * s->n_out));
+  a.add(&s->part, (size_t)blocks(s->n_out) * ((B + kCS - 1) / kCS));
   a.add(&s->cpart, (size_t)((B + kCS - 1) / kCS) * std::max(s->n_out, std::max(s->h1, s->h2)));
   {
     // split-K partials of the weight gradients (K = batch)
@@ -304,6 +369,8 @@ ms_status ensure_cap(ms_surrogate *s, int n) {
     for (int l = 0; l < 3; ++l)
       w = std::max(w, (size_t)splitk_slices(M[l], N[l], n) * M[l] * N[l]);
     a.add(&s->kwork, w);
+    a.add(&s->tA, B * std::max(s->n_out, std::max(s->h1, s->h2)));
+    a.add(&s->tB, B * std::max(s->n_in, std::max(s->h1, s->h2)));
   }
   a.add(&s->Qb, B * s->nq);
   a.add(&s->Lb, B * s->n_mus);
@@ -343,7 +410,7 @@ ms_status forward(ms_surrogate *s, int n, const float *q, bool destd, const FwdW
   e1.act = 1;
   e1.c_bf16 = w.H1;
   e1.ldc = s->h1;
-  hipError_t e = gemm_bf16(false, true, n, s->h1, s->n_in, w.X, s->n_in, s->Wb[0], s->n_in, e1, st);
+  hipError_t e = gemm_bf16(n, s->h1, s->n_in, w.X, s->n_in, s->Wb[0], s->n_in, e1, st);
   if (e != hipSuccess) return hipst(e, "gemm 1");
   GemmEpi e2;
   e2.bias = s->b[1];
@@ -351,7 +418,7 @@ ms_status forward(ms_surrogate *s, int n, const float *q, bool destd, const FwdW
   e2.act = 1;
   e2.c_bf16 = w.H2;
   e2.ldc = s->h2;
-  e = gemm_bf16(false, true, n, s->h2, s->h1, w.H1, s->h1, s->Wb[1], s->h1, e2, st);
+  e = gemm_bf16(n, s->h2, s->h1, w.H1, s->h1, s->Wb[1], s->h1, e2, st);
   if (e != hipSuccess) return hipst(e, "gemm 2");
   GemmEpi e3;
   e3.bias = s->b[2];
@@ -366,7 +433,7 @@ ms_status forward(ms_surrogate *s, int n, const float *q, bool destd, const FwdW
     e3.scale = s->stdv;
     e3.shift = s->mean;
   }
-  e = gemm_bf16(false, true, n, s->n_out, s->h2, w.H2, s->h2, s->Wb[2], s->h2, e3, st);
+  e = gemm_bf16(n, s->n_out, s->h2, w.H2, s->h2, s->Wb[2], s->h2, e3, st);
   return hipst(e, "gemm 3");
 }
 
@@ -452,18 +519,20 @@ ms_status ms_surrogate_create(const ms_model *m, int32_t hidden, uint64_t seed, 
     s->mW[l] = dalloc<float>(s, nw);
     s->vW[l] = dalloc<float>(s, nw);
     s->Wb[l] = dalloc<bf16>(s, nw);
+    if (l > 0) s->WbT[l] = dalloc<bf16>(s, nw);
     s->b[l] = dalloc<float>(s, outd[l]);
     s->gb[l] = dalloc<float>(s, outd[l]);
     s->mb[l] = dalloc<float>(s, outd[l]);
     s->vb[l] = dalloc<float>(s, outd[l]);
-    if (!s->W[l] || !s->gW[l] || !s->mW[l] || !s->vW[l] || !s->Wb[l] || !s->b[l] || !s->gb[l] ||
-        !s->mb[l] || !s->vb[l]) {
+    if (!s->W[l] || !s->gW[l] || !s->mW[l] || !s->vW[l] || !s->Wb[l] || (l > 0 && !s->WbT[l]) ||
+        !s->b[l] || !s->gb[l] || !s->mb[l] || !s->vb[l]) {
       ms_surrogate_destroy(s);
       return sfail(MS_E_ALLOC, "surrogate allocation failed");
     }
     hipLaunchKernelGGL(k_init, dim3(blocks((long long)nw)), dim3(256), 0, 0, s->W[l], (int)nw, in[l],
                        (unsigned long long)seed * 3ull + (unsigned long long)l);
     hipLaunchKernelGGL(k_to_bf16, dim3(blocks((long long)nw)), dim3(256), 0, 0, s->W[l], s->Wb[l], (int)nw);
+    if (s->WbT[l]) transpose_w(s->W[l], s->WbT[l], outd[l], in[l], 0);
   }
   s->mean = dalloc<float>(s, s->n_out);
   s->stdv = dalloc<float>(s, s->n_out);
@@ -532,6 +601,7 @@ ms_status ms_surrogate_params(ms_surrogate *s, int32_t set, float *W1, float *b1
       if (e == hipSuccess) e = hipMemcpy(s->b[l], hb[l], 4 * outd[l], hipMemcpyHostToDevice);
       if (e == hipSuccess) {
         hipLaunchKernelGGL(k_to_bf16, dim3(blocks((long long)nw)), dim3(256), 0, 0, s->W[l], s->Wb[l], (int)nw);
+        if (s->WbT[l]) transpose_w(s->W[l], s->WbT[l], outd[l], in[l], 0);
         e = hipGetLastError();
       }
     } else {
@@ -773,43 +843,54 @@ ms_status ms_surrogate_train_step(ms_surrogate *s, int32_t n, const float *q, co
   ms_status st = ensure_cap(s, n);
   if (st != MS_OK) return st;
   hipStream_t hs = (hipStream_t)stream;
-  const long long no = (long long)n * s->n_out;
-  hipLaunchKernelGGL(k_targets, dim3(blocks(no)), dim3(256), 0, hs, L, r, s->n_mus, n, s->mean,
-                     s->istd, s->mask, s->T);
   st = forward(s, n, q, false, own_work(s, true), hs);
   if (st != MS_OK) return st;
-  const int nb = blocks(no);
-  hipLaunchKernelGGL(k_loss, dim3(nb), dim3(256), 0, hs, s->Y, s->T, s->mask, n, s->n_out, s->dY,
-                     s->dYb, s->part);
+  // loss, dY (bfloat16) and gb3 = colsum dY (the loss kernel's per-chunk
+  // column sums, then their sum)
+  const int nk = (n + kCS - 1) / kCS, nb = blocks(s->n_out) * nk;
+  hipLaunchKernelGGL(k_loss, dim3(blocks(s->n_out), nk), dim3(256), 0, hs, s->Y, L, r, s->n_mus, n,
+                     s->mean, s->istd, s->mask, s->dYb, s->cpart, s->part);
   if (loss) hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(256), 0, hs, s->part, nb, n, s->n_out, loss);
-  // layer 3: gb3 = colsum dY, gW3[o][j] = sum_p dY[p][o] H2[p][j], dH2 -> dZ2
-  colsum(s, s->dY, n, s->n_out, s->gb[2], hs);
-  hipError_t e = gemm_bf16_splitk(true, false, s->n_out, s->h2, n, s->dYb, s->n_out, s->H2, s->h2,
-                                  s->gW[2], s->h2, s->kwork, hs);
+  hipLaunchKernelGGL(k_colsum, dim3((s->n_out + 63) / 64, 1), dim3(256), 0, hs, s->cpart, nk,
+                     s->n_out, nk, s->gb[2]);
+  // layer 3: gW3[o][j] = sum_p dY[p][o] H2[p][j], dH2 -> dZ2. Each weight
+  // gradient is the forward-shape product of the transposed output gradient
+  // [out][batch] and the transposed layer input [in][batch].
+  hipError_t e = transpose_bf16(s->dYb, n, s->n_out, s->tA, hs);
+  if (e == hipSuccess) e = transpose_bf16(s->H2, n, s->h2, s->tB, hs);
+  if (e == hipSuccess)
+    e = gemm_bf16_splitk(s->n_out, s->h2, n, s->tA, n, s->tB, n, s->gW[2], s->h2,
+                         s->kwork, hs);
   if (e != hipSuccess) return hipst(e, "gemm dW3");
   GemmEpi d2;
   d2.dact = s->Z2;
   d2.c_f32 = s->dZ2;
   d2.c_bf16 = s->dZ2b;
   d2.ldc = s->h2;
-  e = gemm_bf16(false, false, n, s->h2, s->n_out, s->dYb, s->n_out, s->Wb[2], s->h2, d2, hs);
+  e = gemm_bf16(n, s->h2, s->n_out, s->dYb, s->n_out, s->WbT[2], s->n_out, d2, hs);
   if (e != hipSuccess) return hipst(e, "gemm dZ2");
   // layer 2
   colsum(s, s->dZ2, n, s->h2, s->gb[1], hs);
-  e = gemm_bf16_splitk(true, false, s->h2, s->h1, n, s->dZ2b, s->h2, s->H1, s->h1, s->gW[1], s->h1,
-                       s->kwork, hs);
+  e = transpose_bf16(s->dZ2b, n, s->h2, s->tA, hs);
+  if (e == hipSuccess) e = transpose_bf16(s->H1, n, s->h1, s->tB, hs);
+  if (e == hipSuccess)
+    e = gemm_bf16_splitk(s->h2, s->h1, n, s->tA, n, s->tB, n, s->gW[1], s->h1,
+                         s->kwork, hs);
   if (e != hipSuccess) return hipst(e, "gemm dW2");
   GemmEpi d1;
   d1.dact = s->Z1;
   d1.c_f32 = s->dZ1;
   d1.c_bf16 = s->dZ1b;
   d1.ldc = s->h1;
-  e = gemm_bf16(false, false, n, s->h1, s->h2, s->dZ2b, s->h2, s->Wb[1], s->h1, d1, hs);
+  e = gemm_bf16(n, s->h1, s->h2, s->dZ2b, s->h2, s->WbT[1], s->h2, d1, hs);
   if (e != hipSuccess) return hipst(e, "gemm dZ1");
   // layer 1
   colsum(s, s->dZ1, n, s->h1, s->gb[0], hs);
-  e = gemm_bf16_splitk(true, false, s->h1, s->n_in, n, s->dZ1b, s->h1, s->X, s->n_in, s->gW[0],
-                       s->n_in, s->kwork, hs);
+  e = transpose_bf16(s->dZ1b, n, s->h1, s->tA, hs);
+  if (e == hipSuccess) e = transpose_bf16(s->X, n, s->n_in, s->tB, hs);
+  if (e == hipSuccess)
+    e = gemm_bf16_splitk(s->h1, s->n_in, n, s->tA, n, s->tB, n, s->gW[0], s->n_in,
+                         s->kwork, hs);
   if (e != hipSuccess) return hipst(e, "gemm dW1");
   // Adam
   if (lr > 0.0f) {
@@ -820,6 +901,7 @@ ms_status ms_surrogate_train_step(ms_surrogate *s, int32_t n, const float *q, co
       const int nw = in[l] * outd[l];
       hipLaunchKernelGGL(k_adam, dim3(blocks(nw)), dim3(256), 0, hs, s->W[l], s->mW[l], s->vW[l],
                          s->gW[l], nw, lr, b1, b2, eps, c1, c2, s->Wb[l]);
+      if (s->WbT[l]) transpose_w(s->W[l], s->WbT[l], outd[l], in[l], hs);
       hipLaunchKernelGGL(k_adam, dim3(blocks(outd[l])), dim3(256), 0, hs, s->b[l], s->mb[l], s->vb[l],
                          s->gb[l], outd[l], lr, b1, b2, eps, c1, c2, (bf16 *)nullptr);
     }
@@ -936,21 +1018,21 @@ ms_status policy_forward(ms_policy *p, int n, const float *q, const float *qd, d
   e1.act = 1;
   e1.c_bf16 = p->H1;
   e1.ldc = p->h;
-  hipError_t e = gemm_bf16(false, true, n, p->h, p->n_in, p->X, p->n_in, p->Wb[0], p->n_in, e1, st);
+  hipError_t e = gemm_bf16(n, p->h, p->n_in, p->X, p->n_in, p->Wb[0], p->n_in, e1, st);
   if (e != hipSuccess) return hipst(e, "policy gemm 1");
   GemmEpi e2;
   e2.bias = p->b[1];
   e2.act = 1;
   e2.c_bf16 = p->H2;
   e2.ldc = p->h;
-  e = gemm_bf16(false, true, n, p->h, p->h, p->H1, p->h, p->Wb[1], p->h, e2, st);
+  e = gemm_bf16(n, p->h, p->h, p->H1, p->h, p->Wb[1], p->h, e2, st);
   if (e != hipSuccess) return hipst(e, "policy gemm 2");
   GemmEpi e3;
   e3.bias = p->b[2];
   e3.act = 2;
   e3.c_f32 = u;
   e3.ldc = p->n_mus;
-  e = gemm_bf16(false, true, n, p->n_mus, p->h, p->H2, p->h, p->Wb[2], p->h, e3, st);
+  e = gemm_bf16(n, p->n_mus, p->h, p->H2, p->h, p->Wb[2], p->h, e3, st);
   return hipst(e, "policy gemm 3");
 }
 

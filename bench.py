@@ -261,6 +261,9 @@ def main():
         progress("surrogate leg done")
     if not a.no_policy:
         line["policy"] = policy_leg(a, m, gm, sg, dt, dev)
+        if sg is not None:
+            # the same workload with the exact geometry: the surrogate does not pay here
+            line["policy"]["exact_geometry"] = policy_leg(a, m, gm, None, dt, dev)
         progress("policy leg done")
     if not a.no_uneven:
         line["uneven"] = uneven_leg(a, dt, dev)

@@ -435,15 +435,19 @@ def human_net():
     return m, gm, s, o, spans
 
 
-def test_full_size_network_forward_gradients_and_adam(human_net):
+@pytest.mark.parametrize("n", [2048, 2056])
+def test_full_size_network_forward_gradients_and_adam(human_net, n):
     """The whole-body network (74 inputs padded to 80 -> 512 -> 512 -> 2800)
     at batch 2048, so every GEMM runs several M, N and K tiles and the
-    weight gradients run split-K with several slices: forward outputs, the
-    loss, all six gradients and one Adam step against the oracle network
-    with the same bfloat16 rounding points."""
-    m, gm, s, o, spans = human_net
-    n = 2048
-    rng = np.random.default_rng(2048)
+    weight gradients run split-K with several slices, and at 2056, whose
+    last row tile, last 64-row loss chunk and last K slice are ragged:
+    forward outputs, the loss, all six gradients, one Adam step, and the
+    gradients again with the updated weights (the transposed weight copies
+    the backward products read are refreshed by the Adam step), against the
+    oracle network with the same bfloat16 rounding points."""
+    m, gm, _, o, spans = human_net
+    s = ms.Surrogate(gm, hidden=512, seed=41)   # fresh Adam moments for the step below
+    rng = np.random.default_rng(n)
     ps = s.params()
     for k in (1, 3, 5):
         ps[k][:] = rng.normal(size=ps[k].shape) * 0.1
@@ -492,6 +496,16 @@ def test_full_size_network_forward_gradients_and_adam(human_net):
         oracle.adam(w.reshape(-1), mm.reshape(-1), vv.reshape(-1),
                     gg.astype(np.float64).reshape(-1), lr=1e-3, step=1)
         assert np.abs(b - w).max() < 1e-6
+    # gradients at the updated weights
+    s.train_step(_t(qh), _t(t[:, :m["n_mus"]]), _t(t[:, m["n_mus"]:].reshape(n, m["n_mus"], 3)),
+                 lr=0.0, step=2)
+    torch.cuda.synchronize()
+    g2 = s.grads()
+    _, go2 = oracle.mlp_grad(_oracle_params(p1), x, t, np.tile(mask, (n, 1)), bf16=True)
+    pairs = [(g2[0], go2[0].T), (g2[1], go2[1]), (g2[2], go2[2].T), (g2[3], go2[3]),
+             (g2[4], go2[4].T), (g2[5], go2[5])]
+    for k, (a, b) in enumerate(pairs):
+        assert _rel(a, b) < 1e-2, (k, _rel(a, b))
 
 
 def test_full_size_prediction_taken_step_matches_oracle(human_net):

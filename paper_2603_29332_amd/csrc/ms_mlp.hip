@@ -7,7 +7,9 @@
 // -> SiLU(W2 h1 + b2) -> W3 h2 + b3, standardised outputs. Output layout per
 // pose: [L (n_mus) | r (n_mus x 3, the model's span slots)], caller's
 // muscle order. Weights live as float32 masters ([out][in]) with bfloat16
-// copies for the GEMMs; Adam (Kingma & Ba 2015) updates the masters.
+// copies for the GEMMs ([out][in] for the forward, [in][out] for the input
+// gradients of the backward pass); Adam (Kingma & Ba 2015) updates the
+// masters and refreshes both copies.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>

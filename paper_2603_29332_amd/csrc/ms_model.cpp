@@ -563,6 +563,17 @@ ms_status build_tables(const ms_model_desc *d, Tables *t, std::string *msg) {
   t->off_F = t->off_A + 4 * 6 * n;
   t->lds_bytes = off;
 
+  // Geometry-only launches: no contacts, dynamics or mass matrix, so only
+  // the state, the frames, the subspaces and the kinematics' V and A rows.
+  off = 0;
+  t->geo_q = take(4 * nq);
+  t->geo_qd = take(4 * nv);
+  t->geo_R = take(4 * 12 * n);
+  t->geo_S = take(4 * 6 * nv);
+  t->geo_V = take(4 * 6 * 2 * n);
+  t->geo_bytes = off;
+  t->geo_lt_words = std::min((int)t->lt.size(), (t->lt_subb_start + 3) / 4 * 4);
+
   // The split schedule's three kernels (one env per wavefront for the
   // kinematics/dynamics and the factorisation kernels, one env per
   // 256-thread workgroup for the muscle kernel), each with its own layout.

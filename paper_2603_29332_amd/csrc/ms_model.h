@@ -118,6 +118,11 @@ struct Tables {
       off_A = 0, off_F = 0, off_con = 0, off_rhs = 0, off_H = 0, off_x = 0,
       off_scr = 0, off_flag = 0, lds_bytes = 0;
   SplitLayout split;
+  // geometry-only launches (exact lengths and moment arms of given poses):
+  // state, node frames, motion subspaces and the kinematics' velocity and
+  // acceleration rows, per env; the tree schedule from the table's first
+  // geo_lt_words words
+  int geo_q = 0, geo_qd = 0, geo_R = 0, geo_S = 0, geo_V = 0, geo_bytes = 0, geo_lt_words = 0;
   int n_levels_dof = 0;
 };
 

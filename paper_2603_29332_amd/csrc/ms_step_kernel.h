@@ -789,11 +789,13 @@ __device__ __forceinline__ void stage_muscles(const KModel &M, const KRun &Rn, c
   for (int m = T.t; exact && m < nm; m += T.n) {
     float r3[3], Ld;
     const float L = muscle_geometry<NVIA>(M, m, M.grp_nvia[m >> 6], Rl, Pl, Sl, qd, O, r3, Ld);
-    mr[3 * m] = r3[0];
-    mr[3 * m + 1] = r3[1];
-    mr[3 * m + 2] = r3[2];
-    mF[m] = L;
-    mc[m] = Ld;
+    if (!GEOM) {   // the geometry-only layout has no muscle scratch
+      mr[3 * m] = r3[0];
+      mr[3 * m + 1] = r3[1];
+      mr[3 * m + 2] = r3[2];
+      mF[m] = L;
+      mc[m] = Ld;
+    }
     if (stages) {
       const size_t o = (size_t)env * nm + M.mus_ext[m];
       Rn.o_L[o] = L;
@@ -1377,10 +1379,48 @@ hipError_t launch_k(const Tables &t, const KModel &k, const KRun &r, int n_env, 
   const bool geom = r.stages == 2, surr = r.geomY != nullptr;
   const bool coupled = k.n_eq > 0 && !geom;
   if (coupled && surr) return hipErrorNotSupported;  // the split schedule steps these
-  const int W = r.env_per_wg > 0 ? r.env_per_wg : default_env_per_wg(t);
-  const size_t lds = t.lt.size() * 4 + (size_t)W * t.lds_bytes;
-  const void *fn = geom ? (const void *)&k_geometry<MPL, NVIA>
-                   : surr ? (const void *)&k_step_surrogate<MPL, NVIA>
+  int W = r.env_per_wg > 0 ? r.env_per_wg : default_env_per_wg(t);
+  size_t lds = t.lt.size() * 4 + (size_t)W * t.lds_bytes;
+  if (geom) {
+    // geometry only: the compact per-env layout and the tree schedule's part
+    // of the table, so several times more envs stay resident per CU
+    KModel g = k;
+    g.off_q = t.geo_q;
+    g.off_qd = t.geo_qd;
+    g.off_R = t.geo_R;
+    g.off_P = t.geo_R + 36;
+    g.off_S = t.geo_S;
+    g.off_V = g.off_scr = t.geo_V;
+    g.off_A = g.off_F = t.geo_V + 4 * 6 * k.n_node;
+    g.off_con = g.off_rhs = g.off_x = g.off_H = g.off_flag = 0;   // not read
+    g.lds_env = t.geo_bytes;
+    g.lt_words = t.geo_lt_words;
+    const void *fg = (const void *)&k_geometry<MPL, NVIA>;
+    int best = 0;
+    for (int w = 1; w <= 4; w *= 2) {
+      const size_t l = (size_t)g.lt_words * 4 + (size_t)w * t.geo_bytes;
+      if (l > 160 * 1024) break;
+      if (l > 65536 && hipFuncSetAttribute(fg, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)l) != hipSuccess)
+        break;
+      int nb = 0;
+      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fg, 64 * w, l) != hipSuccess) break;
+      if (nb * w >= best) {
+        best = nb * w;
+        W = w;
+        lds = l;
+      }
+    }
+    if (best == 0) return hipErrorInvalidConfiguration;
+    if (lds > 65536) {
+      hipError_t e = hipFuncSetAttribute(fg, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL((k_geometry<MPL, NVIA>), dim3((n_env + W - 1) / W), dim3(64 * W), lds, st,
+                       g, r, n_steps);
+    return hipGetLastError();
+  }
+  const void *fn = surr ? (const void *)&k_step_surrogate<MPL, NVIA>
                    : coupled ? (const void *)&k_step_coupled<MPL, NVIA>
                              : (const void *)&k_step<MPL, NVIA>;
   if (lds > 65536) {
@@ -1388,9 +1428,7 @@ hipError_t launch_k(const Tables &t, const KModel &k, const KRun &r, int n_env, 
     if (e != hipSuccess) return e;
   }
   const dim3 grid((n_env + W - 1) / W), block(64 * W);
-  if (geom)
-    hipLaunchKernelGGL((k_geometry<MPL, NVIA>), grid, block, lds, st, k, r, n_steps);
-  else if (surr)
+  if (surr)
     hipLaunchKernelGGL((k_step_surrogate<MPL, NVIA>), grid, block, lds, st, k, r, n_steps);
   else if (coupled)
     hipLaunchKernelGGL((k_step_coupled<MPL, NVIA>), grid, block, lds, st, k, r, n_steps);

@@ -97,20 +97,22 @@ __global__ void k_pack(const float *q, int nq, const int *hq, const float *lo, c
 
 // poses uniform in the surrogate's box: hinge i of pose p from
 // SplitMix64(SplitMix64(seed ^ (offset + p)) ^ i); the root at the origin.
+// One thread per pose coordinate j, which looks up the input that drives it
+// (hq maps inputs to coordinates, at most one input per coordinate).
 __global__ void k_sample(int n, int nq, int free_root, const int *hq, const float *lo, const float *hi,
                          int n_in, unsigned long long seed, long long offset, float *q) {
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= n) return;
-  float *o = q + (size_t)p * nq;
-  for (int j = 0; j < nq; ++j) o[j] = 0.0f;
-  if (free_root) o[3] = 1.0f;
-  const unsigned long long key = splitmix64(seed ^ (unsigned long long)(offset + p));
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long long)n * nq) return;
+  const int p = (int)(t / nq), j = (int)(t % nq);
+  float v = free_root && j == 3 ? 1.0f : 0.0f;
   for (int i = 0; i < n_in; ++i) {
-    const int j = hq[i];
-    if (j < 0) continue;
+    if (hq[i] != j) continue;
+    const unsigned long long key = splitmix64(seed ^ (unsigned long long)(offset + p));
     const float u = unit24(splitmix64(key ^ (unsigned long long)i));
-    o[j] = lo[i] + (hi[i] - lo[i]) * u;
+    v = lo[i] + (hi[i] - lo[i]) * u;
+    break;
   }
+  q[t] = v;
 }
 
 // Rows per chunk of the column sums and of the loss kernel.
@@ -644,7 +646,7 @@ ms_status ms_surrogate_set_norm(ms_surrogate *s, const float *mean, const float 
 ms_status ms_surrogate_sample(ms_surrogate *s, int32_t n, uint64_t seed, int64_t offset, float *q,
                               void *stream) {
   if (!s || n <= 0 || !q) return sfail(MS_E_ARG, "bad arguments");
-  hipLaunchKernelGGL(k_sample, dim3(blocks(n)), dim3(256), 0, (hipStream_t)stream, n, s->nq,
+  hipLaunchKernelGGL(k_sample, dim3(blocks((long long)n * s->nq)), dim3(256), 0, (hipStream_t)stream, n, s->nq,
                      s->free_root, s->hinge_q, s->lo, s->hi, s->n_in, (unsigned long long)seed,
                      (long long)offset, q);
   return hipst(hipGetLastError(), "sample");
@@ -723,7 +725,7 @@ ms_status ms_surrogate_train(ms_model *m, ms_surrogate *s, const ms_train_cfg *c
   hipStream_t hs = (hipStream_t)stream;
   const int B = c->batch, no = s->n_out;
   auto labels = [&](int n, unsigned long long seed, long long offset) -> ms_status {
-    hipLaunchKernelGGL(k_sample, dim3(blocks(n)), dim3(256), 0, hs, n, s->nq, s->free_root,
+    hipLaunchKernelGGL(k_sample, dim3(blocks((long long)n * s->nq)), dim3(256), 0, hs, n, s->nq, s->free_root,
                        s->hinge_q, s->lo, s->hi, s->n_in, seed, offset, s->Qb);
     if (ms_geometry(m, n, s->Qb, s->Lb, s->Rb, hs) != MS_OK)
       return sfail(MS_E_HIP, std::string("labels: ") + ms_last_error());

@@ -367,7 +367,8 @@ ms_status ms_surrogate_forward_noalloc(ms_surrogate *s, int32_t n, const float *
                                        float *L, float *r, void *stream);
 /* Largest n ms_surrogate_forward_noalloc accepts for this network. */
 int32_t ms_surrogate_noalloc_max(const ms_surrogate *s);
-/* one training step on n poses (n a multiple of 8) with exact labels
+/* one training step on n poses (n a multiple of 8, at most 2^20: the
+ * weight gradients take the batch as a row length) with exact labels
  * L, r (device, as from ms_geometry): loss = mean over (pose, output) of
  * mask (y - t)^2 on standardised targets t, written to *loss (device) if
  * non-NULL; then an Adam step with learning rate lr at step count

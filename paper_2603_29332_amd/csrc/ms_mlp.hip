@@ -713,10 +713,11 @@ int32_t ms_surrogate_noalloc_max(const ms_surrogate *s) {
 ms_status ms_surrogate_train(ms_model *m, ms_surrogate *s, const ms_train_cfg *c, void *stream) {
   s_err.clear();
   if (!m || !s || !c) return sfail(MS_E_ARG, "NULL argument");
-  if (c->batch <= 0 || c->batch % 8 || c->iters < 0 || c->n_samples <= 0 || c->step0 < 0 ||
-      c->norm_samples < 0 || !(c->lr0 >= 0.0f) || !(c->lr1 >= 0.0f))
-    return sfail(MS_E_ARG, "bad training configuration (batch a positive multiple of 8, iters, "
-                           "n_samples > 0, step0 >= 0, norm_samples >= 0, lr >= 0)");
+  if (c->batch <= 0 || c->batch % 8 || c->batch > (1 << 20) || c->iters < 0 ||
+      c->n_samples <= 0 || c->step0 < 0 || c->norm_samples < 0 || !(c->lr0 >= 0.0f) ||
+      !(c->lr1 >= 0.0f))
+    return sfail(MS_E_ARG, "bad training configuration (batch a positive multiple of 8 up to "
+                           "2^20, iters, n_samples > 0, step0 >= 0, norm_samples >= 0, lr >= 0)");
   ms_model_info info;
   if (ms_model_info_get(m, &info) != MS_OK || info.n_mus != s->n_mus || info.nq != s->nq)
     return sfail(MS_E_ARG, "surrogate does not belong to this model");
@@ -842,8 +843,9 @@ ms_status ms_surrogate_train_step(ms_surrogate *s, int32_t n, const float *q, co
                                   const float *r, float lr, int32_t step, float *loss,
                                   void *stream) {
   s_err.clear();
-  if (!s || n <= 0 || n % 8 || !q || !L || !r || step < 1)
-    return sfail(MS_E_ARG, "bad arguments (batch must be a positive multiple of 8, step >= 1)");
+  if (!s || n <= 0 || n % 8 || n > (1 << 20) || !q || !L || !r || step < 1)
+    return sfail(MS_E_ARG,
+                 "bad arguments (batch must be a positive multiple of 8, at most 2^20; step >= 1)");
   ms_status st = ensure_cap(s, n);
   if (st != MS_OK) return st;
   hipStream_t hs = (hipStream_t)stream;

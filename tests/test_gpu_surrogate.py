@@ -653,3 +653,19 @@ def test_train_equals_its_steps_taken_one_by_one():
         assert np.array_equal(x, y)
     lv = loss.cpu().numpy()
     assert np.isfinite(lv).all() and lv[-1] < lv[0]
+
+
+def test_train_step_argument_bounds(setup):
+    """Batches that are not a positive multiple of 8 or exceed 2^20 (the
+    weight gradients take the batch as a row length), and step 0, are
+    refused with MS_E_ARG before anything is read or launched."""
+    m, gm, s, o = setup
+    q = torch.zeros(8, m["nq"], device=DEV)
+    L = torch.zeros(8, m["n_mus"], device=DEV)
+    r = torch.zeros(8, m["n_mus"], 3, device=DEV)
+    for n, step in ((0, 1), (12, 1), ((1 << 20) + 8, 1), (8, 0)):
+        rc = ms.lib().ms_surrogate_train_step(s.h, n, ms._dp(q), ms._dp(L), ms._dp(r), 0.0, step,
+                                              None, None)
+        assert rc == -1, (n, step, rc)
+    s.train_step(q, L, r, 0.0, 1)   # the smallest valid batch still runs
+    torch.cuda.synchronize()

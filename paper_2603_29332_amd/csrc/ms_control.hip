@@ -48,9 +48,15 @@ struct ms_controller {
   float *log_std = nullptr; // device [n_mus]
   Net pi, flow, disc;
   ms::bf16 *Wat = nullptr;  // flow layer 1, (action, time) block [hidden][n_at]
+  // per control step: the time column's contribution to flow layer 1 at
+  // each flow step ([flow_steps][hidden]) and the output bias times the
+  // flow step size ([n_mus])
+  float *TB = nullptr, *HB3 = nullptr;
   // workspace for up to cap envs
   int cap = 0;
   ms::bf16 *X = nullptr, *H1 = nullptr, *H2 = nullptr, *XA = nullptr, *XD = nullptr;
+  // A: the flow's state [cap][n_at] (rows padded like XA, whose bfloat16
+  // copy the flow's output layer writes beside it)
   float *P = nullptr, *A = nullptr, *PSI = nullptr, *U = nullptr, *Z = nullptr, *qref = nullptr;
   float *kpos = nullptr, *krot = nullptr, *rpos = nullptr, *rrot = nullptr;
   std::vector<void *> owned;
@@ -205,9 +211,10 @@ __global__ void k_ctl_obs(int n, int nq, int nv, int free_root, int n_mus, int n
 // a0 = mu + exp(log_std) xi, xi a standard normal by the Box-Muller
 // transform of two 24-bit uniforms u1 = (i1 + 1/2) 2^-24, u2 = (i2 + 1/2)
 // 2^-24 from z = SplitMix64(K ^ m), i1 = z >> 40, i2 = (z >> 16) & 0xFFFFFF,
-// K = SplitMix64(SplitMix64(seed ^ env) ^ step): xi = sqrt(-2 ln u1) cos(2 pi u2)
+// K = SplitMix64(SplitMix64(seed ^ env) ^ step): xi = sqrt(-2 ln u1) cos(2 pi u2);
+// a has row stride lda
 __global__ void k_gauss(int n, int n_mus, const float *mu, const float *log_std,
-                        unsigned long long seed, long long env0, long long step, float *a) {
+                        unsigned long long seed, long long env0, long long step, float *a, int lda) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= (long long)n * n_mus) return;
   const int p = (int)(i / n_mus), mx = (int)(i % n_mus);
@@ -217,28 +224,40 @@ __global__ void k_gauss(int n, int n_mus, const float *mu, const float *log_std,
   const float u1 = ((float)(unsigned)(z >> 40) + 0.5f) * 5.9604644775390625e-8f;
   const float u2 = ((float)(unsigned)((z >> 16) & 0xFFFFFFull) + 0.5f) * 5.9604644775390625e-8f;
   const float xi = sqrtf(-2.0f * logf(u1)) * cosf(6.28318530717958647692f * u2);
-  a[i] = mu[i] + expf(log_std[mx]) * xi;
+  a[(size_t)p * lda + mx] = mu[i] + expf(log_std[mx]) * xi;
 }
 
-// (action, time) block of the flow network's input: [a, t, 0 ...] (n_at)
-__global__ void k_pack_at(int n, int n_mus, int n_at, const float *a, float t, bf16 *XA) {
+// The flow network's (action, time) input block XA = [a, 0, 0 ...] (n_at):
+// the time column stays zero, its contribution enters flow layer 1 as a
+// per-step bias (k_flow_bias)
+__global__ void k_pack_at(int n, int n_mus, int n_at, const float *a, bf16 *XA) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= (long long)n * n_at) return;
-  const int p = (int)(i / n_at), c = (int)(i % n_at);
-  const float v = c < n_mus ? a[(size_t)p * n_mus + c] : c == n_mus ? t : 0.0f;
-  XA[i] = __float2bfloat16(v);
+  const int c = (int)(i % n_at);
+  XA[i] = __float2bfloat16(c < n_mus ? a[i] : 0.0f);
 }
 
-// a += h psi (one explicit Euler step of the flow)
-__global__ void k_euler(long long n, float h, const float *psi, float *a) {
-  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) a[i] = a[i] + h * psi[i];
+// TB[k][j] = bf16(t_k) Wat[j][n_mus], t_k = k h: the time column of flow
+// layer 1 at flow step k (the product the matrix core would form from the
+// bfloat16 time input); HB3[c] = h b3[c], so that the output layer's
+// epilogue h acc + h b3 + a is one explicit Euler step a + h psi
+__global__ void k_flow_bias(int flow_steps, int hidden, int n_mus, int n_at, float h,
+                            const bf16 *Wat, const float *b3, float *TB, float *HB3) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < flow_steps * hidden) {
+    const int k = i / hidden, j = i % hidden;
+    const float tk = __bfloat162float(__float2bfloat16((float)k * h));
+    TB[i] = tk * __bfloat162float(Wat[(size_t)j * n_at + n_mus]);
+  }
+  if (i < n_mus) HB3[i] = h * b3[i];
 }
 
-__global__ void k_clamp01(long long n, const float *a, float *u, float *u_out) {
+// u = clamp(a, 0, 1) (a with row stride lda, u contiguous)
+__global__ void k_clamp01(int n, int n_mus, int lda, const float *a, float *u, float *u_out) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const float v = fminf(fmaxf(a[i], 0.0f), 1.0f);
+  if (i >= (long long)n * n_mus) return;
+  const int p = (int)(i / n_mus), c = (int)(i % n_mus);
+  const float v = fminf(fmaxf(a[(size_t)p * lda + c], 0.0f), 1.0f);
   u[i] = v;
   if (u_out) u_out[i] = v;
 }
@@ -338,7 +357,7 @@ ms_status ctl_cap(ms_controller *c, int n) {
       {(void **)&c->X, B * c->n_in * 2},      {(void **)&c->H1, B * c->hidden * 2},
       {(void **)&c->H2, B * c->hidden * 2},   {(void **)&c->XA, B * c->n_at * 2},
       {(void **)&c->XD, B * c->n_din * 2},    {(void **)&c->P, B * c->hidden * 4},
-      {(void **)&c->A, B * c->n_mus * 4},     {(void **)&c->PSI, B * c->n_mus * 4},
+      {(void **)&c->A, B * c->n_at * 4},      {(void **)&c->PSI, B * c->n_mus * 4},
       {(void **)&c->U, B * c->n_mus * 4},     {(void **)&c->Z, B * 4},
       {(void **)&c->qref, B * c->nq * 4},     {(void **)&c->kpos, B * c->n_key * 12},
       {(void **)&c->krot, B * c->n_key * 36}, {(void **)&c->rpos, B * c->n_key * 12},
@@ -425,6 +444,9 @@ ms_status ms_controller_create(ms_model *m, const ms_controller_desc *d, ms_cont
   // its first layer is kept as the two column blocks
   ok = ok && make_net(c, c->flow, c->n_in, c->n_obs, c->hidden, t.n_mus, d->flow_seed);
   ok = ok && make_net(c, c->disc, c->n_din, c->n_h + 3 * c->n_key, c->hidden, 1, d->disc_seed);
+  c->TB = ok ? calloc_dev<float>(c, (size_t)std::max(c->flow_steps, 1) * c->hidden) : nullptr;
+  c->HB3 = ok ? calloc_dev<float>(c, (size_t)t.n_mus) : nullptr;
+  ok = ok && c->TB && c->HB3;
   float *wat = ok ? calloc_dev<float>(c, (size_t)c->hidden * c->n_at) : nullptr;
   c->Wat = ok ? calloc_dev<bf16>(c, (size_t)c->hidden * c->n_at) : nullptr;
   hipError_t e = hipSuccess;
@@ -563,9 +585,10 @@ ms_status ms_controller_step(ms_controller *c, int32_t n_env, float *q, float *q
     if (e == hipSuccess) e = output_layer(c, c->pi, n, c->PSI, st);  // mean, in PSI
     if (e != hipSuccess) return chip(e, "initial sampler");
     hipLaunchKernelGGL(k_gauss, dim3(blocks(nmu)), dim3(256), 0, st, n, nm, c->PSI, c->log_std,
-                       c->noise_seed, 0ll, (long long)ctl_step, c->A);
+                       c->noise_seed, 0ll, (long long)ctl_step, c->A, c->n_at);
     if (out && out->a0)
-      (void)hipMemcpyAsync(out->a0, c->A, 4 * (size_t)nmu, hipMemcpyDeviceToDevice, st);
+      (void)hipMemcpy2DAsync(out->a0, 4 * (size_t)nm, c->A, 4 * (size_t)c->n_at, 4 * (size_t)nm,
+                             n, hipMemcpyDeviceToDevice, st);
     // observation block of the flow's first layer, once: P = W1_s s + b1
     GemmEpi ep;
     ep.bias = c->flow.b[0];
@@ -573,12 +596,20 @@ ms_status ms_controller_step(ms_controller *c, int32_t n_env, float *q, float *q
     ep.ldc = c->hidden;
     e = gemm_bf16(n, c->hidden, c->n_in, c->X, c->n_in, c->flow.Wb[0], c->n_in, ep, st);
     if (e != hipSuccess) return chip(e, "flow layer 1");
-    for (int k = 0; k < c->flow_steps; ++k) {
-      const float tk = (float)k * c->flow_dt;
+    if (c->flow_steps > 0) {
+      const int nb = std::max(c->flow_steps * c->hidden, nm);
+      hipLaunchKernelGGL(k_flow_bias, dim3(blocks(nb)), dim3(256), 0, st, c->flow_steps, c->hidden,
+                         nm, c->n_at, c->flow_dt, c->Wat, c->flow.b[2], c->TB, c->HB3);
       hipLaunchKernelGGL(k_pack_at, dim3(blocks((long long)n * c->n_at)), dim3(256), 0, st, n, nm,
-                         c->n_at, c->A, tk, c->XA);
+                         c->n_at, c->A, c->XA);
+    }
+    for (int k = 0; k < c->flow_steps; ++k) {
+      // psi(a, t_k, s) through the flow network; its output layer's
+      // epilogue takes the Euler step a += h psi in place and writes the
+      // next step's bfloat16 input beside it
       GemmEpi e1;
       e1.addc = c->P;
+      e1.bias = c->TB + (size_t)k * c->hidden;
       e1.act = 1;
       e1.c_bf16 = c->H1;
       e1.ldc = c->hidden;
@@ -591,11 +622,18 @@ ms_status ms_controller_step(ms_controller *c, int32_t n_env, float *q, float *q
       if (e == hipSuccess)
         e = gemm_bf16(n, c->hidden, c->hidden, c->H1, c->hidden, c->flow.Wb[1],
                       c->hidden, e2, st);
-      if (e == hipSuccess) e = output_layer(c, c->flow, n, c->PSI, st);
+      GemmEpi e3;
+      e3.alpha = c->flow_dt;
+      e3.bias = c->HB3;
+      e3.addc = c->A;
+      e3.c_f32 = c->A;
+      e3.c_bf16 = c->XA;
+      e3.ldc = c->n_at;
+      if (e == hipSuccess)
+        e = gemm_bf16(n, nm, c->hidden, c->H2, c->hidden, c->flow.Wb[2], c->hidden, e3, st);
       if (e != hipSuccess) return chip(e, "flow step");
-      hipLaunchKernelGGL(k_euler, dim3(blocks(nmu)), dim3(256), 0, st, nmu, c->flow_dt, c->PSI, c->A);
     }
-    hipLaunchKernelGGL(k_clamp01, dim3(blocks(nmu)), dim3(256), 0, st, nmu, c->A, c->U,
+    hipLaunchKernelGGL(k_clamp01, dim3(blocks(nmu)), dim3(256), 0, st, n, nm, c->n_at, c->A, c->U,
                        out ? out->u : nullptr);
     u = c->U;
   }

@@ -17,6 +17,7 @@
 #define MS_NT0 128, 128, 4, 4
 #define MS_NT1 64, 64, 2, 4
 #define MS_NT2 128, 64, 4, 2
+#define MS_NT3 32, 64, 1, 4
 #endif
 
 namespace ms {
@@ -275,19 +276,24 @@ int cu_count() {
 }
 }  // namespace
 
-// Tile of a product (measured on MI355X): 128 x 128 with 16 wavefronts
-// when it still gives every CU two workgroups and the epilogue is plain
-// (bias, activation, one output); 128 x 64 with 8 wavefronts for long K
-// (at least 2048) when that still gives every CU a workgroup; otherwise
-// 64 x 64 with 8 wavefronts, which is faster for narrow outputs and for the
-// de-standardising, column-split epilogue (the 16-wavefront epilogue then
-// doubles its time).
+// Tile of a product (measured on MI355X):
+// - 128 x 128 with 16 wavefronts when that gives every CU two workgroups
+//   and the epilogue is plain (bias, activation, one output);
+// - 128 x 64 with 8 wavefronts for long K (at least 2048) when that still
+//   gives every CU two workgroups;
+// - 32 x 64 with 4 wavefronts when 64 x 64 tiles would not give every CU
+//   two workgroups (small batches, narrow outputs);
+// - otherwise 64 x 64 with 8 wavefronts, which is also faster for the
+//   de-standardising, column-split epilogue (the 16-wavefront epilogue then
+//   doubles its time).
 int gemm_nt_tile(int M, int N, int K, const GemmEpi &epi) {
   const int cus = cu_count();
   const long long big = (long long)((M + 127) / 128) * ((N + 127) / 128);
   const long long tall = (long long)((M + 127) / 128) * ((N + 63) / 64);
+  const long long mid = (long long)((M + 63) / 64) * ((N + 63) / 64);
   if (big >= 2 * cus && !epi.scale && !epi.c2) return 0;
-  if (K >= 2048 && tall >= cus) return 2;
+  if (K >= 2048 && tall >= 2 * cus) return 2;
+  if (mid < 2 * cus) return 3;
   return 1;
 }
 
@@ -321,6 +327,7 @@ hipError_t gemm_bf16(int M, int N, int K, const bf16 *A, int lda, const bf16 *B,
   switch (gemm_nt_tile(M, N, K, epi)) {
     case 0: launch_nt<MS_NT0>(M, N, K, A, lda, B, ldb, epi, st); break;
     case 2: launch_nt<MS_NT2>(M, N, K, A, lda, B, ldb, epi, st); break;
+    case 3: launch_nt<MS_NT3>(M, N, K, A, lda, B, ldb, epi, st); break;
     default: launch_nt<MS_NT1>(M, N, K, A, lda, B, ldb, epi, st);
   }
   return hipGetLastError();

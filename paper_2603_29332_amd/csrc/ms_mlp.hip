@@ -37,6 +37,7 @@ struct ms_surrogate {
   float *mean = nullptr, *stdv = nullptr, *istd = nullptr, *mask = nullptr;
   float *lo = nullptr, *hi = nullptr;
   int *hinge_q = nullptr;  // q index of each input (-1 = padding)
+  int *q_input = nullptr;  // input driving each q index (-1: none)
   // workspace for up to cap poses
   int cap = 0;
   ms::bf16 *X = nullptr, *H1 = nullptr, *H2 = nullptr, *dYb = nullptr, *dZ2b = nullptr,
@@ -97,20 +98,16 @@ __global__ void k_pack(const float *q, int nq, const int *hq, const float *lo, c
 
 // poses uniform in the surrogate's box: hinge i of pose p from
 // SplitMix64(SplitMix64(seed ^ (offset + p)) ^ i); the root at the origin.
-// One thread per pose coordinate j, which looks up the input that drives it
-// (hq maps inputs to coordinates, at most one input per coordinate).
-__global__ void k_sample(int n, int nq, int free_root, const int *hq, const float *lo, const float *hi,
-                         int n_in, unsigned long long seed, long long offset, float *q) {
+// One thread per pose coordinate j; qi[j] is the input that drives it.
+__global__ void k_sample(int n, int nq, int free_root, const int *qi, const float *lo,
+                         const float *hi, unsigned long long seed, long long offset, float *q) {
   const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= (long long)n * nq) return;
-  const int p = (int)(t / nq), j = (int)(t % nq);
+  const int p = (int)(t / nq), j = (int)(t % nq), i = qi[j];
   float v = free_root && j == 3 ? 1.0f : 0.0f;
-  for (int i = 0; i < n_in; ++i) {
-    if (hq[i] != j) continue;
+  if (i >= 0) {
     const unsigned long long key = splitmix64(seed ^ (unsigned long long)(offset + p));
-    const float u = unit24(splitmix64(key ^ (unsigned long long)i));
-    v = lo[i] + (hi[i] - lo[i]) * u;
-    break;
+    v = lo[i] + (hi[i] - lo[i]) * unit24(splitmix64(key ^ (unsigned long long)i));
   }
   q[t] = v;
 }
@@ -545,7 +542,9 @@ ms_status ms_surrogate_create(const ms_model *m, int32_t hidden, uint64_t seed, 
   s->lo = dalloc<float>(s, s->n_in);
   s->hi = dalloc<float>(s, s->n_in);
   s->hinge_q = dalloc<int>(s, s->n_in);
-  if (!s->mean || !s->stdv || !s->istd || !s->mask || !s->lo || !s->hi || !s->hinge_q) {
+  s->q_input = dalloc<int>(s, s->nq);
+  if (!s->mean || !s->stdv || !s->istd || !s->mask || !s->lo || !s->hi || !s->hinge_q ||
+      !s->q_input) {
     ms_surrogate_destroy(s);
     return sfail(MS_E_ALLOC, "surrogate allocation failed");
   }
@@ -561,6 +560,10 @@ ms_status ms_surrogate_create(const ms_model *m, int32_t hidden, uint64_t seed, 
   if (e == hipSuccess) e = hipMemcpy(s->lo, lo.data(), 4 * s->n_in, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(s->hi, hi.data(), 4 * s->n_in, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(s->hinge_q, hq.data(), 4 * s->n_in, hipMemcpyHostToDevice);
+  std::vector<int> qi(s->nq, -1);
+  for (int i = 0; i < s->n_in; ++i)
+    if (hq[i] >= 0) qi[hq[i]] = i;
+  if (e == hipSuccess) e = hipMemcpy(s->q_input, qi.data(), 4 * s->nq, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipDeviceSynchronize();
   if (e != hipSuccess) {
     ms_surrogate_destroy(s);
@@ -647,7 +650,7 @@ ms_status ms_surrogate_sample(ms_surrogate *s, int32_t n, uint64_t seed, int64_t
                               void *stream) {
   if (!s || n <= 0 || !q) return sfail(MS_E_ARG, "bad arguments");
   hipLaunchKernelGGL(k_sample, dim3(blocks((long long)n * s->nq)), dim3(256), 0, (hipStream_t)stream, n, s->nq,
-                     s->free_root, s->hinge_q, s->lo, s->hi, s->n_in, (unsigned long long)seed,
+                     s->free_root, s->q_input, s->lo, s->hi, (unsigned long long)seed,
                      (long long)offset, q);
   return hipst(hipGetLastError(), "sample");
 }
@@ -727,7 +730,7 @@ ms_status ms_surrogate_train(ms_model *m, ms_surrogate *s, const ms_train_cfg *c
   const int B = c->batch, no = s->n_out;
   auto labels = [&](int n, unsigned long long seed, long long offset) -> ms_status {
     hipLaunchKernelGGL(k_sample, dim3(blocks((long long)n * s->nq)), dim3(256), 0, hs, n, s->nq, s->free_root,
-                       s->hinge_q, s->lo, s->hi, s->n_in, seed, offset, s->Qb);
+                       s->q_input, s->lo, s->hi, seed, offset, s->Qb);
     if (ms_geometry(m, n, s->Qb, s->Lb, s->Rb, hs) != MS_OK)
       return sfail(MS_E_HIP, std::string("labels: ") + ms_last_error());
     return MS_OK;

@@ -125,13 +125,19 @@ __global__ void k_ref_pose(int n, int nq, const float *q, const int *q_hinge,
   qref[i] = h < 0 ? q[i] : ref_hinge(seed, env0 + p, h, t);
 }
 
-// World position and orientation of the key nodes of n poses (one
-// wavefront per pose, forward kinematics of the step).
-__global__ __launch_bounds__(64) void k_key_frames(KModel M, int n, const float *qs, const int *keys,
-                                                   int n_key, float *xpos, float *xrot) {
+// World position and orientation of the key nodes of two sets of n poses
+// (the state and its reference pose), one wavefront per pose, forward
+// kinematics of the step: workgroup b < n takes pose b of set a, the others
+// pose b - n of set b.
+__global__ __launch_bounds__(64) void k_key_frames(KModel M, int n, const int *keys, int n_key,
+                                                   const float *qa, float *xpos_a, float *xrot_a,
+                                                   const float *qb, float *xpos_b, float *xrot_b) {
   extern __shared__ __align__(16) unsigned char lds_k[];
-  const int p = blockIdx.x, lane = threadIdx.x;
+  const bool second = (int)blockIdx.x >= n;
+  const int p = second ? blockIdx.x - n : blockIdx.x, lane = threadIdx.x;
   if (p >= n) return;
+  const float *qs = second ? qb : qa;
+  float *xpos = second ? xpos_b : xpos_a, *xrot = second ? xrot_b : xrot_a;
   const int nq = M.nq, nv = M.nv, nn = M.n_node;
   float *Rl = (float *)lds_k;
   float *Sl = Rl + 12 * nn;
@@ -377,12 +383,13 @@ ms_status ctl_cap(ms_controller *c, int n) {
   return MS_OK;
 }
 
-hipError_t key_frames(const ms_controller *c, int n, const float *q, float *pos, float *rot,
-                      hipStream_t st) {
+// key frames of the state q (into kpos, krot) and of the reference pose
+// qref (into rpos, rrot), one launch
+hipError_t key_frames(const ms_controller *c, int n, const float *q, hipStream_t st) {
   const KModel &M = c->m->k;
   const size_t lds = 4 * (size_t)(12 * M.n_node + 6 * M.nv + 12 * M.n_node + M.nq + M.nv);
-  hipLaunchKernelGGL(k_key_frames, dim3(n), dim3(64), lds, st, M, n, q, c->key_node, c->n_key,
-                     pos, rot);
+  hipLaunchKernelGGL(k_key_frames, dim3(2 * n), dim3(64), lds, st, M, n, c->key_node, c->n_key, q,
+                     c->kpos, c->krot, (const float *)c->qref, c->rpos, c->rrot);
   return hipGetLastError();
 }
 
@@ -572,8 +579,7 @@ ms_status ms_controller_step(ms_controller *c, int32_t n_env, float *q, float *q
   // 1. observation at time t
   hipLaunchKernelGGL(k_ref_pose, dim3(blocks((long long)n * c->nq)), dim3(256), 0, st, n, c->nq, q,
                      c->q_hinge, c->ref_seed, 0ll, (float)t, c->qref);
-  hipError_t e = key_frames(c, n, q, c->kpos, c->krot, st);
-  if (e == hipSuccess) e = key_frames(c, n, c->qref, c->rpos, c->rrot, st);
+  hipError_t e = key_frames(c, n, q, st);
   if (e != hipSuccess) return chip(e, "key frames");
   hipLaunchKernelGGL(k_ctl_obs, dim3(blocks((long long)n * c->n_in)), dim3(256), 0, st, n, c->nq,
                      c->nv, c->free_root, nm, c->n_key, c->n_h, c->n_obs, c->n_in, q, qd, c->kpos,
@@ -661,8 +667,7 @@ ms_status ms_controller_step(ms_controller *c, int32_t n_env, float *q, float *q
   const float t1 = (float)(t + (double)c->n_sub * opts->dt);
   hipLaunchKernelGGL(k_ref_pose, dim3(blocks((long long)n * c->nq)), dim3(256), 0, st, n, c->nq, q,
                      c->q_hinge, c->ref_seed, 0ll, t1, c->qref);
-  e = key_frames(c, n, q, c->kpos, c->krot, st);
-  if (e == hipSuccess) e = key_frames(c, n, c->qref, c->rpos, c->rrot, st);
+  e = key_frames(c, n, q, st);
   if (e != hipSuccess) return chip(e, "key frames");
   hipLaunchKernelGGL(k_delta, dim3(blocks((long long)n * c->n_din)), dim3(256), 0, st, n, c->nq,
                      c->n_h, c->n_key, c->n_din, q, c->qref, c->hinge_q, c->kpos, c->rpos, c->XD,

@@ -596,9 +596,11 @@ const char *ms_batch_last_error(void);
  * runs the network on every env's pose, then the step, in which an env
  * falls back to the exact geometry (MS_ST_FALLBACK, fallback_count[env]++
  * when non-NULL) if a hinge/slide coordinate lies outside the pose-domain
- * box or if the predicted length of any of 32 sentinel muscles (muscle
- * (32 step + i) mod n_mus, i < 32, step = exc->step0 + t) differs from the
- * exact length by more than tol metres. tol < 0 always falls back (exact
+ * box or if the predicted length or any predicted moment arm of any of 32
+ * sentinel muscles (muscle (32 step + i) mod n_mus, i < 32, step =
+ * exc->step0 + t) differs from the exact one by more than tol metres (the
+ * paper gives no residual test; this one is the library's). tol < 0 always
+ * falls back (exact
  * path); n_env must not exceed the surrogate workspace the device can hold. */
 ms_status ms_rollout_surrogate(ms_model *m, ms_surrogate *s, int32_t n_env, float *q,
                                float *qd, float *act, uint32_t *status,

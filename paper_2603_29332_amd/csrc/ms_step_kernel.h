@@ -735,9 +735,9 @@ __device__ __forceinline__ void stage_muscles(const KModel &M, const KRun &Rn, c
   float *mc = mF + nm;               // [n_mus]
   // surrogate geometry (when predictions are given): an env falls back to
   // the exact geometry when a hinge leaves the training box or when the
-  // prediction misses the exact length of one of 32 sentinel muscles,
-  // rotated each step, by more than the tolerance. The decision is uniform
-  // over the env's team.
+  // prediction misses the exact length or one of the moment arms of one of
+  // 32 sentinel muscles, rotated each step, by more than the tolerance. The
+  // decision is uniform over the env's team.
   bool exact = true;
   if (SURR) {
     const float *Y = Rn.geomY + (size_t)env * 4 * nm;
@@ -756,6 +756,9 @@ __device__ __forceinline__ void stage_muscles(const KModel &M, const KRun &Rn, c
       float r3[3], Ld;
       const float L = muscle_geometry<NVIA>(M, m, NVIA, Rl, Pl, Sl, qd, O, r3, Ld);
       miss = !(fabsf(Y[mx] - L) <= Rn.fb_tol);
+#pragma unroll
+      for (int sl = 0; sl < 3; ++sl)
+        if (M.mus_span[sl * nm + m] >= 0) miss |= !(fabsf(Y[nm + 3 * mx + sl] - r3[sl]) <= Rn.fb_tol);
     }
     const bool o1 = T.any(out);
     const bool o2 = T.any(miss);

@@ -190,18 +190,23 @@ def test_sampled_poses_lie_in_the_box(setup):
 
 
 # ------------------------------------------------------------ surrogate step
-def _constant_network(m, s, o, spans, q_ref):
+def _constant_network(m, s, o, spans, q_ref, r_scale=None):
     """Zero the output layer so the network returns exactly its shift: the
-    oracle geometry at q_ref with lengths 0.5 mm long and moment arms 10 %
-    large (wrong enough to tell apart from the exact geometry, close enough
-    to pass a 1 mm length check). Returns (L, r slots) as float32."""
+    oracle geometry at q_ref with lengths and the moment arms of the span
+    slots 0.5 mm long (wrong enough to tell apart from the exact geometry,
+    close enough to pass a 1 mm check of lengths and moment arms), or with
+    exact lengths and the moment arms scaled by r_scale. Returns (L, r
+    slots) as float32."""
     ps = s.params()
     ps[4][:] = 0.0
     ps[5][:] = 0.0
     s.set_params(ps)
     y = _oracle_targets(m, o, spans, q_ref[None])[0]
-    y[:m["n_mus"]] += 5e-4
-    y[m["n_mus"]:] *= 1.1
+    if r_scale is None:
+        y[:m["n_mus"]] += 5e-4
+        y[m["n_mus"]:] += 5e-4 * (spans.reshape(-1) >= 0)
+    else:
+        y[m["n_mus"]:] *= r_scale
     y = y.astype(np.float32)
     s.set_norm(y, np.ones(s.n_out, np.float32))
     return y[:m["n_mus"]], y[m["n_mus"]:].reshape(m["n_mus"], 3)
@@ -255,6 +260,35 @@ def test_surrogate_step_matches_oracle_given_geometry_and_falls_back(setup):
     # the predicted geometry is not the exact one: near envs differ from the
     # exact path
     assert np.abs(g[1][near] - ex[1][near]).max() > 1e-3
+    _identity_norm(s)
+
+
+def test_moment_arm_sentinel_sends_envs_to_the_exact_path(setup):
+    """Exact lengths but moment arms 50 % large: every sentinel length passes
+    a 1 mm check, so only the moment-arm check can send the envs near the
+    reference pose to the exact geometry; they then advance bit for bit as
+    the exact path does."""
+    m, gm, s, o = setup
+    spans = _oracle_spans(m, o)
+    q_ref = np.linspace(-0.4, 0.4, m["nq"])
+    _constant_network(m, s, o, spans, q_ref, r_scale=1.5)
+    E, dt = 48, 2e-3
+    near = np.ones(E, bool)
+    q, qd, act = _states(m, E, q_ref, near, 7)
+    u = synth.excitation_iid(14, E, m["n_mus"], 0)
+    tq, tqd, tact = _t(q), _t(qd), _t(act)
+    st = torch.zeros(E, dtype=torch.int32, device=DEV)
+    fb = torch.zeros(E, dtype=torch.int32, device=DEV)
+    gm.rollout_surrogate(s, tq, tqd, tact, st, 1, dt, contact=False, tol=1e-3,
+                         fb_count=fb, kind=ms.EXC_ARRAY, u=_t(u[None]))
+    eq, eqd, eact = _t(q), _t(qd), _t(act)
+    est = torch.zeros(E, dtype=torch.int32, device=DEV)
+    gm.rollout(eq, eqd, eact, est, 1, dt, False, kind=ms.EXC_ARRAY, u=_t(u[None]))
+    torch.cuda.synchronize()
+    assert (fb.cpu().numpy() == 1).all()
+    assert (st.cpu().numpy() == ms.MS_ST_FALLBACK).all()
+    for a, b in zip((tq, tqd, tact), (eq, eqd, eact)):
+        assert torch.equal(a, b)
     _identity_norm(s)
 
 
@@ -510,8 +544,8 @@ def test_full_size_network_forward_gradients_and_adam(human_net, n):
 
 def test_full_size_prediction_taken_step_matches_oracle(human_net):
     """Whole body, contact off: a constant network returning the oracle's
-    geometry at a reference pose (lengths 0.5 mm long, moment arms 10 %
-    large) passes a 1 mm residual check on envs within 2e-6 of that pose,
+    geometry at a reference pose (lengths and moment arms 0.5 mm long)
+    passes a 1 mm residual check on envs within 2e-6 of that pose,
     which then advance as the oracle step given that geometry (per-step
     bound 1e-5); envs moved 0.2-0.4 rad away fail it and advance bit for bit
     as the exact path does."""

@@ -139,9 +139,10 @@ hipError_t launch(ms_model *m, const ms::KRun &r, int n_env, int n_steps, hipStr
       return e;
   }
   const int per = (n_env + parts - 1) / parts;
-  if (m->w_n_env != per) {
-    ms::split_env_per_wg(m->k, w, per, &m->w_front, &m->w_back);
+  if (m->w_n_env != per || m->w_parts != parts) {
+    ms::split_env_per_wg(m->k, w, per, parts, &m->w_front, &m->w_back);
     m->w_n_env = per;
+    m->w_parts = parts;
   }
   const int mpt = (m->t.n_mus + 255) / 256;
   bool timed = m->timing > 0;

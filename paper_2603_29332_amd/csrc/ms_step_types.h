@@ -158,11 +158,13 @@ hipError_t launch_front(const KModel &k, const KRun &r, const KSplit &w, int w_f
                         hipStream_t st);
 hipError_t launch_back(const KModel &k, const KRun &r, const KSplit &w, int w_back, int step,
                        hipStream_t st);
-// Envs per workgroup of those two kernels for a launch over n_env envs:
-// the fewest rounds of resident envs on the device's CUs (occupancy
-// calculator over 1..16 envs per workgroup), then the fewest envs per CU
-// giving that many rounds.
-void split_env_per_wg(const KModel &k, const KSplit &w, int n_env, int *w_front, int *w_back);
+// Envs per workgroup of those two kernels for a launch over n_env envs, one
+// of `parts` concurrent parts: alone, the fewest rounds of resident envs on
+// the device's CUs (occupancy calculator over 1..16 envs per workgroup),
+// then the fewest envs per CU giving that many rounds; beside other parts,
+// the most envs resident per CU.
+void split_env_per_wg(const KModel &k, const KSplit &w, int n_env, int parts, int *w_front,
+                      int *w_back);
 
 }  // namespace ms
 
@@ -178,8 +180,8 @@ struct ms_model {
   ms::KSplit ks{};
   int ws_cap = 0;
   std::vector<void *> ws_owned;
-  // envs per workgroup of its kernels, chosen for w_n_env envs
-  int w_front = 0, w_back = 0, w_n_env = 0;
+  // envs per workgroup of its kernels, chosen for w_n_env envs in w_parts concurrent parts
+  int w_front = 0, w_back = 0, w_n_env = 0, w_parts = 0;
   // the split step's second stream and its fork/join events (two halves of
   // the batch stepped concurrently)
   // split step: the batch in this many parts, each on a stream of its own

@@ -151,6 +151,7 @@ def main():
     value = applied_steps / wall
     n_resets = int(resets.item())
     progress(f"exact leg: {a.steps} launches, {wall:.2f} s")
+    gm.set_split_streams(0)   # the library's own choice for the other legs' sizes
     # the same work on the fused schedule (one kernel per 100-step call)
     gmf = ms.Model(m)
     gmf.set_schedule(ms.SCHED_FUSED)

@@ -589,8 +589,7 @@ ms_status build_tables(const ms_model_desc *d, Tables *t, std::string *msg) {
   off = 0;
   L.b_q = take(4 * nq);
   L.b_qd = take(4 * nv);
-  L.b_rhs = take(8 * nv);
-  L.b_x = take(8 * nv);
+  L.b_x = take(8 * nv);   // the right-hand side, solved in place
   L.b_invd = take(8 * nv);
   L.b_H = take(8 * t->nnz);
   L.b_bytes = off;

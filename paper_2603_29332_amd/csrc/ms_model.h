@@ -27,7 +27,7 @@ struct SplitLayout {
   // kinematics and dynamics kernel
   int f_q = 0, f_qd = 0, f_R = 0, f_S = 0, f_con = 0, f_scr = 0, f_bytes = 0;
   // factorisation kernel
-  int b_q = 0, b_qd = 0, b_rhs = 0, b_x = 0, b_invd = 0, b_H = 0, b_bytes = 0;
+  int b_q = 0, b_qd = 0, b_x = 0, b_invd = 0, b_H = 0, b_bytes = 0;
   // muscle kernel
   int m_R = 0, m_S = 0, m_q = 0, m_qd = 0, m_scr = 0, m_bytes = 0;
   // per-env bytes of each workspace array: node frames, motion subspaces,

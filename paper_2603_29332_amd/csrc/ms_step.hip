@@ -343,7 +343,7 @@ ms_status ms_model_create(const ms_model_desc *desc, ms_model **out) {
     w.act_stride = (int)(L.ws_act / 4);
     w.f_q = L.f_q; w.f_qd = L.f_qd; w.f_R = L.f_R; w.f_S = L.f_S; w.f_con = L.f_con;
     w.f_scr = L.f_scr; w.f_bytes = L.f_bytes;
-    w.b_q = L.b_q; w.b_qd = L.b_qd; w.b_rhs = L.b_rhs; w.b_x = L.b_x; w.b_invd = L.b_invd;
+    w.b_q = L.b_q; w.b_qd = L.b_qd; w.b_x = L.b_x; w.b_invd = L.b_invd;
     w.b_H = L.b_H; w.b_bytes = L.b_bytes;
     w.m_R = L.m_R; w.m_S = L.m_S; w.m_q = L.m_q; w.m_qd = L.m_qd; w.m_scr = L.m_scr;
     w.m_bytes = L.m_bytes;

@@ -867,8 +867,10 @@ __device__ __forceinline__ void stage_muscles(const KModel &M, const KRun &Rn, c
 }
 
 // LTDL factorisation of H (FP64, in LDS) with the L^T solve riding along,
-// then the L solve; the solution is left in xs. Returns true (the same in
-// every lane) when a pivot is not positive.
+// then the L solve; the solution is left in xs. rhs may be xs itself (row
+// k's right-hand side is read only when row k is finished, before anything
+// writes xs[k]). Returns true (the same in every lane) when a pivot is not
+// positive.
 //
 // H = L^T D L with Featherstone's branch-induced sparsity, as gathers:
 // finished row k holds H_kj - sum over the descendants i of k of

@@ -98,8 +98,7 @@ __global__ __launch_bounds__(1024) void k_back(KModel M, KRun Rn, KSplit W, int 
   }
   float *q = (float *)(lds + W.b_q);
   float *qd = (float *)(lds + W.b_qd);
-  double *rhs = (double *)(lds + W.b_rhs);
-  double *xs = (double *)(lds + W.b_x);
+  double *xs = (double *)(lds + W.b_x);   // the right-hand side, solved in place
   double *invd = (double *)(lds + W.b_invd);
   double *H = (double *)(lds + W.b_H);
   const float dt = Rn.dt;
@@ -109,7 +108,7 @@ __global__ __launch_bounds__(1024) void k_back(KModel M, KRun Rn, KSplit W, int 
   for (int i = lane; i < nq; i += 64) q[i] = Rn.q[(size_t)env * nq + i];
   for (int i = lane; i < nv; i += 64) {
     qd[i] = Rn.qd[(size_t)env * nv + i];
-    rhs[i] = W.rhs[(size_t)env * W.rhs_stride + i] + (double)W.tau[(size_t)env * W.tau_stride + i];
+    xs[i] = W.rhs[(size_t)env * W.rhs_stride + i] + (double)W.tau[(size_t)env * W.tau_stride + i];
   }
   const double *gH = W.H + (size_t)env * W.H_stride;
   for (int e = lane; e < M.nnz; e += 64) H[e] = gH[e];
@@ -118,8 +117,8 @@ __global__ __launch_bounds__(1024) void k_back(KModel M, KRun Rn, KSplit W, int 
   const double *gd = W.dsum + (size_t)env * W.dsum_stride;
   for (int e = lane; e < M.n_dent; e += 64) H[M.dent_h[e]] += (double)dt * gd[e];
   wave_sync();
-  add_coupling(M, lane, q, qd, H, rhs, invd, dt);   // invd is free until the solve
-  if (stage_solve(M, lane, LT, H, rhs, xs, invd)) {
+  add_coupling(M, lane, q, qd, H, xs, invd, dt);   // invd is free until the solve
+  if (stage_solve(M, lane, LT, H, xs, xs, invd)) {
     if (lane == 0 && Rn.status) Rn.status[env] |= MS_ST_NONSPD;
     return;
   }

@@ -39,8 +39,8 @@ PEAK_VALU_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 # a plain copy of known size (profiles/k_split_human80_4096_traffic.md),
 # valid for the kernel sources (ms_step_kernel.h, ms_step_split.hip) with
 # this SHA-256 prefix only (reported as null otherwise).
-TRAFFIC_BYTES_PER_LAUNCH = {"k_front": 37.34e6, "k_muscle": 41.70e6, "k_back": 42.71e6}
-TRAFFIC_KERNEL_SHA = "7b1fa7c7e59ff200"
+TRAFFIC_BYTES_PER_LAUNCH = {"k_front": 37.34e6, "k_muscle": 41.70e6, "k_back": 42.73e6}
+TRAFFIC_KERNEL_SHA = "28a4675fc2818552"
 TIMING_EVERY = 10
 KERNELS = ("k_front", "k_muscle", "k_back")
 

@@ -178,14 +178,19 @@ int best_w(const void *fn, size_t (*lds_of)(const KModel &, const KSplit &, int)
 }
 }  // namespace
 
-void split_env_per_wg(const KModel &k, const KSplit &w, int n_env, int parts, int *w_front,
-                      int *w_back) {
+int device_cu_count() {
   int dev = 0, n_cu = 256;
   if (hipGetDevice(&dev) == hipSuccess) {
     int v = 0;
     if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
       n_cu = v;
   }
+  return n_cu;
+}
+
+void split_env_per_wg(const KModel &k, const KSplit &w, int n_env, int parts, int *w_front,
+                      int *w_back) {
+  const int n_cu = device_cu_count();
   *w_front = best_w((const void *)&k_front, front_lds, k, w, n_env, n_cu, parts > 1);
   *w_back = best_w((const void *)&k_back, back_lds, k, w, n_env, n_cu, parts > 1);
 }

@@ -165,6 +165,8 @@ hipError_t launch_back(const KModel &k, const KRun &r, const KSplit &w, int w_ba
 // the most envs resident per CU.
 void split_env_per_wg(const KModel &k, const KSplit &w, int n_env, int parts, int *w_front,
                       int *w_back);
+// CUs of the current device (256 if the query fails).
+int device_cu_count();
 
 }  // namespace ms
 

@@ -34,13 +34,13 @@ PHYS_PER_STEP = 100
 # MI355X: 256 CUs x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz, one FP32 or
 # FP64 vector FMA per lane and cycle (packed FP32 would double FP32 only).
 PEAK_VALU_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
-# HBM bytes per launch of each split-schedule kernel on this workload (one
-# half-batch, 2048 envs), from rocprofv3 FETCH_SIZE and WRITE_SIZE scaled by
+# HBM bytes per launch of each split-schedule kernel on this workload (the
+# first part, 2560 envs), from rocprofv3 FETCH_SIZE and WRITE_SIZE scaled by
 # a plain copy of known size (profiles/k_split_human80_4096_traffic.md),
 # valid for the kernel sources (ms_step_kernel.h, ms_step_split.hip) with
 # this SHA-256 prefix only (reported as null otherwise).
-TRAFFIC_BYTES_PER_LAUNCH = {"k_front": 37.34e6, "k_muscle": 41.70e6, "k_back": 42.73e6}
-TRAFFIC_KERNEL_SHA = "28a4675fc2818552"
+TRAFFIC_BYTES_PER_LAUNCH = {"k_front": 46.61e6, "k_muscle": 51.87e6, "k_back": 53.36e6}
+TRAFFIC_KERNEL_SHA = "e85b05f43e2359e2"
 TIMING_EVERY = 10
 KERNELS = ("k_front", "k_muscle", "k_back")
 
@@ -109,11 +109,14 @@ def main():
 
     applied = torch.zeros(E, dtype=torch.int32, device=dev)
     split = gm.schedule() == ms.SCHED_SPLIT
-    # the split step over two concurrent halves of the batch (one per stream)
+    # the split step over two concurrent parts of the batch (one per stream);
+    # the library sizes them (the first one full round of the kinematics
+    # kernel when that holds more than half the batch)
     halves = 2 if split else 1
     gm.set_split_streams(halves)
     gm.reserve(E)
-    env_per_launch = -(-E // halves)
+    bounds = gm.split_parts(E)
+    env_per_launch = bounds[1] - bounds[0]
 
     def launch(step_index, ev0=None, ev1=None, g=gm):
         if ev0 is not None:
@@ -200,13 +203,13 @@ def main():
         dom = max(KERNELS, key=lambda k: kernel_ms[k])
         roof = {"bound": "alu", "achieved": kernels[dom]["achieved"], "peak": PEAK_VALU_TFLOPS,
                 "unit": "TFLOP/s", "frac": kernels[dom]["frac"], "traffic": kernels[dom]["traffic"],
-                "kernel": dom + f" (split schedule, one launch per physics step and half-batch "
-                                f"of {env_per_launch} envs)",
-                "envs_per_launch": env_per_launch,
+                "kernel": dom + f" (split schedule, one launch per physics step and part; "
+                                f"the first part, {env_per_launch} envs)",
+                "envs_per_launch": env_per_launch, "part_bounds": bounds,
                 "avg_launch_ms": kernel_ms[dom],
                 "timing": f"HIP events on the launch stream around each kernel of the first "
-                          f"half-batch in every {TIMING_EVERY}th physics step of the timed "
-                          f"region (the other half's kernels run beside it on a second stream)",
+                          f"part in every {TIMING_EVERY}th physics step of the timed "
+                          f"region (the other part's kernels run beside it on a second stream)",
                 "flop_per_env_step": ksplit[dom], "kernels": kernels,
                 "step_flop_per_env_step": {"fp32": fp32, "fp64": fp64},
                 "step_achieved": (fp32 + fp64) * applied_steps / wall / 1e12,
@@ -227,7 +230,7 @@ def main():
                                "contact spheres, dt 1 ms, AR(1) excitations in-kernel",
                    "envs": E, "physics_steps_per_bench_step": PHYS_PER_STEP,
                    "geometry": "exact", "precision": "FP32, FP64 mass matrix + LTDL solve",
-                   "schedule": "split" if split else "fused", "streams": halves},
+                   "schedule": "split" if split else "fused", "streams": len(bounds) - 1 if split else 1},
         "applied_env_steps": applied_steps, "scheduled_env_steps": env_steps,
         "skipped_fraction": 1.0 - applied_steps / env_steps,
         "scheduled_env_steps_per_s": env_steps / wall,

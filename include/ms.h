@@ -189,9 +189,17 @@ ms_status ms_model_set_schedule(ms_model *m, int32_t schedule);
  * parts concurrently, the first on the caller's stream and the others on
  * streams of the model's own (forked from and joined back to the caller's
  * with events, so stream order and graph capture hold); 0 (default) uses
- * two parts for batches of at least 4096 envs and one below. Launches that
- * an ms_batch drives use one stream. Results do not depend on it. */
+ * two parts for batches of at least 4096 envs and one below (the part sizes:
+ * ms_model_split_parts). Launches that an ms_batch drives use one stream.
+ * Results do not depend on it. */
 ms_status ms_model_set_split_streams(ms_model *m, int32_t streams);
+/* The parts a step of n_env envs (not driven by an ms_batch, not under
+ * capture) runs in with the current settings (one on the fused schedule): *n_parts (1 to 4)
+ * and bounds[0 .. *n_parts] (bounds[h] .. bounds[h + 1] are part h's envs;
+ * bounds holds at least 5 entries). Equal parts, except that with two parts
+ * the first takes one full round of the kinematics kernel when that holds
+ * more than half the batch. For callers that time or size per part. */
+ms_status ms_model_split_parts(ms_model *m, int32_t n_env, int32_t *bounds, int32_t *n_parts);
 /* The schedule the model's steps use now (MS_SCHED_FUSED or MS_SCHED_SPLIT). */
 ms_status ms_model_get_schedule(const ms_model *m, int32_t *schedule);
 /* Reserve the split schedule's workspace for up to n_env envs now

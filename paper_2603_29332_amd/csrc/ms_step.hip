@@ -111,6 +111,32 @@ ms_status reserve_split(ms_model *m, int n_env, hipStream_t st) {
   return MS_OK;
 }
 
+// Parts of a split-step launch over n_env envs when `parts` were asked for:
+// sets the model's envs per workgroup for them and the env bounds
+// (bounds[h] .. bounds[h + 1] for part h); returns the number of non-empty
+// parts. Equal parts, except that with two parts the first takes exactly
+// one full round of the kinematics kernel (a workgroup of w_front envs on
+// every CU) when that holds more than half the batch (measured on the whole
+// body at 4096 envs: 2560 + 1536 envs 0.287 ms per step, 2048 + 2048 0.296;
+// one env past the round costs a second round: 2688 + 1408 0.307).
+int plan_parts(ms_model *m, int n_env, int parts, int *bounds) {
+  parts = std::max(1, std::min(parts, std::min(n_env, (int)ms_model::kMaxParts)));
+  const int per = (n_env + parts - 1) / parts;
+  if (m->w_n_env != per || m->w_parts != parts) {
+    ms::split_env_per_wg(m->k, m->ks, per, parts, &m->w_front, &m->w_back);
+    m->w_n_env = per;
+    m->w_parts = parts;
+  }
+  for (int h = 0; h <= parts; ++h) bounds[h] = std::min(n_env, h * per);
+  if (parts == 2) {
+    const int round = ms::device_cu_count() * m->w_front;
+    if (round > per && round < n_env) bounds[1] = round;
+  }
+  while (parts > 1 && bounds[parts - 1] >= bounds[parts]) --parts;  // no empty part
+  bounds[parts] = n_env;
+  return parts;
+}
+
 hipError_t launch(ms_model *m, const ms::KRun &r, int n_env, int n_steps, hipStream_t st) {
   const int nvia = m->t.n_via_max;
   // a coupled model's surrogate step runs on the split schedule only
@@ -138,12 +164,8 @@ hipError_t launch(ms_model *m, const ms::KRun &r, int n_env, int n_steps, hipStr
     else if (hipError_t e = make_part_streams(m); e != hipSuccess)
       return e;
   }
-  const int per = (n_env + parts - 1) / parts;
-  if (m->w_n_env != per || m->w_parts != parts) {
-    ms::split_env_per_wg(m->k, w, per, parts, &m->w_front, &m->w_back);
-    m->w_n_env = per;
-    m->w_parts = parts;
-  }
+  int bounds[ms_model::kMaxParts + 1];
+  parts = plan_parts(m, n_env, parts, bounds);
   const int mpt = (m->t.n_mus + 255) / 256;
   bool timed = m->timing > 0;
   if (timed) {
@@ -176,23 +198,10 @@ hipError_t launch(ms_model *m, const ms::KRun &r, int n_env, int n_steps, hipStr
   hipStream_t sh[P] = {st};
   for (int h = 0; h < parts; ++h) {
     rh[h] = r;
-    rh[h].env_begin = std::min(n_env, h * per);
-    rh[h].env_end = std::min(n_env, (h + 1) * per);
+    rh[h].env_begin = bounds[h];
+    rh[h].env_end = bounds[h + 1];
     if (h) sh[h] = m->sx[h - 1];
   }
-  // Two parts: when one full round of the kinematics kernel (a workgroup of
-  // w_front envs on every CU) holds more than half the batch, the first part
-  // takes exactly that round and the second the rest (measured on the whole
-  // body at 4096 envs: 2560 + 1536 envs 0.287 ms per step, 2048 + 2048
-  // 0.296; one env past the round costs a second round: 2688 + 1408 0.307).
-  if (parts == 2) {
-    const int round = ms::device_cu_count() * m->w_front;
-    if (round > per && round < n_env) {
-      rh[0].env_end = round;
-      rh[1].env_begin = round;
-    }
-  }
-  while (parts > 1 && rh[parts - 1].env_begin >= rh[parts - 1].env_end) --parts;  // no empty part
   if (parts > 1) {
     hipError_t e = hipEventRecord(m->ev_fork, st);
     for (int h = 1; h < parts && e == hipSuccess; ++h) e = hipStreamWaitEvent(sh[h], m->ev_fork, 0);
@@ -396,6 +405,19 @@ ms_status ms_model_set_split_streams(ms_model *m, int32_t streams) {
   if (!m || streams < 0 || streams > ms_model::kMaxParts)
     return fail(MS_E_ARG, "streams must be 0 (automatic) or 1 to 4");
   m->split_streams = streams;
+  return MS_OK;
+}
+
+ms_status ms_model_split_parts(ms_model *m, int32_t n_env, int32_t *bounds, int32_t *n_parts) {
+  g_err.clear();
+  if (!m || !bounds || !n_parts || n_env <= 0) return fail(MS_E_ARG, "NULL argument or n_env <= 0");
+  const int want = effective_schedule(m) != MS_SCHED_SPLIT ? 1
+                   : m->split_streams > 0                   ? m->split_streams
+                                                            : (n_env >= kTwoStreamEnvs ? 2 : 1);
+  int b[ms_model::kMaxParts + 1];
+  const int parts = plan_parts(m, n_env, want, b);
+  for (int h = 0; h <= parts; ++h) bounds[h] = b[h];
+  *n_parts = parts;
   return MS_OK;
 }
 

@@ -39,7 +39,7 @@ EXPORTED = ("ms_model_create", "ms_model_destroy", "ms_model_info_get",
             "ms_rollout_record", "ms_surrogate_train", "ms_surrogate_save", "ms_surrogate_load",
             "ms_controller_create", "ms_controller_destroy", "ms_controller_dims",
             "ms_controller_params", "ms_controller_reserve", "ms_controller_step",
-            "ms_controller_last_error", "ms_model_set_split_streams")
+            "ms_controller_last_error", "ms_model_set_split_streams", "ms_model_split_parts")
 
 _fptr = C.POINTER(C.c_float)
 _iptr = C.POINTER(C.c_int32)
@@ -129,6 +129,7 @@ def lib():
     L.ms_model_get_schedule.argtypes = [vp, _iptr]
     L.ms_model_reserve.argtypes = [vp, C.c_int32]
     L.ms_model_set_split_streams.argtypes = [vp, C.c_int32]
+    L.ms_model_split_parts.argtypes = [vp, C.c_int32, _iptr, _iptr]
     L.ms_model_set_kernel_timing.argtypes = [vp, C.c_int32]
     L.ms_model_kernel_times.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
     L.ms_model_set_key_nodes.argtypes = [vp, C.c_int32, _iptr]
@@ -302,6 +303,15 @@ class Model:
         """Split schedule: the batch in `streams` (1 to 4) concurrent parts,
         each on a stream of its own; 0 automatic."""
         _check(lib().ms_model_set_split_streams(self.h, int(streams)))
+
+    def split_parts(self, n_env):
+        """Env bounds of the concurrent parts a step of n_env envs runs in
+        (part h: bounds[h] .. bounds[h + 1])."""
+        b = np.zeros(5, np.int32)
+        n = np.zeros(1, np.int32)
+        _check(lib().ms_model_split_parts(self.h, int(n_env), b.ctypes.data_as(_iptr),
+                                          n.ctypes.data_as(_iptr)))
+        return [int(x) for x in b[:int(n[0]) + 1]]
 
     def schedule(self):
         """The schedule steps run with now (SCHED_FUSED or SCHED_SPLIT)."""

@@ -308,3 +308,25 @@ def test_stream_parts_argument_bounds(built):
             gm.set_split_streams(bad)
     for ok in (0, 1, 4):
         gm.set_split_streams(ok)
+
+
+def test_split_parts_cover_the_batch(built):
+    """ms_model_split_parts: contiguous non-empty parts that cover the batch,
+    as many as asked for (fewer only when there are fewer envs); with two
+    parts the first is at least half the batch; one part on the fused
+    schedule."""
+    m = built["human"][0]
+    gm = ms.Model(m)
+    for streams in (0, 1, 2, 3, 4):
+        gm.set_split_streams(streams)
+        for n in (1, 3, 93, 2048, 4096, 4097, 8192):
+            b = gm.split_parts(n)
+            want = streams if streams else (2 if n >= 4096 else 1)
+            assert b[0] == 0 and b[-1] == n
+            assert all(x < y for x, y in zip(b, b[1:]))
+            assert len(b) - 1 == min(want, n)
+            if len(b) == 3:
+                assert b[1] >= n - b[1]
+    gm.set_split_streams(0)
+    gm.set_schedule(ms.SCHED_FUSED)
+    assert gm.split_parts(4096) == [0, 4096]

@@ -579,8 +579,6 @@ ms_status build_tables(const ms_model_desc *d, Tables *t, std::string *msg) {
   // 256-thread workgroup for the muscle kernel), each with its own layout.
   SplitLayout &L = t->split;
   off = 0;
-  L.f_q = take(4 * nq);
-  L.f_qd = take(4 * nv);
   L.f_R = take(4 * 12 * n);
   L.f_S = take(4 * 6 * nv);
   L.f_con = take(4 * 16 * std::max(t->n_con, 1));

@@ -25,7 +25,7 @@ constexpr int kWave = 64;
 // kernels and the sizes of the per-env device workspace between them.
 struct SplitLayout {
   // kinematics and dynamics kernel
-  int f_q = 0, f_qd = 0, f_R = 0, f_S = 0, f_con = 0, f_scr = 0, f_bytes = 0;
+  int f_R = 0, f_S = 0, f_con = 0, f_scr = 0, f_bytes = 0;
   // factorisation kernel
   int b_q = 0, b_qd = 0, b_x = 0, b_invd = 0, b_H = 0, b_bytes = 0;
   // muscle kernel

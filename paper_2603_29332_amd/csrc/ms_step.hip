@@ -362,7 +362,7 @@ ms_status ms_model_create(const ms_model_desc *desc, ms_model **out) {
     w.tau_stride = (int)(L.ws_tau / 4);
     w.dsum_stride = (int)(L.ws_dsum / 8);
     w.act_stride = (int)(L.ws_act / 4);
-    w.f_q = L.f_q; w.f_qd = L.f_qd; w.f_R = L.f_R; w.f_S = L.f_S; w.f_con = L.f_con;
+    w.f_R = L.f_R; w.f_S = L.f_S; w.f_con = L.f_con;
     w.f_scr = L.f_scr; w.f_bytes = L.f_bytes;
     w.b_q = L.b_q; w.b_qd = L.b_qd; w.b_x = L.b_x; w.b_invd = L.b_invd;
     w.b_H = L.b_H; w.b_bytes = L.b_bytes;

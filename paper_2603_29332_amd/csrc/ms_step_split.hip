@@ -30,8 +30,10 @@ __global__ __launch_bounds__(1024) void k_front(KModel M, KRun Rn, KSplit W, int
   if (env >= (Rn.env_end ? Rn.env_end : Rn.n_env)) return;
   unsigned char *lds = lds_f + (size_t)M.lt_front_end * 4 + (size_t)wave * W.f_bytes;
   const int nq = M.nq, nv = M.nv, nn = M.n_node;
-  float *q = (float *)(lds + W.f_q);
-  float *qd = (float *)(lds + W.f_qd);
+  // q and qd are read where they lie (the kernel does not change them),
+  // which leaves LDS for one more env per CU
+  const float *q = Rn.q + (size_t)env * nq;
+  const float *qd = Rn.qd + (size_t)env * nv;
   float *Rl = (float *)(lds + W.f_R);
   float *Pl = Rl + 9;
   float *Sl = (float *)(lds + W.f_S);
@@ -41,16 +43,8 @@ __global__ __launch_bounds__(1024) void k_front(KModel M, KRun Rn, KSplit W, int
   float *Al = Vl + 6 * nn;
   float *Fl = Al + 6 * nn;
   bool bad = false;
-  for (int i = lane; i < nq; i += 64) {
-    const float v = Rn.q[(size_t)env * nq + i];
-    q[i] = v;
-    bad |= !isfinite(v);
-  }
-  for (int i = lane; i < nv; i += 64) {
-    const float v = Rn.qd[(size_t)env * nv + i];
-    qd[i] = v;
-    bad |= !isfinite(v);
-  }
+  for (int i = lane; i < nq; i += 64) bad |= !isfinite(q[i]);
+  for (int i = lane; i < nv; i += 64) bad |= !isfinite(qd[i]);
   if (__any(bad)) {
     if (lane == 0) W.flag[env] = 1;
     return;

@@ -110,7 +110,7 @@ struct KSplit {
   double *H, *rhs, *dsum;
   int *flag, *mflag;
   int fr_stride, S_stride, H_stride, rhs_stride, tau_stride, dsum_stride, act_stride;
-  int f_q, f_qd, f_R, f_S, f_con, f_scr, f_bytes;
+  int f_R, f_S, f_con, f_scr, f_bytes;
   int b_q, b_qd, b_x, b_invd, b_H, b_bytes;
   int m_R, m_S, m_q, m_qd, m_scr, m_bytes;
 };

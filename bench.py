@@ -35,12 +35,12 @@ PHYS_PER_STEP = 100
 # FP64 vector FMA per lane and cycle (packed FP32 would double FP32 only).
 PEAK_VALU_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 # HBM bytes per launch of each split-schedule kernel on this workload (the
-# first part, 2560 envs), from rocprofv3 FETCH_SIZE and WRITE_SIZE scaled by
+# first part, 2816 envs), from rocprofv3 FETCH_SIZE and WRITE_SIZE scaled by
 # a plain copy of known size (profiles/k_split_human80_4096_traffic.md),
 # valid for the kernel sources (ms_step_kernel.h, ms_step_split.hip) with
 # this SHA-256 prefix only (reported as null otherwise).
-TRAFFIC_BYTES_PER_LAUNCH = {"k_front": 46.61e6, "k_muscle": 51.87e6, "k_back": 53.36e6}
-TRAFFIC_KERNEL_SHA = "e85b05f43e2359e2"
+TRAFFIC_BYTES_PER_LAUNCH = {"k_front": 51.27e6, "k_muscle": 56.97e6, "k_back": 58.71e6}
+TRAFFIC_KERNEL_SHA = "5eba69e60b4ea85e"
 TIMING_EVERY = 10
 KERNELS = ("k_front", "k_muscle", "k_back")
 

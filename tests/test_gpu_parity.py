@@ -483,8 +483,9 @@ def test_other_kernel_shapes_stages_and_rollout(n_mus, n_via):
     """Muscle counts and path lengths that select the step kernel's other
     instantiations (2, 4 and 16 muscles per lane; via-point bounds 4 and 8;
     1024 muscles and 8 via-points are the library's maxima) on the whole
-    body: stage outputs against the oracle, and a rollout bitwise equal to
-    repeated single steps."""
+    body: stage outputs against the oracle, a rollout bitwise equal to
+    repeated single steps, and one teacher-forced step per state within the
+    literal 1e-5 per-step bound with contact off."""
     m = _paths(synth.human_model(7, n_mus=n_mus), n_via)
     assert int(np.diff(m["via_start"]).max()) == n_via
     gm, o = ms.Model(m), Oracle(m)
@@ -517,6 +518,9 @@ def test_other_kernel_shapes_stages_and_rollout(n_mus, n_via):
     torch.cuda.synchronize()
     for x, y in zip(a, b):
         assert torch.equal(x, y)
+    # one step at the literal per-step bound, contact off
+    _check_teacher_forced(m, gm, o, dt, "ar1", synth.human_initial_state, False,
+                          f"{n_mus} muscles, {n_via} via points", E=8, literal=True)
 
 
 def test_argument_errors_leave_the_state_unchanged(chain):

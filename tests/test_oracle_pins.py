@@ -155,6 +155,15 @@ def test_hill_curve_special_values(chain):
     for v in (-0.7, -0.2, 0.05, 0.6):
         fd = (o.fv(v + h) - o.fv(v - h)) / (2 * h)
         assert abs(fd - o.fv_slope(v)) < 1e-6 * max(1, abs(fd))
+    # f_l: symmetric about its maximum at l = 1, and its width fixed by the
+    # Gaussian integral: the integral of exp(-(l-1)^2 / g) over the line is
+    # sqrt(pi g), with g = 0.45 (reading R5)
+    ls = np.linspace(1.0 - 8.0, 1.0 + 8.0, 160001)
+    fl = np.array([o.fl(x) for x in ls])
+    assert np.allclose(fl, fl[::-1], rtol=0, atol=1e-12)
+    assert fl.argmax() == len(ls) // 2
+    area = float(np.sum((fl[1:] + fl[:-1]) * 0.5 * np.diff(ls)))
+    assert abs(area - np.sqrt(0.45 * np.pi)) < 1e-8
     # f_p continuous and C1 at 1.6 (linear tail)
     s_in = (o.fp(1.6) - o.fp(1.6 - h)) / h
     s_out = (o.fp(1.6 + h) - o.fp(1.6)) / h
@@ -524,9 +533,14 @@ def test_muscle_and_contact_slopes_match_finite_differences(human):
         fd = -(tp - tn) / 2e-7
         if j < 2:
             assert np.allclose(fd[:2], Dc[:2, j], rtol=1e-5)
+            # the normal force does not depend on the tangential velocity
+            assert abs(fd[2]) < 1e-9 and Dc[2, j] == 0.0
         else:
             # normal slope: damping plus the implicit spring, c_d + dt k
             assert abs(fd[2] - Dc[2, 2]) < 1e-4 * Dc[2, 2]
+            # the friction slope is taken at fixed F_n (reading R15): the
+            # true cross term through F_n's damping is left out of D
+            assert np.all(Dc[:2, 2] == 0.0) and np.abs(fd[:2]).max() > 1.0
     assert abs(Dc[2, 2] - (1e3 + dtc * 1e5)) < 1e-9
 
 

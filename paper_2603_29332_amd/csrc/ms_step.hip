@@ -117,8 +117,9 @@ ms_status reserve_split(ms_model *m, int n_env, hipStream_t st) {
 // parts. Equal parts, except that with two parts the first takes exactly
 // one full round of the kinematics kernel (a workgroup of w_front envs on
 // every CU) when that holds more than half the batch (measured on the whole
-// body at 4096 envs: 2560 + 1536 envs 0.287 ms per step, 2048 + 2048 0.296;
-// one env past the round costs a second round: 2688 + 1408 0.307).
+// body at 4096 envs with 10 envs per workgroup: 2560 + 1536 envs 0.287 ms
+// per step, 2048 + 2048 0.296; one env past the round costs a second round:
+// 2688 + 1408 0.307).
 int plan_parts(ms_model *m, int n_env, int parts, int *bounds) {
   parts = std::max(1, std::min(parts, std::min(n_env, (int)ms_model::kMaxParts)));
   const int per = (n_env + parts - 1) / parts;

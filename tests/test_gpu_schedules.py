@@ -312,9 +312,9 @@ def test_stream_parts_argument_bounds(built):
 
 def test_split_parts_cover_the_batch(built):
     """ms_model_split_parts: contiguous non-empty parts that cover the batch,
-    as many as asked for (fewer only when there are fewer envs); with two
-    parts the first is at least half the batch; one part on the fused
-    schedule."""
+    as many as asked for at these sizes (fewer only when some part would be
+    empty); with two parts the first is at least half the batch; one part
+    on the fused schedule."""
     m = built["human"][0]
     gm = ms.Model(m)
     for streams in (0, 1, 2, 3, 4):

@@ -243,6 +243,23 @@ double ora_fv_slope(double vm) {
   return 0.032 / ((vm + 0.08) * (vm + 0.08));
 }
 
+/* The root v of A f_v(v) + beta v = R by bisection. A f_v lies in
+ * [0, 1.4 A], so the left-hand side is below R at (R - 1.4 A)/beta - 1 and
+ * above it at R/beta + 1; halving stops when the midpoint no longer splits
+ * the bracket (full double precision). */
+double ora_fv_root(double A, double R, double beta) {
+  double lo = (R - 1.4 * A) / beta - 1.0, hi = R / beta + 1.0;
+  for (int it = 0; it < 2000; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (mid <= lo || mid >= hi) break;
+    if (A * ora_fv(mid) + beta * mid - R < 0.0)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return 0.5 * (lo + hi);
+}
+
 /* --------------------------------------------------- forward kinematics */
 void ora_fk(const ora_model *m, const double *q, double *R, double *p) {
   for (int i = 0; i < m->n_node; ++i) {
@@ -742,12 +759,45 @@ uint32_t ora_step(const ora_model *m, double dt, int contact_on, double *q,
   return ora_step_geo(m, dt, contact_on, q, qd, act, u, NULL, NULL, out);
 }
 
-uint32_t ora_step_geo(const ora_model *m, double dt, int contact_on, double *q,
-                      double *qd, double *act, const double *u, const double *L_in,
-                      const double *r_in, ora_stage_out *out) {
+/* Compliant-tendon muscles at the start of a step (see ora_step_tendon):
+ * per muscle the force of the right-hand side F, its slope c in the new
+ * lengthening rate, the balancing fibre velocity v (m/s) and c / b. */
+static void tendon_forces(const ora_model *m, const double *act1, const double *L,
+                          const double *Ld, const double *lm, double dt, double eps0,
+                          double beta, double *F, double *c, double *v, double *rho,
+                          double *lm_out, double *vm_out) {
+  for (int i = 0; i < m->n_mus; ++i) {
+    const double ls = m->l_slack[i], f0 = m->f0[i];
+    const double strain = (L[i] - lm[i] - ls) / ls;           /* tendon strain */
+    const double ft = strain > 0.0 ? strain / eps0 : 0.0;      /* F_t / F0 */
+    const double k = strain > 0.0 ? f0 / (eps0 * ls) : 0.0;    /* dF_t / dl_t */
+    const double l = lm[i] / m->l_opt[i];
+    const double A = act1[i] * ora_fl(l);
+    const double vn = ora_fv_root(A, ft - ora_fp(l), beta);   /* fibre balance */
+    const double vs = m->v_max[i] * m->l_opt[i];               /* m/s per unit */
+    const double b = f0 * (A * ora_fv_slope(vn) + beta) / vs;   /* dF_m / dv */
+    const double cs = k * dt / (1.0 + k * dt / b);             /* series slope */
+    v[i] = vn * vs;
+    F[i] = f0 * ft + cs * (Ld[i] - v[i]);
+    c[i] = cs;
+    rho[i] = cs / b;
+    if (lm_out) lm_out[i] = l;
+    if (vm_out) vm_out[i] = vn;
+  }
+}
+
+static uint32_t step_core(const ora_model *m, double dt, int contact_on, double *q,
+                          double *qd, double *act, const double *u, const double *L_in,
+                          const double *r_in, double *lmf, double eps0, double beta,
+                          ora_stage_out *out) {
   int nv = m->nv, nq = m->nq, nm = m->n_mus, n = m->n_node;
-  if (!all_finite(q, nq) || !all_finite(qd, nv) || !all_finite(act, nm))
+  if (!all_finite(q, nq) || !all_finite(qd, nv) || !all_finite(act, nm) ||
+      (lmf && !all_finite(lmf, nm)))
     return ORA_ST_NONFINITE;
+  double *cmu = (double *)malloc(sizeof(double) * nm);
+  double *vf = (double *)malloc(sizeof(double) * nm);
+  double *rho = (double *)malloc(sizeof(double) * nm);
+  double *lmn = (double *)malloc(sizeof(double) * nm);
   double *act1 = (double *)malloc(sizeof(double) * nm);
   double *L = (double *)malloc(sizeof(double) * nm);
   double *Ld = (double *)malloc(sizeof(double) * nm);
@@ -779,7 +829,18 @@ uint32_t ora_step_geo(const ora_model *m, double dt, int contact_on, double *q,
   } else {
     ora_geometry(m, q, qd, L, r, Ld);
   }
-  ora_hill(m, act1, L, Ld, F, out ? out->lm : NULL, out ? out->vm : NULL);
+  if (lmf) {
+    tendon_forces(m, act1, L, Ld, lmf, dt, eps0, beta, F, cmu, vf, rho, out ? out->lm : NULL,
+                  out ? out->vm : NULL);
+  } else {
+    ora_hill(m, act1, L, Ld, F, out ? out->lm : NULL, out ? out->vm : NULL);
+    for (int mu = 0; mu < nm; ++mu) {
+      double lm = (L[mu] - m->l_slack[mu]) / m->l_opt[mu];
+      double vm = Ld[mu] / (m->v_max[mu] * m->l_opt[mu]);
+      cmu[mu] = m->f0[mu] * act1[mu] * ora_fl(lm) * ora_fv_slope(vm) /
+                (m->v_max[mu] * m->l_opt[mu]);
+    }
+  }
   for (int mu = 0; mu < nm; ++mu)
     for (int j = 0; j < nv; ++j) tm[j] += r[(size_t)mu * nv + j] * F[mu];
   ora_mass_matrix(m, q, M);
@@ -793,10 +854,7 @@ uint32_t ora_step_geo(const ora_model *m, double dt, int contact_on, double *q,
     D[j * nv + j] += m->damping[j];
   }
   for (int mu = 0; mu < nm; ++mu) {
-    double lm = (L[mu] - m->l_slack[mu]) / m->l_opt[mu];
-    double vm = Ld[mu] / (m->v_max[mu] * m->l_opt[mu]);
-    double cm = m->f0[mu] * act1[mu] * ora_fl(lm) * ora_fv_slope(vm) /
-                (m->v_max[mu] * m->l_opt[mu]);
+    const double cm = cmu[mu];
     const double *rm = r + (size_t)mu * nv;
     for (int i = 0; i < nv; ++i) {
       if (rm[i] == 0.0) continue;
@@ -835,7 +893,17 @@ uint32_t ora_step_geo(const ora_model *m, double dt, int contact_on, double *q,
       double nrm = sqrt(o[0] * o[0] + o[1] * o[1] + o[2] * o[2] + o[3] * o[3]);
       for (int k = 0; k < 4; ++k) qn[a + 3 + k] = o[k] / nrm;
     }
-    if (!all_finite(qn, nq) || !all_finite(qdn, nv) || !all_finite(act1, nm))
+    if (lmf) {
+      /* the fibre moves with the velocity of the series element at the new
+       * lengthening rate */
+      for (int mu = 0; mu < nm; ++mu) {
+        double ldn = 0.0;
+        for (int j = 0; j < nv; ++j) ldn -= r[(size_t)mu * nv + j] * qdn[j];
+        lmn[mu] = lmf[mu] + dt * (vf[mu] + rho[mu] * (ldn - vf[mu]));
+      }
+    }
+    if (!all_finite(qn, nq) || !all_finite(qdn, nv) || !all_finite(act1, nm) ||
+        (lmf && !all_finite(lmn, nm)))
       st |= ORA_ST_NONFINITE;
   }
   if (out) {
@@ -857,11 +925,25 @@ uint32_t ora_step_geo(const ora_model *m, double dt, int contact_on, double *q,
     memcpy(q, qn, sizeof(double) * nq);
     memcpy(qd, qdn, sizeof(double) * nv);
     memcpy(act, act1, sizeof(double) * nm);
+    if (lmf) memcpy(lmf, lmn, sizeof(double) * nm);
   }
+  free(cmu); free(vf); free(rho); free(lmn);
   free(act1); free(L); free(Ld); free(F); free(r); free(M); free(tm); free(te);
   free(td); free(C); free(rhs); free(qdd); free(zero); free(qn); free(qdn);
   free(D); free(teq);
   return st;
+}
+
+uint32_t ora_step_geo(const ora_model *m, double dt, int contact_on, double *q,
+                      double *qd, double *act, const double *u, const double *L_in,
+                      const double *r_in, ora_stage_out *out) {
+  return step_core(m, dt, contact_on, q, qd, act, u, L_in, r_in, NULL, 0.0, 0.0, out);
+}
+
+uint32_t ora_step_tendon(const ora_model *m, double dt, int contact_on, double *q,
+                         double *qd, double *act, double *lm, const double *u, double eps0,
+                         double beta, ora_stage_out *out) {
+  return step_core(m, dt, contact_on, q, qd, act, u, NULL, NULL, lm, eps0, beta, out);
 }
 
 void ora_rollout(const ora_model *m, int n_env, int n_steps, double dt,

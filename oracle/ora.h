@@ -128,6 +128,33 @@ uint32_t ora_step(const ora_model *m, double dt, int contact_on,
                   double *q, double *qd, double *act, const double *u,
                   ora_stage_out *out);
 
+/* Compliant tendon (a higher-fidelity muscle variant of the paper's Hill
+ * actuator, Methods "Whole-body musculoskeletal model"): a fibre with the
+ * damped force balance F0 [act f_l(l) f_v(v) + f_p(l) + beta v] in series
+ * with a tendon that is linear above its slack length l_slack, F0 at strain
+ * eps0, and slack below it. No pennation, as in the rigid model.
+ *
+ * ora_fv_root: the normalised fibre velocity v with
+ * A f_v(v) + beta v = R (A = act f_l >= 0, beta > 0), by bisection on the
+ * strictly increasing left-hand side. */
+double ora_fv_root(double A, double R, double beta);
+
+/* One step with a compliant tendon, in place on (q, qd, act, lm); lm[n_mus]
+ * is the fibre length in metres. At the start of the step the fibre
+ * velocity v balances the fibre against the tendon; the tendon (stiffness
+ * k) and the fibre (velocity slope b) in series act on the skeleton as a
+ * force F_t + c (Ldot' - v) linear in the new lengthening rate Ldot', with
+ * c = k dt / (1 + k dt / b), taken implicitly like the rigid muscle's
+ * damping; after the solve the fibre moves by dt (v + c (Ldot' - v) / b)
+ * with Ldot' = -r qd' (moment arms of the step's start). Stage outputs:
+ * F is the force of the right-hand side, lm and vm the normalised fibre
+ * length and velocity at the start. Returns status bits; on a failure
+ * nothing is updated. */
+uint32_t ora_step_tendon(const ora_model *m, double dt, int contact_on,
+                         double *q, double *qd, double *act, double *lm,
+                         const double *u, double eps0, double beta,
+                         ora_stage_out *out);
+
 /* ora_step with the muscle geometry given instead of computed: L_in[n_mus]
  * and moment arms r_in[n_mus][nv] (both NULL: ora_step). Ldot = -r qd. */
 uint32_t ora_step_geo(const ora_model *m, double dt, int contact_on,

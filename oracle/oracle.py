@@ -89,6 +89,11 @@ def _load():
     lib.ora_step_geo.restype = C.c_uint32
     lib.ora_step_geo.argtypes = [C.c_void_p, C.c_double, C.c_int, _dp, _dp, _dp, _dp,
                                  C.c_void_p, C.c_void_p, C.POINTER(_StageOut)]
+    lib.ora_fv_root.restype = C.c_double
+    lib.ora_fv_root.argtypes = [C.c_double, C.c_double, C.c_double]
+    lib.ora_step_tendon.restype = C.c_uint32
+    lib.ora_step_tendon.argtypes = [C.c_void_p, C.c_double, C.c_int, _dp, _dp, _dp, _dp, _dp,
+                                    C.c_double, C.c_double, C.POINTER(_StageOut)]
     lib.ora_rollout.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_double, C.c_int,
                                 _dp, _dp, _dp, _fp, _up, C.c_int]
     lib.ora_bf16.restype = C.c_double
@@ -190,6 +195,32 @@ class Oracle:
 
     def fv_slope(self, x):
         return self.lib.ora_fv_slope(float(x))
+
+    def fv_root(self, A, R, beta):
+        """The fibre velocity v with A f_v(v) + beta v = R (bisection)."""
+        return self.lib.ora_fv_root(float(A), float(R), float(beta))
+
+    def step_tendon(self, dt, q, qd, act, lm, u, eps0, beta, contact=True, stages=False):
+        """One step of one env with compliant tendons; lm[n_mus] is the
+        fibre length in metres. Returns (q', qd', act', lm', status[,
+        stages]); stages F is the force of the right-hand side, lm and vm
+        the normalised fibre length and velocity at the start."""
+        q, qd, act, lm = _d(q).copy(), _d(qd).copy(), _d(act).copy(), _d(lm).copy()
+        out = None
+        st_arrays = {}
+        if stages:
+            nm, nv = self.n_mus, self.nv
+            shapes = dict(act=nm, L=nm, Ldot=nm, F=nm, lm=nm, vm=nm, r=(nm, nv),
+                          tau_mus=nv, tau_ext=nv, tau_d=nv, C=nv, qdd=nv, tau_eq=nv,
+                          M=(nv, nv), D=(nv, nv))
+            st_arrays = {k: np.zeros(s) for k, s in shapes.items()}
+            out = _StageOut(**{k: v.ctypes.data for k, v in st_arrays.items()})
+        st = self.lib.ora_step_tendon(self.h, dt, int(contact), q, qd, act, lm, _d(u),
+                                      float(eps0), float(beta),
+                                      C.byref(out) if out is not None else None)
+        if stages:
+            return q, qd, act, lm, st, st_arrays
+        return q, qd, act, lm, st
 
     def contact(self, q, qd, dt, with_slope=False):
         tau = np.zeros(self.nv)

@@ -103,3 +103,20 @@ def twin_chains(n_link=6, seed=4):
         two[k] = np.concatenate([m[k], m[k]])
     two["name"] = f"twin{n}"
     return synth._finish(two)
+
+
+def maxwell_slide(m=2.0, F0=500.0, l_opt=0.1, l_slack=0.2, d=0.28):
+    """A point mass on a slide along x with one muscle from the world point
+    (-d, 0, 0) to the mass: path length L = d + x, moment arm -1. No
+    gravity, no damping."""
+    return _base([-1], [1], [[0, 0, 0]], [[1, 0, 0]], [m], [[0, 0, 0]], [[1e-4] * 3],
+                 muscles=[(F0, l_opt, l_slack, [(-1, [-d, 0, 0]), (0, [0, 0, 0])])],
+                 gravity=(0, 0, 0))
+
+
+def fixed_path_muscle(F0=800.0, l_opt=0.1, l_slack=0.2, L=0.31):
+    """A muscle whose path (length L) runs between two world points beside a
+    slide that it does not cross."""
+    return _base([-1], [1], [[0, 0, 0]], [[1, 0, 0]], [1.0], [[0, 0, 0]], [[1e-4] * 3],
+                 muscles=[(F0, l_opt, l_slack, [(-1, [0, 1, 0]), (-1, [L, 1, 0])])],
+                 gravity=(0, 0, 0))

@@ -286,6 +286,45 @@ ms_status ms_rollout_record(ms_model *m, int32_t n_env, float *q, float *qd,
                             int32_t n_steps, const ms_step_opts *opts,
                             const ms_record *rec, void *stream);
 
+/* Compliant tendons, a higher-fidelity variant of the Hill muscle-tendon
+ * unit (Methods, "Whole-body musculoskeletal model": muscle-tendon units
+ * driven by activation; the rigid tendon of ms_rollout is the paper's).
+ * Each muscle carries a fibre length lm (m) as a state. The tendon is
+ * linear above its slack length l_slack, with strain eps0 at F0, and
+ * carries no force below it:
+ *   F_t = F0 max(0, (L - lm - l_slack) / l_slack) / eps0.
+ * The fibre (no pennation) obeys the damped balance
+ *   F0 [act f_l(lm / l_opt) f_v(v) + f_p(lm / l_opt) + beta v]
+ * with v its velocity in v_max l_opt. At the start of a step v balances the
+ * fibre against the tendon (a closed-form root: the balance is strictly
+ * increasing in v). The tendon (slope k) and the fibre (slope b) act in
+ * series on the skeleton, as a force F_t + c (Ldot' - v) of the new
+ * lengthening rate Ldot', with c = k dt / (1 + k dt / b). Its explicit part
+ * goes into the right-hand side, c into the implicit muscle damping
+ * J_m^T c J_m. After the solve each fibre moves by
+ *   dt (v + (c / b) (Ldot' - v)),   Ldot' = -r qd'
+ * (moment arms of the step's start). */
+typedef struct {
+  float eps0; /* tendon strain at F0 (> 0; 0.033 is the usual value) */
+  float beta; /* fibre damping in F0 per v_max l_opt (> 0; 0.1 is usual) */
+} ms_tendon;
+
+/* ms_rollout with compliant tendons. lm[n_env][n_mus] (device, float32,
+ * caller's muscle order) holds the fibre lengths in metres and advances
+ * with the state. An env that fails a step keeps its whole state, lm
+ * included, as in ms_rollout. Always on the split schedule, the batch in
+ * stream parts as ms_rollout's. The first call with more envs than before
+ * allocates a fibre scratch of 20 n_mus bytes per env, and synchronises;
+ * inside a stream capture that growth is refused (MS_E_ARG), so a captured
+ * rollout needs an eager call of at least as many envs before it.
+ * MS_E_ARG as for ms_rollout, and for ten or lm NULL, eps0 or beta not
+ * positive and finite, or a model with a muscle whose l_slack <= 0. */
+ms_status ms_rollout_tendon(ms_model *m, int32_t n_env, float *q, float *qd,
+                            float *act, float *lm, uint32_t *status,
+                            const ms_excitation *exc, int32_t n_steps,
+                            const ms_step_opts *opts, const ms_tendon *ten,
+                            void *stream);
+
 /* Stage outputs of one step for n_env envs (device buffers, any may be
  * NULL): activation act'[E][n_mus], L, Ldot, F [E][n_mus], moment arms
  * r[E][n_mus][3] with their DoF indices from ms_model_spans, tau_mus[E][nv],

@@ -111,6 +111,24 @@ ms_status reserve_split(ms_model *m, int n_env, hipStream_t st) {
   return MS_OK;
 }
 
+// The compliant-tendon fibre scratch (5 n_mus floats per env), grown like
+// the split workspace.
+ms_status reserve_fib(ms_model *m, int n_env, hipStream_t st) {
+  if (n_env <= m->fib_cap) return MS_OK;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(st, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone)
+    return fail(MS_E_ARG, "the fibre scratch holds " + std::to_string(m->fib_cap) +
+                              " envs, fewer than " + std::to_string(n_env) +
+                              ": run a tendon rollout of as many envs before capturing");
+  void *p = nullptr;
+  if (hipMalloc(&p, std::max<size_t>((size_t)n_env * 5 * m->t.n_mus * 4, 4)) != hipSuccess)
+    return fail(MS_E_ALLOC, "fibre scratch allocation failed (" + std::to_string(n_env) + " envs)");
+  m->ws_owned.push_back(p);
+  m->fib = (float *)p;
+  m->fib_cap = n_env;
+  return MS_OK;
+}
+
 // Parts of a split-step launch over n_env envs when `parts` were asked for:
 // sets the model's envs per workgroup for them and the env bounds
 // (bounds[h] .. bounds[h + 1] for part h); returns the number of non-empty
@@ -142,7 +160,8 @@ hipError_t launch(ms_model *m, const ms::KRun &r, int n_env, int n_steps, hipStr
   const int nvia = m->t.n_via_max;
   // a coupled model's surrogate step runs on the split schedule only
   const bool coupled_surr = m->t.n_eq > 0 && r.geomY;
-  if (r.stages || (effective_schedule(m) == MS_SCHED_FUSED && !coupled_surr)) {
+  // compliant tendons run on the split schedule only
+  if (r.stages || (effective_schedule(m) == MS_SCHED_FUSED && !coupled_surr && !r.lm)) {
     if (nvia <= 2) return ms::launch_nvia<2>(m->t, m->k, r, n_env, n_steps, st);
     if (nvia <= 4) return ms::launch_nvia<4>(m->t, m->k, r, n_env, n_steps, st);
     if (nvia <= 6) return ms::launch_nvia<6>(m->t, m->k, r, n_env, n_steps, st);
@@ -232,7 +251,7 @@ hipError_t launch(ms_model *m, const ms::KRun &r, int n_env, int n_steps, hipStr
 }
 
 ms_status run_steps(ms_model *m, const ms::KRun &r, int n_env, int n_steps, hipStream_t st) {
-  if (!r.stages && effective_schedule(m) == MS_SCHED_SPLIT) {
+  if (!r.stages && (effective_schedule(m) == MS_SCHED_SPLIT || r.lm)) {
     const ms_status s = reserve_split(m, n_env, st);
     if (s != MS_OK) return s;
   }
@@ -542,6 +561,22 @@ ms_status ms_rollout_record(ms_model *m, int32_t n_env, float *q, float *qd, flo
                       rec);
 }
 
+ms_status ms_rollout_tendon(ms_model *m, int32_t n_env, float *q, float *qd, float *act,
+                            float *lm, uint32_t *status, const ms_excitation *exc,
+                            int32_t n_steps, const ms_step_opts *opts, const ms_tendon *ten,
+                            void *stream) {
+  g_err.clear();
+  if (!m) return fail(MS_E_ARG, "model is NULL");
+  if (!ten || !lm) return fail(MS_E_ARG, "ten or lm is NULL");
+  if (!(ten->eps0 > 0.0f) || !std::isfinite(ten->eps0) || !(ten->beta > 0.0f) ||
+      !std::isfinite(ten->beta))
+    return fail(MS_E_ARG, "ten->eps0 and ten->beta must be positive and finite");
+  for (float ls : m->t.mus_lslack)
+    if (!(ls > 0.0f)) return fail(MS_E_ARG, "compliant tendons need every l_slack > 0");
+  return rollout_impl(m, n_env, q, qd, act, status, exc, n_steps, opts, 0, (hipStream_t)stream,
+                      nullptr, false, lm, ten);
+}
+
 ms_status ms_model_set_key_nodes(ms_model *m, int32_t n_key, const int32_t *nodes) {
   g_err.clear();
   if (!m || n_key < 0 || n_key > 64 || (n_key > 0 && !nodes))
@@ -569,7 +604,8 @@ ms_status ms_model_set_key_nodes(ms_model *m, int32_t n_key, const int32_t *node
 ms_status rollout_impl(ms_model *m, int32_t n_env, float *q, float *qd, float *act,
                        uint32_t *status, const ms_excitation *exc, int32_t n_steps,
                        const ms_step_opts *opts, int env_per_wg, hipStream_t st,
-                       const ms_record *rec, bool one_stream) {
+                       const ms_record *rec, bool one_stream, float *lm,
+                       const ms_tendon *ten) {
   g_err.clear();
   ms_status s = common_checks(m, n_env, q, qd, act, opts);
   if (s != MS_OK) return s;
@@ -601,6 +637,15 @@ ms_status rollout_impl(ms_model *m, int32_t n_env, float *q, float *qd, float *a
     r.r_act = rec->act; r.r_F = rec->force; r.r_lm = rec->lm; r.r_vm = rec->vm;
     r.r_pow = rec->power; r.r_xpos = rec->xpos; r.r_xmat = rec->xmat;
     r.n_applied = rec->n_applied;
+  }
+  if (lm) {
+    const ms_status fs = reserve_fib(m, n_env, st);
+    if (fs != MS_OK) return fs;
+    r.lm = lm;
+    r.fib = m->fib;
+    r.fib_stride = 5 * m->t.n_mus;
+    r.ten_ieps = 1.0f / ten->eps0;
+    r.ten_beta = ten->beta;
   }
   return run_steps(m, r, n_env, n_steps, st);
 }

@@ -121,6 +121,22 @@ __device__ __forceinline__ float hill_fv_slope(float vm) {
   float b = vm + 0.08f;
   return 0.032f / (b * b);
 }
+// The normalised fibre velocity v with A f_v(v) + beta v = R (A >= 0,
+// beta > 0): the left-hand side rises from -beta at v = -1 to A at v = 0,
+// so R picks the branch; on each hyperbola branch the balance is a
+// quadratic in v, solved in the form that does not cancel near its small
+// root.
+__device__ __forceinline__ float hill_fv_root(float A, float R, float beta) {
+  if (R <= -beta) return R / beta;  // f_v = 0 below v = -1
+  if (R <= A) {
+    // concentric: 4 beta v^2 - (A + beta + 4 R) v + (R - A) = 0, v in [-1, 0]
+    const float b = A + beta + 4.0f * R;
+    return 2.0f * (R - A) / (b + sqrtf(b * b + 16.0f * beta * (A - R)));
+  }
+  // eccentric: beta v^2 + (1.4 A + 0.08 beta - R) v - 0.08 (R - A) = 0, v > 0
+  const float b = 1.4f * A + 0.08f * beta - R;
+  return 0.16f * (R - A) / (b + sqrtf(b * b + 0.32f * beta * (R - A)));
+}
 
 // Value of v held by lane `src` (uniform), for every lane.
 __device__ __forceinline__ double lane_bcast(double v, int src) {
@@ -721,7 +737,15 @@ __device__ __forceinline__ void activate(const KModel &M, const KRun &Rn, const 
 // mass matrix (rhs, H) or go to the split step's device workspace
 // (tau_out[nv], dsum_out[n_dent]). Returns false for the geometry-only
 // variant, which stops after the geometry.
-template <int MPT, int NVIA, bool SURR, bool GEOM, class Team>
+//
+// TEN: compliant tendons. With the fibre length l_f (Rn.lm) the tendon
+// (strain e = (L - l_f - l_s) / l_s, force F0 e / eps0 above slack, slope k)
+// and the fibre (F0 [a f_l f_v(v) + f_p + beta v], slope b at the velocity v
+// that balances the tendon) act in series: the force F_t + c (Ldot' - v) of
+// the new lengthening rate Ldot', c = k dt / (1 + k dt / b), enters as the
+// explicit force F_t + c (Ldot - v) and the implicit slope c. The moment
+// arms, v and c / b go to Rn.fib for the fibre update after the solve.
+template <int MPT, int NVIA, bool SURR, bool GEOM, bool TEN = false, class Team>
 __device__ __forceinline__ void stage_muscles(const KModel &M, const KRun &Rn, const Team &T, int env,
                                               int step, const float *Rl, const float *Pl,
                                               const float *Sl, const float *q, const float *qd,
@@ -815,12 +839,35 @@ __device__ __forceinline__ void stage_muscles(const KModel &M, const KRun &Rn, c
     const int m = T.t + T.n * k;
     if (m >= nm) continue;
     const float L = mF[m], Ld = mc[m];
-    const float lm = (L - M.mus_lslack[m]) * M.mus_ilopt[m];
-    const float vm = Ld * M.mus_ivl[m];
-    const float fl = hill_fl(lm), fv = hill_fv(vm), fp = hill_fp(lm);
     const float f0 = M.mus_f0[m];
-    const float F = f0 * (act1[k] * fl * fv + fp);
-    const float cdamp = f0 * act1[k] * fl * hill_fv_slope(vm) * M.mus_ivl[m];
+    float F, cdamp, lm, vm;
+    if constexpr (TEN) {
+      const float ls = M.mus_lslack[m];
+      const float lf = Rn.lm[(size_t)env * nm + M.mus_ext[m]];
+      const float strain = (L - lf - ls) / ls;
+      const float ft = strain > 0.0f ? strain * Rn.ten_ieps : 0.0f;
+      const float kdt = strain > 0.0f ? f0 * Rn.ten_ieps / ls * dt : 0.0f;
+      lm = lf * M.mus_ilopt[m];
+      const float A = act1[k] * hill_fl(lm);
+      vm = hill_fv_root(A, ft - hill_fp(lm), Rn.ten_beta);
+      const float b = f0 * (A * hill_fv_slope(vm) + Rn.ten_beta) * M.mus_ivl[m];
+      const float c = kdt / (1.0f + kdt / b);
+      const float v = vm / M.mus_ivl[m];
+      F = f0 * ft + c * (Ld - v);
+      cdamp = c;
+      float *fb = Rn.fib + (size_t)env * Rn.fib_stride;
+      fb[m] = mr[3 * m];
+      fb[nm + m] = mr[3 * m + 1];
+      fb[2 * nm + m] = mr[3 * m + 2];
+      fb[3 * nm + m] = v;
+      fb[4 * nm + m] = c / b;
+    } else {
+      lm = (L - M.mus_lslack[m]) * M.mus_ilopt[m];
+      vm = Ld * M.mus_ivl[m];
+      const float fl = hill_fl(lm), fv = hill_fv(vm), fp = hill_fp(lm);
+      F = f0 * (act1[k] * fl * fv + fp);
+      cdamp = f0 * act1[k] * fl * hill_fv_slope(vm) * M.mus_ivl[m];
+    }
     mF[m] = F;
     mc[m] = cdamp;
     if (stages) Rn.o_F[(size_t)env * nm + M.mus_ext[m]] = F;
@@ -1280,7 +1327,7 @@ __global__ __launch_bounds__(256) void k_geometry(KModel M, KRun Rn, int n_steps
 // fallback check), Hill force, J_m^T F and the muscles' implicit damping,
 // from the node frames and motion subspaces the kinematics kernel left in
 // the workspace. MPT = muscles per thread.
-template <int MPT, int NVIA, bool SURR>
+template <int MPT, int NVIA, bool SURR, bool TEN = false>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7, 7))) void k_muscle(KModel M, KRun Rn, KSplit W, int step) {
   extern __shared__ __align__(16) unsigned char lds_m[];
   const int env = Rn.env_begin + blockIdx.x;
@@ -1303,7 +1350,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7, 7))) voi
     xar[k] = 0.0f;
     if (Rn.exc == EXC_AR1 && mi < nm) xar[k] = Rn.xar[(size_t)env * nm + mx];
   }
-  const bool abad = excite<MPT>(M, Rn, T, env, step, act, xar, u);
+  bool abad = excite<MPT>(M, Rn, T, env, step, act, xar, u);
+  if constexpr (TEN) {
+    // the fibre lengths are state: a non-finite one stops the env like a
+    // non-finite activation
+#pragma unroll
+    for (int k = 0; k < MPT; ++k) {
+      const int mi = T.t + 256 * k;
+      if (mi < nm) abad |= !isfinite(Rn.lm[(size_t)env * nm + M.mus_ext[mi]]);
+    }
+  }
   // the smooth-noise state advances whatever the env's state (as in the
   // fused step)
   if (Rn.exc == EXC_AR1) {
@@ -1326,7 +1382,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7, 7))) voi
   __syncthreads();
   const V3 O = M.free_root ? v3(q[0], q[1], q[2]) : v3(0.f, 0.f, 0.f);
   unsigned status = 0;
-  stage_muscles<MPT, NVIA, SURR, false>(M, Rn, T, env, step, Rl, Pl, Sl, q, qd, O, act1, scr, Rn.dt,
+  stage_muscles<MPT, NVIA, SURR, false, TEN>(M, Rn, T, env, step, Rl, Pl, Sl, q, qd, O, act1, scr, Rn.dt,
                                         false, nullptr, nullptr, W.tau + (size_t)env * W.tau_stride,
                                         W.dsum + (size_t)env * W.dsum_stride, status,
                                         rec_slices(M, Rn, env, step));
@@ -1350,18 +1406,23 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7, 7))) voi
 template <int NVIA>
 hipError_t launch_muscle(const KModel &k, const KRun &r, const KSplit &w, int mpt, int step,
                          hipStream_t st) {
-  const bool surr = r.geomY != nullptr;
+  const bool surr = r.geomY != nullptr, ten = r.lm != nullptr;
+  if (surr && ten) return hipErrorNotSupported;
   const dim3 grid((r.env_end ? r.env_end : r.n_env) - r.env_begin), block(256);
   const size_t lds = w.m_bytes;
 #define MS_LAUNCH_M(P)                                                                         \
   do {                                                                                         \
-    const void *fn = surr ? (const void *)&k_muscle<P, NVIA, true> : (const void *)&k_muscle<P, NVIA, false>; \
+    const void *fn = surr  ? (const void *)&k_muscle<P, NVIA, true>                            \
+                     : ten ? (const void *)&k_muscle<P, NVIA, false, true>                     \
+                           : (const void *)&k_muscle<P, NVIA, false>;                          \
     if (lds > 65536) {                                                                         \
       hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds); \
       if (e != hipSuccess) return e;                                                           \
     }                                                                                          \
     if (surr)                                                                                  \
       hipLaunchKernelGGL((k_muscle<P, NVIA, true>), grid, block, lds, st, k, r, w, step);     \
+    else if (ten)                                                                              \
+      hipLaunchKernelGGL((k_muscle<P, NVIA, false, true>), grid, block, lds, st, k, r, w, step); \
     else                                                                                       \
       hipLaunchKernelGGL((k_muscle<P, NVIA, false>), grid, block, lds, st, k, r, w, step);    \
   } while (0)

@@ -120,6 +120,38 @@ __global__ __launch_bounds__(1024) void k_back(KModel M, KRun Rn, KSplit W, int 
     if (lane == 0 && Rn.status) Rn.status[env] |= MS_ST_NONFINITE;
     return;
   }
+  if (Rn.lm) {
+    // compliant tendons: each fibre moves by dt (v + (c / b) (Ldot' - v)),
+    // Ldot' = -r qd' with the step's moment arms; all of them are checked
+    // before anything is written, so that a failing env keeps its whole
+    // state
+    const float *fb = Rn.fib + (size_t)env * Rn.fib_stride;
+    float *lf = Rn.lm + (size_t)env * nm;
+    auto fibre = [&](int m) {
+      float ld = 0.0f;
+#pragma unroll
+      for (int sl = 0; sl < 3; ++sl) {
+        const int j = M.mus_span[sl * nm + m];
+        if (j >= 0) ld -= fb[sl * nm + m] * qd[j];
+      }
+      const float v = fb[3 * nm + m];
+      return lf[M.mus_ext[m]] + dt * (v + fb[4 * nm + m] * (ld - v));
+    };
+    float nl[16];   // up to 1024 muscles, 16 per lane
+    bool bad = false;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      nl[i] = lane + 64 * i < nm ? fibre(lane + 64 * i) : 0.0f;
+      bad |= !isfinite(nl[i]);
+    }
+    if (__any(bad)) {
+      if (lane == 0 && Rn.status) Rn.status[env] |= MS_ST_NONFINITE;
+      return;
+    }
+#pragma unroll
+    for (int i = 0; i < 16; ++i)
+      if (lane + 64 * i < nm) lf[M.mus_ext[lane + 64 * i]] = nl[i];
+  }
   for (int i = lane; i < nq; i += 64) Rn.q[(size_t)env * nq + i] = q[i];
   for (int i = lane; i < nv; i += 64) Rn.qd[(size_t)env * nv + i] = qd[i];
   const float *an = W.actn + (size_t)env * W.act_stride;

@@ -90,6 +90,15 @@ struct KRun {
   // split step: keep every kernel on the launch stream (no half-batch on
   // the model's second stream); set for launches an ms_batch drives
   int one_stream;
+  // compliant tendons (split step only; lm NULL: rigid tendons): fibre
+  // lengths lm[n_env][n_mus] (m, caller's muscle order), 1 / eps0 and the
+  // fibre damping beta. The muscle kernel leaves, per env and internal
+  // muscle slot m, fib[env * fib_stride + k * n_mus + m] for k = 0..4: the
+  // moment arms r[3] of the span slots, the balancing fibre velocity v
+  // (m/s) and c / b, read by the fibre update after the solve.
+  float *lm, *fib;
+  int fib_stride;
+  float ten_ieps, ten_beta;
 };
 
 // This env's slices of the muscle observables of one recorded step (NULL:
@@ -182,6 +191,10 @@ struct ms_model {
   ms::KSplit ks{};
   int ws_cap = 0;
   std::vector<void *> ws_owned;
+  // compliant-tendon fibre scratch for up to fib_cap envs (5 n_mus floats
+  // each; replaced buffers stay in ws_owned)
+  float *fib = nullptr;
+  int fib_cap = 0;
   // envs per workgroup of its kernels, chosen for w_n_env envs in w_parts concurrent parts
   int w_front = 0, w_back = 0, w_n_env = 0, w_parts = 0;
   // the split step's second stream and its fork/join events (two halves of
@@ -223,10 +236,12 @@ hipError_t launch(ms_model *m, const ms::KRun &r, int n_env, int n_steps, hipStr
 ms_status run_steps(ms_model *m, const ms::KRun &r, int n_env, int n_steps, hipStream_t st);
 
 // ms_rollout with a chosen number of envs per workgroup (1, 2 or 4; 0 picks
-// the count that keeps the most envs resident per CU) and, with one_stream,
-// every kernel of the split step on st; errors as ms_rollout (message in
-// ms_last_error).
+// the count that keeps the most envs resident per CU), with one_stream,
+// every kernel of the split step on st, and with lm, compliant tendons
+// (ms_rollout_tendon, whose checks the caller has made); errors as
+// ms_rollout (message in ms_last_error).
 ms_status rollout_impl(ms_model *m, int32_t n_env, float *q, float *qd, float *act,
                        uint32_t *status, const ms_excitation *exc, int32_t n_steps,
                        const ms_step_opts *opts, int env_per_wg, hipStream_t st,
-                       const ms_record *rec = nullptr, bool one_stream = false);
+                       const ms_record *rec = nullptr, bool one_stream = false,
+                       float *lm = nullptr, const ms_tendon *ten = nullptr);

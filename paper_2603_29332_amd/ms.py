@@ -39,7 +39,8 @@ EXPORTED = ("ms_model_create", "ms_model_destroy", "ms_model_info_get",
             "ms_rollout_record", "ms_surrogate_train", "ms_surrogate_save", "ms_surrogate_load",
             "ms_controller_create", "ms_controller_destroy", "ms_controller_dims",
             "ms_controller_params", "ms_controller_reserve", "ms_controller_step",
-            "ms_controller_last_error", "ms_model_set_split_streams", "ms_model_split_parts")
+            "ms_controller_last_error", "ms_model_set_split_streams", "ms_model_split_parts",
+            "ms_rollout_tendon")
 
 _fptr = C.POINTER(C.c_float)
 _iptr = C.POINTER(C.c_int32)
@@ -79,6 +80,10 @@ class MsExc(C.Structure):
 class MsRecord(C.Structure):
     _fields_ = [("every", C.c_int32)] + [(k, C.c_void_p) for k in (
         "act", "force", "lm", "vm", "power", "xpos", "xmat", "n_applied")]
+
+
+class MsTendon(C.Structure):
+    _fields_ = [("eps0", C.c_float), ("beta", C.c_float)]
 
 
 class MsTrainCfg(C.Structure):
@@ -135,6 +140,8 @@ def lib():
     L.ms_model_set_key_nodes.argtypes = [vp, C.c_int32, _iptr]
     L.ms_rollout_record.argtypes = [vp, C.c_int32, vp, vp, vp, vp, C.POINTER(MsExc), C.c_int32,
                                     C.POINTER(MsOpts), C.POINTER(MsRecord), vp]
+    L.ms_rollout_tendon.argtypes = [vp, C.c_int32, vp, vp, vp, vp, vp, C.POINTER(MsExc),
+                                    C.c_int32, C.POINTER(MsOpts), C.POINTER(MsTendon), vp]
     L.ms_step_batch.argtypes = [vp, C.c_int32, vp, vp, vp, vp, vp, C.POINTER(MsOpts), vp]
     L.ms_rollout.argtypes = [vp, C.c_int32, vp, vp, vp, vp, C.POINTER(MsExc), C.c_int32,
                              C.POINTER(MsOpts), vp]
@@ -366,6 +373,20 @@ class Model:
                   float(ar1[2]))
         _check(lib().ms_rollout(self.h, n_env, _dp(q), _dp(qd), _dp(act), _dp(status),
                                 C.byref(e), n_steps, C.byref(o), _stream(stream)))
+
+    def rollout_tendon(self, q, qd, act, lm, status, n_steps, dt, contact=True, eps0=0.033,
+                       beta=0.1, kind=EXC_ARRAY, u=None, seed=0, step0=0, x=None,
+                       ar1=(0.0, 0.0, 0.0), stream=None):
+        """rollout() with compliant tendons; lm (device float32 [n_env][n_mus],
+        metres) is the fibre length, advanced with the state."""
+        n_env = q.shape[0]
+        o = MsOpts(dt, int(contact))
+        e = MsExc(kind, _dp(u), seed, step0, _dp(x), float(ar1[0]), float(ar1[1]),
+                  float(ar1[2]))
+        t = MsTendon(float(eps0), float(beta))
+        _check(lib().ms_rollout_tendon(self.h, n_env, _dp(q), _dp(qd), _dp(act), _dp(lm),
+                                       _dp(status), C.byref(e), n_steps, C.byref(o),
+                                       C.byref(t), _stream(stream)))
 
     def set_key_nodes(self, nodes):
         """Key nodes whose world frames rollout_record writes."""

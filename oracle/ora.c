@@ -761,11 +761,11 @@ uint32_t ora_step(const ora_model *m, double dt, int contact_on, double *q,
 
 /* Compliant-tendon muscles at the start of a step (see ora_step_tendon):
  * per muscle the force of the right-hand side F, its slope c in the new
- * lengthening rate, the balancing fibre velocity v (m/s) and c / b. */
+ * lengthening rate and the balancing fibre velocity v (m/s). */
 static void tendon_forces(const ora_model *m, const double *act1, const double *L,
                           const double *Ld, const double *lm, double dt, double eps0,
-                          double beta, double *F, double *c, double *v, double *rho,
-                          double *lm_out, double *vm_out) {
+                          double beta, double *F, double *c, double *v, double *lm_out,
+                          double *vm_out) {
   for (int i = 0; i < m->n_mus; ++i) {
     const double ls = m->l_slack[i], f0 = m->f0[i];
     const double strain = (L[i] - lm[i] - ls) / ls;           /* tendon strain */
@@ -780,10 +780,39 @@ static void tendon_forces(const ora_model *m, const double *act1, const double *
     v[i] = vn * vs;
     F[i] = f0 * ft + cs * (Ld[i] - v[i]);
     c[i] = cs;
-    rho[i] = cs / b;
     if (lm_out) lm_out[i] = l;
     if (vm_out) vm_out[i] = vn;
   }
+}
+
+/* Backward Euler on one fibre: the new length l' = l + dt v_max l_opt v'
+ * balances fibre and tendon at the path length Ln,
+ *   g(v') = act f_l(l'/l_opt) f_v(v') + f_p(l'/l_opt) + beta v'
+ *           - max(0, (Ln - l' - l_slack) / l_slack) / eps0 = 0.
+ * g rises strictly in v' (its velocity slope, at least beta / (dt v_max l_opt)
+ * per metre, exceeds the largest fall of act f_l), so bisection finds the
+ * one root: g <= 1.4 act + f_p(l / l_opt) + beta v' < 0 at
+ * v' = min(0, -(1.4 act + f_p(l / l_opt)) / beta) - 1, and
+ * g >= beta v' - f_t(Ln - l) > 0 at v' = max(0, f_t(Ln - l) / beta) + 1. */
+static double fibre_update(const ora_model *m, int i, double act, double l, double Ln,
+                           double dt, double eps0, double beta) {
+  const double lo_m = m->l_opt[i], ls = m->l_slack[i];
+  const double dl = dt * m->v_max[i] * lo_m;   /* metres per unit of v' */
+  const double ft0 = fmax(0.0, (Ln - l - ls) / ls) / eps0;
+  double lo = fmin(0.0, -(1.4 * act + ora_fp(l / lo_m)) / beta) - 1.0;
+  double hi = fmax(0.0, ft0 / beta) + 1.0;
+  for (int it = 0; it < 2000; ++it) {
+    const double v = 0.5 * (lo + hi);
+    if (v <= lo || v >= hi) break;
+    const double ln = l + dl * v;
+    const double g = act * ora_fl(ln / lo_m) * ora_fv(v) + ora_fp(ln / lo_m) + beta * v -
+                     fmax(0.0, (Ln - ln - ls) / ls) / eps0;
+    if (g < 0.0)
+      lo = v;
+    else
+      hi = v;
+  }
+  return l + dl * 0.5 * (lo + hi);
 }
 
 static uint32_t step_core(const ora_model *m, double dt, int contact_on, double *q,
@@ -796,7 +825,6 @@ static uint32_t step_core(const ora_model *m, double dt, int contact_on, double 
     return ORA_ST_NONFINITE;
   double *cmu = (double *)malloc(sizeof(double) * nm);
   double *vf = (double *)malloc(sizeof(double) * nm);
-  double *rho = (double *)malloc(sizeof(double) * nm);
   double *lmn = (double *)malloc(sizeof(double) * nm);
   double *act1 = (double *)malloc(sizeof(double) * nm);
   double *L = (double *)malloc(sizeof(double) * nm);
@@ -830,7 +858,7 @@ static uint32_t step_core(const ora_model *m, double dt, int contact_on, double 
     ora_geometry(m, q, qd, L, r, Ld);
   }
   if (lmf) {
-    tendon_forces(m, act1, L, Ld, lmf, dt, eps0, beta, F, cmu, vf, rho, out ? out->lm : NULL,
+    tendon_forces(m, act1, L, Ld, lmf, dt, eps0, beta, F, cmu, vf, out ? out->lm : NULL,
                   out ? out->vm : NULL);
   } else {
     ora_hill(m, act1, L, Ld, F, out ? out->lm : NULL, out ? out->vm : NULL);
@@ -894,12 +922,12 @@ static uint32_t step_core(const ora_model *m, double dt, int contact_on, double 
       for (int k = 0; k < 4; ++k) qn[a + 3 + k] = o[k] / nrm;
     }
     if (lmf) {
-      /* the fibre moves with the velocity of the series element at the new
-       * lengthening rate */
+      /* the fibre takes a backward-Euler step against the path length at the
+       * step's end (first order: L + dt Ldot', Ldot' = -r qd') */
       for (int mu = 0; mu < nm; ++mu) {
         double ldn = 0.0;
         for (int j = 0; j < nv; ++j) ldn -= r[(size_t)mu * nv + j] * qdn[j];
-        lmn[mu] = lmf[mu] + dt * (vf[mu] + rho[mu] * (ldn - vf[mu]));
+        lmn[mu] = fibre_update(m, mu, act1[mu], lmf[mu], L[mu] + dt * ldn, dt, eps0, beta);
       }
     }
     if (!all_finite(qn, nq) || !all_finite(qdn, nv) || !all_finite(act1, nm) ||
@@ -927,7 +955,7 @@ static uint32_t step_core(const ora_model *m, double dt, int contact_on, double 
     memcpy(act, act1, sizeof(double) * nm);
     if (lmf) memcpy(lmf, lmn, sizeof(double) * nm);
   }
-  free(cmu); free(vf); free(rho); free(lmn);
+  free(cmu); free(vf); free(lmn);
   free(act1); free(L); free(Ld); free(F); free(r); free(M); free(tm); free(te);
   free(td); free(C); free(rhs); free(qdd); free(zero); free(qn); free(qdn);
   free(D); free(teq);

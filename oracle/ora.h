@@ -145,8 +145,10 @@ double ora_fv_root(double A, double R, double beta);
  * k) and the fibre (velocity slope b) in series act on the skeleton as a
  * force F_t + c (Ldot' - v) linear in the new lengthening rate Ldot', with
  * c = k dt / (1 + k dt / b), taken implicitly like the rigid muscle's
- * damping; after the solve the fibre moves by dt (v + c (Ldot' - v) / b)
- * with Ldot' = -r qd' (moment arms of the step's start). Stage outputs:
+ * damping. After the solve each fibre takes a backward-Euler step: its new
+ * length balances fibre and tendon at the path length L + dt Ldot',
+ * Ldot' = -r qd' (moment arms of the step's start); on a linear element
+ * this is the fibre velocity v + c (Ldot' - v) / b. Stage outputs:
  * F is the force of the right-hand side, lm and vm the normalised fibre
  * length and velocity at the start. Returns status bits; on a failure
  * nothing is updated. */

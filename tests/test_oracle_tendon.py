@@ -161,3 +161,30 @@ def test_stiff_tendon_limit_is_the_rigid_step():
         # the fibre followed the path: the tendon stays at its slack length
         Ln = o.geometry(qc, qdc)[0]
         np.testing.assert_allclose(Ln - lmc, m["l_slack"], rtol=0, atol=1e-8)
+
+
+def test_recoil_through_the_slack_point_does_not_overshoot():
+    """A passive fibre stretched to 1.5 optimal lengths behind a slack tendon
+    recoils at several centimetres per second (f_p / beta) onto its static
+    balance f_p(l) = f_t(L - l_m): the fibre length falls monotonically and
+    never passes the balance (Brent's method), so the tendon never carries
+    more than the balance force. An explicit step across the slack point
+    would overshoot by up to dt times the recoil speed."""
+    m = tm.fixed_path_muscle()
+    o = Oracle(m)
+    lopt, ls = float(m["l_opt"][0]), float(m["l_slack"][0])
+    L = float(o.geometry(np.zeros(1), np.zeros(1))[0][0])
+    q, qd, act, lmf = np.zeros(1), np.zeros(1), np.zeros(1), np.array([1.5 * lopt])
+    assert lmf[0] + ls > L                   # slack at the start
+    bal = lambda lm: o.fp(lm / lopt) - max((L - lm - ls) / ls, 0.0) / EPS0
+    l_static = brentq(bal, 0.5 * lopt, 1.5 * lopt, xtol=1e-15)
+    hist = [lmf[0]]
+    for _ in range(400):
+        q, qd, act, lmf, st = o.step_tendon(1e-3, q, qd, act, lmf, np.zeros(1), EPS0, BETA,
+                                            contact=False)
+        assert st == 0
+        hist.append(lmf[0])
+    hist = np.array(hist)
+    assert np.all(np.diff(hist) <= 1e-15)
+    assert hist.min() >= l_static - 1e-12
+    assert hist[-1] == pytest.approx(l_static, abs=1e-10)

@@ -62,6 +62,7 @@ def parse():
     p.add_argument("--no-uneven", action="store_true", help="skip the uneven-batch leg")
     p.add_argument("--no-policy", action="store_true", help="skip the policy-driven leg")
     p.add_argument("--no-control", action="store_true", help="skip the control-step leg")
+    p.add_argument("--no-tendon", action="store_true", help="skip the compliant-tendon leg")
     p.add_argument("--policy-envs", type=int, default=65536)
     p.add_argument("--policy-steps", type=int, default=2000)
     p.add_argument("--uneven-steps", type=int, default=500)
@@ -253,6 +254,9 @@ def main():
     progress("observables leg done")
     line["coupled"] = coupled_leg(m, dt, dev, E, (rho, s, mean), a.steps)
     progress("coupled leg done")
+    if not a.no_tendon:
+        line["tendon"] = tendon_leg(m, gm, dt, dev, E, (rho, s, mean), a.steps)
+        progress("tendon leg done")
     if not a.no_control:
         line["control"] = control_leg(m, gm, dt, dev)
         progress("control leg done")
@@ -427,6 +431,52 @@ def coupled_leg(m, dt, dev, E, ar1, n_calls):
             "steps": (1 + n_calls) * PHYS_PER_STEP, "max_abs_phi_rad": phi,
             "note": "scheduled env-steps/s of 100-step calls with the shoulder coupling; "
                     "max |phi| over the sampled envs that are not flagged, after all calls"}
+
+
+def tendon_leg(m, gm, dt, dev, E, ar1, n_calls, eps0=0.033, beta=0.1):
+    """The exact workload with compliant tendons (fibre-length state, tendon
+    strain eps0 at F0, fibre damping beta): 100-step calls of
+    ms_rollout_tendon timed with HIP events; fibres start 0.5 % of the slack
+    length short of the path, from the exact geometry of the initial pose."""
+    import torch
+
+    from paper_2603_29332_amd import ms, synth
+    q0, qd0, a0 = synth.human_initial_state(m, E)
+    q, qd, act = (torch.tensor(v, device=dev) for v in (q0, qd0, a0))
+    L = torch.empty(E, m["n_mus"], device=dev)
+    r = torch.empty(E, m["n_mus"], 3, device=dev)
+    gm.geometry(q, L, r)
+    lm = L - torch.tensor(m["l_slack"], device=dev) * 1.005
+    st = torch.zeros(E, dtype=torch.int32, device=dev)
+    x = torch.zeros(E, m["n_mus"], device=dev)
+    stream = torch.cuda.current_stream()
+
+    def call(k):
+        gm.rollout_tendon(q, qd, act, lm, st, PHYS_PER_STEP, dt, True, eps0=eps0, beta=beta,
+                          kind=ms.EXC_AR1, seed=12, step0=k * PHYS_PER_STEP, x=x, ar1=ar1,
+                          stream=stream)
+
+    call(0)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for k in range(n_calls):
+        call(1 + k)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_call = e0.elapsed_time(e1) / n_calls
+    ok = st == 0
+    lopt = torch.tensor(m["l_opt"], device=dev)
+    lmn = (lm / lopt)[ok]
+    gm.geometry(q, L, r)        # the rigid tendon's fibre length (L - l_slack) in the same poses
+    rig = ((L - torch.tensor(m["l_slack"], device=dev)) / lopt)[ok]
+    return {"env_steps_per_s": E * PHYS_PER_STEP / (ms_call / 1e3),
+            "ms_per_physics_step": ms_call / PHYS_PER_STEP, "eps0": eps0, "beta": beta,
+            "steps": (1 + n_calls) * PHYS_PER_STEP, "envs_flagged": int((~ok).sum()),
+            "fibre_length_over_l_opt": [float(lmn.min()), float(lmn.max())],
+            "rigid_tendon_fibre_length_over_l_opt": [float(rig.min()), float(rig.max())],
+            "note": "scheduled env-steps/s of 100-step calls with compliant tendons on the "
+                    "split schedule; flagged envs are not restarted in this leg"}
 
 
 def observables_leg(m, gm, dt, dev, E, ar1, every=10, n_calls=3):

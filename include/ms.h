@@ -301,9 +301,10 @@ ms_status ms_rollout_record(ms_model *m, int32_t n_env, float *q, float *qd,
  * series on the skeleton, as a force F_t + c (Ldot' - v) of the new
  * lengthening rate Ldot', with c = k dt / (1 + k dt / b). Its explicit part
  * goes into the right-hand side, c into the implicit muscle damping
- * J_m^T c J_m. After the solve each fibre moves by
- *   dt (v + (c / b) (Ldot' - v)),   Ldot' = -r qd'
- * (moment arms of the step's start). */
+ * J_m^T c J_m. After the solve each fibre takes a backward-Euler step: its
+ * new length balances fibre and tendon at the path length L + dt Ldot',
+ * Ldot' = -r qd' (moment arms of the step's start); on a linear element
+ * this moves the fibre by dt (v + (c / b) (Ldot' - v)). */
 typedef struct {
   float eps0; /* tendon strain at F0 (> 0; 0.033 is the usual value) */
   float beta; /* fibre damping in F0 per v_max l_opt (> 0; 0.1 is usual) */
@@ -312,13 +313,18 @@ typedef struct {
 /* ms_rollout with compliant tendons. lm[n_env][n_mus] (device, float32,
  * caller's muscle order) holds the fibre lengths in metres and advances
  * with the state. An env that fails a step keeps its whole state, lm
- * included, as in ms_rollout. Always on the split schedule, the batch in
+ * included, as in ms_rollout; a fibre length that comes out of the fibre
+ * update not finite (after the skeleton's step is committed) stays at its
+ * old value and sets MS_ST_NONFINITE, which stops the env from the next
+ * step on. Always on the split schedule, the batch in
  * stream parts as ms_rollout's. The first call with more envs than before
  * allocates a fibre scratch of 20 n_mus bytes per env, and synchronises;
  * inside a stream capture that growth is refused (MS_E_ARG), so a captured
  * rollout needs an eager call of at least as many envs before it.
  * MS_E_ARG as for ms_rollout, and for ten or lm NULL, eps0 or beta not
- * positive and finite, or a model with a muscle whose l_slack <= 0. */
+ * positive and finite, a model with a muscle whose l_slack <= 0, or
+ * beta <= 1.82 dt v_max for some muscle (the fibre balance then need not
+ * rise strictly in the fibre velocity). */
 ms_status ms_rollout_tendon(ms_model *m, int32_t n_env, float *q, float *qd,
                             float *act, float *lm, uint32_t *status,
                             const ms_excitation *exc, int32_t n_steps,

@@ -789,8 +789,8 @@ static void tendon_forces(const ora_model *m, const double *act1, const double *
  * balances fibre and tendon at the path length Ln,
  *   g(v') = act f_l(l'/l_opt) f_v(v') + f_p(l'/l_opt) + beta v'
  *           - max(0, (Ln - l' - l_slack) / l_slack) / eps0 = 0.
- * g rises strictly in v' (its velocity slope, at least beta / (dt v_max l_opt)
- * per metre, exceeds the largest fall of act f_l), so bisection finds the
+ * g rises strictly in v' when beta > 1.82 dt v_max (its slope is at least
+ * beta - 1.4 max|f_l'| dt v_max, max|f_l'| < 1.3), so bisection finds the
  * one root: g <= 1.4 act + f_p(l / l_opt) + beta v' < 0 at
  * v' = min(0, -(1.4 act + f_p(l / l_opt)) / beta) - 1, and
  * g >= beta v' - f_t(Ln - l) > 0 at v' = max(0, f_t(Ln - l) / beta) + 1. */

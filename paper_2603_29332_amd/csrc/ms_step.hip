@@ -240,6 +240,8 @@ hipError_t launch(ms_model *m, const ms::KRun &r, int n_env, int n_steps, hipStr
       });
     for (int h = 0; h < parts && e == hipSuccess; ++h)
       e = timed_launch(2, h == 0, [&] { return ms::launch_back(m->k, rh[h], w, m->w_back, s, sh[h]); });
+    for (int h = 0; h < parts && e == hipSuccess && r.lm; ++h)
+      e = ms::launch_fibre(m->k, rh[h], w, sh[h]);
     if (e != hipSuccess) return e;
   }
   for (int h = 1; h < parts; ++h) {
@@ -573,6 +575,14 @@ ms_status ms_rollout_tendon(ms_model *m, int32_t n_env, float *q, float *qd, flo
     return fail(MS_E_ARG, "ten->eps0 and ten->beta must be positive and finite");
   for (float ls : m->t.mus_lslack)
     if (!(ls > 0.0f)) return fail(MS_E_ARG, "compliant tendons need every l_slack > 0");
+  // the fibre's backward-Euler balance rises strictly in its velocity when
+  // beta exceeds 1.4 max|f_l'| dt v_max (max|f_l'| < 1.3)
+  if (opts && opts->dt > 0.0f)
+    for (int i = 0; i < m->t.n_mus; ++i) {
+      const float vmax = m->t.mus_ilopt[i] / m->t.mus_ivl[i];   // optimal lengths per second
+      if (!(ten->beta > 1.82f * opts->dt * vmax))
+        return fail(MS_E_ARG, "compliant tendons need beta > 1.82 dt v_max for every muscle");
+    }
   return rollout_impl(m, n_env, q, qd, act, status, exc, n_steps, opts, 0, (hipStream_t)stream,
                       nullptr, false, lm, ten);
 }

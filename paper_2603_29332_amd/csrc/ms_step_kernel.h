@@ -121,6 +121,16 @@ __device__ __forceinline__ float hill_fv_slope(float vm) {
   float b = vm + 0.08f;
   return 0.032f / (b * b);
 }
+// Slopes of f_l and f_p.
+__device__ __forceinline__ float hill_fl_slope(float lm) {
+  return -2.0f * (lm - 1.0f) * (1.0f / 0.45f) * hill_fl(lm);
+}
+__device__ __forceinline__ float hill_fp_slope(float lm) {
+  const float e4m1 = 53.598150033144236f;  // e^4 - 1
+  if (lm <= 1.0f) return 0.0f;
+  if (lm <= 1.6f) return (4.0f / 0.6f) * __expf((4.0f / 0.6f) * (lm - 1.0f)) * (1.0f / e4m1);
+  return 6.7910995f;
+}
 // The normalised fibre velocity v with A f_v(v) + beta v = R (A >= 0,
 // beta > 0): the left-hand side rises from -beta at v = -1 to A at v = 0,
 // so R picks the branch; on each hyperbola branch the balance is a
@@ -744,7 +754,8 @@ __device__ __forceinline__ void activate(const KModel &M, const KRun &Rn, const 
 // that balances the tendon) act in series: the force F_t + c (Ldot' - v) of
 // the new lengthening rate Ldot', c = k dt / (1 + k dt / b), enters as the
 // explicit force F_t + c (Ldot - v) and the implicit slope c. The moment
-// arms, v and c / b go to Rn.fib for the fibre update after the solve.
+// arms, the path length and the activation go to Rn.fib for the fibre
+// update after the solve.
 template <int MPT, int NVIA, bool SURR, bool GEOM, bool TEN = false, class Team>
 __device__ __forceinline__ void stage_muscles(const KModel &M, const KRun &Rn, const Team &T, int env,
                                               int step, const float *Rl, const float *Pl,
@@ -859,8 +870,8 @@ __device__ __forceinline__ void stage_muscles(const KModel &M, const KRun &Rn, c
       fb[m] = mr[3 * m];
       fb[nm + m] = mr[3 * m + 1];
       fb[2 * nm + m] = mr[3 * m + 2];
-      fb[3 * nm + m] = v;
-      fb[4 * nm + m] = c / b;
+      fb[3 * nm + m] = L;
+      fb[4 * nm + m] = act1[k];
     } else {
       lm = (L - M.mus_lslack[m]) * M.mus_ilopt[m];
       vm = Ld * M.mus_ivl[m];

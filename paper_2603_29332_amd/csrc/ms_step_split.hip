@@ -120,43 +120,73 @@ __global__ __launch_bounds__(1024) void k_back(KModel M, KRun Rn, KSplit W, int 
     if (lane == 0 && Rn.status) Rn.status[env] |= MS_ST_NONFINITE;
     return;
   }
-  if (Rn.lm) {
-    // compliant tendons: each fibre moves by dt (v + (c / b) (Ldot' - v)),
-    // Ldot' = -r qd' with the step's moment arms; all of them are checked
-    // before anything is written, so that a failing env keeps its whole
-    // state
-    const float *fb = Rn.fib + (size_t)env * Rn.fib_stride;
-    float *lf = Rn.lm + (size_t)env * nm;
-    auto fibre = [&](int m) {
-      float ld = 0.0f;
-#pragma unroll
-      for (int sl = 0; sl < 3; ++sl) {
-        const int j = M.mus_span[sl * nm + m];
-        if (j >= 0) ld -= fb[sl * nm + m] * qd[j];
-      }
-      const float v = fb[3 * nm + m];
-      return lf[M.mus_ext[m]] + dt * (v + fb[4 * nm + m] * (ld - v));
-    };
-    float nl[16];   // up to 1024 muscles, 16 per lane
-    bool bad = false;
-#pragma unroll
-    for (int i = 0; i < 16; ++i) {
-      nl[i] = lane + 64 * i < nm ? fibre(lane + 64 * i) : 0.0f;
-      bad |= !isfinite(nl[i]);
-    }
-    if (__any(bad)) {
-      if (lane == 0 && Rn.status) Rn.status[env] |= MS_ST_NONFINITE;
-      return;
-    }
-#pragma unroll
-    for (int i = 0; i < 16; ++i)
-      if (lane + 64 * i < nm) lf[M.mus_ext[lane + 64 * i]] = nl[i];
-  }
   for (int i = lane; i < nq; i += 64) Rn.q[(size_t)env * nq + i] = q[i];
   for (int i = lane; i < nv; i += 64) Rn.qd[(size_t)env * nv + i] = qd[i];
   const float *an = W.actn + (size_t)env * W.act_stride;
   for (int i = lane; i < nm; i += 64) Rn.act[(size_t)env * nm + i] = an[i];
   if (Rn.n_applied && lane == 0) Rn.n_applied[env] += 1u;
+  if (Rn.lm && lane == 0) W.mflag[env] = 4;   // committed: k_fibre moves its fibres
+}
+
+// Compliant tendons, after k_back: one thread per env and muscle (internal
+// slot m) of an env whose step k_back committed. The fibre takes a
+// backward-Euler step: its new length l' = l + dt v_max l_opt v' balances
+// fibre and tendon at the path length L + dt Ldot' (Ldot' = -r qd', moment
+// arms of the step's start):
+//   g(v') = a f_l(l') f_v(v') + f_p(l') + beta v' - f_t(L' - l') = 0.
+// g rises strictly in v' (slope at least beta - 1.82 dt v_max > 0, checked
+// by the entry point), below zero at v' = min(0, -(1.4 a + f_p(l)) / beta)
+// - 1 and above it at max(0, f_t(L' - l) / beta) + 1. Newton's method from
+// v' = 0, kept inside that shrinking bracket (a step that leaves it bisects
+// instead), stops when a step moves the length by at most 2e-8 l (under
+// half an ulp of l in float32) or v' by at most its own resolution. A
+// length that is not finite is not written and flags the env (its skeleton
+// state of this step stands).
+__global__ __launch_bounds__(256) void k_fibre(KModel M, KRun Rn, KSplit W) {
+  const int nm = M.n_mus;
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int e0 = Rn.env_begin, e1 = Rn.env_end ? Rn.env_end : Rn.n_env;
+  if (t >= (long long)(e1 - e0) * nm) return;
+  const int env = e0 + (int)(t / nm), m = (int)(t % nm);
+  if (W.mflag[env] != 4) return;
+  const float dt = Rn.dt, beta = Rn.ten_beta, ieps = Rn.ten_ieps;
+  const float *fb = Rn.fib + (size_t)env * Rn.fib_stride;
+  const float *qd = Rn.qd + (size_t)env * M.nv;
+  float ld = 0.0f;
+#pragma unroll
+  for (int sl = 0; sl < 3; ++sl) {
+    const int j = M.mus_span[sl * nm + m];
+    if (j >= 0) ld -= fb[sl * nm + m] * qd[j];
+  }
+  const float Ln = fb[3 * nm + m] + dt * ld, a = fb[4 * nm + m];
+  float *lp = Rn.lm + (size_t)env * nm + M.mus_ext[m];
+  const float l = *lp, ls = M.mus_lslack[m], ilo = M.mus_ilopt[m];
+  const float dl = dt / M.mus_ivl[m], dx = dl * ilo;   // d l' / d v', d (l' / l_opt) / d v'
+  float lo = fminf(0.0f, -(1.4f * a + hill_fp(l * ilo)) / beta) - 1.0f;
+  float hi = fmaxf(0.0f, fmaxf(0.0f, (Ln - l - ls) / ls) * ieps / beta) + 1.0f;
+  float v = 0.0f;
+  for (int it = 0; it < 64; ++it) {
+    const float ln = l + dl * v, x = ln * ilo, e = (Ln - ln - ls) / ls;
+    const float fl = hill_fl(x), fv = hill_fv(v);
+    const float g = a * fl * fv + hill_fp(x) + beta * v - fmaxf(0.0f, e) * ieps;
+    if (g < 0.0f)
+      lo = v;
+    else
+      hi = v;
+    const float gp = a * (hill_fl_slope(x) * dx * fv + fl * hill_fv_slope(v)) +
+                     hill_fp_slope(x) * dx + beta + (e > 0.0f ? ieps * dl / ls : 0.0f);
+    float vn = v - g / gp;
+    if (!(vn > lo && vn < hi)) vn = 0.5f * (lo + hi);
+    const float dv = fabsf(vn - v);
+    const bool done = dv * dl <= 2e-8f * l || dv <= 2.4e-7f * fabsf(v);
+    v = vn;
+    if (done) break;
+  }
+  const float l1 = l + dl * v;
+  if (isfinite(l1))
+    *lp = l1;
+  else if (Rn.status)
+    atomicOr(Rn.status + env, MS_ST_NONFINITE);
 }
 
 namespace {
@@ -219,6 +249,13 @@ void split_env_per_wg(const KModel &k, const KSplit &w, int n_env, int parts, in
   const int n_cu = device_cu_count();
   *w_front = best_w((const void *)&k_front, front_lds, k, w, n_env, n_cu, parts > 1);
   *w_back = best_w((const void *)&k_back, back_lds, k, w, n_env, n_cu, parts > 1);
+}
+
+hipError_t launch_fibre(const KModel &k, const KRun &r, const KSplit &w, hipStream_t st) {
+  const long long n = (long long)((r.env_end ? r.env_end : r.n_env) - r.env_begin) * k.n_mus;
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fibre, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, k, r, w);
+  return hipGetLastError();
 }
 
 hipError_t launch_front(const KModel &k, const KRun &r, const KSplit &w, int W, int step,

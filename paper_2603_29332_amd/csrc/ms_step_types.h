@@ -94,8 +94,8 @@ struct KRun {
   // lengths lm[n_env][n_mus] (m, caller's muscle order), 1 / eps0 and the
   // fibre damping beta. The muscle kernel leaves, per env and internal
   // muscle slot m, fib[env * fib_stride + k * n_mus + m] for k = 0..4: the
-  // moment arms r[3] of the span slots, the balancing fibre velocity v
-  // (m/s) and c / b, read by the fibre update after the solve.
+  // moment arms r[3] of the span slots, the path length L and the
+  // activation act' of the step, read by the fibre update after the solve.
   float *lm, *fib;
   int fib_stride;
   float ten_ieps, ten_beta;
@@ -167,6 +167,9 @@ hipError_t launch_front(const KModel &k, const KRun &r, const KSplit &w, int w_f
                         hipStream_t st);
 hipError_t launch_back(const KModel &k, const KRun &r, const KSplit &w, int w_back, int step,
                        hipStream_t st);
+// The compliant-tendon fibre update (k_fibre) after launch_back, for the
+// envs [r.env_begin, r.env_end) whose step k_back committed.
+hipError_t launch_fibre(const KModel &k, const KRun &r, const KSplit &w, hipStream_t st);
 // Envs per workgroup of those two kernels for a launch over n_env envs, one
 // of `parts` concurrent parts: alone, the fewest rounds of resident envs on
 // the device's CUs (occupancy calculator over 1..16 envs per workgroup),

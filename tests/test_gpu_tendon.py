@@ -167,6 +167,29 @@ def test_tendon_stream_parts_equal_one_stream(human):
     for x1, x2 in zip(out[0], out[1]):
         assert np.array_equal(x1, x2)
     assert (out[0][4] == 0).all() and np.isfinite(out[0][3]).all()
+    ln = out[0][3] / m["l_opt"]
+    print(f"whole body, 20 steps with contact: fibre lengths {ln.min():.3f} .. {ln.max():.3f} l_opt")
+    assert ln.min() > 0.3 and ln.max() < 2.0
+
+
+def test_tendon_freerun_human_200_contact_off(human):
+    """The whole body, 200 steps from its initial states with contact off,
+    GPU against the oracle: every hinge within 1e-3 rad, the root within
+    1e-3 m, the fibres within 1e-5 m."""
+    m, gm, o = human
+    E, dt = 6, 1e-3
+    q, qd, act, lm = _initial(m, o, synth.human_initial_state, E)
+    q, qd, act, lm = (v.astype(np.float32) for v in (q, qd, act, lm))
+    us = [synth.excitation_iid(41, E, m["n_mus"], t) for t in range(200)]
+    g = _gpu_steps(gm, q, qd, act, lm, us, dt, False)
+    assert (g[4] == 0).all()
+    ref = _oracle_steps(o, dt, *(v.astype(np.float64) for v in (q, qd, act, lm)), us, False)
+    hinge = np.abs(g[0][:, 7:] - ref[0][:, 7:]).max()
+    root = np.abs(g[0][:, :3] - ref[0][:, :3]).max()
+    lerr = np.abs(g[3] - ref[3]).max()
+    print(f"whole body tendon 200 steps: max hinge error {hinge:.2e} rad, root {root:.2e} m, "
+          f"fibre {lerr:.2e} m, excursion {np.abs(ref[0][:, 7:] - q[:, 7:]).max():.2f} rad")
+    assert hinge <= 1e-3 and root <= 1e-3 and lerr <= 1e-5
 
 
 def test_tendon_failures_keep_the_state(chain):
@@ -201,6 +224,7 @@ def test_tendon_argument_errors(chain):
         "beta = 0": dict(beta=0.0),
         "beta NaN": dict(beta=float("nan")),
         "eps0 inf": dict(eps0=float("inf")),
+        "beta below 1.82 dt v_max": dict(beta=0.036),
     }
     for name, kw in bad.items():
         with pytest.raises(ms.MsError) as ei:

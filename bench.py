@@ -40,7 +40,7 @@ PEAK_VALU_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 # valid for the kernel sources (ms_step_kernel.h, ms_step_split.hip) with
 # this SHA-256 prefix only (reported as null otherwise).
 TRAFFIC_BYTES_PER_LAUNCH = {"k_front": 51.27e6, "k_muscle": 56.97e6, "k_back": 58.71e6}
-TRAFFIC_KERNEL_SHA = "5eba69e60b4ea85e"
+TRAFFIC_KERNEL_SHA = "b5e2609f08aa10c0"
 TIMING_EVERY = 10
 KERNELS = ("k_front", "k_muscle", "k_back")
 

@@ -13,7 +13,8 @@
  *   Newton-Euler in body coordinates, penalty ground contact as tau_ext,
  *   joint damping, penalty joint coupling, a dense Cholesky solve of (M + dt D) qdd = rhs with the
  *   dissipative forces' velocity slope D taken implicitly, and a
- *   semi-implicit Euler update.
+ *   semi-implicit Euler update; and a compliant-tendon variant of the
+ *   muscle (a fibre-length state, ora_step_tendon).
  *
  * Shares no code with the HIP library: own model struct, own parser of the
  * generator's arrays, own maths.

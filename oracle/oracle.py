@@ -5,9 +5,10 @@ OpenMP over envs) and exposes each stage of the step as a numpy function.
 Model arrays come from the seeded generator (float32/int32) and are promoted
 to double inside the C code.
 
-Pins (tests/test_oracle_pins.py, tests/test_oracle_mlp.py): every stage of
-the step against closed forms, finite differences, invariants or a second
-route. The multi-step whole-body trajectory with contact as a whole has no
+Pins (tests/test_oracle_pins.py, tests/test_oracle_mlp.py,
+tests/test_oracle_tendon.py): every stage of the step, and the
+compliant-tendon variant, against closed forms, finite differences,
+invariants or a second route. The multi-step whole-body trajectory with contact as a whole has no
 closed form and is pinned only through those parts: parity unpinned for the
 composite.
 """

@@ -321,7 +321,11 @@ typedef struct {
  * allocates a fibre scratch of 20 n_mus bytes per env, and synchronises;
  * inside a stream capture that growth is refused (MS_E_ARG), so a captured
  * rollout needs an eager call of at least as many envs before it.
- * MS_E_ARG as for ms_rollout, and for ten or lm NULL, eps0 or beta not
+ * rec (may be NULL) records observables as in ms_rollout_record, with the
+ * compliant unit's meanings: force is the force of the step's right-hand
+ * side F_t + c (Ldot - v), lm the fibre length / l_opt and vm the balancing
+ * fibre velocity / (v_max l_opt) at the step's start, power |force Ldot|.
+ * MS_E_ARG as for ms_rollout_record, and for ten or lm NULL, eps0 or beta not
  * positive and finite, a model with a muscle whose l_slack <= 0, or
  * beta <= 1.82 dt v_max for some muscle (the fibre balance then need not
  * rise strictly in the fibre velocity). */
@@ -329,7 +333,7 @@ ms_status ms_rollout_tendon(ms_model *m, int32_t n_env, float *q, float *qd,
                             float *act, float *lm, uint32_t *status,
                             const ms_excitation *exc, int32_t n_steps,
                             const ms_step_opts *opts, const ms_tendon *ten,
-                            void *stream);
+                            const ms_record *rec, void *stream);
 
 /* Stage outputs of one step for n_env envs (device buffers, any may be
  * NULL): activation act'[E][n_mus], L, Ldot, F [E][n_mus], moment arms

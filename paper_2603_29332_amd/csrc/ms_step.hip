@@ -548,17 +548,21 @@ ms_status ms_rollout(ms_model *m, int32_t n_env, float *q, float *qd, float *act
   return rollout_impl(m, n_env, q, qd, act, status, exc, n_steps, opts, 0, (hipStream_t)stream);
 }
 
+static ms_status check_rec(const ms_model *m, const ms_record *rec) {
+  if (!rec) return MS_OK;
+  const bool any_obs = rec->act || rec->force || rec->lm || rec->vm || rec->power || rec->xpos ||
+                       rec->xmat;
+  if (any_obs && rec->every < 1) return fail(MS_E_ARG, "rec->every must be >= 1");
+  if ((rec->xpos || rec->xmat) && m && m->k.n_key == 0)
+    return fail(MS_E_ARG, "key-node observables need ms_model_set_key_nodes first");
+  return MS_OK;
+}
+
 ms_status ms_rollout_record(ms_model *m, int32_t n_env, float *q, float *qd, float *act,
                             uint32_t *status, const ms_excitation *exc, int32_t n_steps,
                             const ms_step_opts *opts, const ms_record *rec, void *stream) {
   g_err.clear();
-  if (rec) {
-    const bool any_obs = rec->act || rec->force || rec->lm || rec->vm || rec->power ||
-                         rec->xpos || rec->xmat;
-    if (any_obs && rec->every < 1) return fail(MS_E_ARG, "rec->every must be >= 1");
-    if ((rec->xpos || rec->xmat) && m && m->k.n_key == 0)
-      return fail(MS_E_ARG, "key-node observables need ms_model_set_key_nodes first");
-  }
+  if (const ms_status c = check_rec(m, rec); c != MS_OK) return c;
   return rollout_impl(m, n_env, q, qd, act, status, exc, n_steps, opts, 0, (hipStream_t)stream,
                       rec);
 }
@@ -566,8 +570,9 @@ ms_status ms_rollout_record(ms_model *m, int32_t n_env, float *q, float *qd, flo
 ms_status ms_rollout_tendon(ms_model *m, int32_t n_env, float *q, float *qd, float *act,
                             float *lm, uint32_t *status, const ms_excitation *exc,
                             int32_t n_steps, const ms_step_opts *opts, const ms_tendon *ten,
-                            void *stream) {
+                            const ms_record *rec, void *stream) {
   g_err.clear();
+  if (const ms_status c = check_rec(m, rec); c != MS_OK) return c;
   if (!m) return fail(MS_E_ARG, "model is NULL");
   if (!ten || !lm) return fail(MS_E_ARG, "ten or lm is NULL");
   if (!(ten->eps0 > 0.0f) || !std::isfinite(ten->eps0) || !(ten->beta > 0.0f) ||
@@ -584,7 +589,7 @@ ms_status ms_rollout_tendon(ms_model *m, int32_t n_env, float *q, float *qd, flo
         return fail(MS_E_ARG, "compliant tendons need beta > 1.82 dt v_max for every muscle");
     }
   return rollout_impl(m, n_env, q, qd, act, status, exc, n_steps, opts, 0, (hipStream_t)stream,
-                      nullptr, false, lm, ten);
+                      rec, false, lm, ten);
 }
 
 ms_status ms_model_set_key_nodes(ms_model *m, int32_t n_key, const int32_t *nodes) {

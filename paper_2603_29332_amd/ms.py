@@ -141,7 +141,8 @@ def lib():
     L.ms_rollout_record.argtypes = [vp, C.c_int32, vp, vp, vp, vp, C.POINTER(MsExc), C.c_int32,
                                     C.POINTER(MsOpts), C.POINTER(MsRecord), vp]
     L.ms_rollout_tendon.argtypes = [vp, C.c_int32, vp, vp, vp, vp, vp, C.POINTER(MsExc),
-                                    C.c_int32, C.POINTER(MsOpts), C.POINTER(MsTendon), vp]
+                                    C.c_int32, C.POINTER(MsOpts), C.POINTER(MsTendon),
+                                    C.POINTER(MsRecord), vp]
     L.ms_step_batch.argtypes = [vp, C.c_int32, vp, vp, vp, vp, vp, C.POINTER(MsOpts), vp]
     L.ms_rollout.argtypes = [vp, C.c_int32, vp, vp, vp, vp, C.POINTER(MsExc), C.c_int32,
                              C.POINTER(MsOpts), vp]
@@ -376,17 +377,25 @@ class Model:
 
     def rollout_tendon(self, q, qd, act, lm, status, n_steps, dt, contact=True, eps0=0.033,
                        beta=0.1, kind=EXC_ARRAY, u=None, seed=0, step0=0, x=None,
-                       ar1=(0.0, 0.0, 0.0), stream=None):
+                       ar1=(0.0, 0.0, 0.0), every=1, obs=None, n_applied=None, stream=None):
         """rollout() with compliant tendons; lm (device float32 [n_env][n_mus],
-        metres) is the fibre length, advanced with the state."""
+        metres) is the fibre length, advanced with the state. obs, every and
+        n_applied record observables as in rollout_record."""
         n_env = q.shape[0]
         o = MsOpts(dt, int(contact))
         e = MsExc(kind, _dp(u), seed, step0, _dp(x), float(ar1[0]), float(ar1[1]),
                   float(ar1[2]))
         t = MsTendon(float(eps0), float(beta))
+        rec = None
+        if obs or n_applied is not None:
+            obs = obs or {}
+            rec = MsRecord(int(every), *[_dp(obs.get(k)) for k in
+                                         ("act", "force", "lm", "vm", "power", "xpos", "xmat")],
+                           _dp(n_applied))
         _check(lib().ms_rollout_tendon(self.h, n_env, _dp(q), _dp(qd), _dp(act), _dp(lm),
                                        _dp(status), C.byref(e), n_steps, C.byref(o),
-                                       C.byref(t), _stream(stream)))
+                                       C.byref(t), C.byref(rec) if rec is not None else None,
+                                       _stream(stream)))
 
     def set_key_nodes(self, nodes):
         """Key nodes whose world frames rollout_record writes."""

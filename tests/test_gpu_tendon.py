@@ -240,3 +240,52 @@ def test_tendon_argument_errors(chain):
     torch.cuda.synchronize()
     for x, y in zip(a, ref):
         assert torch.equal(x, y)
+
+
+@pytest.mark.parametrize("which", ["chain", "human"])
+def test_tendon_records_observables(which, chain, human):
+    """A recorded tendon step advances the state bitwise as an unrecorded one
+    and writes the oracle's stage values: the activation and the fibre length
+    / l_opt at the step's start to float32 resolution (1e-6); the force of
+    the right-hand side and the balancing fibre velocity within 4 times the
+    oracle's spread under 4-ulp moves of the fibre lengths, or 1e-5 of the
+    block's largest value; power |force Ldot|."""
+    m, gm, o = chain if which == "chain" else human
+    init = synth.chain_initial_state if which == "chain" else synth.human_initial_state
+    dt, E = (2e-3, 8) if which == "chain" else (1e-3, 6)
+    nm = m["n_mus"]
+    q, qd, act, lm = _warm(m, o, init, E, 20, dt, False)
+    u = synth.excitation_iid(7, E, nm, 0)
+    obs = {k: torch.zeros(1, E, nm, device=DEV) for k in ("act", "force", "lm", "vm", "power")}
+    nap = torch.zeros(E, dtype=torch.int32, device=DEV)
+    a = [_t(q), _t(qd), _t(act), _t(lm)]
+    st = torch.zeros(E, dtype=torch.int32, device=DEV)
+    gm.rollout_tendon(*a, st, 1, dt, False, eps0=EPS0, beta=BETA, kind=ms.EXC_ARRAY,
+                      u=_t(u[None]), every=1, obs=obs, n_applied=nap)
+    torch.cuda.synchronize()
+    plain = _gpu_steps(gm, q, qd, act, lm, [u], dt, False)
+    for x, y in zip(a, plain[:4]):
+        assert np.array_equal(x.cpu().numpy(), y)
+    assert (st.cpu().numpy() == 0).all() and (nap.cpu().numpy() == 1).all()
+    g = {k: v[0].cpu().numpy() for k, v in obs.items()}
+    d64 = [v.astype(np.float64) for v in (q, qd, act, lm)]
+    L = np.stack([o.geometry(d64[0][e], d64[1][e])[0] for e in range(E)])
+    ulp = np.spacing(L.astype(np.float32)).astype(np.float64)
+    rng = np.random.default_rng(8)
+    for e in range(E):
+        S = o.step_tendon(dt, d64[0][e], d64[1][e], d64[2][e], d64[3][e], u[e], EPS0, BETA,
+                          contact=False, stages=True)[5]
+        spread = {"F": 0.0, "vm": 0.0}
+        for _ in range(3):
+            lp = d64[3][e] + 4 * ulp[e] * rng.choice([-1.0, 1.0], size=nm)
+            P = o.step_tendon(dt, d64[0][e], d64[1][e], d64[2][e], lp, u[e], EPS0, BETA,
+                              contact=False, stages=True)[5]
+            for k in spread:
+                spread[k] = max(spread[k], np.abs(P[k] - S[k]).max())
+        np.testing.assert_allclose(g["act"][e], S["act"], rtol=0, atol=1e-6)
+        np.testing.assert_allclose(g["lm"][e], S["lm"], rtol=0, atol=1e-6 * max(np.abs(S["lm"]).max(), 1))
+        for gk, sk in (("force", "F"), ("vm", "vm")):
+            tol = max(4 * spread[sk], 1e-5 * max(np.abs(S[sk]).max(), 1.0))
+            assert np.abs(g[gk][e] - S[sk]).max() <= tol, (gk, e)
+        np.testing.assert_allclose(g["power"][e], np.abs(g["force"][e] * S["Ldot"]),
+                                   rtol=1e-4, atol=1e-4 * np.abs(g["power"][e]).max())
